@@ -1,0 +1,122 @@
+"""Pins of the oracle's LLE weights (Eq. LinSys with the trace regulariser),
+synthesis (Eq. HR_Rec) and overlap blend (the quadratic overlap prior of
+Section 4) against closed forms, a KKT solve and self-reproduction."""
+import numpy as np
+import pytest
+
+import synthdata
+from oracle import imaging, lle, pipeline
+
+
+def test_weights_sum_to_one_and_small_cases():
+    rng = np.random.default_rng(0)
+    q = rng.standard_normal(25)
+    Y = rng.standard_normal((6, 25))
+    w = lle.lle_weights(q, Y, 1e-3)
+    assert abs(w.sum() - 1.0) < 1e-12
+    assert np.array_equal(lle.lle_weights(q, Y[:1], 1e-3), np.array([1.0]))
+    # K = 2 closed form: w1 = (G22 + e - G12) / (G11 + G22 + 2e - 2 G12), e = lam tr G
+    lam = 1e-3
+    Z = q[None] - Y[:2]
+    G = Z @ Z.T
+    e = lam * np.trace(G)
+    w1 = (G[1, 1] + e - G[0, 1]) / (G[0, 0] + G[1, 1] + 2 * e - 2 * G[0, 1])
+    assert np.allclose(lle.lle_weights(q, Y[:2], lam), [w1, 1 - w1], rtol=0, atol=1e-13)
+
+
+def test_weights_equal_kkt_solution_and_invariances():
+    rng = np.random.default_rng(1)
+    q = rng.standard_normal(100)
+    Y = q[None] + 0.3 * rng.standard_normal((8, 100))
+    lam = 1e-3
+    w = lle.lle_weights(q, Y, lam)
+    # KKT system of min w^T A w s.t. 1^T w = 1
+    Z = q[None] - Y
+    A = Z @ Z.T + lam * np.trace(Z @ Z.T) * np.eye(8)
+    kkt = np.block([[2 * A, np.ones((8, 1))], [np.ones((1, 8)), np.zeros((1, 1))]])
+    sol = np.linalg.solve(kkt, np.r_[np.zeros(8), 1.0])
+    assert np.allclose(w, sol[:8], rtol=0, atol=1e-12)
+    perm = rng.permutation(8)
+    assert np.allclose(lle.lle_weights(q, Y[perm], lam), w[perm], atol=1e-12)
+    shift = rng.standard_normal(100)
+    assert np.allclose(lle.lle_weights(q + shift, Y + shift[None], lam), w, atol=1e-12)
+
+
+def test_affine_combination_is_recovered_as_lambda_vanishes():
+    rng = np.random.default_rng(2)
+    Y = rng.standard_normal((5, 30))
+    c = np.array([0.4, 0.3, -0.2, 0.25, 0.25])
+    q = c @ Y
+    assert np.allclose(lle.lle_weights(q, Y, 1e-12), c, atol=1e-8)
+
+
+def test_degenerate_weights():
+    q = np.ones(10)
+    assert np.array_equal(lle.lle_weights(q, np.ones((3, 10)), 1e-3), np.full(3, 1 / 3))
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((4, 10))
+    assert np.allclose(lle.lle_weights(q, Y, 1e9), np.full(4, 0.25), atol=1e-8)
+
+
+def test_blend_is_least_squares_minimiser_and_counts():
+    rng = np.random.default_rng(4)
+    h, w, s = 9, 8, 2
+    lr = rng.random((h, w)).astype(np.float32)
+    pos = imaging.all_positions(h, w)
+    valid = rng.random(len(pos)) > 0.2
+    patches = [rng.random(100) for _ in range(len(pos))]
+    out, cnt = lle.blend(patches, pos, valid, s, lr)
+    # closed-form coverage when every patch is valid
+    _, cnt_all = lle.blend(patches, pos, np.ones(len(pos), bool), s, lr)
+    for Y in range(s * h):
+        ny = sum(1 for i in range(h - 4) if s * i <= Y < s * i + 10)
+        for X in range(s * w):
+            nx = sum(1 for j in range(w - 4) if s * j <= X < s * j + 10)
+            assert cnt_all[Y, X] == ny * nx
+    # least squares: minimise sum_q ||R_q I - x_q||^2 over the covered pixels
+    H, W = s * h, s * w
+    rows, rhs = [], []
+    for q in np.nonzero(valid)[0]:
+        y0, x0 = s * pos[q]
+        for a in range(10):
+            for b in range(10):
+                r = np.zeros(H * W)
+                r[(y0 + a) * W + x0 + b] = 1.0
+                rows.append(r)
+                rhs.append(patches[q][a * 10 + b])
+    Amat = np.array(rows)
+    cov = cnt.ravel() > 0
+    sol = np.linalg.lstsq(Amat[:, cov], np.array(rhs), rcond=None)[0]
+    assert np.allclose(out.ravel()[cov], sol, atol=1e-12)
+    bic = imaging.bicubic_up(lr, s)
+    assert np.array_equal(out[cnt == 0], bic[cnt == 0])
+
+
+def test_constant_patches_give_constant_image():
+    h, w = 10, 11
+    pos = imaging.all_positions(h, w)
+    out, _ = lle.blend([np.full(100, 0.3)] * len(pos), pos, np.ones(len(pos), bool), 2,
+                       np.zeros((h, w), np.float32))
+    assert np.abs(out - 0.3).max() < 1e-15
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_full_image_self_reproduction(mode):
+    """A dictionary holding every patch pair of (HR, degraded HR): each query
+    patch of the degraded HR finds itself at distance 0 and K = 1
+    reconstructs its own HR patch, so the blend returns HR (up to the fp32
+    rounding of the stored residuals). The paper adds part of the test image
+    to the training set for the same effect (Section 5.1)."""
+    hr = synthdata.fractal_voronoi_image(40, 48, 48)
+    lr = imaging.degrade(hr, 2)
+    pos = np.concatenate([np.zeros((len(imaging.all_positions(24, 24)), 1), np.int64),
+                          imaging.all_positions(24, 24)], axis=1)
+    pre = pipeline.prepare(hr[None], pos, 2, mode, L=4, k=6, w=4.0, seed=7)
+    qr = pipeline.query(pre, lr, K=1, lam=1e-3)
+    # own patch is a candidate and at distance zero
+    for q in range(len(pos)):
+        assert q in set(qr.cand[q].tolist())
+    assert np.all(qr.d2[:, 0] == 0.0)
+    out, cnt = pipeline.reconstruct(qr, lr, 2)
+    assert cnt.min() > 0
+    assert np.abs(out - hr.astype(np.float64)).max() < 1e-6
