@@ -1,0 +1,204 @@
+/*
+ * libzoomhash: the data-parallel hot path of patch-hashing image zoom
+ * (Das Gupta, "Hashing Image Patches for Zooming", arXiv:1004.3980) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * For every overlapping 5x5 patch of a low-resolution (LR) image the library
+ * finds neighbours in a training dictionary of LR/HR patch pairs with p-stable
+ * (Cauchy) locality-sensitive hashing, solves the LLE reconstruction weights,
+ * synthesises the high-resolution (HR) patches with those weights, blends the
+ * overlaps and refines the result by error back-projection with an
+ * approximate cross bilateral filter.
+ *
+ * Conventions
+ *  - Every array argument is a HIP device pointer owned by the caller unless
+ *    its comment says "host". Images are fp32, row-major, values nominally in
+ *    [0, 1] (never clamped).
+ *  - A context owns one HIP stream (the caller's, or the null stream) and all
+ *    work is enqueued on it asynchronously; device faults surface at a later
+ *    call or at zh_sync. Argument and state errors return immediately and
+ *    enqueue nothing.
+ *  - No call aborts or throws across this boundary. On failure a call
+ *    returns a nonzero zh_status and zh_last_error() describes it.
+ *  - One context per host thread. Calls on one context are not thread-safe.
+ *  - Patch order: patch q of an h x w LR image has top-left corner
+ *    (i, j) = (q / (w-4), q % (w-4)); Q = (h-4)(w-4).
+ */
+#ifndef ZOOMHASH_H
+#define ZOOMHASH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t zh_status;
+enum {
+    ZH_OK = 0,
+    ZH_EINVAL = 1,        /* bad argument (size, pointer, parameter range) */
+    ZH_ESTATE = 2,        /* call out of order (e.g. zh_reconstruct before zh_lle_weights) */
+    ZH_ENOMEM = 3,        /* device allocation failed or exceeded ZH_MEM_LIMIT */
+    ZH_EDEVICE = 4,       /* HIP runtime or kernel launch error */
+    ZH_EUNSUPPORTED = 5   /* valid request outside what this build implements */
+};
+
+typedef struct zh_ctx zh_ctx;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). *out receives the context. */
+zh_status zh_create(zh_ctx** out, int device, void* hip_stream);
+/* Release every device buffer the context owns. NULL is ignored. */
+void zh_destroy(zh_ctx* ctx);
+zh_status zh_set_stream(zh_ctx* ctx, void* hip_stream);
+/* Wait for the context's stream; reports device errors of earlier calls. */
+zh_status zh_sync(zh_ctx* ctx);
+/* Message of the last failure on this context; owned by the context, valid
+ * until the next call on it. Never NULL. */
+const char* zh_last_error(const zh_ctx* ctx);
+
+/* ---- training data (Section 2.1: Gaussian blur then decimation) -------- */
+
+/* lr[ceil(H/s), ceil(W/s)] = (g * hr)[s i, s j]: g the normalised Gaussian of
+ * `sigma` over offsets -ceil(3 sigma)..ceil(3 sigma) (host libm exp), replicate
+ * border; evaluated in FP64 (rows first, taps in ascending order) and rounded
+ * once to fp32. hr holds n_img images of H x W. sigma in (0, 5]. */
+zh_status zh_degrade(zh_ctx* ctx, const float* hr, int n_img, int H, int W, int scale,
+                     float sigma, float* lr);
+
+/* Feature modes (Section 4.1, "Feature representation"). */
+enum { ZH_FEAT_MEANREM = 0,   /* D = 25: the patch's pixels minus their mean */
+       ZH_FEAT_GRAD4 = 1 };   /* D = 100: 5x5 windows of dx, dy, dxx, dyy maps
+                                 (taps [-1,0,1], [-1,0,2,0,-1], replicate border),
+                                 channel-major, row-major inside a channel */
+
+/* Cut n training pairs from n_img HR images [n_img, H, W] at LR positions
+ * pos[n, 3] = (image, i, j) (int32, device): the LR image is the degradation
+ * of the HR image by `sigma` and `scale`; feat[n, D] is the LR patch's
+ * feature vector and resid[n, (5s)^2] the HR patch at (s i, s j) minus the
+ * mean of the LR patch. Row n is pair ID n (Section 2.1: unique integer IDs).
+ * Positions must satisfy 0 <= i, j <= ceil(H/s) - 5. Uses a temporary device
+ * buffer of n_img * ceil(H/s) * ceil(W/s) * 5 floats. */
+zh_status zh_make_dictionary(zh_ctx* ctx, const float* hr, int n_img, int H, int W,
+                             const int32_t* pos, int64_t n, int scale, float sigma,
+                             int feat_mode, float* feat, float* resid);
+
+/* Feature rows of every stride-1 patch of one LR image: feat[Q, D] and the
+ * patch means mu[Q] (FP64, may be NULL). */
+zh_status zh_features(zh_ctx* ctx, const float* lr, int h, int w, int feat_mode, float* feat,
+                      double* mu);
+
+/* ---- hashing and tables (Section 3.2; Section 4.1, Eq. hash_fn, Eq. cauchy) */
+
+typedef struct {
+    int64_t n;             /* pairs, 1 <= n < 2^31 */
+    int32_t dim;           /* D: 25 or 100 */
+    int32_t scale;         /* 2 or 3: HR patch side 5*scale */
+    int32_t feat_mode;     /* ZH_FEAT_* that produced `feat` */
+    const float* feat;     /* [n, D] fp32; copied at build into the library's own
+                              split storage (bf16 high half + low 16 bits) */
+    const float* resid;    /* [n, (5 scale)^2] fp32 HR residuals; BORROWED: must
+                              stay valid and unchanged while the tables are used */
+} zh_dictionary;
+
+/* Build L hash tables of k concatenated Cauchy hashes of bin width w for the
+ * dictionary of `scale` (one dictionary per scale; rebuilding replaces it).
+ * Hash parameters: per table l an independent SplitMix64 stream with state
+ * fmix64(seed + 0x9E3779B97F4A7C15 (l+1)); standard normals by Marsaglia's
+ * polar method (first variate of each accepted pair); alpha = a/b with b
+ * redrawn while |b| < 1e-3, k*D values in (hash, dim) order; then k values
+ * beta = u w, u in [0,1). FP64, rounded to fp32. A bin is the 64-bit key of
+ * the k codes floor((alpha.v + beta)/w) of a table, folded in order by
+ * h = fmix64(h ^ uint32(code)) from h = fmix64(0x9E3779B97F4A7C15 (l+1)).
+ * Codes equal the FP64 sequential dot-product definition exactly.
+ * Limits: 1 <= L <= 64, 1 <= k <= 32, w > 0. */
+zh_status zh_build_tables(zh_ctx* ctx, const zh_dictionary* dict, int L, int k, float w,
+                          uint64_t seed);
+
+/* Copy the hash parameters of `scale` to HOST arrays alpha[L*k*D], beta[L*k]. */
+zh_status zh_get_hash_params(zh_ctx* ctx, int scale, float* alpha_host, float* beta_host);
+
+/* Codes (int32 [n, L*k], may be NULL) and bucket keys (uint64 [n, L], may be
+ * NULL) of arbitrary feature rows feat[n, D] under the tables of `scale`. */
+zh_status zh_hash(zh_ctx* ctx, int scale, const float* feat, int64_t n, int32_t* codes,
+                  uint64_t* keys);
+
+/* ---- query options ----------------------------------------------------- */
+typedef struct {
+    int32_t cap;           /* 0: candidates are the union of the L bins; > 0: the
+                              early stop of Section 4.2 (tables in order, IDs
+                              ascending in a bin, stop at cap distinct IDs),
+                              cap <= 256 */
+    int32_t rerank;        /* 0: exact ranking (fp32 distances certified against
+                              the FP64 distance, exact K nearest by (d, ID));
+                              R in [K, 64]: rank all candidates on the bf16 high
+                              half of the features, re-rank the best R in fp32 */
+    int32_t proj;          /* projection on the matrix cores: 0 fp32, 1 split
+                              bf16 (three bf16 products); both give exact codes */
+    int32_t lle_fp64;      /* 1: Gram and solve in FP64; 0: fp32, FP64 only when
+                              the Cholesky diagonal ratio squared exceeds 1e6 */
+} zh_query_opts;
+/* Defaults: cap 0, rerank 0, proj 1, lle_fp64 1. */
+zh_status zh_set_query_opts(zh_ctx* ctx, const zh_query_opts* opts);
+
+/* ---- the path --------------------------------------------------------- */
+
+/* Features, codes, bins and the K nearest candidates of every patch of the
+ * LR image lr[h, w] (copied into the context) against the dictionary of
+ * `scale`. 1 <= K <= 16, h, w >= 5. Neighbours are ordered by (distance, ID);
+ * a patch with fewer than K candidates keeps all of them. */
+zh_status zh_query(zh_ctx* ctx, const float* lr, int h, int w, int scale, int K);
+
+/* LLE weights of every patch (Section 4.2, Eq. LinSys): minimise
+ * ||y - sum_m w_m y_m||^2 subject to sum_m w_m = 1, regularised by adding
+ * lambda * trace(G) to the diagonal of the Gram matrix G (lambda > 0). */
+zh_status zh_lle_weights(zh_ctx* ctx, float lambda);
+
+/* HR image hr_out[s h, s w]: each patch x_q = mean(LR patch) + sum_m w_m r_m
+ * (Eq. HR_Rec on the residuals), overlaps averaged per pixel (Section 4
+ * prior); pixels covered by no patch with a neighbour take the bicubic
+ * (Keys a = -0.5) interpolation of the LR image. */
+zh_status zh_reconstruct(zh_ctx* ctx, float* hr_out);
+
+/* `iters` error back-projection steps in place on hr_inout[s h, s w]
+ * (Section 4 update after Eq. Err_img; Section 4.3 approximate cross
+ * bilateral filter, Eq. sx2 and Eq. bl_filter_3): e = I_L - (g * I)
+ * decimated, E its bicubic upsampling, F the in-image-normalised Gaussian of
+ * sigma_s over a (2R+1)^2 window (R = ceil(3 sigma_s) <= 8) applied to E,
+ * S = exp(-(I - mean_window(I))^2 / (2 sigma_r^2)), I += S F. sigma_r may be
+ * +inf (plain Gaussian back-projection). Uses the LR image of the last
+ * zh_query and the blur sigma of the degradation (1.0). */
+zh_status zh_backproject(zh_ctx* ctx, float* hr_inout, int iters, float sigma_s, float sigma_r);
+
+/* ---- results and diagnostics ------------------------------------------ */
+
+/* Copies of the last query's results (device pointers, each may be NULL):
+ * ids[Q, K] int32 (-1 past m), d2[Q, K] squared distances, m[Q] neighbours
+ * used, w[Q, K] weights (after zh_lle_weights), ncand[Q] distinct candidates
+ * (in early-stop mode at most cap). */
+zh_status zh_get_results(zh_ctx* ctx, int32_t* ids, float* d2, int32_t* m, float* w,
+                         int32_t* ncand);
+/* Query size of the last zh_query: *Q patches, *D feature dimension. */
+zh_status zh_query_shape(zh_ctx* ctx, int64_t* Q, int32_t* D);
+
+/* Re-run the candidate search of the last query and write each patch's
+ * candidate IDs ascending into ids[Q, cap_per_query] (device) and their
+ * number into counts[Q]; entries past min(count, cap_per_query) are untouched. */
+zh_status zh_candidates(zh_ctx* ctx, int32_t cap_per_query, int32_t* counts, int32_t* ids);
+
+typedef struct {
+    uint64_t queries;           /* patches of the last zh_query */
+    uint64_t codes_fixed;       /* codes decided by the FP64 recomputation */
+    uint64_t rank_fallbacks;    /* patches re-ranked by FP64 distances */
+    uint64_t deferred;          /* patches sent to the large-union path */
+    uint64_t unsupported;       /* patches whose bins exceed 8192 IDs without a cap */
+    uint64_t lle_fp64;          /* fp32 solves redone in FP64 */
+    uint64_t dict_bytes;        /* device bytes held for dictionaries and tables */
+} zh_stats_t;
+/* Counters of the last zh_query / zh_lle_weights (synchronises the stream). */
+zh_status zh_stats(zh_ctx* ctx, zh_stats_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZOOMHASH_H */

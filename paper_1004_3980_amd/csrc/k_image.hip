@@ -1,0 +1,228 @@
+// Image-side kernels: degradation (Section 2.1: Gaussian blur then
+// decimation), the gradient maps and patch features of Section 4.1, cutting
+// of the LR/HR training pairs, and bicubic upsampling.
+//
+// The degradation and the features are evaluated in FP64 in a fixed order
+// and rounded once to fp32, so the stored LR images and features are
+// reproducible bit for bit by any implementation that follows the same
+// order (the file is compiled without multiply-add contraction).
+#include "zh_internal.h"
+
+namespace zh {
+
+// (g * hr)[s i, s j] in FP64: horizontal pass along each needed row, then the
+// vertical combination, both accumulating taps in ascending offset order.
+__device__ __forceinline__ double blur_at(const float* __restrict__ hr, int H, int W, int y, int x,
+                                          const Taps& t) {
+    double acc = 0.0;
+    for (int a = -t.R; a <= t.R; ++a) {
+        const float* row = hr + (int64_t)clampi(y + a, 0, H - 1) * W;
+        double hrow = 0.0;
+        for (int b = -t.R; b <= t.R; ++b) hrow = hrow + t.g[b + t.R] * (double)row[clampi(x + b, 0, W - 1)];
+        acc = acc + t.g[a + t.R] * hrow;
+    }
+    return acc;
+}
+
+__global__ void k_degrade(const float* __restrict__ hr, int n_img, int H, int W, int scale, Taps t,
+                          float* __restrict__ lr) {
+    const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
+    const int64_t total = (int64_t)n_img * h * w;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t im = idx / ((int64_t)h * w);
+        const int r = (int)(idx % ((int64_t)h * w));
+        const int i = r / w, j = r % w;
+        lr[idx] = (float)blur_at(hr + im * (int64_t)H * W, H, W, scale * i, scale * j, t);
+    }
+}
+
+__global__ void k_degrade_residual(const float* __restrict__ hr, int H, int W, int scale, Taps t,
+                                   const float* __restrict__ lr_ref, float* __restrict__ e) {
+    const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
+    const int64_t total = (int64_t)h * w;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / w), j = (int)(idx % w);
+        e[idx] = (float)((double)lr_ref[idx] - blur_at(hr, H, W, scale * i, scale * j, t));
+    }
+}
+
+// Four gradient maps per image, fp32 [n_img, 4, h, w]:
+//   dx = I(c+1) - I(c-1), dy likewise along rows,
+//   dxx = (2 I(c) - I(c-2)) - I(c+2), dyy likewise; replicate border.
+__global__ void k_gradient_maps(const float* __restrict__ lr, int n_img, int h, int w,
+                                float* __restrict__ maps) {
+    const int64_t total = (int64_t)n_img * h * w;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t im = idx / ((int64_t)h * w);
+        const int rc = (int)(idx % ((int64_t)h * w));
+        const int r = rc / w, c = rc % w;
+        const float* I = lr + im * (int64_t)h * w;
+        auto at = [&](int rr, int cc) -> double {
+            return (double)I[(int64_t)clampi(rr, 0, h - 1) * w + clampi(cc, 0, w - 1)];
+        };
+        const double x0 = at(r, c);
+        const double dx = at(r, c + 1) - at(r, c - 1);
+        const double dy = at(r + 1, c) - at(r - 1, c);
+        const double dxx = (2.0 * x0 - at(r, c - 2)) - at(r, c + 2);
+        const double dyy = (2.0 * x0 - at(r - 2, c)) - at(r + 2, c);
+        float* M = maps + im * 4 * (int64_t)h * w;
+        const int64_t plane = (int64_t)h * w;
+        M[rc] = (float)dx;
+        M[plane + rc] = (float)dy;
+        M[2 * plane + rc] = (float)dxx;
+        M[3 * plane + rc] = (float)dyy;
+    }
+}
+
+// Patch mean: FP64 sum over the 25 pixels in row-major order, then / 25.
+__device__ __forceinline__ double patch_mean(const float* __restrict__ I, int w, int i, int j) {
+    double s = 0.0;
+    for (int a = 0; a < kPatch; ++a)
+        for (int b = 0; b < kPatch; ++b) s = s + (double)I[(int64_t)(i + a) * w + j + b];
+    return s / (double)(kPatch * kPatch);
+}
+
+// One thread per (patch, feature element); the element 0 thread also writes
+// the patch mean.
+__global__ void k_query_features(const float* __restrict__ lr, const float* __restrict__ maps,
+                                 int h, int w, int mode, float* __restrict__ feat,
+                                 double* __restrict__ mu) {
+    const int nj = w - kPatch + 1;
+    const int Q = (h - kPatch + 1) * nj;
+    const int D = mode == 0 ? 25 : 100;
+    const int64_t total = (int64_t)Q * D;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(idx / D), e = (int)(idx % D);
+        const int i = q / nj, j = q % nj;
+        if (mode == 0) {
+            const double m = patch_mean(lr, w, i, j);
+            const int a = e / kPatch, b = e % kPatch;
+            feat[idx] = (float)((double)lr[(int64_t)(i + a) * w + j + b] - m);
+            if (e == 0) mu[q] = m;
+        } else {
+            const int ch = e / 25, a = (e % 25) / kPatch, b = e % kPatch;
+            feat[idx] = maps[(int64_t)ch * h * w + (int64_t)(i + a) * w + j + b];
+            if (e == 0) mu[q] = patch_mean(lr, w, i, j);
+        }
+    }
+}
+
+// Training pairs at positions (image, i, j): features, and the HR patch
+// (5s x 5s at (s i, s j)) minus the mean of the LR patch, in FP64 rounded to
+// fp32. One thread per (pair, element) over D + (5s)^2 elements.
+__global__ void k_dict_cut(const float* __restrict__ hr, const float* __restrict__ lr,
+                           const float* __restrict__ maps, int H, int W, int scale,
+                           const int32_t* __restrict__ pos, int64_t n, int mode,
+                           float* __restrict__ feat, float* __restrict__ resid) {
+    const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
+    const int D = mode == 0 ? 25 : 100;
+    const int ps = kPatch * scale, ps2 = ps * ps;
+    const int per = D + ps2;
+    const int64_t total = n * per;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = idx / per;
+        const int e = (int)(idx % per);
+        const int im = pos[3 * p], i = pos[3 * p + 1], j = pos[3 * p + 2];
+        const float* L = lr + (int64_t)im * h * w;
+        if (e < D) {
+            float v;
+            if (mode == 0) {
+                const double m = patch_mean(L, w, i, j);
+                v = (float)((double)L[(int64_t)(i + e / kPatch) * w + j + e % kPatch] - m);
+            } else {
+                const int ch = e / 25, a = (e % 25) / kPatch, b = e % kPatch;
+                v = maps[((int64_t)im * 4 + ch) * h * w + (int64_t)(i + a) * w + j + b];
+            }
+            feat[p * D + e] = v;
+        } else {
+            const int t = e - D, a = t / ps, b = t % ps;
+            const double m = patch_mean(L, w, i, j);
+            const float x = hr[(int64_t)im * H * W + (int64_t)(scale * i + a) * W + scale * j + b];
+            resid[p * ps2 + t] = (float)((double)x - m);
+        }
+    }
+}
+
+__global__ void k_split_planes(const float* __restrict__ x, int64_t count, uint16_t* __restrict__ hi,
+                               uint16_t* __restrict__ lo) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < count;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = __float_as_uint(x[idx]);
+        hi[idx] = (uint16_t)(b >> 16);
+        lo[idx] = (uint16_t)(b & 0xFFFFu);
+    }
+}
+
+__global__ void k_bicubic(const float* __restrict__ lr, int h, int w, int s, float* __restrict__ out) {
+    const int H = s * h, W = s * w;
+    const int64_t total = (int64_t)H * W;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        out[idx] = bicubic_at(lr, h, w, s, (int)(idx / W), (int)(idx % W));
+}
+
+static inline int grid_for(int64_t total, int block) {
+    int64_t g = (total + block - 1) / block;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_degrade(const float* hr, int n_img, int H, int W, int scale, const Taps& t,
+                          float* lr, hipStream_t st) {
+    const int64_t total = (int64_t)n_img * ((H + scale - 1) / scale) * ((W + scale - 1) / scale);
+    hipLaunchKernelGGL(k_degrade, dim3(grid_for(total, 256)), dim3(256), 0, st, hr, n_img, H, W,
+                       scale, t, lr);
+    return hipGetLastError();
+}
+
+hipError_t launch_degrade_residual(const float* hr, int H, int W, int scale, const Taps& t,
+                                   const float* lr_ref, float* e, hipStream_t st) {
+    const int64_t total = (int64_t)((H + scale - 1) / scale) * ((W + scale - 1) / scale);
+    hipLaunchKernelGGL(k_degrade_residual, dim3(grid_for(total, 256)), dim3(256), 0, st, hr, H, W,
+                       scale, t, lr_ref, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradient_maps(const float* lr, int n_img, int h, int w, float* maps,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_gradient_maps, dim3(grid_for((int64_t)n_img * h * w, 256)), dim3(256), 0,
+                       st, lr, n_img, h, w, maps);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_features(const float* lr, const float* maps, int h, int w, int mode,
+                                 float* feat, double* mu, hipStream_t st) {
+    const int64_t total = (int64_t)(h - kPatch + 1) * (w - kPatch + 1) * (mode == 0 ? 25 : 100);
+    hipLaunchKernelGGL(k_query_features, dim3(grid_for(total, 256)), dim3(256), 0, st, lr, maps,
+                       h, w, mode, feat, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_dict_cut(const float* hr, const float* lr, const float* maps, int H, int W,
+                           int scale, const int32_t* pos, int64_t n, int mode, float* feat,
+                           float* resid, hipStream_t st) {
+    const int per = (mode == 0 ? 25 : 100) + kPatch * scale * kPatch * scale;
+    hipLaunchKernelGGL(k_dict_cut, dim3(grid_for(n * per, 256)), dim3(256), 0, st, hr, lr, maps,
+                       H, W, scale, pos, n, mode, feat, resid);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_planes(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_split_planes, dim3(grid_for(count, 256)), dim3(256), 0, st, x, count, hi,
+                       lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicubic(const float* lr, int h, int w, int scale, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_bicubic, dim3(grid_for((int64_t)scale * h * scale * w, 256)), dim3(256),
+                       0, st, lr, h, w, scale, out);
+    return hipGetLastError();
+}
+
+}  // namespace zh

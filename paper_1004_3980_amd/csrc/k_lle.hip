@@ -1,0 +1,261 @@
+// LLE weights (Section 4.2, Eq. LinSys), HR synthesis (Eq. HR_Rec) and the
+// overlap blend (Section 4: quadratic prior on the overlaps, whose equal-
+// weight minimiser is the per-pixel mean of the covering patches).
+//
+// Weights: Z = y - Y (the K neighbour rows), G = Z Z^T, A = G + lam tr(G) I,
+// A w~ = 1 by Cholesky, w = w~ / sum(w~); uniform weights when tr(G) = 0.
+// A workgroup (one wave) forms the Gram matrices of QPW patches one after
+// the other, every lane owning one (a, b) entry; then each lane solves one
+// patch's system.
+#include "zh_internal.h"
+
+namespace zh {
+
+// (a, b) with a >= b for packed lower index p = a (a + 1) / 2 + b
+__constant__ uint8_t c_pa[136];
+__constant__ uint8_t c_pb[136];
+static bool g_pair_table_ready[64] = {false};
+
+template <typename T, int KMAX, int QPW>
+__global__ __launch_bounds__(64) void k_lle(LleArgs a) {
+    constexpr int NPM = KMAX * (KMAX + 1) / 2;
+    constexpr int GST = NPM + 1;                      // padded per-patch stride
+    __shared__ T sG[QPW * GST];
+    __shared__ T sZ[128 * KMAX];                      // Z transposed: [dim][neighbour]
+    const int lane = threadIdx.x;
+    const int D = a.D, K = a.K;
+    const int q0 = blockIdx.x * QPW;
+
+    for (int qi = 0; qi < QPW; ++qi) {
+        const int q = q0 + qi;
+        if (q >= a.Q) break;
+        const int m = a.m[q];
+        if (m <= 0) continue;
+        const float* qrow = a.qfeat + (int64_t)q * D;
+        for (int r = 0; r < m; ++r) {
+            const int64_t b = (int64_t)a.ids[(int64_t)q * K + r] * D;
+            for (int t = lane; t < D; t += 64)
+                sZ[t * KMAX + r] = (T)qrow[t] - (T)join_planes(a.hi[b + t], a.lo[b + t]);
+        }
+        __syncthreads();
+        const int np = m * (m + 1) / 2;
+        for (int p = lane; p < np; p += 64) {
+            const int ia = c_pa[p], ib = c_pb[p];
+            T g = (T)0;
+            for (int t = 0; t < D; ++t) g += sZ[t * KMAX + ia] * sZ[t * KMAX + ib];
+            sG[qi * GST + p] = g;
+        }
+        __syncthreads();
+    }
+
+    if (lane < QPW && q0 + lane < a.Q) {
+        const int q = q0 + lane;
+        const int m = a.m[q];
+        float* wout = a.w + (int64_t)q * K;
+        if (m <= 0) {
+            for (int r = 0; r < K; ++r) wout[r] = 0.0f;
+            return;
+        }
+        T* G = sG + lane * GST;
+        auto at = [&](int i, int j) -> T& { return G[i * (i + 1) / 2 + j]; };  // i >= j
+        T tau = (T)0;
+        for (int i = 0; i < m; ++i) tau += at(i, i);
+        T wv[KMAX];
+        bool redo64 = false;
+        if (tau == (T)0) {
+            for (int i = 0; i < m; ++i) wv[i] = (T)1 / (T)m;
+        } else {
+            const T reg = (T)a.lam * tau;
+            for (int i = 0; i < m; ++i) at(i, i) += reg;
+            // Cholesky A = L L^T in place (packed lower)
+            T dmin = (T)1e300, dmax = (T)0;
+            for (int j = 0; j < m; ++j) {
+                T s = at(j, j);
+                for (int k = 0; k < j; ++k) s -= at(j, k) * at(j, k);
+                const T d = sqrt(s);
+                at(j, j) = d;
+                dmin = d < dmin ? d : dmin;
+                dmax = d > dmax ? d : dmax;
+                for (int i = j + 1; i < m; ++i) {
+                    T t = at(i, j);
+                    for (int k = 0; k < j; ++k) t -= at(i, k) * at(j, k);
+                    at(i, j) = t / d;
+                }
+            }
+            // condition estimate from the Cholesky diagonal
+            if (sizeof(T) == 4 && (double)dmax * (double)dmax > 1e6 * (double)dmin * (double)dmin) redo64 = true;
+            T y[KMAX];
+            for (int i = 0; i < m; ++i) {
+                T s = (T)1;
+                for (int k = 0; k < i; ++k) s -= at(i, k) * y[k];
+                y[i] = s / at(i, i);
+            }
+            T sum = (T)0;
+            for (int i = m - 1; i >= 0; --i) {
+                T s = y[i];
+                for (int k = i + 1; k < m; ++k) s -= at(k, i) * wv[k];
+                wv[i] = s / at(i, i);
+            }
+            for (int i = 0; i < m; ++i) sum += wv[i];
+            for (int i = 0; i < m; ++i) wv[i] /= sum;
+        }
+        if (redo64) {
+            // ill-conditioned in fp32: the whole solve again in FP64
+            if (a.n_fp64) atomicAdd(a.n_fp64, 1u);
+            double Gd[KMAX * (KMAX + 1) / 2];
+            const float* qrow = a.qfeat + (int64_t)q * D;
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j <= i; ++j) {
+                    const int64_t bi = (int64_t)a.ids[(int64_t)q * K + i] * D;
+                    const int64_t bj = (int64_t)a.ids[(int64_t)q * K + j] * D;
+                    double g = 0.0;
+                    for (int t = 0; t < D; ++t) {
+                        const double zi = (double)qrow[t] - (double)join_planes(a.hi[bi + t], a.lo[bi + t]);
+                        const double zj = (double)qrow[t] - (double)join_planes(a.hi[bj + t], a.lo[bj + t]);
+                        g += zi * zj;
+                    }
+                    Gd[i * (i + 1) / 2 + j] = g;
+                }
+            double td = 0.0;
+            for (int i = 0; i < m; ++i) td += Gd[i * (i + 1) / 2 + i];
+            for (int i = 0; i < m; ++i) Gd[i * (i + 1) / 2 + i] += (double)a.lam * td;
+            for (int j = 0; j < m; ++j) {
+                double s = Gd[j * (j + 1) / 2 + j];
+                for (int k = 0; k < j; ++k) s -= Gd[j * (j + 1) / 2 + k] * Gd[j * (j + 1) / 2 + k];
+                const double d = sqrt(s);
+                Gd[j * (j + 1) / 2 + j] = d;
+                for (int i = j + 1; i < m; ++i) {
+                    double t = Gd[i * (i + 1) / 2 + j];
+                    for (int k = 0; k < j; ++k) t -= Gd[i * (i + 1) / 2 + k] * Gd[j * (j + 1) / 2 + k];
+                    Gd[i * (i + 1) / 2 + j] = t / d;
+                }
+            }
+            double yd[KMAX], xd[KMAX], sd = 0.0;
+            for (int i = 0; i < m; ++i) {
+                double s = 1.0;
+                for (int k = 0; k < i; ++k) s -= Gd[i * (i + 1) / 2 + k] * yd[k];
+                yd[i] = s / Gd[i * (i + 1) / 2 + i];
+            }
+            for (int i = m - 1; i >= 0; --i) {
+                double s = yd[i];
+                for (int k = i + 1; k < m; ++k) s -= Gd[k * (k + 1) / 2 + i] * xd[k];
+                xd[i] = s / Gd[i * (i + 1) / 2 + i];
+            }
+            for (int i = 0; i < m; ++i) sd += xd[i];
+            for (int i = 0; i < m; ++i) wv[i] = (T)(xd[i] / sd);
+        }
+        for (int r = 0; r < K; ++r) wout[r] = r < m ? (float)wv[r] : 0.0f;
+    }
+}
+
+// x_q = mu_q + sum_m w_m r_{n_m}: one wave per patch.
+__global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int32_t* __restrict__ ids,
+                                               const int32_t* __restrict__ m, const float* __restrict__ w,
+                                               const double* __restrict__ mu, const float* __restrict__ resid,
+                                               float* __restrict__ xhat) {
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * (blockDim.x >> 6);
+    for (int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < Q; q += nw) {
+        const int mq = m[q];
+        if (mq <= 0) continue;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < mq; ++r) {
+            const int64_t b = (int64_t)ids[(int64_t)q * K + r] * ps2;
+            const float wr = w[(int64_t)q * K + r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = lane + 64 * u;
+                if (p < ps2) acc[u] = fmaf(wr, resid[b + p], acc[u]);
+            }
+        }
+        const float mf = (float)mu[q];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = lane + 64 * u;
+            if (p < ps2) xhat[(int64_t)q * ps2 + p] = mf + acc[u];
+        }
+    }
+}
+
+// Per HR pixel: mean of the synthesised patches covering it (patches in
+// row-major order); bicubic of the LR image where no patch covers it.
+__global__ void k_blend(const float* __restrict__ xhat, const int32_t* __restrict__ m,
+                        const float* __restrict__ lr, int h, int w, int s, float* __restrict__ hr) {
+    const int H = s * h, W = s * w, ps = kPatch * s, ps2 = ps * ps;
+    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
+    const int64_t total = (int64_t)H * W;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int Y = (int)(idx / W), X = (int)(idx % W);
+        const int ilo = Y - ps + 1 <= 0 ? 0 : (Y - ps + s) / s;
+        const int ihi = min(npi - 1, Y / s);
+        const int jlo = X - ps + 1 <= 0 ? 0 : (X - ps + s) / s;
+        const int jhi = min(npj - 1, X / s);
+        float acc = 0.0f;
+        int cnt = 0;
+        for (int i = ilo; i <= ihi; ++i)
+            for (int j = jlo; j <= jhi; ++j) {
+                const int q = i * npj + j;
+                if (m[q] > 0) {
+                    acc += xhat[(int64_t)q * ps2 + (Y - s * i) * ps + (X - s * j)];
+                    ++cnt;
+                }
+            }
+        hr[idx] = cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
+    }
+}
+
+hipError_t lle_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 64 && g_pair_table_ready[dev]) return hipSuccess;
+    uint8_t pa[136], pb[136];
+    int p = 0;
+    for (int i = 0; i < 16; ++i)
+        for (int j = 0; j <= i; ++j) {
+            pa[p] = (uint8_t)i;
+            pb[p] = (uint8_t)j;
+            ++p;
+        }
+    e = hipMemcpyToSymbol(HIP_SYMBOL(c_pa), pa, sizeof(pa));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_pb), pb, sizeof(pb));
+    if (e == hipSuccess && dev < 64) g_pair_table_ready[dev] = true;
+    return e;
+}
+
+hipError_t launch_lle(const LleArgs& a, hipStream_t st) {
+    if (a.Q == 0) return hipSuccess;
+    if (a.D > 128 || a.K > kMaxK) return hipErrorInvalidValue;
+    if (a.K <= 8) {
+        const int grid = (a.Q + 63) / 64;
+        if (a.fp64) hipLaunchKernelGGL((k_lle<double, 8, 64>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_lle<float, 8, 64>), dim3(grid), dim3(64), 0, st, a);
+    } else {
+        const int grid = (a.Q + 15) / 16;
+        if (a.fp64) hipLaunchKernelGGL((k_lle<double, 16, 16>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_lle<float, 16, 16>), dim3(grid), dim3(64), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m, const float* w,
+                        const double* mu, const float* resid, float* xhat, hipStream_t st) {
+    if (Q == 0) return hipSuccess;
+    if (ps2 > 256) return hipErrorInvalidValue;
+    int grid = (Q + 3) / 4;
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_synth, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, int h, int w, int scale,
+                        float* hr, hipStream_t st) {
+    const int64_t total = (int64_t)scale * h * scale * w;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_blend, dim3((unsigned)g), dim3(256), 0, st, xhat, m, lr, h, w, scale, hr);
+    return hipGetLastError();
+}
+
+}  // namespace zh

@@ -1,0 +1,667 @@
+// C-ABI of libzoomhash: context, argument and state checks, device buffer
+// management, hash-parameter generation and the orchestration of the
+// kernels of the zoom path. Compiled without multiply-add contraction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/zoomhash.h"
+#include "zh_internal.h"
+
+using namespace zh;
+
+namespace {
+
+// ---- device buffers ---------------------------------------------------------
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Dict {
+    bool valid = false;
+    int scale = 0, D = 0, mode = 0;
+    int64_t n = 0;
+    int L = 0, k = 0;
+    float w = 0.f;
+    uint64_t seed = 0;
+    uint64_t cap = 0;             // directory slots per table
+    const float* resid = nullptr; // borrowed
+    Buf hi, lo;                   // [n, D] split planes
+    Buf alpha, beta, anorm, ahi, alo;
+    Buf dir;                      // [L, cap] Slot
+    Buf tids;                     // [L, n] uint32
+    std::vector<float> h_alpha, h_beta;
+};
+
+constexpr int kNumCounters = 8;
+enum { C_OVERFLOW = 0, C_RANKFB = 1, C_UNSUP = 2, C_CODEFIX = 3, C_LLE64 = 4 };
+
+}  // namespace
+
+struct zh_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    size_t mem_limit = 0, mem_used = 0;
+    Dict dicts[4];                // scale 1..3 (index = scale)
+    zh_query_opts opts{0, 0, 1, 1};
+    // last query
+    int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
+    int qh = 0, qw = 0, qscale = 0, qK = 0;
+    int64_t Q = 0;
+    Buf lr, maps, qfeat, qmu, qkeys, ids, d2, m, ncand, w, over, xhat, e, tmp, counters;
+    Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
+};
+
+namespace {
+
+zh_status fail(zh_ctx* c, zh_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIPCHK(c, expr)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail((c), ZH_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+zh_status ensure(zh_ctx* c, Buf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return ZH_OK;
+    if (b.p) {
+        hipFree(b.p);
+        c->mem_used -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (c->mem_limit && c->mem_used + bytes > c->mem_limit)
+        return fail(c, ZH_ENOMEM, "allocation of %zu bytes exceeds ZH_MEM_LIMIT", bytes);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, ZH_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    c->mem_used += bytes;
+    return ZH_OK;
+}
+
+void release(zh_ctx* c, Buf& b) {
+    if (b.p) {
+        hipFree(b.p);
+        c->mem_used -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+#define TRY(expr)                      \
+    do {                               \
+        zh_status s_ = (expr);         \
+        if (s_ != ZH_OK) return s_;    \
+    } while (0)
+
+template <typename T>
+T* P(Buf& b) { return static_cast<T*>(b.p); }
+
+// ---- hash parameters: SplitMix64 + Marsaglia polar normals -------------------
+struct SplitMix {
+    uint64_t s;
+    uint64_t next() {
+        s += kGolden;
+        return fmix64(s);
+    }
+    double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+    double normal() {
+        for (;;) {
+            const double u1 = 2.0 * uniform() - 1.0;
+            const double u2 = 2.0 * uniform() - 1.0;
+            const double s2 = u1 * u1 + u2 * u2;
+            if (s2 > 0.0 && s2 < 1.0) return u1 * std::sqrt(-2.0 * std::log(s2) / s2);
+        }
+    }
+};
+
+void hash_params(uint64_t seed, int L, int k, int D, double w, std::vector<float>& alpha,
+                 std::vector<float>& beta) {
+    alpha.assign((size_t)L * k * D, 0.f);
+    beta.assign((size_t)L * k, 0.f);
+    const double eps = 1e-3;
+    for (int l = 0; l < L; ++l) {
+        SplitMix g{fmix64(seed + kGolden * (uint64_t)(l + 1))};
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < D; ++i) {
+                const double a = g.normal();
+                double b = g.normal();
+                while (std::fabs(b) < eps) b = g.normal();
+                alpha[((size_t)l * k + j) * D + i] = (float)(a / b);
+            }
+        for (int j = 0; j < k; ++j) beta[(size_t)l * k + j] = (float)(g.uniform() * w);
+    }
+}
+
+uint16_t bf16_rne_host(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float bf16_f_host(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+Taps gauss_taps(double sigma) {
+    Taps t{};
+    t.R = (int)std::ceil(3.0 * sigma);
+    std::vector<double> e(2 * t.R + 1);
+    double s = 0.0;
+    for (int d = -t.R; d <= t.R; ++d) {
+        e[d + t.R] = std::exp(-(double)(d * d) / (2.0 * sigma * sigma));
+    }
+    for (double x : e) s = s + x;
+    for (int i = 0; i < 2 * t.R + 1; ++i) t.g[i] = e[i] / s;
+    return t;
+}
+
+zh_status set_device(zh_ctx* c) {
+    HIPCHK(c, hipSetDevice(c->device));
+    return ZH_OK;
+}
+
+int dim_of(int mode) { return mode == ZH_FEAT_MEANREM ? 25 : 100; }
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+zh_status clear_counters(zh_ctx* c) {
+    TRY(ensure(c, c->counters, kNumCounters * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, P<uint32_t>(c->counters), kNumCounters, 0u);
+    HIPCHK(c, hipGetLastError());
+    return ZH_OK;
+}
+
+zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
+    SearchArgs a{};
+    a.Q = (int)c->Q;
+    a.D = d.D;
+    a.L = d.L;
+    a.K = c->qK;
+    a.cap = c->opts.cap;
+    a.rerank = c->opts.rerank;
+    a.exact = c->opts.rerank == 0 ? 1 : 0;
+    a.qkeys = P<uint64_t>(c->qkeys);
+    a.qfeat = P<float>(c->qfeat);
+    a.dir = P<Slot>(d.dir);
+    a.dir_cap = d.cap;
+    a.tids = P<uint32_t>(d.tids);
+    a.N = d.n;
+    a.hi = P<uint16_t>(d.hi);
+    a.lo = P<uint16_t>(d.lo);
+    a.out_ids = P<int32_t>(c->ids);
+    a.out_d2 = P<float>(c->d2);
+    a.out_m = P<int32_t>(c->m);
+    a.out_ncand = P<int32_t>(c->ncand);
+    a.dump = dump;
+    a.dump_cap = dump_cap;
+    a.overflow = P<int32_t>(c->over);
+    a.counters = P<unsigned int>(c->counters);
+    HIPCHK(c, launch_search(a, c->stream));
+    if (a.cap == 0) HIPCHK(c, launch_search_overflow(a, 1024, c->stream));
+    return ZH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+zh_status zh_create(zh_ctx** out, int device, void* hip_stream) {
+    if (!out) return ZH_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return ZH_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) return ZH_EINVAL;
+    zh_ctx* c = new (std::nothrow) zh_ctx();
+    if (!c) return ZH_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (const char* lim = std::getenv("ZH_MEM_LIMIT")) c->mem_limit = (size_t)std::strtoull(lim, nullptr, 10);
+    if (hipSetDevice(device) != hipSuccess || lle_init() != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return ZH_EDEVICE;
+    }
+    *out = c;
+    return ZH_OK;
+}
+
+void zh_destroy(zh_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (Dict& d : c->dicts) {
+        release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.anorm);
+        release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.tids);
+    }
+    Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->ids, &c->d2, &c->m,
+                   &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict};
+    for (Buf* b : bufs) release(c, *b);
+    delete c;
+}
+
+zh_status zh_set_stream(zh_ctx* c, void* s) {
+    if (!c) return ZH_EINVAL;
+    c->stream = (hipStream_t)s;
+    return ZH_OK;
+}
+
+zh_status zh_sync(zh_ctx* c) {
+    if (!c) return ZH_EINVAL;
+    TRY(set_device(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ZH_OK;
+}
+
+const char* zh_last_error(const zh_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+zh_status zh_degrade(zh_ctx* c, const float* hr, int n_img, int H, int W, int scale, float sigma, float* lr) {
+    if (!c) return ZH_EINVAL;
+    if (!hr || !lr || n_img < 1 || H < 1 || W < 1 || scale < 1 || scale > 8 || !(sigma > 0.f) || sigma > 5.f)
+        return fail(c, ZH_EINVAL, "zh_degrade: bad arguments");
+    TRY(set_device(c));
+    HIPCHK(c, launch_degrade(hr, n_img, H, W, scale, gauss_taps(sigma), lr, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_make_dictionary(zh_ctx* c, const float* hr, int n_img, int H, int W, const int32_t* pos, int64_t n,
+                             int scale, float sigma, int mode, float* feat, float* resid) {
+    if (!c) return ZH_EINVAL;
+    if (!hr || !pos || !feat || !resid || n_img < 1 || n < 1 || n >= (1ll << 31) || scale < 1 || scale > 3 ||
+        (mode != ZH_FEAT_MEANREM && mode != ZH_FEAT_GRAD4) || !(sigma > 0.f) || sigma > 5.f)
+        return fail(c, ZH_EINVAL, "zh_make_dictionary: bad arguments");
+    const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
+    if (h < kPatch || w < kPatch) return fail(c, ZH_EINVAL, "zh_make_dictionary: images too small");
+    TRY(set_device(c));
+    TRY(ensure(c, c->tmp, sizeof(float) * (size_t)n_img * h * w * 5));
+    float* lrs = P<float>(c->tmp);
+    float* maps = lrs + (size_t)n_img * h * w;
+    HIPCHK(c, launch_degrade(hr, n_img, H, W, scale, gauss_taps(sigma), lrs, c->stream));
+    HIPCHK(c, launch_gradient_maps(lrs, n_img, h, w, maps, c->stream));
+    HIPCHK(c, launch_dict_cut(hr, lrs, maps, H, W, scale, pos, n, mode, feat, resid, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_features(zh_ctx* c, const float* lr, int h, int w, int mode, float* feat, double* mu) {
+    if (!c) return ZH_EINVAL;
+    if (!lr || !feat || h < kPatch || w < kPatch || (mode != ZH_FEAT_MEANREM && mode != ZH_FEAT_GRAD4))
+        return fail(c, ZH_EINVAL, "zh_features: bad arguments");
+    TRY(set_device(c));
+    const int64_t Q = (int64_t)(h - 4) * (w - 4);
+    TRY(ensure(c, c->maps, sizeof(float) * 4 * (size_t)h * w));
+    double* mup = mu;
+    if (!mup) {
+        TRY(ensure(c, c->qmu, sizeof(double) * (size_t)Q));
+        mup = P<double>(c->qmu);
+    }
+    if (mode == ZH_FEAT_GRAD4) HIPCHK(c, launch_gradient_maps(lr, 1, h, w, P<float>(c->maps), c->stream));
+    HIPCHK(c, launch_query_features(lr, P<float>(c->maps), h, w, mode, feat, mup, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, float w, uint64_t seed) {
+    if (!c) return ZH_EINVAL;
+    if (!dict || !dict->feat || !dict->resid || dict->n < 1 || dict->n >= (1ll << 31) ||
+        (dict->scale < 1 || dict->scale > 3) ||
+        (dict->feat_mode != ZH_FEAT_MEANREM && dict->feat_mode != ZH_FEAT_GRAD4) ||
+        dict->dim != dim_of(dict->feat_mode))
+        return fail(c, ZH_EINVAL, "zh_build_tables: bad dictionary");
+    if (L < 1 || L > kMaxL || k < 1 || k > kMaxKHash || !(w > 0.f) || !std::isfinite(w))
+        return fail(c, ZH_EINVAL, "zh_build_tables: need 1 <= L <= %d, 1 <= k <= %d, w > 0", kMaxL, kMaxKHash);
+    TRY(set_device(c));
+    Dict& d = c->dicts[dict->scale];
+    d.valid = false;
+    c->stage = 0;
+    const int64_t n = dict->n;
+    const int D = dict->dim;
+    d.scale = dict->scale;
+    d.D = D;
+    d.mode = dict->feat_mode;
+    d.n = n;
+    d.L = L;
+    d.k = k;
+    d.w = w;
+    d.seed = seed;
+    d.resid = dict->resid;
+    uint64_t cap = 1;
+    while (cap < 2 * (uint64_t)n) cap <<= 1;
+    d.cap = cap;
+    // split storage of the features
+    TRY(ensure(c, d.hi, sizeof(uint16_t) * (size_t)n * D));
+    TRY(ensure(c, d.lo, sizeof(uint16_t) * (size_t)n * D));
+    HIPCHK(c, launch_split_planes(dict->feat, n * D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
+    // hash parameters
+    hash_params(seed, L, k, D, (double)w, d.h_alpha, d.h_beta);
+    const int m = L * k;
+    const int DP = (D + 31) & ~31;
+    std::vector<float> anorm(m);
+    std::vector<uint16_t> ahi((size_t)m * DP, 0), alo((size_t)m * DP, 0);
+    for (int j = 0; j < m; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < D; ++i) {
+            const float a = d.h_alpha[(size_t)j * D + i];
+            s += (double)a * (double)a;
+            const uint16_t h = bf16_rne_host(a);
+            ahi[(size_t)j * DP + i] = h;
+            alo[(size_t)j * DP + i] = bf16_rne_host(a - bf16_f_host(h));
+        }
+        anorm[j] = (float)(std::sqrt(s) * (1.0 + 1e-12)) * (1.0f + 1e-6f);
+    }
+    TRY(ensure(c, d.alpha, sizeof(float) * (size_t)m * D));
+    TRY(ensure(c, d.beta, sizeof(float) * (size_t)m));
+    TRY(ensure(c, d.anorm, sizeof(float) * (size_t)m));
+    TRY(ensure(c, d.ahi, sizeof(uint16_t) * (size_t)m * DP));
+    TRY(ensure(c, d.alo, sizeof(uint16_t) * (size_t)m * DP));
+    HIPCHK(c, hipMemcpyAsync(d.alpha.p, d.h_alpha.data(), sizeof(float) * (size_t)m * D, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.beta.p, d.h_beta.data(), sizeof(float) * (size_t)m, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.anorm.p, anorm.data(), sizeof(float) * (size_t)m, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.ahi.p, ahi.data(), sizeof(uint16_t) * (size_t)m * DP, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.alo.p, alo.data(), sizeof(uint16_t) * (size_t)m * DP, hipMemcpyHostToDevice, c->stream));
+    // keys of every pair in every table
+    TRY(ensure(c, c->keys_dict, sizeof(uint64_t) * (size_t)n * L));
+    TRY(clear_counters(c));
+    HashArgs ha{};
+    ha.feat = dict->feat;
+    ha.n = n;
+    ha.D = D;
+    ha.L = L;
+    ha.k = k;
+    ha.alpha = P<float>(d.alpha);
+    ha.a_hi = P<uint16_t>(d.ahi);
+    ha.a_lo = P<uint16_t>(d.alo);
+    ha.beta = P<float>(d.beta);
+    ha.anorm = P<float>(d.anorm);
+    ha.w = w;
+    ha.prec = c->opts.proj;
+    ha.keys = P<uint64_t>(c->keys_dict);
+    ha.codes = nullptr;
+    ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
+    HIPCHK(c, launch_hash(ha, c->stream));
+    // directory and bins, table by table
+    TRY(ensure(c, d.dir, sizeof(Slot) * (size_t)L * cap));
+    TRY(ensure(c, d.tids, sizeof(uint32_t) * (size_t)L * n));
+    TRY(ensure(c, c->slot_of, sizeof(uint32_t) * (size_t)n));
+    TRY(ensure(c, c->idsort, sizeof(uint32_t) * (size_t)n));
+    TRY(ensure(c, c->rs_k1, sizeof(uint32_t) * (size_t)n));
+    TRY(ensure(c, c->rs_v1, sizeof(uint32_t) * (size_t)n));
+    const int64_t hs = radix_hist_size(n);
+    TRY(ensure(c, c->rs_hist, sizeof(uint32_t) * (size_t)hs));
+    int bits = 0;
+    while ((1ull << bits) < cap) ++bits;
+    HIPCHK(c, launch_dir_clear(P<Slot>(d.dir), (uint64_t)L * cap, c->stream));
+    for (int l = 0; l < L; ++l) {
+        Slot* dl = P<Slot>(d.dir) + (size_t)l * cap;
+        HIPCHK(c, launch_dir_insert(P<uint64_t>(c->keys_dict), n, L, l, dl, cap, P<uint32_t>(c->slot_of),
+                                    P<uint32_t>(c->idsort), c->stream));
+        bool in_first = true;
+        HIPCHK(c, radix_sort_pairs(P<uint32_t>(c->slot_of), P<uint32_t>(c->idsort), P<uint32_t>(c->rs_k1),
+                                   P<uint32_t>(c->rs_v1), n, bits, P<uint32_t>(c->rs_hist), hs, c->stream, &in_first));
+        const uint32_t* sk = in_first ? P<uint32_t>(c->slot_of) : P<uint32_t>(c->rs_k1);
+        const uint32_t* sv = in_first ? P<uint32_t>(c->idsort) : P<uint32_t>(c->rs_v1);
+        HIPCHK(c, launch_dir_offsets(sk, n, dl, c->stream));
+        HIPCHK(c, hipMemcpyAsync(P<uint32_t>(d.tids) + (size_t)l * n, sv, sizeof(uint32_t) * (size_t)n,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    release(c, c->keys_dict);
+    d.valid = true;
+    return ZH_OK;
+}
+
+zh_status zh_get_hash_params(zh_ctx* c, int scale, float* alpha, float* beta) {
+    if (!c) return ZH_EINVAL;
+    if (scale < 1 || scale > 3 || !c->dicts[scale].valid) return fail(c, ZH_ESTATE, "no tables for scale %d", scale);
+    const Dict& d = c->dicts[scale];
+    if (alpha) std::memcpy(alpha, d.h_alpha.data(), sizeof(float) * d.h_alpha.size());
+    if (beta) std::memcpy(beta, d.h_beta.data(), sizeof(float) * d.h_beta.size());
+    return ZH_OK;
+}
+
+zh_status zh_hash(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* codes, uint64_t* keys) {
+    if (!c) return ZH_EINVAL;
+    if (scale < 1 || scale > 3 || !c->dicts[scale].valid) return fail(c, ZH_ESTATE, "no tables for scale %d", scale);
+    if (!feat || n < 0) return fail(c, ZH_EINVAL, "zh_hash: bad arguments");
+    TRY(set_device(c));
+    Dict& d = c->dicts[scale];
+    uint64_t* kp = keys;
+    if (!kp) {
+        TRY(ensure(c, c->tmp, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1) * d.L));
+        kp = P<uint64_t>(c->tmp);
+    }
+    TRY(clear_counters(c));
+    HashArgs ha{};
+    ha.feat = feat;
+    ha.n = n;
+    ha.D = d.D;
+    ha.L = d.L;
+    ha.k = d.k;
+    ha.alpha = P<float>(d.alpha);
+    ha.a_hi = P<uint16_t>(d.ahi);
+    ha.a_lo = P<uint16_t>(d.alo);
+    ha.beta = P<float>(d.beta);
+    ha.anorm = P<float>(d.anorm);
+    ha.w = d.w;
+    ha.prec = c->opts.proj;
+    ha.keys = kp;
+    ha.codes = codes;
+    ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
+    HIPCHK(c, launch_hash(ha, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_set_query_opts(zh_ctx* c, const zh_query_opts* o) {
+    if (!c) return ZH_EINVAL;
+    if (!o || o->cap < 0 || o->cap > 256 || o->rerank < 0 || o->rerank > 64 || (o->proj != 0 && o->proj != 1) ||
+        (o->lle_fp64 != 0 && o->lle_fp64 != 1))
+        return fail(c, ZH_EINVAL, "zh_set_query_opts: cap in [0,256], rerank in [0,64], proj and lle_fp64 in {0,1}");
+    c->opts = *o;
+    return ZH_OK;
+}
+
+zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
+    if (!c) return ZH_EINVAL;
+    if (!lr || h < kPatch || w < kPatch || K < 1 || K > kMaxK)
+        return fail(c, ZH_EINVAL, "zh_query: need lr, h, w >= 5 and 1 <= K <= %d", kMaxK);
+    if (scale < 1 || scale > 3 || !c->dicts[scale].valid)
+        return fail(c, ZH_ESTATE, "zh_query: no tables built for scale %d", scale);
+    if (c->opts.rerank > 0 && c->opts.rerank < K)
+        return fail(c, ZH_EINVAL, "zh_query: rerank %d below K %d", c->opts.rerank, K);
+    const int64_t Q = (int64_t)(h - 4) * (w - 4);
+    if (Q >= (1ll << 31) / kMaxK) return fail(c, ZH_EINVAL, "zh_query: image too large");
+    TRY(set_device(c));
+    Dict& d = c->dicts[scale];
+    c->stage = 0;
+    const int ps2 = (kPatch * scale) * (kPatch * scale);
+    TRY(ensure(c, c->lr, sizeof(float) * (size_t)h * w));
+    TRY(ensure(c, c->maps, sizeof(float) * 4 * (size_t)h * w));
+    TRY(ensure(c, c->qfeat, sizeof(float) * (size_t)Q * d.D));
+    TRY(ensure(c, c->qmu, sizeof(double) * (size_t)Q));
+    TRY(ensure(c, c->qkeys, sizeof(uint64_t) * (size_t)Q * d.L));
+    TRY(ensure(c, c->ids, sizeof(int32_t) * (size_t)Q * K));
+    TRY(ensure(c, c->d2, sizeof(float) * (size_t)Q * K));
+    TRY(ensure(c, c->w, sizeof(float) * (size_t)Q * K));
+    TRY(ensure(c, c->m, sizeof(int32_t) * (size_t)Q));
+    TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)Q));
+    TRY(ensure(c, c->over, sizeof(int32_t) * (size_t)Q));
+    TRY(ensure(c, c->xhat, sizeof(float) * (size_t)Q * ps2));
+    HIPCHK(c, hipMemcpyAsync(c->lr.p, lr, sizeof(float) * (size_t)h * w, hipMemcpyDeviceToDevice, c->stream));
+    c->qh = h;
+    c->qw = w;
+    c->qscale = scale;
+    c->qK = K;
+    c->Q = Q;
+    TRY(clear_counters(c));
+    if (d.mode == ZH_FEAT_GRAD4) HIPCHK(c, launch_gradient_maps(P<float>(c->lr), 1, h, w, P<float>(c->maps), c->stream));
+    HIPCHK(c, launch_query_features(P<float>(c->lr), P<float>(c->maps), h, w, d.mode, P<float>(c->qfeat),
+                                    P<double>(c->qmu), c->stream));
+    HashArgs ha{};
+    ha.feat = P<float>(c->qfeat);
+    ha.n = Q;
+    ha.D = d.D;
+    ha.L = d.L;
+    ha.k = d.k;
+    ha.alpha = P<float>(d.alpha);
+    ha.a_hi = P<uint16_t>(d.ahi);
+    ha.a_lo = P<uint16_t>(d.alo);
+    ha.beta = P<float>(d.beta);
+    ha.anorm = P<float>(d.anorm);
+    ha.w = d.w;
+    ha.prec = c->opts.proj;
+    ha.keys = P<uint64_t>(c->qkeys);
+    ha.codes = nullptr;
+    ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
+    HIPCHK(c, launch_hash(ha, c->stream));
+    TRY(run_search(c, d, nullptr, 0));
+    c->stage = 1;
+    return ZH_OK;
+}
+
+zh_status zh_lle_weights(zh_ctx* c, float lambda) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_lle_weights before zh_query");
+    if (!(lambda > 0.f) || !std::isfinite(lambda)) return fail(c, ZH_EINVAL, "zh_lle_weights: lambda must be > 0");
+    TRY(set_device(c));
+    Dict& d = c->dicts[c->qscale];
+    LleArgs a{};
+    a.Q = (int)c->Q;
+    a.D = d.D;
+    a.K = c->qK;
+    a.qfeat = P<float>(c->qfeat);
+    a.ids = P<int32_t>(c->ids);
+    a.m = P<int32_t>(c->m);
+    a.hi = P<uint16_t>(d.hi);
+    a.lo = P<uint16_t>(d.lo);
+    a.lam = lambda;
+    a.fp64 = c->opts.lle_fp64;
+    a.w = P<float>(c->w);
+    a.n_fp64 = P<unsigned int>(c->counters) + C_LLE64;
+    HIPCHK(c, launch_lle(a, c->stream));
+    c->stage = 2;
+    return ZH_OK;
+}
+
+zh_status zh_reconstruct(zh_ctx* c, float* hr_out) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 2) return fail(c, ZH_ESTATE, "zh_reconstruct before zh_lle_weights");
+    if (!hr_out) return fail(c, ZH_EINVAL, "zh_reconstruct: null output");
+    TRY(set_device(c));
+    Dict& d = c->dicts[c->qscale];
+    const int s = c->qscale, ps2 = (kPatch * s) * (kPatch * s);
+    HIPCHK(c, launch_synth((int)c->Q, c->qK, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
+                           P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
+    HIPCHK(c, launch_blend(P<float>(c->xhat), P<int32_t>(c->m), P<float>(c->lr), c->qh, c->qw, s, hr_out,
+                           c->stream));
+    c->stage = 3;
+    return ZH_OK;
+}
+
+zh_status zh_backproject(zh_ctx* c, float* hr, int iters, float sigma_s, float sigma_r) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_backproject needs the LR image of a zh_query");
+    if (!hr || iters < 0 || !(sigma_s > 0.f) || std::ceil(3.0 * sigma_s) > 8.0 || !(sigma_r > 0.f))
+        return fail(c, ZH_EINVAL, "zh_backproject: need iters >= 0, 0 < sigma_s <= 8/3, sigma_r > 0");
+    TRY(set_device(c));
+    const int s = c->qscale, H = s * c->qh, W = s * c->qw;
+    TRY(ensure(c, c->e, sizeof(float) * (size_t)c->qh * c->qw));
+    TRY(ensure(c, c->tmp, sizeof(float) * (size_t)H * W));
+    const Taps g = gauss_taps(1.0);
+    float* a = hr;
+    float* b = P<float>(c->tmp);
+    for (int t = 0; t < iters; ++t) {
+        HIPCHK(c, launch_degrade_residual(a, H, W, s, g, P<float>(c->lr), P<float>(c->e), c->stream));
+        HIPCHK(c, launch_bp_update(a, P<float>(c->e), H, W, c->qh, c->qw, s, sigma_s, sigma_r, b, c->stream));
+        float* t2 = a; a = b; b = t2;
+    }
+    if (a != hr)
+        HIPCHK(c, hipMemcpyAsync(hr, a, sizeof(float) * (size_t)H * W, hipMemcpyDeviceToDevice, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_get_results(zh_ctx* c, int32_t* ids, float* d2, int32_t* m, float* w, int32_t* ncand) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_get_results before zh_query");
+    if (w && c->stage < 2) return fail(c, ZH_ESTATE, "weights requested before zh_lle_weights");
+    TRY(set_device(c));
+    const size_t QK = (size_t)c->Q * c->qK, Q = (size_t)c->Q;
+    if (ids) HIPCHK(c, hipMemcpyAsync(ids, c->ids.p, QK * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (d2) HIPCHK(c, hipMemcpyAsync(d2, c->d2.p, QK * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (m) HIPCHK(c, hipMemcpyAsync(m, c->m.p, Q * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (w) HIPCHK(c, hipMemcpyAsync(w, c->w.p, QK * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (ncand) HIPCHK(c, hipMemcpyAsync(ncand, c->ncand.p, Q * 4, hipMemcpyDeviceToDevice, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_query_shape(zh_ctx* c, int64_t* Q, int32_t* D) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "no query");
+    if (Q) *Q = c->Q;
+    if (D) *D = c->dicts[c->qscale].D;
+    return ZH_OK;
+}
+
+zh_status zh_candidates(zh_ctx* c, int32_t cap_per_query, int32_t* counts, int32_t* ids) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_candidates before zh_query");
+    if (cap_per_query < 1 || !counts || !ids) return fail(c, ZH_EINVAL, "zh_candidates: bad arguments");
+    TRY(set_device(c));
+    TRY(clear_counters(c));
+    TRY(run_search(c, c->dicts[c->qscale], ids, cap_per_query));
+    HIPCHK(c, hipMemcpyAsync(counts, c->ncand.p, (size_t)c->Q * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (c->stage > 1) c->stage = 1;
+    return ZH_OK;
+}
+
+zh_status zh_stats(zh_ctx* c, zh_stats_t* out) {
+    if (!c) return ZH_EINVAL;
+    if (!out) return fail(c, ZH_EINVAL, "zh_stats: null output");
+    TRY(set_device(c));
+    std::memset(out, 0, sizeof(*out));
+    uint32_t h[kNumCounters] = {0};
+    if (c->counters.p) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(h, c->counters.p, sizeof(h), hipMemcpyDeviceToHost));
+    }
+    out->queries = (uint64_t)c->Q;
+    out->codes_fixed = h[C_CODEFIX];
+    out->rank_fallbacks = h[C_RANKFB];
+    out->deferred = h[C_OVERFLOW];
+    out->unsupported = h[C_UNSUP];
+    out->lle_fp64 = h[C_LLE64];
+    uint64_t db = 0;
+    for (const Dict& d : c->dicts)
+        db += d.hi.bytes + d.lo.bytes + d.dir.bytes + d.tids.bytes + d.alpha.bytes + d.ahi.bytes + d.alo.bytes;
+    out->dict_bytes = db;
+    return ZH_OK;
+}
+
+}  // extern "C"

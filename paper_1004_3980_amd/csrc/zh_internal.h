@@ -1,0 +1,119 @@
+// Internal launcher interface of libzoomhash (host side). Every launcher
+// enqueues on `st` and returns the hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "zh_device.h"
+
+namespace zh {
+
+constexpr int kPatch = 5;       // LR patch side
+constexpr int kMaxTaps = 33;    // longest 1-D Gaussian the kernels accept
+constexpr int kMaxK = 16;       // neighbours per patch
+constexpr int kMaxL = 64;       // hash tables
+constexpr int kMaxKHash = 32;   // hashes per table
+
+struct Taps {                   // normalised 1-D Gaussian, offsets -R..R
+    double g[kMaxTaps];
+    int R;
+};
+
+// ---- image kernels (k_image.hip) -------------------------------------------
+hipError_t launch_degrade(const float* hr, int n_img, int H, int W, int scale, const Taps& t,
+                          float* lr, hipStream_t st);
+// e = lr_ref - degrade(hr), fp32 [h, w]
+hipError_t launch_degrade_residual(const float* hr, int H, int W, int scale, const Taps& t,
+                                   const float* lr_ref, float* e, hipStream_t st);
+hipError_t launch_gradient_maps(const float* lr, int n_img, int h, int w, float* maps,
+                                hipStream_t st);
+// features of every stride-1 patch of one LR image (row-major patch order)
+hipError_t launch_query_features(const float* lr, const float* maps, int h, int w, int mode,
+                                 float* feat, double* mu, hipStream_t st);
+hipError_t launch_dict_cut(const float* hr, const float* lr, const float* maps, int H, int W,
+                           int scale, const int32_t* pos, int64_t n, int mode, float* feat,
+                           float* resid, hipStream_t st);
+hipError_t launch_split_planes(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
+                               hipStream_t st);
+hipError_t launch_bicubic(const float* lr, int h, int w, int scale, float* out, hipStream_t st);
+
+// ---- hashing (k_hash.hip) ----------------------------------------------------
+struct HashArgs {
+    const float* feat;       // [n, D] fp32
+    int64_t n;
+    int D;
+    int L, k;
+    const float* alpha;      // [L*k, D] fp32
+    const uint16_t* a_hi;    // [L*k, DP] bf16 high parts (split projection), DP = D rounded to 32
+    const uint16_t* a_lo;    // [L*k, DP] bf16 low parts
+    const float* beta;       // [L*k]
+    const float* anorm;      // [L*k] upper bound of ||alpha_j||_2
+    float w;
+    int prec;                // 0 = fp32 MFMA, 1 = split bf16 MFMA
+    uint64_t* keys;          // [n, L]
+    int32_t* codes;          // [n, L*k] or null
+    unsigned int* n_fixed;   // count of codes recomputed in FP64 (nullable)
+};
+hipError_t launch_hash(const HashArgs& a, hipStream_t st);
+
+// ---- table build (k_table.hip) ----------------------------------------------
+hipError_t launch_dir_clear(Slot* dir, uint64_t count, hipStream_t st);
+hipError_t launch_dir_insert(const uint64_t* keys, int64_t n, int L, int l, Slot* dir,
+                             uint64_t cap, uint32_t* slot_of, uint32_t* ids, hipStream_t st);
+hipError_t launch_dir_offsets(const uint32_t* sorted_slot, int64_t n, Slot* dir, hipStream_t st);
+// stable LSD radix sort of (key, val) pairs on the low `bits` bits of key
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
+                            int bits, uint32_t* hist, int64_t hist_cap, hipStream_t st,
+                            bool* result_in_first);
+int64_t radix_hist_size(int64_t n);
+
+// ---- search (k_search.hip) ---------------------------------------------------
+struct SearchArgs {
+    int Q, D, L, K, cap, rerank, exact;
+    const uint64_t* qkeys;   // [Q, L]
+    const float* qfeat;      // [Q, D]
+    const Slot* dir;
+    uint64_t dir_cap;
+    const uint32_t* tids;    // [L, N]
+    int64_t N;
+    const uint16_t* hi;
+    const uint16_t* lo;
+    int32_t* out_ids;        // [Q, K]
+    float* out_d2;           // [Q, K]
+    int32_t* out_m;          // [Q]
+    int32_t* out_ncand;      // [Q]
+    int32_t* dump;           // [Q, dump_cap] or null
+    int dump_cap;
+    int32_t* overflow;       // [Q] deferred queries (uncapped, too many IDs for a wave)
+    unsigned int* counters;  // [0] overflow count, [1] FP64 rank fallbacks
+};
+hipError_t launch_search(const SearchArgs& a, hipStream_t st);
+hipError_t launch_search_overflow(const SearchArgs& a, int n_over, hipStream_t st);
+
+// ---- LLE, synthesis, blend (k_lle.hip) --------------------------------------
+struct LleArgs {
+    int Q, D, K;
+    const float* qfeat;
+    const int32_t* ids;
+    const int32_t* m;
+    const uint16_t* hi;
+    const uint16_t* lo;
+    float lam;
+    int fp64;                // 1: FP64 Gram and solve; 0: FP32, FP64 redo when cond > 1e6
+    float* w;                // [Q, K]
+    unsigned int* n_fp64;    // FP64 redo count (nullable)
+};
+hipError_t lle_init();  // once per device, before any launch_lle
+hipError_t launch_lle(const LleArgs& a, hipStream_t st);
+hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m,
+                        const float* w, const double* mu, const float* resid, float* xhat,
+                        hipStream_t st);
+hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, int h, int w,
+                        int scale, float* hr, hipStream_t st);
+
+// ---- back-projection (k_bp.hip) ---------------------------------------------
+hipError_t launch_bp_update(const float* I, const float* e, int H, int W, int h, int w,
+                            int scale, float sigma_s, float sigma_r, float* out,
+                            hipStream_t st);
+
+}  // namespace zh

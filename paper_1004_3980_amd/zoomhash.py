@@ -1,0 +1,205 @@
+"""Thin ctypes binding of libzoomhash (include/zoomhash.h).
+
+Functions keep the C names; arrays are passed as torch CUDA/HIP tensors (their
+device pointers are handed to the library), host arrays as numpy arrays.
+Nothing here computes any part of the zoom path: every step runs in the HIP
+kernels of libzoomhash.so, and loading fails loudly when the library is
+missing or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzoomhash.so")
+
+ZH_OK, ZH_EINVAL, ZH_ESTATE, ZH_ENOMEM, ZH_EDEVICE, ZH_EUNSUPPORTED = range(6)
+ZH_FEAT_MEANREM, ZH_FEAT_GRAD4 = 0, 1
+STATUS_NAMES = {0: "ZH_OK", 1: "ZH_EINVAL", 2: "ZH_ESTATE", 3: "ZH_ENOMEM", 4: "ZH_EDEVICE",
+                5: "ZH_EUNSUPPORTED"}
+
+
+class ZHError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class zh_dictionary(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("scale", ctypes.c_int32),
+                ("feat_mode", ctypes.c_int32), ("feat", ctypes.c_void_p),
+                ("resid", ctypes.c_void_p)]
+
+
+class zh_query_opts(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int32), ("rerank", ctypes.c_int32), ("proj", ctypes.c_int32),
+                ("lle_fp64", ctypes.c_int32)]
+
+
+class zh_stats_t(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_uint64), ("codes_fixed", ctypes.c_uint64),
+                ("rank_fallbacks", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                ("unsupported", ctypes.c_uint64), ("lle_fp64", ctypes.c_uint64),
+                ("dict_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_V, _I, _I64, _U64, _F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
+SIGNATURES = {
+    "zh_create": [ctypes.POINTER(_V), _I, _V],
+    "zh_destroy": [_V],
+    "zh_set_stream": [_V, _V],
+    "zh_sync": [_V],
+    "zh_last_error": [_V],
+    "zh_degrade": [_V, _V, _I, _I, _I, _I, _F, _V],
+    "zh_make_dictionary": [_V, _V, _I, _I, _I, _V, _I64, _I, _F, _I, _V, _V],
+    "zh_features": [_V, _V, _I, _I, _I, _V, _V],
+    "zh_build_tables": [_V, ctypes.POINTER(zh_dictionary), _I, _I, _F, _U64],
+    "zh_get_hash_params": [_V, _I, _V, _V],
+    "zh_hash": [_V, _I, _V, _I64, _V, _V],
+    "zh_set_query_opts": [_V, ctypes.POINTER(zh_query_opts)],
+    "zh_query": [_V, _V, _I, _I, _I, _I],
+    "zh_lle_weights": [_V, _F],
+    "zh_reconstruct": [_V, _V],
+    "zh_backproject": [_V, _V, _I, _F, _F],
+    "zh_get_results": [_V, _V, _V, _V, _V, _V],
+    "zh_query_shape": [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)],
+    "zh_candidates": [_V, ctypes.c_int32, _V, _V],
+    "zh_stats": [_V, ctypes.POINTER(zh_stats_t)],
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libzoomhash.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with paper_1004_3980_amd/build.py")
+        lib = ctypes.CDLL(path)
+        for name, args in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = None if name == "zh_destroy" else (
+                ctypes.c_char_p if name == "zh_last_error" else ctypes.c_int32)
+        _lib = lib
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    if not t.is_cuda:
+        raise ValueError("libzoomhash takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libzoomhash takes contiguous tensors")
+    return t.data_ptr()
+
+
+class Context:
+    """Owns one zh_ctx; raises ZHError on a nonzero status."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        st = self.lib.zh_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != ZH_OK:
+            raise ZHError(st, "zh_create failed")
+        self.h = h
+        self.device = device
+        self._keep = []
+
+    def _chk(self, st):
+        if st != ZH_OK:
+            raise ZHError(st, self.lib.zh_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.zh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls with the C names (minus the zh_ prefix on the method) --
+    def sync(self):
+        self._chk(self.lib.zh_sync(self.h))
+
+    def degrade(self, hr, n_img, H, W, scale, sigma, lr):
+        self._chk(self.lib.zh_degrade(self.h, _ptr(hr), n_img, H, W, scale, sigma, _ptr(lr)))
+
+    def make_dictionary(self, hr, n_img, H, W, pos, n, scale, sigma, feat_mode, feat, resid):
+        self._chk(self.lib.zh_make_dictionary(self.h, _ptr(hr), n_img, H, W, _ptr(pos), n, scale,
+                                              sigma, feat_mode, _ptr(feat), _ptr(resid)))
+
+    def features(self, lr, h, w, feat_mode, feat, mu=None):
+        self._chk(self.lib.zh_features(self.h, _ptr(lr), h, w, feat_mode, _ptr(feat), _ptr(mu)))
+
+    def build_tables(self, feat, resid, n, dim, scale, feat_mode, L, k, w, seed):
+        d = zh_dictionary(n, dim, scale, feat_mode, _ptr(feat), _ptr(resid))
+        self._chk(self.lib.zh_build_tables(self.h, ctypes.byref(d), L, k, w, seed))
+        self._keep = [t for t in self._keep if getattr(t, "_zh_scale", None) != scale]
+        for t in (feat, resid):
+            try:
+                t._zh_scale = scale
+            except AttributeError:
+                pass
+            self._keep.append(t)
+
+    def get_hash_params(self, scale, L, k, D):
+        a = np.empty(L * k * D, dtype=np.float32)
+        b = np.empty(L * k, dtype=np.float32)
+        self._chk(self.lib.zh_get_hash_params(self.h, scale, a.ctypes.data, b.ctypes.data))
+        return a.reshape(L * k, D), b
+
+    def hash(self, scale, feat, n, codes=None, keys=None):
+        self._chk(self.lib.zh_hash(self.h, scale, _ptr(feat), n, _ptr(codes), _ptr(keys)))
+
+    def set_query_opts(self, cap=0, rerank=0, proj=1, lle_fp64=1):
+        o = zh_query_opts(cap, rerank, proj, lle_fp64)
+        self._chk(self.lib.zh_set_query_opts(self.h, ctypes.byref(o)))
+
+    def query(self, lr, h, w, scale, K):
+        self._chk(self.lib.zh_query(self.h, _ptr(lr), h, w, scale, K))
+
+    def lle_weights(self, lam):
+        self._chk(self.lib.zh_lle_weights(self.h, lam))
+
+    def reconstruct(self, hr_out):
+        self._chk(self.lib.zh_reconstruct(self.h, _ptr(hr_out)))
+
+    def backproject(self, hr, iters, sigma_s, sigma_r):
+        self._chk(self.lib.zh_backproject(self.h, _ptr(hr), iters, sigma_s, sigma_r))
+
+    def get_results(self, ids=None, d2=None, m=None, w=None, ncand=None):
+        self._chk(self.lib.zh_get_results(self.h, _ptr(ids), _ptr(d2), _ptr(m), _ptr(w), _ptr(ncand)))
+
+    def query_shape(self):
+        Q = ctypes.c_int64()
+        D = ctypes.c_int32()
+        self._chk(self.lib.zh_query_shape(self.h, ctypes.byref(Q), ctypes.byref(D)))
+        return Q.value, D.value
+
+    def candidates(self, cap_per_query, counts, ids):
+        self._chk(self.lib.zh_candidates(self.h, cap_per_query, _ptr(counts), _ptr(ids)))
+
+    def stats(self):
+        s = zh_stats_t()
+        self._chk(self.lib.zh_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
