@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Throughput of the patch-hashing zoom path on one MI355X.
+
+Metric: LR patches/s of hash + K-NN + LLE + blend (zh_query, zh_lle_weights,
+zh_reconstruct) on a 1024x1024 LR image at x2 (1,040,400 patches) against a
+2,000,000-pair dictionary (4-gradient features, D = 100), L = 24 tables of
+k = 20 hashes, K = 8, with the dictionary, tables and LR image resident in
+HBM. The default form screens candidates on the bf16 half of the features and
+re-ranks the best 32 exactly in fp32 ("screened"); --form exact ranks every
+candidate with fp32 distances certified against FP64.
+
+One JSON line on stdout. Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def psnr(x, ref):
+    mse = float(np.mean((np.asarray(x, np.float64) - np.asarray(ref, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def search_bytes(ncand, wl, form):
+    """Algorithmic HBM bytes of one launch of the search stage.
+
+    Per patch: its L bin keys (8 B) and directory slots (16 B), its feature
+    row (4D B), the output (K ids + K distances + count). Per distinct
+    candidate: its ID (4 B) and its feature row: the bf16 half (2D B) in the
+    screened form plus the low half (2D B) of every re-ranked candidate, or
+    the full fp32 row (4D B) in the exact form."""
+    M = ncand.astype(np.int64)
+    D, L, K = wl.D, wl.L, wl.K
+    per_q = 8 * L + 16 * L + 4 * D + 8 * K + 8
+    if form == "screened":
+        R = wl.rerank
+        rows = np.where(M > R, M * 2 * D + R * 2 * D, M * 4 * D)
+    else:
+        rows = M * 4 * D
+    return int(len(M) * per_q + (M * 4).sum() + rows.sum())
+
+
+def traffic_from_profile(form):
+    """HBM bytes per search launch from the committed rocprofv3 counter summary,
+    if it was taken with the current search kernel source."""
+    path = os.path.join(ROOT, "profiles", f"search_{form}_traffic.json")
+    src = os.path.join(ROOT, "paper_1004_3980_amd", "csrc", "k_search.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("k_search_sha256") != sha:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(wl, lr, hr_gt, crop):
+    """The FP64 oracle on the top-left crop x crop LR patch grid of the same
+    workload (same dictionary and tables); table build excluded, like the
+    GPU's. Returns (record, oracle query result, oracle HR crop)."""
+    from oracle import pipeline as opipe
+    t0 = time.perf_counter()
+    pre = opipe.prepare(wl.dictionary_images(), wl.positions(), wl.scale, wl.feat_mode, wl.L, wl.k,
+                        wl.w, wl.hash_seed)
+    t_build = time.perf_counter() - t0
+    lr_c = np.ascontiguousarray(lr[:crop, :crop])
+    t0 = time.perf_counter()
+    qr = opipe.query(pre, lr_c, wl.K, wl.lam, cap=wl.cap)
+    hr_c, _ = opipe.reconstruct(qr, lr_c, wl.scale)
+    t_q = time.perf_counter() - t0
+    n = len(qr.pos)
+    cores = len(os.sched_getaffinity(0))
+    rec = {"value": n / t_q, "unit": "LR patches/s", "cores": cores, "kind": "oracle",
+           "sample": f"{crop}x{crop} LR crop ({n} patches) of the same image against the full "
+                     f"{wl.n_dict}-pair dictionary: features, codes, candidates (early stop "
+                     f"{wl.cap}), exact K-NN, FP64 LLE, synthesis, blend; {t_q:.1f} s; the "
+                     f"projection loop runs on {cores} OpenMP threads, the rest on one; table "
+                     f"build ({t_build:.0f} s) excluded"}
+    return rec, qr, hr_c
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="precision")
+    ap.add_argument("--form", choices=["screened", "exact"], default="screened")
+    ap.add_argument("--crop", type=int, default=256, help="LR crop side for quality and the CPU leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times "
+                         "(reference dispatch for scaling HBM counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this path is not sharded across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthdata
+    from paper_1004_3980_amd.pipeline import GpuWorkload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = synthdata.WORKLOADS[args.workload]
+    log(f"[bench] building {wl.name}: {wl.n_dict} pairs, LR {wl.test_h}x{wl.test_w} x{wl.scale}")
+    t0 = time.perf_counter()
+    g = GpuWorkload(wl, device=0)
+    torch.cuda.synchronize()
+    log(f"[bench] inputs + dictionary + tables ready in {time.perf_counter() - t0:.1f} s")
+
+    def set_form(form):
+        if form == "screened":
+            g.set_mode(cap=wl.cap, rerank=wl.rerank, proj=1, lle_fp64=0)
+        else:
+            g.set_mode(cap=wl.cap, rerank=0, proj=1, lle_fp64=1)
+
+    def timed(form, steps, warmup):
+        set_form(form)
+        for _ in range(warmup):
+            g.zoom()
+        torch.cuda.synchronize()
+        g.ctx.get_timing()
+        g.ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.zoom()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.ctx.set_timing(False)
+        st = g.ctx.get_timing()
+        return dt, st
+
+    dt, stages = timed(args.form, args.steps, args.warmup)
+    Q = g.Q
+    value = Q * args.steps / dt
+    res = g.results()
+    ms_stage = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    log(f"[bench] {args.form}: {value:.4g} patches/s, {1e3 * dt / args.steps:.3f} ms/step; "
+        f"stages ms {json.dumps({k: round(v, 4) for k, v in ms_stage.items()})}")
+
+    # dominant kernel: the candidate search
+    dom = max(("hash", "search", "lle", "synth", "blend"), key=lambda k: ms_stage[k])
+    sb = search_bytes(res["ncand"], wl, args.form)
+    ach = sb / (ms_stage["search"] * 1e-3) / 1e9
+    traffic = traffic_from_profile(args.form)
+    roof = {"bound": "hbm", "kernel": "k_search", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes": sb, "launch_ms": round(ms_stage["search"], 4),
+            "dominant_stage": dom}
+
+    # other form on the same image, back-projection, whole path with back-projection
+    other = "exact" if args.form == "screened" else "screened"
+    dt2, st2 = timed(other, max(2, args.steps // 2), 1)
+    other_rec = {"form": other, "value": Q * max(2, args.steps // 2) / dt2,
+                 "ms_per_step": 1e3 * dt2 / max(2, args.steps // 2)}
+    set_form(args.form)
+    g.zoom()
+    hr = g.hr_out.clone()
+    torch.cuda.synchronize()
+    g.ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.backproject(hr.clone())
+    torch.cuda.synchronize()
+    bp_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    g.ctx.set_timing(False)
+    bst = g.ctx.get_timing()
+    stats = g.ctx.stats()
+
+    extra = {"ms_per_stage": {k: round(v, 4) for k, v in ms_stage.items()},
+             "backprojection_ms": round(bp_ms, 3), "bp_iters": wl.bp_iters,
+             "value_with_backprojection": Q / (dt / args.steps + bp_ms * 1e-3),
+             "other_form": other_rec,
+             "mean_candidates": float(res["ncand"].mean()),
+             "patches_without_neighbours": int((res["m"] == 0).sum()),
+             "similarity_checks_saved": float(wl.n_dict / max(1e-9, res["ncand"].mean())),
+             "stats": stats}
+
+    # quality on a crop against the FP64 oracle, and the oracle's CPU rate
+    cpu = None
+    if not (args.no_quality and args.no_cpu_baseline):
+        crop = args.crop
+        lr_np = g.lr.cpu().numpy()
+        gt = g.hr_gt.cpu().numpy()[: wl.scale * crop, : wl.scale * crop] if g.hr_gt is not None else None
+        log(f"[bench] oracle on the {crop}x{crop} crop (table build first)")
+        cpu, qr, hr_o = cpu_baseline(wl, lr_np, gt, crop)
+        log(f"[bench] oracle: {cpu['value']:.4g} patches/s")
+        lr_c = g.lr[:crop, :crop].contiguous()
+        out = torch.empty((wl.scale * crop, wl.scale * crop), dtype=torch.float32, device="cuda")
+        quality = {}
+        for form in ("screened", "exact"):
+            set_form(form)
+            g.zoom(lr=lr_c, out=out)
+            r = g.results()
+            Kq = wl.K
+            ok = qr.m > 0
+            inter = [len(np.intersect1d(r["ids"][q, :r["m"][q]], qr.ids[q, :qr.m[q]]))
+                     for q in np.nonzero(ok)[0]]
+            rec_k = float(np.sum(inter) / max(1, qr.m[ok].sum()))
+            o = out.cpu().numpy()
+            qrec = {"recall_at_k": rec_k, "ids_equal": bool(np.array_equal(
+                r["ids"], np.where(qr.ids >= 0, qr.ids, -1).astype(np.int32))),
+                "max_abs_vs_oracle": float(np.abs(o - hr_o).max()),
+                "psnr_vs_oracle_db": psnr(o, hr_o)}
+            if gt is not None:
+                qrec["psnr_gt_db"] = psnr(o, gt)
+            quality[form] = qrec
+        if gt is not None:
+            p_or = psnr(hr_o, gt)
+            quality["oracle_psnr_gt_db"] = p_or
+            for form in ("screened", "exact"):
+                quality[form]["psnr_loss_db"] = p_or - quality[form]["psnr_gt_db"]
+        extra["quality_crop"] = quality
+        set_form(args.form)
+        if args.no_cpu_baseline:
+            cpu = None
+
+    out = {
+        "metric": "LR patches/sec (hash+KNN+LLE+blend) at 1024² ×2; recall@K, PSNR vs FP64",
+        "value": value,
+        "unit": "LR patches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16/fp32" if args.form == "screened" else "fp32/fp64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.test_h}x{wl.test_w} LR x{wl.scale}, "
+                               f"{wl.n_dict}-pair dictionary (4-gradient features, D={wl.D}), "
+                               f"L={wl.L} k={wl.k} w={wl.w:g} K={wl.K}, early stop {wl.cap}, "
+                               f"form {args.form}" + (f" (bf16 screen to {wl.rerank})" if args.form == "screened" else ""),
+                   "patches_per_step": Q, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["extra"]["copy_probe_bytes"] = n * 4
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,7 +152,7 @@ zh_status zh_query(zh_ctx* ctx, const float* lr, int h, int w, int scale, int K)
 /* LLE weights of every patch (Section 4.2, Eq. LinSys): minimise
  * ||y - sum_m w_m y_m||^2 subject to sum_m w_m = 1, regularised by adding
  * lambda * trace(G) to the diagonal of the Gram matrix G (lambda > 0). */
-zh_status zh_lle_weights(zh_ctx* ctx, float lambda);
+zh_status zh_lle_weights(zh_ctx* ctx, double lambda);
 
 /* HR image hr_out[s h, s w]: each patch x_q = mean(LR patch) + sum_m w_m r_m
  * (Eq. HR_Rec on the residuals), overlaps averaged per pixel (Section 4
@@ -197,6 +197,18 @@ typedef struct {
 } zh_stats_t;
 /* Counters of the last zh_query / zh_lle_weights (synchronises the stream). */
 zh_status zh_stats(zh_ctx* ctx, zh_stats_t* out);
+
+/* ---- stage timing (HIP events on the context's stream) ----------------- */
+enum { ZH_T_FEATURES = 0, ZH_T_HASH = 1, ZH_T_SEARCH = 2, ZH_T_LLE = 3, ZH_T_SYNTH = 4,
+       ZH_T_BLEND = 5, ZH_T_BP_ERROR = 6, ZH_T_BP_UPDATE = 7, ZH_T_COUNT = 8 };
+/* on != 0: bracket every kernel launch of the stages above with a pair of HIP
+ * events (at most 256 launches per stage between two zh_get_timing calls;
+ * later launches are not timed). on = 0 stops recording. */
+zh_status zh_set_timing(zh_ctx* ctx, int on);
+/* Synchronise, then write for each stage the summed milliseconds (ms[8]) and
+ * the number of timed launches (launches[8], may be NULL) since the previous
+ * call, and start a new period. */
+zh_status zh_get_timing(zh_ctx* ctx, double* ms, int32_t* launches);
 
 #ifdef __cplusplus
 }

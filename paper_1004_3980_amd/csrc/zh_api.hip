@@ -58,6 +58,11 @@ struct zh_ctx {
     int64_t Q = 0;
     Buf lr, maps, qfeat, qmu, qkeys, ids, d2, m, ncand, w, over, xhat, e, tmp, counters;
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
+    // stage timing
+    bool timing = false;
+    static constexpr int kEv = 256;
+    hipEvent_t ev[ZH_T_COUNT][kEv][2] = {};
+    int nev[ZH_T_COUNT] = {0};
 };
 
 namespace {
@@ -116,6 +121,30 @@ void release(zh_ctx* c, Buf& b) {
 
 template <typename T>
 T* P(Buf& b) { return static_cast<T*>(b.p); }
+
+// Brackets one stage's launches with a pair of events when timing is on.
+struct StageTimer {
+    zh_ctx* c;
+    int stage;
+    int slot = -1;
+    StageTimer(zh_ctx* c_, int s) : c(c_), stage(s) {
+        if (!c->timing || c->nev[stage] >= zh_ctx::kEv) return;
+        slot = c->nev[stage]++;
+        hipEvent_t* e = c->ev[stage][slot];
+        if (!e[0]) {
+            if (hipEventCreate(&e[0]) != hipSuccess || hipEventCreate(&e[1]) != hipSuccess) {
+                (void)hipGetLastError();
+                slot = -1;
+                --c->nev[stage];
+                return;
+            }
+        }
+        (void)hipEventRecord(e[0], c->stream);
+    }
+    ~StageTimer() {
+        if (slot >= 0) (void)hipEventRecord(c->ev[stage][slot][1], c->stream);
+    }
+};
 
 // ---- hash parameters: SplitMix64 + Marsaglia polar normals -------------------
 struct SplitMix {
@@ -263,6 +292,10 @@ void zh_destroy(zh_ctx* c) {
         release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.anorm);
         release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.tids);
     }
+    for (int st = 0; st < ZH_T_COUNT; ++st)
+        for (int i = 0; i < zh_ctx::kEv; ++i)
+            for (int j = 0; j < 2; ++j)
+                if (c->ev[st][i][j]) (void)hipEventDestroy(c->ev[st][i][j]);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
                    &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict};
@@ -521,9 +554,12 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     c->qK = K;
     c->Q = Q;
     TRY(clear_counters(c));
-    if (d.mode == ZH_FEAT_GRAD4) HIPCHK(c, launch_gradient_maps(P<float>(c->lr), 1, h, w, P<float>(c->maps), c->stream));
-    HIPCHK(c, launch_query_features(P<float>(c->lr), P<float>(c->maps), h, w, d.mode, P<float>(c->qfeat),
-                                    P<double>(c->qmu), c->stream));
+    {
+        StageTimer t(c, ZH_T_FEATURES);
+        if (d.mode == ZH_FEAT_GRAD4) HIPCHK(c, launch_gradient_maps(P<float>(c->lr), 1, h, w, P<float>(c->maps), c->stream));
+        HIPCHK(c, launch_query_features(P<float>(c->lr), P<float>(c->maps), h, w, d.mode, P<float>(c->qfeat),
+                                        P<double>(c->qmu), c->stream));
+    }
     HashArgs ha{};
     ha.feat = P<float>(c->qfeat);
     ha.n = Q;
@@ -540,16 +576,22 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     ha.keys = P<uint64_t>(c->qkeys);
     ha.codes = nullptr;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
-    HIPCHK(c, launch_hash(ha, c->stream));
-    TRY(run_search(c, d, nullptr, 0));
+    {
+        StageTimer t(c, ZH_T_HASH);
+        HIPCHK(c, launch_hash(ha, c->stream));
+    }
+    {
+        StageTimer t(c, ZH_T_SEARCH);
+        TRY(run_search(c, d, nullptr, 0));
+    }
     c->stage = 1;
     return ZH_OK;
 }
 
-zh_status zh_lle_weights(zh_ctx* c, float lambda) {
+zh_status zh_lle_weights(zh_ctx* c, double lambda) {
     if (!c) return ZH_EINVAL;
     if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_lle_weights before zh_query");
-    if (!(lambda > 0.f) || !std::isfinite(lambda)) return fail(c, ZH_EINVAL, "zh_lle_weights: lambda must be > 0");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, ZH_EINVAL, "zh_lle_weights: lambda must be > 0");
     TRY(set_device(c));
     Dict& d = c->dicts[c->qscale];
     LleArgs a{};
@@ -565,6 +607,7 @@ zh_status zh_lle_weights(zh_ctx* c, float lambda) {
     a.fp64 = c->opts.lle_fp64;
     a.w = P<float>(c->w);
     a.n_fp64 = P<unsigned int>(c->counters) + C_LLE64;
+    StageTimer t(c, ZH_T_LLE);
     HIPCHK(c, launch_lle(a, c->stream));
     c->stage = 2;
     return ZH_OK;
@@ -577,10 +620,16 @@ zh_status zh_reconstruct(zh_ctx* c, float* hr_out) {
     TRY(set_device(c));
     Dict& d = c->dicts[c->qscale];
     const int s = c->qscale, ps2 = (kPatch * s) * (kPatch * s);
-    HIPCHK(c, launch_synth((int)c->Q, c->qK, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
-                           P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
-    HIPCHK(c, launch_blend(P<float>(c->xhat), P<int32_t>(c->m), P<float>(c->lr), c->qh, c->qw, s, hr_out,
-                           c->stream));
+    {
+        StageTimer t(c, ZH_T_SYNTH);
+        HIPCHK(c, launch_synth((int)c->Q, c->qK, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
+                               P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
+    }
+    {
+        StageTimer t(c, ZH_T_BLEND);
+        HIPCHK(c, launch_blend(P<float>(c->xhat), P<int32_t>(c->m), P<float>(c->lr), c->qh, c->qw, s, hr_out,
+                               c->stream));
+    }
     c->stage = 3;
     return ZH_OK;
 }
@@ -598,8 +647,14 @@ zh_status zh_backproject(zh_ctx* c, float* hr, int iters, float sigma_s, float s
     float* a = hr;
     float* b = P<float>(c->tmp);
     for (int t = 0; t < iters; ++t) {
-        HIPCHK(c, launch_degrade_residual(a, H, W, s, g, P<float>(c->lr), P<float>(c->e), c->stream));
-        HIPCHK(c, launch_bp_update(a, P<float>(c->e), H, W, c->qh, c->qw, s, sigma_s, sigma_r, b, c->stream));
+        {
+            StageTimer t1(c, ZH_T_BP_ERROR);
+            HIPCHK(c, launch_degrade_residual(a, H, W, s, g, P<float>(c->lr), P<float>(c->e), c->stream));
+        }
+        {
+            StageTimer t2(c, ZH_T_BP_UPDATE);
+            HIPCHK(c, launch_bp_update(a, P<float>(c->e), H, W, c->qh, c->qw, s, sigma_s, sigma_r, b, c->stream));
+        }
         float* t2 = a; a = b; b = t2;
     }
     if (a != hr)
@@ -661,6 +716,31 @@ zh_status zh_stats(zh_ctx* c, zh_stats_t* out) {
     for (const Dict& d : c->dicts)
         db += d.hi.bytes + d.lo.bytes + d.dir.bytes + d.tids.bytes + d.alpha.bytes + d.ahi.bytes + d.alo.bytes;
     out->dict_bytes = db;
+    return ZH_OK;
+}
+
+zh_status zh_set_timing(zh_ctx* c, int on) {
+    if (!c) return ZH_EINVAL;
+    c->timing = on != 0;
+    return ZH_OK;
+}
+
+zh_status zh_get_timing(zh_ctx* c, double* ms, int32_t* launches) {
+    if (!c) return ZH_EINVAL;
+    if (!ms) return fail(c, ZH_EINVAL, "zh_get_timing: null output");
+    TRY(set_device(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int st = 0; st < ZH_T_COUNT; ++st) {
+        double sum = 0.0;
+        for (int i = 0; i < c->nev[st]; ++i) {
+            float t = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&t, c->ev[st][i][0], c->ev[st][i][1]));
+            sum += t;
+        }
+        ms[st] = sum;
+        if (launches) launches[st] = c->nev[st];
+        c->nev[st] = 0;
+    }
     return ZH_OK;
 }
 

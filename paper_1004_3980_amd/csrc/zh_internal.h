@@ -98,7 +98,7 @@ struct LleArgs {
     const int32_t* m;
     const uint16_t* hi;
     const uint16_t* lo;
-    float lam;
+    double lam;
     int fp64;                // 1: FP64 Gram and solve; 0: FP32, FP64 redo when cond > 1e6
     float* w;                // [Q, K]
     unsigned int* n_fp64;    // FP64 redo count (nullable)

@@ -77,7 +77,7 @@ class GpuWorkload:
     def results(self, K=None):
         torch = self.torch
         K = self.wl.K if K is None else K
-        Q = self.Q
+        Q, _ = self.ctx.query_shape()
         ids = torch.empty((Q, K), dtype=torch.int32, device=self.dev)
         d2 = torch.empty((Q, K), dtype=torch.float32, device=self.dev)
         m = torch.empty(Q, dtype=torch.int32, device=self.dev)

@@ -64,14 +64,17 @@ SIGNATURES = {
     "zh_hash": [_V, _I, _V, _I64, _V, _V],
     "zh_set_query_opts": [_V, ctypes.POINTER(zh_query_opts)],
     "zh_query": [_V, _V, _I, _I, _I, _I],
-    "zh_lle_weights": [_V, _F],
+    "zh_lle_weights": [_V, ctypes.c_double],
     "zh_reconstruct": [_V, _V],
     "zh_backproject": [_V, _V, _I, _F, _F],
     "zh_get_results": [_V, _V, _V, _V, _V, _V],
     "zh_query_shape": [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)],
     "zh_candidates": [_V, ctypes.c_int32, _V, _V],
     "zh_stats": [_V, ctypes.POINTER(zh_stats_t)],
+    "zh_set_timing": [_V, _I],
+    "zh_get_timing": [_V, _V, _V],
 }
+STAGES = ["features", "hash", "search", "lle", "synth", "blend", "bp_error", "bp_update"]
 
 _lib = None
 
@@ -198,6 +201,15 @@ class Context:
 
     def candidates(self, cap_per_query, counts, ids):
         self._chk(self.lib.zh_candidates(self.h, cap_per_query, _ptr(counts), _ptr(ids)))
+
+    def set_timing(self, on: bool):
+        self._chk(self.lib.zh_set_timing(self.h, 1 if on else 0))
+
+    def get_timing(self):
+        ms = np.zeros(len(STAGES), dtype=np.float64)
+        n = np.zeros(len(STAGES), dtype=np.int32)
+        self._chk(self.lib.zh_get_timing(self.h, ms.ctypes.data, n.ctypes.data))
+        return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
 
     def stats(self):
         s = zh_stats_t()
