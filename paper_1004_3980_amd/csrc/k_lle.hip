@@ -148,6 +148,133 @@ __global__ __launch_bounds__(64) void k_lle(LleArgs a) {
     }
 }
 
+// FP64 Gram of patch q's m neighbours straight from the rows (the slow path of
+// the fp32 solve when its condition estimate exceeds 1e6).
+__device__ void gram_fp64_rows(const LleArgs& a, int q, int m, double* Gd) {
+    const int D = a.D;
+    const float* qrow = a.qfeat + (int64_t)q * D;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j <= i; ++j) {
+            const int64_t bi = (int64_t)a.ids[(int64_t)q * a.K + i] * D;
+            const int64_t bj = (int64_t)a.ids[(int64_t)q * a.K + j] * D;
+            double g = 0.0;
+            for (int t = 0; t < D; ++t) {
+                const double zi = (double)qrow[t] - (double)join_planes(a.hi[bi + t], a.lo[bi + t]);
+                const double zj = (double)qrow[t] - (double)join_planes(a.hi[bj + t], a.lo[bj + t]);
+                g += zi * zj;
+            }
+            Gd[i * (i + 1) / 2 + j] = g;
+        }
+}
+
+// Solve (G + lam tr(G) I) w~ = 1 on the first m rows (rows m..7 are set to
+// the identity with a zero right-hand side), w = w~ / sum(w~). Returns the
+// squared ratio of the largest to the smallest Cholesky diagonal.
+template <typename T>
+__device__ __forceinline__ double solve8(T (&A)[36], int m, double lam, T (&w)[8]) {
+    T tau = (T)0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (i < m) tau += A[i * (i + 1) / 2 + i];
+    if (tau == (T)0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = i < m ? (T)1 / (T)m : (T)0;
+        return 1.0;
+    }
+    const T reg = (T)lam * tau;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            T& x = A[i * (i + 1) / 2 + j];
+            if (i >= m || j >= m) x = (i == j) ? (T)1 : (T)0;
+            else if (i == j) x += reg;
+        }
+    T dmin = (T)0, dmax = (T)0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        T s = A[j * (j + 1) / 2 + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= A[j * (j + 1) / 2 + k] * A[j * (j + 1) / 2 + k];
+        const T d = sqrt(s);
+        A[j * (j + 1) / 2 + j] = d;
+        if (j < m) {
+            dmin = (j == 0 || d < dmin) ? d : dmin;
+            dmax = d > dmax ? d : dmax;
+        }
+        const T inv = (T)1 / d;
+#pragma unroll
+        for (int i = j + 1; i < 8; ++i) {
+            T t = A[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= A[i * (i + 1) / 2 + k] * A[j * (j + 1) / 2 + k];
+            A[i * (i + 1) / 2 + j] = t * inv;
+        }
+    }
+    T y[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        T s = i < m ? (T)1 : (T)0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= A[i * (i + 1) / 2 + k] * y[k];
+        y[i] = s / A[i * (i + 1) / 2 + i];
+    }
+    T sum = (T)0;
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+        T s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 8; ++k) s -= A[k * (k + 1) / 2 + i] * w[k];
+        w[i] = s / A[i * (i + 1) / 2 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (i < m) sum += w[i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = i < m ? w[i] / sum : (T)0;
+    const double r = (double)dmax / (double)dmin;
+    return r * r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lle_solve(LleArgs a, const T* __restrict__ gram) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.Q) return;
+    const int m = a.m[q];
+    float* wout = a.w + (int64_t)q * a.K;
+    if (m <= 0) {
+        for (int r = 0; r < a.K; ++r) wout[r] = 0.0f;
+        return;
+    }
+    T A[36];
+#pragma unroll
+    for (int p = 0; p < 36; ++p) A[p] = gram[(int64_t)q * 36 + p];
+    T w[8];
+    const double cond = solve8<T>(A, m, a.lam, w);
+    if (sizeof(T) == 4 && cond > 1e6) {
+        if (a.n_fp64) atomicAdd(a.n_fp64, 1u);
+        double Ad[36], wd[8];
+#pragma unroll
+        for (int p = 0; p < 36; ++p) Ad[p] = 0.0;
+        gram_fp64_rows(a, q, m, Ad);
+        solve8<double>(Ad, m, a.lam, wd);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = (T)wd[i];
+    }
+    for (int r = 0; r < a.K; ++r) wout[r] = r < m && r < 8 ? (float)w[r] : 0.0f;
+}
+
+hipError_t launch_lle_solve(const LleArgs& a, const void* gram, int gram_fp64, hipStream_t st) {
+    if (a.Q == 0) return hipSuccess;
+    if (a.K > 8) return hipErrorInvalidValue;
+    const int grid = (a.Q + 255) / 256;
+    if (gram_fp64)
+        hipLaunchKernelGGL(k_lle_solve<double>, dim3(grid), dim3(256), 0, st, a, static_cast<const double*>(gram));
+    else
+        hipLaunchKernelGGL(k_lle_solve<float>, dim3(grid), dim3(256), 0, st, a, static_cast<const float*>(gram));
+    return hipGetLastError();
+}
+
 // x_q = mu_q + sum_m w_m r_{n_m}: one wave per patch.
 __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int32_t* __restrict__ ids,
                                                const int32_t* __restrict__ m, const float* __restrict__ w,
@@ -159,14 +286,24 @@ __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int3
         const int mq = m[q];
         if (mq <= 0) continue;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int r = 0; r < mq; ++r) {
-            const int64_t b = (int64_t)ids[(int64_t)q * K + r] * ps2;
-            const float wr = w[(int64_t)q * K + r];
+        for (int r0 = 0; r0 < mq; r0 += 8) {
+            float v[8][4];
+            float wr[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int p = lane + 64 * u;
-                if (p < ps2) acc[u] = fmaf(wr, resid[b + p], acc[u]);
+            for (int r = 0; r < 8; ++r) {
+                const bool ok = r0 + r < mq;
+                const int64_t b = ok ? (int64_t)ids[(int64_t)q * K + r0 + r] * ps2 : 0;
+                wr[r] = ok ? w[(int64_t)q * K + r0 + r] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int p = lane + 64 * u;
+                    v[r][u] = (ok && p < ps2) ? resid[b + p] : 0.0f;
+                }
             }
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] = fmaf(wr[r], v[r][u], acc[u]);
         }
         const float mf = (float)mu[q];
 #pragma unroll

@@ -12,6 +12,12 @@
 // re-ranked by that FP64 distance, so the result equals the FP64 definition.
 // Screened mode (rerank = R): the high plane alone (a bf16 feature) ranks the
 // candidates, the best R are re-ranked exactly in fp32.
+//
+// With K <= 8 the kernel also forms the Gram matrix G = Z Z^T of the chosen
+// neighbours (Z = query - neighbour rows, Section 4.2 Eq. LinSys) while those
+// rows are in cache, and stores it packed for the LLE solve.
+#include <type_traits>
+
 #include "zh_internal.h"
 
 namespace zh {
@@ -70,51 +76,95 @@ __device__ void wave_sort_u32(uint32_t* s, int n) {
     }
 }
 
-// Squared distances of the query to candidates cids[c0..c1) into cdist[c]
+// Bitonic sort of NS*64 keys held NS per lane (element s*64 + lane) in
+// registers, ascending.
+template <int NS>
+__device__ __forceinline__ void wave_sort_keys(uint64_t (&key)[NS]) {
+    const int lane = threadIdx.x & 63;
+    constexpr int N = NS * 64;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int js = j >> 6;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int t = s ^ js;
+                    if (t > s) {
+                        const bool up = ((s * 64 + lane) & k) == 0;
+                        const uint64_t x = key[s], y = key[t];
+                        if ((x > y) == up) {
+                            key[s] = y;
+                            key[t] = x;
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const uint64_t x = key[s];
+                    const uint64_t y = __shfl_xor(x, j);
+                    const bool up = ((s * 64 + lane) & k) == 0;
+                    const bool lower = (lane & j) == 0;
+                    const uint64_t mn = x < y ? x : y, mx = x < y ? y : x;
+                    key[s] = (lower == up) ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+// Squared distances of the query to candidates cids[0..c1) into cdist[c]
 // (fp32 bits; bit 31 set when the row equals the query exactly). Half a wave
-// per row: lane l of a half holds coordinates [VEC l, VEC l + VEC).
+// per row: lane l of a half holds coordinates [VEC l, VEC l + VEC); U row
+// pairs are loaded before any is used.
 template <int VEC, bool HI_ONLY>
 __device__ void cand_distances(const float (&qv)[VEC], int D, const uint16_t* __restrict__ hi,
                                const uint16_t* __restrict__ lo, const uint32_t* cids, uint32_t* cdist,
-                               int c0, int c1) {
+                               int c1) {
+    // VEC == 4: 8 bytes of each plane per lane; VEC == 1: 2 bytes
+    typedef typename std::conditional<VEC == 4, uint2, uint32_t>::type raw_t;
     const int lane = threadIdx.x, hl = lane & 31, half = lane >> 5;
     const bool dl = hl * VEC < D;
-    constexpr int U = 4;
-    for (int cb = c0; cb < c1; cb += 2 * U) {
-        uint32_t hv[U][VEC], lv[U][VEC];
+    constexpr int U = HI_ONLY ? 16 : 8;
+    for (int cb = 0; cb < c1; cb += 2 * U) {
+        raw_t hr[U], lr[U];
         bool cv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int c = cb + 2 * u + half;
             cv[u] = c < c1;
             const uint32_t id = cv[u] ? cids[c] : 0u;
-            const int64_t base = (int64_t)id * D + hl * VEC;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) { hv[u][e] = 0; lv[u][e] = 0; }
+            // N * D < 2^31 elements: 32-bit offsets from the plane bases
+            const uint32_t base = id * (uint32_t)D + (uint32_t)(hl * VEC);
+            hr[u] = raw_t{};
+            lr[u] = raw_t{};
             if (cv[u] && dl) {
-                if (VEC == 4) {
-                    const uint2 h2 = *reinterpret_cast<const uint2*>(hi + base);
-                    hv[u][0] = h2.x & 0xFFFFu; hv[u][1] = h2.x >> 16; hv[u][2] = h2.y & 0xFFFFu; hv[u][3] = h2.y >> 16;
-                    if (!HI_ONLY) {
-                        const uint2 l2 = *reinterpret_cast<const uint2*>(lo + base);
-                        lv[u][0] = l2.x & 0xFFFFu; lv[u][1] = l2.x >> 16; lv[u][2] = l2.y & 0xFFFFu; lv[u][3] = l2.y >> 16;
-                    }
+                if constexpr (VEC == 4) {
+                    hr[u] = *reinterpret_cast<const uint2*>(hi + base);
+                    if (!HI_ONLY) lr[u] = *reinterpret_cast<const uint2*>(lo + base);
                 } else {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        hv[u][e] = hi[base + e];
-                        if (!HI_ONLY) lv[u][e] = lo[base + e];
-                    }
+                    hr[u] = hi[base];
+                    if (!HI_ONLY) lr[u] = lo[base];
                 }
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            uint32_t hv[VEC], lv[VEC];
+            if constexpr (VEC == 4) {
+                hv[0] = hr[u].x & 0xFFFFu; hv[1] = hr[u].x >> 16; hv[2] = hr[u].y & 0xFFFFu; hv[3] = hr[u].y >> 16;
+                lv[0] = lr[u].x & 0xFFFFu; lv[1] = lr[u].x >> 16; lv[2] = lr[u].y & 0xFFFFu; lv[3] = lr[u].y >> 16;
+            } else {
+                hv[0] = hr[u];
+                lv[0] = lr[u];
+            }
             float p = 0.0f;
             bool eq = true;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const float y = __uint_as_float((hv[u][e] << 16) | lv[u][e]);
+                const float y = __uint_as_float((hv[e] << 16) | lv[e]);
                 const float d = qv[e] - y;
                 p = fmaf(d, d, p);
                 eq = eq && (!dl || __float_as_uint(qv[e]) == __float_as_uint(y));
@@ -131,7 +181,7 @@ __device__ void cand_distances(const float (&qv)[VEC], int D, const uint16_t* __
 }
 
 // K' rounds of wave argmin over the candidates' keys; lane r receives the
-// r-th smallest key.
+// r-th smallest key. (Used when the candidates exceed the register sort.)
 __device__ uint64_t select_topk(const uint32_t* cids, const uint32_t* cdist, int M, int Kp) {
     const int lane = threadIdx.x;
     uint64_t mine = ~0ull, last = 0;
@@ -146,6 +196,35 @@ __device__ uint64_t select_topk(const uint32_t* cids, const uint32_t* cdist, int
         last = best;
     }
     return mine;
+}
+
+// Sorted selection for M <= 256 candidates: lane r < min(M, 64) receives the
+// r-th smallest key.
+__device__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int M) {
+    const int lane = threadIdx.x;
+    if (M <= 64) {
+        uint64_t k[1] = {lane < M ? cand_key(cdist[lane], cids[lane]) : ~0ull};
+        wave_sort_keys<1>(k);
+        return k[0];
+    }
+    if (M <= 128) {
+        uint64_t k[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int c = s * 64 + lane;
+            k[s] = c < M ? cand_key(cdist[c], cids[c]) : ~0ull;
+        }
+        wave_sort_keys<2>(k);
+        return k[0];
+    }
+    uint64_t k[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = s * 64 + lane;
+        k[s] = c < M ? cand_key(cdist[c], cids[c]) : ~0ull;
+    }
+    wave_sort_keys<4>(k);
+    return k[0];
 }
 
 // FP64 sequential squared distance: the definition.
@@ -179,7 +258,6 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
                                int M, int Kp, uint64_t mykey, uint32_t& out_id, float& out_d) {
     const int lane = threadIdx.x;
     const Bounds bd{2.0 * gamma_n(a.D + 3, 1.0 / 16777216.0), (double)a.D * 1.2e-38};
-    // order of consecutive selections
     const bool ex = key_exact(mykey);
     double lo, hi;
     dist_interval(ex ? 0x80000000u : (uint32_t)(mykey >> 32), bd, lo, hi);
@@ -191,7 +269,6 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
         else if (!ex && !ex_n) ok = hi < lo_n;
     }
     bool certified = __ballot(!ok) == 0;
-    // nothing outside the selection may precede its last element
     const uint64_t lastkey = __shfl(mykey, Kp - 1);
     const bool last_ex = key_exact(lastkey);
     double tlo, thi;
@@ -214,7 +291,6 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
         out_d = key_dist(mykey);
         return;
     }
-    // FP64 re-rank of S = candidates that may belong to the top Kp
     if (lane == 0) atomicAdd(&a.counters[1], 1u);
     const float* qrow = a.qfeat + (int64_t)q * a.D;
     const bool bounded = Kp < M && !last_ex;
@@ -239,7 +315,6 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
                 bestid = id;
             }
         }
-        // wave lexicographic min over (d, id)
         for (int o = 32; o > 0; o >>= 1) {
             const double od = __shfl_xor(bestd, o);
             const uint32_t oi = __shfl_xor(bestid, o);
@@ -257,100 +332,175 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
     }
 }
 
-template <int VEC, int CMAX, bool CAPPED>
-__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
-    __shared__ uint32_t cids[CMAX];
-    __shared__ uint32_t cdist[CMAX];
+// One halving step of a reduce-scatter over the wave: lanes whose bit O is
+// clear keep the first half of their N values, the others the second half,
+// each adding its partner's partial sums; (base, cnt) track the index range.
+template <typename T, int N, int O, int NMAX>
+__device__ __forceinline__ void rs_step(T (&v)[NMAX], int& base, int& cnt) {
+    constexpr int NK = (N + 1) / 2;
+    const bool hb = (threadIdx.x & O) != 0;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+        const T lo_v = v[i];
+        const T hi_v = (NK + i < N) ? v[NK + i] : (T)0;
+        const T send = hb ? lo_v : hi_v;
+        const T keep = hb ? hi_v : lo_v;
+        v[i] = keep + __shfl_xor(send, O);
+    }
+    if (hb) {
+        base += NK;
+        cnt -= NK;
+    } else {
+        cnt = cnt < NK ? cnt : NK;
+    }
+}
+
+// Packed Gram matrix (lower triangle, p = i(i+1)/2 + j) of the Kp <= 8 chosen
+// neighbours, Z_m = q - y_m, in T precision; lane r < Kp holds neighbour r's
+// ID. Lane t owns coordinates t and t + 64.
+template <typename T>
+__device__ void gram_store(const SearchArgs& a, int q, int Kp, uint32_t oid) {
+    constexpr int KM = 8, NP = KM * (KM + 1) / 2;
+    const int lane = threadIdx.x, D = a.D;
+    const float* qrow = a.qfeat + (int64_t)q * D;
+    const int t0 = lane, t1 = lane + 64;
+    const bool v0 = t0 < D, v1 = t1 < D;
+    const T q0 = v0 ? (T)qrow[t0] : (T)0, q1 = v1 ? (T)qrow[t1] : (T)0;
+    T z0[KM], z1[KM];
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+        const uint32_t id = __shfl(oid, m);
+        z0[m] = (T)0;
+        z1[m] = (T)0;
+        if (m < Kp) {
+            const uint32_t b = id * (uint32_t)D;
+            if (v0) z0[m] = q0 - (T)join_planes(a.hi[b + t0], a.lo[b + t0]);
+            if (v1) z1[m] = q1 - (T)join_planes(a.hi[b + t1], a.lo[b + t1]);
+        }
+    }
+    T v[NP];
+    {
+        int p = 0;
+#pragma unroll
+        for (int i = 0; i < KM; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) v[p++] = z0[i] * z0[j] + z1[i] * z1[j];
+    }
+    int base = 0, cnt = NP;
+    rs_step<T, 36, 32>(v, base, cnt);
+    rs_step<T, 18, 16>(v, base, cnt);
+    rs_step<T, 9, 8>(v, base, cnt);
+    rs_step<T, 5, 4>(v, base, cnt);
+    rs_step<T, 3, 2>(v, base, cnt);
+    rs_step<T, 2, 1>(v, base, cnt);
+    if (cnt >= 1) static_cast<T*>(a.gram)[(int64_t)q * NP + base] = v[0];
+}
+
+template <bool GFP64>
+__device__ __forceinline__ void write_result(const SearchArgs& a, int q, int Kp, uint32_t oid, float od) {
+    const int lane = threadIdx.x;
+    if (lane < a.K) {
+        a.out_ids[(int64_t)q * a.K + lane] = lane < Kp ? (int32_t)oid : -1;
+        a.out_d2[(int64_t)q * a.K + lane] = lane < Kp ? od : 0.0f;
+    }
+    if (lane == 0) a.out_m[q] = Kp;
+    if (a.gram && a.K <= 8 && Kp > 0) gram_store<typename std::conditional<GFP64, double, float>::type>(a, q, Kp, oid);
+}
+
+template <int VEC>
+__device__ __forceinline__ void load_query(const SearchArgs& a, int q, float (&qv)[VEC]) {
+    const int hl = threadIdx.x & 31;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        qv[e] = (hl * VEC + e < a.D) ? a.qfeat[(int64_t)q * a.D + hl * VEC + e] : 0.0f;
+}
+
+// Early-stop search (cap <= 256): the concatenation of the L bins is read in
+// parallel 128 positions at a time; first occurrences are kept in order.
+template <int VEC, bool GFP64>
+__global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
+    __shared__ uint32_t cids[256];
+    __shared__ uint32_t cdist[256];
+    __shared__ uint32_t chunk[64];
     __shared__ uint32_t sstart[kMaxL + 1];
     __shared__ uint32_t soff[kMaxL];
     const int lane = threadIdx.x;
-    const int L = a.L, D = a.D;
+    const int L = a.L;
 
     for (int q = blockIdx.x; q < a.Q; q += gridDim.x) {
         uint32_t off = 0, cnt = 0;
         if (lane < L) probe_bin(a.dir + (uint64_t)lane * a.dir_cap, a.dir_cap, a.qkeys[(int64_t)q * L + lane], off, cnt);
+        const int T = wave_sum_i32((int)cnt);
+        const int incl = wave_incl_scan((int)cnt);
+        if (lane < L) {
+            sstart[lane] = (uint32_t)(incl - (int)cnt);
+            soff[lane] = off;
+        }
+        if (lane == 0) sstart[L] = (uint32_t)T;
+        __syncthreads();
         int M = 0;
-        if (CAPPED) {
-            for (int l = 0; l < L && M < a.cap; ++l) {
-                const uint32_t n_l = __shfl(cnt, l), o_l = __shfl(off, l);
-                const uint32_t* T = a.tids + (int64_t)l * a.N + o_l;
-                for (uint32_t b = 0; b < n_l && M < a.cap; b += 64) {
-                    const bool valid = b + lane < n_l;
-                    const uint32_t id = valid ? T[b + lane] : 0xFFFFFFFFu;
-                    bool dup = false;
-                    for (int i = 0; i < M; ++i) dup |= cids[i] == id;
-                    const bool nw = valid && !dup;
-                    const uint64_t bal = __ballot(nw);
-                    const int rank = __popcll(bal & lanemask_lt());
-                    if (nw && M + rank < a.cap) cids[M + rank] = id;
-                    M = min(a.cap, M + (int)__popcll(bal));
+        for (int base = 0; base < T && M < a.cap; base += 128) {
+            uint32_t idv[2];
+            int tabv[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int i = base + 64 * u + lane;
+                idv[u] = 0xFFFFFFFFu;
+                tabv[u] = -1;
+                if (i < T) {
+                    int lo = 0, hi = L;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sstart[mid] <= (uint32_t)i) lo = mid; else hi = mid;
+                    }
+                    tabv[u] = lo;
+                    idv[u] = a.tids[(int64_t)lo * a.N + soff[lo] + (i - sstart[lo])];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int cb = base + 64 * u;
+                if (cb >= T || M >= a.cap) break;
+                const bool valid = cb + lane < T;
+                const uint32_t id = idv[u];
+                bool dup = false;
+                for (int i = 0; i < M; ++i) dup |= cids[i] == id;
+                // IDs inside one bin are distinct: only a chunk that spans
+                // several tables can repeat an ID within itself
+                const int tfirst = __shfl(tabv[u], 0);
+                const int tlast = __shfl(tabv[u], min(63, T - 1 - cb));
+                if (tfirst != tlast) {
+                    chunk[lane] = id;
                     __syncthreads();
+                    for (int j = 0; j < 64; ++j) dup |= (j < lane) && chunk[j] == id;
                 }
-            }
-            if (a.dump) wave_sort_u32(cids, M);
-        } else {
-            const int T = wave_sum_i32((int)cnt);
-            if (T > CMAX) {
-                if (lane == 0) {
-                    const unsigned int pos = atomicAdd(&a.counters[0], 1u);
-                    a.overflow[pos] = q;
-                }
-                continue;
-            }
-            const int incl = wave_incl_scan((int)cnt);
-            if (lane < L) {
-                sstart[lane] = (uint32_t)(incl - (int)cnt);
-                soff[lane] = off;
-            }
-            if (lane == 0) sstart[L] = (uint32_t)T;
-            __syncthreads();
-            for (int i = lane; i < T; i += 64) {
-                int lo = 0, hi = L;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sstart[mid] <= (uint32_t)i) lo = mid; else hi = mid;
-                }
-                cids[i] = a.tids[(int64_t)lo * a.N + soff[lo] + (i - sstart[lo])];
-            }
-            __syncthreads();
-            if (T > 0) wave_sort_u32(cids, T);
-            for (int b = 0; b < T; b += 64) {
-                const int i = b + lane;
-                const bool valid = i < T;
-                const uint32_t v = valid ? cids[i] : 0u;
-                const uint32_t prev = (valid && i > 0) ? cids[i - 1] : 0xFFFFFFFFu;
-                __syncthreads();
-                const bool keep = valid && (i == 0 || v != prev);
-                const uint64_t bal = __ballot(keep);
-                if (keep) cids[M + __popcll(bal & lanemask_lt())] = v;
-                M += __popcll(bal);
+                const bool nw = valid && !dup;
+                const uint64_t bal = __ballot(nw);
+                const int rank = __popcll(bal & lanemask_lt());
+                if (nw && M + rank < a.cap) cids[M + rank] = id;
+                M = min(a.cap, M + (int)__popcll(bal));
                 __syncthreads();
             }
         }
         if (a.dump) {
+            wave_sort_u32(cids, M);
             for (int i = lane; i < M && i < a.dump_cap; i += 64) a.dump[(int64_t)q * a.dump_cap + i] = (int32_t)cids[i];
         }
         if (lane == 0) a.out_ncand[q] = M;
-
         float qv[VEC];
-        {
-            const int hl = lane & 31;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) qv[e] = (hl * VEC + e < D) ? a.qfeat[(int64_t)q * D + hl * VEC + e] : 0.0f;
-        }
+        load_query<VEC>(a, q, qv);
         int Mr = M;
         if (a.rerank > 0 && M > a.rerank) {
-            // screen on the bf16 plane, keep the best R, re-rank them exactly
-            cand_distances<VEC, true>(qv, D, a.hi, a.lo, cids, cdist, 0, M);
-            const uint64_t k2 = select_topk(cids, cdist, M, a.rerank);
+            cand_distances<VEC, true>(qv, a.D, a.hi, a.lo, cids, cdist, M);
+            const uint64_t k2 = sort_select(cids, cdist, M);
             __syncthreads();
             if (lane < a.rerank) cids[lane] = key_id(k2);
             __syncthreads();
             Mr = a.rerank;
         }
-        cand_distances<VEC, false>(qv, D, a.hi, a.lo, cids, cdist, 0, Mr);
+        cand_distances<VEC, false>(qv, a.D, a.hi, a.lo, cids, cdist, Mr);
         const int Kp = min(a.K, Mr);
-        const uint64_t mykey = select_topk(cids, cdist, Mr, Kp);
+        const uint64_t mykey = sort_select(cids, cdist, Mr);
         uint32_t oid = 0xFFFFFFFFu;
         float od = 0.0f;
         if (a.exact && Kp > 0) {
@@ -359,38 +509,42 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             oid = key_id(mykey);
             od = key_dist(mykey);
         }
-        if (lane < a.K) {
-            a.out_ids[(int64_t)q * a.K + lane] = lane < Kp ? (int32_t)oid : -1;
-            a.out_d2[(int64_t)q * a.K + lane] = lane < Kp ? od : 0.0f;
-        }
-        if (lane == 0) a.out_m[q] = Kp;
+        write_result<GFP64>(a, q, Kp, oid, od);
         __syncthreads();
     }
 }
 
-// Patches whose bins hold more IDs than a wave's buffer: one wave each with
-// a larger buffer; the list of such patches is produced by k_search.
-template <int VEC, int CMAXB>
-__global__ __launch_bounds__(64) void k_search_big(SearchArgs a) {
-    __shared__ uint32_t cids[CMAXB];
-    __shared__ uint32_t cdist[CMAXB];
+// Union search without early stop: all IDs of the L bins are gathered,
+// sorted and deduplicated in LDS (T <= CMAX), else the patch is deferred.
+template <int VEC, int CMAX, bool BIG, bool GFP64>
+__global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
+    __shared__ uint32_t cids[CMAX];
+    __shared__ uint32_t cdist[CMAX];
     __shared__ uint32_t sstart[kMaxL + 1];
     __shared__ uint32_t soff[kMaxL];
     const int lane = threadIdx.x;
-    const int L = a.L, D = a.D;
-    const int nover = (int)a.counters[0];
-    for (int t = blockIdx.x; t < nover; t += gridDim.x) {
-        const int q = a.overflow[t];
+    const int L = a.L;
+    const int nq = BIG ? (int)a.counters[0] : a.Q;
+
+    for (int t = blockIdx.x; t < nq; t += gridDim.x) {
+        const int q = BIG ? a.overflow[t] : t;
         uint32_t off = 0, cnt = 0;
         if (lane < L) probe_bin(a.dir + (uint64_t)lane * a.dir_cap, a.dir_cap, a.qkeys[(int64_t)q * L + lane], off, cnt);
         const int T = wave_sum_i32((int)cnt);
-        if (T > CMAXB) {
-            if (lane == 0) {
-                a.out_m[q] = -1;
-                a.out_ncand[q] = T;
-                atomicAdd(&a.counters[2], 1u);
+        if (T > CMAX) {
+            if (!BIG) {
+                if (lane == 0) {
+                    const unsigned int pos = atomicAdd(&a.counters[0], 1u);
+                    a.overflow[pos] = q;
+                }
+            } else {
+                if (lane == 0) {
+                    a.out_m[q] = -1;
+                    a.out_ncand[q] = T;
+                    atomicAdd(&a.counters[2], 1u);
+                }
+                if (lane < a.K) a.out_ids[(int64_t)q * a.K + lane] = -1;
             }
-            if (lane < a.K) a.out_ids[(int64_t)q * a.K + lane] = -1;
             continue;
         }
         const int incl = wave_incl_scan((int)cnt);
@@ -409,7 +563,7 @@ __global__ __launch_bounds__(64) void k_search_big(SearchArgs a) {
             cids[i] = a.tids[(int64_t)lo * a.N + soff[lo] + (i - sstart[lo])];
         }
         __syncthreads();
-        wave_sort_u32(cids, T);
+        if (T > 0) wave_sort_u32(cids, T);
         int M = 0;
         for (int b = 0; b < T; b += 64) {
             const int i = b + lane;
@@ -428,23 +582,19 @@ __global__ __launch_bounds__(64) void k_search_big(SearchArgs a) {
         }
         if (lane == 0) a.out_ncand[q] = M;
         float qv[VEC];
-        {
-            const int hl = lane & 31;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) qv[e] = (hl * VEC + e < D) ? a.qfeat[(int64_t)q * D + hl * VEC + e] : 0.0f;
-        }
+        load_query<VEC>(a, q, qv);
         int Mr = M;
         if (a.rerank > 0 && M > a.rerank) {
-            cand_distances<VEC, true>(qv, D, a.hi, a.lo, cids, cdist, 0, M);
-            const uint64_t k2 = select_topk(cids, cdist, M, a.rerank);
+            cand_distances<VEC, true>(qv, a.D, a.hi, a.lo, cids, cdist, M);
+            const uint64_t k2 = M <= 256 ? sort_select(cids, cdist, M) : select_topk(cids, cdist, M, a.rerank);
             __syncthreads();
             if (lane < a.rerank) cids[lane] = key_id(k2);
             __syncthreads();
             Mr = a.rerank;
         }
-        cand_distances<VEC, false>(qv, D, a.hi, a.lo, cids, cdist, 0, Mr);
+        cand_distances<VEC, false>(qv, a.D, a.hi, a.lo, cids, cdist, Mr);
         const int Kp = min(a.K, Mr);
-        const uint64_t mykey = select_topk(cids, cdist, Mr, Kp);
+        const uint64_t mykey = Mr <= 256 ? sort_select(cids, cdist, Mr) : select_topk(cids, cdist, Mr, Kp);
         uint32_t oid = 0xFFFFFFFFu;
         float od = 0.0f;
         if (a.exact && Kp > 0) {
@@ -453,11 +603,7 @@ __global__ __launch_bounds__(64) void k_search_big(SearchArgs a) {
             oid = key_id(mykey);
             od = key_dist(mykey);
         }
-        if (lane < a.K) {
-            a.out_ids[(int64_t)q * a.K + lane] = lane < Kp ? (int32_t)oid : -1;
-            a.out_d2[(int64_t)q * a.K + lane] = lane < Kp ? od : 0.0f;
-        }
-        if (lane == 0) a.out_m[q] = Kp;
+        write_result<GFP64>(a, q, Kp, oid, od);
         __syncthreads();
     }
 }
@@ -466,26 +612,39 @@ constexpr int kCapMax = 256;      // early-stop limit a wave can hold
 constexpr int kUnionMax = 2048;   // uncapped: IDs per wave before deferring
 constexpr int kUnionBig = 8192;   // uncapped, deferred patches
 
+template <int VEC, bool GFP64>
+static void launch_search_t(const SearchArgs& a, int grid, hipStream_t st) {
+    if (a.cap > 0)
+        hipLaunchKernelGGL((k_search_cap<VEC, GFP64>), dim3(grid), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_search_union<VEC, kUnionMax, false, GFP64>), dim3(grid), dim3(64), 0, st, a);
+}
+
 hipError_t launch_search(const SearchArgs& a, hipStream_t st) {
     if (a.Q == 0) return hipSuccess;
-    const int grid = a.Q < 16384 ? a.Q : 16384;
+    const int grid = a.Q < 32768 ? a.Q : 32768;
     const bool v4 = a.D % 4 == 0 && a.D <= 128;
     if (!v4 && a.D > 32) return hipErrorInvalidValue;
-    if (a.cap > 0) {
-        if (a.cap > kCapMax) return hipErrorInvalidValue;
-        if (v4) hipLaunchKernelGGL((k_search<4, kCapMax, true>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_search<1, kCapMax, true>), dim3(grid), dim3(64), 0, st, a);
+    if (a.cap > kCapMax) return hipErrorInvalidValue;
+    const bool g64 = a.gram && a.gram_fp64;
+    if (v4) {
+        if (g64) launch_search_t<4, true>(a, grid, st); else launch_search_t<4, false>(a, grid, st);
     } else {
-        if (v4) hipLaunchKernelGGL((k_search<4, kUnionMax, false>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_search<1, kUnionMax, false>), dim3(grid), dim3(64), 0, st, a);
+        if (g64) launch_search_t<1, true>(a, grid, st); else launch_search_t<1, false>(a, grid, st);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_search_overflow(const SearchArgs& a, int grid, hipStream_t st) {
     const bool v4 = a.D % 4 == 0 && a.D <= 128;
-    if (v4) hipLaunchKernelGGL((k_search_big<4, kUnionBig>), dim3(grid), dim3(64), 0, st, a);
-    else hipLaunchKernelGGL((k_search_big<1, kUnionBig>), dim3(grid), dim3(64), 0, st, a);
+    const bool g64 = a.gram && a.gram_fp64;
+    if (v4) {
+        if (g64) hipLaunchKernelGGL((k_search_union<4, kUnionBig, true, true>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_search_union<4, kUnionBig, true, false>), dim3(grid), dim3(64), 0, st, a);
+    } else {
+        if (g64) hipLaunchKernelGGL((k_search_union<1, kUnionBig, true, true>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_search_union<1, kUnionBig, true, false>), dim3(grid), dim3(64), 0, st, a);
+    }
     return hipGetLastError();
 }
 

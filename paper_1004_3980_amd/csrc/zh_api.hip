@@ -34,7 +34,8 @@ struct Dict {
     uint64_t cap = 0;             // directory slots per table
     const float* resid = nullptr; // borrowed
     Buf hi, lo;                   // [n, D] split planes
-    Buf alpha, beta, anorm, ahi, alo;
+    Buf alpha, beta, bc0[2], ahi, alo;
+    float bc1[2] = {0.f, 0.f}, bc2[2] = {0.f, 0.f};
     Buf dir;                      // [L, cap] Slot
     Buf tids;                     // [L, n] uint32
     std::vector<float> h_alpha, h_beta;
@@ -56,7 +57,9 @@ struct zh_ctx {
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
     int64_t Q = 0;
-    Buf lr, maps, qfeat, qmu, qkeys, ids, d2, m, ncand, w, over, xhat, e, tmp, counters;
+    Buf lr, maps, qfeat, qmu, qkeys, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram;
+    bool gram_valid = false;
+    int gram_fp64 = 0;
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -208,6 +211,13 @@ Taps gauss_taps(double sigma) {
     return t;
 }
 
+void set_bounds(HashArgs& ha, Dict& d, int prec) {
+    ha.bound_c0 = P<float>(d.bc0[prec]);
+    ha.bound_c1 = d.bc1[prec];
+    ha.bound_c2 = d.bc2[prec];
+    ha.inv_w = 1.0f / d.w;
+}
+
 zh_status set_device(zh_ctx* c) {
     HIPCHK(c, hipSetDevice(c->device));
     return ZH_OK;
@@ -252,6 +262,8 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.dump_cap = dump_cap;
     a.overflow = P<int32_t>(c->over);
     a.counters = P<unsigned int>(c->counters);
+    a.gram = c->gram_valid ? c->gram.p : nullptr;
+    a.gram_fp64 = c->gram_fp64;
     HIPCHK(c, launch_search(a, c->stream));
     if (a.cap == 0) HIPCHK(c, launch_search_overflow(a, 1024, c->stream));
     return ZH_OK;
@@ -289,7 +301,7 @@ void zh_destroy(zh_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (Dict& d : c->dicts) {
-        release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.anorm);
+        release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.bc0[0]); release(c, d.bc0[1]);
         release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.tids);
     }
     for (int st = 0; st < ZH_T_COUNT; ++st)
@@ -298,7 +310,7 @@ void zh_destroy(zh_ctx* c) {
                 if (c->ev[st][i][j]) (void)hipEventDestroy(c->ev[st][i][j]);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -397,27 +409,29 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     hash_params(seed, L, k, D, (double)w, d.h_alpha, d.h_beta);
     const int m = L * k;
     const int DP = (D + 31) & ~31;
-    std::vector<float> anorm(m);
     std::vector<uint16_t> ahi((size_t)m * DP, 0), alo((size_t)m * DP, 0);
     for (int j = 0; j < m; ++j) {
-        double s = 0.0;
         for (int i = 0; i < D; ++i) {
             const float a = d.h_alpha[(size_t)j * D + i];
-            s += (double)a * (double)a;
             const uint16_t h = bf16_rne_host(a);
             ahi[(size_t)j * DP + i] = h;
             alo[(size_t)j * DP + i] = bf16_rne_host(a - bf16_f_host(h));
         }
-        anorm[j] = (float)(std::sqrt(s) * (1.0 + 1e-12)) * (1.0f + 1e-6f);
     }
+    std::vector<float> bc0[2] = {std::vector<float>(m), std::vector<float>(m)};
+    for (int pr = 0; pr < 2; ++pr)
+        hash_bound_coeffs(pr, D, (double)w, d.h_beta.data(), m, bc0[pr].data(), &d.bc1[pr], &d.bc2[pr]);
     TRY(ensure(c, d.alpha, sizeof(float) * (size_t)m * D));
     TRY(ensure(c, d.beta, sizeof(float) * (size_t)m));
-    TRY(ensure(c, d.anorm, sizeof(float) * (size_t)m));
+    TRY(ensure(c, d.bc0[0], sizeof(float) * (size_t)m));
+    TRY(ensure(c, d.bc0[1], sizeof(float) * (size_t)m));
     TRY(ensure(c, d.ahi, sizeof(uint16_t) * (size_t)m * DP));
     TRY(ensure(c, d.alo, sizeof(uint16_t) * (size_t)m * DP));
     HIPCHK(c, hipMemcpyAsync(d.alpha.p, d.h_alpha.data(), sizeof(float) * (size_t)m * D, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(d.beta.p, d.h_beta.data(), sizeof(float) * (size_t)m, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(d.anorm.p, anorm.data(), sizeof(float) * (size_t)m, hipMemcpyHostToDevice, c->stream));
+    for (int pr = 0; pr < 2; ++pr)
+        HIPCHK(c, hipMemcpyAsync(d.bc0[pr].p, bc0[pr].data(), sizeof(float) * (size_t)m, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpyAsync(d.ahi.p, ahi.data(), sizeof(uint16_t) * (size_t)m * DP, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(d.alo.p, alo.data(), sizeof(uint16_t) * (size_t)m * DP, hipMemcpyHostToDevice, c->stream));
     // keys of every pair in every table
@@ -433,7 +447,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     ha.a_hi = P<uint16_t>(d.ahi);
     ha.a_lo = P<uint16_t>(d.alo);
     ha.beta = P<float>(d.beta);
-    ha.anorm = P<float>(d.anorm);
+    set_bounds(ha, d, c->opts.proj);
     ha.w = w;
     ha.prec = c->opts.proj;
     ha.keys = P<uint64_t>(c->keys_dict);
@@ -502,7 +516,7 @@ zh_status zh_hash(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* c
     ha.a_hi = P<uint16_t>(d.ahi);
     ha.a_lo = P<uint16_t>(d.alo);
     ha.beta = P<float>(d.beta);
-    ha.anorm = P<float>(d.anorm);
+    set_bounds(ha, d, c->opts.proj);
     ha.w = d.w;
     ha.prec = c->opts.proj;
     ha.keys = kp;
@@ -547,6 +561,10 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->over, sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->xhat, sizeof(float) * (size_t)Q * ps2));
+    // Gram matrices of the neighbours are formed by the search when K <= 8
+    c->gram_valid = K <= 8;
+    c->gram_fp64 = c->opts.lle_fp64;
+    if (c->gram_valid) TRY(ensure(c, c->gram, (c->gram_fp64 ? 8 : 4) * (size_t)Q * 36));
     HIPCHK(c, hipMemcpyAsync(c->lr.p, lr, sizeof(float) * (size_t)h * w, hipMemcpyDeviceToDevice, c->stream));
     c->qh = h;
     c->qw = w;
@@ -570,7 +588,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     ha.a_hi = P<uint16_t>(d.ahi);
     ha.a_lo = P<uint16_t>(d.alo);
     ha.beta = P<float>(d.beta);
-    ha.anorm = P<float>(d.anorm);
+    set_bounds(ha, d, c->opts.proj);
     ha.w = d.w;
     ha.prec = c->opts.proj;
     ha.keys = P<uint64_t>(c->qkeys);
@@ -608,7 +626,10 @@ zh_status zh_lle_weights(zh_ctx* c, double lambda) {
     a.w = P<float>(c->w);
     a.n_fp64 = P<unsigned int>(c->counters) + C_LLE64;
     StageTimer t(c, ZH_T_LLE);
-    HIPCHK(c, launch_lle(a, c->stream));
+    if (c->gram_valid && c->gram_fp64 == c->opts.lle_fp64)
+        HIPCHK(c, launch_lle_solve(a, c->gram.p, c->gram_fp64, c->stream));
+    else
+        HIPCHK(c, launch_lle(a, c->stream));
     c->stage = 2;
     return ZH_OK;
 }

@@ -47,7 +47,10 @@ struct HashArgs {
     const uint16_t* a_hi;    // [L*k, DP] bf16 high parts (split projection), DP = D rounded to 32
     const uint16_t* a_lo;    // [L*k, DP] bf16 low parts
     const float* beta;       // [L*k]
-    const float* anorm;      // [L*k] upper bound of ||alpha_j||_2
+    const float* bound_c0;   // [L*k] per-hash constant term of the code error bound
+    float bound_c1;          // coefficient of the |alpha|.|v| MFMA value in the bound
+    float bound_c2;          // coefficient of |alpha.v|
+    float inv_w;             // fp32 1/w
     float w;
     int prec;                // 0 = fp32 MFMA, 1 = split bf16 MFMA
     uint64_t* keys;          // [n, L]
@@ -55,6 +58,10 @@ struct HashArgs {
     unsigned int* n_fixed;   // count of codes recomputed in FP64 (nullable)
 };
 hipError_t launch_hash(const HashArgs& a, hipStream_t st);
+size_t hash_lds_bytes(int prec, int D, int k);
+// bound coefficients for the MFMA projection of precision `prec` (host)
+void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, float* c0, float* c1,
+                       float* c2);
 
 // ---- table build (k_table.hip) ----------------------------------------------
 hipError_t launch_dir_clear(Slot* dir, uint64_t count, hipStream_t st);
@@ -86,6 +93,8 @@ struct SearchArgs {
     int dump_cap;
     int32_t* overflow;       // [Q] deferred queries (uncapped, too many IDs for a wave)
     unsigned int* counters;  // [0] overflow count, [1] FP64 rank fallbacks
+    void* gram;              // [Q, 36] packed Gram of the <= 8 neighbours, or null
+    int gram_fp64;           // gram holds double (1) or float (0)
 };
 hipError_t launch_search(const SearchArgs& a, hipStream_t st);
 hipError_t launch_search_overflow(const SearchArgs& a, int n_over, hipStream_t st);
@@ -104,6 +113,8 @@ struct LleArgs {
     unsigned int* n_fp64;    // FP64 redo count (nullable)
 };
 hipError_t lle_init();  // once per device, before any launch_lle
+// weights from packed Gram matrices [Q, 36] (K <= 8), thread per patch
+hipError_t launch_lle_solve(const LleArgs& a, const void* gram, int gram_fp64, hipStream_t st);
 hipError_t launch_lle(const LleArgs& a, hipStream_t st);
 hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m,
                         const float* w, const double* mu, const float* resid, float* xhat,
