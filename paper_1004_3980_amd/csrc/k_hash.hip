@@ -1,21 +1,24 @@
-// Projection, p-stable codes and bucket keys (Section 4.1, Eq. hash_fn;
-// Section 3.2: k concatenated hashes per table, L tables).
+// Projection, p-stable codes, bucket keys and bin lookup (Section 4.1,
+// Eq. hash_fn; Section 3.2: k concatenated hashes per table, L tables).
 //
 //   code_j(v) = floor((alpha_j . v + beta_j) / w)
 //
-// The dot products of a tile of 64 feature rows with the k hashes of one
-// table run on the matrix cores, either as fp32 MFMA or as three bf16 MFMAs
-// over a high/low split of both operands (alpha = a_hi + a_lo, v = v_hi +
-// v_lo; the products a_hi v_hi + a_hi v_lo + a_lo v_hi accumulate in fp32).
-// A fourth product of the absolute values bounds sum_i |alpha_i v_i|, which
-// gives a rigorous bound B on |P_mfma - P_exact|; when [P - B, P + B] holds
-// no integer the MFMA floor is the exact code, otherwise the code is
-// recomputed by the FP64 sequential dot product that defines it (all lanes of
-// a wave re-evaluate the flagged codes together). The codes therefore equal
-// the FP64 definition bit for bit.
+// One wave owns 16 feature rows and runs over all tables. The dot products of
+// its rows with the k hashes of a table run on the matrix cores, either as
+// fp32 MFMA or as three bf16 MFMAs over a high/low split of both operands
+// (alpha = a_hi + a_lo, v = v_hi + v_lo; a_hi v_hi + a_hi v_lo + a_lo v_hi
+// accumulate in fp32); the split of the wave's rows stays in registers for
+// all tables. A fourth product of the absolute values bounds
+// sum_i |alpha_i v_i|, which gives a rigorous bound B on |P_mfma - P_exact|;
+// when [P - B, P + B] holds no integer the MFMA floor is the exact code,
+// otherwise the code is recomputed by the FP64 sequential dot product that
+// defines it (in a second kernel, for the few tables that need it). The
+// codes therefore equal the FP64 definition bit for bit.
 //
-// The k codes of a table are folded into a 64-bit key in index order:
-//   h = fmix64(GOLDEN*(l+1)); h = fmix64(h ^ uint32(c_j)) for j = 0..k-1.
+// The k codes of a table are folded into a 64-bit key in index order,
+//   h = fmix64(GOLDEN*(l+1)); h = fmix64(h ^ uint32(c_j)) for j = 0..k-1,
+// and, when a directory is given, a third kernel looks up each key's bin
+// (offset, count).
 #include <cmath>
 
 #include "zh_internal.h"
@@ -26,8 +29,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kHashBQ = 64;   // feature rows per workgroup
-constexpr int kHashWaves = 4;
+constexpr int kRowsPerWave = 16;
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
@@ -48,171 +50,354 @@ __device__ __forceinline__ u16x8 abs8(u16x8 x) {
     return x & m;
 }
 
-// Bound coefficients, per hash: B = c1 * S_abs + c2 * |S| + c0[j] with
-// S_abs the MFMA value of sum |alpha_hi_i| |v_hi_i| (or of sum |alpha_i||v_i|
-// on the fp32 path). Computed on the host, rounded up.
-template <int PREC>
-__global__ __launch_bounds__(256) void k_hash(HashArgs a) {
-    const int D = a.D;
-    const int DP = PREC == 0 ? ((D + 3) & ~3) : ((D + 31) & ~31);
-    const int KP = a.k <= 16 ? 16 : 32;
-    const int m = a.L * a.k;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t q0 = (int64_t)blockIdx.x * kHashBQ;
-
-    extern __shared__ float smem[];
-    // fp32 path: sfeat [64][DP+1] floats; split path: vh, vl [64][DP] bf16
-    float* sfeat = smem;
-    uint16_t* vh = reinterpret_cast<uint16_t*>(smem);
-    uint16_t* vl = vh + kHashBQ * DP;
-    const int feat_words = PREC == 0 ? kHashBQ * (DP + 1) : kHashBQ * DP;  // 32-bit words
-    int32_t* sC = reinterpret_cast<int32_t*>(smem + feat_words) + wave * (a.k * kHashBQ);  // per wave [k][64]
-    uint16_t* flist = reinterpret_cast<uint16_t*>(smem + feat_words + kHashWaves * a.k * kHashBQ) +
-                      wave * (a.k * kHashBQ);
-
-    for (int t = threadIdx.x; t < kHashBQ * DP; t += blockDim.x) {
-        const int r = t / DP, c = t % DP;
-        const int64_t q = q0 + r;
-        const float x = (q < a.n && c < D) ? a.feat[q * D + c] : 0.0f;
-        if (PREC == 0) {
-            sfeat[r * (DP + 1) + c] = x;
-        } else {
-            const uint16_t h = bf16_rne(x);
-            vh[r * DP + c] = h;
-            vl[r * DP + c] = bf16_rne(x - bf16_to_f(h));
+__device__ __forceinline__ void probe_bin_h(const Slot* __restrict__ dir, uint64_t cap, uint64_t key,
+                                            uint32_t& off, uint32_t& cnt) {
+    const uint64_t mask = cap - 1;
+    uint64_t s = key & mask;
+    off = 0;
+    cnt = 0;
+    for (uint64_t step = 0; step < cap; ++step) {
+        const uint4 e = *reinterpret_cast<const uint4*>(dir + s);
+        const uint64_t k = ((uint64_t)e.y << 32) | e.x;
+        if (k == key) {
+            cnt = e.z;
+            off = e.w;
+            return;
         }
+        if (k == kEmptyKey) return;
+        s = (s + 1) & mask;
+    }
+}
+
+constexpr int kWaves = 4;         // waves per workgroup, 16 feature rows each
+constexpr int kStage = 2;         // tables whose alpha is staged in LDS together
+
+// Staged hash rows of a pair of tables, padded to whole 16-row MFMA tiles.
+__host__ __device__ inline int stage_rows(int k) { return (kStage * k + 15) & ~15; }
+// LDS row stride of the staged alpha. Split path: halfwords, the 32*NS
+// coordinates of the MFMA steps plus one 16-byte chunk, so that a row holds
+// an odd number of chunks and the 16-byte reads of eight consecutive rows
+// fall on distinct banks. fp32 path: an odd number of words.
+__host__ __device__ inline int stage_stride(int prec, int D) {
+    if (prec == 0) return (D & 1) ? D : D + 1;
+    return ((D + 31) & ~31) + 8;
+}
+__host__ __device__ inline int fold_tables(int k) { return k <= 24 ? 4 : 2; }
+// bytes of the staged alpha, then beta and the bound constant of each staged row
+__host__ __device__ inline int stage_alpha_bytes(int prec, int k, int D) {
+    const int R = stage_rows(k);
+    return prec == 0 ? R * stage_stride(0, D) * 4 : 2 * R * stage_stride(1, D) * 2;
+}
+__host__ __device__ inline int stage_bytes(int prec, int k, int D) {
+    return ((stage_alpha_bytes(prec, k, D) + 15) & ~15) + 2 * stage_rows(k) * 4;
+}
+
+// PREC 0: fp32 MFMA (4 coordinates per step); PREC 1: split bf16 (32 per
+// step, NS steps). The alpha of two tables at a time is staged in LDS with
+// its beta and bound constants and shared by the four waves; on the split
+// path the next pair is fetched into registers while the current one is in
+// use. The 2k hash rows of a pair are packed into ceil(2k/16) MFMA tiles.
+// A code whose interval [P - B, P + B] holds an integer is left to
+// k_hash_fix: its table's bit is set in the row's dirty mask and the key
+// written here is replaced there.
+template <int PREC, int NS, int NPRE>
+__global__ __launch_bounds__(256) void k_hash(HashArgs a) {
+    const int D = a.D, k = a.k, L = a.L, m = L * k;
+    const int GK = kStage * k;
+    const int R = stage_rows(k);
+    const int ntile = R >> 4;
+    const int nsteps = PREC == 0 ? (D + 3) / 4 : NS;
+    const int DP = (D + 31) & ~31;
+    const int DS = stage_stride(PREC, D);
+    const int fold = fold_tables(k);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ri = lane & 15, kb = lane >> 4;
+    const int64_t r0 = ((int64_t)blockIdx.x * kWaves + wave) * kRowsPerWave;
+    const int64_t myrow = r0 + ri;
+    const bool rowok = myrow < a.n;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* sA16 = reinterpret_cast<uint16_t*>(smem);
+    float* sAf = reinterpret_cast<float*>(smem);
+    float* sBeta = reinterpret_cast<float*>(smem + ((stage_alpha_bytes(PREC, k, D) + 15) & ~15));
+    float* sBc0 = sBeta + R;
+    // per wave codes of `fold` tables: [fold*k][16 rows]
+    int32_t* sC = reinterpret_cast<int32_t*>(smem + stage_bytes(PREC, k, D)) + wave * (fold * k * kRowsPerWave);
+
+    // B operand of this lane for every k-step: feature row ri, coordinates
+    // 32 s + 8 kb + e (e < 8) as bf16 high/low parts (PREC 1), or 4 s + kb
+    // as fp32 (PREC 0)
+    u16x8 bh[PREC == 1 ? NS : 1], bl[PREC == 1 ? NS : 1];
+    float bf[PREC == 0 ? 32 : 1];
+    if (PREC == 1) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int d = 32 * s + 8 * kb + e;
+                const float x = (rowok && d < D) ? a.feat[myrow * D + d] : 0.0f;
+                const uint16_t h = bf16_rne(x);
+                bh[s][e] = h;
+                bl[s][e] = bf16_rne(x - bf16_to_f(h));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+            const int d = 4 * s + kb;
+            bf[s] = (rowok && d < D) ? a.feat[myrow * D + d] : 0.0f;
+        }
+    }
+    const float c1 = a.bound_c1, c2 = a.bound_c2;
+
+    // split path: 16-byte chunks [plane][row][chunk], CH chunks a row (the
+    // zero-padded DP coordinates of the host copy); rows past the last table
+    // are zero
+    constexpr int CH = 4 * NS;
+    const int NC = 2 * GK * CH;
+    u16x8 pre[NPRE];
+    float pbc = 0.0f;
+    auto fetch = [&](int g) {
+        const int l0 = g * kStage;
+#pragma unroll
+        for (int c = 0; c < NPRE; ++c) {
+            const int ci = threadIdx.x + 256 * c;
+            u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (ci < NC) {
+                const int plane = ci >= GK * CH;
+                const int r2 = ci - plane * GK * CH;
+                const int r = r2 / CH, ch = r2 - r * CH;
+                const int grow = l0 * k + r;
+                if (grow < m) v = *reinterpret_cast<const u16x8*>((plane ? a.a_lo : a.a_hi) + (int64_t)grow * DP + 8 * ch);
+            }
+            pre[c] = v;
+        }
+        // beta and the bound constant: thread t < 2 GK takes one value
+        const int t = threadIdx.x;
+        const int r = t < GK ? t : t - GK;
+        pbc = 0.0f;
+        if (t < 2 * GK && l0 * k + r < m) pbc = (t < GK ? a.beta : a.bound_c0)[l0 * k + r];
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int c = 0; c < NPRE; ++c) {
+            const int ci = threadIdx.x + 256 * c;
+            if (ci < NC) {
+                const int plane = ci >= GK * CH;
+                const int r2 = ci - plane * GK * CH;
+                const int r = r2 / CH, ch = r2 - r * CH;
+                *reinterpret_cast<u16x8*>(sA16 + (plane * R + r) * DS + 8 * ch) = pre[c];
+            }
+        }
+        const int t = threadIdx.x;
+        if (t < 2 * GK) (t < GK ? sBeta[t] : sBc0[t - GK]) = pbc;
+    };
+    auto copy_f32 = [&](int g) {
+        const int l0 = g * kStage;
+        const int tot = GK * D;
+        for (int e = threadIdx.x; e < tot; e += 256) {
+            const int r = e / D, c = e - r * D;
+            sAf[r * DS + c] = l0 * k + r < m ? a.alpha[(int64_t)l0 * k * D + e] : 0.0f;
+        }
+        for (int t = threadIdx.x; t < 2 * GK; t += 256) {
+            const int r = t < GK ? t : t - GK;
+            const float v = l0 * k + r < m ? (t < GK ? a.beta : a.bound_c0)[l0 * k + r] : 0.0f;
+            (t < GK ? sBeta[r] : sBc0[r]) = v;
+        }
+    };
+
+    // rows GK..R-1 of the stage are never written by the staging: zero them
+    if (PREC == 1) {
+        const int padrows = R - GK;
+        for (int e = threadIdx.x; e < 2 * padrows * (DS / 8); e += 256) {
+            const int plane = e >= padrows * (DS / 8);
+            const int e2 = e - plane * padrows * (DS / 8);
+            const int r = GK + e2 / (DS / 8), ch = e2 % (DS / 8);
+            *reinterpret_cast<u16x8*>(sA16 + (plane * R + r) * DS + 8 * ch) = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+    } else {
+        for (int e = threadIdx.x; e < (R - GK) * DS; e += 256) sAf[GK * DS + e] = 0.0f;
+    }
+    for (int e = threadIdx.x; e < R - GK; e += 256) sBeta[GK + e] = sBc0[GK + e] = 0.0f;
+
+    const int ngroups = (L + kStage - 1) / kStage;
+    if (PREC == 1) {
+        fetch(0);
+        stash();
+    } else {
+        copy_f32(0);
     }
     __syncthreads();
 
-    const int iters = (a.L + kHashWaves - 1) / kHashWaves;
-    const int ri = lane & 15, kb = lane >> 4;
-    const float c1 = a.bound_c1, c2 = a.bound_c2;
-    const double wd = (double)a.w;
-
-    for (int it = 0; it < iters; ++it) {
-        const int l = it * kHashWaves + wave;
-        int nflag = 0;
-        if (l < a.L) {
-            f32x4 acc[2][4], aab[2][4];
+    uint64_t dirty = 0;
+    unsigned nflag = 0;
+    for (int g = 0; g < ngroups; ++g) {
+        const int l0 = g * kStage;
+        const int GKa = (L - l0 < kStage ? L - l0 : kStage) * k;
+        if (PREC == 1 && g + 1 < ngroups) fetch(g + 1);
+        for (int tt = 0; tt < ntile; ++tt) {
+            const int ar = tt * 16 + ri;
+            f32x4 cs = f32x4{0.f, 0.f, 0.f, 0.f}, cab = cs;
+            if (PREC == 1) {
+                f32x4 chl = cs, clh = cs;
+                const uint16_t* Ah = sA16 + ar * DS + 8 * kb;
+                const uint16_t* Al = Ah + R * DS;
+                u16x8 ah[NS], al[NS];
 #pragma unroll
-            for (int ht = 0; ht < 2; ++ht)
-#pragma unroll
-                for (int qt = 0; qt < 4; ++qt) {
-                    acc[ht][qt] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    aab[ht][qt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int s = 0; s < NS; ++s) {
+                    ah[s] = *reinterpret_cast<const u16x8*>(Ah + 32 * s);
+                    al[s] = *reinterpret_cast<const u16x8*>(Al + 32 * s);
                 }
-            const int nht = KP / 16;
-            if (PREC == 0) {
-                for (int d0 = 0; d0 < DP; d0 += 4) {
-                    const int d = d0 + kb;
-                    float bv[4];
 #pragma unroll
-                    for (int qt = 0; qt < 4; ++qt) bv[qt] = sfeat[(qt * 16 + ri) * (DP + 1) + d];
-#pragma unroll
-                    for (int ht = 0; ht < 2; ++ht) {
-                        if (ht >= nht) break;
-                        const int j = ht * 16 + ri;
-                        const float av = (j < a.k && d < D) ? a.alpha[(int64_t)(l * a.k + j) * D + d] : 0.0f;
-#pragma unroll
-                        for (int qt = 0; qt < 4; ++qt) {
-                            acc[ht][qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[qt], acc[ht][qt], 0, 0, 0);
-                            aab[ht][qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(av), fabsf(bv[qt]), aab[ht][qt], 0, 0, 0);
-                        }
-                    }
+                for (int s = 0; s < NS; ++s) {
+                    const bf16x8 vhb = __builtin_bit_cast(bf16x8, bh[s]);
+                    const bf16x8 vlb = __builtin_bit_cast(bf16x8, bl[s]);
+                    const bf16x8 vab = __builtin_bit_cast(bf16x8, abs8(bh[s]));
+                    const bf16x8 ahb = __builtin_bit_cast(bf16x8, ah[s]);
+                    const bf16x8 alb = __builtin_bit_cast(bf16x8, al[s]);
+                    const bf16x8 aab8 = __builtin_bit_cast(bf16x8, abs8(ah[s]));
+                    cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vhb, cs, 0, 0, 0);
+                    chl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, chl, 0, 0, 0);
+                    clh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, clh, 0, 0, 0);
+                    cab = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aab8, vab, cab, 0, 0, 0);
                 }
+                cs = cs + (chl + clh);
             } else {
-                for (int d0 = 0; d0 < DP; d0 += 32) {
-                    const int d = d0 + 8 * kb;
-                    u16x8 xh[4], xl[4];
-#pragma unroll
-                    for (int qt = 0; qt < 4; ++qt) {
-                        xh[qt] = *reinterpret_cast<const u16x8*>(vh + (qt * 16 + ri) * DP + d);
-                        xl[qt] = *reinterpret_cast<const u16x8*>(vl + (qt * 16 + ri) * DP + d);
-                    }
-#pragma unroll
-                    for (int ht = 0; ht < 2; ++ht) {
-                        if (ht >= nht) break;
-                        const int j = ht * 16 + ri;
-                        u16x8 ah = u16x8{0, 0, 0, 0, 0, 0, 0, 0}, al = ah;
-                        if (j < a.k) {
-                            const int64_t off = (int64_t)(l * a.k + j) * DP + d;
-                            ah = *reinterpret_cast<const u16x8*>(a.a_hi + off);
-                            al = *reinterpret_cast<const u16x8*>(a.a_lo + off);
-                        }
-                        const bf16x8 ahb = __builtin_bit_cast(bf16x8, ah);
-                        const bf16x8 alb = __builtin_bit_cast(bf16x8, al);
-                        const bf16x8 aab8 = __builtin_bit_cast(bf16x8, abs8(ah));
-#pragma unroll
-                        for (int qt = 0; qt < 4; ++qt) {
-                            const bf16x8 vhb = __builtin_bit_cast(bf16x8, xh[qt]);
-                            const bf16x8 vlb = __builtin_bit_cast(bf16x8, xl[qt]);
-                            const bf16x8 vab = __builtin_bit_cast(bf16x8, abs8(xh[qt]));
-                            acc[ht][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vhb, acc[ht][qt], 0, 0, 0);
-                            acc[ht][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, acc[ht][qt], 0, 0, 0);
-                            acc[ht][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, acc[ht][qt], 0, 0, 0);
-                            aab[ht][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aab8, vab, aab[ht][qt], 0, 0, 0);
-                        }
-                    }
+                const float* Af = sAf + ar * DS;
+                for (int s = 0; s < nsteps; ++s) {
+                    const int d = 4 * s + kb;
+                    const float av = d < D ? Af[d] : 0.0f;
+                    cs = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[s < 32 ? s : 0], cs, 0, 0, 0);
+                    cab = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(av), fabsf(bf[s < 32 ? s : 0]), cab, 0, 0, 0);
                 }
             }
-            // D layout of a 16x16 MFMA tile: lane holds rows 4*(lane/16)+i, column
-            // lane%16. Decide every code whose bin is certain; list the others.
+            // 16x16 tile: lane holds hash rows 4*kb+i of the tile, feature row ri
+            const float4 be = *reinterpret_cast<const float4*>(sBeta + tt * 16 + 4 * kb);
+            const float4 b0 = *reinterpret_cast<const float4*>(sBc0 + tt * 16 + 4 * kb);
+            const float bev[4] = {be.x, be.y, be.z, be.w};
+            const float b0v[4] = {b0.x, b0.y, b0.z, b0.w};
 #pragma unroll
-            for (int ht = 0; ht < 2; ++ht) {
-                if (ht >= nht) break;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int j = ht * 16 + 4 * kb + i;
-                    const int row = l * a.k + (j < a.k ? j : 0);
-                    const float bj = a.beta[row], c0 = a.bound_c0[row];
-#pragma unroll
-                    for (int qt = 0; qt < 4; ++qt) {
-                        const int qi = qt * 16 + ri;
-                        const bool valid = j < a.k && q0 + qi < a.n;
-                        const float S = acc[ht][qt][i];
-                        const float P = (S + bj) * a.inv_w;
-                        const float B = fmaf(c1, aab[ht][qt][i], fmaf(c2, fabsf(S), c0));
-                        const float n = rintf(P);
-                        const bool flag = !(fabsf(P - n) > B) || !(fabsf(P) < 4194304.0f);
-                        const uint64_t fm = __ballot(flag && valid);
-                        if (flag && valid) flist[nflag + __popcll(fm & lanemask_lt())] = (uint16_t)((j << 6) | qi);
-                        nflag += __popcll(fm);
-                        if (valid) sC[j * kHashBQ + qi] = flag ? 0 : (int32_t)floorf(P);
+            for (int i = 0; i < 4; ++i) {
+                const int hr = tt * 16 + 4 * kb + i;
+                const bool valid = hr < GKa && rowok;
+                const float S = cs[i];
+                const float P = (S + bev[i]) * a.inv_w;
+                const float B = fmaf(c1, cab[i], fmaf(c2, fabsf(S), b0v[i]));
+                const float n = rintf(P);
+                const bool flag = !(fabsf(P - n) > B) || !(fabsf(P) < 4194304.0f);
+                if (valid) {
+                    if (flag) {
+                        dirty |= 1ull << (l0 + (hr >= k ? 1 : 0));
+                        ++nflag;
                     }
+                    sC[((l0 % fold) * k + hr) * kRowsPerWave + ri] = flag ? 0 : (int32_t)floorf(P);
                 }
             }
         }
-        __syncthreads();
-        if (l < a.L) {
-            // FP64 sequential dot products of the flagged codes, one per lane
-            for (int f = lane; f < nflag; f += 64) {
-                const int e = flist[f];
-                const int j = e >> 6, qi = e & 63;
-                const int row = l * a.k + j;
-                const float* ar = a.alpha + (int64_t)row * D;
-                const float* vr = a.feat + (q0 + qi) * D;
-                double s = 0.0;
-#pragma unroll 10
-                for (int i = 0; i < D; ++i) s = s + (double)ar[i] * (double)vr[i];
-                sC[j * kHashBQ + qi] = floor_sat((s + (double)a.beta[row]) / wd);
-            }
-            if (lane == 0 && nflag && a.n_fixed) atomicAdd(a.n_fixed, (unsigned)nflag);
+        __syncthreads();   // the staged pair is no longer read; codes visible to the wave
+        if (g + 1 < ngroups) {
+            if (PREC == 1)
+                stash();
+            else
+                copy_f32(g + 1);
         }
-        __syncthreads();
-        if (l < a.L) {
-            const int qi = lane;
-            const int64_t q = q0 + qi;
-            if (q < a.n) {
-                uint64_t h = key_seed(l);
-                for (int j = 0; j < a.k; ++j) {
-                    const int32_t c = sC[j * kHashBQ + qi];
-                    if (a.codes) a.codes[q * m + l * a.k + j] = c;
+        if ((l0 + kStage) % fold == 0 || g + 1 == ngroups) {
+            // fold codes into keys: lane = (table of the fold group, feature row)
+            const int fl0 = (l0 / fold) * fold;
+            const int t = lane >> 4, rr = lane & 15;
+            const int lt = fl0 + t;
+            const int64_t row = r0 + rr;
+            if (t < fold && lt < L && row < a.n) {
+                uint64_t h = key_seed(lt);
+                for (int j = 0; j < k; ++j) {
+                    const int32_t c = sC[(t * k + j) * kRowsPerWave + rr];
+                    if (a.codes) a.codes[row * m + lt * k + j] = c;
                     h = key_step(h, c);
                 }
-                a.keys[q * a.L + l] = key_final(h);
+                a.keys[row * L + lt] = key_final(h);
             }
         }
         __syncthreads();
+    }
+    dirty |= __shfl_xor(dirty, 16);
+    dirty |= __shfl_xor(dirty, 32);
+    if (kb == 0 && rowok) a.dirty[myrow] = dirty;
+    if (nflag && a.n_fixed) atomicAdd(a.n_fixed, nflag);
+}
+
+// Keys of the (row, table) pairs whose codes were not certain: every code of
+// the table is recomputed by the FP64 sequential dot product that defines it
+// (coordinates in index order), and the key is folded again. One wave (one
+// workgroup) takes 64 rows; its lanes form G = min(4, 64/k) groups, each
+// group one (row, table) pair with a lane per hash. The k alpha rows of the
+// table (contiguous in memory) and the feature row are first copied to LDS
+// with coalesced loads; each lane then runs its dot product from LDS.
+__host__ __device__ inline int fix_groups(int k) { return 64 / k < 4 ? 64 / k : 4; }
+
+__global__ __launch_bounds__(64) void k_hash_fix(HashArgs a) {
+    extern __shared__ float sfix[];   // [G][k*D alpha | D feature]
+    const int lane = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int k = a.k, D = a.D, L = a.L, m = L * k;
+    const int G = fix_groups(k);
+    const int per = (k + 1) * D;
+    const int grp = lane / k, jj = lane - grp * k;
+    const double wd = (double)a.w;
+    uint64_t mk = r0 + lane < a.n ? a.dirty[r0 + lane] : 0;
+    for (;;) {
+        int src_mine = 0, l_mine = 0, got = 0;
+        for (int g = 0; g < G; ++g) {
+            const uint64_t any = __ballot(mk != 0);
+            if (!any) break;
+            const int src = __builtin_ctzll(any);
+            const uint64_t bits = __shfl(mk, src);
+            const int l = __builtin_ctzll(bits);
+            if (lane == src) mk &= mk - 1;
+            // stage alpha rows l*k .. l*k+k-1 and the feature row of row r0+src
+            float* dst = sfix + g * per;
+            const float* asrc = a.alpha + (int64_t)l * k * D;
+#pragma unroll 8
+            for (int e = lane; e < k * D; e += 64) dst[e] = asrc[e];
+            const float* vsrc = a.feat + (r0 + src) * D;
+            for (int e = lane; e < D; e += 64) dst[k * D + e] = vsrc[e];
+            if (grp == g) {
+                src_mine = src;
+                l_mine = l;
+            }
+            ++got;
+        }
+        if (got == 0) break;
+        __syncthreads();
+        const bool act = grp < got;
+        const int64_t row = r0 + src_mine;
+        int32_t c = 0;
+        if (act) {
+            const int hrow = l_mine * k + jj;
+            const float* ar = sfix + grp * per + jj * D;
+            const float* vr = sfix + grp * per + k * D;
+            double s = 0.0;
+#pragma unroll 4
+            for (int i = 0; i < D; ++i) s = s + (double)ar[i] * (double)vr[i];
+            c = floor_sat((s + (double)a.beta[hrow]) / wd);
+            if (a.codes) a.codes[row * m + hrow] = c;
+        }
+        uint64_t h = key_seed(l_mine);
+        const int base = act ? grp * k : 0;
+        for (int j = 0; j < k; ++j) h = key_step(h, __shfl(c, base + j));
+        if (act && jj == 0) a.keys[row * L + l_mine] = key_final(h);
+        __syncthreads();
+    }
+}
+
+// Bin (offset, count) of every key: one thread per (row, table).
+__global__ __launch_bounds__(256) void k_probe(const uint64_t* __restrict__ keys, int64_t n, int L,
+                                               const Slot* __restrict__ dir, uint64_t cap, uint2* __restrict__ bins) {
+    const int64_t total = n * L;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i % L);
+        uint32_t off, cnt;
+        probe_bin_h(dir + (uint64_t)l * cap, cap, keys[i], off, cnt);
+        bins[i] = make_uint2(off, cnt);
     }
 }
 
@@ -249,20 +434,44 @@ void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, floa
     for (int j = 0; j < m; ++j) c0[j] = (float)((2.0 * 3.1 * u * std::fabs((double)beta[j]) / w + 1e-30) * up);
 }
 
-size_t hash_lds_bytes(int prec, int D, int k) {
-    const int DP = prec == 0 ? ((D + 3) & ~3) : ((D + 31) & ~31);
-    const size_t feat_words = prec == 0 ? (size_t)kHashBQ * (DP + 1) : (size_t)kHashBQ * DP;
-    return 4 * (feat_words + (size_t)kHashWaves * k * kHashBQ) + 2 * (size_t)kHashWaves * k * kHashBQ;
+template <int NS>
+static void launch_split(const HashArgs& a, dim3 grid, size_t lds, hipStream_t st) {
+    const int nc = 2 * kStage * a.k * 4 * NS;
+    if (nc <= 5 * 256)
+        hipLaunchKernelGGL((k_hash<1, NS, 5>), grid, dim3(256), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_hash<1, NS, 8>), grid, dim3(256), lds, st, a);
 }
 
 hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    const size_t lds = hash_lds_bytes(a.prec, a.D, a.k);
-    const dim3 grid((unsigned)((a.n + kHashBQ - 1) / kHashBQ));
-    if (a.prec == 0)
-        hipLaunchKernelGGL(k_hash<0>, grid, dim3(256), lds, st, a);
-    else
-        hipLaunchKernelGGL(k_hash<1>, grid, dim3(256), lds, st, a);
+    if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty)
+        return hipErrorInvalidValue;
+    const int rows = kWaves * kRowsPerWave;
+    const dim3 grid((unsigned)((a.n + rows - 1) / rows));
+    const size_t lds = (size_t)stage_bytes(a.prec, a.k, a.D) +
+                       (size_t)kWaves * fold_tables(a.k) * a.k * kRowsPerWave * 4;
+    if (a.prec == 0) {
+        hipLaunchKernelGGL((k_hash<0, 1, 1>), grid, dim3(256), lds, st, a);
+    } else {
+        switch ((a.D + 31) / 32) {
+            case 1: launch_split<1>(a, grid, lds, st); break;
+            case 2: launch_split<2>(a, grid, lds, st); break;
+            case 3: launch_split<3>(a, grid, lds, st); break;
+            default: launch_split<4>(a, grid, lds, st); break;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 gfix((unsigned)((a.n + 63) / 64));
+    const size_t lfix = (size_t)fix_groups(a.k) * (a.k + 1) * a.D * sizeof(float);
+    hipLaunchKernelGGL(k_hash_fix, gfix, dim3(64), lfix, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess || !a.bins) return e;
+    const int64_t total = a.n * a.L;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)g), dim3(256), 0, st, a.keys, a.n, a.L, a.dir, a.dir_cap, a.bins);
     return hipGetLastError();
 }
 

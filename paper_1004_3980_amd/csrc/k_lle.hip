@@ -7,6 +7,8 @@
 // A workgroup (one wave) forms the Gram matrices of QPW patches one after
 // the other, every lane owning one (a, b) entry; then each lane solves one
 // patch's system.
+#include <type_traits>
+
 #include "zh_internal.h"
 
 namespace zh {
@@ -146,6 +148,124 @@ __global__ __launch_bounds__(64) void k_lle(LleArgs a) {
         }
         for (int r = 0; r < K; ++r) wout[r] = r < m ? (float)wv[r] : 0.0f;
     }
+}
+
+// One halving step of a reduce-scatter over the lanes of a half wave: lanes
+// whose bit O is clear keep the first half of their N values, the others the
+// second half, each adding its partner's partial sums; (base, cnt) track the
+// index range the lane holds.
+template <typename T, int N, int O, int NMAX>
+__device__ __forceinline__ void rs_step(T (&v)[NMAX], int& base, int& cnt) {
+    constexpr int NK = (N + 1) / 2;
+    const bool hb = (threadIdx.x & O) != 0;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+        const T lo_v = v[i];
+        const T hi_v = (NK + i < N) ? v[NK + i] : (T)0;
+        const T send = hb ? lo_v : hi_v;
+        const T keep = hb ? hi_v : lo_v;
+        v[i] = keep + __shfl_xor(send, O);
+    }
+    if (hb) {
+        base += NK;
+        cnt -= NK;
+    } else {
+        cnt = cnt < NK ? cnt : NK;
+    }
+}
+
+// Packed Gram matrix (lower triangle, p = i(i+1)/2 + j, 36 entries) of the
+// m <= 8 neighbours of each patch, Z_r = q - y_r, in T precision. Two patches
+// per wave: half h of the wave owns one patch and lane l of the half holds
+// coordinates [VEC l, VEC l + VEC); the 8 neighbour rows are loaded before
+// use, partial products are reduce-scattered over the half in two groups of
+// 18 entries.
+template <typename T, int VEC>
+__global__ __launch_bounds__(256) void k_gram(LleArgs a, T* __restrict__ gram) {
+    typedef typename std::conditional<VEC == 4, uint2, uint32_t>::type raw_t;
+    constexpr int PI[36] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4, 5, 5, 5,
+                            5, 5, 5, 6, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7};
+    constexpr int PJ[36] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4, 0, 1, 2,
+                            3, 4, 5, 0, 1, 2, 3, 4, 5, 6, 0, 1, 2, 3, 4, 5, 6, 7};
+    const int lane = threadIdx.x & 63, hl = lane & 31, half = lane >> 5;
+    const int wpb = blockDim.x >> 6;
+    const int D = a.D;
+    const bool dl = hl * VEC < D;
+    for (int pr = blockIdx.x * wpb + (threadIdx.x >> 6); 2 * pr < a.Q; pr += gridDim.x * wpb) {
+        const int q = 2 * pr + half;
+        const bool qv = q < a.Q;
+        const int m = qv ? a.m[q] : 0;
+        float qf[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) qf[e] = (qv && dl) ? a.qfeat[(int64_t)q * D + hl * VEC + e] : 0.0f;
+        raw_t hr[8], lr[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            hr[r] = raw_t{};
+            lr[r] = raw_t{};
+            if (r < m && dl) {
+                const uint32_t id = (uint32_t)a.ids[(int64_t)q * a.K + r];
+                const uint32_t bo = (id * (uint32_t)D + (uint32_t)(hl * VEC)) * 2u;
+                if constexpr (VEC == 4) {
+                    hr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.hi) + bo);
+                    lr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.lo) + bo);
+                } else {
+                    hr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.hi) + bo);
+                    lr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.lo) + bo);
+                }
+            }
+        }
+        T z[8][VEC];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            uint32_t hv[VEC], lv[VEC];
+            if constexpr (VEC == 4) {
+                hv[0] = hr[r].x & 0xFFFFu; hv[1] = hr[r].x >> 16; hv[2] = hr[r].y & 0xFFFFu; hv[3] = hr[r].y >> 16;
+                lv[0] = lr[r].x & 0xFFFFu; lv[1] = lr[r].x >> 16; lv[2] = lr[r].y & 0xFFFFu; lv[3] = lr[r].y >> 16;
+            } else {
+                hv[0] = hr[r];
+                lv[0] = lr[r];
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                z[r][e] = (r < m && dl) ? (T)qf[e] - (T)__uint_as_float((hv[e] << 16) | lv[e]) : (T)0;
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            T v[18];
+#pragma unroll
+            for (int p = 0; p < 18; ++p) {
+                T acc = (T)0;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc += z[PI[18 * g + p]][e] * z[PJ[18 * g + p]][e];
+                v[p] = acc;
+            }
+            int base = 0, cnt = 18;
+            rs_step<T, 18, 16>(v, base, cnt);
+            rs_step<T, 9, 8>(v, base, cnt);
+            rs_step<T, 5, 4>(v, base, cnt);
+            rs_step<T, 3, 2>(v, base, cnt);
+            rs_step<T, 2, 1>(v, base, cnt);
+            if (m > 0 && cnt >= 1) gram[(int64_t)q * 36 + 18 * g + base] = v[0];
+        }
+    }
+}
+
+hipError_t launch_gram(const LleArgs& a, void* gram, int gram_fp64, hipStream_t st) {
+    if (a.Q == 0) return hipSuccess;
+    if (a.K > 8 || a.D > 128) return hipErrorInvalidValue;
+    const bool v4 = a.D % 4 == 0;
+    if (!v4 && a.D > 32) return hipErrorInvalidValue;
+    int grid = (a.Q + 7) / 8;
+    if (grid > 65536) grid = 65536;
+    if (gram_fp64) {
+        if (v4) hipLaunchKernelGGL((k_gram<double, 4>), dim3(grid), dim3(256), 0, st, a, static_cast<double*>(gram));
+        else hipLaunchKernelGGL((k_gram<double, 1>), dim3(grid), dim3(256), 0, st, a, static_cast<double*>(gram));
+    } else {
+        if (v4) hipLaunchKernelGGL((k_gram<float, 4>), dim3(grid), dim3(256), 0, st, a, static_cast<float*>(gram));
+        else hipLaunchKernelGGL((k_gram<float, 1>), dim3(grid), dim3(256), 0, st, a, static_cast<float*>(gram));
+    }
+    return hipGetLastError();
 }
 
 // FP64 Gram of patch q's m neighbours straight from the rows (the slow path of

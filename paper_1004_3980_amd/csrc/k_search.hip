@@ -1,5 +1,5 @@
 // Candidate search for every LR patch (Section 3.2, Section 4.2):
-// probe the patch's bin in each of the L tables, collect the union of the
+// given the patch's bin in each of the L tables, collect the union of the
 // IDs found (t = 1), optionally with the early stop of Section 4.2 (tables in
 // order, IDs ascending inside a bin, stop at `cap` distinct IDs), then keep
 // the K nearest by squared l2 distance, ties broken by the lower ID.
@@ -12,34 +12,11 @@
 // re-ranked by that FP64 distance, so the result equals the FP64 definition.
 // Screened mode (rerank = R): the high plane alone (a bf16 feature) ranks the
 // candidates, the best R are re-ranked exactly in fp32.
-//
-// With K <= 8 the kernel also forms the Gram matrix G = Z Z^T of the chosen
-// neighbours (Z = query - neighbour rows, Section 4.2 Eq. LinSys) while those
-// rows are in cache, and stores it packed for the LLE solve.
 #include <type_traits>
 
 #include "zh_internal.h"
 
 namespace zh {
-
-__device__ __forceinline__ void probe_bin(const Slot* __restrict__ dir, uint64_t cap, uint64_t key,
-                                          uint32_t& off, uint32_t& cnt) {
-    const uint64_t mask = cap - 1;
-    uint64_t s = key & mask;
-    off = 0;
-    cnt = 0;
-    for (uint64_t step = 0; step < cap; ++step) {
-        const uint4 e = *reinterpret_cast<const uint4*>(dir + s);
-        const uint64_t k = ((uint64_t)e.y << 32) | e.x;
-        if (k == key) {
-            cnt = e.z;
-            off = e.w;
-            return;
-        }
-        if (k == kEmptyKey) return;
-        s = (s + 1) & mask;
-    }
-}
 
 // candidate ordering key: distance bits, then a "not exactly equal" bit, then
 // the ID (IDs < 2^31). Exactly equal rows have distance 0 in every precision.
@@ -141,12 +118,13 @@ __device__ void cand_distances(const float (&qv)[VEC], int D, const uint16_t* __
             hr[u] = raw_t{};
             lr[u] = raw_t{};
             if (cv[u] && dl) {
+                const uint32_t bo = base * 2u;  // byte offset, < 2^32
                 if constexpr (VEC == 4) {
-                    hr[u] = *reinterpret_cast<const uint2*>(hi + base);
-                    if (!HI_ONLY) lr[u] = *reinterpret_cast<const uint2*>(lo + base);
+                    hr[u] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(hi) + bo);
+                    if (!HI_ONLY) lr[u] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(lo) + bo);
                 } else {
-                    hr[u] = hi[base];
-                    if (!HI_ONLY) lr[u] = lo[base];
+                    hr[u] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(hi) + bo);
+                    if (!HI_ONLY) lr[u] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(lo) + bo);
                 }
             }
         }
@@ -332,71 +310,6 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
     }
 }
 
-// One halving step of a reduce-scatter over the wave: lanes whose bit O is
-// clear keep the first half of their N values, the others the second half,
-// each adding its partner's partial sums; (base, cnt) track the index range.
-template <typename T, int N, int O, int NMAX>
-__device__ __forceinline__ void rs_step(T (&v)[NMAX], int& base, int& cnt) {
-    constexpr int NK = (N + 1) / 2;
-    const bool hb = (threadIdx.x & O) != 0;
-#pragma unroll
-    for (int i = 0; i < NK; ++i) {
-        const T lo_v = v[i];
-        const T hi_v = (NK + i < N) ? v[NK + i] : (T)0;
-        const T send = hb ? lo_v : hi_v;
-        const T keep = hb ? hi_v : lo_v;
-        v[i] = keep + __shfl_xor(send, O);
-    }
-    if (hb) {
-        base += NK;
-        cnt -= NK;
-    } else {
-        cnt = cnt < NK ? cnt : NK;
-    }
-}
-
-// Packed Gram matrix (lower triangle, p = i(i+1)/2 + j) of the Kp <= 8 chosen
-// neighbours, Z_m = q - y_m, in T precision; lane r < Kp holds neighbour r's
-// ID. Lane t owns coordinates t and t + 64.
-template <typename T>
-__device__ void gram_store(const SearchArgs& a, int q, int Kp, uint32_t oid) {
-    constexpr int KM = 8, NP = KM * (KM + 1) / 2;
-    const int lane = threadIdx.x, D = a.D;
-    const float* qrow = a.qfeat + (int64_t)q * D;
-    const int t0 = lane, t1 = lane + 64;
-    const bool v0 = t0 < D, v1 = t1 < D;
-    const T q0 = v0 ? (T)qrow[t0] : (T)0, q1 = v1 ? (T)qrow[t1] : (T)0;
-    T z0[KM], z1[KM];
-#pragma unroll
-    for (int m = 0; m < KM; ++m) {
-        const uint32_t id = __shfl(oid, m);
-        z0[m] = (T)0;
-        z1[m] = (T)0;
-        if (m < Kp) {
-            const uint32_t b = id * (uint32_t)D;
-            if (v0) z0[m] = q0 - (T)join_planes(a.hi[b + t0], a.lo[b + t0]);
-            if (v1) z1[m] = q1 - (T)join_planes(a.hi[b + t1], a.lo[b + t1]);
-        }
-    }
-    T v[NP];
-    {
-        int p = 0;
-#pragma unroll
-        for (int i = 0; i < KM; ++i)
-#pragma unroll
-            for (int j = 0; j <= i; ++j) v[p++] = z0[i] * z0[j] + z1[i] * z1[j];
-    }
-    int base = 0, cnt = NP;
-    rs_step<T, 36, 32>(v, base, cnt);
-    rs_step<T, 18, 16>(v, base, cnt);
-    rs_step<T, 9, 8>(v, base, cnt);
-    rs_step<T, 5, 4>(v, base, cnt);
-    rs_step<T, 3, 2>(v, base, cnt);
-    rs_step<T, 2, 1>(v, base, cnt);
-    if (cnt >= 1) static_cast<T*>(a.gram)[(int64_t)q * NP + base] = v[0];
-}
-
-template <bool GFP64>
 __device__ __forceinline__ void write_result(const SearchArgs& a, int q, int Kp, uint32_t oid, float od) {
     const int lane = threadIdx.x;
     if (lane < a.K) {
@@ -404,7 +317,6 @@ __device__ __forceinline__ void write_result(const SearchArgs& a, int q, int Kp,
         a.out_d2[(int64_t)q * a.K + lane] = lane < Kp ? od : 0.0f;
     }
     if (lane == 0) a.out_m[q] = Kp;
-    if (a.gram && a.K <= 8 && Kp > 0) gram_store<typename std::conditional<GFP64, double, float>::type>(a, q, Kp, oid);
 }
 
 template <int VEC>
@@ -417,7 +329,7 @@ __device__ __forceinline__ void load_query(const SearchArgs& a, int q, float (&q
 
 // Early-stop search (cap <= 256): the concatenation of the L bins is read in
 // parallel 128 positions at a time; first occurrences are kept in order.
-template <int VEC, bool GFP64>
+template <int VEC, bool EXACT>
 __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
     __shared__ uint32_t cids[256];
     __shared__ uint32_t cdist[256];
@@ -429,7 +341,11 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
 
     for (int q = blockIdx.x; q < a.Q; q += gridDim.x) {
         uint32_t off = 0, cnt = 0;
-        if (lane < L) probe_bin(a.dir + (uint64_t)lane * a.dir_cap, a.dir_cap, a.qkeys[(int64_t)q * L + lane], off, cnt);
+        if (lane < L) {
+            const uint2 b = a.bins[(int64_t)q * L + lane];
+            off = b.x;
+            cnt = b.y;
+        }
         const int T = wave_sum_i32((int)cnt);
         const int incl = wave_incl_scan((int)cnt);
         if (lane < L) {
@@ -490,7 +406,7 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
         float qv[VEC];
         load_query<VEC>(a, q, qv);
         int Mr = M;
-        if (a.rerank > 0 && M > a.rerank) {
+        if (!EXACT && M > a.rerank) {
             cand_distances<VEC, true>(qv, a.D, a.hi, a.lo, cids, cdist, M);
             const uint64_t k2 = sort_select(cids, cdist, M);
             __syncthreads();
@@ -503,20 +419,20 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
         const uint64_t mykey = sort_select(cids, cdist, Mr);
         uint32_t oid = 0xFFFFFFFFu;
         float od = 0.0f;
-        if (a.exact && Kp > 0) {
+        if (EXACT && Kp > 0) {
             certify_or_fix(a, q, cids, cdist, Mr, Kp, mykey, oid, od);
         } else if (lane < Kp) {
             oid = key_id(mykey);
             od = key_dist(mykey);
         }
-        write_result<GFP64>(a, q, Kp, oid, od);
+        write_result(a, q, Kp, oid, od);
         __syncthreads();
     }
 }
 
 // Union search without early stop: all IDs of the L bins are gathered,
 // sorted and deduplicated in LDS (T <= CMAX), else the patch is deferred.
-template <int VEC, int CMAX, bool BIG, bool GFP64>
+template <int VEC, int CMAX, bool BIG>
 __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
     __shared__ uint32_t cids[CMAX];
     __shared__ uint32_t cdist[CMAX];
@@ -529,7 +445,11 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
     for (int t = blockIdx.x; t < nq; t += gridDim.x) {
         const int q = BIG ? a.overflow[t] : t;
         uint32_t off = 0, cnt = 0;
-        if (lane < L) probe_bin(a.dir + (uint64_t)lane * a.dir_cap, a.dir_cap, a.qkeys[(int64_t)q * L + lane], off, cnt);
+        if (lane < L) {
+            const uint2 b = a.bins[(int64_t)q * L + lane];
+            off = b.x;
+            cnt = b.y;
+        }
         const int T = wave_sum_i32((int)cnt);
         if (T > CMAX) {
             if (!BIG) {
@@ -603,7 +523,7 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
             oid = key_id(mykey);
             od = key_dist(mykey);
         }
-        write_result<GFP64>(a, q, Kp, oid, od);
+        write_result(a, q, Kp, oid, od);
         __syncthreads();
     }
 }
@@ -612,12 +532,14 @@ constexpr int kCapMax = 256;      // early-stop limit a wave can hold
 constexpr int kUnionMax = 2048;   // uncapped: IDs per wave before deferring
 constexpr int kUnionBig = 8192;   // uncapped, deferred patches
 
-template <int VEC, bool GFP64>
+template <int VEC>
 static void launch_search_t(const SearchArgs& a, int grid, hipStream_t st) {
-    if (a.cap > 0)
-        hipLaunchKernelGGL((k_search_cap<VEC, GFP64>), dim3(grid), dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_search_union<VEC, kUnionMax, false, GFP64>), dim3(grid), dim3(64), 0, st, a);
+    if (a.cap > 0) {
+        if (a.exact) hipLaunchKernelGGL((k_search_cap<VEC, true>), dim3(grid), dim3(64), 0, st, a);
+        else hipLaunchKernelGGL((k_search_cap<VEC, false>), dim3(grid), dim3(64), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_search_union<VEC, kUnionMax, false>), dim3(grid), dim3(64), 0, st, a);
+    }
 }
 
 hipError_t launch_search(const SearchArgs& a, hipStream_t st) {
@@ -626,25 +548,16 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t st) {
     const bool v4 = a.D % 4 == 0 && a.D <= 128;
     if (!v4 && a.D > 32) return hipErrorInvalidValue;
     if (a.cap > kCapMax) return hipErrorInvalidValue;
-    const bool g64 = a.gram && a.gram_fp64;
-    if (v4) {
-        if (g64) launch_search_t<4, true>(a, grid, st); else launch_search_t<4, false>(a, grid, st);
-    } else {
-        if (g64) launch_search_t<1, true>(a, grid, st); else launch_search_t<1, false>(a, grid, st);
-    }
+    if (!a.exact && (a.rerank < 1 || a.rerank > 64)) return hipErrorInvalidValue;
+    if (v4) launch_search_t<4>(a, grid, st);
+    else launch_search_t<1>(a, grid, st);
     return hipGetLastError();
 }
 
 hipError_t launch_search_overflow(const SearchArgs& a, int grid, hipStream_t st) {
     const bool v4 = a.D % 4 == 0 && a.D <= 128;
-    const bool g64 = a.gram && a.gram_fp64;
-    if (v4) {
-        if (g64) hipLaunchKernelGGL((k_search_union<4, kUnionBig, true, true>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_search_union<4, kUnionBig, true, false>), dim3(grid), dim3(64), 0, st, a);
-    } else {
-        if (g64) hipLaunchKernelGGL((k_search_union<1, kUnionBig, true, true>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_search_union<1, kUnionBig, true, false>), dim3(grid), dim3(64), 0, st, a);
-    }
+    if (v4) hipLaunchKernelGGL((k_search_union<4, kUnionBig, true>), dim3(grid), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_search_union<1, kUnionBig, true>), dim3(grid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

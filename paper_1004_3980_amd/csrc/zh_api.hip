@@ -57,9 +57,7 @@ struct zh_ctx {
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
     int64_t Q = 0;
-    Buf lr, maps, qfeat, qmu, qkeys, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram;
-    bool gram_valid = false;
-    int gram_fp64 = 0;
+    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask;
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -246,10 +244,8 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.cap = c->opts.cap;
     a.rerank = c->opts.rerank;
     a.exact = c->opts.rerank == 0 ? 1 : 0;
-    a.qkeys = P<uint64_t>(c->qkeys);
+    a.bins = P<uint2>(c->qbins);
     a.qfeat = P<float>(c->qfeat);
-    a.dir = P<Slot>(d.dir);
-    a.dir_cap = d.cap;
     a.tids = P<uint32_t>(d.tids);
     a.N = d.n;
     a.hi = P<uint16_t>(d.hi);
@@ -262,8 +258,6 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.dump_cap = dump_cap;
     a.overflow = P<int32_t>(c->over);
     a.counters = P<unsigned int>(c->counters);
-    a.gram = c->gram_valid ? c->gram.p : nullptr;
-    a.gram_fp64 = c->gram_fp64;
     HIPCHK(c, launch_search(a, c->stream));
     if (a.cap == 0) HIPCHK(c, launch_search_overflow(a, 1024, c->stream));
     return ZH_OK;
@@ -308,9 +302,9 @@ void zh_destroy(zh_ctx* c) {
         for (int i = 0; i < zh_ctx::kEv; ++i)
             for (int j = 0; j < 2; ++j)
                 if (c->ev[st][i][j]) (void)hipEventDestroy(c->ev[st][i][j]);
-    Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->ids, &c->d2, &c->m,
+    Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -453,6 +447,8 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     ha.keys = P<uint64_t>(c->keys_dict);
     ha.codes = nullptr;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
+    TRY(ensure(c, c->hmask, sizeof(uint64_t) * (size_t)(ha.n > 0 ? ha.n : 1)));
+    ha.dirty = P<uint64_t>(c->hmask);
     HIPCHK(c, launch_hash(ha, c->stream));
     // directory and bins, table by table
     TRY(ensure(c, d.dir, sizeof(Slot) * (size_t)L * cap));
@@ -522,6 +518,8 @@ zh_status zh_hash(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* c
     ha.keys = kp;
     ha.codes = codes;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
+    TRY(ensure(c, c->hmask, sizeof(uint64_t) * (size_t)(ha.n > 0 ? ha.n : 1)));
+    ha.dirty = P<uint64_t>(c->hmask);
     HIPCHK(c, launch_hash(ha, c->stream));
     return ZH_OK;
 }
@@ -554,6 +552,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     TRY(ensure(c, c->qfeat, sizeof(float) * (size_t)Q * d.D));
     TRY(ensure(c, c->qmu, sizeof(double) * (size_t)Q));
     TRY(ensure(c, c->qkeys, sizeof(uint64_t) * (size_t)Q * d.L));
+    TRY(ensure(c, c->qbins, sizeof(uint2) * (size_t)Q * d.L));
     TRY(ensure(c, c->ids, sizeof(int32_t) * (size_t)Q * K));
     TRY(ensure(c, c->d2, sizeof(float) * (size_t)Q * K));
     TRY(ensure(c, c->w, sizeof(float) * (size_t)Q * K));
@@ -561,10 +560,6 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->over, sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->xhat, sizeof(float) * (size_t)Q * ps2));
-    // Gram matrices of the neighbours are formed by the search when K <= 8
-    c->gram_valid = K <= 8;
-    c->gram_fp64 = c->opts.lle_fp64;
-    if (c->gram_valid) TRY(ensure(c, c->gram, (c->gram_fp64 ? 8 : 4) * (size_t)Q * 36));
     HIPCHK(c, hipMemcpyAsync(c->lr.p, lr, sizeof(float) * (size_t)h * w, hipMemcpyDeviceToDevice, c->stream));
     c->qh = h;
     c->qw = w;
@@ -594,6 +589,11 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     ha.keys = P<uint64_t>(c->qkeys);
     ha.codes = nullptr;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
+    TRY(ensure(c, c->hmask, sizeof(uint64_t) * (size_t)(ha.n > 0 ? ha.n : 1)));
+    ha.dirty = P<uint64_t>(c->hmask);
+    ha.dir = P<Slot>(d.dir);
+    ha.dir_cap = d.cap;
+    ha.bins = P<uint2>(c->qbins);
     {
         StageTimer t(c, ZH_T_HASH);
         HIPCHK(c, launch_hash(ha, c->stream));
@@ -625,11 +625,17 @@ zh_status zh_lle_weights(zh_ctx* c, double lambda) {
     a.fp64 = c->opts.lle_fp64;
     a.w = P<float>(c->w);
     a.n_fp64 = P<unsigned int>(c->counters) + C_LLE64;
-    StageTimer t(c, ZH_T_LLE);
-    if (c->gram_valid && c->gram_fp64 == c->opts.lle_fp64)
-        HIPCHK(c, launch_lle_solve(a, c->gram.p, c->gram_fp64, c->stream));
-    else
+    if (c->qK <= 8) {
+        // packed Gram matrices, then one thread per patch solves its system
+        const int f64 = c->opts.lle_fp64;
+        TRY(ensure(c, c->gram, (f64 ? 8 : 4) * (size_t)c->Q * 36));
+        StageTimer t(c, ZH_T_LLE);
+        HIPCHK(c, launch_gram(a, c->gram.p, f64, c->stream));
+        HIPCHK(c, launch_lle_solve(a, c->gram.p, f64, c->stream));
+    } else {
+        StageTimer t(c, ZH_T_LLE);
         HIPCHK(c, launch_lle(a, c->stream));
+    }
     c->stage = 2;
     return ZH_OK;
 }

@@ -56,9 +56,12 @@ struct HashArgs {
     uint64_t* keys;          // [n, L]
     int32_t* codes;          // [n, L*k] or null
     unsigned int* n_fixed;   // count of codes recomputed in FP64 (nullable)
+    uint64_t* dirty;         // [n] scratch: per row, bit l set when table l holds a code decided in FP64
+    const Slot* dir;         // bin directories [L, dir_cap], or null: no lookup
+    uint64_t dir_cap;
+    uint2* bins;             // [n, L] (offset, count) of each key's bin, when dir is set
 };
 hipError_t launch_hash(const HashArgs& a, hipStream_t st);
-size_t hash_lds_bytes(int prec, int D, int k);
 // bound coefficients for the MFMA projection of precision `prec` (host)
 void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, float* c0, float* c1,
                        float* c2);
@@ -77,10 +80,8 @@ int64_t radix_hist_size(int64_t n);
 // ---- search (k_search.hip) ---------------------------------------------------
 struct SearchArgs {
     int Q, D, L, K, cap, rerank, exact;
-    const uint64_t* qkeys;   // [Q, L]
+    const uint2* bins;       // [Q, L] (offset, count) of the query's bin in each table
     const float* qfeat;      // [Q, D]
-    const Slot* dir;
-    uint64_t dir_cap;
     const uint32_t* tids;    // [L, N]
     int64_t N;
     const uint16_t* hi;
@@ -93,8 +94,6 @@ struct SearchArgs {
     int dump_cap;
     int32_t* overflow;       // [Q] deferred queries (uncapped, too many IDs for a wave)
     unsigned int* counters;  // [0] overflow count, [1] FP64 rank fallbacks
-    void* gram;              // [Q, 36] packed Gram of the <= 8 neighbours, or null
-    int gram_fp64;           // gram holds double (1) or float (0)
 };
 hipError_t launch_search(const SearchArgs& a, hipStream_t st);
 hipError_t launch_search_overflow(const SearchArgs& a, int n_over, hipStream_t st);
@@ -113,7 +112,9 @@ struct LleArgs {
     unsigned int* n_fp64;    // FP64 redo count (nullable)
 };
 hipError_t lle_init();  // once per device, before any launch_lle
-// weights from packed Gram matrices [Q, 36] (K <= 8), thread per patch
+// packed Gram matrices [Q, 36] of the <= 8 neighbours (Z = query - rows),
+// two patches per wave; then the weights from them, one thread per patch
+hipError_t launch_gram(const LleArgs& a, void* gram, int gram_fp64, hipStream_t st);
 hipError_t launch_lle_solve(const LleArgs& a, const void* gram, int gram_fp64, hipStream_t st);
 hipError_t launch_lle(const LleArgs& a, hipStream_t st);
 hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m,
