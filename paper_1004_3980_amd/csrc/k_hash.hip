@@ -31,12 +31,6 @@ typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kRowsPerWave = 16;
 
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ int32_t floor_sat(double t) {
     const double f = floor(t);

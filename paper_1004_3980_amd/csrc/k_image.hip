@@ -148,13 +148,42 @@ __global__ void k_dict_cut(const float* __restrict__ hr, const float* __restrict
     }
 }
 
-__global__ void k_split_planes(const float* __restrict__ x, int64_t count, uint16_t* __restrict__ hi,
+// Split storage of the dictionary features: the high plane holds the upper
+// 16 bits of each fp32 value (a bf16 truncation) in rows of hi_stride(D)
+// halfwords, the low plane the lower 16 bits in rows of D.
+__global__ void k_split_planes(const float* __restrict__ x, int64_t n, int D, uint16_t* __restrict__ hi,
                                uint16_t* __restrict__ lo) {
+    const int hs = hi_stride(D);
+    const int64_t count = n * D;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < count;
          idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx / D;
+        const int c = (int)(idx - r * D);
         const uint32_t b = __float_as_uint(x[idx]);
-        hi[idx] = (uint16_t)(b >> 16);
+        hi[r * hs + c] = (uint16_t)(b >> 16);
         lo[idx] = (uint16_t)(b & 0xFFFFu);
+    }
+}
+
+// Row tail of the high plane: |x_hi|^2 summed in fp32 in index order, and
+// |x - x_hi| from an FP64 sum, rounded up to fp32 (with a relative margin
+// for the FP64 rounding).
+__global__ void k_hi_tails(const float* __restrict__ x, int64_t n, int D, uint16_t* __restrict__ hi) {
+    const int hs = hi_stride(D);
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        double e = 0.0;
+        for (int i = 0; i < D; ++i) {
+            const float v = x[r * D + i];
+            const float h = __uint_as_float(__float_as_uint(v) & 0xFFFF0000u);
+            s = fmaf(h, h, s);
+            const double d = (double)v - (double)h;
+            e += d * d;
+        }
+        const float rho = __double2float_ru(sqrt(e) * (1.0 + 1e-12));
+        float* tail = reinterpret_cast<float*>(hi + r * hs + hi_tail(D));
+        tail[0] = s;
+        tail[1] = rho;
     }
 }
 
@@ -212,10 +241,16 @@ hipError_t launch_dict_cut(const float* hr, const float* lr, const float* maps, 
     return hipGetLastError();
 }
 
-hipError_t launch_split_planes(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
+hipError_t launch_split_planes(const float* x, int64_t n, int D, uint16_t* hi, uint16_t* lo,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_split_planes, dim3(grid_for(count, 256)), dim3(256), 0, st, x, count, hi,
-                       lo);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_planes, dim3(grid_for(n * D, 256)), dim3(256), 0, st, x, n, D, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_hi_tails(const float* x, int64_t n, int D, uint16_t* hi, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hi_tails, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, D, hi);
     return hipGetLastError();
 }
 

@@ -35,9 +35,10 @@ __global__ __launch_bounds__(64) void k_lle(LleArgs a) {
         if (m <= 0) continue;
         const float* qrow = a.qfeat + (int64_t)q * D;
         for (int r = 0; r < m; ++r) {
-            const int64_t b = (int64_t)a.ids[(int64_t)q * K + r] * D;
+            const int64_t id = a.ids[(int64_t)q * K + r];
+            const int64_t b = id * D, bh = id * a.hs;
             for (int t = lane; t < D; t += 64)
-                sZ[t * KMAX + r] = (T)qrow[t] - (T)join_planes(a.hi[b + t], a.lo[b + t]);
+                sZ[t * KMAX + r] = (T)qrow[t] - (T)join_planes(a.hi[bh + t], a.lo[b + t]);
         }
         __syncthreads();
         const int np = m * (m + 1) / 2;
@@ -108,12 +109,12 @@ __global__ __launch_bounds__(64) void k_lle(LleArgs a) {
             const float* qrow = a.qfeat + (int64_t)q * D;
             for (int i = 0; i < m; ++i)
                 for (int j = 0; j <= i; ++j) {
-                    const int64_t bi = (int64_t)a.ids[(int64_t)q * K + i] * D;
-                    const int64_t bj = (int64_t)a.ids[(int64_t)q * K + j] * D;
+                    const int64_t ii = a.ids[(int64_t)q * K + i], ij = a.ids[(int64_t)q * K + j];
+                    const int64_t bi = ii * D, bj = ij * D, hi_i = ii * a.hs, hi_j = ij * a.hs;
                     double g = 0.0;
                     for (int t = 0; t < D; ++t) {
-                        const double zi = (double)qrow[t] - (double)join_planes(a.hi[bi + t], a.lo[bi + t]);
-                        const double zj = (double)qrow[t] - (double)join_planes(a.hi[bj + t], a.lo[bj + t]);
+                        const double zi = (double)qrow[t] - (double)join_planes(a.hi[hi_i + t], a.lo[bi + t]);
+                        const double zj = (double)qrow[t] - (double)join_planes(a.hi[hi_j + t], a.lo[bj + t]);
                         g += zi * zj;
                     }
                     Gd[i * (i + 1) / 2 + j] = g;
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(256) void k_gram(LleArgs a, T* __restrict__ gram) {
     const int wpb = blockDim.x >> 6;
     const int D = a.D;
     const bool dl = hl * VEC < D;
-    for (int pr = blockIdx.x * wpb + (threadIdx.x >> 6); 2 * pr < a.Q; pr += gridDim.x * wpb) {
+    for (int pr = xcd_block() * wpb + (threadIdx.x >> 6); 2 * pr < a.Q; pr += gridDim.x * wpb) {
         const int q = 2 * pr + half;
         const bool qv = q < a.Q;
         const int m = qv ? a.m[q] : 0;
@@ -206,11 +207,12 @@ __global__ __launch_bounds__(256) void k_gram(LleArgs a, T* __restrict__ gram) {
             if (r < m && dl) {
                 const uint32_t id = (uint32_t)a.ids[(int64_t)q * a.K + r];
                 const uint32_t bo = (id * (uint32_t)D + (uint32_t)(hl * VEC)) * 2u;
+                const uint32_t bh = (id * (uint32_t)a.hs + (uint32_t)(hl * VEC)) * 2u;
                 if constexpr (VEC == 4) {
-                    hr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.hi) + bo);
+                    hr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.hi) + bh);
                     lr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.lo) + bo);
                 } else {
-                    hr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.hi) + bo);
+                    hr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.hi) + bh);
                     lr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.lo) + bo);
                 }
             }
@@ -258,6 +260,7 @@ hipError_t launch_gram(const LleArgs& a, void* gram, int gram_fp64, hipStream_t 
     if (!v4 && a.D > 32) return hipErrorInvalidValue;
     int grid = (a.Q + 7) / 8;
     if (grid > 65536) grid = 65536;
+    grid = round_grid8(grid);
     if (gram_fp64) {
         if (v4) hipLaunchKernelGGL((k_gram<double, 4>), dim3(grid), dim3(256), 0, st, a, static_cast<double*>(gram));
         else hipLaunchKernelGGL((k_gram<double, 1>), dim3(grid), dim3(256), 0, st, a, static_cast<double*>(gram));
@@ -275,12 +278,12 @@ __device__ void gram_fp64_rows(const LleArgs& a, int q, int m, double* Gd) {
     const float* qrow = a.qfeat + (int64_t)q * D;
     for (int i = 0; i < m; ++i)
         for (int j = 0; j <= i; ++j) {
-            const int64_t bi = (int64_t)a.ids[(int64_t)q * a.K + i] * D;
-            const int64_t bj = (int64_t)a.ids[(int64_t)q * a.K + j] * D;
+            const int64_t ii = a.ids[(int64_t)q * a.K + i], ij = a.ids[(int64_t)q * a.K + j];
+            const int64_t bi = ii * D, bj = ij * D, hi_i = ii * a.hs, hi_j = ij * a.hs;
             double g = 0.0;
             for (int t = 0; t < D; ++t) {
-                const double zi = (double)qrow[t] - (double)join_planes(a.hi[bi + t], a.lo[bi + t]);
-                const double zj = (double)qrow[t] - (double)join_planes(a.hi[bj + t], a.lo[bj + t]);
+                const double zi = (double)qrow[t] - (double)join_planes(a.hi[hi_i + t], a.lo[bi + t]);
+                const double zj = (double)qrow[t] - (double)join_planes(a.hi[hi_j + t], a.lo[bj + t]);
                 g += zi * zj;
             }
             Gd[i * (i + 1) / 2 + j] = g;
@@ -402,7 +405,7 @@ __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int3
                                                float* __restrict__ xhat) {
     const int lane = threadIdx.x & 63;
     const int nw = gridDim.x * (blockDim.x >> 6);
-    for (int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < Q; q += nw) {
+    for (int q = xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6); q < Q; q += nw) {
         const int mq = m[q];
         if (mq <= 0) continue;
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -502,6 +505,7 @@ hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t
     if (ps2 > 256) return hipErrorInvalidValue;
     int grid = (Q + 3) / 4;
     if (grid > 65536) grid = 65536;
+    grid = round_grid8(grid);
     hipLaunchKernelGGL(k_synth, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
     return hipGetLastError();
 }

@@ -54,11 +54,11 @@ __device__ void wave_sort_u32(uint32_t* s, int n) {
 }
 
 // Bitonic sort of NS*64 keys held NS per lane (element s*64 + lane) in
-// registers, ascending.
-template <int NS>
+// registers, ascending. With NS == 1 and N < 64, each aligned group of N lanes
+// is sorted on its own.
+template <int NS, int N = NS * 64>
 __device__ __forceinline__ void wave_sort_keys(uint64_t (&key)[NS]) {
     const int lane = threadIdx.x & 63;
-    constexpr int N = NS * 64;
 #pragma unroll
     for (int k = 2; k <= N; k <<= 1) {
 #pragma unroll
@@ -97,7 +97,7 @@ __device__ __forceinline__ void wave_sort_keys(uint64_t (&key)[NS]) {
 // per row: lane l of a half holds coordinates [VEC l, VEC l + VEC); U row
 // pairs are loaded before any is used.
 template <int VEC, bool HI_ONLY>
-__device__ void cand_distances(const float (&qv)[VEC], int D, const uint16_t* __restrict__ hi,
+__device__ void cand_distances(const float (&qv)[VEC], int D, int HS, const uint16_t* __restrict__ hi,
                                const uint16_t* __restrict__ lo, const uint32_t* cids, uint32_t* cdist,
                                int c1) {
     // VEC == 4: 8 bytes of each plane per lane; VEC == 1: 2 bytes
@@ -115,15 +115,16 @@ __device__ void cand_distances(const float (&qv)[VEC], int D, const uint16_t* __
             const uint32_t id = cv[u] ? cids[c] : 0u;
             // N * D < 2^31 elements: 32-bit offsets from the plane bases
             const uint32_t base = id * (uint32_t)D + (uint32_t)(hl * VEC);
+            const uint32_t hbase = id * (uint32_t)HS + (uint32_t)(hl * VEC);
             hr[u] = raw_t{};
             lr[u] = raw_t{};
             if (cv[u] && dl) {
-                const uint32_t bo = base * 2u;  // byte offset, < 2^32
+                const uint32_t bo = base * 2u, bh = hbase * 2u;  // byte offsets, < 2^32
                 if constexpr (VEC == 4) {
-                    hr[u] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(hi) + bo);
+                    hr[u] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(hi) + bh);
                     if (!HI_ONLY) lr[u] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(lo) + bo);
                 } else {
-                    hr[u] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(hi) + bo);
+                    hr[u] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(hi) + bh);
                     if (!HI_ONLY) lr[u] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(lo) + bo);
                 }
             }
@@ -176,16 +177,22 @@ __device__ uint64_t select_topk(const uint32_t* cids, const uint32_t* cdist, int
     return mine;
 }
 
-// Sorted selection for M <= 256 candidates: lane r < min(M, 64) receives the
-// r-th smallest key.
+// Sorted selection for M <= 64 NSL candidates: lane r < min(M, 64) receives
+// the r-th smallest key.
+template <int NSL = 4>
 __device__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int M) {
     const int lane = threadIdx.x;
     if (M <= 64) {
         uint64_t k[1] = {lane < M ? cand_key(cdist[lane], cids[lane]) : ~0ull};
-        wave_sort_keys<1>(k);
+        if (M <= 16)
+            wave_sort_keys<1, 16>(k);
+        else if (M <= 32)
+            wave_sort_keys<1, 32>(k);
+        else
+            wave_sort_keys<1>(k);
         return k[0];
     }
-    if (M <= 128) {
+    if (NSL <= 2 || M <= 128) {
         uint64_t k[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -206,12 +213,12 @@ __device__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int
 }
 
 // FP64 sequential squared distance: the definition.
-__device__ double exact_dist64(const float* __restrict__ qrow, int D, const uint16_t* __restrict__ hi,
+__device__ double exact_dist64(const float* __restrict__ qrow, int D, int HS, const uint16_t* __restrict__ hi,
                                const uint16_t* __restrict__ lo, uint32_t id) {
-    const int64_t b = (int64_t)id * D;
+    const int64_t b = (int64_t)id * D, bh = (int64_t)id * HS;
     double s = 0.0;
     for (int i = 0; i < D; ++i) {
-        const double d = (double)qrow[i] - (double)join_planes(hi[b + i], lo[b + i]);
+        const double d = (double)qrow[i] - (double)join_planes(hi[bh + i], lo[b + i]);
         s = s + d * d;
     }
     return s;
@@ -286,7 +293,7 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
                 if (l2 > thi) continue;
             }
             const uint32_t id = cids[c];
-            const double d = cex ? 0.0 : exact_dist64(qrow, a.D, a.hi, a.lo, id);
+            const double d = cex ? 0.0 : exact_dist64(qrow, a.D, a.hs, a.hi, a.lo, id);
             const bool after = r == 0 || d > lastd || (d == lastd && id > lastid);
             if (after && (d < bestd || (d == bestd && id < bestid))) {
                 bestd = d;
@@ -327,19 +334,101 @@ __device__ __forceinline__ void load_query(const SearchArgs& a, int q, float (&q
         qv[e] = (hl * VEC + e < a.D) ? a.qfeat[(int64_t)q * a.D + hl * VEC + e] : 0.0f;
 }
 
-// Early-stop search (cap <= 256): the concatenation of the L bins is read in
-// parallel 128 positions at a time; first occurrences are kept in order.
-template <int VEC, bool EXACT>
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// order-preserving map of a finite float to uint32
+__device__ __forceinline__ uint32_t ord_u32(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+// 16 bytes from an 8-byte aligned address
+__device__ __forceinline__ uint4 ld16(const char* p) {
+    const uint2 x = *reinterpret_cast<const uint2*>(p);
+    const uint2 y = *reinterpret_cast<const uint2*>(p + 8);
+    return make_uint4(x.x, x.y, y.x, y.y);
+}
+// keep the first nv (0..8) bf16 elements of a 16-byte group
+__device__ __forceinline__ uint32_t keep_mask(int nv, int w) {
+    return (nv > 2 * w ? 0x0000FFFFu : 0u) | (nv > 2 * w + 1 ? 0xFFFF0000u : 0u);
+}
+
+// R-th smallest (R >= 1) of the M keys held NSL per lane (element s*64 + lane):
+// a 32-step radix search with wave ballots.
+template <int NSL>
+__device__ uint32_t radix_kth(const uint32_t (&kv)[NSL], int M, int R) {
+    const int lane = threadIdx.x & 63;
+    const int nsl = (M + 63) >> 6;
+    uint32_t tau = 0;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t trial = tau + (1u << b);
+        int n = 0;
+#pragma unroll
+        for (int s = 0; s < NSL; ++s)
+            if (s < nsl) n += __popcll(__ballot(s * 64 + lane < M && kv[s] < trial));
+        if (n < R) tau = trial;
+    }
+    return tau;
+}
+
+// Relative error coefficient c of the screen value |q|^2 + |x_hi|^2 - 2 q.x_hi
+// against |q - x_hi|^2: the error is at most c (|q|^2 + |x_hi|^2). Terms: the
+// fp32 sums of squares (gamma_D each), the bf16 split of q (the low part
+// leaves at most 2^-16 |q_i|), the fp32 accumulation of the MFMA dot product
+// (at most 33 roundings per 32 coordinates, and the sum of the two columns),
+// with |q.x_hi| <= (|q|^2 + |x_hi|^2) / 2, and the fp32 evaluation of the
+// screen value (8 u). The total is doubled.
+float screen_coeff(int D) {
+    const double u = 1.0 / 16777216.0;
+    const int ns = (D + 31) / 32;
+    const double c = 2.0 * gamma_n(D, u) + 1.0 / 65536.0 + 1.01 * gamma_n(33 * ns + 1, u) + 8.0 * u;
+    return (float)(2.0 * c);
+}
+
+// Early-stop search (cap <= 256), one wave per patch.
+//  1. Candidates: the concatenation of the L bins is read 64 positions at a
+//     time; an LDS hash set of the IDs seen so far (open addressing, atomic
+//     compare-and-swap inserts, an atomic minimum keeping the earliest lane
+//     of a chunk) keeps first occurrences in order, up to `cap`.
+//  2. Pre-filter, when more than K candidates: |q - x_hi|^2 is evaluated as
+//     |q|^2 + |x_hi|^2 - 2 q.x_hi with MFMA dot products (candidate rows of
+//     the bf16 high plane as A, the query split into bf16 high and low parts
+//     as two columns of B) and the |x_hi|^2 stored at the end of the row.
+//     With the stored bound rho >= |x - x_hi| and the screen's error bound
+//     this gives an interval [L, U] that holds the candidate's distance; a
+//     candidate whose L exceeds the K-th smallest U (32-step ballot radix
+//     select) is farther than K others and is dropped. The screened form
+//     keeps at most R survivors (smallest L).
+//  3. Exact fp32 distances of the survivors from both planes, eight lanes
+//     per row (16 coordinates each); a row whose fp32 distance is 0 is checked
+//     for exact equality with the query.
+//  4. Sorted selection of the K best, certification (exact form), output.
+template <int NS, bool EXACT, int NSL>
 __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
-    __shared__ uint32_t cids[256];
-    __shared__ uint32_t cdist[256];
-    __shared__ uint32_t chunk[64];
+    // dynamic LDS: hash set [hsz] of (id << 32 | first lane), empty = ~0, then
+    // the candidate IDs and values [cp] each, cp = max(64, next_pow2(cap))
+    extern __shared__ uint64_t hset[];
+    uint32_t* cids = reinterpret_cast<uint32_t*>(hset + a.hsz);
+    uint32_t* cdist = cids + a.cp;
+    __shared__ __align__(16) float sq[128];
+    __shared__ __align__(16) uint16_t sqs[2][128];   // bf16 high and low parts of the query
     __shared__ uint32_t sstart[kMaxL + 1];
     __shared__ uint32_t soff[kMaxL];
     const int lane = threadIdx.x;
-    const int L = a.L;
+    const int L = a.L, D = a.D;
+    const int HS = a.hs, TO = hi_tail(D);
+    const int hsz = a.hsz;
+    const uint32_t hmask = (uint32_t)hsz - 1u;
+    const int hshift = 32 - __builtin_ctz((unsigned)hsz);
+    const int ri = lane & 15, kb = lane >> 4;   // MFMA layout
+    const int rg = lane >> 3, g = lane & 7;     // eight lanes per row
+    // coordinates of this lane's last MFMA step, and of its two 16-byte groups
+    const int nvt = D - (32 * (NS - 1) + 8 * kb);
+    const int nvg = D - 16 * g;
 
-    for (int q = blockIdx.x; q < a.Q; q += gridDim.x) {
+    {
+        const int q = xcd_block();
+        if (q >= a.Q) return;
         uint32_t off = 0, cnt = 0;
         if (lane < L) {
             const uint2 b = a.bins[(int64_t)q * L + lane];
@@ -353,70 +442,290 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
             soff[lane] = off;
         }
         if (lane == 0) sstart[L] = (uint32_t)T;
-        __syncthreads();
-        int M = 0;
-        for (int base = 0; base < T && M < a.cap; base += 128) {
-            uint32_t idv[2];
-            int tabv[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int i = base + 64 * u + lane;
-                idv[u] = 0xFFFFFFFFu;
-                tabv[u] = -1;
-                if (i < T) {
-                    int lo = 0, hi = L;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (sstart[mid] <= (uint32_t)i) lo = mid; else hi = mid;
-                    }
-                    tabv[u] = lo;
-                    idv[u] = a.tids[(int64_t)lo * a.N + soff[lo] + (i - sstart[lo])];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int cb = base + 64 * u;
-                if (cb >= T || M >= a.cap) break;
-                const bool valid = cb + lane < T;
-                const uint32_t id = idv[u];
-                bool dup = false;
-                for (int i = 0; i < M; ++i) dup |= cids[i] == id;
-                // IDs inside one bin are distinct: only a chunk that spans
-                // several tables can repeat an ID within itself
-                const int tfirst = __shfl(tabv[u], 0);
-                const int tlast = __shfl(tabv[u], min(63, T - 1 - cb));
-                if (tfirst != tlast) {
-                    chunk[lane] = id;
-                    __syncthreads();
-                    for (int j = 0; j < 64; ++j) dup |= (j < lane) && chunk[j] == id;
-                }
-                const bool nw = valid && !dup;
-                const uint64_t bal = __ballot(nw);
-                const int rank = __popcll(bal & lanemask_lt());
-                if (nw && M + rank < a.cap) cids[M + rank] = id;
-                M = min(a.cap, M + (int)__popcll(bal));
-                __syncthreads();
-            }
+        for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
+        double qd = 0.0;
+        for (int i = lane; i < 128; i += 64) {
+            const float x = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
+            sq[i] = x;
+            const uint16_t h = bf16_rne(x);
+            sqs[0][i] = h;
+            sqs[1][i] = bf16_rne(x - bf16_to_f(h));
+            qd += (double)x * (double)x;
         }
+        const float qn2 = (float)wave_sum_f64(qd);
+        __syncthreads();
+
+        // ---- 1. candidates, first occurrences in order, up to cap
+        int M = 0;
+        for (int base = 0; base < T && M < a.cap; base += 64) {
+            const int i = base + lane;
+            const bool valid = i < T;
+            uint32_t id = 0xFFFFFFFFu;
+            if (valid) {
+                int lo = 0, hi = L;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sstart[mid] <= (uint32_t)i) lo = mid; else hi = mid;
+                }
+                id = a.tids[(int64_t)lo * a.N + soff[lo] + (i - sstart[lo])];
+            }
+            uint32_t slot = (id * 0x9E3779B1u) >> hshift;
+            bool found = false;
+            if (valid) {
+                for (;;) {
+                    const uint64_t v = hset[slot];
+                    if ((uint32_t)(v >> 32) == id) {
+                        found = true;
+                        break;
+                    }
+                    if (v == ~0ull) break;
+                    slot = (slot + 1u) & hmask;
+                }
+            }
+            const bool ins = valid && !found;
+            const uint64_t mine = ((uint64_t)id << 32) | (uint32_t)lane;
+            if (ins) {
+                for (;;) {
+                    const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&hset[slot]), ~0ull, mine);
+                    if (old == ~0ull) break;
+                    if ((uint32_t)(old >> 32) == id) {
+                        atomicMin(reinterpret_cast<unsigned long long*>(&hset[slot]), mine);
+                        break;
+                    }
+                    slot = (slot + 1u) & hmask;
+                }
+            }
+            __syncthreads();
+            const bool nw = ins && hset[slot] == mine;
+            const uint64_t bal = __ballot(nw);
+            const int rank = __popcll(bal & lanemask_lt());
+            if (nw && M + rank < a.cap) cids[M + rank] = id;
+            M = min(a.cap, M + (int)__popcll(bal));
+        }
+        __syncthreads();
         if (a.dump) {
             wave_sort_u32(cids, M);
             for (int i = lane; i < M && i < a.dump_cap; i += 64) a.dump[(int64_t)q * a.dump_cap + i] = (int32_t)cids[i];
         }
         if (lane == 0) a.out_ncand[q] = M;
-        float qv[VEC];
-        load_query<VEC>(a, q, qv);
+
+        // ---- 2. bf16 pre-filter: an interval [L, U] around each candidate's
+        // distance; candidates with L above the K-th smallest U cannot be
+        // among the K nearest
         int Mr = M;
-        if (!EXACT && M > a.rerank) {
-            cand_distances<VEC, true>(qv, a.D, a.hi, a.lo, cids, cdist, M);
-            const uint64_t k2 = sort_select(cids, cdist, M);
+        if (M > a.K) {
+            uint4 qb[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const uint4 t4 = *reinterpret_cast<const uint4*>(&sqs[ri & 1][32 * s + 8 * kb]);
+                qb[s] = ri < 2 ? t4 : make_uint4(0u, 0u, 0u, 0u);
+            }
+            for (int t = 0; t < M; t += 16) {
+                const int c = t + ri;
+                const bool cv = c < M;
+                const uint32_t id = cv ? cids[c] : 0u;
+                const char* rowp = reinterpret_cast<const char*>(a.hi) + id * (uint32_t)(2 * HS);
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int d = 32 * s + 8 * kb;
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (cv && d < D) {
+                        v = *reinterpret_cast<const uint4*>(rowp + 2 * d);
+                        if (s == NS - 1 && nvt < 8) {
+                            v.x &= keep_mask(nvt, 0);
+                            v.y &= keep_mask(nvt, 1);
+                            v.z &= keep_mask(nvt, 2);
+                            v.w &= keep_mask(nvt, 3);
+                        }
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v),
+                                                                 __builtin_bit_cast(bf16x8, qb[s]), acc, 0, 0, 0);
+                }
+                // lane (kb, 0) holds q_hi.x_hi and lane (kb, 1) q_lo.x_hi of candidates t + 4 kb + r
+                float lo4[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) lo4[r] = __shfl_down(acc[r], 1);
+                if (ri == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int cc = t + 4 * kb + r;
+                        if (cc < M) cdist[cc] = __float_as_uint(acc[r] + lo4[r]);
+                    }
+                }
+            }
             __syncthreads();
-            if (lane < a.rerank) cids[lane] = key_id(k2);
+            // |q - x|^2 in [(a_lo - rho)^2, (a_hi + rho)^2], a = |q - x_hi|, rho >= |x - x_hi|;
+            // every fp32 step moves its result outward by a relative margin far
+            // above its rounding error
+            uint32_t lv[NSL], uv[NSL], iv[NSL];
+#pragma unroll
+            for (int s = 0; s < NSL; ++s) {
+                const int c = s * 64 + lane;
+                lv[s] = uv[s] = iv[s] = 0xFFFFFFFFu;
+                if (c < M) {
+                    const uint32_t id = cids[c];
+                    const float2 tl = *reinterpret_cast<const float2*>(a.hi + (size_t)id * HS + TO);
+                    const float dot = __uint_as_float(cdist[c]);
+                    const float nn = qn2 + tl.x;
+                    const float a2 = nn - 2.0f * dot;
+                    const float E = fmaf(a.ce, nn, 1e-30f);
+                    const float alo = sqrtf(fmaxf((a2 - E) * (1.0f - 1e-6f), 0.0f)) * (1.0f - 1e-6f);
+                    const float ahi = sqrtf((a2 + E) * (1.0f + 1e-6f)) * (1.0f + 1e-6f);
+                    const float l = fmaxf(alo * (1.0f - 1e-6f) - tl.y * (1.0f + 1e-6f), 0.0f);
+                    const float u = ahi * (1.0f + 1e-6f) + tl.y * (1.0f + 1e-6f);
+                    lv[s] = __float_as_uint(l * l * (1.0f - 1e-5f));
+                    uv[s] = __float_as_uint(u * u * (1.0f + 1e-5f));
+                    iv[s] = id;
+                }
+            }
+            // an upper bound of the K-th smallest U: radix search on the top 16 bits
+            uint32_t hk = 0;
+            {
+                const int nsl = (M + 63) >> 6;
+                for (int b = 15; b >= 0; --b) {
+                    const uint32_t trial = hk + (1u << b);
+                    int n = 0;
+#pragma unroll
+                    for (int s = 0; s < NSL; ++s)
+                        if (s < nsl) n += __popcll(__ballot(s * 64 + lane < M && (uv[s] >> 16) < trial));
+                    if (n < a.K) hk = trial;
+                }
+            }
+            const uint32_t uk = (hk << 16) | 0xFFFFu;
+            bool sel[NSL];
+            int S = 0;
+#pragma unroll
+            for (int s = 0; s < NSL; ++s) {
+                sel[s] = s * 64 + lane < M && lv[s] <= uk;
+                S += __popcll(__ballot(sel[s]));
+            }
+            if (!EXACT && S > a.rerank) {
+                // screened form: at most R survivors, by lower bound, equal bounds by lower ID
+                const int R = a.rerank;
+                uint32_t kv[NSL];
+#pragma unroll
+                for (int s = 0; s < NSL; ++s) kv[s] = sel[s] ? lv[s] : 0xFFFFFFFFu;
+                const uint32_t tau = radix_kth(kv, M, R);
+                int nlt = 0, neq = 0;
+#pragma unroll
+                for (int s = 0; s < NSL; ++s) {
+                    nlt += __popcll(__ballot(sel[s] && kv[s] < tau));
+                    neq += __popcll(__ballot(sel[s] && kv[s] == tau));
+                }
+                bool keep[NSL];
+#pragma unroll
+                for (int s = 0; s < NSL; ++s) keep[s] = sel[s] && kv[s] < tau;
+                const int need = R - nlt;
+                if (neq == need) {
+#pragma unroll
+                    for (int s = 0; s < NSL; ++s) keep[s] = keep[s] || (sel[s] && kv[s] == tau);
+                } else {
+                    uint32_t last = 0;
+                    for (int r = 0; r < need; ++r) {
+                        uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+                        for (int s = 0; s < NSL; ++s)
+                            if (sel[s] && kv[s] == tau && (r == 0 || iv[s] > last) && iv[s] < best) best = iv[s];
+                        best = wave_min_u32(best);
+#pragma unroll
+                        for (int s = 0; s < NSL; ++s)
+                            if (sel[s] && kv[s] == tau && iv[s] == best) keep[s] = true;
+                        last = best;
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < NSL; ++s) sel[s] = keep[s];
+                S = R;
+            }
             __syncthreads();
-            Mr = a.rerank;
+            int pos = 0;
+#pragma unroll
+            for (int s = 0; s < NSL; ++s) {
+                const uint64_t bal = __ballot(sel[s]);
+                if (sel[s]) cids[pos + __popcll(bal & lanemask_lt())] = iv[s];
+                pos += __popcll(bal);
+            }
+            __syncthreads();
+            Mr = S;
         }
-        cand_distances<VEC, false>(qv, a.D, a.hi, a.lo, cids, cdist, Mr);
+
+        // ---- 3. exact fp32 distances, eight lanes per row
+        for (int cb = 0; cb < Mr; cb += 8) {
+            const int c = cb + rg;
+            const bool cv = c < Mr;
+            const uint32_t id = cv ? cids[c] : 0u;
+            const uint32_t bo = (id * (uint32_t)D + 16u * g) * 2u;
+            const uint32_t bh = (id * (uint32_t)HS + 16u * g) * 2u;
+            uint4 h[2], l[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                h[u] = make_uint4(0u, 0u, 0u, 0u);
+                l[u] = h[u];
+                if (cv && 16 * g + 8 * u < D) {
+                    h[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.hi) + bh + 16 * u);
+                    l[u] = ld16(reinterpret_cast<const char*>(a.lo) + bo + 16 * u);
+                }
+                const int nv = nvg - 8 * u;
+                if (nv < 8) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const uint32_t km = keep_mask(nv, w);
+                        (&h[u].x)[w] &= km;
+                        (&l[u].x)[w] &= km;
+                    }
+                }
+            }
+            float qv[16];
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const float4 t4 = *reinterpret_cast<const float4*>(sq + 16 * g + 4 * e4);
+                qv[4 * e4] = t4.x;
+                qv[4 * e4 + 1] = t4.y;
+                qv[4 * e4 + 2] = t4.z;
+                qv[4 * e4 + 3] = t4.w;
+            }
+            float p = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
+                const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const float y0 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u));
+                    const float y1 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u));
+                    const float d0 = qv[8 * u + 2 * w] - y0;
+                    const float d1 = qv[8 * u + 2 * w + 1] - y1;
+                    p = fmaf(d0, d0, p);
+                    p = fmaf(d1, d1, p);
+                }
+            }
+            p += __shfl_xor(p, 1);
+            p += __shfl_xor(p, 2);
+            p += __shfl_xor(p, 4);
+            bool exact_row = false;
+            if (__ballot(cv && p == 0.0f) != 0) {
+                bool eq = true;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
+                    const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u) == __float_as_uint(qv[8 * u + 2 * w]);
+                        eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u) == __float_as_uint(qv[8 * u + 2 * w + 1]);
+                    }
+                }
+                const uint32_t grp = (uint32_t)(__ballot(eq) >> (8 * rg)) & 0xFFu;
+                exact_row = grp == 0xFFu;
+            }
+            if (g == 0 && cv) cdist[c] = __float_as_uint(p) | (exact_row ? 0x80000000u : 0u);
+        }
+        __syncthreads();
+
+        // ---- 4. K best, certification, output
         const int Kp = min(a.K, Mr);
-        const uint64_t mykey = sort_select(cids, cdist, Mr);
+        const uint64_t mykey = sort_select<NSL>(cids, cdist, Mr);
         uint32_t oid = 0xFFFFFFFFu;
         float od = 0.0f;
         if (EXACT && Kp > 0) {
@@ -442,7 +751,7 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
     const int L = a.L;
     const int nq = BIG ? (int)a.counters[0] : a.Q;
 
-    for (int t = blockIdx.x; t < nq; t += gridDim.x) {
+    for (int t = xcd_block(); t < nq; t += gridDim.x) {
         const int q = BIG ? a.overflow[t] : t;
         uint32_t off = 0, cnt = 0;
         if (lane < L) {
@@ -505,14 +814,14 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
         load_query<VEC>(a, q, qv);
         int Mr = M;
         if (a.rerank > 0 && M > a.rerank) {
-            cand_distances<VEC, true>(qv, a.D, a.hi, a.lo, cids, cdist, M);
+            cand_distances<VEC, true>(qv, a.D, a.hs, a.hi, a.lo, cids, cdist, M);
             const uint64_t k2 = M <= 256 ? sort_select(cids, cdist, M) : select_topk(cids, cdist, M, a.rerank);
             __syncthreads();
             if (lane < a.rerank) cids[lane] = key_id(k2);
             __syncthreads();
             Mr = a.rerank;
         }
-        cand_distances<VEC, false>(qv, a.D, a.hi, a.lo, cids, cdist, Mr);
+        cand_distances<VEC, false>(qv, a.D, a.hs, a.hi, a.lo, cids, cdist, Mr);
         const int Kp = min(a.K, Mr);
         const uint64_t mykey = Mr <= 256 ? sort_select(cids, cdist, Mr) : select_topk(cids, cdist, Mr, Kp);
         uint32_t oid = 0xFFFFFFFFu;
@@ -532,25 +841,50 @@ constexpr int kCapMax = 256;      // early-stop limit a wave can hold
 constexpr int kUnionMax = 2048;   // uncapped: IDs per wave before deferring
 constexpr int kUnionBig = 8192;   // uncapped, deferred patches
 
-template <int VEC>
-static void launch_search_t(const SearchArgs& a, int grid, hipStream_t st) {
-    if (a.cap > 0) {
-        if (a.exact) hipLaunchKernelGGL((k_search_cap<VEC, true>), dim3(grid), dim3(64), 0, st, a);
-        else hipLaunchKernelGGL((k_search_cap<VEC, false>), dim3(grid), dim3(64), 0, st, a);
-    } else {
-        hipLaunchKernelGGL((k_search_union<VEC, kUnionMax, false>), dim3(grid), dim3(64), 0, st, a);
-    }
+static int cap_hash_slots_min(int cap) { return (5 * (cap + 63) + 2) / 3; }
+
+template <int NS, int NSL>
+static void launch_cap_n(const SearchArgs& a, int grid, size_t lds, hipStream_t st) {
+    if (a.exact) hipLaunchKernelGGL((k_search_cap<NS, true, NSL>), dim3(grid), dim3(64), lds, st, a);
+    else hipLaunchKernelGGL((k_search_cap<NS, false, NSL>), dim3(grid), dim3(64), lds, st, a);
+}
+// one wave (workgroup) per patch: no loop over patches, so that nothing is
+// held in registers from one patch to the next
+template <int NS>
+static void launch_cap(const SearchArgs& a, hipStream_t st) {
+    const int grid = round_grid8(a.Q);
+    const size_t lds = (size_t)a.hsz * sizeof(uint64_t) + 2 * (size_t)a.cp * sizeof(uint32_t);
+    if (a.cap <= 128) launch_cap_n<NS, 2>(a, grid, lds, st);
+    else launch_cap_n<NS, 4>(a, grid, lds, st);
 }
 
-hipError_t launch_search(const SearchArgs& a, hipStream_t st) {
-    if (a.Q == 0) return hipSuccess;
-    const int grid = a.Q < 32768 ? a.Q : 32768;
-    const bool v4 = a.D % 4 == 0 && a.D <= 128;
-    if (!v4 && a.D > 32) return hipErrorInvalidValue;
+hipError_t launch_search(const SearchArgs& a_in, hipStream_t st) {
+    if (a_in.Q == 0) return hipSuccess;
+    SearchArgs a = a_in;
+    const int grid = round_grid8(a.Q < 32768 ? a.Q : 32768);
+    if (a.D < 1 || a.D > 128) return hipErrorInvalidValue;
     if (a.cap > kCapMax) return hipErrorInvalidValue;
     if (!a.exact && (a.rerank < 1 || a.rerank > 64)) return hipErrorInvalidValue;
-    if (v4) launch_search_t<4>(a, grid, st);
-    else launch_search_t<1>(a, grid, st);
+    if (a.cap > 0) {
+        // hash set of at most cap + 63 IDs at load <= 0.6
+        int h = 64;
+        while (h < cap_hash_slots_min(a.cap)) h <<= 1;
+        a.hsz = h;
+        int cp = 64;
+        while (cp < a.cap) cp <<= 1;
+        a.cp = cp;
+        switch ((a.D + 31) / 32) {
+            case 1: launch_cap<1>(a, st); break;
+            case 2: launch_cap<2>(a, st); break;
+            case 3: launch_cap<3>(a, st); break;
+            default: launch_cap<4>(a, st); break;
+        }
+        return hipGetLastError();
+    }
+    const bool v4 = a.D % 4 == 0;
+    if (!v4 && a.D > 32) return hipErrorInvalidValue;
+    if (v4) hipLaunchKernelGGL((k_search_union<4, kUnionMax, false>), dim3(grid), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_search_union<1, kUnionMax, false>), dim3(grid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ struct Dict {
     uint64_t seed = 0;
     uint64_t cap = 0;             // directory slots per table
     const float* resid = nullptr; // borrowed
-    Buf hi, lo;                   // [n, D] split planes
+    Buf hi, lo;                   // [n, hi_stride(D)] and [n, D] split planes (64 bytes of slack at the end)
     Buf alpha, beta, bc0[2], ahi, alo;
     float bc1[2] = {0.f, 0.f}, bc2[2] = {0.f, 0.f};
     Buf dir;                      // [L, cap] Slot
@@ -250,6 +250,8 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.N = d.n;
     a.hi = P<uint16_t>(d.hi);
     a.lo = P<uint16_t>(d.lo);
+    a.hs = hi_stride(d.D);
+    a.ce = screen_coeff(d.D);
     a.out_ids = P<int32_t>(c->ids);
     a.out_d2 = P<float>(c->d2);
     a.out_m = P<int32_t>(c->m);
@@ -396,9 +398,12 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     while (cap < 2 * (uint64_t)n) cap <<= 1;
     d.cap = cap;
     // split storage of the features
-    TRY(ensure(c, d.hi, sizeof(uint16_t) * (size_t)n * D));
-    TRY(ensure(c, d.lo, sizeof(uint16_t) * (size_t)n * D));
-    HIPCHK(c, launch_split_planes(dict->feat, n * D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
+    TRY(ensure(c, d.hi, sizeof(uint16_t) * (size_t)n * hi_stride(D) + 64));
+    TRY(ensure(c, d.lo, sizeof(uint16_t) * (size_t)n * D + 64));
+    HIPCHK(c, hipMemsetAsync(d.hi.p, 0, d.hi.bytes, c->stream));
+    HIPCHK(c, hipMemsetAsync(d.lo.p, 0, d.lo.bytes, c->stream));
+    HIPCHK(c, launch_split_planes(dict->feat, n, D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
+    HIPCHK(c, launch_hi_tails(dict->feat, n, D, P<uint16_t>(d.hi), c->stream));
     // hash parameters
     hash_params(seed, L, k, D, (double)w, d.h_alpha, d.h_beta);
     const int m = L * k;
@@ -621,6 +626,7 @@ zh_status zh_lle_weights(zh_ctx* c, double lambda) {
     a.m = P<int32_t>(c->m);
     a.hi = P<uint16_t>(d.hi);
     a.lo = P<uint16_t>(d.lo);
+    a.hs = hi_stride(d.D);
     a.lam = lambda;
     a.fp64 = c->opts.lle_fp64;
     a.w = P<float>(c->w);

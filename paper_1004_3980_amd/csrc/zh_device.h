@@ -52,6 +52,14 @@ __device__ inline unsigned long long wave_min_u64(unsigned long long v) {
     }
     return v;
 }
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = __shfl_xor(v, o);
+        v = t < v ? t : v;
+    }
+    return v;
+}
 __device__ inline int wave_sum_i32(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -81,6 +89,27 @@ __device__ inline uint64_t lanemask_lt() {
     const int lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
+
+// bf16 of an fp32 value, round to nearest even; and back (exact)
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Block index for XCD-aware launches. Workgroups are handed to the eight
+// XCDs in turn (block b runs on XCD b % 8) and every XCD has its own L2.
+// Renumbering so that XCD x owns the x-th contiguous eighth of the blocks puts
+// blocks that run at the same time on one XCD on neighbouring work items
+// (neighbouring patches share most of their dictionary candidates). Grids
+// whose size is not a multiple of 8 keep the plain numbering.
+__device__ inline int xcd_block() {
+    const int G = gridDim.x;
+    if (G & 7) return blockIdx.x;
+    return (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+}
+__host__ __device__ inline int round_grid8(int g) { return g >= 8 ? (g + 7) & ~7 : g; }
 
 // Higham's gamma_n = n u / (1 - n u) for unit roundoff u.
 __host__ __device__ inline double gamma_n(int n, double u) { return n * u / (1.0 - n * u); }

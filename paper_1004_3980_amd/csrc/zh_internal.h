@@ -33,7 +33,7 @@ hipError_t launch_query_features(const float* lr, const float* maps, int h, int 
 hipError_t launch_dict_cut(const float* hr, const float* lr, const float* maps, int H, int W,
                            int scale, const int32_t* pos, int64_t n, int mode, float* feat,
                            float* resid, hipStream_t st);
-hipError_t launch_split_planes(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
+hipError_t launch_split_planes(const float* x, int64_t n, int D, uint16_t* hi, uint16_t* lo,
                                hipStream_t st);
 hipError_t launch_bicubic(const float* lr, int h, int w, int scale, float* out, hipStream_t st);
 
@@ -80,6 +80,9 @@ int64_t radix_hist_size(int64_t n);
 // ---- search (k_search.hip) ---------------------------------------------------
 struct SearchArgs {
     int Q, D, L, K, cap, rerank, exact;
+    int hsz, cp;             // LDS hash set slots, candidate slots (set by the launcher)
+    int hs;                  // row stride of the high plane (halfwords)
+    float ce;                // relative error coefficient of the screen's |q - x_hi|^2
     const uint2* bins;       // [Q, L] (offset, count) of the query's bin in each table
     const float* qfeat;      // [Q, D]
     const uint32_t* tids;    // [L, N]
@@ -96,11 +99,19 @@ struct SearchArgs {
     unsigned int* counters;  // [0] overflow count, [1] FP64 rank fallbacks
 };
 hipError_t launch_search(const SearchArgs& a, hipStream_t st);
+float screen_coeff(int D);   // error coefficient of the search's bf16 pre-filter (host)
+// Row layout of the high plane: D bf16 values, zero padding to a multiple of 4,
+// two floats (|x_hi|^2 in fp32 and an upper bound on |x - x_hi|), zero padding
+// to a multiple of 8 halfwords (16-byte rows).
+__host__ __device__ inline int hi_stride(int D) { return ((((D + 3) & ~3) + 4) + 7) & ~7; }
+__host__ __device__ inline int hi_tail(int D) { return (D + 3) & ~3; }
+hipError_t launch_hi_tails(const float* x, int64_t n, int D, uint16_t* hi, hipStream_t st);
 hipError_t launch_search_overflow(const SearchArgs& a, int n_over, hipStream_t st);
 
 // ---- LLE, synthesis, blend (k_lle.hip) --------------------------------------
 struct LleArgs {
     int Q, D, K;
+    int hs;                  // row stride of the high plane (halfwords)
     const float* qfeat;
     const int32_t* ids;
     const int32_t* m;
