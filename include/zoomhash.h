@@ -23,6 +23,12 @@
  *  - One context per host thread. Calls on one context are not thread-safe.
  *  - Patch order: patch q of an h x w LR image has top-left corner
  *    (i, j) = (q / (w-4), q % (w-4)); Q = (h-4)(w-4).
+ *  - Environment: ZH_MEM_LIMIT (bytes) caps the library's device
+ *    allocations; ZH_HASH_FIX_CAP (0..16) overrides the number of entries,
+ *    per 16 feature rows, of the list through which codes that the MFMA
+ *    projection cannot certify reach the FP64 recomputation (0 sends every
+ *    such table through the slower per-row path; results are identical
+ *    either way).
  */
 #ifndef ZOOMHASH_H
 #define ZOOMHASH_H

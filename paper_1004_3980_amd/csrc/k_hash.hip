@@ -77,6 +77,8 @@ __host__ __device__ inline int stage_stride(int prec, int D) {
     return ((D + 31) & ~31) + 8;
 }
 __host__ __device__ inline int fold_tables(int k) { return k <= 24 ? 4 : 2; }
+// fix-list entry: row, table, k codes, padded to 16 bytes
+__host__ __device__ inline int fix_entry_ints(int k) { return (k + 2 + 3) & ~3; }
 // bytes of the staged alpha, then beta and the bound constant of each staged row
 __host__ __device__ inline int stage_alpha_bytes(int prec, int k, int D) {
     const int R = stage_rows(k);
@@ -91,9 +93,11 @@ __host__ __device__ inline int stage_bytes(int prec, int k, int D) {
 // its beta and bound constants and shared by the four waves; on the split
 // path the next pair is fetched into registers while the current one is in
 // use. The 2k hash rows of a pair are packed into ceil(2k/16) MFMA tiles.
-// A code whose interval [P - B, P + B] holds an integer is left to
-// k_hash_fix: its table's bit is set in the row's dirty mask and the key
-// written here is replaced there.
+// A code whose interval [P - B, P + B] holds an integer is left to the FP64
+// definition: the table's k codes go to a compact list (the uncertain ones
+// marked kCodeUnset) for k_hash_fixlist, or, when the list is full, the
+// table's bit is set in the row's dirty mask for k_hash_fix; the key written
+// here is replaced there.
 template <int PREC, int NS, int NPRE>
 __global__ __launch_bounds__(256) void k_hash(HashArgs a) {
     const int D = a.D, k = a.k, L = a.L, m = L * k;
@@ -115,8 +119,12 @@ __global__ __launch_bounds__(256) void k_hash(HashArgs a) {
     float* sAf = reinterpret_cast<float*>(smem);
     float* sBeta = reinterpret_cast<float*>(smem + ((stage_alpha_bytes(PREC, k, D) + 15) & ~15));
     float* sBc0 = sBeta + R;
-    // per wave codes of `fold` tables: [fold*k][16 rows]
+    // per wave codes of `fold` tables: [fold*k][16 rows], then per wave a flag
+    // per (table of the fold group, row) with an uncertain code
     int32_t* sC = reinterpret_cast<int32_t*>(smem + stage_bytes(PREC, k, D)) + wave * (fold * k * kRowsPerWave);
+    uint8_t* sU = reinterpret_cast<uint8_t*>(reinterpret_cast<int32_t*>(smem + stage_bytes(PREC, k, D)) +
+                                             kWaves * fold * k * kRowsPerWave) + wave * (4 * kRowsPerWave);
+    if (lane < 4 * kRowsPerWave) sU[lane] = 0;
 
     // B operand of this lane for every k-step: feature row ri, coordinates
     // 32 s + 8 kb + e (e < 8) as bf16 high/low parts (PREC 1), or 4 s + kb
@@ -223,8 +231,9 @@ __global__ __launch_bounds__(256) void k_hash(HashArgs a) {
     }
     __syncthreads();
 
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wave;
     uint64_t dirty = 0;
-    unsigned nflag = 0;
+    unsigned nflag = 0, wcnt = 0;
     for (int g = 0; g < ngroups; ++g) {
         const int l0 = g * kStage;
         const int GKa = (L - l0 < kStage ? L - l0 : kStage) * k;
@@ -281,10 +290,10 @@ __global__ __launch_bounds__(256) void k_hash(HashArgs a) {
                 const bool flag = !(fabsf(P - n) > B) || !(fabsf(P) < 4194304.0f);
                 if (valid) {
                     if (flag) {
-                        dirty |= 1ull << (l0 + (hr >= k ? 1 : 0));
                         ++nflag;
+                        sU[((l0 % fold) + (hr >= k ? 1 : 0)) * kRowsPerWave + ri] = 1;
                     }
-                    sC[((l0 % fold) * k + hr) * kRowsPerWave + ri] = flag ? 0 : (int32_t)floorf(P);
+                    sC[((l0 % fold) * k + hr) * kRowsPerWave + ri] = flag ? kCodeUnset : (int32_t)floorf(P);
                 }
             }
         }
@@ -301,22 +310,120 @@ __global__ __launch_bounds__(256) void k_hash(HashArgs a) {
             const int t = lane >> 4, rr = lane & 15;
             const int lt = fl0 + t;
             const int64_t row = r0 + rr;
-            if (t < fold && lt < L && row < a.n) {
+            const bool act = t < fold && lt < L && row < a.n;
+            const bool unset = act && sU[t * kRowsPerWave + rr] != 0;
+            // a table with an uncertain code goes to this wave's region of the
+            // fix list with its codes (or, when the region is full, to the
+            // row's dirty mask)
+            const uint64_t bal = __ballot(unset);
+            const int idx = (int)wcnt + __popcll(bal & lanemask_lt());
+            int32_t* ent = nullptr;
+            if (unset) {
+                if (idx < a.fix_cap) {
+                    ent = a.fix_list + ((int64_t)wid * a.fix_cap + idx) * fix_entry_ints(k);
+                    ent[0] = (int32_t)row;
+                    ent[1] = lt;
+                } else {
+                    dirty |= 1ull << lt;
+                }
+            }
+            wcnt += (unsigned)__popcll(bal);
+            if (act) {
                 uint64_t h = key_seed(lt);
                 for (int j = 0; j < k; ++j) {
                     const int32_t c = sC[(t * k + j) * kRowsPerWave + rr];
                     if (a.codes) a.codes[row * m + lt * k + j] = c;
+                    if (ent) ent[2 + j] = c;
                     h = key_step(h, c);
                 }
                 a.keys[row * L + lt] = key_final(h);
             }
+            if (lane < 4 * kRowsPerWave) sU[lane] = 0;
         }
         __syncthreads();
     }
+    // tables of the fold lanes (t, row) that did not fit in the list
     dirty |= __shfl_xor(dirty, 16);
     dirty |= __shfl_xor(dirty, 32);
     if (kb == 0 && rowok) a.dirty[myrow] = dirty;
+    if (lane == 0 && r0 < a.n) a.fix_count[wid] = wcnt < (unsigned)a.fix_cap ? wcnt : (unsigned)a.fix_cap;
     if (nflag && a.n_fixed) atomicAdd(a.n_fixed, nflag);
+}
+
+// FP64 sequential dot product of an alpha row and a feature row (coordinates
+// in index order; each product is exact in FP64), 16-byte loads when the rows
+// allow it.
+__device__ __forceinline__ double dot_fp64(const float* __restrict__ ar, const float* __restrict__ vr, int D) {
+    double s = 0.0;
+    int i = 0;
+    if ((D & 3) == 0 && ((reinterpret_cast<uintptr_t>(ar) | reinterpret_cast<uintptr_t>(vr)) & 15) == 0) {
+        const float4* a4 = reinterpret_cast<const float4*>(ar);
+        const float4* v4 = reinterpret_cast<const float4*>(vr);
+#pragma unroll 5
+        for (int c = 0; c < D / 4; ++c) {
+            const float4 x = a4[c], y = v4[c];
+            s = s + (double)x.x * (double)y.x;
+            s = s + (double)x.y * (double)y.y;
+            s = s + (double)x.z * (double)y.z;
+            s = s + (double)x.w * (double)y.w;
+        }
+        i = D;
+    }
+    for (; i < D; ++i) s = s + (double)ar[i] * (double)vr[i];
+    return s;
+}
+
+// Entries of the fix list, one thread per entry slot: the uncertain codes of
+// the (row, table) pair are computed by the FP64 sequential dot product that
+// defines them, and the table's key is folded again from all k codes. The
+// entry is read into registers with 16-byte loads first.
+__global__ __launch_bounds__(256) void k_hash_fixlist(HashArgs a) {
+    const int64_t nw = (a.n + kRowsPerWave - 1) / kRowsPerWave;
+    const int cap = a.fix_cap;
+    const int64_t total = nw * cap;
+    const int k = a.k, D = a.D, L = a.L, m = L * k;
+    const int es4 = fix_entry_ints(k) / 4;
+    const double wd = (double)a.w;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w = (uint64_t)i / (uint32_t)cap;
+        if ((int)(i - w * cap) >= (int)a.fix_count[w]) continue;
+        const int4* e4 = reinterpret_cast<const int4*>(a.fix_list + i * fix_entry_ints(k));
+        int32_t ev[(kMaxKHash + 2 + 3) & ~3];
+#pragma unroll
+        for (int c = 0; c < (kMaxKHash + 2 + 3) / 4; ++c) {
+            int4 v = make_int4(0, 0, 0, 0);
+            if (c < es4) v = e4[c];
+            ev[4 * c] = v.x;
+            ev[4 * c + 1] = v.y;
+            ev[4 * c + 2] = v.z;
+            ev[4 * c + 3] = v.w;
+        }
+        const int64_t row = (uint32_t)ev[0];
+        const int l = ev[1];
+        const float* vr = a.feat + row * D;
+        uint32_t um = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxKHash; ++j)
+            if (j < k && ev[2 + j] == kCodeUnset) um |= 1u << j;
+        while (um) {
+            const int j = __builtin_ctz(um);
+            um &= um - 1;
+            const int hrow = l * k + j;
+            const int32_t c = floor_sat((dot_fp64(a.alpha + (int64_t)hrow * D, vr, D) + (double)a.beta[hrow]) / wd);
+#pragma unroll
+            for (int jj = 0; jj < kMaxKHash; ++jj)
+                if (jj == j) ev[2 + jj] = c;
+        }
+        uint64_t h = key_seed(l);
+#pragma unroll
+        for (int j = 0; j < kMaxKHash; ++j) {
+            if (j < k) {
+                if (a.codes) a.codes[row * m + l * k + j] = ev[2 + j];
+                h = key_step(h, ev[2 + j]);
+            }
+        }
+        a.keys[row * L + l] = key_final(h);
+    }
 }
 
 // Keys of the (row, table) pairs whose codes were not certain: every code of
@@ -439,12 +546,13 @@ static void launch_split(const HashArgs& a, dim3 grid, size_t lds, hipStream_t s
 
 hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty)
+    if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty || !a.fix_count ||
+        a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list))
         return hipErrorInvalidValue;
     const int rows = kWaves * kRowsPerWave;
     const dim3 grid((unsigned)((a.n + rows - 1) / rows));
     const size_t lds = (size_t)stage_bytes(a.prec, a.k, a.D) +
-                       (size_t)kWaves * fold_tables(a.k) * a.k * kRowsPerWave * 4;
+                       (size_t)kWaves * fold_tables(a.k) * a.k * kRowsPerWave * 4 + kWaves * 4 * kRowsPerWave;
     if (a.prec == 0) {
         hipLaunchKernelGGL((k_hash<0, 1, 1>), grid, dim3(256), lds, st, a);
     } else {
@@ -456,6 +564,13 @@ hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
         }
     }
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t slots = (a.n + kRowsPerWave - 1) / kRowsPerWave * a.fix_cap;
+    if (slots > 0) {
+        const int64_t gl = (slots + 255) / 256;
+        hipLaunchKernelGGL(k_hash_fixlist, dim3((unsigned)(gl < 8192 ? gl : 8192)), dim3(256), 0, st, a);
+    }
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 gfix((unsigned)((a.n + 63) / 64));
     const size_t lfix = (size_t)fix_groups(a.k) * (a.k + 1) * a.D * sizeof(float);

@@ -3,6 +3,7 @@
 // kernels of the zoom path. Compiled without multiply-add contraction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -57,7 +58,7 @@ struct zh_ctx {
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
     int64_t Q = 0;
-    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask;
+    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc;
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -235,6 +236,23 @@ zh_status clear_counters(zh_ctx* c) {
     return ZH_OK;
 }
 
+// Scratch of the hash kernels: the per-row dirty mask, and a fix list of
+// kFixSlots entries for each wave of 16 rows (384 tables at L = 24; on
+// average about 1% of the tables need a fix) with its entry counts.
+zh_status hash_scratch(zh_ctx* c, HashArgs& ha) {
+    TRY(ensure(c, c->hmask, sizeof(uint64_t) * (size_t)(ha.n > 0 ? ha.n : 1)));
+    ha.dirty = P<uint64_t>(c->hmask);
+    int cap = kFixSlots;
+    if (const char* ev = std::getenv("ZH_HASH_FIX_CAP")) cap = std::min(kFixSlots, std::max(0, std::atoi(ev)));
+    const size_t nw = (size_t)((ha.n + 15) / 16);
+    TRY(ensure(c, c->fixl, sizeof(int32_t) * nw * cap * (size_t)(((ha.k + 2) + 3) & ~3)));
+    TRY(ensure(c, c->fixc, sizeof(uint32_t) * (nw > 0 ? nw : 1)));
+    ha.fix_list = P<int32_t>(c->fixl);
+    ha.fix_cap = cap;
+    ha.fix_count = P<unsigned int>(c->fixc);
+    return ZH_OK;
+}
+
 zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     SearchArgs a{};
     a.Q = (int)c->Q;
@@ -306,7 +324,7 @@ void zh_destroy(zh_ctx* c) {
                 if (c->ev[st][i][j]) (void)hipEventDestroy(c->ev[st][i][j]);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -452,8 +470,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     ha.keys = P<uint64_t>(c->keys_dict);
     ha.codes = nullptr;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
-    TRY(ensure(c, c->hmask, sizeof(uint64_t) * (size_t)(ha.n > 0 ? ha.n : 1)));
-    ha.dirty = P<uint64_t>(c->hmask);
+    TRY(hash_scratch(c, ha));
     HIPCHK(c, launch_hash(ha, c->stream));
     // directory and bins, table by table
     TRY(ensure(c, d.dir, sizeof(Slot) * (size_t)L * cap));
@@ -523,8 +540,7 @@ zh_status zh_hash(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* c
     ha.keys = kp;
     ha.codes = codes;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
-    TRY(ensure(c, c->hmask, sizeof(uint64_t) * (size_t)(ha.n > 0 ? ha.n : 1)));
-    ha.dirty = P<uint64_t>(c->hmask);
+    TRY(hash_scratch(c, ha));
     HIPCHK(c, launch_hash(ha, c->stream));
     return ZH_OK;
 }
@@ -594,8 +610,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     ha.keys = P<uint64_t>(c->qkeys);
     ha.codes = nullptr;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
-    TRY(ensure(c, c->hmask, sizeof(uint64_t) * (size_t)(ha.n > 0 ? ha.n : 1)));
-    ha.dirty = P<uint64_t>(c->hmask);
+    TRY(hash_scratch(c, ha));
     ha.dir = P<Slot>(d.dir);
     ha.dir_cap = d.cap;
     ha.bins = P<uint2>(c->qbins);

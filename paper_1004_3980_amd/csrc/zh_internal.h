@@ -12,7 +12,9 @@ constexpr int kPatch = 5;       // LR patch side
 constexpr int kMaxTaps = 33;    // longest 1-D Gaussian the kernels accept
 constexpr int kMaxK = 16;       // neighbours per patch
 constexpr int kMaxL = 64;       // hash tables
-constexpr int kMaxKHash = 32;   // hashes per table
+constexpr int kMaxKHash = 32;
+constexpr int32_t kCodeUnset = (int32_t)0x80000000;   // MFMA codes lie within +-2^22
+constexpr int kFixSlots = 16;                        // fix-list entries per wave of 16 rows   // hashes per table
 
 struct Taps {                   // normalised 1-D Gaussian, offsets -R..R
     double g[kMaxTaps];
@@ -56,7 +58,11 @@ struct HashArgs {
     uint64_t* keys;          // [n, L]
     int32_t* codes;          // [n, L*k] or null
     unsigned int* n_fixed;   // count of codes recomputed in FP64 (nullable)
-    uint64_t* dirty;         // [n] scratch: per row, bit l set when table l holds a code decided in FP64
+    uint64_t* dirty;         // [n] scratch: per row, bit l set when table l must be recomputed in full
+    int32_t* fix_list;       // scratch: per wave of 16 rows, fix_cap entries (row, table, k codes;
+                             // kCodeUnset where the FP64 definition must decide)
+    int fix_cap;             // entries per wave (<= kFixSlots); tables beyond go to `dirty`
+    unsigned int* fix_count; // [ceil(n/16)] entries written by each wave
     const Slot* dir;         // bin directories [L, dir_cap], or null: no lookup
     uint64_t dir_cap;
     uint2* bins;             // [n, L] (offset, count) of each key's bin, when dir is set

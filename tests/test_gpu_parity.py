@@ -144,6 +144,30 @@ def test_codes_and_keys_bit_exact(gpu, name, proj):
     ctx.set_query_opts(cap=c.cap, proj=1)
 
 
+@pytest.mark.parametrize("fix_cap", ["0", "3"])
+def test_codes_and_keys_when_fix_list_overflows(gpu, fix_cap, monkeypatch):
+    """Tables whose uncertain codes do not fit the fix list (capacity forced
+    to 0 or 3 entries) take the per-row recomputation path: same codes and
+    keys."""
+    torch = _torch()
+    c = case(MID)
+    wl = c.wl
+    ctx = c.g.ctx
+    monkeypatch.setenv("ZH_HASH_FIX_CAP", fix_cap)
+    feat = c.pre.dictionary.feat[:50_000]
+    n = feat.shape[0]
+    ft = torch.from_numpy(feat).cuda()
+    codes = torch.empty((n, wl.L * wl.k), dtype=torch.int32, device="cuda")
+    keys = torch.empty((n, wl.L), dtype=torch.int64, device="cuda")
+    ctx.hash(wl.scale, ft, n, codes, keys)
+    ctx.sync()
+    monkeypatch.delenv("ZH_HASH_FIX_CAP")
+    ref = lsh.codes(feat, c.pre.alpha, c.pre.beta, wl.w)
+    assert ctx.stats()["codes_fixed"] > 3
+    assert np.array_equal(_np(codes), ref)
+    assert np.array_equal(_np(keys).view(np.uint64), lsh.bucket_keys(ref, wl.L, wl.k))
+
+
 def test_codes_boundary_cases_are_fixed(gpu):
     """Rows built so that alpha.v + beta sits within a few ulps of a bin
     edge: the fp32 and split-bf16 projections alone would misplace some of
