@@ -38,23 +38,21 @@ def psnr(x, ref):
     return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
 
 
-def search_bytes(ncand, wl, form):
-    """Algorithmic HBM bytes of one launch of the search stage.
+def search_bytes(ncand, nsurv, wl):
+    """Algorithmic HBM bytes of one launch of the search kernel (each byte the
+    kernel needs, read or written once).
 
-    Per patch: its L bin keys (8 B) and directory slots (16 B), its feature
-    row (4D B), the output (K ids + K distances + count). Per distinct
-    candidate: its ID (4 B) and its feature row: the bf16 half (2D B) in the
-    screened form plus the low half (2D B) of every re-ranked candidate, or
-    the full fp32 row (4D B) in the exact form."""
+    Per patch: its L bins (offset, count: 8 B each), its feature row (4D B),
+    the output (K ids, K distances, count, candidate count, survivor count).
+    Per distinct candidate: its ID (4 B) and its high-plane row with the
+    16-byte-aligned tail (2 hi_stride(D) B). Per survivor of the pre-filter:
+    the low-plane row (2D B)."""
     M = ncand.astype(np.int64)
+    S = nsurv.astype(np.int64)
     D, L, K = wl.D, wl.L, wl.K
-    per_q = 8 * L + 16 * L + 4 * D + 8 * K + 8
-    if form == "screened":
-        R = wl.rerank
-        rows = np.where(M > R, M * 2 * D + R * 2 * D, M * 4 * D)
-    else:
-        rows = M * 4 * D
-    return int(len(M) * per_q + (M * 4).sum() + rows.sum())
+    hs = ((((D + 3) & ~3) + 4) + 7) & ~7
+    per_q = 8 * L + 4 * D + 8 * K + 12
+    return int(len(M) * per_q + (M * (4 + 2 * hs)).sum() + (S * 2 * D).sum())
 
 
 def traffic_from_profile(form):
@@ -163,7 +161,7 @@ def main():
 
     # dominant kernel: the candidate search
     dom = max(("hash", "search", "lle", "synth", "blend"), key=lambda k: ms_stage[k])
-    sb = search_bytes(res["ncand"], wl, args.form)
+    sb = search_bytes(res["ncand"], res["nsurv"], wl)
     ach = sb / (ms_stage["search"] * 1e-3) / 1e9
     traffic = traffic_from_profile(args.form)
     roof = {"bound": "hbm", "kernel": "k_search", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -195,6 +193,7 @@ def main():
              "value_with_backprojection": Q / (dt / args.steps + bp_ms * 1e-3),
              "other_form": other_rec,
              "mean_candidates": float(res["ncand"].mean()),
+             "mean_survivors": float(res["nsurv"].mean()),
              "patches_without_neighbours": int((res["m"] == 0).sum()),
              "similarity_checks_saved": float(wl.n_dict / max(1e-9, res["ncand"].mean())),
              "stats": stats}

@@ -184,6 +184,11 @@ zh_status zh_backproject(zh_ctx* ctx, float* hr_inout, int iters, float sigma_s,
  * (in early-stop mode at most cap). */
 zh_status zh_get_results(zh_ctx* ctx, int32_t* ids, float* d2, int32_t* m, float* w,
                          int32_t* ncand);
+/* Candidates of each patch of the last zh_query that reached the exact
+ * distance pass (after the bf16 pre-filter; equal to the candidate count
+ * when the pre-filter did not run) into survivors[Q] (device). Early-stop
+ * search only (cap > 0); ZH_ESTATE otherwise. */
+zh_status zh_survivors(zh_ctx* ctx, int32_t* survivors);
 /* Query size of the last zh_query: *Q patches, *D feature dimension. */
 zh_status zh_query_shape(zh_ctx* ctx, int64_t* Q, int32_t* D);
 

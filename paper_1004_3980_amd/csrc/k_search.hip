@@ -650,6 +650,8 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
             Mr = S;
         }
 
+        if (lane == 0 && a.out_nsurv) a.out_nsurv[q] = Mr;
+
         // ---- 3. exact fp32 distances, eight lanes per row
         for (int cb = 0; cb < Mr; cb += 8) {
             const int c = cb + rg;

@@ -58,7 +58,7 @@ struct zh_ctx {
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
     int64_t Q = 0;
-    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc;
+    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv;
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -274,6 +274,10 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.out_d2 = P<float>(c->d2);
     a.out_m = P<int32_t>(c->m);
     a.out_ncand = P<int32_t>(c->ncand);
+    if (a.cap > 0) {
+        TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)(a.Q > 0 ? a.Q : 1)));
+        a.out_nsurv = P<int32_t>(c->nsurv);
+    }
     a.dump = dump;
     a.dump_cap = dump_cap;
     a.overflow = P<int32_t>(c->over);
@@ -324,7 +328,7 @@ void zh_destroy(zh_ctx* c) {
                 if (c->ev[st][i][j]) (void)hipEventDestroy(c->ev[st][i][j]);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -721,6 +725,15 @@ zh_status zh_get_results(zh_ctx* c, int32_t* ids, float* d2, int32_t* m, float* 
     if (m) HIPCHK(c, hipMemcpyAsync(m, c->m.p, Q * 4, hipMemcpyDeviceToDevice, c->stream));
     if (w) HIPCHK(c, hipMemcpyAsync(w, c->w.p, QK * 4, hipMemcpyDeviceToDevice, c->stream));
     if (ncand) HIPCHK(c, hipMemcpyAsync(ncand, c->ncand.p, Q * 4, hipMemcpyDeviceToDevice, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_survivors(zh_ctx* c, int32_t* survivors) {
+    if (!c || !survivors) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_survivors before zh_query");
+    if (c->opts.cap <= 0 || !c->nsurv.p) return fail(c, ZH_ESTATE, "zh_survivors: the last query had no early stop");
+    TRY(set_device(c));
+    HIPCHK(c, hipMemcpyAsync(survivors, c->nsurv.p, (size_t)c->Q * 4, hipMemcpyDeviceToDevice, c->stream));
     return ZH_OK;
 }
 

@@ -99,6 +99,7 @@ struct SearchArgs {
     float* out_d2;           // [Q, K]
     int32_t* out_m;          // [Q]
     int32_t* out_ncand;      // [Q]
+    int32_t* out_nsurv;      // [Q] candidates given an exact distance (early-stop search), nullable
     int32_t* dump;           // [Q, dump_cap] or null
     int dump_cap;
     int32_t* overflow;       // [Q] deferred queries (uncapped, too many IDs for a wave)

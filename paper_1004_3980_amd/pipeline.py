@@ -37,6 +37,7 @@ class GpuWorkload:
         self.ctx.make_dictionary(hr, hr.shape[0], hr.shape[1], hr.shape[2], pos, n, s,
                                  wl.blur_sigma, wl.feat_mode, self.feat, self.resid)
         del hr
+        self._cap = wl.cap
         self.ctx.set_query_opts(cap=wl.cap, rerank=0, proj=proj, lle_fp64=1)
         self.ctx.build_tables(self.feat, self.resid, n, self.D, s, wl.feat_mode, wl.L, wl.k,
                               wl.w, wl.hash_seed)
@@ -56,8 +57,8 @@ class GpuWorkload:
         self.hr_out = torch.empty((s * self.h, s * self.w), dtype=torch.float32, device=self.dev)
 
     def set_mode(self, cap=None, rerank=0, proj=1, lle_fp64=1):
-        self.ctx.set_query_opts(cap=self.wl.cap if cap is None else cap, rerank=rerank, proj=proj,
-                                lle_fp64=lle_fp64)
+        self._cap = self.wl.cap if cap is None else cap
+        self.ctx.set_query_opts(cap=self._cap, rerank=rerank, proj=proj, lle_fp64=lle_fp64)
 
     def zoom(self, lr=None, K=None, lam=None, out=None):
         """hash + K-NN + LLE + blend for the test image; returns the HR image."""
@@ -84,6 +85,16 @@ class GpuWorkload:
         w = torch.empty((Q, K), dtype=torch.float32, device=self.dev)
         nc = torch.empty(Q, dtype=torch.int32, device=self.dev)
         self.ctx.get_results(ids, d2, m, w, nc)
+        out = {}
+        if self.ctx_cap() > 0:
+            sv = torch.empty(Q, dtype=torch.int32, device=self.dev)
+            self.ctx.survivors(sv)
+            out["nsurv"] = sv
         self.ctx.sync()
-        return {"ids": ids.cpu().numpy(), "d2": d2.cpu().numpy(), "m": m.cpu().numpy(),
-                "w": w.cpu().numpy(), "ncand": nc.cpu().numpy()}
+        out = {k: v.cpu().numpy() for k, v in out.items()}
+        out.update({"ids": ids.cpu().numpy(), "d2": d2.cpu().numpy(), "m": m.cpu().numpy(),
+                    "w": w.cpu().numpy(), "ncand": nc.cpu().numpy()})
+        return out
+
+    def ctx_cap(self):
+        return self._cap

@@ -68,6 +68,7 @@ SIGNATURES = {
     "zh_reconstruct": [_V, _V],
     "zh_backproject": [_V, _V, _I, _F, _F],
     "zh_get_results": [_V, _V, _V, _V, _V, _V],
+    "zh_survivors": [_V, _V],
     "zh_query_shape": [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)],
     "zh_candidates": [_V, ctypes.c_int32, _V, _V],
     "zh_stats": [_V, ctypes.POINTER(zh_stats_t)],
@@ -192,6 +193,9 @@ class Context:
 
     def get_results(self, ids=None, d2=None, m=None, w=None, ncand=None):
         self._chk(self.lib.zh_get_results(self.h, _ptr(ids), _ptr(d2), _ptr(m), _ptr(w), _ptr(ncand)))
+
+    def survivors(self, out):
+        self._chk(self.lib.zh_survivors(self.h, _ptr(out)))
 
     def query_shape(self):
         Q = ctypes.c_int64()
