@@ -176,6 +176,23 @@ zh_status zh_reconstruct(zh_ctx* ctx, float* hr_out);
  * zh_query and the blur sigma of the degradation (1.0). */
 zh_status zh_backproject(zh_ctx* ctx, float* hr_inout, int iters, float sigma_s, float sigma_r);
 
+/* Gradients of a loss L on the output image of the last zh_reconstruct,
+ * or of the zh_backproject call that followed it on that image (one call;
+ * after a second one the chain is not recorded and this returns ZH_ESTATE):
+ *   g_hr[s h, s w]     (in)  dL/d output image;
+ *   g_resid[N, (5s)^2] (out) dL/d the HR residual patches of the dictionary
+ *                      used by the query (the same values as dL/d the HR
+ *                      patches), overwritten, zero for rows no patch uses;
+ *   g_lambda[1]        (out) dL/d lambda of the last zh_lle_weights.
+ * Neighbour indices (hash codes, candidates, K nearest) are held at their
+ * forward values. Adjoints of the back-projection iterations (Section 4,
+ * Section 4.3; the range weight included, from the guides zh_backproject
+ * keeps), of the blend, of the synthesis (Eq. HR_Rec) and of the LLE
+ * weights through lambda (Eq. LinSys; Gram matrices recomputed and
+ * factorised again in FP64). Deterministic: no floating-point atomics.
+ * All pointers are device pointers; K <= 16, D <= 128. */
+zh_status zh_backward(zh_ctx* ctx, const float* g_hr, float* g_resid, float* g_lambda);
+
 /* ---- results and diagnostics ------------------------------------------ */
 
 /* Copies of the last query's results (device pointers, each may be NULL):

@@ -1,0 +1,372 @@
+// Adjoint of the zoom: gradients of a loss on the output image with respect
+// to the dictionary's HR residual patches and the LLE regulariser lambda.
+// Neighbour indices (hash codes, candidates, top-K) are discrete and stay at
+// their forward values.
+//
+// Back-projection (Section 4, the update after Eq. Err_img; Section 4.3,
+// Eq. sx2 and Eq. bl_filter_3), one iteration I' = I + S(I) F(I) with
+// F = N Up (I_L - Dec Blur I) and S = exp(-(I - Box I)^2 / (2 sigma_r^2)):
+//
+//   g <- g - Blur^T Dec^T Up^T N^T (S g) + (Id - Box)^T [-(a / sigma_r^2) S F g],
+//
+// a = I - Box I. Every operator is separable (a matrix per axis with
+// replicate or in-image-normalised borders), so each transpose is two
+// one-axis gathers (k_axis_adj) whose weights are rebuilt from the forward
+// definitions: normalised Gaussian (taps inside the image, divided by their
+// sum), box mean (in-image count), Keys' cubic (a = -0.5, replicate border),
+// Gaussian blur with replicate border followed by phase-0 decimation.
+//
+// Blend (per-pixel mean of the covering patches): each patch pixel receives
+// g(X) / cnt(X). Synthesis x_q = mu_q + sum_m w_qm r_{n_qm} (Eq. HR_Rec):
+// dL/dr_n = sum over the (q, m) with n_qm = n of w_qm g_q, gathered per
+// dictionary row over a stable sort of the neighbour lists (no float
+// atomics, fixed order); dL/dw_qm = <g_q, r_{n_qm}>. LLE weights (Eq. LinSys)
+// with A = G + lambda tr(G) I: the Gram matrix is recomputed in FP64 and
+// factorised again, dw~/dlambda = -tr(G) A^-1 w~, dw/dlambda =
+// (dw~/dlambda - w 1^T dw~/dlambda) / 1^T w~; dL/dlambda is a fixed-order
+// FP64 reduction over the patches.
+#include <cmath>
+
+#include "zh_internal.h"
+
+namespace zh {
+
+// ---- one-axis transposed operators ------------------------------------------
+// Along x (AXIS 0) the array is [rows][n] and the pass maps rows of n_in to
+// rows of n_out; along y (AXIS 1) it is [n][cols], cols = a.rows.
+template <int OP, int AXIS>
+__global__ __launch_bounds__(256) void k_axis_adj(AxisAdjArgs a) {
+    const int64_t total = (int64_t)a.rows * a.n_out;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int c, o;
+        if (AXIS == 0) {
+            c = (int)(idx / a.n_out);
+            o = (int)(idx - (int64_t)c * a.n_out);
+        } else {
+            o = (int)(idx / a.rows);
+            c = (int)(idx - (int64_t)o * a.rows);
+        }
+        auto in = [&](int x) -> float {
+            const int64_t p = AXIS == 0 ? (int64_t)c * a.n_in + x : (int64_t)x * a.rows + c;
+            return a.mul ? a.in[p] * a.mul[p] : a.in[p];
+        };
+        const int n = a.n_in, R = a.R;
+        float acc = 0.0f;
+        if (OP == kAdjGauss) {
+            // out[o] = sum_x c(o - x) in[x] / nrm(x), nrm(x) = sum of the in-image taps at x
+            for (int x = max(0, o - R); x <= min(n - 1, o + R); ++x) {
+                float nrm = 0.0f;
+                for (int d = -R; d <= R; ++d)
+                    if (x + d >= 0 && x + d < n) nrm += a.taps[d + R];
+                acc = fmaf(a.taps[o - x + R] / nrm, in(x), acc);
+            }
+        } else if (OP == kAdjBox) {
+            for (int x = max(0, o - R); x <= min(n - 1, o + R); ++x) {
+                const int cnt = min(n - 1, x + R) - max(0, x - R) + 1;
+                acc += in(x) / (float)cnt;
+            }
+        } else if (OP == kAdjUp) {
+            // HR n_in -> LR n_out: HR sample x reads LR floor(x/s) - 1 + t, t = 0..3
+            const int s = a.s;
+            for (int x = max(0, s * (o - 2)); x < min(n, s * (o + 3)); ++x) {
+                const int i0 = x / s;
+                const float tx = (float)(x - i0 * s) / (float)s;
+                float wsum = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (clampi(i0 - 1 + t, 0, a.n_out - 1) == o) wsum += keys_w(tx - (float)(t - 1));
+                acc = fmaf(wsum, in(x), acc);
+            }
+        } else {
+            // LR n_in -> HR n_out: LR sample i reads HR clamp(s i + t), |t| <= R
+            const int s = a.s;
+            const int ilo = max(0, (o - R) / s - 1), ihi = min(n - 1, (o + R) / s + 1);
+            for (int i = ilo; i <= ihi; ++i) {
+                float wsum = 0.0f;
+                for (int t = -R; t <= R; ++t)
+                    if (clampi(s * i + t, 0, a.n_out - 1) == o) wsum += a.taps[t + R];
+                acc = fmaf(wsum, in(i), acc);
+            }
+        }
+        const int64_t po = AXIS == 0 ? (int64_t)c * a.n_out + o : (int64_t)o * a.rows + c;
+        a.out[po] = acc;
+    }
+}
+
+template <int OP>
+static hipError_t axis_pass(AxisAdjArgs a, int axis, hipStream_t st) {
+    const int64_t total = (int64_t)a.rows * a.n_out;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (axis == 0)
+        hipLaunchKernelGGL((k_axis_adj<OP, 0>), dim3((unsigned)g), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_axis_adj<OP, 1>), dim3((unsigned)g), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_axis_adj(int op, int axis, const AxisAdjArgs& a, hipStream_t st) {
+    if (a.R > kMaxAdjR) return hipErrorInvalidValue;
+    switch (op) {
+        case kAdjGauss: return axis_pass<kAdjGauss>(a, axis, st);
+        case kAdjBox: return axis_pass<kAdjBox>(a, axis, st);
+        case kAdjUp: return axis_pass<kAdjUp>(a, axis, st);
+        default: return axis_pass<kAdjDec>(a, axis, st);
+    }
+}
+
+// ---- elementwise pieces of one iteration's adjoint --------------------------
+// z = -(a / sigma_r^2) S F g   (FSa = [F | S | a])
+__global__ void k_bp_adj_z(const float* __restrict__ FSa, const float* __restrict__ g, int64_t n, float inv_sr2,
+                           float* __restrict__ z) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = -(FSa[2 * n + i] * inv_sr2) * FSa[n + i] * FSa[i] * g[i];
+}
+// g <- g - v + z - bz  (z, bz null when the range weight is constant)
+__global__ void k_bp_adj_combine(float* __restrict__ g, const float* __restrict__ v, const float* __restrict__ z,
+                                 const float* __restrict__ bz, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float r = g[i] - v[i];
+        if (z) r += z[i] - bz[i];
+        g[i] = r;
+    }
+}
+
+static dim3 grid1(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return dim3((unsigned)(g > 65536 ? 65536 : (g < 1 ? 1 : g)));
+}
+
+hipError_t launch_bp_adj_z(const float* FSa, const float* g, int64_t n, float sigma_r, float* z, hipStream_t st) {
+    hipLaunchKernelGGL(k_bp_adj_z, grid1(n), dim3(256), 0, st, FSa, g, n, 1.0f / (sigma_r * sigma_r), z);
+    return hipGetLastError();
+}
+hipError_t launch_bp_adj_combine(float* g, const float* v, const float* z, const float* bz, int64_t n,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_bp_adj_combine, grid1(n), dim3(256), 0, st, g, v, z, bz, n);
+    return hipGetLastError();
+}
+
+// ---- blend adjoint: gradient per covered pixel divided by its count ---------
+__global__ void k_blend_adj(const float* __restrict__ g, const int32_t* __restrict__ m, int h, int w, int s,
+                            float* __restrict__ gp) {
+    const int H = s * h, W = s * w, ps = kPatch * s;
+    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
+    const int64_t total = (int64_t)H * W;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int Y = (int)(idx / W), X = (int)(idx % W);
+        const int ilo = Y - ps + 1 <= 0 ? 0 : (Y - ps + s) / s;
+        const int ihi = min(npi - 1, Y / s);
+        const int jlo = X - ps + 1 <= 0 ? 0 : (X - ps + s) / s;
+        const int jhi = min(npj - 1, X / s);
+        int cnt = 0;
+        for (int i = ilo; i <= ihi; ++i)
+            for (int j = jlo; j <= jhi; ++j) cnt += m[i * npj + j] > 0 ? 1 : 0;
+        gp[idx] = cnt > 0 ? g[idx] / (float)cnt : 0.0f;
+    }
+}
+
+hipError_t launch_blend_adj(const float* g, const int32_t* m, int h, int w, int s, float* gp, hipStream_t st) {
+    hipLaunchKernelGGL(k_blend_adj, grid1((int64_t)s * h * s * w), dim3(256), 0, st, g, m, h, w, s, gp);
+    return hipGetLastError();
+}
+
+// ---- LLE adjoint through lambda: one wave per patch --------------------------
+// dL/dw_m = <g_q, r_{n_m}> over the patch's HR pixels; the Gram matrix of
+// Z = q - X_N in FP64 (coordinates over the lanes, wave sums), then on lane
+// 0: A = G + lambda tau I, Cholesky, w~ = A^-1 1, d = -tau A^-1 w~,
+// contribution [g_w . d - (g_w . w)(1 . d)] / (1 . w~).
+__global__ __launch_bounds__(256) void k_lle_lambda_adj(BackwardArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int D = a.D, K = a.K, s = a.s, ps = kPatch * s, ps2 = ps * ps;
+    const int npj = a.w - kPatch + 1;
+    const int W = s * a.w;
+    for (int q = blockIdx.x * wpb + (threadIdx.x >> 6); q < a.Q; q += gridDim.x * wpb) {
+        const int mq = a.m[q];
+        if (mq <= 0) {
+            if (lane == 0) a.c_lam[q] = 0.0;
+            continue;
+        }
+        const int pi = q / npj, pj = q % npj;
+        // patch gradient values of this lane: pixels lane + 64 u
+        float gq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int P = lane + 64 * u;
+            gq[u] = 0.0f;
+            if (P < ps2) {
+                const int py = P / ps, px = P % ps;
+                gq[u] = a.gp[(int64_t)(s * pi + py) * W + s * pj + px];
+            }
+        }
+        double gw[kMaxK];
+        for (int mi = 0; mi < K; ++mi) {
+            double acc = 0.0;
+            if (mi < mq) {
+                const float* r = a.resid + (int64_t)a.ids[(int64_t)q * K + mi] * ps2;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int P = lane + 64 * u;
+                    if (P < ps2) acc += (double)gq[u] * (double)r[P];
+                }
+            }
+            gw[mi] = wave_sum_f64(acc);
+        }
+        // Gram of Z = q - x_n (FP64), coordinates lane and lane + 64
+        double z0[kMaxK], z1[kMaxK];
+        const float* qf = a.qfeat + (int64_t)q * D;
+        for (int mi = 0; mi < K; ++mi) {
+            z0[mi] = z1[mi] = 0.0;
+            if (mi < mq) {
+                const int64_t id = a.ids[(int64_t)q * K + mi];
+                if (lane < D)
+                    z0[mi] = (double)qf[lane] - (double)join_planes(a.hi[id * a.hs + lane], a.lo[id * D + lane]);
+                if (lane + 64 < D)
+                    z1[mi] = (double)qf[lane + 64] -
+                             (double)join_planes(a.hi[id * a.hs + lane + 64], a.lo[id * D + lane + 64]);
+            }
+        }
+        double G[kMaxK * (kMaxK + 1) / 2];
+        for (int i = 0; i < mq; ++i)
+            for (int j = 0; j <= i; ++j) G[i * (i + 1) / 2 + j] = wave_sum_f64(z0[i] * z0[j] + z1[i] * z1[j]);
+        if (lane == 0) {
+            double tau = 0.0;
+            for (int i = 0; i < mq; ++i) tau += G[i * (i + 1) / 2 + i];
+            double contrib = 0.0;
+            if (tau > 0.0) {
+                // Cholesky of A = G + lambda tau I (lower, packed)
+                double Lc[kMaxK * (kMaxK + 1) / 2];
+                for (int i = 0; i < mq; ++i) {
+                    for (int j = 0; j <= i; ++j) {
+                        double v = G[i * (i + 1) / 2 + j] + (i == j ? a.lam * tau : 0.0);
+                        for (int t = 0; t < j; ++t) v -= Lc[i * (i + 1) / 2 + t] * Lc[j * (j + 1) / 2 + t];
+                        Lc[i * (i + 1) / 2 + j] = i == j ? sqrt(v) : v / Lc[j * (j + 1) / 2 + j];
+                    }
+                }
+                auto solve = [&](const double* b, double* x) {
+                    for (int i = 0; i < mq; ++i) {
+                        double v = b[i];
+                        for (int t = 0; t < i; ++t) v -= Lc[i * (i + 1) / 2 + t] * x[t];
+                        x[i] = v / Lc[i * (i + 1) / 2 + i];
+                    }
+                    for (int i = mq - 1; i >= 0; --i) {
+                        double v = x[i];
+                        for (int t = i + 1; t < mq; ++t) v -= Lc[t * (t + 1) / 2 + i] * x[t];
+                        x[i] = v / Lc[i * (i + 1) / 2 + i];
+                    }
+                };
+                double one[kMaxK], wt[kMaxK], d[kMaxK];
+                for (int i = 0; i < mq; ++i) one[i] = 1.0;
+                solve(one, wt);
+                double sig = 0.0;
+                for (int i = 0; i < mq; ++i) sig += wt[i];
+                solve(wt, d);
+                double dsum = 0.0, gd = 0.0, gww = 0.0;
+                for (int i = 0; i < mq; ++i) {
+                    d[i] *= -tau;
+                    dsum += d[i];
+                    gd += gw[i] * d[i];
+                    gww += gw[i] * wt[i] / sig;
+                }
+                contrib = (gd - gww * dsum) / sig;
+            }
+            a.c_lam[q] = contrib;
+        }
+    }
+}
+
+hipError_t launch_lle_lambda_adj(const BackwardArgs& a, hipStream_t st) {
+    if (a.K > kMaxK || a.D > 128 || kPatch * a.s * kPatch * a.s > 256) return hipErrorInvalidValue;
+    int g = (a.Q + 3) / 4;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_lle_lambda_adj, dim3(g < 1 ? 1 : g), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Fixed-order FP64 sum of n values: one workgroup, thread t adds t, t + 1024,
+// ... in order, then a tree over the threads; the result is rounded to fp32.
+__global__ __launch_bounds__(1024) void k_sum_f64(const double* __restrict__ x, int64_t n, float* __restrict__ out) {
+    __shared__ double s[1024];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += x[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (float)s[0];
+}
+
+hipError_t launch_sum_f64(const double* x, int64_t n, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(1024), 0, st, x, n, out);
+    return hipGetLastError();
+}
+
+// ---- dictionary gradient ----------------------------------------------------
+// Neighbour list entries e = q K + m as (key = dictionary row, value = e);
+// entries past m_q get the key `none` and sort last.
+__global__ void k_nbr_pairs(const int32_t* __restrict__ ids, const int32_t* __restrict__ m, int Q, int K,
+                            uint32_t none, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    const int64_t total = (int64_t)Q * K;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(e / K), mi = (int)(e % K);
+        key[e] = mi < m[q] ? (uint32_t)ids[e] : none;
+        val[e] = (uint32_t)e;
+    }
+}
+
+hipError_t launch_nbr_pairs(const int32_t* ids, const int32_t* m, int Q, int K, uint32_t none, uint32_t* key,
+                            uint32_t* val, hipStream_t st) {
+    hipLaunchKernelGGL(k_nbr_pairs, grid1((int64_t)Q * K), dim3(256), 0, st, ids, m, Q, K, none, key, val);
+    return hipGetLastError();
+}
+
+// One wave per run of equal keys in the sorted entries (the wave at the first
+// entry of the run): g_r[n][P] = sum over the run, in entry order, of
+// w_e g_q(e)[P].
+__global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ key, const uint32_t* __restrict__ val,
+                                                   int64_t n_ent, uint32_t none, const float* __restrict__ wts,
+                                                   const float* __restrict__ gp, int w, int s, int K,
+                                                   float* __restrict__ g_r) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int ps = kPatch * s, ps2 = ps * ps;
+    const int npj = w - kPatch + 1, W = s * w;
+    for (int64_t p = blockIdx.x * (int64_t)wpb + (threadIdx.x >> 6); p < n_ent; p += (int64_t)gridDim.x * wpb) {
+        const uint32_t k = key[p];
+        if (k == none || (p > 0 && key[p - 1] == k)) continue;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int64_t e = p; e < n_ent && key[e] == k; ++e) {
+            const uint32_t v = val[e];
+            const int q = (int)(v / (uint32_t)K);
+            const float wq = wts[v];
+            const int pi = q / npj, pj = q % npj;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int P = lane + 64 * u;
+                if (P < ps2) acc[u] = fmaf(wq, gp[(int64_t)(s * pi + P / ps) * W + s * pj + P % ps], acc[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int P = lane + 64 * u;
+            if (P < ps2) g_r[(int64_t)k * ps2 + P] = acc[u];
+        }
+    }
+}
+
+hipError_t launch_dict_grad(const uint32_t* key, const uint32_t* val, int64_t n_ent, uint32_t none, const float* wts,
+                            const float* gp, int w, int s, int K, float* g_r, hipStream_t st) {
+    if (kPatch * s * kPatch * s > 256) return hipErrorInvalidValue;
+    int64_t g = (n_ent + 3) / 4;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_dict_grad, dim3((unsigned)(g < 1 ? 1 : g)), dim3(256), 0, st, key, val, n_ent, none, wts,
+                       gp, w, s, K, g_r);
+    return hipGetLastError();
+}
+
+}  // namespace zh

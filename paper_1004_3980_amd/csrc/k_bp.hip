@@ -22,6 +22,9 @@ constexpr int kBpTile = 32;
 constexpr int kBpMaxR = 8;
 constexpr int kBpReg = kBpTile + 2 * kBpMaxR;
 
+// TERMS: instead of the update, write F, S and a = I - mu (the pieces the
+// adjoint of the iteration needs) to out, out + H W and out + 2 H W.
+template <bool TERMS>
 __global__ __launch_bounds__(256) void k_bp_update(const float* __restrict__ I, const float* __restrict__ e,
                                                    int H, int W, int h, int w, int s, int R, float sigma_s,
                                                    float inv2sr2, float* __restrict__ out) {
@@ -80,7 +83,14 @@ __global__ __launch_bounds__(256) void k_bp_update(const float* __restrict__ I, 
         const float mu = bs / (float)(ny * nx);
         const float dd = Ixy - mu;
         const float S = expf(-dd * dd * inv2sr2);
-        out[(int64_t)Y * W + X] = fmaf(S, ge / gn, Ixy);
+        if (TERMS) {
+            const int64_t hw = (int64_t)H * W, o = (int64_t)Y * W + X;
+            out[o] = ge / gn;
+            out[hw + o] = S;
+            out[2 * hw + o] = dd;
+        } else {
+            out[(int64_t)Y * W + X] = fmaf(S, ge / gn, Ixy);
+        }
     }
 }
 
@@ -90,8 +100,19 @@ hipError_t launch_bp_update(const float* I, const float* e, int H, int W, int h,
     if (R > kBpMaxR || R < 0) return hipErrorInvalidValue;
     const float inv2sr2 = sigma_r > 0.0f && std::isfinite(sigma_r) ? 1.0f / (2.0f * sigma_r * sigma_r) : 0.0f;
     dim3 grid((W + kBpTile - 1) / kBpTile, (H + kBpTile - 1) / kBpTile);
-    hipLaunchKernelGGL(k_bp_update, grid, dim3(256), 0, st, I, e, H, W, h, w, scale, R, sigma_s, inv2sr2,
+    hipLaunchKernelGGL((k_bp_update<false>), grid, dim3(256), 0, st, I, e, H, W, h, w, scale, R, sigma_s, inv2sr2,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_terms(const float* I, const float* e, int H, int W, int h, int w, int scale,
+                           float sigma_s, float sigma_r, float* FSa, hipStream_t st) {
+    const int R = (int)std::ceil(3.0 * (double)sigma_s);
+    if (R > kBpMaxR || R < 0) return hipErrorInvalidValue;
+    const float inv2sr2 = sigma_r > 0.0f && std::isfinite(sigma_r) ? 1.0f / (2.0f * sigma_r * sigma_r) : 0.0f;
+    dim3 grid((W + kBpTile - 1) / kBpTile, (H + kBpTile - 1) / kBpTile);
+    hipLaunchKernelGGL((k_bp_update<true>), grid, dim3(256), 0, st, I, e, H, W, h, w, scale, R, sigma_s, inv2sr2,
+                       FSa);
     return hipGetLastError();
 }
 

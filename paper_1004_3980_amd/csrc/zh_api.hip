@@ -57,8 +57,12 @@ struct zh_ctx {
     // last query
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
+    double lam = 0.0;             // lambda of the last zh_lle_weights
+    // back-projection record for zh_backward: 0 none, 1 one call kept, -1 more than one
+    int bp_rec = 0, bp_iters = 0;
+    float bp_sigma_s = 0.f, bp_sigma_r = 0.f;
     int64_t Q = 0;
-    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv;
+    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv, guides, bwd, bwd_k, clam;
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -328,7 +332,7 @@ void zh_destroy(zh_ctx* c) {
                 if (c->ev[st][i][j]) (void)hipEventDestroy(c->ev[st][i][j]);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -661,6 +665,7 @@ zh_status zh_lle_weights(zh_ctx* c, double lambda) {
         StageTimer t(c, ZH_T_LLE);
         HIPCHK(c, launch_lle(a, c->stream));
     }
+    c->lam = lambda;
     c->stage = 2;
     return ZH_OK;
 }
@@ -683,6 +688,7 @@ zh_status zh_reconstruct(zh_ctx* c, float* hr_out) {
                                c->stream));
     }
     c->stage = 3;
+    c->bp_rec = 0;
     return ZH_OK;
 }
 
@@ -698,7 +704,20 @@ zh_status zh_backproject(zh_ctx* c, float* hr, int iters, float sigma_s, float s
     const Taps g = gauss_taps(1.0);
     float* a = hr;
     float* b = P<float>(c->tmp);
+    // keep the guides I^0 .. I^{iters-1} of the first call after zh_reconstruct
+    const bool record = c->stage == 3 && c->bp_rec == 0;
+    if (c->stage == 3 && c->bp_rec != 0) c->bp_rec = -1;
+    if (record) {
+        TRY(ensure(c, c->guides, sizeof(float) * (size_t)H * W * (size_t)(iters > 0 ? iters : 1)));
+        c->bp_rec = 1;
+        c->bp_iters = iters;
+        c->bp_sigma_s = sigma_s;
+        c->bp_sigma_r = sigma_r;
+    }
     for (int t = 0; t < iters; ++t) {
+        if (record)
+            HIPCHK(c, hipMemcpyAsync(P<float>(c->guides) + (size_t)t * H * W, a, sizeof(float) * (size_t)H * W,
+                                     hipMemcpyDeviceToDevice, c->stream));
         {
             StageTimer t1(c, ZH_T_BP_ERROR);
             HIPCHK(c, launch_degrade_residual(a, H, W, s, g, P<float>(c->lr), P<float>(c->e), c->stream));
@@ -711,6 +730,130 @@ zh_status zh_backproject(zh_ctx* c, float* hr, int iters, float sigma_s, float s
     }
     if (a != hr)
         HIPCHK(c, hipMemcpyAsync(hr, a, sizeof(float) * (size_t)H * W, hipMemcpyDeviceToDevice, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_backward(zh_ctx* c, const float* g_hr, float* g_resid, float* g_lambda) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 3) return fail(c, ZH_ESTATE, "zh_backward needs zh_reconstruct first");
+    if (c->bp_rec < 0)
+        return fail(c, ZH_ESTATE, "zh_backward: more than one zh_backproject after zh_reconstruct");
+    if (!g_hr || !g_resid || !g_lambda) return fail(c, ZH_EINVAL, "zh_backward: null pointer");
+    Dict& d = c->dicts[c->qscale];
+    if (!d.resid) return fail(c, ZH_ESTATE, "zh_backward: the dictionary has no HR residuals");
+    const int s = c->qscale, h = c->qh, w = c->qw, H = s * h, W = s * w, K = c->qK;
+    const int ps2 = (kPatch * s) * (kPatch * s);
+    if (K > kMaxK || d.D > 128 || ps2 > 256) return fail(c, ZH_EUNSUPPORTED, "zh_backward: K <= 16, D <= 128, s <= 3");
+    TRY(set_device(c));
+    const int64_t HW = (int64_t)H * W, Q = c->Q;
+    // workspace: gamma, F|S|a, four HR temporaries, H x w, h x w, h x W
+    TRY(ensure(c, c->bwd, sizeof(float) * (size_t)(8 * HW + (int64_t)H * w + (int64_t)h * w + (int64_t)h * W)));
+    float* gam = P<float>(c->bwd);
+    float* FSa = gam + HW;
+    float* tA = FSa + 3 * HW;
+    float* tB = tA + HW;
+    float* tC = tB + HW;
+    float* tD = tC + HW;
+    float* tHw = tD + HW;
+    float* thw = tHw + (int64_t)H * w;
+    float* thW = thw + (int64_t)h * w;
+    TRY(ensure(c, c->e, sizeof(float) * (size_t)h * w));
+    HIPCHK(c, hipMemcpyAsync(gam, g_hr, sizeof(float) * (size_t)HW, hipMemcpyDeviceToDevice, c->stream));
+    const int T = c->bp_rec == 1 ? c->bp_iters : 0;
+    if (T > 0) {
+        const Taps g = gauss_taps(1.0);
+        const float ss = c->bp_sigma_s, sr = c->bp_sigma_r;
+        const int Rs = (int)std::ceil(3.0 * (double)ss);
+        AxisAdjArgs gx{}, bx{}, ux{}, dx{};
+        for (int dd = -Rs; dd <= Rs; ++dd) gx.taps[dd + Rs] = (float)std::exp(-(double)(dd * dd) / (2.0 * ss * ss));
+        gx.R = Rs;
+        bx.R = Rs;
+        ux.s = s;
+        dx.s = s;
+        dx.R = g.R;
+        for (int t = -g.R; t <= g.R; ++t) dx.taps[t + g.R] = (float)g.g[t + g.R];
+        const bool range = std::isfinite(sr);
+        for (int t = T - 1; t >= 0; --t) {
+            const float* I = P<float>(c->guides) + (size_t)t * HW;
+            HIPCHK(c, launch_degrade_residual(I, H, W, s, g, P<float>(c->lr), P<float>(c->e), c->stream));
+            HIPCHK(c, launch_bp_terms(I, P<float>(c->e), H, W, h, w, s, ss, sr, FSa, c->stream));
+            // v = Blur^T Dec^T Up^T N^T (S gamma)
+            AxisAdjArgs a = gx;
+            a.in = gam; a.mul = FSa + HW; a.out = tA; a.rows = H; a.n_in = W; a.n_out = W;
+            HIPCHK(c, launch_axis_adj(kAdjGauss, 0, a, c->stream));
+            a = gx;
+            a.in = tA; a.out = tB; a.rows = W; a.n_in = H; a.n_out = H;
+            HIPCHK(c, launch_axis_adj(kAdjGauss, 1, a, c->stream));
+            a = ux;
+            a.in = tB; a.out = tHw; a.rows = H; a.n_in = W; a.n_out = w;
+            HIPCHK(c, launch_axis_adj(kAdjUp, 0, a, c->stream));
+            a = ux;
+            a.in = tHw; a.out = thw; a.rows = w; a.n_in = H; a.n_out = h;
+            HIPCHK(c, launch_axis_adj(kAdjUp, 1, a, c->stream));
+            a = dx;
+            a.in = thw; a.out = thW; a.rows = h; a.n_in = w; a.n_out = W;
+            HIPCHK(c, launch_axis_adj(kAdjDec, 0, a, c->stream));
+            a = dx;
+            a.in = thW; a.out = tA; a.rows = W; a.n_in = h; a.n_out = H;
+            HIPCHK(c, launch_axis_adj(kAdjDec, 1, a, c->stream));
+            if (range) {
+                // z = -(a / sigma_r^2) S F gamma, then Box^T z
+                HIPCHK(c, launch_bp_adj_z(FSa, gam, HW, sr, tC, c->stream));
+                a = bx;
+                a.in = tC; a.out = tB; a.rows = H; a.n_in = W; a.n_out = W;
+                HIPCHK(c, launch_axis_adj(kAdjBox, 0, a, c->stream));
+                a = bx;
+                a.in = tB; a.out = tD; a.rows = W; a.n_in = H; a.n_out = H;
+                HIPCHK(c, launch_axis_adj(kAdjBox, 1, a, c->stream));
+                HIPCHK(c, launch_bp_adj_combine(gam, tA, tC, tD, HW, c->stream));
+            } else {
+                HIPCHK(c, launch_bp_adj_combine(gam, tA, nullptr, nullptr, HW, c->stream));
+            }
+        }
+    }
+    // blend: gradient per covered pixel over its count
+    float* gp = tB;
+    HIPCHK(c, launch_blend_adj(gam, P<int32_t>(c->m), h, w, s, gp, c->stream));
+    // lambda
+    TRY(ensure(c, c->clam, sizeof(double) * (size_t)(Q > 0 ? Q : 1)));
+    BackwardArgs ba{};
+    ba.Q = (int)Q;
+    ba.D = d.D;
+    ba.K = K;
+    ba.s = s;
+    ba.w = w;
+    ba.hs = hi_stride(d.D);
+    ba.qfeat = P<float>(c->qfeat);
+    ba.ids = P<int32_t>(c->ids);
+    ba.m = P<int32_t>(c->m);
+    ba.hi = P<uint16_t>(d.hi);
+    ba.lo = P<uint16_t>(d.lo);
+    ba.resid = d.resid;
+    ba.gp = gp;
+    ba.lam = c->lam;
+    ba.c_lam = P<double>(c->clam);
+    HIPCHK(c, launch_lle_lambda_adj(ba, c->stream));
+    HIPCHK(c, launch_sum_f64(P<double>(c->clam), Q, g_lambda, c->stream));
+    // dictionary rows: the neighbour lists sorted by row (stable), one wave per row
+    const int64_t E = Q * K;
+    const uint32_t none = (uint32_t)d.n;
+    int bits = 1;
+    while (bits < 32 && (1ull << bits) <= (uint64_t)d.n) ++bits;
+    const int64_t hsz = radix_hist_size(E > 0 ? E : 1);
+    TRY(ensure(c, c->bwd_k, sizeof(uint32_t) * (size_t)(4 * (E > 0 ? E : 1) + hsz)));
+    uint32_t* k0 = P<uint32_t>(c->bwd_k);
+    uint32_t* v0 = k0 + E;
+    uint32_t* k1 = v0 + E;
+    uint32_t* v1 = k1 + E;
+    uint32_t* hist = v1 + E;
+    HIPCHK(c, hipMemsetAsync(g_resid, 0, sizeof(float) * (size_t)d.n * ps2, c->stream));
+    if (E > 0) {
+        HIPCHK(c, launch_nbr_pairs(P<int32_t>(c->ids), P<int32_t>(c->m), (int)Q, K, none, k0, v0, c->stream));
+        bool first = true;
+        HIPCHK(c, radix_sort_pairs(k0, v0, k1, v1, E, bits, hist, hsz, c->stream, &first));
+        HIPCHK(c, launch_dict_grad(first ? k0 : k1, first ? v0 : v1, E, none, P<float>(c->w), gp, w, s, K, g_resid,
+                                   c->stream));
+    }
     return ZH_OK;
 }
 

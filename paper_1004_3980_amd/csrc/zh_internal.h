@@ -145,5 +145,47 @@ hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, in
 hipError_t launch_bp_update(const float* I, const float* e, int H, int W, int h, int w,
                             int scale, float sigma_s, float sigma_r, float* out,
                             hipStream_t st);
+// F, S and a = I - box mean of one iteration into FSa = [F | S | a] (HR each)
+hipError_t launch_bp_terms(const float* I, const float* e, int H, int W, int h, int w, int scale,
+                           float sigma_s, float sigma_r, float* FSa, hipStream_t st);
+
+// ---- adjoint (k_backward.hip) -------------------------------------------------
+constexpr int kMaxAdjR = 8;
+enum { kAdjGauss = 0, kAdjBox = 1, kAdjUp = 2, kAdjDec = 3 };
+struct AxisAdjArgs {
+    const float* in;
+    const float* mul;        // optional elementwise factor of the input (same layout), nullable
+    float* out;
+    int rows;                // rows (x pass) or columns (y pass) of the other axis
+    int n_in, n_out;         // length of the axis in and out
+    int s;                   // zoom factor (bicubic and degradation)
+    int R;                   // tap radius (Gaussian, box, blur)
+    float taps[2 * kMaxAdjR + 1];   // Gaussian taps (unnormalised) or blur taps
+};
+// one pass of a transposed separable operator along x (axis 0) or y (axis 1)
+hipError_t launch_axis_adj(int op, int axis, const AxisAdjArgs& a, hipStream_t st);
+hipError_t launch_bp_adj_z(const float* FSa, const float* g, int64_t n, float sigma_r, float* z, hipStream_t st);
+hipError_t launch_bp_adj_combine(float* g, const float* v, const float* z, const float* bz, int64_t n,
+                                 hipStream_t st);
+hipError_t launch_blend_adj(const float* g, const int32_t* m, int h, int w, int s, float* gp, hipStream_t st);
+struct BackwardArgs {
+    int Q, D, K, s, w;       // patches, feature dimension, neighbours, zoom, LR width
+    int hs;                  // row stride of the high plane
+    const float* qfeat;
+    const int32_t* ids;
+    const int32_t* m;
+    const uint16_t* hi;
+    const uint16_t* lo;
+    const float* resid;      // [N, (5s)^2]
+    const float* gp;         // [s h, s w] gradient per covered pixel / its count
+    double lam;
+    double* c_lam;           // [Q] per-patch contribution to dL/dlambda
+};
+hipError_t launch_lle_lambda_adj(const BackwardArgs& a, hipStream_t st);
+hipError_t launch_sum_f64(const double* x, int64_t n, float* out, hipStream_t st);
+hipError_t launch_nbr_pairs(const int32_t* ids, const int32_t* m, int Q, int K, uint32_t none, uint32_t* key,
+                            uint32_t* val, hipStream_t st);
+hipError_t launch_dict_grad(const uint32_t* key, const uint32_t* val, int64_t n_ent, uint32_t none, const float* wts,
+                            const float* gp, int w, int s, int K, float* g_r, hipStream_t st);
 
 }  // namespace zh

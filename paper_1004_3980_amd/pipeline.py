@@ -70,6 +70,22 @@ class GpuWorkload:
         self.ctx.reconstruct(out)
         return out
 
+    token = 0
+
+    def forward_record(self, lr, lam, K=None, iters=None, out=None):
+        """Query, weights, reconstruction and back-projection of `lr` into a
+        new image (or `out`), recorded for zh_backward."""
+        wl = self.wl
+        s = wl.scale
+        out = self.torch.empty((s * lr.shape[0], s * lr.shape[1]), dtype=self.torch.float32,
+                               device=self.dev) if out is None else out
+        self.ctx.query(lr, lr.shape[0], lr.shape[1], s, wl.K if K is None else K)
+        self.ctx.lle_weights(lam)
+        self.ctx.reconstruct(out)
+        self.ctx.backproject(out, wl.bp_iters if iters is None else iters, wl.sigma_s, wl.sigma_r)
+        self.token += 1
+        return out
+
     def backproject(self, hr, iters=None):
         wl = self.wl
         self.ctx.backproject(hr, wl.bp_iters if iters is None else iters, wl.sigma_s, wl.sigma_r)

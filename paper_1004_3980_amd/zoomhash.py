@@ -67,6 +67,7 @@ SIGNATURES = {
     "zh_lle_weights": [_V, ctypes.c_double],
     "zh_reconstruct": [_V, _V],
     "zh_backproject": [_V, _V, _I, _F, _F],
+    "zh_backward": [_V, _V, _V, _V],
     "zh_get_results": [_V, _V, _V, _V, _V, _V],
     "zh_survivors": [_V, _V],
     "zh_query_shape": [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)],
@@ -190,6 +191,9 @@ class Context:
 
     def backproject(self, hr, iters, sigma_s, sigma_r):
         self._chk(self.lib.zh_backproject(self.h, _ptr(hr), iters, sigma_s, sigma_r))
+
+    def backward(self, g_hr, g_resid, g_lambda):
+        self._chk(self.lib.zh_backward(self.h, _ptr(g_hr), _ptr(g_resid), _ptr(g_lambda)))
 
     def get_results(self, ids=None, d2=None, m=None, w=None, ncand=None):
         self._chk(self.lib.zh_get_results(self.h, _ptr(ids), _ptr(d2), _ptr(m), _ptr(w), _ptr(ncand)))
