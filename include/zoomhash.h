@@ -193,6 +193,45 @@ zh_status zh_backproject(zh_ctx* ctx, float* hr_inout, int iters, float sigma_s,
  * All pointers are device pointers; K <= 16, D <= 128. */
 zh_status zh_backward(zh_ctx* ctx, const float* g_hr, float* g_resid, float* g_lambda);
 
+/* ---- batched form ------------------------------------------------------ */
+
+/* Many LR images of uneven size and zoom factor in one launch chain: for
+ * each zoom factor present, the patches of all its images form one index
+ * space for features, hashing, search, LLE weights and synthesis; the blend
+ * and the back-projection run over the images' pixels and tiles (a
+ * persistent update kernel takes (image, tile) items from a work counter).
+ * The chain is captured once into a HIP graph and replayed while the batch
+ * (pointers, sizes, parameters, query options, tuning) stays the same; it
+ * runs on a stream of the context ordered after and before the context's
+ * stream. Results equal those of zh_query, zh_lle_weights, zh_reconstruct
+ * and zh_backproject run image by image. Afterwards the single-image query
+ * state is cleared (zh_lle_weights etc. need a new zh_query). */
+typedef struct {
+    int32_t n_images;
+    const float* const* lr;      /* host array [n_images] of device pointers, image i is [h[i], w[i]] */
+    float* const* hr_out;        /* host array [n_images] of device pointers, [scale[i] h[i], scale[i] w[i]] */
+    const int32_t* h;            /* host arrays [n_images]; h, w >= 5 */
+    const int32_t* w;
+    const int32_t* scale;        /* each with tables built (zh_build_tables) */
+    int32_t K;                   /* neighbours, 1..16 */
+    double lambda;               /* LLE regulariser, > 0 */
+    int32_t bp_iters;            /* back-projection iterations, >= 0 */
+    float sigma_s, sigma_r;      /* as zh_backproject */
+} zh_batch;
+zh_status zh_run_batch(zh_ctx* ctx, const zh_batch* batch);
+
+/* Autotuner of the batched form: times the back-projection update over the
+ * batch's tiles for tile sides {16, 32} and persistent grids of {2, 4, 8}
+ * workgroups per compute unit (HIP events, best of 2), keeps the fastest for
+ * later zh_run_batch calls and reports it in *out (host, nullable). Runs the
+ * batch once first; the images' outputs are overwritten. */
+typedef struct {
+    int32_t bp_tile;             /* chosen tile side */
+    int32_t bp_grid_per_cu;      /* chosen workgroups per compute unit */
+    float bp_ms[6];              /* per configuration (tile 16: 2, 4, 8; tile 32: 2, 4, 8), ms per iteration */
+} zh_batch_tuning;
+zh_status zh_tune_batch(zh_ctx* ctx, const zh_batch* batch, zh_batch_tuning* out);
+
 /* ---- results and diagnostics ------------------------------------------ */
 
 /* Copies of the last query's results (device pointers, each may be NULL):

@@ -20,22 +20,22 @@ namespace zh {
 
 constexpr int kBpTile = 32;
 constexpr int kBpMaxR = 8;
-constexpr int kBpReg = kBpTile + 2 * kBpMaxR;
 
-// TERMS: instead of the update, write F, S and a = I - mu (the pieces the
-// adjoint of the iteration needs) to out, out + H W and out + 2 H W.
-template <bool TERMS>
-__global__ __launch_bounds__(256) void k_bp_update(const float* __restrict__ I, const float* __restrict__ e,
-                                                   int H, int W, int h, int w, int s, int R, float sigma_s,
-                                                   float inv2sr2, float* __restrict__ out) {
-    __shared__ float sI[kBpReg][kBpReg];
-    __shared__ float sE[kBpReg][kBpReg];
-    __shared__ float sHE[kBpReg][kBpTile];
-    __shared__ float sHB[kBpReg][kBpTile];
+// One T x T output tile with origin (Y0, X0). TERMS: instead of the update,
+// write F, S and a = I - mu (the pieces the adjoint of the iteration needs)
+// to out, out + H W and out + 2 H W.
+template <int T, bool TERMS>
+__device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float* __restrict__ e, int H, int W, int h,
+                                        int w, int s, int R, float sigma_s, float inv2sr2, float* __restrict__ out,
+                                        int Y0, int X0) {
+    constexpr int REG = T + 2 * kBpMaxR;
+    __shared__ float sI[REG][REG];
+    __shared__ float sE[REG][REG];
+    __shared__ float sHE[REG][T];
+    __shared__ float sHB[REG][T];
     __shared__ float sg[2 * kBpMaxR + 1];
-    const int Y0 = blockIdx.y * kBpTile, X0 = blockIdx.x * kBpTile;
-    const int reg = kBpTile + 2 * R;
-    if (threadIdx.x < 2 * R + 1) {
+    const int reg = T + 2 * R;
+    if ((int)threadIdx.x < 2 * R + 1) {
         const float d = (float)((int)threadIdx.x - R);
         sg[threadIdx.x] = expf(-(d * d) / (2.0f * sigma_s * sigma_s));
     }
@@ -48,8 +48,8 @@ __global__ __launch_bounds__(256) void k_bp_update(const float* __restrict__ I, 
     }
     __syncthreads();
     // horizontal passes over every staged row, the tile's columns
-    for (int t = threadIdx.x; t < reg * kBpTile; t += blockDim.x) {
-        const int r = t / kBpTile, c = t % kBpTile;
+    for (int t = threadIdx.x; t < reg * T; t += blockDim.x) {
+        const int r = t / T, c = t % T;
         const int X = X0 + c;
         float ge = 0.0f, gn = 0.0f, bs = 0.0f;
         for (int d = -R; d <= R; ++d) {
@@ -64,8 +64,8 @@ __global__ __launch_bounds__(256) void k_bp_update(const float* __restrict__ I, 
         sHB[r][c] = bs;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < kBpTile * kBpTile; t += blockDim.x) {
-        const int r = t / kBpTile, c = t % kBpTile;
+    for (int t = threadIdx.x; t < T * T; t += blockDim.x) {
+        const int r = t / T, c = t % T;
         const int Y = Y0 + r, X = X0 + c;
         if (Y >= H || X >= W) continue;
         float ge = 0.0f, gn = 0.0f, bs = 0.0f;
@@ -94,6 +94,53 @@ __global__ __launch_bounds__(256) void k_bp_update(const float* __restrict__ I, 
     }
 }
 
+template <bool TERMS>
+__global__ __launch_bounds__(256) void k_bp_update(const float* __restrict__ I, const float* __restrict__ e,
+                                                   int H, int W, int h, int w, int s, int R, float sigma_s,
+                                                   float inv2sr2, float* __restrict__ out) {
+    bp_tile<kBpTile, TERMS>(I, e, H, W, h, w, s, R, sigma_s, inv2sr2, out, blockIdx.y * kBpTile,
+                            blockIdx.x * kBpTile);
+}
+
+int bp_tiles(int H, int W, int tile) { return ((H + tile - 1) / tile) * ((W + tile - 1) / tile); }
+
+// Batched update: persistent workgroups take (image, tile) items from the
+// counter until none is left; every workgroup exits after one failed take.
+template <int T>
+__global__ __launch_bounds__(256) void k_b_bp_update(const BatchImage* __restrict__ im, int n, int64_t n_tiles, int s,
+                                                     int R, float sigma_s, float inv2sr2, const float* __restrict__ e,
+                                                     int parity, unsigned int* __restrict__ counter) {
+    __shared__ int64_t item;
+    for (;;) {
+        if (threadIdx.x == 0) item = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t it = item;
+        __syncthreads();
+        if (it >= n_tiles) break;
+        const BatchImage& b = im[batch_image_of<&BatchImage::tile_off>(im, n, it)];
+        const int H = s * b.h, W = s * b.w;
+        const int tx = (W + T - 1) / T;
+        const int local = (int)(it - b.tile_off);
+        const float* I = parity ? b.scr : b.out;
+        float* out = parity ? b.out : b.scr;
+        bp_tile<T, false>(I, e + b.lr_off, H, W, b.h, b.w, s, R, sigma_s, inv2sr2, out, (local / tx) * T,
+                          (local % tx) * T);
+        __syncthreads();
+    }
+}
+
+__global__ void k_b_zero_u32(unsigned int* p) { *p = 0u; }
+
+// Results of an odd number of iterations are in scr: copy them to out.
+__global__ void k_b_copy_scr(const BatchImage* __restrict__ im, int n, int64_t total, int s) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const BatchImage& b = im[batch_image_of<&BatchImage::hr_off>(im, n, idx)];
+        const int64_t r = idx - b.hr_off;
+        b.out[r] = b.scr[r];
+    }
+}
+
 hipError_t launch_bp_update(const float* I, const float* e, int H, int W, int h, int w, int scale,
                             float sigma_s, float sigma_r, float* out, hipStream_t st) {
     const int R = (int)std::ceil(3.0 * (double)sigma_s);
@@ -113,6 +160,31 @@ hipError_t launch_bp_terms(const float* I, const float* e, int H, int W, int h, 
     dim3 grid((W + kBpTile - 1) / kBpTile, (H + kBpTile - 1) / kBpTile);
     hipLaunchKernelGGL((k_bp_update<true>), grid, dim3(256), 0, st, I, e, H, W, h, w, scale, R, sigma_s, inv2sr2,
                        FSa);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_bp_update(const BatchImage* im, int n, int64_t n_tiles, int tile, int grid, int scale,
+                              float sigma_s, float sigma_r, const float* e, int parity, unsigned int* counter,
+                              hipStream_t st) {
+    const int R = (int)std::ceil(3.0 * (double)sigma_s);
+    if (R > kBpMaxR || R < 0 || (tile != 16 && tile != 32) || grid < 1) return hipErrorInvalidValue;
+    if (n_tiles == 0) return hipSuccess;
+    const float inv2sr2 = sigma_r > 0.0f && std::isfinite(sigma_r) ? 1.0f / (2.0f * sigma_r * sigma_r) : 0.0f;
+    hipLaunchKernelGGL(k_b_zero_u32, dim3(1), dim3(1), 0, st, counter);
+    if (tile == 16)
+        hipLaunchKernelGGL((k_b_bp_update<16>), dim3(grid), dim3(256), 0, st, im, n, n_tiles, scale, R, sigma_s, inv2sr2,
+                           e, parity, counter);
+    else
+        hipLaunchKernelGGL((k_b_bp_update<32>), dim3(grid), dim3(256), 0, st, im, n, n_tiles, scale, R, sigma_s, inv2sr2,
+                           e, parity, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_copy_scr(const BatchImage* im, int n, int64_t hr_total, int scale, hipStream_t st) {
+    if (hr_total == 0) return hipSuccess;
+    int64_t g = (hr_total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_b_copy_scr, dim3((unsigned)g), dim3(256), 0, st, im, n, hr_total, scale);
     return hipGetLastError();
 }
 

@@ -48,9 +48,41 @@ __global__ void k_degrade_residual(const float* __restrict__ hr, int H, int W, i
     }
 }
 
+// Batched: LR error of every image, the current estimate in out (parity 0)
+// or scr (parity 1); image b's error at e + lr_off.
+__global__ void k_b_degrade_residual(const BatchImage* __restrict__ im, int n, int64_t total, int scale, Taps t,
+                                     int parity, float* __restrict__ e) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const BatchImage& b = im[batch_image_of<&BatchImage::lr_off>(im, n, idx)];
+        const int r = (int)(idx - b.lr_off);
+        const int i = r / b.w, j = r % b.w;
+        const float* hr = parity ? b.scr : b.out;
+        e[idx] = (float)((double)b.lr[r] - blur_at(hr, scale * b.h, scale * b.w, scale * i, scale * j, t));
+    }
+}
+
 // Four gradient maps per image, fp32 [n_img, 4, h, w]:
 //   dx = I(c+1) - I(c-1), dy likewise along rows,
 //   dxx = (2 I(c) - I(c-2)) - I(c+2), dyy likewise; replicate border.
+__device__ __forceinline__ void gradient_maps_at(const float* __restrict__ I, int h, int w, int rc,
+                                                 float* __restrict__ M) {
+    const int r = rc / w, c = rc % w;
+    auto at = [&](int rr, int cc) -> double {
+        return (double)I[(int64_t)clampi(rr, 0, h - 1) * w + clampi(cc, 0, w - 1)];
+    };
+    const double x0 = at(r, c);
+    const double dx = at(r, c + 1) - at(r, c - 1);
+    const double dy = at(r + 1, c) - at(r - 1, c);
+    const double dxx = (2.0 * x0 - at(r, c - 2)) - at(r, c + 2);
+    const double dyy = (2.0 * x0 - at(r - 2, c)) - at(r + 2, c);
+    const int64_t plane = (int64_t)h * w;
+    M[rc] = (float)dx;
+    M[plane + rc] = (float)dy;
+    M[2 * plane + rc] = (float)dxx;
+    M[3 * plane + rc] = (float)dyy;
+}
+
 __global__ void k_gradient_maps(const float* __restrict__ lr, int n_img, int h, int w,
                                 float* __restrict__ maps) {
     const int64_t total = (int64_t)n_img * h * w;
@@ -58,22 +90,16 @@ __global__ void k_gradient_maps(const float* __restrict__ lr, int n_img, int h, 
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t im = idx / ((int64_t)h * w);
         const int rc = (int)(idx % ((int64_t)h * w));
-        const int r = rc / w, c = rc % w;
-        const float* I = lr + im * (int64_t)h * w;
-        auto at = [&](int rr, int cc) -> double {
-            return (double)I[(int64_t)clampi(rr, 0, h - 1) * w + clampi(cc, 0, w - 1)];
-        };
-        const double x0 = at(r, c);
-        const double dx = at(r, c + 1) - at(r, c - 1);
-        const double dy = at(r + 1, c) - at(r - 1, c);
-        const double dxx = (2.0 * x0 - at(r, c - 2)) - at(r, c + 2);
-        const double dyy = (2.0 * x0 - at(r - 2, c)) - at(r + 2, c);
-        float* M = maps + im * 4 * (int64_t)h * w;
-        const int64_t plane = (int64_t)h * w;
-        M[rc] = (float)dx;
-        M[plane + rc] = (float)dy;
-        M[2 * plane + rc] = (float)dxx;
-        M[3 * plane + rc] = (float)dyy;
+        gradient_maps_at(lr + im * (int64_t)h * w, h, w, rc, maps + im * 4 * (int64_t)h * w);
+    }
+}
+
+// Batched: every LR pixel of every image; maps of image b at 4 lr_off.
+__global__ void k_b_gradient_maps(const BatchImage* __restrict__ im, int n, int64_t total, float* __restrict__ maps) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const BatchImage& b = im[batch_image_of<&BatchImage::lr_off>(im, n, idx)];
+        gradient_maps_at(b.lr, b.h, b.w, (int)(idx - b.lr_off), maps + 4 * b.lr_off);
     }
 }
 
@@ -87,27 +113,49 @@ __device__ __forceinline__ double patch_mean(const float* __restrict__ I, int w,
 
 // One thread per (patch, feature element); the element 0 thread also writes
 // the patch mean.
+// element e of the features of patch q (and its mean when e == 0)
+__device__ __forceinline__ void feature_at(const float* __restrict__ lr, const float* __restrict__ maps, int h,
+                                           int w, int mode, int q, int e, float* __restrict__ f,
+                                           double* __restrict__ mu) {
+    const int nj = w - kPatch + 1;
+    const int i = q / nj, j = q % nj;
+    if (mode == 0) {
+        const double m = patch_mean(lr, w, i, j);
+        const int a = e / kPatch, b = e % kPatch;
+        *f = (float)((double)lr[(int64_t)(i + a) * w + j + b] - m);
+        if (e == 0) *mu = m;
+    } else {
+        const int ch = e / 25, a = (e % 25) / kPatch, b = e % kPatch;
+        *f = maps[(int64_t)ch * h * w + (int64_t)(i + a) * w + j + b];
+        if (e == 0) *mu = patch_mean(lr, w, i, j);
+    }
+}
+
 __global__ void k_query_features(const float* __restrict__ lr, const float* __restrict__ maps,
                                  int h, int w, int mode, float* __restrict__ feat,
                                  double* __restrict__ mu) {
-    const int nj = w - kPatch + 1;
-    const int Q = (h - kPatch + 1) * nj;
+    const int Q = (h - kPatch + 1) * (w - kPatch + 1);
     const int D = mode == 0 ? 25 : 100;
     const int64_t total = (int64_t)Q * D;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int q = (int)(idx / D), e = (int)(idx % D);
-        const int i = q / nj, j = q % nj;
-        if (mode == 0) {
-            const double m = patch_mean(lr, w, i, j);
-            const int a = e / kPatch, b = e % kPatch;
-            feat[idx] = (float)((double)lr[(int64_t)(i + a) * w + j + b] - m);
-            if (e == 0) mu[q] = m;
-        } else {
-            const int ch = e / 25, a = (e % 25) / kPatch, b = e % kPatch;
-            feat[idx] = maps[(int64_t)ch * h * w + (int64_t)(i + a) * w + j + b];
-            if (e == 0) mu[q] = patch_mean(lr, w, i, j);
-        }
+        feature_at(lr, maps, h, w, mode, q, e, feat + idx, mu + q);
+    }
+}
+
+// Batched: every (patch, element) of every image, patches in image order.
+__global__ void k_b_query_features(const BatchImage* __restrict__ im, int n, int64_t q_total, int mode,
+                                   const float* __restrict__ maps, float* __restrict__ feat,
+                                   double* __restrict__ mu) {
+    const int D = mode == 0 ? 25 : 100;
+    const int64_t total = q_total * D;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = idx / D;
+        const int e = (int)(idx - p * D);
+        const BatchImage& b = im[batch_image_of<&BatchImage::q_off>(im, n, p)];
+        feature_at(b.lr, maps + 4 * b.lr_off, b.h, b.w, mode, (int)(p - b.q_off), e, feat + idx, mu + p);
     }
 }
 
@@ -229,6 +277,29 @@ hipError_t launch_query_features(const float* lr, const float* maps, int h, int 
     const int64_t total = (int64_t)(h - kPatch + 1) * (w - kPatch + 1) * (mode == 0 ? 25 : 100);
     hipLaunchKernelGGL(k_query_features, dim3(grid_for(total, 256)), dim3(256), 0, st, lr, maps,
                        h, w, mode, feat, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gradient_maps(const BatchImage* im, int n, int64_t lr_total, float* maps, hipStream_t st) {
+    if (lr_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_gradient_maps, dim3(grid_for(lr_total, 256)), dim3(256), 0, st, im, n, lr_total, maps);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t q_total, int mode, const float* maps,
+                                   float* feat, double* mu, hipStream_t st) {
+    const int64_t total = q_total * (mode == 0 ? 25 : 100);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_query_features, dim3(grid_for(total, 256)), dim3(256), 0, st, im, n, q_total, mode, maps,
+                       feat, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int scale, const Taps& t,
+                                     int parity, float* e, hipStream_t st) {
+    if (lr_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_b_degrade_residual, dim3(grid_for(lr_total, 256)), dim3(256), 0, st, im, n, lr_total, scale,
+                       t, parity, e);
     return hipGetLastError();
 }
 

@@ -439,29 +439,45 @@ __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int3
 
 // Per HR pixel: mean of the synthesised patches covering it (patches in
 // row-major order); bicubic of the LR image where no patch covers it.
+__device__ __forceinline__ float blend_at(const float* __restrict__ xhat, const int32_t* __restrict__ m,
+                                         const float* __restrict__ lr, int h, int w, int s, int Y, int X) {
+    const int ps = kPatch * s, ps2 = ps * ps;
+    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
+    const int ilo = Y - ps + 1 <= 0 ? 0 : (Y - ps + s) / s;
+    const int ihi = min(npi - 1, Y / s);
+    const int jlo = X - ps + 1 <= 0 ? 0 : (X - ps + s) / s;
+    const int jhi = min(npj - 1, X / s);
+    float acc = 0.0f;
+    int cnt = 0;
+    for (int i = ilo; i <= ihi; ++i)
+        for (int j = jlo; j <= jhi; ++j) {
+            const int q = i * npj + j;
+            if (m[q] > 0) {
+                acc += xhat[(int64_t)q * ps2 + (Y - s * i) * ps + (X - s * j)];
+                ++cnt;
+            }
+        }
+    return cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
+}
+
 __global__ void k_blend(const float* __restrict__ xhat, const int32_t* __restrict__ m,
                         const float* __restrict__ lr, int h, int w, int s, float* __restrict__ hr) {
-    const int H = s * h, W = s * w, ps = kPatch * s, ps2 = ps * ps;
-    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
-    const int64_t total = (int64_t)H * W;
+    const int W = s * w;
+    const int64_t total = (int64_t)s * h * W;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        hr[idx] = blend_at(xhat, m, lr, h, w, s, (int)(idx / W), (int)(idx % W));
+}
+
+// Batched: every HR pixel of every image, into the image's output.
+__global__ void k_b_blend(const BatchImage* __restrict__ im, int n, int64_t total, int s,
+                          const float* __restrict__ xhat, const int32_t* __restrict__ m) {
+    const int ps2 = (kPatch * s) * (kPatch * s);
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int Y = (int)(idx / W), X = (int)(idx % W);
-        const int ilo = Y - ps + 1 <= 0 ? 0 : (Y - ps + s) / s;
-        const int ihi = min(npi - 1, Y / s);
-        const int jlo = X - ps + 1 <= 0 ? 0 : (X - ps + s) / s;
-        const int jhi = min(npj - 1, X / s);
-        float acc = 0.0f;
-        int cnt = 0;
-        for (int i = ilo; i <= ihi; ++i)
-            for (int j = jlo; j <= jhi; ++j) {
-                const int q = i * npj + j;
-                if (m[q] > 0) {
-                    acc += xhat[(int64_t)q * ps2 + (Y - s * i) * ps + (X - s * j)];
-                    ++cnt;
-                }
-            }
-        hr[idx] = cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
+        const BatchImage& b = im[batch_image_of<&BatchImage::hr_off>(im, n, idx)];
+        const int r = (int)(idx - b.hr_off), W = s * b.w;
+        b.out[r] = blend_at(xhat + b.q_off * ps2, m + b.q_off, b.lr, b.h, b.w, s, r / W, r % W);
     }
 }
 
@@ -516,6 +532,15 @@ hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, in
     int64_t g = (total + 255) / 256;
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_blend, dim3((unsigned)g), dim3(256), 0, st, xhat, m, lr, h, w, scale, hr);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_blend(const BatchImage* im, int n, int64_t hr_total, int scale, const float* xhat,
+                          const int32_t* m, hipStream_t st) {
+    if (hr_total == 0) return hipSuccess;
+    int64_t g = (hr_total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_b_blend, dim3((unsigned)g), dim3(256), 0, st, im, n, hr_total, scale, xhat, m);
     return hipGetLastError();
 }
 

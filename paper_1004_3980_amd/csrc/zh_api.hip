@@ -58,6 +58,21 @@ struct zh_ctx {
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
     double lam = 0.0;             // lambda of the last zh_lle_weights
+    // batched form: plan of the last batch, its captured graph, tuning
+    struct BatchGroup {
+        int n = 0;
+        int64_t q_total = 0, lr_total = 0, hr_total = 0, tiles = 0;
+        Buf table;                // device BatchImage[n]
+    };
+    struct Batch {
+        std::vector<uint64_t> sig;
+        BatchGroup g[4];          // by zoom factor
+        hipGraphExec_t exec = nullptr;
+        hipStream_t stream = nullptr;
+        hipEvent_t ev_in = nullptr, ev_out = nullptr;
+        int tile = 32, grid_per_cu = 4;
+        Buf scr, e, counter;
+    } batch;
     // back-projection record for zh_backward: 0 none, 1 one call kept, -1 more than one
     int bp_rec = 0, bp_iters = 0;
     float bp_sigma_s = 0.f, bp_sigma_r = 0.f;
@@ -330,6 +345,15 @@ void zh_destroy(zh_ctx* c) {
         for (int i = 0; i < zh_ctx::kEv; ++i)
             for (int j = 0; j < 2; ++j)
                 if (c->ev[st][i][j]) (void)hipEventDestroy(c->ev[st][i][j]);
+    if (c->batch.stream) (void)hipStreamSynchronize(c->batch.stream);
+    if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
+    if (c->batch.ev_in) (void)hipEventDestroy(c->batch.ev_in);
+    if (c->batch.ev_out) (void)hipEventDestroy(c->batch.ev_out);
+    if (c->batch.stream) (void)hipStreamDestroy(c->batch.stream);
+    for (auto& g : c->batch.g) release(c, g.table);
+    release(c, c->batch.scr);
+    release(c, c->batch.e);
+    release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
                    &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam};
@@ -853,6 +877,317 @@ zh_status zh_backward(zh_ctx* c, const float* g_hr, float* g_resid, float* g_lam
         HIPCHK(c, radix_sort_pairs(k0, v0, k1, v1, E, bits, hist, hsz, c->stream, &first));
         HIPCHK(c, launch_dict_grad(first ? k0 : k1, first ? v0 : v1, E, none, P<float>(c->w), gp, w, s, K, g_resid,
                                    c->stream));
+    }
+    return ZH_OK;
+}
+
+// ---- batched form -------------------------------------------------------------
+namespace {
+
+zh_status batch_check(zh_ctx* c, const zh_batch* b) {
+    if (!b || b->n_images < 1 || !b->lr || !b->hr_out || !b->h || !b->w || !b->scale)
+        return fail(c, ZH_EINVAL, "zh_run_batch: empty or incomplete batch");
+    if (b->K < 1 || b->K > kMaxK || !(b->lambda > 0.0) || !std::isfinite(b->lambda) || b->bp_iters < 0 ||
+        !(b->sigma_s > 0.f) || std::ceil(3.0 * b->sigma_s) > 8.0 || !(b->sigma_r > 0.f))
+        return fail(c, ZH_EINVAL, "zh_run_batch: bad K, lambda or back-projection parameters");
+    if (c->opts.rerank > 0 && c->opts.rerank < b->K) return fail(c, ZH_EINVAL, "zh_run_batch: rerank below K");
+    for (int i = 0; i < b->n_images; ++i) {
+        const int s = b->scale[i];
+        if (!b->lr[i] || !b->hr_out[i] || b->h[i] < kPatch || b->w[i] < kPatch)
+            return fail(c, ZH_EINVAL, "zh_run_batch: image %d: null pointer or side < 5", i);
+        if (s < 1 || s > 3 || !c->dicts[s].valid) return fail(c, ZH_ESTATE, "zh_run_batch: no tables for scale %d", s);
+    }
+    return ZH_OK;
+}
+
+std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
+    std::vector<uint64_t> v;
+    uint64_t lb;
+    std::memcpy(&lb, &b->lambda, 8);
+    uint32_t ss, sr;
+    std::memcpy(&ss, &b->sigma_s, 4);
+    std::memcpy(&sr, &b->sigma_r, 4);
+    v.insert(v.end(), {(uint64_t)b->n_images, (uint64_t)b->K, lb, (uint64_t)b->bp_iters, ss, sr,
+                       (uint64_t)c->opts.cap, (uint64_t)c->opts.rerank, (uint64_t)c->opts.proj,
+                       (uint64_t)c->opts.lle_fp64, (uint64_t)c->batch.tile, (uint64_t)c->batch.grid_per_cu,
+                       (uint64_t)(uintptr_t)c->stream});
+    for (int s = 1; s <= 3; ++s) v.push_back((uint64_t)(uintptr_t)c->dicts[s].dir.p);
+    for (int i = 0; i < b->n_images; ++i)
+        v.insert(v.end(), {(uint64_t)(uintptr_t)b->lr[i], (uint64_t)(uintptr_t)b->hr_out[i], (uint64_t)b->h[i],
+                           (uint64_t)b->w[i], (uint64_t)b->scale[i]});
+    return v;
+}
+
+// Image tables and every buffer the chain needs, sized before any capture.
+zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
+    auto& B = c->batch;
+    int64_t q_max = 0, lr_max = 0, hr_max = 0, ps2_max = 0, L_max = 0, k_max = 0, D_max = 0;
+    std::vector<BatchImage> tabs[4];
+    for (int s = 1; s <= 3; ++s) {
+        auto& g = B.g[s];
+        int64_t q = 0, lr = 0, hr = 0, tiles = 0;
+        for (int i = 0; i < b->n_images; ++i) {
+            if (b->scale[i] != s) continue;
+            BatchImage im{};
+            im.lr = b->lr[i];
+            im.out = b->hr_out[i];
+            im.h = b->h[i];
+            im.w = b->w[i];
+            im.lr_off = lr;
+            im.q_off = q;
+            im.hr_off = hr;
+            im.tile_off = tiles;
+            tabs[s].push_back(im);
+            lr += (int64_t)im.h * im.w;
+            q += (int64_t)(im.h - 4) * (im.w - 4);
+            hr += (int64_t)s * im.h * s * im.w;
+            tiles += bp_tiles(s * im.h, s * im.w, B.tile);
+        }
+        g.n = (int)tabs[s].size();
+        g.q_total = q;
+        g.lr_total = lr;
+        g.hr_total = hr;
+        g.tiles = tiles;
+        if (!g.n) continue;
+        if (q * kMaxK >= (1ll << 31)) return fail(c, ZH_EINVAL, "zh_run_batch: too many patches at scale %d", s);
+        const Dict& d = c->dicts[s];
+        q_max = std::max(q_max, q);
+        lr_max = std::max(lr_max, lr);
+        hr_max = std::max(hr_max, hr);
+        ps2_max = std::max<int64_t>(ps2_max, (kPatch * s) * (kPatch * s));
+        L_max = std::max<int64_t>(L_max, d.L);
+        k_max = std::max<int64_t>(k_max, d.k);
+        D_max = std::max<int64_t>(D_max, d.D);
+    }
+    // the groups run one after another and share the scratch
+    TRY(ensure(c, B.scr, sizeof(float) * (size_t)std::max<int64_t>(hr_max, 1)));
+    for (int s = 1; s <= 3; ++s) {
+        auto& g = B.g[s];
+        if (!g.n) continue;
+        for (auto& im : tabs[s]) im.scr = P<float>(B.scr) + im.hr_off;
+        TRY(ensure(c, g.table, sizeof(BatchImage) * tabs[s].size()));
+        HIPCHK(c, hipMemcpy(g.table.p, tabs[s].data(), sizeof(BatchImage) * tabs[s].size(), hipMemcpyHostToDevice));
+    }
+    const int64_t K = b->K;
+    TRY(ensure(c, B.e, sizeof(float) * (size_t)std::max<int64_t>(lr_max, 1)));
+    TRY(ensure(c, B.counter, 16));
+    TRY(ensure(c, c->maps, sizeof(float) * 4 * (size_t)std::max<int64_t>(lr_max, 1)));
+    TRY(ensure(c, c->qfeat, sizeof(float) * (size_t)q_max * D_max));
+    TRY(ensure(c, c->qmu, sizeof(double) * (size_t)q_max));
+    TRY(ensure(c, c->qkeys, sizeof(uint64_t) * (size_t)q_max * L_max));
+    TRY(ensure(c, c->qbins, sizeof(uint2) * (size_t)q_max * L_max));
+    TRY(ensure(c, c->ids, sizeof(int32_t) * (size_t)q_max * K));
+    TRY(ensure(c, c->d2, sizeof(float) * (size_t)q_max * K));
+    TRY(ensure(c, c->w, sizeof(float) * (size_t)q_max * K));
+    TRY(ensure(c, c->m, sizeof(int32_t) * (size_t)q_max));
+    TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)q_max));
+    TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)std::max<int64_t>(q_max, 1)));
+    TRY(ensure(c, c->over, sizeof(int32_t) * (size_t)q_max));
+    TRY(ensure(c, c->xhat, sizeof(float) * (size_t)q_max * ps2_max));
+    TRY(ensure(c, c->counters, kNumCounters * sizeof(uint32_t)));
+    if (K <= 8) TRY(ensure(c, c->gram, (c->opts.lle_fp64 ? 8 : 4) * (size_t)q_max * 36));
+    HashArgs ha{};
+    ha.n = q_max;
+    ha.L = (int)L_max;
+    ha.k = (int)k_max;
+    TRY(hash_scratch(c, ha));
+    return ZH_OK;
+}
+
+// The launch chain of a planned batch on stream st: nothing allocates.
+zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
+    auto& B = c->batch;
+    hipStream_t saved = c->stream;
+    const bool timing = c->timing;
+    c->stream = st;
+    c->timing = false;
+    zh_status rc = ZH_OK;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1) ncu = 256;
+    for (int s = 1; s <= 3 && rc == ZH_OK; ++s) {
+        auto& g = B.g[s];
+        if (!g.n) continue;
+        Dict& d = c->dicts[s];
+        const BatchImage* tab = P<BatchImage>(g.table);
+        const int K = b->K, ps2 = (kPatch * s) * (kPatch * s);
+        rc = [&]() -> zh_status {
+            c->Q = g.q_total;
+            c->qK = K;
+            c->qscale = s;
+            TRY(clear_counters(c));
+            if (d.mode == ZH_FEAT_GRAD4) HIPCHK(c, launch_b_gradient_maps(tab, g.n, g.lr_total, P<float>(c->maps), st));
+            HIPCHK(c, launch_b_query_features(tab, g.n, g.q_total, d.mode, P<float>(c->maps), P<float>(c->qfeat),
+                                              P<double>(c->qmu), st));
+            HashArgs ha{};
+            ha.feat = P<float>(c->qfeat);
+            ha.n = g.q_total;
+            ha.D = d.D;
+            ha.L = d.L;
+            ha.k = d.k;
+            ha.alpha = P<float>(d.alpha);
+            ha.a_hi = P<uint16_t>(d.ahi);
+            ha.a_lo = P<uint16_t>(d.alo);
+            ha.beta = P<float>(d.beta);
+            set_bounds(ha, d, c->opts.proj);
+            ha.w = d.w;
+            ha.prec = c->opts.proj;
+            ha.keys = P<uint64_t>(c->qkeys);
+            ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
+            TRY(hash_scratch(c, ha));
+            ha.dir = P<Slot>(d.dir);
+            ha.dir_cap = d.cap;
+            ha.bins = P<uint2>(c->qbins);
+            HIPCHK(c, launch_hash(ha, st));
+            TRY(run_search(c, d, nullptr, 0));
+            LleArgs la{};
+            la.Q = (int)g.q_total;
+            la.D = d.D;
+            la.K = K;
+            la.qfeat = P<float>(c->qfeat);
+            la.ids = P<int32_t>(c->ids);
+            la.m = P<int32_t>(c->m);
+            la.hi = P<uint16_t>(d.hi);
+            la.lo = P<uint16_t>(d.lo);
+            la.hs = hi_stride(d.D);
+            la.lam = b->lambda;
+            la.fp64 = c->opts.lle_fp64;
+            la.w = P<float>(c->w);
+            la.n_fp64 = P<unsigned int>(c->counters) + C_LLE64;
+            if (K <= 8) {
+                HIPCHK(c, launch_gram(la, c->gram.p, c->opts.lle_fp64, st));
+                HIPCHK(c, launch_lle_solve(la, c->gram.p, c->opts.lle_fp64, st));
+            } else {
+                HIPCHK(c, launch_lle(la, st));
+            }
+            HIPCHK(c, launch_synth((int)g.q_total, K, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
+                                   P<double>(c->qmu), d.resid, P<float>(c->xhat), st));
+            HIPCHK(c, launch_b_blend(tab, g.n, g.hr_total, s, P<float>(c->xhat), P<int32_t>(c->m), st));
+            const Taps tg = gauss_taps(1.0);
+            for (int t = 0; t < b->bp_iters; ++t) {
+                HIPCHK(c, launch_b_degrade_residual(tab, g.n, g.lr_total, s, tg, t & 1, P<float>(B.e), st));
+                HIPCHK(c, launch_b_bp_update(tab, g.n, g.tiles, B.tile, B.grid_per_cu * ncu, s, b->sigma_s, b->sigma_r,
+                                             P<float>(B.e), t & 1, P<unsigned int>(B.counter), st));
+            }
+            if (b->bp_iters & 1) HIPCHK(c, launch_b_copy_scr(tab, g.n, g.hr_total, s, st));
+            return ZH_OK;
+        }();
+    }
+    c->stream = saved;
+    c->timing = timing;
+    return rc;
+}
+
+zh_status batch_stream(zh_ctx* c) {
+    auto& B = c->batch;
+    if (!B.stream) {
+        HIPCHK(c, hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&B.ev_out, hipEventDisableTiming));
+    }
+    return ZH_OK;
+}
+
+}  // namespace
+
+zh_status zh_run_batch(zh_ctx* c, const zh_batch* b) {
+    if (!c) return ZH_EINVAL;
+    TRY(batch_check(c, b));
+    TRY(set_device(c));
+    TRY(batch_stream(c));
+    auto& B = c->batch;
+    c->stage = 0;
+    std::vector<uint64_t> sig = batch_signature(c, b);
+    if (sig != B.sig || !B.exec) {
+        if (B.exec) {
+            HIPCHK(c, hipStreamSynchronize(B.stream));
+            HIPCHK(c, hipGraphExecDestroy(B.exec));
+            B.exec = nullptr;
+        }
+        B.sig.clear();
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        TRY(batch_plan(c, b));
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(B.stream, hipStreamCaptureModeRelaxed));
+        const zh_status rc = batch_chain(c, b, B.stream);
+        const hipError_t ec = hipStreamEndCapture(B.stream, &graph);
+        if (rc != ZH_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        HIPCHK(c, ec);
+        const hipError_t ei = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(c, ei);
+        B.sig = std::move(sig);
+    }
+    HIPCHK(c, hipEventRecord(B.ev_in, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(B.stream, B.ev_in, 0));
+    HIPCHK(c, hipGraphLaunch(B.exec, B.stream));
+    HIPCHK(c, hipEventRecord(B.ev_out, B.stream));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, B.ev_out, 0));
+    return ZH_OK;
+}
+
+zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
+    if (!c) return ZH_EINVAL;
+    TRY(zh_run_batch(c, b));
+    auto& B = c->batch;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int tiles[2] = {16, 32}, mults[3] = {2, 4, 8};
+    float ms[6];
+    int best = -1;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1) ncu = 256;
+    const int keep_tile = B.tile, keep_mult = B.grid_per_cu;
+    zh_status rc = ZH_OK;
+    for (int ti = 0; ti < 2 && rc == ZH_OK; ++ti) {
+        B.tile = tiles[ti];
+        B.sig.clear();
+        rc = batch_plan(c, b);   // tile offsets of this tile size
+        for (int mi = 0; mi < 3 && rc == ZH_OK; ++mi) {
+            float bestrun = 1e30f;
+            for (int rep = 0; rep < 2 && rc == ZH_OK; ++rep) {
+                if (hipEventRecord(e0, B.stream) != hipSuccess) { rc = fail(c, ZH_EDEVICE, "event"); break; }
+                for (int s = 1; s <= 3; ++s) {
+                    auto& g = B.g[s];
+                    if (!g.n) continue;
+                    const BatchImage* tab = P<BatchImage>(g.table);
+                    if (launch_b_degrade_residual(tab, g.n, g.lr_total, s, gauss_taps(1.0), 0, P<float>(B.e), B.stream) !=
+                            hipSuccess ||
+                        launch_b_bp_update(tab, g.n, g.tiles, tiles[ti], mults[mi] * ncu, s, b->sigma_s, b->sigma_r,
+                                           P<float>(B.e), 0, P<unsigned int>(B.counter), B.stream) != hipSuccess) {
+                        rc = fail(c, ZH_EDEVICE, "zh_tune_batch: launch failed");
+                        break;
+                    }
+                }
+                (void)hipEventRecord(e1, B.stream);
+                (void)hipEventSynchronize(e1);
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                bestrun = std::min(bestrun, t);
+            }
+            ms[ti * 3 + mi] = bestrun;
+            if (best < 0 || bestrun < ms[best]) best = ti * 3 + mi;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ZH_OK || best < 0) {
+        B.tile = keep_tile;
+        B.grid_per_cu = keep_mult;
+        B.sig.clear();
+        return rc != ZH_OK ? rc : fail(c, ZH_EDEVICE, "zh_tune_batch: nothing timed");
+    }
+    B.tile = tiles[best / 3];
+    B.grid_per_cu = mults[best % 3];
+    B.sig.clear();   // re-plan and capture again with the chosen tuning
+    if (out) {
+        out->bp_tile = B.tile;
+        out->bp_grid_per_cu = B.grid_per_cu;
+        for (int i = 0; i < 6; ++i) out->bp_ms[i] = ms[i];
     }
     return ZH_OK;
 }

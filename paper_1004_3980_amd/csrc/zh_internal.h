@@ -149,6 +149,43 @@ hipError_t launch_bp_update(const float* I, const float* e, int H, int W, int h,
 hipError_t launch_bp_terms(const float* I, const float* e, int H, int W, int h, int w, int scale,
                            float sigma_s, float sigma_r, float* FSa, hipStream_t st);
 
+// ---- batched form: many LR images of one zoom factor ---------------------------
+// One entry per image. Offsets place each image in the concatenated index
+// spaces of the batch: LR pixels (gradient maps use 4x, the LR error 1x),
+// patches, HR pixels and back-projection tiles.
+struct BatchImage {
+    const float* lr;         // [h, w]
+    float* out;              // [s h, s w] result
+    float* scr;              // [s h, s w] back-projection scratch
+    int h, w;
+    int64_t lr_off, q_off, hr_off, tile_off;
+};
+// image of a concatenated index: the last entry whose offset field is <= i
+template <int64_t BatchImage::*F>
+__device__ __forceinline__ int batch_image_of(const BatchImage* im, int n, int64_t i) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (im[mid].*F <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+hipError_t launch_b_gradient_maps(const BatchImage* im, int n, int64_t lr_total, float* maps, hipStream_t st);
+hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t q_total, int mode, const float* maps,
+                                   float* feat, double* mu, hipStream_t st);
+hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int scale, const Taps& t,
+                                     int parity, float* e, hipStream_t st);
+hipError_t launch_b_blend(const BatchImage* im, int n, int64_t hr_total, int scale, const float* xhat,
+                          const int32_t* m, hipStream_t st);
+// one back-projection update over all tiles of the batch, persistent: `grid`
+// workgroups take tiles from the counter (zeroed here by a fill kernel);
+// parity 0 reads out and writes scr, parity 1 the reverse
+hipError_t launch_b_bp_update(const BatchImage* im, int n, int64_t n_tiles, int tile, int grid, int scale,
+                              float sigma_s, float sigma_r, const float* e, int parity, unsigned int* counter,
+                              hipStream_t st);
+hipError_t launch_b_copy_scr(const BatchImage* im, int n, int64_t hr_total, int scale, hipStream_t st);
+int bp_tiles(int H, int W, int tile);
+
 // ---- adjoint (k_backward.hip) -------------------------------------------------
 constexpr int kMaxAdjR = 8;
 enum { kAdjGauss = 0, kAdjBox = 1, kAdjUp = 2, kAdjDec = 3 };

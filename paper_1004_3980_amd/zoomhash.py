@@ -49,6 +49,18 @@ class zh_stats_t(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class zh_batch(ctypes.Structure):
+    _fields_ = [("n_images", ctypes.c_int32), ("lr", ctypes.POINTER(ctypes.c_void_p)),
+                ("hr_out", ctypes.POINTER(ctypes.c_void_p)), ("h", ctypes.POINTER(ctypes.c_int32)),
+                ("w", ctypes.POINTER(ctypes.c_int32)), ("scale", ctypes.POINTER(ctypes.c_int32)),
+                ("K", ctypes.c_int32), ("lam", ctypes.c_double), ("bp_iters", ctypes.c_int32),
+                ("sigma_s", ctypes.c_float), ("sigma_r", ctypes.c_float)]
+
+
+class zh_batch_tuning(ctypes.Structure):
+    _fields_ = [("bp_tile", ctypes.c_int32), ("bp_grid_per_cu", ctypes.c_int32), ("bp_ms", ctypes.c_float * 6)]
+
+
 _V, _I, _I64, _U64, _F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
 SIGNATURES = {
     "zh_create": [ctypes.POINTER(_V), _I, _V],
@@ -68,6 +80,8 @@ SIGNATURES = {
     "zh_reconstruct": [_V, _V],
     "zh_backproject": [_V, _V, _I, _F, _F],
     "zh_backward": [_V, _V, _V, _V],
+    "zh_run_batch": [_V, ctypes.POINTER(zh_batch)],
+    "zh_tune_batch": [_V, ctypes.POINTER(zh_batch), ctypes.POINTER(zh_batch_tuning)],
     "zh_get_results": [_V, _V, _V, _V, _V, _V],
     "zh_survivors": [_V, _V],
     "zh_query_shape": [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)],
@@ -194,6 +208,30 @@ class Context:
 
     def backward(self, g_hr, g_resid, g_lambda):
         self._chk(self.lib.zh_backward(self.h, _ptr(g_hr), _ptr(g_resid), _ptr(g_lambda)))
+
+    def _batch(self, lrs, outs, scales, K, lam, bp_iters, sigma_s, sigma_r):
+        n = len(lrs)
+        if not (n == len(outs) == len(scales)) or n == 0:
+            raise ValueError("lrs, outs and scales must be non-empty and of one length")
+        for t in list(lrs) + list(outs):
+            _ptr(t)
+        arrs = ((ctypes.c_void_p * n)(*[t.data_ptr() for t in lrs]),
+                (ctypes.c_void_p * n)(*[t.data_ptr() for t in outs]),
+                (ctypes.c_int32 * n)(*[t.shape[0] for t in lrs]),
+                (ctypes.c_int32 * n)(*[t.shape[1] for t in lrs]),
+                (ctypes.c_int32 * n)(*[int(s) for s in scales]))
+        return arrs, zh_batch(n, *arrs, K, lam, bp_iters, sigma_s, sigma_r)
+
+    def run_batch(self, lrs, outs, scales, K, lam, bp_iters, sigma_s, sigma_r):
+        """Zoom many LR images (device tensors [h, w]) into outs ([s h, s w])."""
+        keep, b = self._batch(lrs, outs, scales, K, lam, bp_iters, sigma_s, sigma_r)
+        self._chk(self.lib.zh_run_batch(self.h, ctypes.byref(b)))
+
+    def tune_batch(self, lrs, outs, scales, K, lam, bp_iters, sigma_s, sigma_r):
+        keep, b = self._batch(lrs, outs, scales, K, lam, bp_iters, sigma_s, sigma_r)
+        t = zh_batch_tuning()
+        self._chk(self.lib.zh_tune_batch(self.h, ctypes.byref(b), ctypes.byref(t)))
+        return {"bp_tile": t.bp_tile, "bp_grid_per_cu": t.bp_grid_per_cu, "bp_ms": list(t.bp_ms)}
 
     def get_results(self, ids=None, d2=None, m=None, w=None, ncand=None):
         self._chk(self.lib.zh_get_results(self.h, _ptr(ids), _ptr(d2), _ptr(m), _ptr(w), _ptr(ncand)))

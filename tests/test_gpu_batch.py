@@ -1,0 +1,119 @@
+"""Batched form (zh_run_batch): many LR images of uneven size at x2 and x3 in
+one captured launch chain. Bar: bit-exact against the same images run one
+by one through zh_query, zh_lle_weights, zh_reconstruct and
+zh_backproject (odd and even iteration counts, a one-patch image, graph
+replays, after autotuning), and an x3 image within 1e-5 of the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import synthdata
+from oracle import pipeline
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(20, 24, 2), (31, 17, 2), (9, 40, 2), (5, 5, 2), (25, 25, 3), (14, 30, 3), (12, 12, 3), (5, 9, 3)]
+WL2 = dict(dict_images=6, dict_hr=96, n_dict=8000, L=8, k=8, w=32.0, K=5, cap=40)
+WL3 = dict(dict_images=10, dict_hr=96, n_dict=6000, L=8, k=8, w=32.0, K=5, cap=40, scale=3)
+_state = {}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+def _setup():
+    if _state:
+        return _state
+    torch = _torch()
+    from paper_1004_3980_amd import zoomhash as zb
+    from paper_1004_3980_amd.pipeline import GpuWorkload
+    ctx = zb.Context(0)
+    wl2 = synthdata.scaled(synthdata.WORKLOADS["mid"], **WL2)
+    wl3 = synthdata.scaled(synthdata.WORKLOADS["mid"], **WL3)
+    g2 = GpuWorkload(wl2, ctx=ctx)
+    g3 = GpuWorkload(wl3, ctx=ctx)
+    ctx.set_query_opts(cap=40, rerank=0, proj=1, lle_fp64=1)
+    lrs = [torch.from_numpy(synthdata.fractal_voronoi_image(synthdata.SEED_BASE + 7000 + i, h, w)).cuda()
+           for i, (h, w, s) in enumerate(SIZES)]
+    _state.update(ctx=ctx, g2=g2, g3=g3, wl2=wl2, wl3=wl3, lrs=lrs, torch=torch)
+    return _state
+
+
+def _one_by_one(st, iters, K, lam, ss, sr):
+    torch, ctx = st["torch"], st["ctx"]
+    outs = []
+    for lr, (h, w, s) in zip(st["lrs"], SIZES):
+        out = torch.empty((s * h, s * w), dtype=torch.float32, device="cuda")
+        ctx.query(lr, h, w, s, K)
+        ctx.lle_weights(lam)
+        ctx.reconstruct(out)
+        ctx.backproject(out, iters, ss, sr)
+        outs.append(out)
+    ctx.sync()
+    return outs
+
+
+def _batch(st, iters, K, lam, ss, sr, tune=False):
+    torch, ctx = st["torch"], st["ctx"]
+    outs = [torch.full((s * h, s * w), -1.0, dtype=torch.float32, device="cuda") for h, w, s in SIZES]
+    args = (st["lrs"], outs, [s for _, _, s in SIZES], K, lam, iters, ss, sr)
+    info = ctx.tune_batch(*args) if tune else None
+    for o in outs:
+        o.fill_(-1.0)
+    ctx.run_batch(*args)
+    ctx.sync()
+    return outs, info
+
+
+@pytest.mark.parametrize("iters", [0, 1, 2])
+def test_batch_equals_image_by_image(iters):
+    st = _setup()
+    torch = st["torch"]
+    ref = _one_by_one(st, iters, 5, 1e-3, 1.5, 0.1)
+    got, _ = _batch(st, iters, 5, 1e-3, 1.5, 0.1)
+    for r, g, sz in zip(ref, got, SIZES):
+        assert torch.equal(r, g), sz
+    # the captured graph replayed
+    got2, _ = _batch(st, iters, 5, 1e-3, 1.5, 0.1)
+    for r, g in zip(ref, got2):
+        assert torch.equal(r, g)
+
+
+def test_batch_after_autotuning():
+    st = _setup()
+    torch = st["torch"]
+    ref = _one_by_one(st, 3, 5, 1e-3, 1.5, 0.1)
+    got, info = _batch(st, 3, 5, 1e-3, 1.5, 0.1, tune=True)
+    assert info["bp_tile"] in (16, 32) and info["bp_grid_per_cu"] in (2, 4, 8)
+    assert all(t > 0 for t in info["bp_ms"])
+    for r, g in zip(ref, got):
+        assert torch.equal(r, g)
+
+
+def test_batch_x3_image_against_oracle():
+    st = _setup()
+    wl3 = st["wl3"]
+    got, _ = _batch(st, 2, 5, 1e-3, 1.5, 0.1)
+    pre = pipeline.prepare(wl3.dictionary_images(), wl3.positions(), 3, wl3.feat_mode, wl3.L, wl3.k, wl3.w,
+                           wl3.hash_seed)
+    i = SIZES.index((14, 30, 3))
+    lr = st["lrs"][i].cpu().numpy()
+    _, _, hr_bp = pipeline.run(pre, lr, 3, 5, 1e-3, 2, 1.5, 0.1, cap=40)
+    assert np.abs(got[i].cpu().numpy() - hr_bp).max() <= 1e-5
+
+
+def test_batch_argument_errors():
+    st = _setup()
+    torch = st["torch"]
+    from paper_1004_3980_amd import zoomhash as zb
+    lr = st["lrs"][0]
+    out = torch.empty((2 * lr.shape[0], 2 * lr.shape[1]), device="cuda")
+    with pytest.raises(zb.ZHError):
+        st["ctx"].run_batch([lr], [out], [1], 5, 1e-3, 1, 1.5, 0.1)     # no tables at x1
+    with pytest.raises(zb.ZHError):
+        st["ctx"].run_batch([lr], [out], [2], 0, 1e-3, 1, 1.5, 0.1)     # K = 0
+    with pytest.raises(ValueError):
+        st["ctx"].run_batch([lr], [], [2], 5, 1e-3, 1, 1.5, 0.1)
