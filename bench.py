@@ -101,7 +101,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="precision")
-    ap.add_argument("--form", choices=["screened", "exact"], default="screened")
+    ap.add_argument("--form", choices=["screened", "exact", "batched", "diff"], default="screened",
+                    help="screened/exact: the 1024^2 workload (the headline line); batched: 64 images "
+                         "at x2/x3 in one captured graph against per-image launches; diff: forward and "
+                         "backward of the differentiation workload")
     ap.add_argument("--crop", type=int, default=256, help="LR crop side for quality and the CPU leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
@@ -121,6 +124,10 @@ def main():
     from paper_1004_3980_amd.pipeline import GpuWorkload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.form == "batched":
+        return bench_batched(args)
+    if args.form == "diff":
+        return bench_diff(args)
     wl = synthdata.WORKLOADS[args.workload]
     log(f"[bench] building {wl.name}: {wl.n_dict} pairs, LR {wl.test_h}x{wl.test_w} x{wl.scale}")
     t0 = time.perf_counter()
@@ -267,6 +274,125 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["extra"]["copy_probe_bytes"] = n * 4
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """64 LR images (sides 96..1024, aspect 0.5..2; 32 at x2, 32 at x3) against
+    1M-pair dictionaries per zoom factor, screened form, 3 back-projection
+    iterations: zh_run_batch (one captured graph, autotuned) against the same
+    images launched one by one."""
+    import torch
+    import synthdata
+    from paper_1004_3980_amd import zoomhash as zb
+    from paper_1004_3980_amd.pipeline import GpuWorkload
+    ctx = zb.Context(0)
+    t0 = time.perf_counter()
+    dicts = {s: GpuWorkload(synthdata.BATCHED[s], ctx=ctx) for s in (2, 3)}
+    wl = synthdata.BATCHED[2]
+    ctx.set_query_opts(cap=wl.cap, rerank=wl.rerank, proj=1, lle_fp64=0)
+    imgs = synthdata.batched_images()
+    lrs = [torch.from_numpy(im).cuda() for im, _ in imgs]
+    scales = [s for _, s in imgs]
+    outs = [torch.empty((s * l.shape[0], s * l.shape[1]), device="cuda") for l, s in zip(lrs, scales)]
+    ref = [torch.empty_like(o) for o in outs]
+    torch.cuda.synchronize()
+    log(f"[bench] batched: dictionaries and {len(imgs)} images ready in {time.perf_counter() - t0:.1f} s")
+    Q = sum((l.shape[0] - 4) * (l.shape[1] - 4) for l in lrs)
+    args_b = (lrs, outs, scales, wl.K, wl.lam, wl.bp_iters, wl.sigma_s, wl.sigma_r)
+
+    def per_image(dst):
+        for l, o, s in zip(lrs, dst, scales):
+            ctx.query(l, l.shape[0], l.shape[1], s, wl.K)
+            ctx.lle_weights(wl.lam)
+            ctx.reconstruct(o)
+            ctx.backproject(o, wl.bp_iters, wl.sigma_s, wl.sigma_r)
+
+    steps, warm = max(1, args.steps // 2), max(1, args.warmup)
+    for _ in range(warm):
+        per_image(ref)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per_image(ref)
+    torch.cuda.synchronize()
+    t_img = (time.perf_counter() - t0) / steps
+    tuning = ctx.tune_batch(*args_b)
+    for _ in range(warm):
+        ctx.run_batch(*args_b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run_batch(*args_b)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    same = all(torch.equal(a, b) for a, b in zip(outs, ref))
+    out = {"metric": "LR patches/s, batched form (64 images x2/x3, 1M-pair dictionaries, "
+                     "hash+KNN+LLE+blend+3 BP iterations)",
+           "value": Q / t_b, "unit": "LR patches/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+           "ms_per_step": 1e3 * t_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16/fp32", "data": "synthetic",
+           "config": {"workload": "batched: 64 LR images, sides U{96..1024}, aspect 0.5-2, 32 at x2 and 32 "
+                                  "at x3, one 1,000,000-pair dictionary per zoom factor, L=24 k=20 w=32 K=8, "
+                                  "early stop 72, screened form (R=32), 3 back-projection iterations",
+                      "patches_per_step": Q, "parallelism": "single GPU"},
+           "extra": {"per_image_launches": {"value": Q / t_img, "ms_per_step": 1e3 * t_img},
+                     "speedup_vs_per_image": t_img / t_b, "outputs_equal_per_image": same,
+                     "tuning": tuning}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_diff(args):
+    """Differentiation workload: 8 HR images 512^2 degraded to 256^2 LR (x2),
+    200,000-pair fp32 dictionary, K = 5, 3 back-projection iterations;
+    forward (query, weights, reconstruction, back-projection) and zh_backward
+    of the MSE to the HR ground truth, per image."""
+    import torch
+    import synthdata
+    from paper_1004_3980_amd.pipeline import GpuWorkload
+    wl = synthdata.WORKLOADS["diff"]
+    g = GpuWorkload(wl)
+    g.set_mode(cap=0, rerank=0, proj=1, lle_fp64=1)
+    imgs = []
+    for i in range(8):
+        gt = torch.from_numpy(synthdata.fractal_voronoi_image(wl.seed_test + i, 2 * wl.test_h,
+                                                              2 * wl.test_w)).cuda()
+        lr = torch.empty((wl.test_h, wl.test_w), device="cuda")
+        g.ctx.degrade(gt, 1, gt.shape[0], gt.shape[1], wl.scale, wl.blur_sigma, lr)
+        imgs.append((gt, lr))
+    g_resid = torch.empty_like(g.resid)
+    g_lam = torch.empty(1, device="cuda")
+    acc = torch.zeros_like(g.resid)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_f = t_b = 0.0
+    steps, warm = max(1, args.steps // 2), max(1, args.warmup)
+    for it in range(warm + steps):
+        for gt, lr in imgs:
+            ev[0].record()
+            out = g.forward_record(lr, wl.lam)
+            ev[1].record()
+            gout = (2.0 / gt.numel()) * (out - gt)
+            g.ctx.backward(gout, g_resid, g_lam)
+            ev[2].record()
+            acc += g_resid
+            torch.cuda.synchronize()
+            if it >= warm:
+                t_f += ev[0].elapsed_time(ev[1])
+                t_b += ev[1].elapsed_time(ev[2])
+    Q = 8 * (wl.test_h - 4) * (wl.test_w - 4)
+    t_f /= steps
+    t_b /= steps
+    out = {"metric": "LR patches/s, forward + backward (differentiation form)",
+           "value": Q / ((t_f + t_b) * 1e-3), "unit": "LR patches/s", "n_gpus": 1, "steps": steps,
+           "warmup": warm, "ms_per_step": t_f + t_b, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32 (FP64 LLE)", "data": "synthetic",
+           "config": {"workload": "diff: 8 HR 512^2 images degraded to 256^2 LR x2, 200,000-pair fp32 "
+                                  "dictionary, L=16 k=16 w=4 K=5, 3 back-projection iterations, MSE to the HR "
+                                  "ground truth; gradients for the residual patches and lambda",
+                      "patches_per_step": Q, "parallelism": "single GPU"},
+           "extra": {"forward_ms_8_images": t_f, "backward_ms_8_images": t_b,
+                     "grad_lambda_last": float(g_lam.item()),
+                     "grad_resid_rows_touched": int((acc.abs().sum(1) > 0).sum().item())}}
     print(json.dumps(out), flush=True)
 
 

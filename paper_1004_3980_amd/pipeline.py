@@ -42,6 +42,9 @@ class GpuWorkload:
         self.ctx.build_tables(self.feat, self.resid, n, self.D, s, wl.feat_mode, wl.L, wl.k,
                               wl.w, wl.hash_seed)
         self.n = n
+        if wl.test_h == 0:        # dictionary only
+            self.hr_gt = self.lr = self.hr_out = None
+            return
         img = torch.from_numpy(wl.test_image()).to(self.dev)
         if wl.test_lr_direct:
             self.hr_gt = None

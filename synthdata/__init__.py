@@ -176,6 +176,24 @@ def scaled(wl: Workload, **kw) -> Workload:
     return dataclasses.replace(wl, **kw)
 
 
+# dictionaries of the batched workload: 1M pairs per zoom factor from 64
+# seeded 512^2 HR images each; method parameters as the precision workload
+BATCHED = {
+    s: Workload(f"batched_x{s}", 0, 0, s, 1, 64, 512, 1_000_000, L=24, k=20, w=32.0, K=8, cap=72, lam=1e-3,
+                bp_iters=3, sigma_s=1.5, sigma_r=0.1, test_lr_direct=True, seed_test=B + 4,
+                seed_dict_images=B + 700 + 100 * s, seed_positions=B + 750 + 100 * s, hash_seed=10 + s,
+                rerank=32, feat_bf16=True)
+    for s in (2, 3)
+}
+
+
+def batched_images(seed: int = B + 4, count: int = 64):
+    """The LR images of the batched workload (drawn directly at LR) with their
+    zoom factors: a list of (image float32 [h, w], scale)."""
+    return [(fractal_voronoi_image(seed + 1000 + i, h, w), s)
+            for i, (h, w, s) in enumerate(batched_sizes(seed, count))]
+
+
 def batched_sizes(seed: int = B + 4, count: int = 64):
     """Image sizes of the batched workload: side a ~ U{96..1024}, aspect
     rho ~ log-uniform[0.5, 2], b = clamp(round(a*rho), 96, 1024); the first
