@@ -352,7 +352,7 @@ def bench_diff(args):
     from paper_1004_3980_amd.pipeline import GpuWorkload
     wl = synthdata.WORKLOADS["diff"]
     g = GpuWorkload(wl)
-    g.set_mode(cap=0, rerank=0, proj=1, lle_fp64=1)
+    g.set_mode(cap=wl.cap, rerank=0, proj=1, lle_fp64=1)
     imgs = []
     for i in range(8):
         gt = torch.from_numpy(synthdata.fractal_voronoi_image(wl.seed_test + i, 2 * wl.test_h,
@@ -387,10 +387,11 @@ def bench_diff(args):
            "warmup": warm, "ms_per_step": t_f + t_b, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "fp32 (FP64 LLE)", "data": "synthetic",
            "config": {"workload": "diff: 8 HR 512^2 images degraded to 256^2 LR x2, 200,000-pair fp32 "
-                                  "dictionary, L=16 k=16 w=4 K=5, 3 back-projection iterations, MSE to the HR "
+                                  "dictionary, L=16 k=16 w=32 K=5, early stop 48, 3 back-projection iterations, MSE to the HR "
                                   "ground truth; gradients for the residual patches and lambda",
                       "patches_per_step": Q, "parallelism": "single GPU"},
            "extra": {"forward_ms_8_images": t_f, "backward_ms_8_images": t_b,
+                     "patches_without_neighbours_last": int((g.results()["m"] == 0).sum()),
                      "grad_lambda_last": float(g_lam.item()),
                      "grad_resid_rows_touched": int((acc.abs().sum(1) > 0).sum().item())}}
     print(json.dumps(out), flush=True)

@@ -163,11 +163,12 @@ WORKLOADS = {
                           w=32.0, K=8, cap=72, lam=1e-3, bp_iters=3, sigma_s=1.5, sigma_r=0.1,
                           test_lr_direct=False, seed_test=B + 3, seed_dict_images=B + 500,
                           seed_positions=B + 600, hash_seed=3, rerank=32, feat_bf16=True),
-    # one batch image of the differentiation workload; 200k fp32 pairs
-    "diff": Workload("diff", 256, 256, 2, 1, 64, 512, 200_000, L=16, k=16, w=4.0, K=5,
+    # one batch image of the differentiation workload; 200k fp32 pairs (w and
+    # the early stop at 3L chosen as for the 1024^2 workload)
+    "diff": Workload("diff", 256, 256, 2, 1, 64, 512, 200_000, L=16, k=16, w=32.0, K=5,
                      lam=1e-3, bp_iters=3, sigma_s=1.5, sigma_r=0.1, test_lr_direct=False,
                      seed_test=B + 1000, seed_dict_images=B + 1100, seed_positions=B + 1150,
-                     hash_seed=4),
+                     hash_seed=4, cap=48),
 }
 
 
