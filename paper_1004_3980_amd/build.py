@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libzoomhash.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("ZH_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["zh_api.hip", "k_image.hip", "k_hash.hip", "k_table.hip", "k_search.hip",
+SOURCES = ["zh_api.hip", "k_image.hip", "k_hash.hip", "k_table.hip", "k_search.hip", "k_screen.hip",
            "k_lle.hip", "k_bp.hip", "k_backward.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

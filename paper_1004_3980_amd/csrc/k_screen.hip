@@ -1,0 +1,325 @@
+// Screen plane of the dictionary and rotated query coordinates for the
+// search's pre-filter (Section 4.2: the similarity checks of the candidates
+// are the costly part of the search).
+//
+// The pre-filter only has to discard candidates that are certainly farther
+// than K others. It reads, per candidate, one row of the screen plane: the
+// coordinates y = Phi x of the feature vector in m = min(D, 60) orthonormal
+// directions, stored in bf16, with |y~|^2 and rho_x >= |Phi x - y~| in the
+// row's tail (128 bytes at D = 100, one memory line). Phi holds the leading
+// principal directions of the dictionary's features: the 4-channel gradient
+// features of a 5x5 patch are linear in the 65 pixels of a 9x9 cross minus
+// their mean, so they span at most 64 dimensions and 60 of them hold all but
+// a few 1e-4 of the energy.
+//
+// For any matrix Phi with largest singular value sigma,
+//   |q - x| >= |Phi (q - x)| / sigma >= (|y_q - y~_x| - rho_q - rho_x) / sigma,
+// where y_q approximates Phi q within rho_q. This lower bound is all the
+// search takes from the screen; upper bounds come from exact distances.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "zh_internal.h"
+
+namespace zh {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// ---- covariance of a row sample --------------------------------------------
+// Block b sums x_r x_r^T (FP64) over its share of the sample rows
+// r_i = floor(i n / ns); thread t owns entries t, t + 1024, ... of the D x D
+// matrix. A second kernel adds the block partials in block order.
+constexpr int kCovThreads = 1024;
+constexpr int kCovBlocks = 128;
+
+__global__ __launch_bounds__(kCovThreads) void k_cov_partial(const float* __restrict__ x, int64_t n, int D,
+                                                             int64_t ns, double* __restrict__ part) {
+    __shared__ float row[128];
+    const int t = threadIdx.x;
+    const int DD = D * D;
+    constexpr int E = 128 * 128 / kCovThreads;
+    double acc[E];
+    int ri[E], ci[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        acc[e] = 0.0;
+        const int idx = t + kCovThreads * e;
+        ri[e] = idx < DD ? idx / D : 0;
+        ci[e] = idx < DD ? idx - (idx / D) * D : 0;
+    }
+    const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * per;
+    const int64_t i1 = i0 + per < ns ? i0 + per : ns;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t r = i * n / ns;   // i < ns <= 2^16 and n < 2^31: no overflow
+        __syncthreads();
+        if (t < D) row[t] = x[r * D + t];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (t + kCovThreads * e < DD) acc[e] += (double)row[ri[e]] * (double)row[ci[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int idx = t + kCovThreads * e;
+        if (idx < DD) part[(int64_t)blockIdx.x * DD + idx] = acc[e];
+    }
+}
+
+__global__ void k_cov_sum(const double* __restrict__ part, int nblk, int DD, double* __restrict__ cov) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= DD) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * DD + e];
+    cov[e] = s;
+}
+
+hipError_t launch_cov(const float* x, int64_t n, int D, int64_t ns, double* part, double* cov, hipStream_t st) {
+    if (D < 1 || D > 128 || ns < 1 || ns > n || ns > 65536) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cov_partial, dim3(kCovBlocks), dim3(kCovThreads), 0, st, x, n, D, ns, part);
+    const int DD = D * D;
+    hipLaunchKernelGGL(k_cov_sum, dim3((DD + 255) / 256), dim3(256), 0, st, part, kCovBlocks, DD, cov);
+    return hipGetLastError();
+}
+
+// ---- principal directions (host) -------------------------------------------
+// Cyclic Jacobi eigenvalue iteration on the symmetric D x D matrix C (FP64);
+// the m eigenvectors of the largest eigenvalues (ties by index) become the
+// rows of Phi (fp32, unit length). Returns an upper bound on the largest
+// eigenvalue of Phi Phi^T (Gershgorin, FP64 sums of exact products), i.e. on
+// sigma^2.
+double screen_basis(const double* C, int D, int m, float* phi) {
+    std::vector<double> A(C, C + (size_t)D * D), V((size_t)D * D, 0.0);
+    for (int i = 0; i < D; ++i) V[(size_t)i * D + i] = 1.0;
+    for (int i = 0; i < D; ++i)
+        for (int j = i + 1; j < D; ++j) {
+            const double s = 0.5 * (A[(size_t)i * D + j] + A[(size_t)j * D + i]);
+            A[(size_t)i * D + j] = A[(size_t)j * D + i] = s;
+        }
+    double diag2 = 0.0;
+    for (int i = 0; i < D; ++i) diag2 += A[(size_t)i * D + i] * A[(size_t)i * D + i];
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < D; ++p)
+            for (int q = p + 1; q < D; ++q) off += A[(size_t)p * D + q] * A[(size_t)p * D + q];
+        if (off <= 1e-30 * diag2) break;
+        for (int p = 0; p < D; ++p) {
+            for (int q = p + 1; q < D; ++q) {
+                const double apq = A[(size_t)p * D + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * D + p], aqq = A[(size_t)q * D + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                double t;
+                if (std::fabs(theta) > 1e150)
+                    t = 0.5 / theta;
+                else
+                    t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < D; ++k) {
+                    const double akp = A[(size_t)k * D + p], akq = A[(size_t)k * D + q];
+                    A[(size_t)k * D + p] = c * akp - s * akq;
+                    A[(size_t)k * D + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < D; ++k) {
+                    const double apk = A[(size_t)p * D + k], aqk = A[(size_t)q * D + k];
+                    A[(size_t)p * D + k] = c * apk - s * aqk;
+                    A[(size_t)q * D + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < D; ++k) {
+                    const double vkp = V[(size_t)k * D + p], vkq = V[(size_t)k * D + q];
+                    V[(size_t)k * D + p] = c * vkp - s * vkq;
+                    V[(size_t)k * D + q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    std::vector<int> order(D);
+    for (int i = 0; i < D; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return A[(size_t)a * D + a] > A[(size_t)b * D + b]; });
+    for (int j = 0; j < m; ++j) {
+        const int col = order[j];
+        double nrm = 0.0;
+        for (int i = 0; i < D; ++i) nrm += V[(size_t)i * D + col] * V[(size_t)i * D + col];
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < D; ++i) phi[(size_t)j * D + i] = (float)(V[(size_t)i * D + col] / nrm);
+    }
+    double lmax = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double row = 0.0;
+        for (int j = 0; j < m; ++j) {
+            double g = 0.0;
+            for (int k = 0; k < D; ++k) g += (double)phi[(size_t)i * D + k] * (double)phi[(size_t)j * D + k];
+            row += std::fabs(g);
+        }
+        lmax = std::max(lmax, row);
+    }
+    // FP64 rounding of the Gram sums is below 1e-13 of each entry
+    return lmax * (1.0 + 1e-12) + 1e-14;
+}
+
+// Bound coefficient of the split-bf16 MFMA projection of a query onto Phi:
+// |y~_j - (Phi q)_j| <= c * S_abs_j with S_abs_j the MFMA value of
+// sum_i |phi_ji,hi| |q_i,hi| (the same error model as the hash projection at
+// w = 1 and beta = 0: accumulation, the dropped low x low products and the
+// split residuals, every term doubled).
+float rotate_bound_coeff(int D) {
+    const double u = 1.0 / 16777216.0;
+    const int DP = (D + 31) & ~31;
+    const double e_rel = gamma_n(2 * 3 * DP, u) * 1.016 + 3.5 / 65536.0;
+    const double t = 1.0 - 1.0 / 256.0;
+    const double c_abs = 1.0 / (t * t * (1.0 - gamma_n(2 * DP, u)));
+    return (float)(2.0 * e_rel * c_abs * (1.0 + 1e-6));
+}
+
+// ---- screen rows of the dictionary -----------------------------------------
+// One wave per row: lane j < m forms y_j = sum_i phi_ji x_i in FP64 (phi^T in
+// LDS), rounds it to bf16 and the wave adds (y~_j - y_j)^2 and y~_j^2. The
+// FP64 sum itself is within D 2^-53 sum_i |phi_ji x_i| <= 1e-13 |x|_1 of the
+// exact product, which is added to rho_x.
+__global__ __launch_bounds__(256) void k_screen_rows(const float* __restrict__ x, int64_t n, int D, int m,
+                                                     const double* __restrict__ phiT, uint16_t* __restrict__ sc) {
+    extern __shared__ double sphi[];   // [D][64]
+    __shared__ double sx[4][128];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = threadIdx.x; e < D * 64; e += 256) sphi[e] = phiT[e];
+    __syncthreads();
+    const int TS = screen_tail(D), SS = screen_stride(D);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < n; r += nw) {
+        double l1 = 0.0;
+        for (int i = lane; i < 128; i += 64) {
+            const double v = i < D ? (double)x[r * D + i] : 0.0;
+            sx[wave][i] = v;
+            l1 += fabs(v);
+        }
+        l1 = wave_sum_f64(l1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double y = 0.0;
+        for (int i = 0; i < D; ++i) y += sphi[i * 64 + lane] * sx[wave][i];
+        const uint16_t h = lane < m ? bf16_rne((float)y) : (uint16_t)0;
+        const double yt = (double)bf16_to_f(h);
+        const double err = lane < m ? yt - y : 0.0;
+        const double rho2 = wave_sum_f64(err * err);
+        const double n2 = wave_sum_f64(yt * yt);
+        const double rho = sqrt(rho2) * (1.0 + 1e-12) + 1e-13 * l1 + 1e-300;
+        float rf = (float)rho;
+        if ((double)rf < rho) rf = __uint_as_float(__float_as_uint(rf) + 1u);
+        const float nf = (float)n2;
+        uint16_t v = h;
+        if (lane >= TS && lane < TS + 4) {
+            const uint32_t bits = __float_as_uint(lane < TS + 2 ? nf : rf);
+            v = (lane & 1) == (TS & 1) ? (uint16_t)(bits & 0xFFFFu) : (uint16_t)(bits >> 16);
+        }
+        if (lane < SS) sc[r * SS + lane] = v;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+hipError_t launch_screen_rows(const float* x, int64_t n, int D, int m, const double* phiT, uint16_t* sc,
+                              hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (D < 1 || D > 128 || m < 1 || m > kScreenMax || m > D) return hipErrorInvalidValue;
+    const int64_t blocks = std::min<int64_t>((n + 3) / 4, 4096);
+    hipLaunchKernelGGL(k_screen_rows, dim3((unsigned)blocks), dim3(256), sizeof(double) * D * 64, st, x, n, D, m,
+                       phiT, sc);
+    return hipGetLastError();
+}
+
+// ---- rotated query coordinates ----------------------------------------------
+// y_q = Phi q for every query row, on the matrix cores: Phi (64 rows, rows
+// >= m zero) split into bf16 high and low parts and staged once per
+// workgroup in LDS, the feature rows split likewise in registers; three
+// products (hi.hi, hi.lo, lo.hi) and a fourth of the absolute high parts for
+// the error bound. One wave takes 16 rows at a time. Output row (64 floats):
+// y_0 .. y_{m-1}, zeros, and in the last slot rho_q >= |y_q - Phi q|.
+template <int NS>
+__global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ feat, int64_t n, int D,
+                                                const uint16_t* __restrict__ p_hi, const uint16_t* __restrict__ p_lo,
+                                                float c1, float* __restrict__ out) {
+    constexpr int DS = 32 * NS + 8;   // LDS row stride (halfwords): an odd number of 16-byte chunks
+    __shared__ __align__(16) uint16_t sA[2][64 * DS];
+    const int DP = 32 * NS;
+    for (int e = threadIdx.x; e < 2 * 64 * (DP / 8); e += 256) {
+        const int plane = e >= 64 * (DP / 8);
+        const int e2 = e - plane * 64 * (DP / 8);
+        const int r = e2 / (DP / 8), ch = e2 - r * (DP / 8);
+        *reinterpret_cast<u16x8*>(&sA[plane][r * DS + 8 * ch]) =
+            *reinterpret_cast<const u16x8*>((plane ? p_lo : p_hi) + (int64_t)r * DP + 8 * ch);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ri = lane & 15, kb = lane >> 4;
+    const u16x8 am = {0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF};
+    const int64_t nblk = (n + 15) / 16;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + wave; b < nblk; b += (int64_t)gridDim.x * 4) {
+        const int64_t row = b * 16 + ri;
+        const bool rowok = row < n;
+        u16x8 bh[NS], bl[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int d = 32 * s + 8 * kb + e;
+                const float v = (rowok && d < D) ? feat[row * D + d] : 0.0f;
+                const uint16_t h = bf16_rne(v);
+                bh[s][e] = h;
+                bl[s][e] = bf16_rne(v - bf16_to_f(h));
+            }
+        }
+        float b2 = 0.0f;
+#pragma unroll 1
+        for (int tt = 0; tt < 4; ++tt) {
+            f32x4 cs = f32x4{0.f, 0.f, 0.f, 0.f}, chl = cs, clh = cs, cab = cs;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const u16x8 ah = *reinterpret_cast<const u16x8*>(&sA[0][(tt * 16 + ri) * DS + 32 * s + 8 * kb]);
+                const u16x8 al = *reinterpret_cast<const u16x8*>(&sA[1][(tt * 16 + ri) * DS + 32 * s + 8 * kb]);
+                const bf16x8 ahb = __builtin_bit_cast(bf16x8, ah), alb = __builtin_bit_cast(bf16x8, al);
+                const bf16x8 vhb = __builtin_bit_cast(bf16x8, bh[s]), vlb = __builtin_bit_cast(bf16x8, bl[s]);
+                cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vhb, cs, 0, 0, 0);
+                chl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, chl, 0, 0, 0);
+                clh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, clh, 0, 0, 0);
+                cab = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah & am),
+                                                             __builtin_bit_cast(bf16x8, bh[s] & am), cab, 0, 0, 0);
+            }
+            cs = cs + (chl + clh);
+            // lane holds y_j, j = 16 tt + 4 kb + i, of feature row ri
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float bnd = fmaf(c1, cab[i], 1e-30f);
+                b2 = fmaf(bnd, bnd, b2);
+            }
+            if (rowok) *reinterpret_cast<float4*>(out + row * 64 + 16 * tt + 4 * kb) = make_float4(cs[0], cs[1], cs[2], cs[3]);
+        }
+        b2 += __shfl_xor(b2, 16);
+        b2 += __shfl_xor(b2, 32);
+        // at most 64 terms of fp32 sums: relative error below 1e-5
+        const float rho = sqrtf(b2 * (1.0f + 1e-5f)) * (1.0f + 1e-6f);
+        if (rowok && kb == 3) out[row * 64 + 63] = rho;
+    }
+}
+
+hipError_t launch_rotate(const float* feat, int64_t n, int D, const uint16_t* p_hi, const uint16_t* p_lo, float c1,
+                         float* out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (D < 1 || D > 128) return hipErrorInvalidValue;
+    const int64_t nblk = (n + 15) / 16;
+    const int blocks = (int)std::min<int64_t>((nblk + 3) / 4, 2048);
+    switch ((D + 31) / 32) {
+        case 1: hipLaunchKernelGGL(k_rotate<1>, dim3(blocks), dim3(256), 0, st, feat, n, D, p_hi, p_lo, c1, out); break;
+        case 2: hipLaunchKernelGGL(k_rotate<2>, dim3(blocks), dim3(256), 0, st, feat, n, D, p_hi, p_lo, c1, out); break;
+        case 3: hipLaunchKernelGGL(k_rotate<3>, dim3(blocks), dim3(256), 0, st, feat, n, D, p_hi, p_lo, c1, out); break;
+        default: hipLaunchKernelGGL(k_rotate<4>, dim3(blocks), dim3(256), 0, st, feat, n, D, p_hi, p_lo, c1, out); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace zh

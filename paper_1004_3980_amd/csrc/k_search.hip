@@ -385,46 +385,163 @@ float screen_coeff(int D) {
     return (float)(2.0 * c);
 }
 
+// Exact fp32 distances |q - x|^2 of the candidates cids[c0..c1) from both
+// planes, eight lanes per row (16 coordinates each), into cdist; a row whose
+// fp32 distance is 0 is checked for exact equality with the query (flag bit).
+__device__ __forceinline__ void exact_rows(const SearchArgs& a, const float* sq, const uint32_t* cids,
+                                           uint32_t* cdist, int c0, int c1) {
+    const int lane = threadIdx.x;
+    const int D = a.D, HS = a.hs;
+    const int rg = lane >> 3, g = lane & 7;
+    const int nvg = D - 16 * g;
+    for (int cb = c0; cb < c1; cb += 8) {
+        const int c = cb + rg;
+        const bool cv = c < c1;
+        const uint32_t id = cv ? cids[c] : 0u;
+        const size_t bo = ((size_t)id * (uint32_t)D + 16u * g) * 2u;
+        const size_t bh = ((size_t)id * (uint32_t)HS + 16u * g) * 2u;
+        uint4 h[2], l[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            h[u] = make_uint4(0u, 0u, 0u, 0u);
+            l[u] = h[u];
+            if (cv && 16 * g + 8 * u < D) {
+                h[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.hi) + bh + 16 * u);
+                l[u] = ld16(reinterpret_cast<const char*>(a.lo) + bo + 16 * u);
+            }
+            const int nv = nvg - 8 * u;
+            if (nv < 8) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t km = keep_mask(nv, w);
+                    (&h[u].x)[w] &= km;
+                    (&l[u].x)[w] &= km;
+                }
+            }
+        }
+        float qv[16];
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4) {
+            const float4 t4 = *reinterpret_cast<const float4*>(sq + 16 * g + 4 * e4);
+            qv[4 * e4] = t4.x;
+            qv[4 * e4 + 1] = t4.y;
+            qv[4 * e4 + 2] = t4.z;
+            qv[4 * e4 + 3] = t4.w;
+        }
+        float p = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
+            const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float y0 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u));
+                const float y1 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u));
+                const float d0 = qv[8 * u + 2 * w] - y0;
+                const float d1 = qv[8 * u + 2 * w + 1] - y1;
+                p = fmaf(d0, d0, p);
+                p = fmaf(d1, d1, p);
+            }
+        }
+        p += __shfl_xor(p, 1);
+        p += __shfl_xor(p, 2);
+        p += __shfl_xor(p, 4);
+        bool exact_row = false;
+        if (__ballot(cv && p == 0.0f) != 0) {
+            bool eq = true;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
+                const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u) == __float_as_uint(qv[8 * u + 2 * w]);
+                    eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u) == __float_as_uint(qv[8 * u + 2 * w + 1]);
+                }
+            }
+            const uint32_t grp = (uint32_t)(__ballot(eq) >> (8 * rg)) & 0xFFu;
+            exact_row = grp == 0xFFu;
+        }
+        if (g == 0 && cv) cdist[c] = __float_as_uint(p) | (exact_row ? 0x80000000u : 0u);
+    }
+}
+
+// Of the M keys held NSL per lane (element s*64 + lane) with flag `in`, mark
+// the n smallest (n <= number flagged); equal keys by lower `tie` value.
+template <int NSL>
+__device__ void mark_smallest(const uint32_t (&kv)[NSL], const uint32_t (&tie)[NSL], const bool (&in)[NSL], int M,
+                              int n, bool (&keep)[NSL]) {
+    const int lane = threadIdx.x & 63;
+    uint32_t k2[NSL];
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) k2[s] = in[s] ? kv[s] : 0xFFFFFFFFu;
+    const uint32_t tau = radix_kth(k2, M, n);
+    int nlt = 0, neq = 0;
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) {
+        nlt += __popcll(__ballot(in[s] && k2[s] < tau));
+        neq += __popcll(__ballot(in[s] && k2[s] == tau));
+    }
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) keep[s] = in[s] && k2[s] < tau;
+    const int need = n - nlt;
+    if (neq == need) {
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) keep[s] = keep[s] || (in[s] && k2[s] == tau);
+    } else {
+        uint32_t last = 0;
+        for (int r = 0; r < need; ++r) {
+            uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+            for (int s = 0; s < NSL; ++s)
+                if (in[s] && k2[s] == tau && (r == 0 || tie[s] > last) && tie[s] < best) best = tie[s];
+            best = wave_min_u32(best);
+#pragma unroll
+            for (int s = 0; s < NSL; ++s)
+                if (in[s] && k2[s] == tau && tie[s] == best) keep[s] = true;
+            last = best;
+        }
+    }
+    (void)lane;
+}
+
 // Early-stop search (cap <= 256), one wave per patch.
 //  1. Candidates: the concatenation of the L bins is read 64 positions at a
 //     time; an LDS hash set of the IDs seen so far (open addressing, atomic
 //     compare-and-swap inserts, an atomic minimum keeping the earliest lane
 //     of a chunk) keeps first occurrences in order, up to `cap`.
-//  2. Pre-filter, when more than K candidates: |q - x_hi|^2 is evaluated as
-//     |q|^2 + |x_hi|^2 - 2 q.x_hi with MFMA dot products (candidate rows of
-//     the bf16 high plane as A, the query split into bf16 high and low parts
-//     as two columns of B) and the |x_hi|^2 stored at the end of the row.
-//     With the stored bound rho >= |x - x_hi| and the screen's error bound
-//     this gives an interval [L, U] that holds the candidate's distance; a
-//     candidate whose L exceeds the K-th smallest U (32-step ballot radix
-//     select) is farther than K others and is dropped. The screened form
-//     keeps at most R survivors (smallest L).
-//  3. Exact fp32 distances of the survivors from both planes, eight lanes
-//     per row (16 coordinates each); a row whose fp32 distance is 0 is checked
-//     for exact equality with the query.
+//  2. Screen, when more than K candidates: each candidate's screen row (one
+//     memory line: its coordinates y~ in the dictionary's leading principal
+//     directions, bf16, with |y~|^2 and rho_x) gives |y_q - y~|^2 =
+//     |y_q|^2 + |y~|^2 - 2 y_q.y~ on the matrix cores (screen rows as A, the
+//     rotated query split into bf16 high and low parts as two columns of B),
+//     and with the error bounds a lower bound L <= |q - x|^2. The K
+//     candidates of smallest L get exact distances; the largest upper bound
+//     U_K of those bounds the K-th smallest distance, so only candidates with
+//     L <= U_K can be among the K nearest. Those get exact distances too (the
+//     screened form keeps at most R in all, by smallest L).
+//  3. Exact fp32 distances from both planes of the full features.
 //  4. Sorted selection of the K best, certification (exact form), output.
 template <int NS, bool EXACT, int NSL>
 __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
     // dynamic LDS: hash set [hsz] of (id << 32 | first lane), empty = ~0, then
-    // the candidate IDs and values [cp] each, cp = max(64, next_pow2(cap))
+    // the candidate IDs and values [cp] each, cp = max(64, next_pow2(cap));
+    // after the union the hash set holds the screen tails (float2 per candidate)
     extern __shared__ uint64_t hset[];
     uint32_t* cids = reinterpret_cast<uint32_t*>(hset + a.hsz);
     uint32_t* cdist = cids + a.cp;
+    float2* stl = reinterpret_cast<float2*>(hset);
     __shared__ __align__(16) float sq[128];
-    __shared__ __align__(16) uint16_t sqs[2][128];   // bf16 high and low parts of the query
+    __shared__ __align__(16) uint16_t sqs[2][kRotStride];   // bf16 high and low parts of y_q
     __shared__ uint32_t sstart[kMaxL + 1];
     __shared__ uint32_t soff[kMaxL];
     const int lane = threadIdx.x;
     const int L = a.L, D = a.D;
-    const int HS = a.hs, TO = hi_tail(D);
+    const int SS = screen_stride(D), TS = screen_tail(D);
     const int hsz = a.hsz;
     const uint32_t hmask = (uint32_t)hsz - 1u;
     const int hshift = 32 - __builtin_ctz((unsigned)hsz);
     const int ri = lane & 15, kb = lane >> 4;   // MFMA layout
-    const int rg = lane >> 3, g = lane & 7;     // eight lanes per row
-    // coordinates of this lane's last MFMA step, and of its two 16-byte groups
-    const int nvt = D - (32 * (NS - 1) + 8 * kb);
-    const int nvg = D - 16 * g;
 
     {
         const int q = xcd_block();
@@ -443,16 +560,16 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
         }
         if (lane == 0) sstart[L] = (uint32_t)T;
         for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
-        double qd = 0.0;
-        for (int i = lane; i < 128; i += 64) {
-            const float x = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
-            sq[i] = x;
-            const uint16_t h = bf16_rne(x);
-            sqs[0][i] = h;
-            sqs[1][i] = bf16_rne(x - bf16_to_f(h));
-            qd += (double)x * (double)x;
+        for (int i = lane; i < 128; i += 64) sq[i] = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
+        const float rv = a.qrot[(int64_t)q * kRotStride + lane];
+        const float rho_q = __shfl(rv, kRotStride - 1);
+        const float yq = lane < kScreenMax ? rv : 0.0f;
+        {
+            const uint16_t h = bf16_rne(yq);
+            sqs[0][lane] = h;
+            sqs[1][lane] = bf16_rne(yq - bf16_to_f(h));
         }
-        const float qn2 = (float)wave_sum_f64(qd);
+        const float qn2 = (float)wave_sum_f64((double)yq * (double)yq);
         __syncthreads();
 
         // ---- 1. candidates, first occurrences in order, up to cap
@@ -509,40 +626,45 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
         }
         if (lane == 0) a.out_ncand[q] = M;
 
-        // ---- 2. bf16 pre-filter: an interval [L, U] around each candidate's
-        // distance; candidates with L above the K-th smallest U cannot be
-        // among the K nearest
+        // ---- 2. screen lower bounds, exact distances of the K lowest, U_K
         int Mr = M;
         if (M > a.K) {
-            uint4 qb[NS];
+            const int K = a.K;
+            uint4 qb[2];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
+            for (int s = 0; s < 2; ++s) {
                 const uint4 t4 = *reinterpret_cast<const uint4*>(&sqs[ri & 1][32 * s + 8 * kb]);
                 qb[s] = ri < 2 ? t4 : make_uint4(0u, 0u, 0u, 0u);
             }
+            const int nss = SS >> 5;
             for (int t = 0; t < M; t += 16) {
                 const int c = t + ri;
                 const bool cv = c < M;
                 const uint32_t id = cv ? cids[c] : 0u;
-                const char* rowp = reinterpret_cast<const char*>(a.hi) + id * (uint32_t)(2 * HS);
+                const char* rowp = reinterpret_cast<const char*>(a.sc) + (size_t)id * (uint32_t)(2 * SS);
                 f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    const int d = 32 * s + 8 * kb;
-                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                    if (cv && d < D) {
-                        v = *reinterpret_cast<const uint4*>(rowp + 2 * d);
-                        if (s == NS - 1 && nvt < 8) {
-                            v.x &= keep_mask(nvt, 0);
-                            v.y &= keep_mask(nvt, 1);
-                            v.z &= keep_mask(nvt, 2);
-                            v.w &= keep_mask(nvt, 3);
+                for (int s = 0; s < 2; ++s) {
+                    if (s < nss) {
+                        const int d = 32 * s + 8 * kb;
+                        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                        if (cv) {
+                            v = *reinterpret_cast<const uint4*>(rowp + 2 * d);
+                            if (d <= TS && TS < d + 8) stl[c] = TS == d ? make_float2(__uint_as_float(v.x), __uint_as_float(v.y))
+                                                                      : make_float2(__uint_as_float(v.z), __uint_as_float(v.w));
+                            const int nv = TS - d;
+                            if (nv < 8) {
+                                v.x &= keep_mask(nv, 0);
+                                v.y &= keep_mask(nv, 1);
+                                v.z &= keep_mask(nv, 2);
+                                v.w &= keep_mask(nv, 3);
+                            }
                         }
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v),
+                                                                     __builtin_bit_cast(bf16x8, qb[s]), acc, 0, 0, 0);
                     }
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v),
-                                                                 __builtin_bit_cast(bf16x8, qb[s]), acc, 0, 0, 0);
                 }
-                // lane (kb, 0) holds q_hi.x_hi and lane (kb, 1) q_lo.x_hi of candidates t + 4 kb + r
+                // lane (kb, 0) holds y_q,hi.y~ and lane (kb, 1) y_q,lo.y~ of candidates t + 4 kb + r
                 float lo4[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) lo4[r] = __shfl_down(acc[r], 1);
@@ -555,91 +677,66 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
                 }
             }
             __syncthreads();
-            // |q - x|^2 in [(a_lo - rho)^2, (a_hi + rho)^2], a = |q - x_hi|, rho >= |x - x_hi|;
-            // every fp32 step moves its result outward by a relative margin far
-            // above its rounding error
-            uint32_t lv[NSL], uv[NSL], iv[NSL];
+            // |y_q - y~| >= a_lo from the screen value and its error bound c (|y_q|^2 + |y~|^2);
+            // |q - x| >= (a_lo - rho_q - rho_x) / sigma; every fp32 step moves outward
+            uint32_t lv[NSL], iv[NSL];
+            bool valid[NSL];
 #pragma unroll
             for (int s = 0; s < NSL; ++s) {
                 const int c = s * 64 + lane;
-                lv[s] = uv[s] = iv[s] = 0xFFFFFFFFu;
+                lv[s] = iv[s] = 0xFFFFFFFFu;
+                valid[s] = c < M;
                 if (c < M) {
-                    const uint32_t id = cids[c];
-                    const float2 tl = *reinterpret_cast<const float2*>(a.hi + (size_t)id * HS + TO);
+                    const float2 tl = stl[c];
                     const float dot = __uint_as_float(cdist[c]);
                     const float nn = qn2 + tl.x;
                     const float a2 = nn - 2.0f * dot;
                     const float E = fmaf(a.ce, nn, 1e-30f);
                     const float alo = sqrtf(fmaxf((a2 - E) * (1.0f - 1e-6f), 0.0f)) * (1.0f - 1e-6f);
-                    const float ahi = sqrtf((a2 + E) * (1.0f + 1e-6f)) * (1.0f + 1e-6f);
-                    const float l = fmaxf(alo * (1.0f - 1e-6f) - tl.y * (1.0f + 1e-6f), 0.0f);
-                    const float u = ahi * (1.0f + 1e-6f) + tl.y * (1.0f + 1e-6f);
-                    lv[s] = __float_as_uint(l * l * (1.0f - 1e-5f));
-                    uv[s] = __float_as_uint(u * u * (1.0f + 1e-5f));
-                    iv[s] = id;
+                    const float l = fmaxf(alo * (1.0f - 1e-6f) - (rho_q + tl.y) * (1.0f + 1e-6f), 0.0f);
+                    lv[s] = __float_as_uint(l * l * a.inv_s2 * (1.0f - 1e-5f));
+                    iv[s] = cids[c];
                 }
             }
-            // an upper bound of the K-th smallest U: radix search on the top 16 bits
-            uint32_t hk = 0;
-            {
-                const int nsl = (M + 63) >> 6;
-                for (int b = 15; b >= 0; --b) {
-                    const uint32_t trial = hk + (1u << b);
-                    int n = 0;
+            bool inA[NSL];
+            mark_smallest<NSL>(lv, iv, valid, M, K, inA);
+            __syncthreads();
+            int pos = 0;
 #pragma unroll
-                    for (int s = 0; s < NSL; ++s)
-                        if (s < nsl) n += __popcll(__ballot(s * 64 + lane < M && (uv[s] >> 16) < trial));
-                    if (n < a.K) hk = trial;
-                }
+            for (int s = 0; s < NSL; ++s) {
+                const uint64_t bal = __ballot(inA[s]);
+                if (inA[s]) cids[pos + __popcll(bal & lanemask_lt())] = iv[s];
+                pos += __popcll(bal);
             }
-            const uint32_t uk = (hk << 16) | 0xFFFFu;
+            __syncthreads();
+            exact_rows(a, sq, cids, cdist, 0, K);
+            __syncthreads();
+            // U_K: the largest upper bound of the K exact distances
+            const Bounds bd{2.0 * gamma_n(D + 3, 1.0 / 16777216.0), (double)D * 1.2e-38};
+            double uk = 0.0;
+            if (lane < K) {
+                double dlo, dhi;
+                dist_interval(cdist[lane], bd, dlo, dhi);
+                uk = dhi;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) uk = fmax(uk, __shfl_xor(uk, o));
             bool sel[NSL];
             int S = 0;
 #pragma unroll
             for (int s = 0; s < NSL; ++s) {
-                sel[s] = s * 64 + lane < M && lv[s] <= uk;
+                sel[s] = valid[s] && !inA[s] && (double)__uint_as_float(lv[s]) <= uk;
                 S += __popcll(__ballot(sel[s]));
             }
-            if (!EXACT && S > a.rerank) {
-                // screened form: at most R survivors, by lower bound, equal bounds by lower ID
-                const int R = a.rerank;
-                uint32_t kv[NSL];
-#pragma unroll
-                for (int s = 0; s < NSL; ++s) kv[s] = sel[s] ? lv[s] : 0xFFFFFFFFu;
-                const uint32_t tau = radix_kth(kv, M, R);
-                int nlt = 0, neq = 0;
-#pragma unroll
-                for (int s = 0; s < NSL; ++s) {
-                    nlt += __popcll(__ballot(sel[s] && kv[s] < tau));
-                    neq += __popcll(__ballot(sel[s] && kv[s] == tau));
-                }
+            if (!EXACT && K + S > a.rerank) {
+                // screened form: at most R survivors in all, by lower bound, equal bounds by lower ID
                 bool keep[NSL];
-#pragma unroll
-                for (int s = 0; s < NSL; ++s) keep[s] = sel[s] && kv[s] < tau;
-                const int need = R - nlt;
-                if (neq == need) {
-#pragma unroll
-                    for (int s = 0; s < NSL; ++s) keep[s] = keep[s] || (sel[s] && kv[s] == tau);
-                } else {
-                    uint32_t last = 0;
-                    for (int r = 0; r < need; ++r) {
-                        uint32_t best = 0xFFFFFFFFu;
-#pragma unroll
-                        for (int s = 0; s < NSL; ++s)
-                            if (sel[s] && kv[s] == tau && (r == 0 || iv[s] > last) && iv[s] < best) best = iv[s];
-                        best = wave_min_u32(best);
-#pragma unroll
-                        for (int s = 0; s < NSL; ++s)
-                            if (sel[s] && kv[s] == tau && iv[s] == best) keep[s] = true;
-                        last = best;
-                    }
-                }
+                mark_smallest<NSL>(lv, iv, sel, M, a.rerank - K, keep);
 #pragma unroll
                 for (int s = 0; s < NSL; ++s) sel[s] = keep[s];
-                S = R;
+                S = a.rerank - K;
             }
-            __syncthreads();
-            int pos = 0;
+            pos = K;
 #pragma unroll
             for (int s = 0; s < NSL; ++s) {
                 const uint64_t bal = __ballot(sel[s]);
@@ -647,82 +744,14 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
                 pos += __popcll(bal);
             }
             __syncthreads();
-            Mr = S;
+            Mr = K + S;
+            // ---- 3. exact distances of the remaining survivors
+            if (S > 0) exact_rows(a, sq, cids, cdist, K, Mr);
+        } else {
+            // ---- 3. exact distances of all candidates
+            exact_rows(a, sq, cids, cdist, 0, M);
         }
-
         if (lane == 0 && a.out_nsurv) a.out_nsurv[q] = Mr;
-
-        // ---- 3. exact fp32 distances, eight lanes per row
-        for (int cb = 0; cb < Mr; cb += 8) {
-            const int c = cb + rg;
-            const bool cv = c < Mr;
-            const uint32_t id = cv ? cids[c] : 0u;
-            const uint32_t bo = (id * (uint32_t)D + 16u * g) * 2u;
-            const uint32_t bh = (id * (uint32_t)HS + 16u * g) * 2u;
-            uint4 h[2], l[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                h[u] = make_uint4(0u, 0u, 0u, 0u);
-                l[u] = h[u];
-                if (cv && 16 * g + 8 * u < D) {
-                    h[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.hi) + bh + 16 * u);
-                    l[u] = ld16(reinterpret_cast<const char*>(a.lo) + bo + 16 * u);
-                }
-                const int nv = nvg - 8 * u;
-                if (nv < 8) {
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const uint32_t km = keep_mask(nv, w);
-                        (&h[u].x)[w] &= km;
-                        (&l[u].x)[w] &= km;
-                    }
-                }
-            }
-            float qv[16];
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                const float4 t4 = *reinterpret_cast<const float4*>(sq + 16 * g + 4 * e4);
-                qv[4 * e4] = t4.x;
-                qv[4 * e4 + 1] = t4.y;
-                qv[4 * e4 + 2] = t4.z;
-                qv[4 * e4 + 3] = t4.w;
-            }
-            float p = 0.0f;
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
-                const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const float y0 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u));
-                    const float y1 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u));
-                    const float d0 = qv[8 * u + 2 * w] - y0;
-                    const float d1 = qv[8 * u + 2 * w + 1] - y1;
-                    p = fmaf(d0, d0, p);
-                    p = fmaf(d1, d1, p);
-                }
-            }
-            p += __shfl_xor(p, 1);
-            p += __shfl_xor(p, 2);
-            p += __shfl_xor(p, 4);
-            bool exact_row = false;
-            if (__ballot(cv && p == 0.0f) != 0) {
-                bool eq = true;
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
-                    const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u) == __float_as_uint(qv[8 * u + 2 * w]);
-                        eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u) == __float_as_uint(qv[8 * u + 2 * w + 1]);
-                    }
-                }
-                const uint32_t grp = (uint32_t)(__ballot(eq) >> (8 * rg)) & 0xFFu;
-                exact_row = grp == 0xFFu;
-            }
-            if (g == 0 && cv) cdist[c] = __float_as_uint(p) | (exact_row ? 0x80000000u : 0u);
-        }
         __syncthreads();
 
         // ---- 4. K best, certification, output

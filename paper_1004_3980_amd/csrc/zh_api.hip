@@ -39,6 +39,10 @@ struct Dict {
     float bc1[2] = {0.f, 0.f}, bc2[2] = {0.f, 0.f};
     Buf dir;                      // [L, cap] Slot
     Buf tids;                     // [L, n] uint32
+    Buf sc;                       // [n, screen_stride(D)] screen plane
+    Buf phi_hi, phi_lo;           // [64, round32(D)] bf16 split of the principal directions
+    float inv_s2 = 0.f;           // lower bound of 1 / sigma_max(Phi)^2
+    float rot_c1 = 0.f;           // error-bound coefficient of the query rotation
     std::vector<float> h_alpha, h_beta;
 };
 
@@ -78,6 +82,7 @@ struct zh_ctx {
     float bp_sigma_s = 0.f, bp_sigma_r = 0.f;
     int64_t Q = 0;
     Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv, guides, bwd, bwd_k, clam;
+    Buf qrot;                     // [Q, 64] rotated queries of the screen
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -272,6 +277,65 @@ zh_status hash_scratch(zh_ctx* c, HashArgs& ha) {
     return ZH_OK;
 }
 
+// Screen plane of a dictionary: FP64 covariance of up to 65536 evenly spaced
+// rows, its leading eigenvectors as Phi (host), the bf16 split of Phi for the
+// query rotation and the screen row of every entry.
+zh_status build_screen(zh_ctx* c, Dict& d, const float* feat) {
+    const int D = d.D, m = screen_dims(D);
+    const int64_t n = d.n;
+    const int64_t ns = std::min<int64_t>(n, 65536);
+    Buf part, cov, phit;
+    zh_status st = ZH_OK;
+    std::vector<double> C((size_t)D * D), phiT((size_t)D * kRotStride, 0.0);
+    std::vector<float> phi((size_t)m * D);
+    const int DP = (D + 31) & ~31;
+    std::vector<uint16_t> ph((size_t)kRotStride * DP, 0), pl((size_t)kRotStride * DP, 0);
+    double s2 = 0.0;
+    if ((st = ensure(c, part, sizeof(double) * 128 * (size_t)D * D)) != ZH_OK) goto out;
+    if ((st = ensure(c, cov, sizeof(double) * (size_t)D * D)) != ZH_OK) goto out;
+    if ((st = ensure(c, phit, sizeof(double) * (size_t)D * kRotStride)) != ZH_OK) goto out;
+    if (launch_cov(feat, n, D, ns, P<double>(part), P<double>(cov), c->stream) != hipSuccess ||
+        hipMemcpyAsync(C.data(), cov.p, sizeof(double) * (size_t)D * D, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        st = fail(c, ZH_EDEVICE, "zh_build_tables: covariance of the screen failed");
+        goto out;
+    }
+    s2 = screen_basis(C.data(), D, m, phi.data());
+    {
+        const double v = (1.0 / s2) * (1.0 - 1e-9);
+        float f = (float)v;
+        if ((double)f > v) f = std::nextafter(f, 0.0f);
+        d.inv_s2 = f;
+    }
+    d.rot_c1 = rotate_bound_coeff(D);
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < D; ++i) {
+            const float v = phi[(size_t)j * D + i];
+            phiT[(size_t)i * kRotStride + j] = (double)v;
+            const uint16_t h = bf16_rne_host(v);
+            ph[(size_t)j * DP + i] = h;
+            pl[(size_t)j * DP + i] = bf16_rne_host(v - bf16_f_host(h));
+        }
+    if ((st = ensure(c, d.sc, sizeof(uint16_t) * (size_t)n * screen_stride(D))) != ZH_OK) goto out;
+    if ((st = ensure(c, d.phi_hi, sizeof(uint16_t) * ph.size())) != ZH_OK) goto out;
+    if ((st = ensure(c, d.phi_lo, sizeof(uint16_t) * pl.size())) != ZH_OK) goto out;
+    if (hipMemcpyAsync(phit.p, phiT.data(), sizeof(double) * phiT.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(d.phi_hi.p, ph.data(), sizeof(uint16_t) * ph.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(d.phi_lo.p, pl.data(), sizeof(uint16_t) * pl.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        launch_screen_rows(feat, n, D, m, P<double>(phit), P<uint16_t>(d.sc), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        st = fail(c, ZH_EDEVICE, "zh_build_tables: screen rows failed");
+        goto out;
+    }
+out:
+    release(c, part);
+    release(c, cov);
+    release(c, phit);
+    return st;
+}
+
 zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     SearchArgs a{};
     a.Q = (int)c->Q;
@@ -288,7 +352,9 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.hi = P<uint16_t>(d.hi);
     a.lo = P<uint16_t>(d.lo);
     a.hs = hi_stride(d.D);
-    a.ce = screen_coeff(d.D);
+    a.ce = screen_coeff(screen_tail(d.D));
+    a.sc = P<uint16_t>(d.sc);
+    a.inv_s2 = d.inv_s2;
     a.out_ids = P<int32_t>(c->ids);
     a.out_d2 = P<float>(c->d2);
     a.out_m = P<int32_t>(c->m);
@@ -296,6 +362,10 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     if (a.cap > 0) {
         TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)(a.Q > 0 ? a.Q : 1)));
         a.out_nsurv = P<int32_t>(c->nsurv);
+        TRY(ensure(c, c->qrot, sizeof(float) * kRotStride * (size_t)(a.Q > 0 ? a.Q : 1)));
+        a.qrot = P<float>(c->qrot);
+        HIPCHK(c, launch_rotate(a.qfeat, a.Q, d.D, P<uint16_t>(d.phi_hi), P<uint16_t>(d.phi_lo), d.rot_c1,
+                                P<float>(c->qrot), c->stream));
     }
     a.dump = dump;
     a.dump_cap = dump_cap;
@@ -340,6 +410,7 @@ void zh_destroy(zh_ctx* c) {
     for (Dict& d : c->dicts) {
         release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.bc0[0]); release(c, d.bc0[1]);
         release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.tids);
+        release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo);
     }
     for (int st = 0; st < ZH_T_COUNT; ++st)
         for (int i = 0; i < zh_ctx::kEv; ++i)
@@ -356,7 +427,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -454,6 +525,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     HIPCHK(c, hipMemsetAsync(d.lo.p, 0, d.lo.bytes, c->stream));
     HIPCHK(c, launch_split_planes(dict->feat, n, D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
     HIPCHK(c, launch_hi_tails(dict->feat, n, D, P<uint16_t>(d.hi), c->stream));
+    TRY(build_screen(c, d, dict->feat));
     // hash parameters
     hash_params(seed, L, k, D, (double)w, d.h_alpha, d.h_beta);
     const int m = L * k;
@@ -982,6 +1054,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     TRY(ensure(c, c->m, sizeof(int32_t) * (size_t)q_max));
     TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)q_max));
     TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)std::max<int64_t>(q_max, 1)));
+    TRY(ensure(c, c->qrot, sizeof(float) * kRotStride * (size_t)std::max<int64_t>(q_max, 1)));
     TRY(ensure(c, c->over, sizeof(int32_t) * (size_t)q_max));
     TRY(ensure(c, c->xhat, sizeof(float) * (size_t)q_max * ps2_max));
     TRY(ensure(c, c->counters, kNumCounters * sizeof(uint32_t)));
