@@ -93,19 +93,32 @@ def _fmix64_np(z: np.ndarray) -> np.ndarray:
     return z ^ (z >> np.uint64(31))
 
 
+def key_multipliers(L: int, k: int) -> np.ndarray:
+    """Multipliers of the bucket key: entry (l, j) is output number
+    64 l + j + 1 of SplitMix64 started from state 0; columns 0..k-1 weigh the
+    k codes of table l and the last column (output 64 l + 64) starts the sum
+    (k <= 32). uint64 [L, k + 1]."""
+    gen = SplitMix64(0)
+    outs = [gen.next_u64() for _ in range(64 * L)]
+    return np.array([[outs[64 * l + j] for j in range(k)] + [outs[64 * l + 63]] for l in range(L)],
+                    dtype=np.uint64)
+
+
 def bucket_keys(c: np.ndarray, L: int, k: int) -> np.ndarray:
     """64-bit key of each table's k-tuple of codes (the bin of Section 4.1):
-    h = fmix64(GOLDEN * (l+1)); for each code c_j of table l in order:
-    h = fmix64(h XOR uint32(c_j)); a key equal to all-ones becomes all-ones
-    minus one. uint64 [n, L]."""
+    the start value of table l plus the sum over j of uint32(c_j) times the
+    multiplier M_lj, modulo 2^64, through the SplitMix64 output function; a
+    key equal to all-ones becomes all-ones minus one. uint64 [n, L]."""
     n = c.shape[0]
+    M = key_multipliers(L, k)
     out = np.empty((n, L), dtype=np.uint64)
     with np.errstate(over="ignore"):
         for l in range(L):
-            h = np.full(n, fmix64((GOLDEN * (l + 1)) & MASK64), dtype=np.uint64)
+            s = np.full(n, M[l, k], dtype=np.uint64)
             for j in range(k):
-                cj = c[:, l * k + j].astype(np.int64) & 0xFFFFFFFF
-                h = _fmix64_np(h ^ cj.astype(np.uint64))
+                cj = (c[:, l * k + j].astype(np.int64) & 0xFFFFFFFF).astype(np.uint64)
+                s = s + cj * M[l, j]
+            h = _fmix64_np(s)
             h[h == np.uint64(EMPTY_KEY)] = np.uint64(EMPTY_KEY - 1)
             out[:, l] = h
     return out

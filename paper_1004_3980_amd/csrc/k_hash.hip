@@ -15,9 +15,11 @@
 // defines it (in a second kernel, for the few tables that need it). The
 // codes therefore equal the FP64 definition bit for bit.
 //
-// The k codes of a table are folded into a 64-bit key in index order,
-//   h = fmix64(GOLDEN*(l+1)); h = fmix64(h ^ uint32(c_j)) for j = 0..k-1,
-// and, when a directory is given, a third kernel looks up each key's bin
+// The k codes of a table become a 64-bit key
+//   key = fmix64( M_l63 + sum_j uint32(c_j) * M_lj  mod 2^64 ),
+// M_lj = SplitMix64 output 64 l + j + 1 from state 0 (table a.key_mul: k
+// multipliers and the start value M_l63 per table), and,
+// when a directory is given, a third kernel looks up each key's bin
 // (offset, count).
 #include <cmath>
 
@@ -98,8 +100,10 @@ __host__ __device__ inline int stage_bytes(int prec, int k, int D) {
 // marked kCodeUnset) for k_hash_fixlist, or, when the list is full, the
 // table's bit is set in the row's dirty mask for k_hash_fix; the key written
 // here is replaced there.
+// Three waves per SIMD (at most 168 registers, a few bytes of spill) run the
+// kernel faster than two without spill.
 template <int PREC, int NS, int NPRE>
-__global__ __launch_bounds__(256) void k_hash(HashArgs a) {
+__global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
     const int D = a.D, k = a.k, L = a.L, m = L * k;
     const int GK = kStage * k;
     const int R = stage_rows(k);
@@ -125,6 +129,10 @@ __global__ __launch_bounds__(256) void k_hash(HashArgs a) {
     uint8_t* sU = reinterpret_cast<uint8_t*>(reinterpret_cast<int32_t*>(smem + stage_bytes(PREC, k, D)) +
                                              kWaves * fold * k * kRowsPerWave) + wave * (4 * kRowsPerWave);
     if (lane < 4 * kRowsPerWave) sU[lane] = 0;
+    // key multipliers of every table, [L][k + 1]
+    uint64_t* smul = reinterpret_cast<uint64_t*>(reinterpret_cast<unsigned char*>(sU - wave * (4 * kRowsPerWave)) +
+                                                 kWaves * 4 * kRowsPerWave);
+    for (int e = threadIdx.x; e < L * (k + 1); e += 256) smul[e] = a.key_mul[e];
 
     // B operand of this lane for every k-step: feature row ri, coordinates
     // 32 s + 8 kb + e (e < 8) as bf16 high/low parts (PREC 1), or 4 s + kb
@@ -329,12 +337,14 @@ __global__ __launch_bounds__(256) void k_hash(HashArgs a) {
             }
             wcnt += (unsigned)__popcll(bal);
             if (act) {
-                uint64_t h = key_seed(lt);
+                const uint64_t* mul = smul + lt * (k + 1);
+                uint64_t h = mul[k];
+#pragma unroll 4
                 for (int j = 0; j < k; ++j) {
                     const int32_t c = sC[(t * k + j) * kRowsPerWave + rr];
                     if (a.codes) a.codes[row * m + lt * k + j] = c;
                     if (ent) ent[2 + j] = c;
-                    h = key_step(h, c);
+                    h += key_term(c, mul[j]);
                 }
                 a.keys[row * L + lt] = key_final(h);
             }
@@ -414,12 +424,12 @@ __global__ __launch_bounds__(256) void k_hash_fixlist(HashArgs a) {
             for (int jj = 0; jj < kMaxKHash; ++jj)
                 if (jj == j) ev[2 + jj] = c;
         }
-        uint64_t h = key_seed(l);
+        uint64_t h = a.key_mul[l * (k + 1) + k];
 #pragma unroll
         for (int j = 0; j < kMaxKHash; ++j) {
             if (j < k) {
                 if (a.codes) a.codes[row * m + l * k + j] = ev[2 + j];
-                h = key_step(h, ev[2 + j]);
+                h += key_term(ev[2 + j], a.key_mul[l * (k + 1) + j]);
             }
         }
         a.keys[row * L + l] = key_final(h);
@@ -482,9 +492,9 @@ __global__ __launch_bounds__(64) void k_hash_fix(HashArgs a) {
             c = floor_sat((s + (double)a.beta[hrow]) / wd);
             if (a.codes) a.codes[row * m + hrow] = c;
         }
-        uint64_t h = key_seed(l_mine);
+        uint64_t h = a.key_mul[l_mine * (k + 1) + k];
         const int base = act ? grp * k : 0;
-        for (int j = 0; j < k; ++j) h = key_step(h, __shfl(c, base + j));
+        for (int j = 0; j < k; ++j) h += key_term(__shfl(c, base + j), a.key_mul[l_mine * (k + 1) + j]);
         if (act && jj == 0) a.keys[row * L + l_mine] = key_final(h);
         __syncthreads();
     }
@@ -546,13 +556,14 @@ static void launch_split(const HashArgs& a, dim3 grid, size_t lds, hipStream_t s
 
 hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty || !a.fix_count ||
+    if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty || !a.fix_count || !a.key_mul ||
         a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list))
         return hipErrorInvalidValue;
     const int rows = kWaves * kRowsPerWave;
     const dim3 grid((unsigned)((a.n + rows - 1) / rows));
     const size_t lds = (size_t)stage_bytes(a.prec, a.k, a.D) +
-                       (size_t)kWaves * fold_tables(a.k) * a.k * kRowsPerWave * 4 + kWaves * 4 * kRowsPerWave;
+                       (size_t)kWaves * fold_tables(a.k) * a.k * kRowsPerWave * 4 + kWaves * 4 * kRowsPerWave +
+                       sizeof(uint64_t) * (size_t)a.L * (a.k + 1);
     if (a.prec == 0) {
         hipLaunchKernelGGL((k_hash<0, 1, 1>), grid, dim3(256), lds, st, a);
     } else {

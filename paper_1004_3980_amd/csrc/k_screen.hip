@@ -265,13 +265,31 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ feat, 
         u16x8 bh[NS], bl[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            float v[8];
+            if ((D & 3) == 0) {
+                // rows start on 16-byte boundaries: two float4 loads per step
+#pragma unroll
+                for (int h4 = 0; h4 < 2; ++h4) {
+                    const int d = 32 * s + 8 * kb + 4 * h4;
+                    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (rowok && d < D) t = *reinterpret_cast<const float4*>(feat + row * D + d);
+                    v[4 * h4] = t.x;
+                    v[4 * h4 + 1] = t.y;
+                    v[4 * h4 + 2] = t.z;
+                    v[4 * h4 + 3] = t.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int d = 32 * s + 8 * kb + e;
+                    v[e] = (rowok && d < D) ? feat[row * D + d] : 0.0f;
+                }
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int d = 32 * s + 8 * kb + e;
-                const float v = (rowok && d < D) ? feat[row * D + d] : 0.0f;
-                const uint16_t h = bf16_rne(v);
+                const uint16_t h = bf16_rne(v[e]);
                 bh[s][e] = h;
-                bl[s][e] = bf16_rne(v - bf16_to_f(h));
+                bl[s][e] = bf16_rne(v[e] - bf16_to_f(h));
             }
         }
         float b2 = 0.0f;

@@ -180,7 +180,7 @@ __device__ uint64_t select_topk(const uint32_t* cids, const uint32_t* cdist, int
 // Sorted selection for M <= 64 NSL candidates: lane r < min(M, 64) receives
 // the r-th smallest key.
 template <int NSL = 4>
-__device__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int M) {
+__device__ __forceinline__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int M) {
     const int lane = threadIdx.x;
     if (M <= 64) {
         uint64_t k[1] = {lane < M ? cand_key(cdist[lane], cids[lane]) : ~0ull};
@@ -357,18 +357,47 @@ __device__ __forceinline__ uint32_t keep_mask(int nv, int w) {
 // a 32-step radix search with wave ballots.
 template <int NSL>
 __device__ uint32_t radix_kth(const uint32_t (&kv)[NSL], int M, int R) {
-    const int lane = threadIdx.x & 63;
-    const int nsl = (M + 63) >> 6;
+    // keys past M are 0xFFFFFFFF, which no trial value exceeds
+    (void)M;
     uint32_t tau = 0;
     for (int b = 31; b >= 0; --b) {
         const uint32_t trial = tau + (1u << b);
         int n = 0;
 #pragma unroll
-        for (int s = 0; s < NSL; ++s)
-            if (s < nsl) n += __popcll(__ballot(s * 64 + lane < M && kv[s] < trial));
+        for (int s = 0; s < NSL; ++s) n += __popcll(__ballot(kv[s] < trial));
         if (n < R) tau = trial;
     }
     return tau;
+}
+
+// Marks n (1 <= n <= number of keys below 0xFFFFFFFF) of the keys held NSL per
+// lane that are among the smallest up to the top 16 bits: all keys whose top
+// 16 bits lie below the n-th smallest key's, and the rest from those equal to
+// it in that prefix, in slot order.
+template <int NSL>
+__device__ void mark_lowest16(const uint32_t (&kv)[NSL], int n, bool (&keep)[NSL]) {
+    uint32_t k16[NSL];
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) k16[s] = kv[s] >> 16;
+    uint32_t hk = 0;
+    for (int b = 15; b >= 0; --b) {
+        const uint32_t trial = hk | (1u << b);
+        int c = 0;
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) c += __popcll(__ballot(k16[s] < trial));
+        if (c < n) hk = trial;
+    }
+    int nlt = 0;
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) nlt += __popcll(__ballot(k16[s] < hk));
+    int need = n - nlt;
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) {
+        const uint64_t eq = __ballot(k16[s] == hk);
+        const int rank = __popcll(eq & lanemask_lt());
+        keep[s] = k16[s] < hk || (k16[s] == hk && rank < need);
+        need -= __popcll(eq);
+    }
 }
 
 // Relative error coefficient c of the screen value |q|^2 + |x_hi|^2 - 2 q.x_hi
@@ -522,8 +551,10 @@ __device__ void mark_smallest(const uint32_t (&kv)[NSL], const uint32_t (&tie)[N
 //     screened form keeps at most R in all, by smallest L).
 //  3. Exact fp32 distances from both planes of the full features.
 //  4. Sorted selection of the K best, certification (exact form), output.
+// Eight waves per SIMD (64 registers; the rarely taken paths spill a few
+// bytes) hide more of the dependent memory round trips than six.
 template <int NS, bool EXACT, int NSL>
-__global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
+__global__ __launch_bounds__(64, 8) void k_search_cap(SearchArgs a) {
     // dynamic LDS: hash set [hsz] of (id << 32 | first lane), empty = ~0, then
     // the candidate IDs and values [cp] each, cp = max(64, next_pow2(cap));
     // after the union the hash set holds the screen tails (float2 per candidate)
@@ -699,7 +730,7 @@ __global__ __launch_bounds__(64) void k_search_cap(SearchArgs a) {
                 }
             }
             bool inA[NSL];
-            mark_smallest<NSL>(lv, iv, valid, M, K, inA);
+            mark_lowest16<NSL>(lv, K, inA);
             __syncthreads();
             int pos = 0;
 #pragma unroll

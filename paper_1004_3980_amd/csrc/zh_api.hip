@@ -39,6 +39,7 @@ struct Dict {
     float bc1[2] = {0.f, 0.f}, bc2[2] = {0.f, 0.f};
     Buf dir;                      // [L, cap] Slot
     Buf tids;                     // [L, n] uint32
+    Buf kmul;                     // [L, k] multipliers of the bucket-key sum
     Buf sc;                       // [n, screen_stride(D)] screen plane
     Buf phi_hi, phi_lo;           // [64, round32(D)] bf16 split of the principal directions
     float inv_s2 = 0.f;           // lower bound of 1 / sigma_max(Phi)^2
@@ -410,7 +411,7 @@ void zh_destroy(zh_ctx* c) {
     for (Dict& d : c->dicts) {
         release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.bc0[0]); release(c, d.bc0[1]);
         release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.tids);
-        release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo);
+        release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo); release(c, d.kmul);
     }
     for (int st = 0; st < ZH_T_COUNT; ++st)
         for (int i = 0; i < zh_ctx::kEv; ++i)
@@ -542,6 +543,16 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     std::vector<float> bc0[2] = {std::vector<float>(m), std::vector<float>(m)};
     for (int pr = 0; pr < 2; ++pr)
         hash_bound_coeffs(pr, D, (double)w, d.h_beta.data(), m, bc0[pr].data(), &d.bc1[pr], &d.bc2[pr]);
+    {
+        std::vector<uint64_t> km((size_t)L * (k + 1));
+        for (int l = 0; l < L; ++l) {
+            for (int j = 0; j < k; ++j) km[(size_t)l * (k + 1) + j] = key_mul(l, j);
+            km[(size_t)l * (k + 1) + k] = key_mul(l, 63);
+        }
+        TRY(ensure(c, d.kmul, sizeof(uint64_t) * km.size()));
+        HIPCHK(c, hipMemcpyAsync(d.kmul.p, km.data(), sizeof(uint64_t) * km.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     TRY(ensure(c, d.alpha, sizeof(float) * (size_t)m * D));
     TRY(ensure(c, d.beta, sizeof(float) * (size_t)m));
     TRY(ensure(c, d.bc0[0], sizeof(float) * (size_t)m));
@@ -568,6 +579,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     ha.a_hi = P<uint16_t>(d.ahi);
     ha.a_lo = P<uint16_t>(d.alo);
     ha.beta = P<float>(d.beta);
+    ha.key_mul = P<uint64_t>(d.kmul);
     set_bounds(ha, d, c->opts.proj);
     ha.w = w;
     ha.prec = c->opts.proj;
@@ -638,6 +650,7 @@ zh_status zh_hash(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* c
     ha.a_hi = P<uint16_t>(d.ahi);
     ha.a_lo = P<uint16_t>(d.alo);
     ha.beta = P<float>(d.beta);
+    ha.key_mul = P<uint64_t>(d.kmul);
     set_bounds(ha, d, c->opts.proj);
     ha.w = d.w;
     ha.prec = c->opts.proj;
@@ -708,6 +721,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     ha.a_hi = P<uint16_t>(d.ahi);
     ha.a_lo = P<uint16_t>(d.alo);
     ha.beta = P<float>(d.beta);
+    ha.key_mul = P<uint64_t>(d.kmul);
     set_bounds(ha, d, c->opts.proj);
     ha.w = d.w;
     ha.prec = c->opts.proj;
@@ -1101,6 +1115,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             ha.a_hi = P<uint16_t>(d.ahi);
             ha.a_lo = P<uint16_t>(d.alo);
             ha.beta = P<float>(d.beta);
+            ha.key_mul = P<uint64_t>(d.kmul);
             set_bounds(ha, d, c->opts.proj);
             ha.w = d.w;
             ha.prec = c->opts.proj;

@@ -17,15 +17,19 @@ __host__ __device__ inline uint64_t fmix64(uint64_t z) {
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kEmptyKey = ~0ull;
 
-// Start value of the bucket-key chain of table l.
-__host__ __device__ inline uint64_t key_seed(int l) {
-    return fmix64(kGolden * (uint64_t)(l + 1));
+// Multiplier of code j of table l in the bucket key (j = 63: the start value
+// of the sum): SplitMix64 output number 64 l + j + 1 from state 0.
+__host__ __device__ inline uint64_t key_mul(int l, int j) {
+    return fmix64(kGolden * (uint64_t)(64 * l + j + 1));
 }
-// One step of the chain: fold one code into the key.
-__host__ __device__ inline uint64_t key_step(uint64_t h, int32_t c) {
-    return fmix64(h ^ (uint64_t)(uint32_t)c);
+// One term of the key sum: uint32(c) times the 64-bit multiplier, mod 2^64.
+__host__ __device__ inline uint64_t key_term(int32_t c, uint64_t mul) {
+    return (uint64_t)(uint32_t)c * mul;
 }
-__host__ __device__ inline uint64_t key_final(uint64_t h) {
+// Bucket key from the wrapped sum of the terms; the empty-slot marker is
+// never a key.
+__host__ __device__ inline uint64_t key_final(uint64_t sum) {
+    const uint64_t h = fmix64(sum);
     return h == kEmptyKey ? kEmptyKey - 1 : h;
 }
 

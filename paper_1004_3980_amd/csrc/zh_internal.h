@@ -55,6 +55,7 @@ struct HashArgs {
     float inv_w;             // fp32 1/w
     float w;
     int prec;                // 0 = fp32 MFMA, 1 = split bf16 MFMA
+    const uint64_t* key_mul; // [L, k + 1] multipliers of the key sum, then its start value
     uint64_t* keys;          // [n, L]
     int32_t* codes;          // [n, L*k] or null
     unsigned int* n_fixed;   // count of codes recomputed in FP64 (nullable)

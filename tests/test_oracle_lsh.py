@@ -113,6 +113,30 @@ def test_keys_identify_code_tuples():
     assert k2[0, 0] != k2[0, 1]
 
 
+def test_key_depends_on_every_position_and_the_order():
+    rng = np.random.default_rng(11)
+    L, k = 3, 7
+    c = rng.integers(-50, 50, size=(200, L * k)).astype(np.int32)
+    base = lsh.bucket_keys(c, L, k)
+    for j in range(L * k):
+        d = c.copy()
+        d[:, j] += 1
+        assert (lsh.bucket_keys(d, L, k)[:, j // k] != base[:, j // k]).all()
+        others = [l for l in range(L) if l != j // k]
+        assert (lsh.bucket_keys(d, L, k)[:, others] == base[:, others]).all()
+    # swapping two unequal codes of a table changes its key
+    s = c.copy()
+    s[:, [0, 1]] = s[:, [1, 0]]
+    diff = c[:, 0] != c[:, 1]
+    assert (lsh.bucket_keys(s, L, k)[diff, 0] != base[diff, 0]).all()
+    # the multipliers are the SplitMix64 stream from state 0, 64 per table
+    gen = lsh.SplitMix64(0)
+    first = [gen.next_u64() for _ in range(64 + 2)]
+    M = lsh.key_multipliers(2, 3)
+    assert int(M[0, 0]) == first[0] and int(M[0, 2]) == first[2] and int(M[1, 1]) == first[65]
+    assert int(M[0, 3]) == first[63] and M.shape == (2, 4)
+
+
 def _brute_candidates(qc, dc, L, k, cap=0):
     """Candidates by comparing the k-tuples of codes directly (no keys)."""
     out = []
