@@ -131,16 +131,41 @@ __device__ __forceinline__ void feature_at(const float* __restrict__ lr, const f
     }
 }
 
-__global__ void k_query_features(const float* __restrict__ lr, const float* __restrict__ maps,
-                                 int h, int w, int mode, float* __restrict__ feat,
-                                 double* __restrict__ mu) {
-    const int Q = (h - kPatch + 1) * (w - kPatch + 1);
-    const int D = mode == 0 ? 25 : 100;
-    const int64_t total = (int64_t)Q * D;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int q = (int)(idx / D), e = (int)(idx % D);
-        feature_at(lr, maps, h, w, mode, q, e, feat + idx, mu + q);
+// One workgroup per segment of up to 64 consecutive patches of one patch row:
+// the first threads form the segment's patch means, then the threads write
+// the segment's features in memory order (coalesced), with the same
+// arithmetic as feature_at.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_query_features(const float* __restrict__ lr, const float* __restrict__ maps,
+                                                        int h, int w, float* __restrict__ feat,
+                                                        double* __restrict__ mu) {
+    constexpr int D = MODE == 0 ? 25 : 100;
+    __shared__ double smu[64];
+    const int nj = w - kPatch + 1;
+    const int nseg = (nj + 63) / 64;
+    const int i = blockIdx.x / nseg, j0 = (blockIdx.x - i * nseg) * 64;
+    const int np = nj - j0 < 64 ? nj - j0 : 64;
+    const int64_t q0 = (int64_t)i * nj + j0;
+    const int t = threadIdx.x;
+    if (t < np) {
+        const double m = patch_mean(lr, w, i, j0 + t);
+        smu[t] = m;
+        mu[q0 + t] = m;
+    }
+    __syncthreads();
+    const int64_t plane = (int64_t)h * w;
+    for (int l = t; l < np * D; l += 256) {
+        const int p = l / D, e = l - p * D;
+        const int j = j0 + p;
+        float v;
+        if (MODE == 0) {
+            const int a = e / kPatch, b = e - a * kPatch;
+            v = (float)((double)lr[(int64_t)(i + a) * w + j + b] - smu[p]);
+        } else {
+            const int ch = e / 25, r = e - ch * 25, a = r / kPatch, b = r - a * kPatch;
+            v = maps[ch * plane + (int64_t)(i + a) * w + j + b];
+        }
+        feat[q0 * D + l] = v;
     }
 }
 
@@ -274,9 +299,15 @@ hipError_t launch_gradient_maps(const float* lr, int n_img, int h, int w, float*
 
 hipError_t launch_query_features(const float* lr, const float* maps, int h, int w, int mode,
                                  float* feat, double* mu, hipStream_t st) {
-    const int64_t total = (int64_t)(h - kPatch + 1) * (w - kPatch + 1) * (mode == 0 ? 25 : 100);
-    hipLaunchKernelGGL(k_query_features, dim3(grid_for(total, 256)), dim3(256), 0, st, lr, maps,
-                       h, w, mode, feat, mu);
+    const int ni = h - kPatch + 1, nj = w - kPatch + 1;
+    if (ni < 1 || nj < 1) return hipSuccess;
+    const int64_t blocks = (int64_t)ni * ((nj + 63) / 64);
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_query_features<0>, grid, dim3(256), 0, st, lr, maps, h, w, feat, mu);
+    else
+        hipLaunchKernelGGL(k_query_features<1>, grid, dim3(256), 0, st, lr, maps, h, w, feat, mu);
     return hipGetLastError();
 }
 
