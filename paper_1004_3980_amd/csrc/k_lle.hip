@@ -437,6 +437,45 @@ __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int3
     }
 }
 
+// Patches of (5s)^2 = 4c values: half a wave per patch, lane l < c of the half
+// holds values 4l .. 4l+3 and reads them from each neighbour's residual row
+// with one 16-byte load (rows start on 16-byte boundaries); the same fused
+// multiply-adds in the same neighbour order as k_synth.
+__global__ __launch_bounds__(256) void k_synth4(int Q, int K, int ps2, const int32_t* __restrict__ ids,
+                                                const int32_t* __restrict__ m, const float* __restrict__ w,
+                                                const double* __restrict__ mu, const float* __restrict__ resid,
+                                                float* __restrict__ xhat) {
+    const int hl = threadIdx.x & 31;
+    const int nc = ps2 >> 2;
+    const int nh = gridDim.x * (blockDim.x >> 5);
+    for (int q = xcd_block() * (blockDim.x >> 5) + (threadIdx.x >> 5); q < Q; q += nh) {
+        const int mq = m[q];
+        if (mq <= 0 || hl >= nc) continue;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int r0 = 0; r0 < mq; r0 += 8) {
+            float4 v[8];
+            float wr[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const bool ok = r0 + r < mq;
+                const int64_t b = ok ? (int64_t)ids[(int64_t)q * K + r0 + r] * ps2 : 0;
+                wr[r] = ok ? w[(int64_t)q * K + r0 + r] : 0.0f;
+                v[r] = ok ? *reinterpret_cast<const float4*>(resid + b + 4 * hl) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                acc.x = fmaf(wr[r], v[r].x, acc.x);
+                acc.y = fmaf(wr[r], v[r].y, acc.y);
+                acc.z = fmaf(wr[r], v[r].z, acc.z);
+                acc.w = fmaf(wr[r], v[r].w, acc.w);
+            }
+        }
+        const float mf = (float)mu[q];
+        *reinterpret_cast<float4*>(xhat + (int64_t)q * ps2 + 4 * hl) =
+            make_float4(mf + acc.x, mf + acc.y, mf + acc.z, mf + acc.w);
+    }
+}
+
 // Per HR pixel: mean of the synthesised patches covering it (patches in
 // row-major order); bicubic of the LR image where no patch covers it.
 __device__ __forceinline__ float blend_at(const float* __restrict__ xhat, const int32_t* __restrict__ m,
@@ -460,13 +499,55 @@ __device__ __forceinline__ float blend_at(const float* __restrict__ xhat, const 
     return cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
 }
 
-__global__ void k_blend(const float* __restrict__ xhat, const int32_t* __restrict__ m,
-                        const float* __restrict__ lr, int h, int w, int s, float* __restrict__ hr) {
+// One workgroup per segment of 256 HR pixels of one HR row Y. For each patch
+// row i covering Y (ascending), the row Y - s i of every patch the segment
+// touches is staged in LDS with coalesced loads (ps consecutive floats per
+// patch), then each pixel adds the staged values of its patches in ascending
+// column order: the order and arithmetic of blend_at.
+constexpr int kBlendSeg = 256;
+__global__ __launch_bounds__(kBlendSeg) void k_blend_rows(const float* __restrict__ xhat, const int32_t* __restrict__ m,
+                                                          const float* __restrict__ lr, int h, int w, int s,
+                                                          float* __restrict__ hr) {
+    __shared__ float sv[1408];   // staged patch rows: at most 1350 floats (s = 3)
+    __shared__ int sm[kBlendSeg + 8];
+    const int ps = kPatch * s, ps2 = ps * ps;
     const int W = s * w;
-    const int64_t total = (int64_t)s * h * W;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x)
-        hr[idx] = blend_at(xhat, m, lr, h, w, s, (int)(idx / W), (int)(idx % W));
+    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
+    const int nseg = (W + kBlendSeg - 1) / kBlendSeg;
+    const int Y = blockIdx.x / nseg;
+    const int X0 = (blockIdx.x - Y * nseg) * kBlendSeg;
+    const int X = X0 + threadIdx.x;
+    const int X1 = min(W, X0 + kBlendSeg) - 1;
+    // patch columns of the segment
+    const int jb0 = X0 - ps + 1 <= 0 ? 0 : (X0 - ps + s) / s;
+    const int jb1 = min(npj - 1, X1 / s);
+    const int njb = jb1 - jb0 + 1;
+    const int ilo = Y - ps + 1 <= 0 ? 0 : (Y - ps + s) / s;
+    const int ihi = min(npi - 1, Y / s);
+    const int jlo = X - ps + 1 <= 0 ? 0 : (X - ps + s) / s;
+    const int jhi = min(npj - 1, X / s);
+    float acc = 0.0f;
+    int cnt = 0;
+    for (int i = ilo; i <= ihi; ++i) {
+        const int u = Y - s * i;
+        const int64_t qrow = (int64_t)i * npj + jb0;
+        __syncthreads();
+        for (int e = threadIdx.x; e < njb; e += kBlendSeg) sm[e] = m[qrow + e] > 0;
+        for (int e = threadIdx.x; e < njb * ps; e += kBlendSeg) {
+            const int jj = e / ps, v = e - jj * ps;
+            sv[e] = xhat[(qrow + jj) * ps2 + u * ps + v];
+        }
+        __syncthreads();
+        if (X < W) {
+            for (int j = jlo; j <= jhi; ++j) {
+                if (sm[j - jb0]) {
+                    acc += sv[(j - jb0) * ps + (X - s * j)];
+                    ++cnt;
+                }
+            }
+        }
+    }
+    if (X < W) hr[(int64_t)Y * W + X] = cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
 }
 
 // Batched: every HR pixel of every image, into the image's output.
@@ -519,6 +600,13 @@ hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t
                         const double* mu, const float* resid, float* xhat, hipStream_t st) {
     if (Q == 0) return hipSuccess;
     if (ps2 > 256) return hipErrorInvalidValue;
+    if ((ps2 & 3) == 0 && ps2 <= 128 && (reinterpret_cast<uintptr_t>(resid) & 15) == 0) {
+        int grid = (Q + 7) / 8;
+        if (grid > 65536) grid = 65536;
+        grid = round_grid8(grid);
+        hipLaunchKernelGGL(k_synth4, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+        return hipGetLastError();
+    }
     int grid = (Q + 3) / 4;
     if (grid > 65536) grid = 65536;
     grid = round_grid8(grid);
@@ -528,10 +616,11 @@ hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t
 
 hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, int h, int w, int scale,
                         float* hr, hipStream_t st) {
-    const int64_t total = (int64_t)scale * h * scale * w;
-    int64_t g = (total + 255) / 256;
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_blend, dim3((unsigned)g), dim3(256), 0, st, xhat, m, lr, h, w, scale, hr);
+    const int64_t H = (int64_t)scale * h, W = (int64_t)scale * w;
+    if (H == 0 || W == 0) return hipSuccess;
+    const int64_t g = H * ((W + kBlendSeg - 1) / kBlendSeg);
+    if (g > 0x7FFFFFFF || scale < 1 || scale > 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_blend_rows, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, scale, hr);
     return hipGetLastError();
 }
 
