@@ -414,84 +414,170 @@ float screen_coeff(int D) {
     return (float)(2.0 * c);
 }
 
-// Exact fp32 distances |q - x|^2 of the candidates cids[c0..c1) from both
-// planes, eight lanes per row (16 coordinates each), into cdist; a row whose
-// fp32 distance is 0 is checked for exact equality with the query (flag bit).
-__device__ __forceinline__ void exact_rows(const SearchArgs& a, const float* sq, const uint32_t* cids,
-                                           uint32_t* cdist, int c0, int c1) {
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Gram matrix G[i][j] = sum_c z_i[c] z_j[c] of the eight rows of one exact
+// pass (lane = 8 row + group g, z = the lane's 16 coordinates 16 g + e), on
+// the matrix cores: 16 steps of a 16x16x4 product whose operand rows 0..7
+// carry the eight rows' first 64 coordinates and rows 8..15 their last 64,
+// each value fetched from the lane that holds it; A and B are the same
+// register, and the two diagonal 8x8 blocks of the product add up to G.
+// Writes sG[8][8].
+template <typename T>
+__device__ __forceinline__ void gram_mfma(const T (&z)[16], T* sG) {
+    const int lane = threadIdx.x;
+    const int col = lane & 15, kk = lane >> 4;
+    // operand lane (row r = l % 16, k = l / 16) of step t: coordinate 16 g + t
+    // of neighbour r % 8, with g = 4 (r / 8) + k: rows 0..7 take the first 64
+    // coordinates, rows 8..15 the last 64
+    const int src = (col & 7) * 8 + 4 * (col >> 3) + kk;
+    typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type acc = {};
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const T v = __shfl(z[t], src);
+        if constexpr (sizeof(T) == 4)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v, v, acc, 0, 0, 0);
+        else
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+    // G = C[0..7][0..7] + C[8..15][8..15] (the other quadrants mix the halves)
+    if constexpr (sizeof(T) == 4) {
+        // fp32: lane l holds C[4 (l / 16) + i][l % 16]
+        T o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = __shfl(acc[i], (lane + 40) & 63);
+        if (kk < 2 && col < 8) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sG[(4 * kk + i) * 8 + col] = acc[i] + o[i];
+        }
+    } else {
+        // FP64: lane l holds C[4 i + l / 16][l % 16]
+        T o[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) o[i] = __shfl(acc[i + 2], (lane + 8) & 63);
+        if (col < 8) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) sG[(4 * i + kk) * 8 + col] = acc[i] + o[i];
+        }
+    }
+}
+
+// Exact fp32 distances |q - x|^2 of the candidates cids[cb..min(cb+8, c1))
+// from both planes, eight lanes per row (16 coordinates each), into cdist; a
+// row whose fp32 distance is 0 is checked for exact equality with the query
+// (flag bit). GT float or double: also the Gram matrix of the pass's rows in
+// that precision, into sG[8][8] (rows past c1 zero); GT int: none.
+template <typename GT>
+__device__ __forceinline__ void exact_pass(const SearchArgs& a, const float* sq, const uint32_t* cids,
+                                           uint32_t* cdist, int cb, int c1, GT* sG) {
     const int lane = threadIdx.x;
     const int D = a.D, HS = a.hs;
     const int rg = lane >> 3, g = lane & 7;
     const int nvg = D - 16 * g;
-    for (int cb = c0; cb < c1; cb += 8) {
-        const int c = cb + rg;
-        const bool cv = c < c1;
-        const uint32_t id = cv ? cids[c] : 0u;
-        const size_t bo = ((size_t)id * (uint32_t)D + 16u * g) * 2u;
-        const size_t bh = ((size_t)id * (uint32_t)HS + 16u * g) * 2u;
-        uint4 h[2], l[2];
+    const int c = cb + rg;
+    const bool cv = c < c1;
+    const uint32_t id = cv ? cids[c] : 0u;
+    const size_t bo = ((size_t)id * (uint32_t)D + 16u * g) * 2u;
+    const size_t bh = ((size_t)id * (uint32_t)HS + 16u * g) * 2u;
+    uint4 h[2], l[2];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            h[u] = make_uint4(0u, 0u, 0u, 0u);
-            l[u] = h[u];
-            if (cv && 16 * g + 8 * u < D) {
-                h[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.hi) + bh + 16 * u);
-                l[u] = ld16(reinterpret_cast<const char*>(a.lo) + bo + 16 * u);
-            }
-            const int nv = nvg - 8 * u;
-            if (nv < 8) {
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const uint32_t km = keep_mask(nv, w);
-                    (&h[u].x)[w] &= km;
-                    (&l[u].x)[w] &= km;
-                }
-            }
+    for (int u = 0; u < 2; ++u) {
+        h[u] = make_uint4(0u, 0u, 0u, 0u);
+        l[u] = h[u];
+        if (cv && 16 * g + 8 * u < D) {
+            h[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.hi) + bh + 16 * u);
+            l[u] = ld16(reinterpret_cast<const char*>(a.lo) + bo + 16 * u);
         }
-        float qv[16];
-#pragma unroll
-        for (int e4 = 0; e4 < 4; ++e4) {
-            const float4 t4 = *reinterpret_cast<const float4*>(sq + 16 * g + 4 * e4);
-            qv[4 * e4] = t4.x;
-            qv[4 * e4 + 1] = t4.y;
-            qv[4 * e4 + 2] = t4.z;
-            qv[4 * e4 + 3] = t4.w;
-        }
-        float p = 0.0f;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
-            const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
+        const int nv = nvg - 8 * u;
+        if (nv < 8) {
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const float y0 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u));
-                const float y1 = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u));
-                const float d0 = qv[8 * u + 2 * w] - y0;
-                const float d1 = qv[8 * u + 2 * w + 1] - y1;
-                p = fmaf(d0, d0, p);
-                p = fmaf(d1, d1, p);
+                const uint32_t km = keep_mask(nv, w);
+                (&h[u].x)[w] &= km;
+                (&l[u].x)[w] &= km;
             }
         }
-        p += __shfl_xor(p, 1);
-        p += __shfl_xor(p, 2);
-        p += __shfl_xor(p, 4);
-        bool exact_row = false;
-        if (__ballot(cv && p == 0.0f) != 0) {
-            bool eq = true;
+    }
+    float qv[16];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
-                const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
+    for (int e4 = 0; e4 < 4; ++e4) {
+        const float4 t4 = *reinterpret_cast<const float4*>(sq + 16 * g + 4 * e4);
+        qv[4 * e4] = t4.x;
+        qv[4 * e4 + 1] = t4.y;
+        qv[4 * e4 + 2] = t4.z;
+        qv[4 * e4 + 3] = t4.w;
+    }
+    float y[16];
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u) == __float_as_uint(qv[8 * u + 2 * w]);
-                    eq = eq && __builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u) == __float_as_uint(qv[8 * u + 2 * w + 1]);
-                }
-            }
-            const uint32_t grp = (uint32_t)(__ballot(eq) >> (8 * rg)) & 0xFFu;
-            exact_row = grp == 0xFFu;
+    for (int u = 0; u < 2; ++u) {
+        const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
+        const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            y[8 * u + 2 * w] = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u));
+            y[8 * u + 2 * w + 1] = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u));
         }
-        if (g == 0 && cv) cdist[c] = __float_as_uint(p) | (exact_row ? 0x80000000u : 0u);
+    }
+    float p = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const float d = qv[e] - y[e];
+        p = fmaf(d, d, p);
+    }
+    p += __shfl_xor(p, 1);
+    p += __shfl_xor(p, 2);
+    p += __shfl_xor(p, 4);
+    bool exact_row = false;
+    if (__ballot(cv && p == 0.0f) != 0) {
+        bool eq = true;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) eq = eq && __float_as_uint(y[e]) == __float_as_uint(qv[e]);
+        const uint32_t grp = (uint32_t)(__ballot(eq) >> (8 * rg)) & 0xFFu;
+        exact_row = grp == 0xFFu;
+    }
+    if (g == 0 && cv) cdist[c] = __float_as_uint(p) | (exact_row ? 0x80000000u : 0u);
+    if constexpr (!std::is_same<GT, int>::value) {
+        GT z[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) z[e] = cv ? (GT)qv[e] - (GT)y[e] : (GT)0;
+        gram_mfma<GT>(z, sG);
+    }
+}
+
+__device__ __forceinline__ void exact_rows(const SearchArgs& a, const float* sq, const uint32_t* cids,
+                                           uint32_t* cdist, int c0, int c1) {
+    for (int cb = c0; cb < c1; cb += 8) exact_pass<int>(a, sq, cids, cdist, cb, c1, nullptr);
+}
+
+// Packed lower triangle (p = i (i + 1) / 2 + j, 36 entries) of the Gram
+// matrix of the Kp final neighbours into gram[q]: lane r < Kp holds the r-th
+// neighbour's id. When every neighbour is one of the nA rows whose Gram
+// matrix sG was formed in the first exact pass (cids[0..nA)), the entries are
+// taken from it; otherwise the rows of the neighbours are read again.
+template <typename GT>
+__device__ void write_gram(const SearchArgs& a, int q, const float* sq, uint32_t* cids, uint32_t* cdist, int nA,
+                           int Kp, uint32_t oid, GT* sG) {
+    const int lane = threadIdx.x;
+    int pi = -1;
+    for (int s = 0; s < nA; ++s)
+        if (cids[s] == oid) pi = s;
+    const bool all = __ballot(lane < Kp && pi < 0) == 0;
+    if (!all) {
+        // rare: a neighbour outside the first pass; its rows in final order
+        __syncthreads();
+        if (lane < Kp) cids[lane] = oid;
+        __syncthreads();
+        exact_pass<GT>(a, sq, cids, cdist, 0, Kp, sG);
+        pi = lane;
+    }
+    __syncthreads();
+    GT* out = reinterpret_cast<GT*>(a.gram) + (int64_t)q * 36;
+    if (lane < 36) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= lane) ++i;
+        const int j = lane - i * (i + 1) / 2;
+        const int pa = __shfl(pi, i), pb = __shfl(pi, j);
+        out[lane] = i < Kp ? sG[pa * 8 + pb] : (GT)0;
     }
 }
 
@@ -552,8 +638,9 @@ __device__ void mark_smallest(const uint32_t (&kv)[NSL], const uint32_t (&tie)[N
 //  3. Exact fp32 distances from both planes of the full features.
 //  4. Sorted selection of the K best, certification (exact form), output.
 // Eight waves per SIMD (64 registers; the rarely taken paths spill a few
-// bytes) hide more of the dependent memory round trips than six.
-template <int NS, bool EXACT, int NSL>
+// bytes) hide more of the dependent memory round trips than six. GT float or
+// double: the Gram matrix of the neighbours is formed too (K <= 8).
+template <bool EXACT, int NSL, typename GT>
 __global__ __launch_bounds__(64, 8) void k_search_cap(SearchArgs a) {
     // dynamic LDS: hash set [hsz] of (id << 32 | first lane), empty = ~0, then
     // the candidate IDs and values [cp] each, cp = max(64, next_pow2(cap));
@@ -659,6 +746,7 @@ __global__ __launch_bounds__(64, 8) void k_search_cap(SearchArgs a) {
 
         // ---- 2. screen lower bounds, exact distances of the K lowest, U_K
         int Mr = M;
+        int nA = 0;   // rows of the first exact pass (cids[0..nA)), whose Gram matrix is in hset
         if (M > a.K) {
             const int K = a.K;
             uint4 qb[2];
@@ -740,7 +828,12 @@ __global__ __launch_bounds__(64, 8) void k_search_cap(SearchArgs a) {
                 pos += __popcll(bal);
             }
             __syncthreads();
-            exact_rows(a, sq, cids, cdist, 0, K);
+            if constexpr (std::is_same<GT, int>::value) {
+                exact_rows(a, sq, cids, cdist, 0, K);
+            } else {
+                exact_pass<GT>(a, sq, cids, cdist, 0, K, reinterpret_cast<GT*>(hset));
+                nA = K;
+            }
             __syncthreads();
             // U_K: the largest upper bound of the K exact distances
             const Bounds bd{2.0 * gamma_n(D + 3, 1.0 / 16777216.0), (double)D * 1.2e-38};
@@ -778,6 +871,10 @@ __global__ __launch_bounds__(64, 8) void k_search_cap(SearchArgs a) {
             Mr = K + S;
             // ---- 3. exact distances of the remaining survivors
             if (S > 0) exact_rows(a, sq, cids, cdist, K, Mr);
+        } else if (!std::is_same<GT, int>::value && M <= 8) {
+            // ---- 3. exact distances of all candidates, and their Gram matrix
+            exact_pass<GT>(a, sq, cids, cdist, 0, M, reinterpret_cast<GT*>(hset));
+            nA = M;
         } else {
             // ---- 3. exact distances of all candidates
             exact_rows(a, sq, cids, cdist, 0, M);
@@ -797,6 +894,7 @@ __global__ __launch_bounds__(64, 8) void k_search_cap(SearchArgs a) {
             od = key_dist(mykey);
         }
         write_result(a, q, Kp, oid, od);
+        if constexpr (!std::is_same<GT, int>::value) write_gram<GT>(a, q, sq, cids, cdist, nA, Kp, oid, reinterpret_cast<GT*>(hset));
         __syncthreads();
     }
 }
@@ -905,19 +1003,24 @@ constexpr int kUnionBig = 8192;   // uncapped, deferred patches
 
 static int cap_hash_slots_min(int cap) { return (5 * (cap + 63) + 2) / 3; }
 
-template <int NS, int NSL>
+template <int NSL, typename GT>
+static void launch_cap_g(const SearchArgs& a, int grid, size_t lds, hipStream_t st) {
+    if (a.exact) hipLaunchKernelGGL((k_search_cap<true, NSL, GT>), dim3(grid), dim3(64), lds, st, a);
+    else hipLaunchKernelGGL((k_search_cap<false, NSL, GT>), dim3(grid), dim3(64), lds, st, a);
+}
+template <int NSL>
 static void launch_cap_n(const SearchArgs& a, int grid, size_t lds, hipStream_t st) {
-    if (a.exact) hipLaunchKernelGGL((k_search_cap<NS, true, NSL>), dim3(grid), dim3(64), lds, st, a);
-    else hipLaunchKernelGGL((k_search_cap<NS, false, NSL>), dim3(grid), dim3(64), lds, st, a);
+    if (!a.gram) launch_cap_g<NSL, int>(a, grid, lds, st);
+    else if (a.gram_fp64) launch_cap_g<NSL, double>(a, grid, lds, st);
+    else launch_cap_g<NSL, float>(a, grid, lds, st);
 }
 // one wave (workgroup) per patch: no loop over patches, so that nothing is
 // held in registers from one patch to the next
-template <int NS>
 static void launch_cap(const SearchArgs& a, hipStream_t st) {
     const int grid = round_grid8(a.Q);
     const size_t lds = (size_t)a.hsz * sizeof(uint64_t) + 2 * (size_t)a.cp * sizeof(uint32_t);
-    if (a.cap <= 128) launch_cap_n<NS, 2>(a, grid, lds, st);
-    else launch_cap_n<NS, 4>(a, grid, lds, st);
+    if (a.cap <= 128) launch_cap_n<2>(a, grid, lds, st);
+    else launch_cap_n<4>(a, grid, lds, st);
 }
 
 hipError_t launch_search(const SearchArgs& a_in, hipStream_t st) {
@@ -935,12 +1038,8 @@ hipError_t launch_search(const SearchArgs& a_in, hipStream_t st) {
         int cp = 64;
         while (cp < a.cap) cp <<= 1;
         a.cp = cp;
-        switch ((a.D + 31) / 32) {
-            case 1: launch_cap<1>(a, st); break;
-            case 2: launch_cap<2>(a, st); break;
-            case 3: launch_cap<3>(a, st); break;
-            default: launch_cap<4>(a, st); break;
-        }
+        if (a.gram && a.K > 8) return hipErrorInvalidValue;
+        launch_cap(a, st);
         return hipGetLastError();
     }
     const bool v4 = a.D % 4 == 0;

@@ -62,6 +62,8 @@ struct zh_ctx {
     // last query
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
+    bool gram_ready = false;      // gram holds the Gram matrices of the last search's neighbours
+    int gram_fp64 = 0;            // ... in FP64 (else fp32)
     double lam = 0.0;             // lambda of the last zh_lle_weights
     // batched form: plan of the last batch, its captured graph, tuning
     struct BatchGroup {
@@ -365,6 +367,12 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
         a.out_nsurv = P<int32_t>(c->nsurv);
         TRY(ensure(c, c->qrot, sizeof(float) * kRotStride * (size_t)(a.Q > 0 ? a.Q : 1)));
         a.qrot = P<float>(c->qrot);
+        if (a.K <= 8) {
+            // the search forms the Gram matrices of the neighbours as well
+            a.gram_fp64 = c->opts.lle_fp64;
+            TRY(ensure(c, c->gram, (a.gram_fp64 ? 8 : 4) * (size_t)(a.Q > 0 ? a.Q : 1) * 36));
+            a.gram = c->gram.p;
+        }
         HIPCHK(c, launch_rotate(a.qfeat, a.Q, d.D, P<uint16_t>(d.phi_hi), P<uint16_t>(d.phi_lo), d.rot_c1,
                                 P<float>(c->qrot), c->stream));
     }
@@ -372,8 +380,11 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.dump_cap = dump_cap;
     a.overflow = P<int32_t>(c->over);
     a.counters = P<unsigned int>(c->counters);
+    c->gram_ready = false;
     HIPCHK(c, launch_search(a, c->stream));
     if (a.cap == 0) HIPCHK(c, launch_search_overflow(a, 1024, c->stream));
+    c->gram_ready = a.gram != nullptr;
+    c->gram_fp64 = a.gram_fp64;
     return ZH_OK;
 }
 
@@ -769,7 +780,7 @@ zh_status zh_lle_weights(zh_ctx* c, double lambda) {
         const int f64 = c->opts.lle_fp64;
         TRY(ensure(c, c->gram, (f64 ? 8 : 4) * (size_t)c->Q * 36));
         StageTimer t(c, ZH_T_LLE);
-        HIPCHK(c, launch_gram(a, c->gram.p, f64, c->stream));
+        if (!(c->gram_ready && c->gram_fp64 == f64)) HIPCHK(c, launch_gram(a, c->gram.p, f64, c->stream));
         HIPCHK(c, launch_lle_solve(a, c->gram.p, f64, c->stream));
     } else {
         StageTimer t(c, ZH_T_LLE);
@@ -1142,7 +1153,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             la.w = P<float>(c->w);
             la.n_fp64 = P<unsigned int>(c->counters) + C_LLE64;
             if (K <= 8) {
-                HIPCHK(c, launch_gram(la, c->gram.p, c->opts.lle_fp64, st));
+                if (!c->gram_ready) HIPCHK(c, launch_gram(la, c->gram.p, c->opts.lle_fp64, st));
                 HIPCHK(c, launch_lle_solve(la, c->gram.p, c->opts.lle_fp64, st));
             } else {
                 HIPCHK(c, launch_lle(la, st));

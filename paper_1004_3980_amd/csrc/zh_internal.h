@@ -93,6 +93,8 @@ struct SearchArgs {
     const uint16_t* sc;      // [N, screen_stride(D)] screen plane (early-stop search)
     const float* qrot;       // [Q, 64] rotated queries: y_q, zeros, rho_q in the last slot
     float inv_s2;            // lower bound of 1 / sigma_max(Phi)^2
+    void* gram;              // [Q, 36] packed Gram matrices of the neighbours (K <= 8), or null
+    int gram_fp64;           // their precision: FP64 or fp32
     const uint2* bins;       // [Q, L] (offset, count) of the query's bin in each table
     const float* qfeat;      // [Q, D]
     const uint32_t* tids;    // [L, N]
