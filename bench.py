@@ -38,21 +38,27 @@ def psnr(x, ref):
     return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
 
 
-def search_bytes(ncand, nsurv, wl):
-    """Algorithmic HBM bytes of one launch of the search kernel (each byte the
-    kernel needs, read or written once).
+def search_bytes(ncand, nsurv, wl, gram_bytes):
+    """Algorithmic HBM bytes of one launch of the early-stop search kernel
+    (each byte the kernel needs, read or written once).
 
     Per patch: its L bins (offset, count: 8 B each), its feature row (4D B),
-    the output (K ids, K distances, count, candidate count, survivor count).
-    Per distinct candidate: its ID (4 B) and its high-plane row with the
-    16-byte-aligned tail (2 hi_stride(D) B). Per survivor of the pre-filter:
-    the low-plane row (2D B)."""
+    its rotated coordinates (64 floats), the output (K ids, K distances,
+    count, candidate count, survivor count) and the packed Gram matrix of the
+    neighbours (36 entries of gram_bytes). Per distinct candidate: its ID
+    (4 B) and its screen row (2 screen_stride(D) B: the coordinates in the
+    leading principal directions and the bounds). Per row given an exact
+    distance: its high- and low-plane rows (2 hi_stride(D) + 2D B)."""
     M = ncand.astype(np.int64)
     S = nsurv.astype(np.int64)
     D, L, K = wl.D, wl.L, wl.K
     hs = ((((D + 3) & ~3) + 4) + 7) & ~7
-    per_q = 8 * L + 4 * D + 8 * K + 12
-    return int(len(M) * per_q + (M * (4 + 2 * hs)).sum() + (S * 2 * D).sum())
+    m = min(D, 60)
+    ss = 32
+    while ss < ((m + 3) & ~3) + 4:
+        ss *= 2
+    per_q = 8 * L + 4 * D + 4 * 64 + 8 * K + 12 + 36 * gram_bytes
+    return int(len(M) * per_q + (M * (4 + 2 * ss)).sum() + (S * (2 * hs + 2 * D)).sum())
 
 
 def traffic_from_profile(form):
@@ -168,7 +174,7 @@ def main():
 
     # dominant kernel: the candidate search
     dom = max(("hash", "search", "lle", "synth", "blend"), key=lambda k: ms_stage[k])
-    sb = search_bytes(res["ncand"], res["nsurv"], wl)
+    sb = search_bytes(res["ncand"], res["nsurv"], wl, 4 if args.form == "screened" else 8)
     ach = sb / (ms_stage["search"] * 1e-3) / 1e9
     traffic = traffic_from_profile(args.form)
     roof = {"bound": "hbm", "kernel": "k_search", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,

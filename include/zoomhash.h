@@ -267,13 +267,17 @@ zh_status zh_stats(zh_ctx* ctx, zh_stats_t* out);
 
 /* ---- stage timing (HIP events on the context's stream) ----------------- */
 enum { ZH_T_FEATURES = 0, ZH_T_HASH = 1, ZH_T_SEARCH = 2, ZH_T_LLE = 3, ZH_T_SYNTH = 4,
-       ZH_T_BLEND = 5, ZH_T_BP_ERROR = 6, ZH_T_BP_UPDATE = 7, ZH_T_COUNT = 8 };
+       ZH_T_BLEND = 5, ZH_T_BP_ERROR = 6, ZH_T_BP_UPDATE = 7, ZH_T_ROTATE = 8, ZH_T_COUNT = 9 };
+/* ZH_T_SEARCH times the candidate search kernel alone; ZH_T_ROTATE the
+ * projection of the queries onto the dictionary's screen directions that
+ * precedes it (early-stop search only). */
 /* on != 0: bracket every kernel launch of the stages above with a pair of HIP
  * events (at most 256 launches per stage between two zh_get_timing calls;
  * later launches are not timed). on = 0 stops recording. */
 zh_status zh_set_timing(zh_ctx* ctx, int on);
-/* Synchronise, then write for each stage the summed milliseconds (ms[8]) and
- * the number of timed launches (launches[8], may be NULL) since the previous
+/* Synchronise, then write for each stage the summed milliseconds
+ * (ms[ZH_T_COUNT]) and the number of timed launches (launches[ZH_T_COUNT],
+ * may be NULL) since the previous
  * call, and start a new period. */
 zh_status zh_get_timing(zh_ctx* ctx, double* ms, int32_t* launches);
 

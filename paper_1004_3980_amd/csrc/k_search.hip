@@ -498,32 +498,22 @@ __device__ __forceinline__ void exact_pass(const SearchArgs& a, const float* sq,
             }
         }
     }
-    float qv[16];
-#pragma unroll
-    for (int e4 = 0; e4 < 4; ++e4) {
-        const float4 t4 = *reinterpret_cast<const float4*>(sq + 16 * g + 4 * e4);
-        qv[4 * e4] = t4.x;
-        qv[4 * e4 + 1] = t4.y;
-        qv[4 * e4 + 2] = t4.z;
-        qv[4 * e4 + 3] = t4.w;
-    }
-    float y[16];
+    // z = q - x in fp32, one perm per coordinate (the high and low halves of
+    // x joined); x itself is rebuilt only for the rare exact-equality check
+    float z[16];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        const uint32_t hw[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
-        const uint32_t lw[4] = {l[u].x, l[u].y, l[u].z, l[u].w};
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            y[8 * u + 2 * w] = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x05040100u));
-            y[8 * u + 2 * w + 1] = __uint_as_float(__builtin_amdgcn_perm(hw[w], lw[w], 0x07060302u));
+            const float2 q2 = *reinterpret_cast<const float2*>(sq + 16 * g + 8 * u + 2 * w);
+            const uint32_t hw = (&h[u].x)[w], lw = (&l[u].x)[w];
+            z[8 * u + 2 * w] = q2.x - __uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x05040100u));
+            z[8 * u + 2 * w + 1] = q2.y - __uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x07060302u));
         }
     }
     float p = 0.0f;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const float d = qv[e] - y[e];
-        p = fmaf(d, d, p);
-    }
+    for (int e = 0; e < 16; ++e) p = fmaf(z[e], z[e], p);
     p += __shfl_xor(p, 1);
     p += __shfl_xor(p, 2);
     p += __shfl_xor(p, 4);
@@ -531,16 +521,37 @@ __device__ __forceinline__ void exact_pass(const SearchArgs& a, const float* sq,
     if (__ballot(cv && p == 0.0f) != 0) {
         bool eq = true;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) eq = eq && __float_as_uint(y[e]) == __float_as_uint(qv[e]);
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float2 q2 = *reinterpret_cast<const float2*>(sq + 16 * g + 8 * u + 2 * w);
+                const uint32_t hw = (&h[u].x)[w], lw = (&l[u].x)[w];
+                eq = eq && __builtin_amdgcn_perm(hw, lw, 0x05040100u) == __float_as_uint(q2.x);
+                eq = eq && __builtin_amdgcn_perm(hw, lw, 0x07060302u) == __float_as_uint(q2.y);
+            }
+        }
         const uint32_t grp = (uint32_t)(__ballot(eq) >> (8 * rg)) & 0xFFu;
         exact_row = grp == 0xFFu;
     }
     if (g == 0 && cv) cdist[c] = __float_as_uint(p) | (exact_row ? 0x80000000u : 0u);
-    if constexpr (!std::is_same<GT, int>::value) {
-        GT z[16];
+    if constexpr (std::is_same<GT, float>::value) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) z[e] = cv ? (GT)qv[e] - (GT)y[e] : (GT)0;
-        gram_mfma<GT>(z, sG);
+        for (int e = 0; e < 16; ++e) z[e] = cv ? z[e] : 0.0f;
+        gram_mfma<float>(z, sG);
+    } else if constexpr (std::is_same<GT, double>::value) {
+        // exact differences: q - x in FP64 from the fp32 values
+        double zd[16];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float2 q2 = *reinterpret_cast<const float2*>(sq + 16 * g + 8 * u + 2 * w);
+                const uint32_t hw = (&h[u].x)[w], lw = (&l[u].x)[w];
+                zd[8 * u + 2 * w] = cv ? (double)q2.x - (double)__uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x05040100u)) : 0.0;
+                zd[8 * u + 2 * w + 1] = cv ? (double)q2.y - (double)__uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x07060302u)) : 0.0;
+            }
+        }
+        gram_mfma<double>(zd, sG);
     }
 }
 
@@ -637,11 +648,12 @@ __device__ void mark_smallest(const uint32_t (&kv)[NSL], const uint32_t (&tie)[N
 //     screened form keeps at most R in all, by smallest L).
 //  3. Exact fp32 distances from both planes of the full features.
 //  4. Sorted selection of the K best, certification (exact form), output.
-// Eight waves per SIMD (64 registers; the rarely taken paths spill a few
-// bytes) hide more of the dependent memory round trips than six. GT float or
-// double: the Gram matrix of the neighbours is formed too (K <= 8).
+// Seven waves per SIMD (72 registers, a few bytes of spill) hide more of the
+// dependent memory round trips than six without spill, and spill less than
+// eight. GT float or double: the Gram matrix of the neighbours is formed too
+// (K <= 8).
 template <bool EXACT, int NSL, typename GT>
-__global__ __launch_bounds__(64, 8) void k_search_cap(SearchArgs a) {
+__global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
     // dynamic LDS: hash set [hsz] of (id << 32 | first lane), empty = ~0, then
     // the candidate IDs and values [cp] each, cp = max(64, next_pow2(cap));
     // after the union the hash set holds the screen tails (float2 per candidate)

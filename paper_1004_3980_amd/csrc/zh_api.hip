@@ -373,6 +373,7 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
             TRY(ensure(c, c->gram, (a.gram_fp64 ? 8 : 4) * (size_t)(a.Q > 0 ? a.Q : 1) * 36));
             a.gram = c->gram.p;
         }
+        StageTimer t(c, ZH_T_ROTATE);
         HIPCHK(c, launch_rotate(a.qfeat, a.Q, d.D, P<uint16_t>(d.phi_hi), P<uint16_t>(d.phi_lo), d.rot_c1,
                                 P<float>(c->qrot), c->stream));
     }
@@ -381,8 +382,11 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.overflow = P<int32_t>(c->over);
     a.counters = P<unsigned int>(c->counters);
     c->gram_ready = false;
-    HIPCHK(c, launch_search(a, c->stream));
-    if (a.cap == 0) HIPCHK(c, launch_search_overflow(a, 1024, c->stream));
+    {
+        StageTimer t(c, ZH_T_SEARCH);
+        HIPCHK(c, launch_search(a, c->stream));
+        if (a.cap == 0) HIPCHK(c, launch_search_overflow(a, 1024, c->stream));
+    }
     c->gram_ready = a.gram != nullptr;
     c->gram_fp64 = a.gram_fp64;
     return ZH_OK;
@@ -747,10 +751,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
         StageTimer t(c, ZH_T_HASH);
         HIPCHK(c, launch_hash(ha, c->stream));
     }
-    {
-        StageTimer t(c, ZH_T_SEARCH);
-        TRY(run_search(c, d, nullptr, 0));
-    }
+    TRY(run_search(c, d, nullptr, 0));
     c->stage = 1;
     return ZH_OK;
 }

@@ -90,7 +90,7 @@ SIGNATURES = {
     "zh_set_timing": [_V, _I],
     "zh_get_timing": [_V, _V, _V],
 }
-STAGES = ["features", "hash", "search", "lle", "synth", "blend", "bp_error", "bp_update"]
+STAGES = ["features", "hash", "search", "lle", "synth", "blend", "bp_error", "bp_update", "rotate"]
 
 _lib = None
 
