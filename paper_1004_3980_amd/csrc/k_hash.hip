@@ -41,9 +41,14 @@ __device__ __forceinline__ int32_t floor_sat(double t) {
     return (int32_t)f;
 }
 
+// |x| of eight bf16 values: the sign bits cleared, one 32-bit AND per pair
 __device__ __forceinline__ u16x8 abs8(u16x8 x) {
-    const u16x8 m = {0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF, 0x7FFF};
-    return x & m;
+    uint4 w = __builtin_bit_cast(uint4, x);
+    w.x &= 0x7FFF7FFFu;
+    w.y &= 0x7FFF7FFFu;
+    w.z &= 0x7FFF7FFFu;
+    w.w &= 0x7FFF7FFFu;
+    return __builtin_bit_cast(u16x8, w);
 }
 
 __device__ __forceinline__ void probe_bin_h(const Slot* __restrict__ dir, uint64_t cap, uint64_t key,
