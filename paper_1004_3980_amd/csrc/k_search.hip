@@ -768,30 +768,38 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
                 qb[s] = ri < 2 ? t4 : make_uint4(0u, 0u, 0u, 0u);
             }
             const int nss = SS >> 5;
-            for (int t = 0; t < M; t += 16) {
+            // screen rows of 16 candidates: lane (ri, kb) holds coordinates
+            // 32 s + 8 kb .. + 7 of candidate t + ri; the row tail goes to stl
+            auto load_chunk = [&](int t, uint4 (&v)[2]) {
                 const int c = t + ri;
                 const bool cv = c < M;
                 const uint32_t id = cv ? cids[c] : 0u;
                 const char* rowp = reinterpret_cast<const char*>(a.sc) + (size_t)id * (uint32_t)(2 * SS);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    v[s] = make_uint4(0u, 0u, 0u, 0u);
+                    if (s < nss && cv) v[s] = *reinterpret_cast<const uint4*>(rowp + 2 * (32 * s + 8 * kb));
+                }
+            };
+            auto screen_chunk = [&](int t, uint4 (&v)[2]) {
+                const int c = t + ri;
+                const bool cv = c < M;
                 f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     if (s < nss) {
                         const int d = 32 * s + 8 * kb;
-                        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                        if (cv) {
-                            v = *reinterpret_cast<const uint4*>(rowp + 2 * d);
-                            if (d <= TS && TS < d + 8) stl[c] = TS == d ? make_float2(__uint_as_float(v.x), __uint_as_float(v.y))
-                                                                      : make_float2(__uint_as_float(v.z), __uint_as_float(v.w));
-                            const int nv = TS - d;
-                            if (nv < 8) {
-                                v.x &= keep_mask(nv, 0);
-                                v.y &= keep_mask(nv, 1);
-                                v.z &= keep_mask(nv, 2);
-                                v.w &= keep_mask(nv, 3);
-                            }
+                        if (cv && d <= TS && TS < d + 8)
+                            stl[c] = TS == d ? make_float2(__uint_as_float(v[s].x), __uint_as_float(v[s].y))
+                                             : make_float2(__uint_as_float(v[s].z), __uint_as_float(v[s].w));
+                        const int nv = TS - d;
+                        if (nv < 8) {
+                            v[s].x &= keep_mask(nv, 0);
+                            v[s].y &= keep_mask(nv, 1);
+                            v[s].z &= keep_mask(nv, 2);
+                            v[s].w &= keep_mask(nv, 3);
                         }
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v),
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v[s]),
                                                                      __builtin_bit_cast(bf16x8, qb[s]), acc, 0, 0, 0);
                     }
                 }
@@ -806,6 +814,14 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
                         if (cc < M) cdist[cc] = __float_as_uint(acc[r] + lo4[r]);
                     }
                 }
+            };
+            // two chunks in flight per step
+            for (int t = 0; t < M; t += 32) {
+                uint4 v0[2], v1[2];
+                load_chunk(t, v0);
+                load_chunk(t + 16, v1);
+                screen_chunk(t, v0);
+                if (t + 16 < M) screen_chunk(t + 16, v1);
             }
             __syncthreads();
             // |y_q - y~| >= a_lo from the screen value and its error bound c (|y_q|^2 + |y~|^2);
