@@ -238,27 +238,6 @@ __global__ void k_split_planes(const float* __restrict__ x, int64_t n, int D, ui
     }
 }
 
-// Row tail of the high plane: |x_hi|^2 summed in fp32 in index order, and
-// |x - x_hi| from an FP64 sum, rounded up to fp32 (with a relative margin
-// for the FP64 rounding).
-__global__ void k_hi_tails(const float* __restrict__ x, int64_t n, int D, uint16_t* __restrict__ hi) {
-    const int hs = hi_stride(D);
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        double e = 0.0;
-        for (int i = 0; i < D; ++i) {
-            const float v = x[r * D + i];
-            const float h = __uint_as_float(__float_as_uint(v) & 0xFFFF0000u);
-            s = fmaf(h, h, s);
-            const double d = (double)v - (double)h;
-            e += d * d;
-        }
-        const float rho = __double2float_ru(sqrt(e) * (1.0 + 1e-12));
-        float* tail = reinterpret_cast<float*>(hi + r * hs + hi_tail(D));
-        tail[0] = s;
-        tail[1] = rho;
-    }
-}
 
 __global__ void k_bicubic(const float* __restrict__ lr, int h, int w, int s, float* __restrict__ out) {
     const int H = s * h, W = s * w;
@@ -350,11 +329,6 @@ hipError_t launch_split_planes(const float* x, int64_t n, int D, uint16_t* hi, u
     return hipGetLastError();
 }
 
-hipError_t launch_hi_tails(const float* x, int64_t n, int D, uint16_t* hi, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hi_tails, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, D, hi);
-    return hipGetLastError();
-}
 
 hipError_t launch_bicubic(const float* lr, int h, int w, int scale, float* out, hipStream_t st) {
     hipLaunchKernelGGL(k_bicubic, dim3(grid_for((int64_t)scale * h * scale * w, 256)), dim3(256),

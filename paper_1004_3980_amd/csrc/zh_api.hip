@@ -540,7 +540,6 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     HIPCHK(c, hipMemsetAsync(d.hi.p, 0, d.hi.bytes, c->stream));
     HIPCHK(c, hipMemsetAsync(d.lo.p, 0, d.lo.bytes, c->stream));
     HIPCHK(c, launch_split_planes(dict->feat, n, D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
-    HIPCHK(c, launch_hi_tails(dict->feat, n, D, P<uint16_t>(d.hi), c->stream));
     TRY(build_screen(c, d, dict->feat));
     // hash parameters
     hash_params(seed, L, k, D, (double)w, d.h_alpha, d.h_beta);

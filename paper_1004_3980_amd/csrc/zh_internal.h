@@ -113,12 +113,9 @@ struct SearchArgs {
 };
 hipError_t launch_search(const SearchArgs& a, hipStream_t st);
 float screen_coeff(int D);   // error coefficient of the search's bf16 pre-filter (host)
-// Row layout of the high plane: D bf16 values, zero padding to a multiple of 4,
-// two floats (|x_hi|^2 in fp32 and an upper bound on |x - x_hi|), zero padding
-// to a multiple of 8 halfwords (16-byte rows).
+// Row layout of the high plane: D bf16 values, zero padding to whole 16-byte
+// rows with at least 4 halfwords of padding.
 __host__ __device__ inline int hi_stride(int D) { return ((((D + 3) & ~3) + 4) + 7) & ~7; }
-__host__ __device__ inline int hi_tail(int D) { return (D + 3) & ~3; }
-hipError_t launch_hi_tails(const float* x, int64_t n, int D, uint16_t* hi, hipStream_t st);
 hipError_t launch_search_overflow(const SearchArgs& a, int n_over, hipStream_t st);
 
 // ---- screen plane and rotated queries (k_screen.hip) --------------------------
