@@ -278,6 +278,137 @@ __global__ __launch_bounds__(256) void k_lle_lambda_adj(BackwardArgs a) {
     }
 }
 
+// dL/dw_m = <g_q, r_{n_m}> for K <= 8, one wave per patch (pixels lane + 64 u),
+// into gw[q][8] (FP64, zero past m_q).
+__global__ __launch_bounds__(256) void k_lam_gw(BackwardArgs a, double* __restrict__ gw) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int K = a.K, s = a.s, ps = kPatch * s, ps2 = ps * ps;
+    const int npj = a.w - kPatch + 1;
+    const int W = s * a.w;
+    for (int q = blockIdx.x * wpb + (threadIdx.x >> 6); q < a.Q; q += gridDim.x * wpb) {
+        const int mq = a.m[q];
+        const int pi = q / npj, pj = q - (q / npj) * npj;
+        float gq[4];
+        int P4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int P = lane + 64 * u;
+            P4[u] = P;
+            gq[u] = 0.0f;
+            if (P < ps2 && mq > 0) {
+                const int py = P / ps, px = P - py * ps;
+                gq[u] = a.gp[(int64_t)(s * pi + py) * W + s * pj + px];
+            }
+        }
+#pragma unroll
+        for (int mi = 0; mi < 8; ++mi) {
+            double acc = 0.0;
+            if (mi < mq) {
+                const float* r = a.resid + (int64_t)a.ids[(int64_t)q * K + mi] * ps2;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (P4[u] < ps2) acc += (double)gq[u] * (double)r[P4[u]];
+            }
+            acc = wave_sum_f64(acc);
+            if (lane == mi) gw[(int64_t)q * 8 + mi] = acc;
+        }
+    }
+}
+
+// Contribution of each patch to dL/dlambda (K <= 8), one thread per patch,
+// from its packed FP64 Gram matrix G and gw: with tau = tr(G) and
+// A = G + lambda tau I factored again here (Cholesky),
+//   w~ = A^-1 1, sigma = sum w~, d = -tau A^-1 w~,
+//   dL/dlambda_q = (gw.d - (gw.w~ / sigma) sum d) / sigma.
+__global__ __launch_bounds__(256) void k_lam_solve(BackwardArgs a, const double* __restrict__ gram,
+                                                   const double* __restrict__ gw) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.Q) return;
+    const int m = a.m[q];
+    double A[36], g[8];
+#pragma unroll
+    for (int p = 0; p < 36; ++p) A[p] = gram[(int64_t)q * 36 + p];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] = i < m ? gw[(int64_t)q * 8 + i] : 0.0;
+    double tau = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (i < m) tau += A[i * (i + 1) / 2 + i];
+    if (m <= 0 || !(tau > 0.0)) {
+        a.c_lam[q] = 0.0;
+        return;
+    }
+    // rows m..7: identity, so that the unrolled factorisation stays valid
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double& x = A[i * (i + 1) / 2 + j];
+            if (i >= m || j >= m) x = i == j ? 1.0 : 0.0;
+            else if (i == j) x += a.lam * tau;
+        }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        double v = A[j * (j + 1) / 2 + j];
+#pragma unroll
+        for (int t = 0; t < j; ++t) v -= A[j * (j + 1) / 2 + t] * A[j * (j + 1) / 2 + t];
+        A[j * (j + 1) / 2 + j] = sqrt(v);
+#pragma unroll
+        for (int i = j + 1; i < 8; ++i) {
+            double t2 = A[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int t = 0; t < j; ++t) t2 -= A[i * (i + 1) / 2 + t] * A[j * (j + 1) / 2 + t];
+            A[i * (i + 1) / 2 + j] = t2 / A[j * (j + 1) / 2 + j];
+        }
+    }
+    auto solve = [&](const double (&b)[8], double (&x)[8]) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            double v = b[i];
+#pragma unroll
+            for (int t = 0; t < i; ++t) v -= A[i * (i + 1) / 2 + t] * x[t];
+            x[i] = v / A[i * (i + 1) / 2 + i];
+        }
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+            double v = x[i];
+#pragma unroll
+            for (int t = i + 1; t < 8; ++t) v -= A[t * (t + 1) / 2 + i] * x[t];
+            x[i] = v / A[i * (i + 1) / 2 + i];
+        }
+    };
+    double one[8], wt[8], d[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) one[i] = i < m ? 1.0 : 0.0;
+    solve(one, wt);
+    double sig = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sig += i < m ? wt[i] : 0.0;
+    solve(wt, d);
+    double dsum = 0.0, gd = 0.0, gww = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (i < m) {
+            const double di = -tau * d[i];
+            dsum += di;
+            gd += g[i] * di;
+            gww += g[i] * wt[i] / sig;
+        }
+    }
+    a.c_lam[q] = (gd - gww * dsum) / sig;
+}
+
+hipError_t launch_lam_adj8(const BackwardArgs& a, const double* gram, double* gw, hipStream_t st) {
+    if (a.Q == 0) return hipSuccess;
+    if (a.K > 8) return hipErrorInvalidValue;
+    int g = (a.Q + 3) / 4;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_lam_gw, dim3(g), dim3(256), 0, st, a, gw);
+    hipLaunchKernelGGL(k_lam_solve, dim3((a.Q + 255) / 256), dim3(256), 0, st, a, gram, gw);
+    return hipGetLastError();
+}
+
 hipError_t launch_lle_lambda_adj(const BackwardArgs& a, hipStream_t st) {
     if (a.K > kMaxK || a.D > 128 || kPatch * a.s * kPatch * a.s > 256) return hipErrorInvalidValue;
     int g = (a.Q + 3) / 4;

@@ -86,6 +86,7 @@ struct zh_ctx {
     int64_t Q = 0;
     Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv, guides, bwd, bwd_k, clam;
     Buf qrot;                     // [Q, 64] rotated queries of the screen
+    Buf bwd_gw;                   // [Q, 8] FP64 scratch of the lambda adjoint
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -443,7 +444,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -953,7 +954,30 @@ zh_status zh_backward(zh_ctx* c, const float* g_hr, float* g_resid, float* g_lam
     ba.gp = gp;
     ba.lam = c->lam;
     ba.c_lam = P<double>(c->clam);
-    HIPCHK(c, launch_lle_lambda_adj(ba, c->stream));
+    if (K <= 8) {
+        // FP64 Gram matrices of the neighbours: those of the search when it
+        // formed them in FP64, else formed here
+        if (!(c->gram_ready && c->gram_fp64)) {
+            LleArgs la{};
+            la.Q = (int)Q;
+            la.D = d.D;
+            la.K = K;
+            la.qfeat = P<float>(c->qfeat);
+            la.ids = P<int32_t>(c->ids);
+            la.m = P<int32_t>(c->m);
+            la.hi = P<uint16_t>(d.hi);
+            la.lo = P<uint16_t>(d.lo);
+            la.hs = hi_stride(d.D);
+            TRY(ensure(c, c->gram, sizeof(double) * (size_t)(Q > 0 ? Q : 1) * 36));
+            HIPCHK(c, launch_gram(la, c->gram.p, 1, c->stream));
+            c->gram_ready = true;
+            c->gram_fp64 = 1;
+        }
+        TRY(ensure(c, c->bwd_gw, sizeof(double) * 8 * (size_t)(Q > 0 ? Q : 1)));
+        HIPCHK(c, launch_lam_adj8(ba, P<double>(c->gram), P<double>(c->bwd_gw), c->stream));
+    } else {
+        HIPCHK(c, launch_lle_lambda_adj(ba, c->stream));
+    }
     HIPCHK(c, launch_sum_f64(P<double>(c->clam), Q, g_lambda, c->stream));
     // dictionary rows: the neighbour lists sorted by row (stable), one wave per row
     const int64_t E = Q * K;

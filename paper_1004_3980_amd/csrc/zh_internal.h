@@ -249,6 +249,9 @@ struct BackwardArgs {
     double* c_lam;           // [Q] per-patch contribution to dL/dlambda
 };
 hipError_t launch_lle_lambda_adj(const BackwardArgs& a, hipStream_t st);
+// K <= 8: the same contributions from the packed FP64 Gram matrices [Q, 36];
+// gw is scratch [Q, 8] doubles
+hipError_t launch_lam_adj8(const BackwardArgs& a, const double* gram, double* gw, hipStream_t st);
 hipError_t launch_sum_f64(const double* x, int64_t n, float* out, hipStream_t st);
 hipError_t launch_nbr_pairs(const int32_t* ids, const int32_t* m, int Q, int K, uint32_t none, uint32_t* key,
                             uint32_t* val, hipStream_t st);

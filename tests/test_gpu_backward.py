@@ -31,19 +31,19 @@ def _torch():
     return torch
 
 
-def _setup(cfg, bp_iters, sigma_r):
-    key = (tuple(sorted(cfg.items())), bp_iters, sigma_r)
+def _setup(cfg, bp_iters, sigma_r, cap=0):
+    key = (tuple(sorted(cfg.items())), bp_iters, sigma_r, cap)
     if key in _cache:
         return _cache[key]
     from paper_1004_3980_amd.pipeline import GpuWorkload
     wl = synthdata.scaled(synthdata.WORKLOADS["diff"], bp_iters=bp_iters, sigma_r=sigma_r, **cfg)
     g = GpuWorkload(wl)
-    g.set_mode(cap=0, rerank=0, proj=1, lle_fp64=1)
+    g.set_mode(cap=cap, rerank=0, proj=1, lle_fp64=1)
     pre = pipeline.prepare(wl.dictionary_images(), wl.positions(), wl.scale, wl.feat_mode, wl.L, wl.k, wl.w,
                            wl.hash_seed)
     gt = wl.test_image().astype(np.float64)
     lr = imaging.degrade(gt, wl.scale)
-    rec = obw.forward(pre, lr, wl.scale, wl.K, wl.lam, bp_iters, wl.sigma_s, sigma_r)
+    rec = obw.forward(pre, lr, wl.scale, wl.K, wl.lam, bp_iters, wl.sigma_s, sigma_r, cap=cap)
     _cache[key] = (wl, g, pre, gt, rec)
     return _cache[key]
 
@@ -59,11 +59,14 @@ def _compare(g_gpu, glam_gpu, g_ref, glam_ref, used):
     assert abs(glam_gpu - glam_ref) <= REL * abs(glam_ref) + 1e-12, (glam_gpu, glam_ref)
 
 
-@pytest.mark.parametrize("cfg,bp_iters,sigma_r", [(SMALL, 0, 0.1), (SMALL, 3, 0.1), (SMALL, 2, math.inf),
-                                                  (MID, 3, 0.1)])
-def test_backward_matches_oracle_gradient(gpu_ok, cfg, bp_iters, sigma_r):
+@pytest.mark.parametrize("cfg,bp_iters,sigma_r,cap", [(SMALL, 0, 0.1, 0), (SMALL, 3, 0.1, 0), (SMALL, 2, math.inf, 0),
+                                                      (MID, 3, 0.1, 0), (SMALL, 3, 0.1, 20), (MID, 3, 0.1, 40)])
+def test_backward_matches_oracle_gradient(gpu_ok, cfg, bp_iters, sigma_r, cap):
+    """cap > 0: the early-stop search, whose FP64 Gram matrices the lambda
+    adjoint takes over; cap = 0: the union search, Gram matrices formed in the
+    backward."""
     torch = _torch()
-    wl, g, pre, gt, rec = _setup(cfg, bp_iters, sigma_r)
+    wl, g, pre, gt, rec = _setup(cfg, bp_iters, sigma_r, cap)
     out = g.forward_record(g.lr, wl.lam)
     assert np.abs(out.cpu().numpy() - rec.out).max() <= PIX_TOL
     rng = np.random.default_rng(3)
