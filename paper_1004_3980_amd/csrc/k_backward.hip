@@ -456,47 +456,139 @@ hipError_t launch_nbr_pairs(const int32_t* ids, const int32_t* m, int Q, int K, 
     return hipGetLastError();
 }
 
-// One wave per run of equal keys in the sorted entries (the wave at the first
-// entry of the run): g_r[n][P] = sum over the run, in entry order, of
-// w_e g_q(e)[P].
+// Gradient of each dictionary row that some patch uses: the sum over its
+// entries (q, m) of w_qm g_q, with the pairs sorted stably by row. Pass 1:
+// a wave per chunk of 64 consecutive entries (one per lane) sums each run of
+// equal rows inside the chunk in entry order (lane = pixel); a run that lies
+// wholly in the chunk is written, while a run that crosses a chunk border
+// leaves its partial sum in the chunk's first or last slot. Pass 2: a wave
+// per run that starts in a chunk and continues into the next adds the
+// partial sums in chunk order. The result depends only on the sorted pairs:
+// equal calls give equal gradients.
+struct DictGradChunk {
+    uint32_t key_last;   // row of the chunk's last run
+    uint8_t nseg;        // runs (of used rows) starting or continuing in the chunk
+    uint8_t first_cont;  // the first run continues from the previous chunk
+    uint8_t last_cont;   // the last run continues into the next chunk
+    uint8_t last_start;  // the last run starts in this chunk
+};
+
 __global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ key, const uint32_t* __restrict__ val,
                                                    int64_t n_ent, uint32_t none, const float* __restrict__ wts,
                                                    const float* __restrict__ gp, int w, int s, int K,
-                                                   float* __restrict__ g_r) {
+                                                   float* __restrict__ g_r, float* __restrict__ part,
+                                                   DictGradChunk* __restrict__ info) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int ps = kPatch * s, ps2 = ps * ps;
     const int npj = w - kPatch + 1, W = s * w;
-    for (int64_t p = blockIdx.x * (int64_t)wpb + (threadIdx.x >> 6); p < n_ent; p += (int64_t)gridDim.x * wpb) {
-        const uint32_t k = key[p];
-        if (k == none || (p > 0 && key[p - 1] == k)) continue;
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int64_t e = p; e < n_ent && key[e] == k; ++e) {
-            const uint32_t v = val[e];
-            const int q = (int)(v / (uint32_t)K);
-            const float wq = wts[v];
-            const int pi = q / npj, pj = q % npj;
+    int off[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int P = lane + 64 * u;
+        off[u] = P < ps2 ? (P / ps) * W + P % ps : 0;
+    }
+    const int64_t nchunk = (n_ent + 63) / 64;
+    for (int64_t c = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); c < nchunk; c += (int64_t)gridDim.x * wpb) {
+        const int64_t base = c * 64;
+        const int64_t e = base + lane;
+        const bool in = e < n_ent;
+        const uint32_t k = in ? key[e] : none;
+        const uint32_t kprev = (in && e > 0) ? key[e - 1] : none;
+        const uint32_t knext = (e + 1 < n_ent) ? key[e + 1] : none;
+        const uint32_t v = in ? val[e] : 0u;
+        const float wv = (in && k != none) ? wts[v] : 0.0f;
+        // segment starts inside the chunk: first lane, or a change of row
+        const uint64_t seg = __ballot(in && k != none && (lane == 0 || k != kprev));
+        const uint64_t ends = __ballot(in && k != none && (lane == 63 || e + 1 == n_ent || knext != k));
+        uint64_t todo = seg;
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int stop = __builtin_ctzll(ends & (~0ull << src));   // last entry of the segment
+            const uint32_t kk = __shfl(k, src);
+            float acc[4] = {0.f, 0.f, 0.f, 0.f};
+            for (int j = src; j <= stop; ++j) {
+                const uint32_t vv = __shfl(v, j);
+                const float ww = __shfl(wv, j);
+                const int q = (int)(vv / (uint32_t)K);
+                const int pi = q / npj, pj = q - pi * npj;
+                const float* g = gp + (int64_t)s * pi * W + (int64_t)s * pj;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (lane + 64 * u < ps2) acc[u] = fmaf(ww, g[off[u]], acc[u]);
+            }
+            const bool from_prev = src == 0 && __shfl(kprev, 0) == kk;
+            const bool into_next = stop == 63 && __shfl(knext, 63) == kk;
+            float* dst = g_r + (int64_t)kk * ps2;
+            if (from_prev) dst = part + (c * 2) * ps2;
+            else if (into_next) dst = part + (c * 2 + 1) * ps2;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int P = lane + 64 * u;
-                if (P < ps2) acc[u] = fmaf(wq, gp[(int64_t)(s * pi + P / ps) * W + s * pj + P % ps], acc[u]);
+                if (P < ps2) dst[P] = acc[u];
             }
+        }
+        const int last = seg ? 63 - __builtin_clzll(seg) : 0;
+        const uint32_t kl = __shfl(k, last);
+        const uint32_t k0 = __shfl(k, 0), kp0 = __shfl(kprev, 0);
+        const uint32_t k63 = __shfl(k, 63), kn63 = __shfl(knext, 63);
+        if (lane == 0) {
+            DictGradChunk ci;
+            ci.key_last = seg ? kl : none;
+            ci.nseg = (uint8_t)__popcll(seg);
+            ci.first_cont = (uint8_t)(k0 != none && kp0 == k0);
+            ci.last_cont = (uint8_t)(seg && k63 == kl && kn63 == kl);
+            ci.last_start = (uint8_t)(seg && !(last == 0 && kp0 == kl));
+            info[c] = ci;
+        }
+    }
+}
+
+// Pass 2: runs that cross chunk borders, from the chunk where they start.
+__global__ __launch_bounds__(256) void k_dict_grad_join(int64_t n_ent, int s, const float* __restrict__ part,
+                                                        const DictGradChunk* __restrict__ info, float* __restrict__ g_r) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int ps = kPatch * s, ps2 = ps * ps;
+    const int64_t nchunk = (n_ent + 63) / 64;
+    for (int64_t c = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); c < nchunk; c += (int64_t)gridDim.x * wpb) {
+        const DictGradChunk ci = info[c];
+        if (!ci.last_cont || !ci.last_start) continue;
+        // the run starts in chunk c and continues: its partial is in slot 1,
+        // and in slot 0 of every later chunk it reaches
+        const float* p0 = part + (c * 2 + 1) * ps2;
+        float acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = lane + 64 * u < ps2 ? p0[lane + 64 * u] : 0.0f;
+        for (int64_t cc = c + 1; cc < nchunk; ++cc) {
+            const DictGradChunk cn = info[cc];
+            const float* pp = part + (cc * 2) * ps2;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (lane + 64 * u < ps2) acc[u] += pp[lane + 64 * u];
+            if (!(cn.nseg == 1 && cn.last_cont)) break;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int P = lane + 64 * u;
-            if (P < ps2) g_r[(int64_t)k * ps2 + P] = acc[u];
+            if (P < ps2) g_r[(int64_t)ci.key_last * ps2 + P] = acc[u];
         }
     }
 }
 
 hipError_t launch_dict_grad(const uint32_t* key, const uint32_t* val, int64_t n_ent, uint32_t none, const float* wts,
-                            const float* gp, int w, int s, int K, float* g_r, hipStream_t st) {
+                            const float* gp, int w, int s, int K, float* g_r, float* part, void* info,
+                            hipStream_t st) {
     if (kPatch * s * kPatch * s > 256) return hipErrorInvalidValue;
-    int64_t g = (n_ent + 3) / 4;
+    if (n_ent == 0) return hipSuccess;
+    const int64_t nchunk = (n_ent + 63) / 64;
+    int64_t g = (nchunk + 3) / 4;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_dict_grad, dim3((unsigned)(g < 1 ? 1 : g)), dim3(256), 0, st, key, val, n_ent, none, wts,
-                       gp, w, s, K, g_r);
+    hipLaunchKernelGGL(k_dict_grad, dim3((unsigned)g), dim3(256), 0, st, key, val, n_ent, none, wts, gp, w, s, K, g_r,
+                       part, static_cast<DictGradChunk*>(info));
+    hipLaunchKernelGGL(k_dict_grad_join, dim3((unsigned)g), dim3(256), 0, st, n_ent, s, part,
+                       static_cast<const DictGradChunk*>(info), g_r);
     return hipGetLastError();
 }
 

@@ -87,6 +87,7 @@ struct zh_ctx {
     Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv, guides, bwd, bwd_k, clam;
     Buf qrot;                     // [Q, 64] rotated queries of the screen
     Buf bwd_gw;                   // [Q, 8] FP64 scratch of the lambda adjoint
+    Buf bwd_part;                 // partial row gradients of the dictionary-gradient passes
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -444,7 +445,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -996,8 +997,12 @@ zh_status zh_backward(zh_ctx* c, const float* g_hr, float* g_resid, float* g_lam
         HIPCHK(c, launch_nbr_pairs(P<int32_t>(c->ids), P<int32_t>(c->m), (int)Q, K, none, k0, v0, c->stream));
         bool first = true;
         HIPCHK(c, radix_sort_pairs(k0, v0, k1, v1, E, bits, hist, hsz, c->stream, &first));
+        const int64_t nchunk = (E + 63) / 64;
+        TRY(ensure(c, c->bwd_part, sizeof(float) * 2 * (size_t)ps2 * nchunk + 8 * (size_t)nchunk));
+        float* part = P<float>(c->bwd_part);
+        void* info = part + 2 * (size_t)ps2 * nchunk;
         HIPCHK(c, launch_dict_grad(first ? k0 : k1, first ? v0 : v1, E, none, P<float>(c->w), gp, w, s, K, g_resid,
-                                   c->stream));
+                                   part, info, c->stream));
     }
     return ZH_OK;
 }

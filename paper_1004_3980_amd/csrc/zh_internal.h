@@ -255,7 +255,9 @@ hipError_t launch_lam_adj8(const BackwardArgs& a, const double* gram, double* gw
 hipError_t launch_sum_f64(const double* x, int64_t n, float* out, hipStream_t st);
 hipError_t launch_nbr_pairs(const int32_t* ids, const int32_t* m, int Q, int K, uint32_t none, uint32_t* key,
                             uint32_t* val, hipStream_t st);
+// part: scratch of 2 (5s)^2 floats per chunk of 64 entries; info: 8 bytes per chunk
 hipError_t launch_dict_grad(const uint32_t* key, const uint32_t* val, int64_t n_ent, uint32_t none, const float* wts,
-                            const float* gp, int w, int s, int K, float* g_r, hipStream_t st);
+                            const float* gp, int w, int s, int K, float* g_r, float* part, void* info,
+                            hipStream_t st);
 
 }  // namespace zh
