@@ -275,6 +275,9 @@ enum { ZH_T_FEATURES = 0, ZH_T_HASH = 1, ZH_T_SEARCH = 2, ZH_T_LLE = 3, ZH_T_SYN
  * events (at most 256 launches per stage between two zh_get_timing calls;
  * later launches are not timed). on = 0 stops recording. */
 zh_status zh_set_timing(zh_ctx* ctx, int on);
+/* Times only the stages whose bit (1 << ZH_T_*) is set in mask (0 stops
+ * recording). Every pair of events costs a short gap on the stream. */
+zh_status zh_set_timing_stages(zh_ctx* ctx, uint32_t mask);
 /* Synchronise, then write for each stage the summed milliseconds
  * (ms[ZH_T_COUNT]) and the number of timed launches (launches[ZH_T_COUNT],
  * may be NULL) since the previous

@@ -91,6 +91,7 @@ struct zh_ctx {
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
+    uint32_t timing_mask = ~0u;   // stages bracketed with events while timing is on
     static constexpr int kEv = 256;
     hipEvent_t ev[ZH_T_COUNT][kEv][2] = {};
     int nev[ZH_T_COUNT] = {0};
@@ -159,7 +160,7 @@ struct StageTimer {
     int stage;
     int slot = -1;
     StageTimer(zh_ctx* c_, int s) : c(c_), stage(s) {
-        if (!c->timing || c->nev[stage] >= zh_ctx::kEv) return;
+        if (!c->timing || !((c->timing_mask >> stage) & 1u) || c->nev[stage] >= zh_ctx::kEv) return;
         slot = c->nev[stage]++;
         hipEvent_t* e = c->ev[stage][slot];
         if (!e[0]) {
@@ -1389,6 +1390,14 @@ zh_status zh_stats(zh_ctx* c, zh_stats_t* out) {
 zh_status zh_set_timing(zh_ctx* c, int on) {
     if (!c) return ZH_EINVAL;
     c->timing = on != 0;
+    c->timing_mask = ~0u;
+    return ZH_OK;
+}
+
+zh_status zh_set_timing_stages(zh_ctx* c, uint32_t mask) {
+    if (!c) return ZH_EINVAL;
+    c->timing = mask != 0;
+    c->timing_mask = mask;
     return ZH_OK;
 }
 

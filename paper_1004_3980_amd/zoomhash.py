@@ -88,6 +88,7 @@ SIGNATURES = {
     "zh_candidates": [_V, ctypes.c_int32, _V, _V],
     "zh_stats": [_V, ctypes.POINTER(zh_stats_t)],
     "zh_set_timing": [_V, _I],
+    "zh_set_timing_stages": [_V, ctypes.c_uint32],
     "zh_get_timing": [_V, _V, _V],
 }
 STAGES = ["features", "hash", "search", "lle", "synth", "blend", "bp_error", "bp_update", "rotate"]
@@ -248,8 +249,15 @@ class Context:
     def candidates(self, cap_per_query, counts, ids):
         self._chk(self.lib.zh_candidates(self.h, cap_per_query, _ptr(counts), _ptr(ids)))
 
-    def set_timing(self, on: bool):
-        self._chk(self.lib.zh_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on: bool, stages=None):
+        """stages: names from STAGES to time (None: all)."""
+        if stages is None:
+            self._chk(self.lib.zh_set_timing(self.h, 1 if on else 0))
+        else:
+            mask = 0
+            for n in stages:
+                mask |= 1 << STAGES.index(n)
+            self._chk(self.lib.zh_set_timing_stages(self.h, mask if on else 0))
 
     def get_timing(self):
         ms = np.zeros(len(STAGES), dtype=np.float64)
