@@ -471,46 +471,32 @@ template <typename GT>
 __device__ __forceinline__ void exact_pass(const SearchArgs& a, const float* sq, const uint32_t* cids,
                                            uint32_t* cdist, int cb, int c1, GT* sG) {
     const int lane = threadIdx.x;
-    const int D = a.D, HS = a.hs;
+    const int D = a.D;
     const int rg = lane >> 3, g = lane & 7;
-    const int nvg = D - 16 * g;
     const int c = cb + rg;
     const bool cv = c < c1;
     const uint32_t id = cv ? cids[c] : 0u;
-    const size_t bo = ((size_t)id * (uint32_t)D + 16u * g) * 2u;
-    const size_t bh = ((size_t)id * (uint32_t)HS + 16u * g) * 2u;
-    uint4 h[2], l[2];
+    // the row's fp32 values 16 g .. 16 g + 15 (zero past D)
+    const float* xr = a.xf + (size_t)id * (uint32_t)D;
+    float x[16];
+    if ((D & 3) == 0) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        h[u] = make_uint4(0u, 0u, 0u, 0u);
-        l[u] = h[u];
-        if (cv && 16 * g + 8 * u < D) {
-            h[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(a.hi) + bh + 16 * u);
-            l[u] = ld16(reinterpret_cast<const char*>(a.lo) + bo + 16 * u);
+        for (int u = 0; u < 4; ++u) {
+            const int c0 = 16 * g + 4 * u;
+            float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (cv && c0 < D) t = *reinterpret_cast<const float4*>(xr + c0);
+            x[4 * u] = t.x;
+            x[4 * u + 1] = t.y;
+            x[4 * u + 2] = t.z;
+            x[4 * u + 3] = t.w;
         }
-        const int nv = nvg - 8 * u;
-        if (nv < 8) {
+    } else {
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const uint32_t km = keep_mask(nv, w);
-                (&h[u].x)[w] &= km;
-                (&l[u].x)[w] &= km;
-            }
-        }
+        for (int e = 0; e < 16; ++e) x[e] = (cv && 16 * g + e < D) ? xr[16 * g + e] : 0.0f;
     }
-    // z = q - x in fp32, one perm per coordinate (the high and low halves of
-    // x joined); x itself is rebuilt only for the rare exact-equality check
     float z[16];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const float2 q2 = *reinterpret_cast<const float2*>(sq + 16 * g + 8 * u + 2 * w);
-            const uint32_t hw = (&h[u].x)[w], lw = (&l[u].x)[w];
-            z[8 * u + 2 * w] = q2.x - __uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x05040100u));
-            z[8 * u + 2 * w + 1] = q2.y - __uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x07060302u));
-        }
-    }
+    for (int e = 0; e < 16; ++e) z[e] = sq[16 * g + e] - x[e];
     float p = 0.0f;
 #pragma unroll
     for (int e = 0; e < 16; ++e) p = fmaf(z[e], z[e], p);
@@ -521,15 +507,7 @@ __device__ __forceinline__ void exact_pass(const SearchArgs& a, const float* sq,
     if (__ballot(cv && p == 0.0f) != 0) {
         bool eq = true;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const float2 q2 = *reinterpret_cast<const float2*>(sq + 16 * g + 8 * u + 2 * w);
-                const uint32_t hw = (&h[u].x)[w], lw = (&l[u].x)[w];
-                eq = eq && __builtin_amdgcn_perm(hw, lw, 0x05040100u) == __float_as_uint(q2.x);
-                eq = eq && __builtin_amdgcn_perm(hw, lw, 0x07060302u) == __float_as_uint(q2.y);
-            }
-        }
+        for (int e = 0; e < 16; ++e) eq = eq && __float_as_uint(x[e]) == __float_as_uint(sq[16 * g + e]);
         const uint32_t grp = (uint32_t)(__ballot(eq) >> (8 * rg)) & 0xFFu;
         exact_row = grp == 0xFFu;
     }
@@ -542,15 +520,7 @@ __device__ __forceinline__ void exact_pass(const SearchArgs& a, const float* sq,
         // exact differences: q - x in FP64 from the fp32 values
         double zd[16];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const float2 q2 = *reinterpret_cast<const float2*>(sq + 16 * g + 8 * u + 2 * w);
-                const uint32_t hw = (&h[u].x)[w], lw = (&l[u].x)[w];
-                zd[8 * u + 2 * w] = cv ? (double)q2.x - (double)__uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x05040100u)) : 0.0;
-                zd[8 * u + 2 * w + 1] = cv ? (double)q2.y - (double)__uint_as_float(__builtin_amdgcn_perm(hw, lw, 0x07060302u)) : 0.0;
-            }
-        }
+        for (int e = 0; e < 16; ++e) zd[e] = cv ? (double)sq[16 * g + e] - (double)x[e] : 0.0;
         gram_mfma<double>(zd, sG);
     }
 }

@@ -41,6 +41,7 @@ struct Dict {
     Buf tids;                     // [L, n] uint32
     Buf kmul;                     // [L, k] multipliers of the bucket-key sum
     Buf sc;                       // [n, screen_stride(D)] screen plane
+    Buf xf;                       // [n, D] fp32 copy of the features (exact passes of the search)
     Buf phi_hi, phi_lo;           // [64, round32(D)] bf16 split of the principal directions
     float inv_s2 = 0.f;           // lower bound of 1 / sigma_max(Phi)^2
     float rot_c1 = 0.f;           // error-bound coefficient of the query rotation
@@ -360,6 +361,7 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.hs = hi_stride(d.D);
     a.ce = screen_coeff(screen_tail(d.D));
     a.sc = P<uint16_t>(d.sc);
+    a.xf = P<float>(d.xf);
     a.inv_s2 = d.inv_s2;
     a.out_ids = P<int32_t>(c->ids);
     a.out_d2 = P<float>(c->d2);
@@ -429,7 +431,7 @@ void zh_destroy(zh_ctx* c) {
     for (Dict& d : c->dicts) {
         release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.bc0[0]); release(c, d.bc0[1]);
         release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.tids);
-        release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo); release(c, d.kmul);
+        release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo); release(c, d.kmul); release(c, d.xf);
     }
     for (int st = 0; st < ZH_T_COUNT; ++st)
         for (int i = 0; i < zh_ctx::kEv; ++i)
@@ -543,6 +545,8 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     HIPCHK(c, hipMemsetAsync(d.hi.p, 0, d.hi.bytes, c->stream));
     HIPCHK(c, hipMemsetAsync(d.lo.p, 0, d.lo.bytes, c->stream));
     HIPCHK(c, launch_split_planes(dict->feat, n, D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
+    TRY(ensure(c, d.xf, sizeof(float) * (size_t)n * D + 64));
+    HIPCHK(c, hipMemcpyAsync(d.xf.p, dict->feat, sizeof(float) * (size_t)n * D, hipMemcpyDeviceToDevice, c->stream));
     TRY(build_screen(c, d, dict->feat));
     // hash parameters
     hash_params(seed, L, k, D, (double)w, d.h_alpha, d.h_beta);

@@ -91,6 +91,7 @@ struct SearchArgs {
     int hs;                  // row stride of the high plane (halfwords)
     float ce;                // relative error coefficient of the screen's |y_q - y~_x|^2
     const uint16_t* sc;      // [N, screen_stride(D)] screen plane (early-stop search)
+    const float* xf;         // [N, D] fp32 features: the exact passes of the early-stop search
     const float* qrot;       // [Q, 64] rotated queries: y_q, zeros, rho_q in the last slot
     float inv_s2;            // lower bound of 1 / sigma_max(Phi)^2
     void* gram;              // [Q, 36] packed Gram matrices of the neighbours (K <= 8), or null
