@@ -41,6 +41,13 @@ __device__ __forceinline__ int32_t floor_sat(double t) {
     return (int32_t)f;
 }
 
+// floor(x) as int32 in one instruction (x of magnitude below 2^31)
+__device__ __forceinline__ int32_t cvt_floor(float x) {
+    int32_t r;
+    asm volatile("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // |x| of eight bf16 values: the sign bits cleared, one 32-bit AND per pair
 __device__ __forceinline__ u16x8 abs8(u16x8 x) {
     uint4 w = __builtin_bit_cast(uint4, x);
@@ -255,7 +262,8 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
             const int ar = tt * 16 + ri;
             f32x4 cs = f32x4{0.f, 0.f, 0.f, 0.f}, cab = cs;
             if (PREC == 1) {
-                f32x4 chl = cs, clh = cs;
+                // the three split products share one fp32 accumulator: the
+                // bound covers any order of the 3 DP additions
                 const uint16_t* Ah = sA16 + ar * DS + 8 * kb;
                 const uint16_t* Al = Ah + R * DS;
                 u16x8 ah[NS], al[NS];
@@ -273,11 +281,10 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
                     const bf16x8 alb = __builtin_bit_cast(bf16x8, al[s]);
                     const bf16x8 aab8 = __builtin_bit_cast(bf16x8, abs8(ah[s]));
                     cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vhb, cs, 0, 0, 0);
-                    chl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, chl, 0, 0, 0);
-                    clh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, clh, 0, 0, 0);
                     cab = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aab8, vab, cab, 0, 0, 0);
+                    cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, cs, 0, 0, 0);
+                    cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, cs, 0, 0, 0);
                 }
-                cs = cs + (chl + clh);
             } else {
                 const float* Af = sAf + ar * DS;
                 for (int s = 0; s < nsteps; ++s) {
@@ -292,21 +299,42 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
             const float4 b0 = *reinterpret_cast<const float4*>(sBc0 + tt * 16 + 4 * kb);
             const float bev[4] = {be.x, be.y, be.z, be.w};
             const float b0v[4] = {b0.x, b0.y, b0.z, b0.w};
+            // codes of rows past the table count stay out of the stage (their
+            // slots belong to other tables); codes of feature rows past n are
+            // written but never read
+            const bool full = tt * 16 + 16 <= GKa;
+            int32_t* cdst = sC + ((l0 % fold) * k + tt * 16 + 4 * kb) * kRowsPerWave + ri;
+            unsigned fl = 0;
+            int32_t cv[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int hr = tt * 16 + 4 * kb + i;
-                const bool valid = hr < GKa && rowok;
                 const float S = cs[i];
                 const float P = (S + bev[i]) * a.inv_w;
                 const float B = fmaf(c1, cab[i], fmaf(c2, fabsf(S), b0v[i]));
-                const float n = rintf(P);
-                const bool flag = !(fabsf(P - n) > B) || !(fabsf(P) < 4194304.0f);
-                if (valid) {
-                    if (flag) {
+                // uncertain when an integer lies within B of P; every P of
+                // magnitude >= 2^23 is an integer, so each certain code has
+                // |floor(P)| <= 2^23 (a NaN P or B is uncertain as well)
+                const bool flag = !(fabsf(P - rintf(P)) > B);
+                fl |= (flag ? 1u : 0u) << i;
+                const int32_t c = cvt_floor(P);
+                cv[i] = flag ? kCodeUnset : c;
+            }
+            if (full) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) cdst[i * kRowsPerWave] = cv[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (tt * 16 + 4 * kb + i < GKa) cdst[i * kRowsPerWave] = cv[i];
+            }
+            if (fl != 0 && rowok) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int hr = tt * 16 + 4 * kb + i;
+                    if (((fl >> i) & 1u) && hr < GKa) {
                         ++nflag;
                         sU[((l0 % fold) + (hr >= k ? 1 : 0)) * kRowsPerWave + ri] = 1;
                     }
-                    sC[((l0 % fold) * k + hr) * kRowsPerWave + ri] = flag ? kCodeUnset : (int32_t)floorf(P);
                 }
             }
         }
@@ -343,15 +371,15 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
             wcnt += (unsigned)__popcll(bal);
             if (act) {
                 const uint64_t* mul = smul + lt * (k + 1);
+                const int32_t* cp = sC + t * k * kRowsPerWave + rr;
                 uint64_t h = mul[k];
-#pragma unroll 4
-                for (int j = 0; j < k; ++j) {
-                    const int32_t c = sC[(t * k + j) * kRowsPerWave + rr];
-                    if (a.codes) a.codes[row * m + lt * k + j] = c;
-                    if (ent) ent[2 + j] = c;
-                    h += key_term(c, mul[j]);
-                }
+#pragma unroll 10
+                for (int j = 0; j < k; ++j) h += key_term(cp[j * kRowsPerWave], mul[j]);
                 a.keys[row * L + lt] = key_final(h);
+                if (a.codes)
+                    for (int j = 0; j < k; ++j) a.codes[row * m + lt * k + j] = cp[j * kRowsPerWave];
+                if (ent)
+                    for (int j = 0; j < k; ++j) ent[2 + j] = cp[j * kRowsPerWave];
             }
             if (lane < 4 * kRowsPerWave) sU[lane] = 0;
         }

@@ -13,7 +13,7 @@ constexpr int kMaxTaps = 33;    // longest 1-D Gaussian the kernels accept
 constexpr int kMaxK = 16;       // neighbours per patch
 constexpr int kMaxL = 64;       // hash tables
 constexpr int kMaxKHash = 32;
-constexpr int32_t kCodeUnset = (int32_t)0x80000000;   // MFMA codes lie within +-2^22
+constexpr int32_t kCodeUnset = (int32_t)0x80000000;   // MFMA codes lie within +-2^23
 constexpr int kFixSlots = 16;                        // fix-list entries per wave of 16 rows   // hashes per table
 
 struct Taps {                   // normalised 1-D Gaussian, offsets -R..R
