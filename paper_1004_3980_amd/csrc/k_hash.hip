@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
                 uint64_t h = mul[k];
 #pragma unroll 10
                 for (int j = 0; j < k; ++j) h += key_term(cp[j * kRowsPerWave], mul[j]);
-                a.keys[row * L + lt] = key_final(h);
+                a.keys[key_pos(a, row, lt)] = key_final(h);
                 if (a.codes)
                     for (int j = 0; j < k; ++j) a.codes[row * m + lt * k + j] = cp[j * kRowsPerWave];
                 if (ent)
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_hash_fixlist(HashArgs a) {
                 h += key_term(ev[2 + j], a.key_mul[l * (k + 1) + j]);
             }
         }
-        a.keys[row * L + l] = key_final(h);
+        a.keys[key_pos(a, row, l)] = key_final(h);
     }
 }
 
@@ -528,17 +528,22 @@ __global__ __launch_bounds__(64) void k_hash_fix(HashArgs a) {
         uint64_t h = a.key_mul[l_mine * (k + 1) + k];
         const int base = act ? grp * k : 0;
         for (int j = 0; j < k; ++j) h += key_term(__shfl(c, base + j), a.key_mul[l_mine * (k + 1) + j]);
-        if (act && jj == 0) a.keys[row * L + l_mine] = key_final(h);
+        if (act && jj == 0) a.keys[key_pos(a, row, l_mine)] = key_final(h);
         __syncthreads();
     }
 }
 
-// Bin (offset, count) of every key: one thread per (row, table).
+// Bin (offset, count) of every key, keys and bins table by table: blocks of
+// one table run together, so the lookups of the whole chip go to one
+// table's directory at a time (it stays in the last-level cache).
 __global__ __launch_bounds__(256) void k_probe(const uint64_t* __restrict__ keys, int64_t n, int L,
                                                const Slot* __restrict__ dir, uint64_t cap, uint2* __restrict__ bins) {
-    const int64_t total = n * L;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int l = (int)(i % L);
+    const int64_t bpt = (n + 255) / 256;   // blocks per table
+    for (int64_t b = blockIdx.x; b < bpt * L; b += gridDim.x) {
+        const int l = (int)(b / bpt);
+        const int64_t row = (b - l * bpt) * 256 + threadIdx.x;
+        if (row >= n) continue;
+        const int64_t i = (int64_t)l * n + row;
         uint32_t off, cnt;
         probe_bin_h(dir + (uint64_t)l * cap, cap, keys[i], off, cnt);
         bins[i] = make_uint2(off, cnt);
@@ -590,7 +595,7 @@ static void launch_split(const HashArgs& a, dim3 grid, size_t lds, hipStream_t s
 hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
     if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty || !a.fix_count || !a.key_mul ||
-        a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list))
+        a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list) || (a.bins && !a.keys_tmajor))
         return hipErrorInvalidValue;
     const int rows = kWaves * kRowsPerWave;
     const dim3 grid((unsigned)((a.n + rows - 1) / rows));

@@ -648,7 +648,7 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
         if (q >= a.Q) return;
         uint32_t off = 0, cnt = 0;
         if (lane < L) {
-            const uint2 b = a.bins[(int64_t)q * L + lane];
+            const uint2 b = a.bins[(int64_t)lane * a.Q + q];
             off = b.x;
             cnt = b.y;
         }
@@ -913,7 +913,7 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
         const int q = BIG ? a.overflow[t] : t;
         uint32_t off = 0, cnt = 0;
         if (lane < L) {
-            const uint2 b = a.bins[(int64_t)q * L + lane];
+            const uint2 b = a.bins[(int64_t)lane * a.Q + q];
             off = b.x;
             cnt = b.y;
         }

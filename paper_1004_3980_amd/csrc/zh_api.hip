@@ -753,6 +753,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     ha.dir = P<Slot>(d.dir);
     ha.dir_cap = d.cap;
     ha.bins = P<uint2>(c->qbins);
+    ha.keys_tmajor = 1;
     {
         StageTimer t(c, ZH_T_HASH);
         HIPCHK(c, launch_hash(ha, c->stream));
@@ -1170,6 +1171,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             ha.dir = P<Slot>(d.dir);
             ha.dir_cap = d.cap;
             ha.bins = P<uint2>(c->qbins);
+            ha.keys_tmajor = 1;
             HIPCHK(c, launch_hash(ha, st));
             TRY(run_search(c, d, nullptr, 0));
             LleArgs la{};

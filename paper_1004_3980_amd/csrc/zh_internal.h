@@ -56,7 +56,8 @@ struct HashArgs {
     float w;
     int prec;                // 0 = fp32 MFMA, 1 = split bf16 MFMA
     const uint64_t* key_mul; // [L, k + 1] multipliers of the key sum, then its start value
-    uint64_t* keys;          // [n, L]
+    uint64_t* keys;          // [n, L], or [L, n] when keys_tmajor
+    int keys_tmajor;         // keys (and bins) stored table by table
     int32_t* codes;          // [n, L*k] or null
     unsigned int* n_fixed;   // count of codes recomputed in FP64 (nullable)
     uint64_t* dirty;         // [n] scratch: per row, bit l set when table l must be recomputed in full
@@ -66,8 +67,13 @@ struct HashArgs {
     unsigned int* fix_count; // [ceil(n/16)] entries written by each wave
     const Slot* dir;         // bin directories [L, dir_cap], or null: no lookup
     uint64_t dir_cap;
-    uint2* bins;             // [n, L] (offset, count) of each key's bin, when dir is set
+    uint2* bins;             // [L, n] (offset, count) of each key's bin, when dir is set
+                             // (needs keys_tmajor)
 };
+// position of the key of (row, table)
+__device__ __forceinline__ int64_t key_pos(const HashArgs& a, int64_t row, int l) {
+    return a.keys_tmajor ? (int64_t)l * a.n + row : row * a.L + l;
+}
 hipError_t launch_hash(const HashArgs& a, hipStream_t st);
 // bound coefficients for the MFMA projection of precision `prec` (host)
 void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, float* c0, float* c1,
@@ -96,7 +102,7 @@ struct SearchArgs {
     float inv_s2;            // lower bound of 1 / sigma_max(Phi)^2
     void* gram;              // [Q, 36] packed Gram matrices of the neighbours (K <= 8), or null
     int gram_fp64;           // their precision: FP64 or fp32
-    const uint2* bins;       // [Q, L] (offset, count) of the query's bin in each table
+    const uint2* bins;       // [L, Q] (offset, count) of the query's bin in each table
     const float* qfeat;      // [Q, D]
     const uint32_t* tids;    // [L, N]
     int64_t N;
