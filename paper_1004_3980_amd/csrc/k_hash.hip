@@ -58,10 +58,11 @@ __device__ __forceinline__ u16x8 abs8(u16x8 x) {
     return __builtin_bit_cast(u16x8, w);
 }
 
-__device__ __forceinline__ void probe_bin_h(const Slot* __restrict__ dir, uint64_t cap, uint64_t key,
-                                            uint32_t& off, uint32_t& cnt) {
+// Walk the directory from slot s on (linear probing) to the key or an empty
+// slot; (off, cnt) stay 0 for an absent key.
+__device__ __forceinline__ void probe_bin_from(const Slot* __restrict__ dir, uint64_t cap, uint64_t key, uint64_t s,
+                                               uint32_t& off, uint32_t& cnt) {
     const uint64_t mask = cap - 1;
-    uint64_t s = key & mask;
     off = 0;
     cnt = 0;
     for (uint64_t step = 0; step < cap; ++step) {
@@ -535,18 +536,56 @@ __global__ __launch_bounds__(64) void k_hash_fix(HashArgs a) {
 
 // Bin (offset, count) of every key, keys and bins table by table: blocks of
 // one table run together, so the lookups of the whole chip go to one
-// table's directory at a time (it stays in the last-level cache).
+// table's directory at a time (it stays in the last-level cache). A thread
+// takes kProbeRows rows of a block's kProbeRows * 256 and keeps their
+// lookups in flight together: keys, then filter words, then the first
+// directory slot of each key the filter lets through; a key that meets
+// neither itself nor an empty slot there walks on alone.
+constexpr int kProbeRows = 4;
 __global__ __launch_bounds__(256) void k_probe(const uint64_t* __restrict__ keys, int64_t n, int L,
-                                               const Slot* __restrict__ dir, uint64_t cap, uint2* __restrict__ bins) {
-    const int64_t bpt = (n + 255) / 256;   // blocks per table
+                                               const Slot* __restrict__ dir, uint64_t cap,
+                                               const uint32_t* __restrict__ filter, uint2* __restrict__ bins) {
+    const uint64_t fw = dir_filter_words(cap);
+    const uint64_t mask = cap - 1;
+    const int64_t span = 256 * kProbeRows;
+    const int64_t bpt = (n + span - 1) / span;   // blocks per table
     for (int64_t b = blockIdx.x; b < bpt * L; b += gridDim.x) {
         const int l = (int)(b / bpt);
-        const int64_t row = (b - l * bpt) * 256 + threadIdx.x;
-        if (row >= n) continue;
-        const int64_t i = (int64_t)l * n + row;
-        uint32_t off, cnt;
-        probe_bin_h(dir + (uint64_t)l * cap, cap, keys[i], off, cnt);
-        bins[i] = make_uint2(off, cnt);
+        const int64_t row0 = (b - l * bpt) * span + threadIdx.x;
+        const Slot* dl = dir + (uint64_t)l * cap;
+        const uint32_t* fl = filter + (uint64_t)l * fw;
+        uint64_t key[kProbeRows];
+        uint32_t fword[kProbeRows];
+        uint4 e[kProbeRows];
+#pragma unroll
+        for (int j = 0; j < kProbeRows; ++j) {
+            const int64_t row = row0 + 256 * j;
+            key[j] = row < n ? keys[(int64_t)l * n + row] : kEmptyKey;
+        }
+#pragma unroll
+        for (int j = 0; j < kProbeRows; ++j) fword[j] = key[j] != kEmptyKey ? fl[dir_filter_bit(key[j], cap) >> 5] : 0u;
+#pragma unroll
+        for (int j = 0; j < kProbeRows; ++j) {
+            e[j] = make_uint4(0u, 0u, 0u, 0u);
+            if ((fword[j] >> (dir_filter_bit(key[j], cap) & 31)) & 1u)
+                e[j] = *reinterpret_cast<const uint4*>(dl + (key[j] & mask));
+        }
+#pragma unroll
+        for (int j = 0; j < kProbeRows; ++j) {
+            const int64_t row = row0 + 256 * j;
+            if (row >= n) continue;
+            uint32_t off = 0, cnt = 0;
+            if ((fword[j] >> (dir_filter_bit(key[j], cap) & 31)) & 1u) {
+                const uint64_t k0 = ((uint64_t)e[j].y << 32) | e[j].x;
+                if (k0 == key[j]) {
+                    cnt = e[j].z;
+                    off = e[j].w;
+                } else if (k0 != kEmptyKey) {
+                    probe_bin_from(dl, cap, key[j], ((key[j] & mask) + 1) & mask, off, cnt);
+                }
+            }
+            bins[(int64_t)l * n + row] = make_uint2(off, cnt);
+        }
     }
 }
 
@@ -595,7 +634,8 @@ static void launch_split(const HashArgs& a, dim3 grid, size_t lds, hipStream_t s
 hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
     if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty || !a.fix_count || !a.key_mul ||
-        a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list) || (a.bins && !a.keys_tmajor))
+        a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list) ||
+        (a.bins && (!a.keys_tmajor || !a.dir || !a.dir_filter)))
         return hipErrorInvalidValue;
     const int rows = kWaves * kRowsPerWave;
     const dim3 grid((unsigned)((a.n + rows - 1) / rows));
@@ -627,9 +667,10 @@ hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess || !a.bins) return e;
     const int64_t total = a.n * a.L;
-    int64_t g = (total + 255) / 256;
+    int64_t g = (total + 256 * kProbeRows - 1) / (256 * kProbeRows);
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_probe, dim3((unsigned)g), dim3(256), 0, st, a.keys, a.n, a.L, a.dir, a.dir_cap, a.bins);
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)g), dim3(256), 0, st, a.keys, a.n, a.L, a.dir, a.dir_cap,
+                       a.dir_filter, a.bins);
     return hipGetLastError();
 }
 

@@ -31,8 +31,8 @@ __global__ void k_dir_clear(Slot* __restrict__ dir, uint64_t count) {
 }
 
 __global__ void k_dir_insert(const uint64_t* __restrict__ keys, int64_t n, int L, int l,
-                             Slot* __restrict__ dir, uint64_t cap, uint32_t* __restrict__ slot_of,
-                             uint32_t* __restrict__ ids) {
+                             Slot* __restrict__ dir, uint64_t cap, uint32_t* __restrict__ filter,
+                             uint32_t* __restrict__ slot_of, uint32_t* __restrict__ ids) {
     const uint64_t mask = cap - 1;
     for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n;
          id += (int64_t)gridDim.x * blockDim.x) {
@@ -43,6 +43,10 @@ __global__ void k_dir_insert(const uint64_t* __restrict__ keys, int64_t n, int L
         for (uint64_t step = 0; step < cap; ++step) {
             const unsigned long long old = atomicCAS(&dir[s].key, (unsigned long long)kEmptyKey, key);
             if (old == kEmptyKey || old == key) {
+                if (old == kEmptyKey) {
+                    const uint32_t fb = dir_filter_bit(key, cap);
+                    atomicOr(&filter[fb >> 5], 1u << (fb & 31));
+                }
                 atomicAdd(&dir[s].count, 1u);
                 slot_of[id] = (uint32_t)s;
                 ids[id] = (uint32_t)id;
@@ -67,9 +71,9 @@ hipError_t launch_dir_clear(Slot* dir, uint64_t count, hipStream_t st) {
 }
 
 hipError_t launch_dir_insert(const uint64_t* keys, int64_t n, int L, int l, Slot* dir, uint64_t cap,
-                             uint32_t* slot_of, uint32_t* ids, hipStream_t st) {
+                             uint32_t* filter, uint32_t* slot_of, uint32_t* ids, hipStream_t st) {
     hipLaunchKernelGGL(k_dir_insert, dim3(grid_for(n, 256)), dim3(256), 0, st, keys, n, L, l, dir,
-                       cap, slot_of, ids);
+                       cap, filter, slot_of, ids);
     return hipGetLastError();
 }
 

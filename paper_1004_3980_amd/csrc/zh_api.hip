@@ -38,6 +38,7 @@ struct Dict {
     Buf alpha, beta, bc0[2], ahi, alo;
     float bc1[2] = {0.f, 0.f}, bc2[2] = {0.f, 0.f};
     Buf dir;                      // [L, cap] Slot
+    Buf dfilt;                    // [L, dir_filter_words(cap)] presence bits of the keys
     Buf tids;                     // [L, n] uint32
     Buf kmul;                     // [L, k] multipliers of the bucket-key sum
     Buf sc;                       // [n, screen_stride(D)] screen plane
@@ -430,7 +431,7 @@ void zh_destroy(zh_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (Dict& d : c->dicts) {
         release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.bc0[0]); release(c, d.bc0[1]);
-        release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.tids);
+        release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.dfilt); release(c, d.tids);
         release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo); release(c, d.kmul); release(c, d.xf);
     }
     for (int st = 0; st < ZH_T_COUNT; ++st)
@@ -611,6 +612,9 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     HIPCHK(c, launch_hash(ha, c->stream));
     // directory and bins, table by table
     TRY(ensure(c, d.dir, sizeof(Slot) * (size_t)L * cap));
+    const uint64_t fw = dir_filter_words(cap);
+    TRY(ensure(c, d.dfilt, sizeof(uint32_t) * (size_t)L * fw));
+    HIPCHK(c, hipMemsetAsync(d.dfilt.p, 0, sizeof(uint32_t) * (size_t)L * fw, c->stream));
     TRY(ensure(c, d.tids, sizeof(uint32_t) * (size_t)L * n));
     TRY(ensure(c, c->slot_of, sizeof(uint32_t) * (size_t)n));
     TRY(ensure(c, c->idsort, sizeof(uint32_t) * (size_t)n));
@@ -623,7 +627,8 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     HIPCHK(c, launch_dir_clear(P<Slot>(d.dir), (uint64_t)L * cap, c->stream));
     for (int l = 0; l < L; ++l) {
         Slot* dl = P<Slot>(d.dir) + (size_t)l * cap;
-        HIPCHK(c, launch_dir_insert(P<uint64_t>(c->keys_dict), n, L, l, dl, cap, P<uint32_t>(c->slot_of),
+        HIPCHK(c, launch_dir_insert(P<uint64_t>(c->keys_dict), n, L, l, dl, cap,
+                                    P<uint32_t>(d.dfilt) + (size_t)l * fw, P<uint32_t>(c->slot_of),
                                     P<uint32_t>(c->idsort), c->stream));
         bool in_first = true;
         HIPCHK(c, radix_sort_pairs(P<uint32_t>(c->slot_of), P<uint32_t>(c->idsort), P<uint32_t>(c->rs_k1),
@@ -752,6 +757,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     TRY(hash_scratch(c, ha));
     ha.dir = P<Slot>(d.dir);
     ha.dir_cap = d.cap;
+    ha.dir_filter = P<uint32_t>(d.dfilt);
     ha.bins = P<uint2>(c->qbins);
     ha.keys_tmajor = 1;
     {
@@ -1043,7 +1049,10 @@ std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
                        (uint64_t)c->opts.cap, (uint64_t)c->opts.rerank, (uint64_t)c->opts.proj,
                        (uint64_t)c->opts.lle_fp64, (uint64_t)c->batch.tile, (uint64_t)c->batch.grid_per_cu,
                        (uint64_t)(uintptr_t)c->stream});
-    for (int s = 1; s <= 3; ++s) v.push_back((uint64_t)(uintptr_t)c->dicts[s].dir.p);
+    for (int s = 1; s <= 3; ++s) {
+        v.push_back((uint64_t)(uintptr_t)c->dicts[s].dir.p);
+        v.push_back((uint64_t)(uintptr_t)c->dicts[s].dfilt.p);
+    }
     for (int i = 0; i < b->n_images; ++i)
         v.insert(v.end(), {(uint64_t)(uintptr_t)b->lr[i], (uint64_t)(uintptr_t)b->hr_out[i], (uint64_t)b->h[i],
                            (uint64_t)b->w[i], (uint64_t)b->scale[i]});
@@ -1170,6 +1179,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             TRY(hash_scratch(c, ha));
             ha.dir = P<Slot>(d.dir);
             ha.dir_cap = d.cap;
+            ha.dir_filter = P<uint32_t>(d.dfilt);
             ha.bins = P<uint2>(c->qbins);
             ha.keys_tmajor = 1;
             HIPCHK(c, launch_hash(ha, st));
@@ -1388,7 +1398,7 @@ zh_status zh_stats(zh_ctx* c, zh_stats_t* out) {
     out->lle_fp64 = h[C_LLE64];
     uint64_t db = 0;
     for (const Dict& d : c->dicts)
-        db += d.hi.bytes + d.lo.bytes + d.dir.bytes + d.tids.bytes + d.alpha.bytes + d.ahi.bytes + d.alo.bytes;
+        db += d.hi.bytes + d.lo.bytes + d.dir.bytes + d.dfilt.bytes + d.tids.bytes + d.alpha.bytes + d.ahi.bytes + d.alo.bytes;
     out->dict_bytes = db;
     return ZH_OK;
 }

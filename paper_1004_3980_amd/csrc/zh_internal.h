@@ -67,9 +67,21 @@ struct HashArgs {
     unsigned int* fix_count; // [ceil(n/16)] entries written by each wave
     const Slot* dir;         // bin directories [L, dir_cap], or null: no lookup
     uint64_t dir_cap;
+    const uint32_t* dir_filter;  // [L, dir_cap / 8] presence bits of the keys (dir_filter_bit)
     uint2* bins;             // [L, n] (offset, count) of each key's bin, when dir is set
                              // (needs keys_tmajor)
 };
+// Presence filter of a table's keys: min(4 dir_cap, 2^32) bits, a key's bit
+// taken from its high half (the directory slot comes from the low bits).
+// A clear bit proves the key absent; a set bit sends the lookup on to the
+// directory.
+__host__ __device__ inline uint64_t dir_filter_words(uint64_t cap) {
+    const uint64_t w = cap / 8;
+    return w < 1 ? 1 : (w > (1ull << 27) ? (1ull << 27) : w);
+}
+__host__ __device__ inline uint32_t dir_filter_bit(uint64_t key, uint64_t cap) {
+    return (uint32_t)(key >> 32) & (uint32_t)(32 * dir_filter_words(cap) - 1);
+}
 // position of the key of (row, table)
 __device__ __forceinline__ int64_t key_pos(const HashArgs& a, int64_t row, int l) {
     return a.keys_tmajor ? (int64_t)l * a.n + row : row * a.L + l;
@@ -81,8 +93,9 @@ void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, floa
 
 // ---- table build (k_table.hip) ----------------------------------------------
 hipError_t launch_dir_clear(Slot* dir, uint64_t count, hipStream_t st);
+// also sets the key bits of the table's presence filter (cleared beforehand)
 hipError_t launch_dir_insert(const uint64_t* keys, int64_t n, int L, int l, Slot* dir,
-                             uint64_t cap, uint32_t* slot_of, uint32_t* ids, hipStream_t st);
+                             uint64_t cap, uint32_t* filter, uint32_t* slot_of, uint32_t* ids, hipStream_t st);
 hipError_t launch_dir_offsets(const uint32_t* sorted_slot, int64_t n, Slot* dir, hipStream_t st);
 // stable LSD radix sort of (key, val) pairs on the low `bits` bits of key
 hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
