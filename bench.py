@@ -46,18 +46,14 @@ def search_bytes(ncand, nsurv, wl, gram_bytes):
     its rotated coordinates (64 floats), the output (K ids, K distances,
     count, candidate count, survivor count) and the packed Gram matrix of the
     neighbours (36 entries of gram_bytes). Per distinct candidate: its ID
-    (4 B) and its screen row (2 screen_stride(D) B: the coordinates in the
-    leading principal directions and the bounds). Per row given an exact
-    distance: its fp32 feature row (4D B)."""
+    (4 B) and its 64-byte screen row (int8 coordinates in the leading
+    principal directions and the bounds). Per row given an exact distance:
+    its fp32 feature row (4D B)."""
     M = ncand.astype(np.int64)
     S = nsurv.astype(np.int64)
     D, L, K = wl.D, wl.L, wl.K
-    m = min(D, 60)
-    ss = 32
-    while ss < ((m + 3) & ~3) + 4:
-        ss *= 2
     per_q = 8 * L + 4 * D + 4 * 64 + 8 * K + 12 + 36 * gram_bytes
-    return int(len(M) * per_q + (M * (4 + 2 * ss)).sum() + (S * 4 * D).sum())
+    return int(len(M) * per_q + (M * (4 + 64)).sum() + (S * 4 * D).sum())
 
 
 def traffic_from_profile(form):

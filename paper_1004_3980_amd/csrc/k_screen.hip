@@ -3,14 +3,14 @@
 // are the costly part of the search).
 //
 // The pre-filter only has to discard candidates that are certainly farther
-// than K others. It reads, per candidate, one row of the screen plane: the
-// coordinates y = Phi x of the feature vector in m = min(D, 60) orthonormal
-// directions, stored in bf16, with |y~|^2 and rho_x >= |Phi x - y~| in the
-// row's tail (128 bytes at D = 100, one memory line). Phi holds the leading
-// principal directions of the dictionary's features: the 4-channel gradient
-// features of a 5x5 patch are linear in the 65 pixels of a 9x9 cross minus
-// their mean, so they span at most 64 dimensions and 60 of them hold all but
-// a few 1e-4 of the energy.
+// than K others. It reads, per candidate, one 64-byte row of the screen
+// plane: the coordinates y = Phi x of the feature vector in m = min(D, 56)
+// orthonormal directions as int8 codes of one bf16 row scale, with |y~|^2,
+// the scale and rho_x >= |Phi x - y~| in the row's tail. Phi holds the
+// leading principal directions of the dictionary's features: the 4-channel
+// gradient features of a 5x5 patch are linear in the 65 pixels of a 9x9 cross
+// minus their mean, so they span at most 64 dimensions and 56 of them hold
+// all but a few 1e-4 of the energy.
 //
 // For any matrix Phi with largest singular value sigma,
 //   |q - x| >= |Phi (q - x)| / sigma >= (|y_q - y~_x| - rho_q - rho_x) / sigma,
@@ -177,17 +177,28 @@ float rotate_bound_coeff(int D) {
 
 // ---- screen rows of the dictionary -----------------------------------------
 // One wave per row: lane j < m forms y_j = sum_i phi_ji x_i in FP64 (phi^T in
-// LDS), rounds it to bf16 and the wave adds (y~_j - y_j)^2 and y~_j^2. The
-// FP64 sum itself is within D 2^-53 sum_i |phi_ji x_i| <= 1e-13 |x|_1 of the
-// exact product, which is added to rho_x.
+// LDS). The row scale s_x is max_j |y_j| / 127 rounded up to bf16, so every
+// code c_j = rint(y_j / s_x) lies in [-127, 127] and y~_j = s_x c_j is exact
+// in fp32; the wave adds (y~_j - y_j)^2 and y~_j^2. The FP64 sum itself is
+// within D 2^-53 sum_i |phi_ji x_i| <= 1e-13 |x|_1 of the exact product,
+// which is added to rho_x.
+__device__ __forceinline__ uint32_t f32_up_bits(double v) {   // fp32 >= v >= 0
+    float f = (float)v;
+    if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+    return __float_as_uint(f);
+}
+__device__ __forceinline__ uint16_t bf16_up(double v) {         // bf16 >= v >= 0
+    uint32_t b = f32_up_bits(v);
+    if (b & 0xFFFFu) b = (b | 0xFFFFu) + 1u;
+    return (uint16_t)(b >> 16);
+}
 __global__ __launch_bounds__(256) void k_screen_rows(const float* __restrict__ x, int64_t n, int D, int m,
-                                                     const double* __restrict__ phiT, uint16_t* __restrict__ sc) {
+                                                     const double* __restrict__ phiT, uint8_t* __restrict__ sc) {
     extern __shared__ double sphi[];   // [D][64]
     __shared__ double sx[4][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int e = threadIdx.x; e < D * 64; e += 256) sphi[e] = phiT[e];
     __syncthreads();
-    const int TS = screen_tail(D), SS = screen_stride(D);
     const int64_t nw = (int64_t)gridDim.x * 4;
     for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < n; r += nw) {
         double l1 = 0.0;
@@ -202,29 +213,29 @@ __global__ __launch_bounds__(256) void k_screen_rows(const float* __restrict__ x
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double y = 0.0;
         for (int i = 0; i < D; ++i) y += sphi[i * 64 + lane] * sx[wave][i];
-        const uint16_t h = lane < m ? bf16_rne((float)y) : (uint16_t)0;
-        const double yt = (double)bf16_to_f(h);
-        const double err = lane < m ? yt - y : 0.0;
+        if (lane >= m) y = 0.0;
+        const double amax = wave_max_f64(fabs(y));
+        const uint16_t sb = bf16_up(amax / 127.0);
+        const double sxf = (double)bf16_to_f(sb);
+        const double cq = sxf > 0.0 ? rint(y / sxf) : 0.0;
+        const int code = (int)fmin(127.0, fmax(-127.0, cq));
+        const double yt = sxf * (double)code;
+        const double err = yt - y;
         const double rho2 = wave_sum_f64(err * err);
         const double n2 = wave_sum_f64(yt * yt);
         const double rho = sqrt(rho2) * (1.0 + 1e-12) + 1e-13 * l1 + 1e-300;
-        float rf = (float)rho;
-        if ((double)rf < rho) rf = __uint_as_float(__float_as_uint(rf) + 1u);
-        const float nf = (float)n2;
-        uint16_t v = h;
-        if (lane >= TS && lane < TS + 4) {
-            const uint32_t bits = __float_as_uint(lane < TS + 2 ? nf : rf);
-            v = (lane & 1) == (TS & 1) ? (uint16_t)(bits & 0xFFFFu) : (uint16_t)(bits >> 16);
-        }
-        if (lane < SS) sc[r * SS + lane] = v;
+        const uint64_t tail = (uint64_t)__float_as_uint((float)n2) | ((uint64_t)sb << 32) | ((uint64_t)bf16_up(rho) << 48);
+        const uint8_t v = lane < kScreenMax ? (uint8_t)(int8_t)code : (uint8_t)(tail >> (8 * (lane - kScreenMax)));
+        sc[r * kScreenBytes + lane] = v;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
-hipError_t launch_screen_rows(const float* x, int64_t n, int D, int m, const double* phiT, uint16_t* sc,
+hipError_t launch_screen_rows(const float* x, int64_t n, int D, int m, const double* phiT, uint8_t* sc,
                               hipStream_t st) {
+    static_assert(kScreenMax + 8 == kScreenBytes && kScreenBytes == 64, "screen row: 56 codes and 8 tail bytes");
     if (n == 0) return hipSuccess;
     if (D < 1 || D > 128 || m < 1 || m > kScreenMax || m > D) return hipErrorInvalidValue;
     const int64_t blocks = std::min<int64_t>((n + 3) / 4, 4096);

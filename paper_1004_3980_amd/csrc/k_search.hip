@@ -335,6 +335,7 @@ __device__ __forceinline__ void load_query(const SearchArgs& a, int q, float (&q
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // order-preserving map of a finite float to uint32
@@ -347,10 +348,6 @@ __device__ __forceinline__ uint4 ld16(const char* p) {
     const uint2 x = *reinterpret_cast<const uint2*>(p);
     const uint2 y = *reinterpret_cast<const uint2*>(p + 8);
     return make_uint4(x.x, x.y, y.x, y.y);
-}
-// keep the first nv (0..8) bf16 elements of a 16-byte group
-__device__ __forceinline__ uint32_t keep_mask(int nv, int w) {
-    return (nv > 2 * w ? 0x0000FFFFu : 0u) | (nv > 2 * w + 1 ? 0xFFFF0000u : 0u);
 }
 
 // R-th smallest (R >= 1) of the M keys held NSL per lane (element s*64 + lane):
@@ -400,19 +397,15 @@ __device__ void mark_lowest16(const uint32_t (&kv)[NSL], int n, bool (&keep)[NSL
     }
 }
 
-// Relative error coefficient c of the screen value |q|^2 + |x_hi|^2 - 2 q.x_hi
-// against |q - x_hi|^2: the error is at most c (|q|^2 + |x_hi|^2). Terms: the
-// fp32 sums of squares (gamma_D each), the bf16 split of q (the low part
-// leaves at most 2^-16 |q_i|), the fp32 accumulation of the MFMA dot product
-// (at most 33 roundings per 32 coordinates, and the sum of the two columns),
-// with |q.x_hi| <= (|q|^2 + |x_hi|^2) / 2, and the fp32 evaluation of the
-// screen value (8 u). The total is doubled.
-float screen_coeff(int D) {
-    const double u = 1.0 / 16777216.0;
-    const int ns = (D + 31) / 32;
-    const double c = 2.0 * gamma_n(D, u) + 1.0 / 65536.0 + 1.01 * gamma_n(33 * ns + 1, u) + 8.0 * u;
-    return (float)(2.0 * c);
-}
+// Relative error coefficient c of the screen value a2 = |y^|^2 + |y~|^2 -
+// 2 y^.y~ against |y^ - y~|^2, y^ = s_q (h + l / 128) the coded query and
+// y~ = s_x c the screen row: the error is at most c (|y^|^2 + |y~|^2). The
+// integer products h.c and l.c are exact; the terms are the fp32 roundings
+// of |y^|^2 and |y~|^2 (u each), of (128 h.c + l.c) / 128 and its two scale
+// factors (3 u of |y^.y~| <= (|y^|^2 + |y~|^2) / 2, doubled in a2), of the sum
+// |y^|^2 + |y~|^2 (u) and of the difference (u |a2| <= 2 u (|y^|^2 + |y~|^2)):
+// 7 u in all, doubled, rounded up to 16 u.
+float screen_coeff() { return (float)(16.0 / 16777216.0); }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -606,12 +599,13 @@ __device__ void mark_smallest(const uint32_t (&kv)[NSL], const uint32_t (&tie)[N
 //     time; an LDS hash set of the IDs seen so far (open addressing, atomic
 //     compare-and-swap inserts, an atomic minimum keeping the earliest lane
 //     of a chunk) keeps first occurrences in order, up to `cap`.
-//  2. Screen, when more than K candidates: each candidate's screen row (one
-//     memory line: its coordinates y~ in the dictionary's leading principal
-//     directions, bf16, with |y~|^2 and rho_x) gives |y_q - y~|^2 =
-//     |y_q|^2 + |y~|^2 - 2 y_q.y~ on the matrix cores (screen rows as A, the
-//     rotated query split into bf16 high and low parts as two columns of B),
-//     and with the error bounds a lower bound L <= |q - x|^2. The K
+//  2. Screen, when more than K candidates: each candidate's 64-byte screen
+//     row (its coordinates y~ = s_x c in the dictionary's leading principal
+//     directions as int8 codes c, with |y~|^2, s_x and rho_x) gives
+//     |y^_q - y~|^2 = |y^_q|^2 + |y~|^2 - 2 y^_q.y~ from one int8 product on
+//     the matrix cores (screen rows as A, the rotated query coded as
+//     s_q (h + l / 128), its int8 codes h and l as two columns of B), and
+//     with the error bounds a lower bound L <= |q - x|^2. The K
 //     candidates of smallest L get exact distances; the largest upper bound
 //     U_K of those bounds the K-th smallest distance, so only candidates with
 //     L <= U_K can be among the K nearest. Those get exact distances too (the
@@ -632,12 +626,11 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
     uint32_t* cdist = cids + a.cp;
     float2* stl = reinterpret_cast<float2*>(hset);
     __shared__ __align__(16) float sq[128];
-    __shared__ __align__(16) uint16_t sqs[2][kRotStride];   // bf16 high and low parts of y_q
+    __shared__ __align__(16) int8_t sqi[2][kRotStride];     // int8 high and low codes of y_q
     __shared__ uint32_t sstart[kMaxL + 1];
     __shared__ uint32_t soff[kMaxL];
     const int lane = threadIdx.x;
     const int L = a.L, D = a.D;
-    const int SS = screen_stride(D), TS = screen_tail(D);
     const int hsz = a.hsz;
     const uint32_t hmask = (uint32_t)hsz - 1u;
     const int hshift = 32 - __builtin_ctz((unsigned)hsz);
@@ -662,14 +655,24 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
         for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
         for (int i = lane; i < 128; i += 64) sq[i] = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
         const float rv = a.qrot[(int64_t)q * kRotStride + lane];
-        const float rho_q = __shfl(rv, kRotStride - 1);
         const float yq = lane < kScreenMax ? rv : 0.0f;
+        // y_q as s_q (h + l / 128) with int8 codes h, l; the residual
+        // eps_q = |y_q - that| joins rho_q, |that|^2 goes to the screen value
+        float rho_q, qn2, s_q;
         {
-            const uint16_t h = bf16_rne(yq);
-            sqs[0][lane] = h;
-            sqs[1][lane] = bf16_rne(yq - bf16_to_f(h));
+            const float amax = wave_max_f32(fabsf(yq));
+            s_q = amax > 0.0f ? amax / 127.0f : 1.0f;
+            const float t = yq / s_q;
+            const float h = fminf(127.0f, fmaxf(-127.0f, rintf(t)));
+            const float l = fminf(127.0f, fmaxf(-127.0f, rintf((t - h) * 128.0f)));
+            sqi[0][lane] = (int8_t)h;
+            sqi[1][lane] = (int8_t)l;
+            const double yh = (double)s_q * ((double)h + (double)l * (1.0 / 128.0));
+            const double er = (double)yq - yh;
+            const double eps = sqrt(wave_sum_f64(er * er)) * (1.0 + 1e-12) + 1e-300;
+            qn2 = (float)wave_sum_f64(yh * yh);
+            rho_q = (__shfl(rv, kRotStride - 1) + (float)eps) * (1.0f + 1e-6f);
         }
-        const float qn2 = (float)wave_sum_f64((double)yq * (double)yq);
         __syncthreads();
 
         // ---- 1. candidates, first occurrences in order, up to cap
@@ -731,70 +734,50 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
         int nA = 0;   // rows of the first exact pass (cids[0..nA)), whose Gram matrix is in hset
         if (M > a.K) {
             const int K = a.K;
-            uint4 qb[2];
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const uint4 t4 = *reinterpret_cast<const uint4*>(&sqs[ri & 1][32 * s + 8 * kb]);
-                qb[s] = ri < 2 ? t4 : make_uint4(0u, 0u, 0u, 0u);
-            }
-            const int nss = SS >> 5;
-            // screen rows of 16 candidates: lane (ri, kb) holds coordinates
-            // 32 s + 8 kb .. + 7 of candidate t + ri; the row tail goes to stl
-            auto load_chunk = [&](int t, uint4 (&v)[2]) {
+            // B operand: column 0 the high codes of y_q, column 1 the low
+            // codes, lane (ri, kb) coordinates 16 kb .. 16 kb + 15
+            const i32x4 qb = ri < 2 ? *reinterpret_cast<const i32x4*>(&sqi[ri][16 * kb]) : i32x4{0, 0, 0, 0};
+            // screen rows of 16 candidates: lane (ri, kb) holds bytes
+            // 16 kb .. 16 kb + 15 of candidate t + ri's row; the tail (bytes
+            // 56 .. 63) goes to stl and out of the product
+            auto load_chunk = [&](int t, i32x4& v) {
                 const int c = t + ri;
-                const bool cv = c < M;
-                const uint32_t id = cv ? cids[c] : 0u;
-                const char* rowp = reinterpret_cast<const char*>(a.sc) + (size_t)id * (uint32_t)(2 * SS);
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    v[s] = make_uint4(0u, 0u, 0u, 0u);
-                    if (s < nss && cv) v[s] = *reinterpret_cast<const uint4*>(rowp + 2 * (32 * s + 8 * kb));
-                }
+                const uint32_t id = c < M ? cids[c] : 0u;
+                v = i32x4{0, 0, 0, 0};
+                if (c < M) v = *reinterpret_cast<const i32x4*>(a.sc + (size_t)id * kScreenBytes + 16 * kb);
             };
-            auto screen_chunk = [&](int t, uint4 (&v)[2]) {
+            auto screen_chunk = [&](int t, i32x4& v) {
                 const int c = t + ri;
-                const bool cv = c < M;
-                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    if (s < nss) {
-                        const int d = 32 * s + 8 * kb;
-                        if (cv && d <= TS && TS < d + 8)
-                            stl[c] = TS == d ? make_float2(__uint_as_float(v[s].x), __uint_as_float(v[s].y))
-                                             : make_float2(__uint_as_float(v[s].z), __uint_as_float(v[s].w));
-                        const int nv = TS - d;
-                        if (nv < 8) {
-                            v[s].x &= keep_mask(nv, 0);
-                            v[s].y &= keep_mask(nv, 1);
-                            v[s].z &= keep_mask(nv, 2);
-                            v[s].w &= keep_mask(nv, 3);
-                        }
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, v[s]),
-                                                                     __builtin_bit_cast(bf16x8, qb[s]), acc, 0, 0, 0);
-                    }
+                if (kb == 3) {
+                    if (c < M) stl[c] = make_float2(__int_as_float(v[2]), __int_as_float(v[3]));
+                    v[2] = 0;
+                    v[3] = 0;
                 }
-                // lane (kb, 0) holds y_q,hi.y~ and lane (kb, 1) y_q,lo.y~ of candidates t + 4 kb + r
-                float lo4[4];
+                const i32x4 acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(v, qb, i32x4{0, 0, 0, 0}, 0, 0, 0);
+                // lane (kb, 0) holds h.c and lane (kb, 1) l.c of candidates
+                // t + 4 kb + r, both exact; (128 h.c + l.c) / 128 is rounded once
+                int lo4[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) lo4[r] = __shfl_down(acc[r], 1);
                 if (ri == 0) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int cc = t + 4 * kb + r;
-                        if (cc < M) cdist[cc] = __float_as_uint(acc[r] + lo4[r]);
+                        if (cc < M) cdist[cc] = __float_as_uint((float)(128 * acc[r] + lo4[r]) * (1.0f / 128.0f));
                     }
                 }
             };
-            // two chunks in flight per step
-            for (int t = 0; t < M; t += 32) {
-                uint4 v0[2], v1[2];
-                load_chunk(t, v0);
-                load_chunk(t + 16, v1);
-                screen_chunk(t, v0);
-                if (t + 16 < M) screen_chunk(t + 16, v1);
+            // four chunks (64 rows) in flight per step
+            for (int t = 0; t < M; t += 64) {
+                i32x4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) load_chunk(t + 16 * u, v[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (t + 16 * u < M) screen_chunk(t + 16 * u, v[u]);
             }
             __syncthreads();
-            // |y_q - y~| >= a_lo from the screen value and its error bound c (|y_q|^2 + |y~|^2);
+            // |y^_q - y~| >= a_lo from the screen value and its error bound c (|y^_q|^2 + |y~|^2);
             // |q - x| >= (a_lo - rho_q - rho_x) / sigma; every fp32 step moves outward
             uint32_t lv[NSL], iv[NSL];
             bool valid[NSL];
@@ -805,12 +788,14 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
                 valid[s] = c < M;
                 if (c < M) {
                     const float2 tl = stl[c];
-                    const float dot = __uint_as_float(cdist[c]);
+                    const uint32_t sr = __float_as_uint(tl.y);
+                    const float dot = __uint_as_float(cdist[c]) * s_q * bf16_to_f((uint16_t)(sr & 0xFFFFu));
+                    const float rho_x = bf16_to_f((uint16_t)(sr >> 16));
                     const float nn = qn2 + tl.x;
                     const float a2 = nn - 2.0f * dot;
                     const float E = fmaf(a.ce, nn, 1e-30f);
                     const float alo = sqrtf(fmaxf((a2 - E) * (1.0f - 1e-6f), 0.0f)) * (1.0f - 1e-6f);
-                    const float l = fmaxf(alo * (1.0f - 1e-6f) - (rho_q + tl.y) * (1.0f + 1e-6f), 0.0f);
+                    const float l = fmaxf(alo * (1.0f - 1e-6f) - (rho_q + rho_x) * (1.0f + 1e-6f), 0.0f);
                     lv[s] = __float_as_uint(l * l * a.inv_s2 * (1.0f - 1e-5f));
                     iv[s] = cids[c];
                 }

@@ -325,13 +325,13 @@ zh_status build_screen(zh_ctx* c, Dict& d, const float* feat) {
             ph[(size_t)j * DP + i] = h;
             pl[(size_t)j * DP + i] = bf16_rne_host(v - bf16_f_host(h));
         }
-    if ((st = ensure(c, d.sc, sizeof(uint16_t) * (size_t)n * screen_stride(D))) != ZH_OK) goto out;
+    if ((st = ensure(c, d.sc, (size_t)kScreenBytes * (size_t)n)) != ZH_OK) goto out;
     if ((st = ensure(c, d.phi_hi, sizeof(uint16_t) * ph.size())) != ZH_OK) goto out;
     if ((st = ensure(c, d.phi_lo, sizeof(uint16_t) * pl.size())) != ZH_OK) goto out;
     if (hipMemcpyAsync(phit.p, phiT.data(), sizeof(double) * phiT.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(d.phi_hi.p, ph.data(), sizeof(uint16_t) * ph.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(d.phi_lo.p, pl.data(), sizeof(uint16_t) * pl.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        launch_screen_rows(feat, n, D, m, P<double>(phit), P<uint16_t>(d.sc), c->stream) != hipSuccess ||
+        launch_screen_rows(feat, n, D, m, P<double>(phit), P<uint8_t>(d.sc), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         (void)hipGetLastError();
         st = fail(c, ZH_EDEVICE, "zh_build_tables: screen rows failed");
@@ -360,8 +360,8 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.hi = P<uint16_t>(d.hi);
     a.lo = P<uint16_t>(d.lo);
     a.hs = hi_stride(d.D);
-    a.ce = screen_coeff(screen_tail(d.D));
-    a.sc = P<uint16_t>(d.sc);
+    a.ce = screen_coeff();
+    a.sc = P<uint8_t>(d.sc);
     a.xf = P<float>(d.xf);
     a.inv_s2 = d.inv_s2;
     a.out_ids = P<int32_t>(c->ids);

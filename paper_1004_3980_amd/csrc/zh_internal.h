@@ -109,7 +109,7 @@ struct SearchArgs {
     int hsz, cp;             // LDS hash set slots, candidate slots (set by the launcher)
     int hs;                  // row stride of the high plane (halfwords)
     float ce;                // relative error coefficient of the screen's |y_q - y~_x|^2
-    const uint16_t* sc;      // [N, screen_stride(D)] screen plane (early-stop search)
+    const uint8_t* sc;       // [N, kScreenBytes] screen plane (early-stop search)
     const float* xf;         // [N, D] fp32 features: the exact passes of the early-stop search
     const float* qrot;       // [Q, 64] rotated queries: y_q, zeros, rho_q in the last slot
     float inv_s2;            // lower bound of 1 / sigma_max(Phi)^2
@@ -132,25 +132,20 @@ struct SearchArgs {
     unsigned int* counters;  // [0] overflow count, [1] FP64 rank fallbacks
 };
 hipError_t launch_search(const SearchArgs& a, hipStream_t st);
-float screen_coeff(int D);   // error coefficient of the search's bf16 pre-filter (host)
+float screen_coeff();        // error coefficient of the search's int8 pre-filter (host)
 // Row layout of the high plane: D bf16 values, zero padding to whole 16-byte
 // rows with at least 4 halfwords of padding.
 __host__ __device__ inline int hi_stride(int D) { return ((((D + 3) & ~3) + 4) + 7) & ~7; }
 hipError_t launch_search_overflow(const SearchArgs& a, int n_over, hipStream_t st);
 
 // ---- screen plane and rotated queries (k_screen.hip) --------------------------
-// Screen row of a dictionary entry: m = screen_dims(D) bf16 coordinates in the
-// leading principal directions Phi, zeros to a multiple of 4, |y~|^2 (fp32)
-// and rho_x >= |Phi x - y~| (fp32, rounded up), zeros to a power of two of at
-// least 32 halfwords (128 bytes at D = 100: one memory line).
-constexpr int kScreenMax = 60;
+// Screen row of a dictionary entry, 64 bytes: the coordinates y = Phi x in the
+// m = screen_dims(D) leading principal directions as int8 codes c_j of one
+// row scale s_x (bf16), y~ = s_x c, zeros to byte 56; then |y~|^2 (fp32),
+// s_x and rho_x >= |Phi x - y~| (bf16, rounded up).
+constexpr int kScreenMax = 56;
+constexpr int kScreenBytes = 64;
 __host__ __device__ inline int screen_dims(int D) { return D < kScreenMax ? D : kScreenMax; }
-__host__ __device__ inline int screen_tail(int D) { return (screen_dims(D) + 3) & ~3; }
-__host__ __device__ inline int screen_stride(int D) {
-    int s = 32;
-    while (s < screen_tail(D) + 4) s <<= 1;
-    return s;
-}
 constexpr int kRotStride = 64;   // floats per rotated query row; the last holds rho_q
 // FP64 sum of x x^T over ns rows r_i = floor(i n / ns) (ns <= 65536); part holds
 // 128 partial D x D matrices
@@ -158,8 +153,8 @@ hipError_t launch_cov(const float* x, int64_t n, int D, int64_t ns, double* part
 // rows of Phi (m x D fp32) from the covariance; returns a bound on sigma_max(Phi)^2
 double screen_basis(const double* C, int D, int m, float* phi);
 float rotate_bound_coeff(int D);
-// screen rows [n, screen_stride(D)] from x [n, D]; phiT is FP64 [D][64]
-hipError_t launch_screen_rows(const float* x, int64_t n, int D, int m, const double* phiT, uint16_t* sc,
+// screen rows [n, kScreenBytes] from x [n, D]; phiT is FP64 [D][64]
+hipError_t launch_screen_rows(const float* x, int64_t n, int D, int m, const double* phiT, uint8_t* sc,
                               hipStream_t st);
 // rotated queries [n, 64] from feat [n, D]; Phi split into bf16 [64][round32(D)] planes
 hipError_t launch_rotate(const float* feat, int64_t n, int D, const uint16_t* p_hi, const uint16_t* p_lo, float c1,
