@@ -153,16 +153,37 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
     u16x8 bh[PREC == 1 ? NS : 1], bl[PREC == 1 ? NS : 1];
     float bf[PREC == 0 ? 32 : 1];
     if (PREC == 1) {
+        // rows on 16-byte boundaries: two 16-byte loads per step
+        const bool vec = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(a.feat) & 15) == 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            const int d0 = 32 * s + 8 * kb;
+            float x[8];
+            if (vec) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const float4 v = (rowok && d0 + 4 * j < D)
+                                         ? *reinterpret_cast<const float4*>(a.feat + myrow * D + d0 + 4 * j)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                    x[4 * j] = v.x;
+                    x[4 * j + 1] = v.y;
+                    x[4 * j + 2] = v.z;
+                    x[4 * j + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = (rowok && d0 + e < D) ? a.feat[myrow * D + d0 + e] : 0.0f;
+            }
+            // high part: x rounded to bf16 (nearest even); low part: the
+            // exact remainder rounded likewise
+            bf16x8 hv, lv;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int d = 32 * s + 8 * kb + e;
-                const float x = (rowok && d < D) ? a.feat[myrow * D + d] : 0.0f;
-                const uint16_t h = bf16_rne(x);
-                bh[s][e] = h;
-                bl[s][e] = bf16_rne(x - bf16_to_f(h));
+                hv[e] = (__bf16)x[e];
+                lv[e] = (__bf16)(x[e] - (float)hv[e]);
             }
+            bh[s] = __builtin_bit_cast(u16x8, hv);
+            bl[s] = __builtin_bit_cast(u16x8, lv);
         }
     } else {
 #pragma unroll
@@ -180,19 +201,33 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
     const int NC = 2 * GK * CH;
     u16x8 pre[NPRE];
     float pbc = 0.0f;
+    // per chunk of this thread, fixed over the groups: bits 0..15 its offset
+    // r DP + 8 ch in the pair's rows (halfwords), bits 16..30 its LDS offset,
+    // bit 31 the low plane; 0x7FFFFFFF when the thread has no such chunk
+    // (offsets below 2^15: GK <= 64 rows of DP <= 128, 2 R DS < 2^15)
+    uint32_t cdesc[NPRE];
+#pragma unroll
+    for (int c = 0; c < NPRE; ++c) {
+        const int ci = threadIdx.x + 256 * c;
+        const int plane = ci >= GK * CH;
+        const int r2 = ci - plane * GK * CH;
+        const int r = r2 / CH, ch = r2 - r * CH;
+        cdesc[c] = ci < NC ? (uint32_t)(r * DP + 8 * ch) | ((uint32_t)((plane * R + r) * DS + 8 * ch) << 16) |
+                                 ((uint32_t)plane << 31)
+                           : 0x7FFFFFFFu;
+    }
     auto fetch = [&](int g) {
         const int l0 = g * kStage;
+        // chunks of rows l0 k + r < m only
+        const uint32_t lim = (uint32_t)((m - l0 * k) * DP);
+        const uint16_t* bhi = a.a_hi + (int64_t)l0 * k * DP;
+        const uint16_t* blo = a.a_lo + (int64_t)l0 * k * DP;
 #pragma unroll
         for (int c = 0; c < NPRE; ++c) {
-            const int ci = threadIdx.x + 256 * c;
+            const uint32_t off = cdesc[c] & 0xFFFFu;
             u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-            if (ci < NC) {
-                const int plane = ci >= GK * CH;
-                const int r2 = ci - plane * GK * CH;
-                const int r = r2 / CH, ch = r2 - r * CH;
-                const int grow = l0 * k + r;
-                if (grow < m) v = *reinterpret_cast<const u16x8*>((plane ? a.a_lo : a.a_hi) + (int64_t)grow * DP + 8 * ch);
-            }
+            if (cdesc[c] != 0x7FFFFFFFu && off < lim)
+                v = *reinterpret_cast<const u16x8*>(((cdesc[c] >> 31) ? blo : bhi) + off);
             pre[c] = v;
         }
         // beta and the bound constant: thread t < 2 GK takes one value
@@ -203,15 +238,8 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int c = 0; c < NPRE; ++c) {
-            const int ci = threadIdx.x + 256 * c;
-            if (ci < NC) {
-                const int plane = ci >= GK * CH;
-                const int r2 = ci - plane * GK * CH;
-                const int r = r2 / CH, ch = r2 - r * CH;
-                *reinterpret_cast<u16x8*>(sA16 + (plane * R + r) * DS + 8 * ch) = pre[c];
-            }
-        }
+        for (int c = 0; c < NPRE; ++c)
+            if (cdesc[c] != 0x7FFFFFFFu) *reinterpret_cast<u16x8*>(sA16 + ((cdesc[c] >> 16) & 0x7FFFu)) = pre[c];
         const int t = threadIdx.x;
         if (t < 2 * GK) (t < GK ? sBeta[t] : sBc0[t - GK]) = pbc;
     };
