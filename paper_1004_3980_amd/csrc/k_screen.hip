@@ -249,8 +249,12 @@ hipError_t launch_screen_rows(const float* x, int64_t n, int D, int m, const dou
 // >= m zero) split into bf16 high and low parts and staged once per
 // workgroup in LDS, the feature rows split likewise in registers; three
 // products (hi.hi, hi.lo, lo.hi) and a fourth of the absolute high parts for
-// the error bound. One wave takes 16 rows at a time. Output row (64 floats):
-// y_0 .. y_{m-1}, zeros, and in the last slot rho_q >= |y_q - Phi q|.
+// the error bound. One wave takes 16 rows at a time. Then y_q is coded for
+// the screen's int8 product as y^ = s_q (h + l / 128): s_q = max_j |y_j| /
+// 127, h = rint(y / s_q), l = rint((y / s_q - h) 128), all codes in
+// [-127, 127]. Output row (kRotStride floats): the h codes (64 bytes, zeros
+// past m), the l codes (64 bytes), then s_q, |y^|^2 (fp32 of the FP64 sum)
+// and rho_q >= |y^ - Phi q| (the rotation bound plus |y^ - y_q|, rounded up).
 template <int NS>
 __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ feat, int64_t n, int D,
                                                 const uint16_t* __restrict__ p_hi, const uint16_t* __restrict__ p_lo,
@@ -304,7 +308,8 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ feat, 
             }
         }
         float b2 = 0.0f;
-#pragma unroll 1
+        float y[4][4];   // lane holds y_j, j = 16 tt + 4 kb + i, of feature row ri
+#pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
             f32x4 cs = f32x4{0.f, 0.f, 0.f, 0.f}, chl = cs, clh = cs, cab = cs;
 #pragma unroll
@@ -320,19 +325,66 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ feat, 
                                                              __builtin_bit_cast(bf16x8, bh[s] & am), cab, 0, 0, 0);
             }
             cs = cs + (chl + clh);
-            // lane holds y_j, j = 16 tt + 4 kb + i, of feature row ri
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float bnd = fmaf(c1, cab[i], 1e-30f);
                 b2 = fmaf(bnd, bnd, b2);
+                y[tt][i] = cs[i];
             }
-            if (rowok) *reinterpret_cast<float4*>(out + row * 64 + 16 * tt + 4 * kb) = make_float4(cs[0], cs[1], cs[2], cs[3]);
+            // one tile at a time: keeps the unrolled tiles from holding all
+            // their operands at once
+            __builtin_amdgcn_sched_barrier(0);
         }
         b2 += __shfl_xor(b2, 16);
         b2 += __shfl_xor(b2, 32);
         // at most 64 terms of fp32 sums: relative error below 1e-5
         const float rho = sqrtf(b2 * (1.0f + 1e-5f)) * (1.0f + 1e-6f);
-        if (rowok && kb == 3) out[row * 64 + 63] = rho;
+        // int8 coding of the row; its error |y^ - y_q| is summed exactly (FP64)
+        float amax = 0.0f;
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(y[tt][i]));
+        amax = fmaxf(amax, __shfl_xor(amax, 16));
+        amax = fmaxf(amax, __shfl_xor(amax, 32));
+        const float s_q = amax > 0.0f ? amax * (1.0f / 127.0f) : 1.0f;
+        const float inv = 1.0f / s_q;
+        double e2 = 0.0, n2 = 0.0;
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            hw[tt] = lw[tt] = 0u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float t = y[tt][i] * inv;
+                const float h = fminf(127.0f, fmaxf(-127.0f, rintf(t)));
+                const float l = fminf(127.0f, fmaxf(-127.0f, rintf((t - h) * 128.0f)));
+                const double yh = (double)s_q * ((double)h + (double)l * (1.0 / 128.0));
+                const double er = (double)y[tt][i] - yh;
+                e2 += er * er;
+                n2 += yh * yh;
+                hw[tt] |= (uint32_t)(uint8_t)(int8_t)h << (8 * i);
+                lw[tt] |= (uint32_t)(uint8_t)(int8_t)l << (8 * i);
+            }
+        }
+        e2 += __shfl_xor(e2, 16);
+        e2 += __shfl_xor(e2, 32);
+        n2 += __shfl_xor(n2, 16);
+        n2 += __shfl_xor(n2, 32);
+        if (rowok) {
+            uint32_t* orow = reinterpret_cast<uint32_t*>(out + row * kRotStride);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                orow[4 * tt + kb] = hw[tt];
+                orow[16 + 4 * tt + kb] = lw[tt];
+            }
+            if (kb == 0) {
+                const float eps = (float)(sqrt(e2) * (1.0 + 1e-12) + 1e-300);
+                out[row * kRotStride + 32] = s_q;
+                out[row * kRotStride + 33] = (float)n2;
+                out[row * kRotStride + 34] = (rho + eps) * (1.0f + 1e-6f) + 1e-37f;
+            }
+        }
     }
 }
 

@@ -626,7 +626,6 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
     uint32_t* cdist = cids + a.cp;
     float2* stl = reinterpret_cast<float2*>(hset);
     __shared__ __align__(16) float sq[128];
-    __shared__ __align__(16) int8_t sqi[2][kRotStride];     // int8 high and low codes of y_q
     __shared__ uint32_t sstart[kMaxL + 1];
     __shared__ uint32_t soff[kMaxL];
     const int lane = threadIdx.x;
@@ -654,25 +653,10 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
         if (lane == 0) sstart[L] = (uint32_t)T;
         for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
         for (int i = lane; i < 128; i += 64) sq[i] = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
-        const float rv = a.qrot[(int64_t)q * kRotStride + lane];
-        const float yq = lane < kScreenMax ? rv : 0.0f;
-        // y_q as s_q (h + l / 128) with int8 codes h, l; the residual
-        // eps_q = |y_q - that| joins rho_q, |that|^2 goes to the screen value
-        float rho_q, qn2, s_q;
-        {
-            const float amax = wave_max_f32(fabsf(yq));
-            s_q = amax > 0.0f ? amax / 127.0f : 1.0f;
-            const float t = yq / s_q;
-            const float h = fminf(127.0f, fmaxf(-127.0f, rintf(t)));
-            const float l = fminf(127.0f, fmaxf(-127.0f, rintf((t - h) * 128.0f)));
-            sqi[0][lane] = (int8_t)h;
-            sqi[1][lane] = (int8_t)l;
-            const double yh = (double)s_q * ((double)h + (double)l * (1.0 / 128.0));
-            const double er = (double)yq - yh;
-            const double eps = sqrt(wave_sum_f64(er * er)) * (1.0 + 1e-12) + 1e-300;
-            qn2 = (float)wave_sum_f64(yh * yh);
-            rho_q = (__shfl(rv, kRotStride - 1) + (float)eps) * (1.0f + 1e-6f);
-        }
+        // the coded query y^ = s_q (h + l / 128): int8 codes h and l, then
+        // s_q, |y^|^2 and rho_q >= |y^ - Phi q|
+        const float* qr = a.qrot + (int64_t)q * kRotStride;
+        const float s_q = qr[32], qn2 = qr[33], rho_q = qr[34];
         __syncthreads();
 
         // ---- 1. candidates, first occurrences in order, up to cap
@@ -736,7 +720,7 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
             const int K = a.K;
             // B operand: column 0 the high codes of y_q, column 1 the low
             // codes, lane (ri, kb) coordinates 16 kb .. 16 kb + 15
-            const i32x4 qb = ri < 2 ? *reinterpret_cast<const i32x4*>(&sqi[ri][16 * kb]) : i32x4{0, 0, 0, 0};
+            const i32x4 qb = ri < 2 ? *reinterpret_cast<const i32x4*>(qr + 16 * ri + 4 * kb) : i32x4{0, 0, 0, 0};
             // screen rows of 16 candidates: lane (ri, kb) holds bytes
             // 16 kb .. 16 kb + 15 of candidate t + ri's row; the tail (bytes
             // 56 .. 63) goes to stl and out of the product

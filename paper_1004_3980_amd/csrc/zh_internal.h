@@ -111,7 +111,7 @@ struct SearchArgs {
     float ce;                // relative error coefficient of the screen's |y_q - y~_x|^2
     const uint8_t* sc;       // [N, kScreenBytes] screen plane (early-stop search)
     const float* xf;         // [N, D] fp32 features: the exact passes of the early-stop search
-    const float* qrot;       // [Q, 64] rotated queries: y_q, zeros, rho_q in the last slot
+    const float* qrot;       // [Q, kRotStride] coded rotated queries (k_rotate)
     float inv_s2;            // lower bound of 1 / sigma_max(Phi)^2
     void* gram;              // [Q, 36] packed Gram matrices of the neighbours (K <= 8), or null
     int gram_fp64;           // their precision: FP64 or fp32
@@ -146,7 +146,7 @@ hipError_t launch_search_overflow(const SearchArgs& a, int n_over, hipStream_t s
 constexpr int kScreenMax = 56;
 constexpr int kScreenBytes = 64;
 __host__ __device__ inline int screen_dims(int D) { return D < kScreenMax ? D : kScreenMax; }
-constexpr int kRotStride = 64;   // floats per rotated query row; the last holds rho_q
+constexpr int kRotStride = 64;   // floats per coded query row (k_rotate)
 // FP64 sum of x x^T over ns rows r_i = floor(i n / ns) (ns <= 65536); part holds
 // 128 partial D x D matrices
 hipError_t launch_cov(const float* x, int64_t n, int D, int64_t ns, double* part, double* cov, hipStream_t st);
@@ -156,7 +156,8 @@ float rotate_bound_coeff(int D);
 // screen rows [n, kScreenBytes] from x [n, D]; phiT is FP64 [D][64]
 hipError_t launch_screen_rows(const float* x, int64_t n, int D, int m, const double* phiT, uint8_t* sc,
                               hipStream_t st);
-// rotated queries [n, 64] from feat [n, D]; Phi split into bf16 [64][round32(D)] planes
+// coded rotated queries [n, kRotStride] from feat [n, D] (int8 codes h, l of
+// y_q = Phi q, then s_q, |y^|^2, rho_q); Phi split into bf16 [64][round32(D)] planes
 hipError_t launch_rotate(const float* feat, int64_t n, int D, const uint16_t* p_hi, const uint16_t* p_lo, float c1,
                          float* out, hipStream_t st);
 
