@@ -154,6 +154,8 @@ __global__ __launch_bounds__(256) void k_query_features(const float* __restrict_
     }
     __syncthreads();
     const int64_t plane = (int64_t)h * w;
+    // unrolled so that several gathers are in flight per thread
+#pragma unroll 5
     for (int l = t; l < np * D; l += 256) {
         const int p = l / D, e = l - p * D;
         const int j = j0 + p;

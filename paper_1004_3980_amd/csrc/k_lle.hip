@@ -504,13 +504,16 @@ __device__ __forceinline__ float blend_at(const float* __restrict__ xhat, const 
 // touches is staged in LDS with coalesced loads (ps consecutive floats per
 // patch), then each pixel adds the staged values of its patches in ascending
 // column order: the order and arithmetic of blend_at.
+// The zoom factor is a template parameter: every division by s or 5 s is
+// by a constant.
 constexpr int kBlendSeg = 256;
+template <int s>
 __global__ __launch_bounds__(kBlendSeg) void k_blend_rows(const float* __restrict__ xhat, const int32_t* __restrict__ m,
-                                                          const float* __restrict__ lr, int h, int w, int s,
+                                                          const float* __restrict__ lr, int h, int w,
                                                           float* __restrict__ hr) {
     __shared__ float sv[1408];   // staged patch rows: at most 1350 floats (s = 3)
     __shared__ int sm[kBlendSeg + 8];
-    const int ps = kPatch * s, ps2 = ps * ps;
+    constexpr int ps = kPatch * s, ps2 = ps * ps;
     const int W = s * w;
     const int npi = h - kPatch + 1, npj = w - kPatch + 1;
     const int nseg = (W + kBlendSeg - 1) / kBlendSeg;
@@ -620,7 +623,9 @@ hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, in
     if (H == 0 || W == 0) return hipSuccess;
     const int64_t g = H * ((W + kBlendSeg - 1) / kBlendSeg);
     if (g > 0x7FFFFFFF || scale < 1 || scale > 3) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_blend_rows, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, scale, hr);
+    if (scale == 1) hipLaunchKernelGGL(k_blend_rows<1>, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, hr);
+    else if (scale == 2) hipLaunchKernelGGL(k_blend_rows<2>, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, hr);
+    else hipLaunchKernelGGL(k_blend_rows<3>, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, hr);
     return hipGetLastError();
 }
 
