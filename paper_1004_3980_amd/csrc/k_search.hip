@@ -242,7 +242,7 @@ __device__ __forceinline__ void dist_interval(uint32_t dbits, const Bounds& bd, 
 __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids, const uint32_t* cdist,
                                int M, int Kp, uint64_t mykey, uint32_t& out_id, float& out_d) {
     const int lane = threadIdx.x;
-    const Bounds bd{2.0 * gamma_n(a.D + 3, 1.0 / 16777216.0), (double)a.D * 1.2e-38};
+    const Bounds bd{a.dist_eps, (double)a.D * 1.2e-38};
     const bool ex = key_exact(mykey);
     double lo, hi;
     dist_interval(ex ? 0x80000000u : (uint32_t)(mykey >> 32), bd, lo, hi);
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
             }
             __syncthreads();
             // U_K: the largest upper bound of the K exact distances
-            const Bounds bd{2.0 * gamma_n(D + 3, 1.0 / 16777216.0), (double)D * 1.2e-38};
+            const Bounds bd{a.dist_eps, (double)D * 1.2e-38};
             double uk = 0.0;
             if (lane < K) {
                 double dlo, dhi;
@@ -993,6 +993,7 @@ static void launch_cap(const SearchArgs& a, hipStream_t st) {
 hipError_t launch_search(const SearchArgs& a_in, hipStream_t st) {
     if (a_in.Q == 0) return hipSuccess;
     SearchArgs a = a_in;
+    a.dist_eps = 2.0 * gamma_n(a.D + 3, 1.0 / 16777216.0);
     const int grid = round_grid8(a.Q < 32768 ? a.Q : 32768);
     if (a.D < 1 || a.D > 128) return hipErrorInvalidValue;
     if (a.cap > kCapMax) return hipErrorInvalidValue;
@@ -1016,7 +1017,9 @@ hipError_t launch_search(const SearchArgs& a_in, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_search_overflow(const SearchArgs& a, int grid, hipStream_t st) {
+hipError_t launch_search_overflow(const SearchArgs& a_in, int grid, hipStream_t st) {
+    SearchArgs a = a_in;
+    a.dist_eps = 2.0 * gamma_n(a.D + 3, 1.0 / 16777216.0);
     const bool v4 = a.D % 4 == 0 && a.D <= 128;
     if (v4) hipLaunchKernelGGL((k_search_union<4, kUnionBig, true>), dim3(grid), dim3(64), 0, st, a);
     else hipLaunchKernelGGL((k_search_union<1, kUnionBig, true>), dim3(grid), dim3(64), 0, st, a);

@@ -113,6 +113,7 @@ struct SearchArgs {
     const float* xf;         // [N, D] fp32 features: the exact passes of the early-stop search
     const float* qrot;       // [Q, kRotStride] coded rotated queries (k_rotate)
     float inv_s2;            // lower bound of 1 / sigma_max(Phi)^2
+    double dist_eps;         // 2 gamma_{D+3}: relative bound of an fp32 distance (set by the launcher)
     void* gram;              // [Q, 36] packed Gram matrices of the neighbours (K <= 8), or null
     int gram_fp64;           // their precision: FP64 or fp32
     const uint2* bins;       // [L, Q] (offset, count) of the query's bin in each table
