@@ -5,9 +5,11 @@ Metric: LR patches/s of hash + K-NN + LLE + blend (zh_query, zh_lle_weights,
 zh_reconstruct) on a 1024x1024 LR image at x2 (1,040,400 patches) against a
 2,000,000-pair dictionary (4-gradient features, D = 100), L = 24 tables of
 k = 20 hashes, K = 8, with the dictionary, tables and LR image resident in
-HBM. The default form screens candidates on the bf16 half of the features and
-re-ranks the best 32 exactly in fp32 ("screened"); --form exact ranks every
-candidate with fp32 distances certified against FP64.
+HBM. The default form ("screened") bounds every candidate's distance from
+below with int8 coordinates in the dictionary's leading principal directions
+and gives exact fp32 distances to at most 32 of them (those the bounds cannot
+rule out); --form exact does the same with no limit and certifies the
+selection against FP64.
 
 One JSON line on stdout. Progress goes to stderr.
 """
