@@ -45,7 +45,8 @@ def search_bytes(ncand, nsurv, wl, gram_bytes):
     (each byte the kernel needs, read or written once).
 
     Per patch: its L bins (offset, count: 8 B each), its feature row (4D B),
-    its rotated coordinates (64 floats), the output (K ids, K distances,
+    its coded rotated coordinates (two rows of 64 int8 codes and three
+    floats: 140 B), the output (K ids, K distances,
     count, candidate count, survivor count) and the packed Gram matrix of the
     neighbours (36 entries of gram_bytes). Per distinct candidate: its ID
     (4 B) and its 64-byte screen row (int8 coordinates in the leading
@@ -54,7 +55,7 @@ def search_bytes(ncand, nsurv, wl, gram_bytes):
     M = ncand.astype(np.int64)
     S = nsurv.astype(np.int64)
     D, L, K = wl.D, wl.L, wl.K
-    per_q = 8 * L + 4 * D + 4 * 64 + 8 * K + 12 + 36 * gram_bytes
+    per_q = 8 * L + 4 * D + 140 + 8 * K + 12 + 36 * gram_bytes
     return int(len(M) * per_q + (M * (4 + 64)).sum() + (S * 4 * D).sum())
 
 
