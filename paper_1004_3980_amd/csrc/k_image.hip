@@ -140,7 +140,10 @@ __global__ __launch_bounds__(256) void k_query_features(const float* __restrict_
                                                         int h, int w, float* __restrict__ feat,
                                                         double* __restrict__ mu) {
     constexpr int D = MODE == 0 ? 25 : 100;
+    constexpr int NCH = MODE == 0 ? 1 : 4;        // image, or the four gradient maps
+    constexpr int SW = 64 + kPatch - 1;           // columns under 64 patches
     __shared__ double smu[64];
+    __shared__ float stile[NCH * kPatch * SW];    // the 5 rows of each channel under the segment
     const int nj = w - kPatch + 1;
     const int nseg = (nj + 63) / 64;
     const int i = blockIdx.x / nseg, j0 = (blockIdx.x - i * nseg) * 64;
@@ -152,20 +155,25 @@ __global__ __launch_bounds__(256) void k_query_features(const float* __restrict_
         smu[t] = m;
         mu[q0 + t] = m;
     }
-    __syncthreads();
     const int64_t plane = (int64_t)h * w;
-    // unrolled so that several gathers are in flight per thread
+    const int ncols = np + kPatch - 1;
+    // coalesced reads of the rows i .. i + 4 of every channel, columns j0 ..
+    for (int e = t; e < NCH * kPatch * SW; e += 256) {
+        const int ca = e / SW, c = e - ca * SW;
+        const int ch = ca / kPatch, a = ca - ch * kPatch;
+        if (c < ncols) stile[e] = (MODE == 0 ? lr : maps + ch * plane)[(int64_t)(i + a) * w + j0 + c];
+    }
+    __syncthreads();
 #pragma unroll 5
     for (int l = t; l < np * D; l += 256) {
         const int p = l / D, e = l - p * D;
-        const int j = j0 + p;
         float v;
         if (MODE == 0) {
             const int a = e / kPatch, b = e - a * kPatch;
-            v = (float)((double)lr[(int64_t)(i + a) * w + j + b] - smu[p]);
+            v = (float)((double)stile[a * SW + p + b] - smu[p]);
         } else {
             const int ch = e / 25, r = e - ch * 25, a = r / kPatch, b = r - a * kPatch;
-            v = maps[ch * plane + (int64_t)(i + a) * w + j + b];
+            v = stile[(ch * kPatch + a) * SW + p + b];
         }
         feat[q0 * D + l] = v;
     }
