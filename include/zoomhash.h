@@ -137,8 +137,12 @@ typedef struct {
                               cap <= 256 */
     int32_t rerank;        /* 0: exact ranking (fp32 distances certified against
                               the FP64 distance, exact K nearest by (d, ID));
-                              R in [K, 64]: rank all candidates on the bf16 high
-                              half of the features, re-rank the best R in fp32 */
+                              R in [K, 64]: at most R candidates get fp32
+                              distances; with cap > 0 those the screen's lower
+                              bounds (int8 coordinates in the dictionary's
+                              principal directions) do not rule out, smallest
+                              bounds first; with cap = 0 the best R by a distance
+                              on the bf16 high half of the features */
     int32_t proj;          /* projection on the matrix cores: 0 fp32, 1 split
                               bf16 (three bf16 products); both give exact codes */
     int32_t lle_fp64;      /* 1: Gram and solve in FP64; 0: fp32, FP64 only when
@@ -241,8 +245,8 @@ zh_status zh_tune_batch(zh_ctx* ctx, const zh_batch* batch, zh_batch_tuning* out
 zh_status zh_get_results(zh_ctx* ctx, int32_t* ids, float* d2, int32_t* m, float* w,
                          int32_t* ncand);
 /* Candidates of each patch of the last zh_query that reached the exact
- * distance pass (after the bf16 pre-filter; equal to the candidate count
- * when the pre-filter did not run) into survivors[Q] (device). Early-stop
+ * distance pass (after the screen's lower bounds; equal to the candidate
+ * count when the screen did not run) into survivors[Q] (device). Early-stop
  * search only (cap > 0); ZH_ESTATE otherwise. */
 zh_status zh_survivors(zh_ctx* ctx, int32_t* survivors);
 /* Query size of the last zh_query: *Q patches, *D feature dimension. */
