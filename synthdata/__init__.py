@@ -57,11 +57,11 @@ def fractal_voronoi_image(seed: int, h: int, w: int, amp: float = 0.2,
     return np.clip(img, 0.0, 1.0).astype(np.float32)
 
 
-def image_stack(seed0: int, count: int, h: int, w: int) -> np.ndarray:
+def image_stack(seed0: int, count: int, h: int, w: int, amp: float = 0.2) -> np.ndarray:
     """`count` images with seeds seed0, seed0+1, ...; float32 [count, h, w]."""
     out = np.empty((count, h, w), dtype=np.float32)
     for i in range(count):
-        out[i] = fractal_voronoi_image(seed0 + i, h, w)
+        out[i] = fractal_voronoi_image(seed0 + i, h, w, amp=amp)
     return out
 
 
@@ -118,6 +118,7 @@ class Workload:
     rerank: int = 0         # 0 = exact FP32 rank of every candidate; >0 = BF16 screen to this many
     feat_bf16: bool = False
     cap: int = 0            # 0 = union of all bins; >0 = early stop at this many matches
+    amp: float = 0.2        # noise amplitude of the images (0: piecewise constant)
 
     @property
     def D(self) -> int:
@@ -129,12 +130,12 @@ class Workload:
 
     def test_image(self) -> np.ndarray:
         if self.test_lr_direct:
-            return fractal_voronoi_image(self.seed_test, self.test_h, self.test_w)
+            return fractal_voronoi_image(self.seed_test, self.test_h, self.test_w, amp=self.amp)
         return fractal_voronoi_image(self.seed_test, self.scale * self.test_h,
-                                     self.scale * self.test_w)
+                                     self.scale * self.test_w, amp=self.amp)
 
     def dictionary_images(self) -> np.ndarray:
-        return image_stack(self.seed_dict_images, self.dict_images, self.dict_hr, self.dict_hr)
+        return image_stack(self.seed_dict_images, self.dict_images, self.dict_hr, self.dict_hr, amp=self.amp)
 
     def positions(self) -> np.ndarray:
         h_lr = self.dict_hr // self.scale

@@ -80,6 +80,11 @@ TINY = "tiny"
 # ragged, non-square test image and a small early-stop limit
 TINY_RAGGED = ("tiny", (("test_h", 50), ("test_w", 77)))
 MID = "mid"
+# piecewise-constant images (no noise): most gradient features are exactly
+# zero, so the early-stop search meets bins of thousands of IDs and ties of
+# distance 0 everywhere (the screen's bounds are all 0, every candidate is
+# kept and ranked by ID)
+FLAT = ("mid", (("amp", 0.0), ("test_h", 96), ("test_w", 96), ("n_dict", 60000), ("dict_images", 16)))
 
 
 def test_dictionary_bit_exact(gpu):
@@ -212,7 +217,7 @@ def _gpu_candidates(c, cap_per_query):
     return _np(counts), _np(ids)
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (MID, 0), (MID, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (MID, 0), (MID, 40), (FLAT, 40)])
 def test_candidate_sets_bit_exact(gpu, name, cap):
     c = case(name, cap=cap)
     maxc = max(len(x) for x in c.qr.cand)
@@ -225,7 +230,7 @@ def test_candidate_sets_bit_exact(gpu, name, cap):
         assert np.array_equal(ids[q, :len(ref)], ref), q
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (MID, 0), (MID, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (MID, 0), (MID, 40), (FLAT, 40)])
 def test_neighbours_weights_pixels(gpu, name, cap):
     torch = _torch()
     c = case(name, cap=cap)
