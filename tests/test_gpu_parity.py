@@ -251,6 +251,44 @@ def test_neighbours_weights_pixels(gpu, name, cap):
     assert np.abs(_np(hb).astype(np.float64) - c.hr_bp).max() < PIX_TOL
 
 
+@pytest.mark.parametrize("name,cap", [(TINY, 12), (MID, 40), (FLAT, 40)])
+def test_screened_form_neighbour_sets_and_pixels(gpu, name, cap):
+    """Screened form (int8 screen, at most R = 32 exact fp32 rows, fp32 LLE
+    with the FP64 redo): at most R survivors, the neighbour count of the
+    oracle, and a neighbour set that is a K-nearest set of the FP64
+    definition; where it differs from the oracle's, only by candidates tied
+    with the K-th distance within fp32 rounding (2 gamma_{D+3}). Pixels
+    within 1e-5."""
+    R = 32
+    c = case(name, cap=cap)
+    g, wl = c.g, c.wl
+    g.set_mode(cap=cap, rerank=R, proj=1, lle_fp64=0)
+    hr = g.zoom()
+    r = g.results()
+    assert (r["nsurv"] <= R).all()
+    assert np.array_equal(r["m"], c.qr.m)
+    feat = c.pre.dictionary.feat.astype(np.float64)
+    tie = 2.0 * (wl.D + 3) * 2.0 ** -24 * 1.01
+    s, ps = wl.scale, 5 * wl.scale
+    H, W = c.hr.shape
+    covered = np.zeros((H, W), dtype=bool)   # HR pixels under a patch whose set differs
+    nj = c.lr.shape[1] - 4
+    for q in np.nonzero(c.qr.m > 0)[0]:
+        mq = c.qr.m[q]
+        mine, ref = np.sort(r["ids"][q, :mq]), np.sort(c.qr.ids[q, :mq])
+        if np.array_equal(mine, ref):
+            continue
+        x = c.qr.feat[q].astype(np.float64)
+        dk = np.nanmax(c.qr.d2[q, :mq])
+        d_mine = ((feat[mine] - x) ** 2).sum(axis=1)
+        assert (d_mine <= dk * (1.0 + tie) + 1e-30).all(), q
+        i, j = divmod(int(q), nj)
+        covered[s * i:s * i + ps, s * j:s * j + ps] = True
+    g.set_mode(cap=cap)
+    err = np.abs(_np(hr).astype(np.float64) - c.hr)
+    assert err[~covered].max() < PIX_TOL
+
+
 def test_single_patch_image_and_k_edges(gpu):
     """Q = 1 (a 5x5 LR image), K = 1 and K = 16."""
     torch = _torch()
