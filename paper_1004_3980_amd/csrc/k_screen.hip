@@ -300,18 +300,27 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ feat, 
                     v[e] = (rowok && d < D) ? feat[row * D + d] : 0.0f;
                 }
             }
+            // high part: v rounded to bf16 (nearest even, the packed
+            // conversion); low part: the exact remainder rounded likewise
+            bf16x8 hv, lv;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const uint16_t h = bf16_rne(v[e]);
-                bh[s][e] = h;
-                bl[s][e] = bf16_rne(v[e] - bf16_to_f(h));
+                hv[e] = (__bf16)v[e];
+                lv[e] = (__bf16)(v[e] - (float)hv[e]);
             }
+            bh[s] = __builtin_bit_cast(u16x8, hv);
+            bl[s] = __builtin_bit_cast(u16x8, lv);
         }
+        u16x8 bab[NS];   // |high part|, for the bound product
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bab[s] = bh[s] & am;
         float b2 = 0.0f;
         float y[4][4];   // lane holds y_j, j = 16 tt + 4 kb + i, of feature row ri
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-            f32x4 cs = f32x4{0.f, 0.f, 0.f, 0.f}, chl = cs, clh = cs, cab = cs;
+            // the three split products share one fp32 accumulator: the bound
+            // covers any order of the 3 DP additions
+            f32x4 cs = f32x4{0.f, 0.f, 0.f, 0.f}, cab = cs;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const u16x8 ah = *reinterpret_cast<const u16x8*>(&sA[0][(tt * 16 + ri) * DS + 32 * s + 8 * kb]);
@@ -319,12 +328,11 @@ __global__ __launch_bounds__(256) void k_rotate(const float* __restrict__ feat, 
                 const bf16x8 ahb = __builtin_bit_cast(bf16x8, ah), alb = __builtin_bit_cast(bf16x8, al);
                 const bf16x8 vhb = __builtin_bit_cast(bf16x8, bh[s]), vlb = __builtin_bit_cast(bf16x8, bl[s]);
                 cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vhb, cs, 0, 0, 0);
-                chl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, chl, 0, 0, 0);
-                clh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, clh, 0, 0, 0);
                 cab = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah & am),
-                                                             __builtin_bit_cast(bf16x8, bh[s] & am), cab, 0, 0, 0);
+                                                             __builtin_bit_cast(bf16x8, bab[s]), cab, 0, 0, 0);
+                cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, cs, 0, 0, 0);
+                cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, cs, 0, 0, 0);
             }
-            cs = cs + (chl + clh);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float bnd = fmaf(c1, cab[i], 1e-30f);
