@@ -531,16 +531,42 @@ __global__ __launch_bounds__(kBlendSeg) void k_blend_rows(const float* __restric
     const int jhi = min(npj - 1, X / s);
     float acc = 0.0f;
     int cnt = 0;
-    for (int i = ilo; i <= ihi; ++i) {
+    // the next patch row's values are loaded into registers while the
+    // current one is summed (at most kStg staged values per thread)
+    constexpr int kStg = (1408 + kBlendSeg - 1) / kBlendSeg;
+    constexpr int kSm = (kBlendSeg + 8 + kBlendSeg - 1) / kBlendSeg;   // patch flags per thread
+    float pv[kStg];
+    int pm[kSm];
+    auto fetch = [&](int i) {
         const int u = Y - s * i;
         const int64_t qrow = (int64_t)i * npj + jb0;
-        __syncthreads();
-        for (int e = threadIdx.x; e < njb; e += kBlendSeg) sm[e] = m[qrow + e] > 0;
-        for (int e = threadIdx.x; e < njb * ps; e += kBlendSeg) {
+#pragma unroll
+        for (int r = 0; r < kSm; ++r) {
+            const int e = (int)threadIdx.x + r * kBlendSeg;
+            pm[r] = e < njb ? m[qrow + e] > 0 : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kStg; ++r) {
+            const int e = (int)threadIdx.x + r * kBlendSeg;
             const int jj = e / ps, v = e - jj * ps;
-            sv[e] = xhat[(qrow + jj) * ps2 + u * ps + v];
+            pv[r] = e < njb * ps ? xhat[(qrow + jj) * ps2 + u * ps + v] : 0.0f;
+        }
+    };
+    if (ilo <= ihi) fetch(ilo);
+    for (int i = ilo; i <= ihi; ++i) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSm; ++r) {
+            const int e = (int)threadIdx.x + r * kBlendSeg;
+            if (e < njb) sm[e] = pm[r];
+        }
+#pragma unroll
+        for (int r = 0; r < kStg; ++r) {
+            const int e = (int)threadIdx.x + r * kBlendSeg;
+            if (e < njb * ps) sv[e] = pv[r];
         }
         __syncthreads();
+        if (i < ihi) fetch(i + 1);
         if (X < W) {
             for (int j = jlo; j <= jhi; ++j) {
                 if (sm[j - jb0]) {
