@@ -164,18 +164,28 @@ __global__ __launch_bounds__(256) void k_query_features(const float* __restrict_
         if (c < ncols) stile[e] = (MODE == 0 ? lr : maps + ch * plane)[(int64_t)(i + a) * w + j0 + c];
     }
     __syncthreads();
+    if (MODE == 0) {
 #pragma unroll 5
-    for (int l = t; l < np * D; l += 256) {
-        const int p = l / D, e = l - p * D;
-        float v;
-        if (MODE == 0) {
+        for (int l = t; l < np * D; l += 256) {
+            const int p = l / D, e = l - p * D;
             const int a = e / kPatch, b = e - a * kPatch;
-            v = (float)((double)stile[a * SW + p + b] - smu[p]);
-        } else {
-            const int ch = e / 25, r = e - ch * 25, a = r / kPatch, b = r - a * kPatch;
-            v = stile[(ch * kPatch + a) * SW + p + b];
+            feat[q0 * D + l] = (float)((double)stile[a * SW + p + b] - smu[p]);
         }
-        feat[q0 * D + l] = v;
+    } else {
+        // 16-byte stores: D = 100 keeps a group of four inside one patch row
+        float4* f4 = reinterpret_cast<float4*>(feat + q0 * D);
+#pragma unroll 2
+        for (int l4 = t; l4 < np * (D / 4); l4 += 256) {
+            const int p = l4 / (D / 4), e0 = 4 * (l4 - p * (D / 4));
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u;
+                const int ch = e / 25, r = e - ch * 25, a = r / kPatch, b = r - a * kPatch;
+                v[u] = stile[(ch * kPatch + a) * SW + p + b];
+            }
+            f4[l4] = make_float4(v[0], v[1], v[2], v[3]);
+        }
     }
 }
 
