@@ -111,43 +111,22 @@ __device__ __forceinline__ double patch_mean(const float* __restrict__ I, int w,
     return s / (double)(kPatch * kPatch);
 }
 
-// One thread per (patch, feature element); the element 0 thread also writes
-// the patch mean.
-// element e of the features of patch q (and its mean when e == 0)
-__device__ __forceinline__ void feature_at(const float* __restrict__ lr, const float* __restrict__ maps, int h,
-                                           int w, int mode, int q, int e, float* __restrict__ f,
-                                           double* __restrict__ mu) {
-    const int nj = w - kPatch + 1;
-    const int i = q / nj, j = q % nj;
-    if (mode == 0) {
-        const double m = patch_mean(lr, w, i, j);
-        const int a = e / kPatch, b = e % kPatch;
-        *f = (float)((double)lr[(int64_t)(i + a) * w + j + b] - m);
-        if (e == 0) *mu = m;
-    } else {
-        const int ch = e / 25, a = (e % 25) / kPatch, b = e % kPatch;
-        *f = maps[(int64_t)ch * h * w + (int64_t)(i + a) * w + j + b];
-        if (e == 0) *mu = patch_mean(lr, w, i, j);
-    }
-}
-
 // One workgroup per segment of up to 64 consecutive patches of one patch row:
-// the first threads form the segment's patch means, then the threads write
-// the segment's features in memory order (coalesced), with the same
-// arithmetic as feature_at.
+// the first threads form the segment's patch means (patch_mean), the rows
+// under the segment are staged in LDS, then the threads write the
+// segment's features in memory order (coalesced): the map values (gradient
+// mode) or the pixels minus the FP64 mean, rounded to fp32.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_query_features(const float* __restrict__ lr, const float* __restrict__ maps,
-                                                        int h, int w, float* __restrict__ feat,
-                                                        double* __restrict__ mu) {
+__device__ __forceinline__ void query_features_seg(const float* __restrict__ lr, const float* __restrict__ maps,
+                                                   int h, int w, int i, int j0, float* __restrict__ feat,
+                                                   double* __restrict__ mu) {
     constexpr int D = MODE == 0 ? 25 : 100;
     constexpr int NCH = MODE == 0 ? 1 : 4;        // image, or the four gradient maps
-    constexpr int SW = 64 + kPatch - 1;           // columns under 64 patches
-    __shared__ double smu[64];
+    constexpr int SW = kFeatSeg + kPatch - 1;     // columns under a segment of patches
+    __shared__ double smu[kFeatSeg];
     __shared__ float stile[NCH * kPatch * SW];    // the 5 rows of each channel under the segment
     const int nj = w - kPatch + 1;
-    const int nseg = (nj + 63) / 64;
-    const int i = blockIdx.x / nseg, j0 = (blockIdx.x - i * nseg) * 64;
-    const int np = nj - j0 < 64 ? nj - j0 : 64;
+    const int np = nj - j0 < kFeatSeg ? nj - j0 : kFeatSeg;
     const int64_t q0 = (int64_t)i * nj + j0;
     const int t = threadIdx.x;
     if (t < np) {
@@ -189,19 +168,27 @@ __global__ __launch_bounds__(256) void k_query_features(const float* __restrict_
     }
 }
 
-// Batched: every (patch, element) of every image, patches in image order.
-__global__ void k_b_query_features(const BatchImage* __restrict__ im, int n, int64_t q_total, int mode,
-                                   const float* __restrict__ maps, float* __restrict__ feat,
-                                   double* __restrict__ mu) {
-    const int D = mode == 0 ? 25 : 100;
-    const int64_t total = q_total * D;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = idx / D;
-        const int e = (int)(idx - p * D);
-        const BatchImage& b = im[batch_image_of<&BatchImage::q_off>(im, n, p)];
-        feature_at(b.lr, maps + 4 * b.lr_off, b.h, b.w, mode, (int)(p - b.q_off), e, feat + idx, mu + p);
-    }
+template <int MODE>
+__global__ __launch_bounds__(256) void k_query_features(const float* __restrict__ lr, const float* __restrict__ maps,
+                                                        int h, int w, float* __restrict__ feat,
+                                                        double* __restrict__ mu) {
+    const int nseg = (w - kPatch + 1 + kFeatSeg - 1) / kFeatSeg;
+    const int i = blockIdx.x / nseg, j0 = (blockIdx.x - i * nseg) * kFeatSeg;
+    query_features_seg<MODE>(lr, maps, h, w, i, j0, feat, mu);
+}
+
+// Batched: one workgroup per segment of every image (the image from the
+// table's segment offsets), the single-image code on the image's arrays.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_b_query_features(const BatchImage* __restrict__ im, int n,
+                                                          const float* __restrict__ maps, float* __restrict__ feat,
+                                                          double* __restrict__ mu) {
+    constexpr int D = MODE == 0 ? 25 : 100;
+    const BatchImage& b = im[batch_image_of<&BatchImage::fblk_off>(im, n, blockIdx.x)];
+    const int64_t lb = blockIdx.x - b.fblk_off;
+    const int nseg = (b.w - kPatch + 1 + kFeatSeg - 1) / kFeatSeg;
+    const int i = (int)(lb / nseg), j0 = (int)(lb - (int64_t)i * nseg) * kFeatSeg;
+    query_features_seg<MODE>(b.lr, maps + 4 * b.lr_off, b.h, b.w, i, j0, feat + b.q_off * D, mu + b.q_off);
 }
 
 // Training pairs at positions (image, i, j): features, and the HR patch
@@ -300,7 +287,7 @@ hipError_t launch_query_features(const float* lr, const float* maps, int h, int 
                                  float* feat, double* mu, hipStream_t st) {
     const int ni = h - kPatch + 1, nj = w - kPatch + 1;
     if (ni < 1 || nj < 1) return hipSuccess;
-    const int64_t blocks = (int64_t)ni * ((nj + 63) / 64);
+    const int64_t blocks = feature_segments(h, w);
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks);
     if (mode == 0)
@@ -316,12 +303,14 @@ hipError_t launch_b_gradient_maps(const BatchImage* im, int n, int64_t lr_total,
     return hipGetLastError();
 }
 
-hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t q_total, int mode, const float* maps,
+hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t seg_total, int mode, const float* maps,
                                    float* feat, double* mu, hipStream_t st) {
-    const int64_t total = q_total * (mode == 0 ? 25 : 100);
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_b_query_features, dim3(grid_for(total, 256)), dim3(256), 0, st, im, n, q_total, mode, maps,
-                       feat, mu);
+    if (seg_total == 0) return hipSuccess;
+    if (seg_total > 0x7FFFFFFF) return hipErrorInvalidValue;
+    if (mode == 0)
+        hipLaunchKernelGGL(k_b_query_features<0>, dim3((unsigned)seg_total), dim3(256), 0, st, im, n, maps, feat, mu);
+    else
+        hipLaunchKernelGGL(k_b_query_features<1>, dim3((unsigned)seg_total), dim3(256), 0, st, im, n, maps, feat, mu);
     return hipGetLastError();
 }
 

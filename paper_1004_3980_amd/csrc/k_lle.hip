@@ -476,49 +476,23 @@ __global__ __launch_bounds__(256) void k_synth4(int Q, int K, int ps2, const int
     }
 }
 
-// Per HR pixel: mean of the synthesised patches covering it (patches in
-// row-major order); bicubic of the LR image where no patch covers it.
-__device__ __forceinline__ float blend_at(const float* __restrict__ xhat, const int32_t* __restrict__ m,
-                                         const float* __restrict__ lr, int h, int w, int s, int Y, int X) {
-    const int ps = kPatch * s, ps2 = ps * ps;
-    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
-    const int ilo = Y - ps + 1 <= 0 ? 0 : (Y - ps + s) / s;
-    const int ihi = min(npi - 1, Y / s);
-    const int jlo = X - ps + 1 <= 0 ? 0 : (X - ps + s) / s;
-    const int jhi = min(npj - 1, X / s);
-    float acc = 0.0f;
-    int cnt = 0;
-    for (int i = ilo; i <= ihi; ++i)
-        for (int j = jlo; j <= jhi; ++j) {
-            const int q = i * npj + j;
-            if (m[q] > 0) {
-                acc += xhat[(int64_t)q * ps2 + (Y - s * i) * ps + (X - s * j)];
-                ++cnt;
-            }
-        }
-    return cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
-}
-
-// One workgroup per segment of 256 HR pixels of one HR row Y. For each patch
-// row i covering Y (ascending), the row Y - s i of every patch the segment
-// touches is staged in LDS with coalesced loads (ps consecutive floats per
-// patch), then each pixel adds the staged values of its patches in ascending
-// column order: the order and arithmetic of blend_at.
-// The zoom factor is a template parameter: every division by s or 5 s is
-// by a constant.
-constexpr int kBlendSeg = 256;
+// Per HR pixel: the mean of the synthesised patches covering it (patches in
+// row-major order, each added in fp32), or the bicubic of the LR image where
+// no patch covers it. One workgroup per segment of 256 HR pixels of one HR
+// row Y: for each patch row i covering Y (ascending), the row Y - s i of every
+// patch the segment touches is staged in LDS with coalesced loads (ps
+// consecutive floats per patch), then each pixel adds the staged values of
+// its patches in ascending column order. The zoom factor is a template
+// parameter: every division by s or 5 s is by a constant.
 template <int s>
-__global__ __launch_bounds__(kBlendSeg) void k_blend_rows(const float* __restrict__ xhat, const int32_t* __restrict__ m,
-                                                          const float* __restrict__ lr, int h, int w,
-                                                          float* __restrict__ hr) {
+__device__ __forceinline__ void blend_seg(const float* __restrict__ xhat, const int32_t* __restrict__ m,
+                                          const float* __restrict__ lr, int h, int w, int Y, int X0,
+                                          float* __restrict__ hr) {
     __shared__ float sv[1408];   // staged patch rows: at most 1350 floats (s = 3)
     __shared__ int sm[kBlendSeg + 8];
     constexpr int ps = kPatch * s, ps2 = ps * ps;
     const int W = s * w;
     const int npi = h - kPatch + 1, npj = w - kPatch + 1;
-    const int nseg = (W + kBlendSeg - 1) / kBlendSeg;
-    const int Y = blockIdx.x / nseg;
-    const int X0 = (blockIdx.x - Y * nseg) * kBlendSeg;
     const int X = X0 + threadIdx.x;
     const int X1 = min(W, X0 + kBlendSeg) - 1;
     // patch columns of the segment
@@ -579,16 +553,27 @@ __global__ __launch_bounds__(kBlendSeg) void k_blend_rows(const float* __restric
     if (X < W) hr[(int64_t)Y * W + X] = cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
 }
 
-// Batched: every HR pixel of every image, into the image's output.
-__global__ void k_b_blend(const BatchImage* __restrict__ im, int n, int64_t total, int s,
-                          const float* __restrict__ xhat, const int32_t* __restrict__ m) {
-    const int ps2 = (kPatch * s) * (kPatch * s);
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const BatchImage& b = im[batch_image_of<&BatchImage::hr_off>(im, n, idx)];
-        const int r = (int)(idx - b.hr_off), W = s * b.w;
-        b.out[r] = blend_at(xhat + b.q_off * ps2, m + b.q_off, b.lr, b.h, b.w, s, r / W, r % W);
-    }
+template <int s>
+__global__ __launch_bounds__(kBlendSeg) void k_blend_rows(const float* __restrict__ xhat, const int32_t* __restrict__ m,
+                                                          const float* __restrict__ lr, int h, int w,
+                                                          float* __restrict__ hr) {
+    const int nseg = (s * w + kBlendSeg - 1) / kBlendSeg;
+    const int Y = blockIdx.x / nseg;
+    blend_seg<s>(xhat, m, lr, h, w, Y, (blockIdx.x - Y * nseg) * kBlendSeg, hr);
+}
+
+// Batched: one workgroup per segment of every image (the image from the
+// table's segment offsets), the single-image code on the image's patches.
+template <int s>
+__global__ __launch_bounds__(kBlendSeg) void k_b_blend(const BatchImage* __restrict__ im, int n,
+                                                       const float* __restrict__ xhat, const int32_t* __restrict__ m) {
+    constexpr int ps2 = (kPatch * s) * (kPatch * s);
+    const BatchImage& b = im[batch_image_of<&BatchImage::bblk_off>(im, n, blockIdx.x)];
+    const int64_t lb = blockIdx.x - b.bblk_off;
+    const int nseg = (s * b.w + kBlendSeg - 1) / kBlendSeg;
+    const int Y = (int)(lb / nseg);
+    blend_seg<s>(xhat + b.q_off * ps2, m + b.q_off, b.lr, b.h, b.w, Y, (int)(lb - (int64_t)Y * nseg) * kBlendSeg,
+                 b.out);
 }
 
 hipError_t lle_init() {
@@ -655,12 +640,14 @@ hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, in
     return hipGetLastError();
 }
 
-hipError_t launch_b_blend(const BatchImage* im, int n, int64_t hr_total, int scale, const float* xhat,
+hipError_t launch_b_blend(const BatchImage* im, int n, int64_t seg_total, int scale, const float* xhat,
                           const int32_t* m, hipStream_t st) {
-    if (hr_total == 0) return hipSuccess;
-    int64_t g = (hr_total + 255) / 256;
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_b_blend, dim3((unsigned)g), dim3(256), 0, st, im, n, hr_total, scale, xhat, m);
+    if (seg_total == 0) return hipSuccess;
+    if (seg_total > 0x7FFFFFFF || scale < 1 || scale > 3) return hipErrorInvalidValue;
+    const dim3 g((unsigned)seg_total);
+    if (scale == 1) hipLaunchKernelGGL(k_b_blend<1>, g, dim3(kBlendSeg), 0, st, im, n, xhat, m);
+    else if (scale == 2) hipLaunchKernelGGL(k_b_blend<2>, g, dim3(kBlendSeg), 0, st, im, n, xhat, m);
+    else hipLaunchKernelGGL(k_b_blend<3>, g, dim3(kBlendSeg), 0, st, im, n, xhat, m);
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct zh_ctx {
     struct BatchGroup {
         int n = 0;
         int64_t q_total = 0, lr_total = 0, hr_total = 0, tiles = 0;
+        int64_t fsegs = 0, bsegs = 0;   // feature and blend segments of all images
         Buf table;                // device BatchImage[n]
     };
     struct Batch {
@@ -1066,7 +1067,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     std::vector<BatchImage> tabs[4];
     for (int s = 1; s <= 3; ++s) {
         auto& g = B.g[s];
-        int64_t q = 0, lr = 0, hr = 0, tiles = 0;
+        int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, bsegs = 0;
         for (int i = 0; i < b->n_images; ++i) {
             if (b->scale[i] != s) continue;
             BatchImage im{};
@@ -1078,17 +1079,23 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
             im.q_off = q;
             im.hr_off = hr;
             im.tile_off = tiles;
+            im.fblk_off = fsegs;
+            im.bblk_off = bsegs;
             tabs[s].push_back(im);
             lr += (int64_t)im.h * im.w;
             q += (int64_t)(im.h - 4) * (im.w - 4);
             hr += (int64_t)s * im.h * s * im.w;
             tiles += bp_tiles(s * im.h, s * im.w, B.tile);
+            fsegs += feature_segments(im.h, im.w);
+            bsegs += blend_segments(s, im.h, im.w);
         }
         g.n = (int)tabs[s].size();
         g.q_total = q;
         g.lr_total = lr;
         g.hr_total = hr;
         g.tiles = tiles;
+        g.fsegs = fsegs;
+        g.bsegs = bsegs;
         if (!g.n) continue;
         if (q * kMaxK >= (1ll << 31)) return fail(c, ZH_EINVAL, "zh_run_batch: too many patches at scale %d", s);
         const Dict& d = c->dicts[s];
@@ -1158,7 +1165,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             c->qscale = s;
             TRY(clear_counters(c));
             if (d.mode == ZH_FEAT_GRAD4) HIPCHK(c, launch_b_gradient_maps(tab, g.n, g.lr_total, P<float>(c->maps), st));
-            HIPCHK(c, launch_b_query_features(tab, g.n, g.q_total, d.mode, P<float>(c->maps), P<float>(c->qfeat),
+            HIPCHK(c, launch_b_query_features(tab, g.n, g.fsegs, d.mode, P<float>(c->maps), P<float>(c->qfeat),
                                               P<double>(c->qmu), st));
             HashArgs ha{};
             ha.feat = P<float>(c->qfeat);
@@ -1206,7 +1213,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             }
             HIPCHK(c, launch_synth((int)g.q_total, K, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
                                    P<double>(c->qmu), d.resid, P<float>(c->xhat), st));
-            HIPCHK(c, launch_b_blend(tab, g.n, g.hr_total, s, P<float>(c->xhat), P<int32_t>(c->m), st));
+            HIPCHK(c, launch_b_blend(tab, g.n, g.bsegs, s, P<float>(c->xhat), P<int32_t>(c->m), st));
             const Taps tg = gauss_taps(1.0);
             for (int t = 0; t < b->bp_iters; ++t) {
                 HIPCHK(c, launch_b_degrade_residual(tab, g.n, g.lr_total, s, tg, t & 1, P<float>(B.e), st));

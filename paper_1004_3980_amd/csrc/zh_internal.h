@@ -206,7 +206,18 @@ struct BatchImage {
     float* scr;              // [s h, s w] back-projection scratch
     int h, w;
     int64_t lr_off, q_off, hr_off, tile_off;
+    int64_t fblk_off, bblk_off;   // first workgroup of the image's feature and blend segments
 };
+// feature segments (64 patches of a patch row) and blend segments
+// (kBlendSeg HR pixels of a row) of an h x w LR image at zoom s
+constexpr int kFeatSeg = 64;
+constexpr int kBlendSeg = 256;
+__host__ __device__ inline int64_t feature_segments(int h, int w) {
+    return h >= kPatch && w >= kPatch ? (int64_t)(h - kPatch + 1) * ((w - kPatch + 1 + kFeatSeg - 1) / kFeatSeg) : 0;
+}
+__host__ __device__ inline int64_t blend_segments(int s, int h, int w) {
+    return (int64_t)s * h * ((s * w + kBlendSeg - 1) / kBlendSeg);
+}
 // image of a concatenated index: the last entry whose offset field is <= i
 template <int64_t BatchImage::*F>
 __device__ __forceinline__ int batch_image_of(const BatchImage* im, int n, int64_t i) {
@@ -218,11 +229,13 @@ __device__ __forceinline__ int batch_image_of(const BatchImage* im, int n, int64
     return lo;
 }
 hipError_t launch_b_gradient_maps(const BatchImage* im, int n, int64_t lr_total, float* maps, hipStream_t st);
-hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t q_total, int mode, const float* maps,
+// one workgroup per feature segment (64 patches of a patch row) of every image
+hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t seg_total, int mode, const float* maps,
                                    float* feat, double* mu, hipStream_t st);
 hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int scale, const Taps& t,
                                      int parity, float* e, hipStream_t st);
-hipError_t launch_b_blend(const BatchImage* im, int n, int64_t hr_total, int scale, const float* xhat,
+// one workgroup per blend segment (256 HR pixels of a row) of every image
+hipError_t launch_b_blend(const BatchImage* im, int n, int64_t seg_total, int scale, const float* xhat,
                           const int32_t* m, hipStream_t st);
 // one back-projection update over all tiles of the batch, persistent: `grid`
 // workgroups take tiles from the counter (zeroed here by a fill kernel);
