@@ -41,7 +41,7 @@ struct Dict {
     Buf dfilt;                    // [L, dir_filter_words(cap)] presence bits of the keys
     Buf tids;                     // [L, n] uint32
     Buf kmul;                     // [L, k] multipliers of the bucket-key sum
-    Buf sc;                       // [n, screen_stride(D)] screen plane
+    Buf sc;                       // [n, kScreenBytes] screen plane
     Buf xf;                       // [n, D] fp32 copy of the features (exact passes of the search)
     Buf phi_hi, phi_lo;           // [64, round32(D)] bf16 split of the principal directions
     float inv_s2 = 0.f;           // lower bound of 1 / sigma_max(Phi)^2
