@@ -118,27 +118,39 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ ke
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of `count` values in place by one workgroup of 1024 threads
+// exclusive scan of `count` values in place by one workgroup of 1024 threads:
+// chunks of 4096 values, four consecutive values per thread, wave scans of
+// the thread sums and a scan of the 16 wave sums, a running carry between
+// chunks
 __global__ __launch_bounds__(1024) void k_scan_1wg(uint32_t* __restrict__ v, int64_t count) {
-    __shared__ uint32_t part[1024];
-    const int64_t per = (count + 1023) / 1024;
-    const int64_t b = threadIdx.x * per;
-    const int64_t e = b + per < count ? b + per : count;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += v[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t wtot;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < count; base += 4096) {
+        const int64_t i0 = base + 4 * (int64_t)t;
+        uint32_t x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = i0 + j < count ? v[i0 + j] : 0u;
+        const uint32_t loc = x[0] + x[1] + x[2] + x[3];
+        const uint32_t incl = (uint32_t)wave_incl_scan((int)loc);
+        if (lane == 63) wsum[wv] = incl;
         __syncthreads();
-        part[threadIdx.x] += t;
+        if (wv == 0) {
+            const uint32_t ws = lane < 16 ? wsum[lane] : 0u;
+            const uint32_t wi = (uint32_t)wave_incl_scan((int)ws);
+            if (lane < 16) wsum[lane] = wi - ws;
+            if (lane == 15) wtot = wi;
+        }
         __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - s;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t x = v[i];
-        v[i] = run;
-        run += x;
+        uint32_t run = carry + wsum[wv] + incl - loc;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < count) v[i0 + j] = run;
+            run += x[j];
+        }
+        carry += wtot;
+        __syncthreads();
     }
 }
 
