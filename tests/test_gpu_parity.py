@@ -289,6 +289,37 @@ def test_screened_form_neighbour_sets_and_pixels(gpu, name, cap):
     assert err[~covered].max() < PIX_TOL
 
 
+@pytest.mark.parametrize("rerank", [0, 32])
+def test_early_stop_with_k_above_eight(gpu, rerank):
+    """K = 12 with the early stop (the search's exact passes without the
+    fused Gram, the LLE forming it): exact form bit-exact neighbours, the
+    screened form a K-nearest set of the FP64 definition; pixels within 1e-5."""
+    K, cap = 12, 40
+    c = case(MID, cap=cap)
+    g, wl = c.g, c.wl
+    qr = pipeline.query(c.pre, c.lr, K, wl.lam, cap=cap)
+    hr_ref, _ = pipeline.reconstruct(qr, c.lr, wl.scale)
+    g.set_mode(cap=cap, rerank=rerank, proj=1, lle_fp64=1)
+    hr = g.zoom(K=K)
+    r = g.results(K=K)
+    assert np.array_equal(r["m"], qr.m)
+    if rerank == 0:
+        assert np.array_equal(r["ids"], np.where(qr.ids >= 0, qr.ids, -1).astype(np.int32))
+        assert np.abs(_np(hr).astype(np.float64) - hr_ref).max() < PIX_TOL
+    else:
+        assert (r["nsurv"] <= rerank).all()
+        feat = c.pre.dictionary.feat.astype(np.float64)
+        tie = 2.0 * (wl.D + 3) * 2.0 ** -24 * 1.01
+        for q in np.nonzero(qr.m > 0)[0]:
+            mq = qr.m[q]
+            mine = np.sort(r["ids"][q, :mq])
+            if np.array_equal(mine, np.sort(qr.ids[q, :mq])):
+                continue
+            d_mine = ((feat[mine] - qr.feat[q].astype(np.float64)) ** 2).sum(axis=1)
+            assert (d_mine <= np.nanmax(qr.d2[q, :mq]) * (1.0 + tie) + 1e-30).all(), q
+    g.set_mode(cap=cap)
+
+
 def test_single_patch_image_and_k_edges(gpu):
     """Q = 1 (a 5x5 LR image), K = 1 and K = 16."""
     torch = _torch()
