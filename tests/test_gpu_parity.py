@@ -84,6 +84,8 @@ MID = "mid"
 # zero, so the early-stop search meets bins of thousands of IDs and ties of
 # distance 0 everywhere (the screen's bounds are all 0, every candidate is
 # kept and ranked by ID)
+# zoom x3 (15 x 15 HR patches; the blend, synthesis and search at s = 3)
+TINY3 = ("tiny", (("scale", 3), ("n_dict", 10000)))
 FLAT = ("mid", (("amp", 0.0), ("test_h", 96), ("test_w", 96), ("n_dict", 60000), ("dict_images", 16)))
 
 
@@ -217,7 +219,7 @@ def _gpu_candidates(c, cap_per_query):
     return _np(counts), _np(ids)
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (MID, 0), (MID, 40), (FLAT, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (TINY3, 12), (MID, 0), (MID, 40), (FLAT, 40)])
 def test_candidate_sets_bit_exact(gpu, name, cap):
     c = case(name, cap=cap)
     maxc = max(len(x) for x in c.qr.cand)
@@ -230,7 +232,7 @@ def test_candidate_sets_bit_exact(gpu, name, cap):
         assert np.array_equal(ids[q, :len(ref)], ref), q
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (MID, 0), (MID, 40), (FLAT, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (TINY3, 12), (MID, 0), (MID, 40), (FLAT, 40)])
 def test_neighbours_weights_pixels(gpu, name, cap):
     torch = _torch()
     c = case(name, cap=cap)
@@ -251,7 +253,7 @@ def test_neighbours_weights_pixels(gpu, name, cap):
     assert np.abs(_np(hb).astype(np.float64) - c.hr_bp).max() < PIX_TOL
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 12), (MID, 40), (FLAT, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 12), (TINY3, 12), (MID, 40), (FLAT, 40)])
 def test_screened_form_neighbour_sets_and_pixels(gpu, name, cap):
     """Screened form (int8 screen, at most R = 32 exact fp32 rows, fp32 LLE
     with the FP64 redo): at most R survivors, the neighbour count of the
