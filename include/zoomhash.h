@@ -99,7 +99,7 @@ zh_status zh_features(zh_ctx* ctx, const float* lr, int h, int w, int feat_mode,
 typedef struct {
     int64_t n;             /* pairs, 1 <= n < 2^31 */
     int32_t dim;           /* D: 25 or 100 */
-    int32_t scale;         /* 2 or 3: HR patch side 5*scale */
+    int32_t scale;         /* zoom factor 1 .. 4: HR patch side 5*scale */
     int32_t feat_mode;     /* ZH_FEAT_* that produced `feat` */
     const float* feat;     /* [n, D] fp32; copied at build into the library's own
                               split storage (bf16 high half + low 16 bits) */

@@ -31,6 +31,9 @@
 
 namespace zh {
 
+// HR patch values per lane, in chunks of 64, at the largest zoom factor
+constexpr int kPixChunks = (kMaxPs2 + 63) / 64;
+
 // ---- one-axis transposed operators ------------------------------------------
 // Along x (AXIS 0) the array is [rows][n] and the pass maps rows of n_in to
 // rows of n_out; along y (AXIS 1) it is [n][cols], cols = a.rows.
@@ -178,6 +181,7 @@ hipError_t launch_blend_adj(const float* g, const int32_t* m, int h, int w, int 
 // Z = q - X_N in FP64 (coordinates over the lanes, wave sums), then on lane
 // 0: A = G + lambda tau I, Cholesky, w~ = A^-1 1, d = -tau A^-1 w~,
 // contribution [g_w . d - (g_w . w)(1 . d)] / (1 . w~).
+template <int U>
 __global__ __launch_bounds__(256) void k_lle_lambda_adj(BackwardArgs a) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -192,9 +196,9 @@ __global__ __launch_bounds__(256) void k_lle_lambda_adj(BackwardArgs a) {
         }
         const int pi = q / npj, pj = q % npj;
         // patch gradient values of this lane: pixels lane + 64 u
-        float gq[4];
+        float gq[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int P = lane + 64 * u;
             gq[u] = 0.0f;
             if (P < ps2) {
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(256) void k_lle_lambda_adj(BackwardArgs a) {
             if (mi < mq) {
                 const float* r = a.resid + (int64_t)a.ids[(int64_t)q * K + mi] * ps2;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < U; ++u) {
                     const int P = lane + 64 * u;
                     if (P < ps2) acc += (double)gq[u] * (double)r[P];
                 }
@@ -280,6 +284,7 @@ __global__ __launch_bounds__(256) void k_lle_lambda_adj(BackwardArgs a) {
 
 // dL/dw_m = <g_q, r_{n_m}> for K <= 8, one wave per patch (pixels lane + 64 u),
 // into gw[q][8] (FP64, zero past m_q).
+template <int U>
 __global__ __launch_bounds__(256) void k_lam_gw(BackwardArgs a, double* __restrict__ gw) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -289,10 +294,10 @@ __global__ __launch_bounds__(256) void k_lam_gw(BackwardArgs a, double* __restri
     for (int q = blockIdx.x * wpb + (threadIdx.x >> 6); q < a.Q; q += gridDim.x * wpb) {
         const int mq = a.m[q];
         const int pi = q / npj, pj = q - (q / npj) * npj;
-        float gq[4];
-        int P4[4];
+        float gq[U];
+        int P4[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int P = lane + 64 * u;
             P4[u] = P;
             gq[u] = 0.0f;
@@ -307,7 +312,7 @@ __global__ __launch_bounds__(256) void k_lam_gw(BackwardArgs a, double* __restri
             if (mi < mq) {
                 const float* r = a.resid + (int64_t)a.ids[(int64_t)q * K + mi] * ps2;
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < U; ++u)
                     if (P4[u] < ps2) acc += (double)gq[u] * (double)r[P4[u]];
             }
             acc = wave_sum_f64(acc);
@@ -401,19 +406,22 @@ __global__ __launch_bounds__(256) void k_lam_solve(BackwardArgs a, const double*
 
 hipError_t launch_lam_adj8(const BackwardArgs& a, const double* gram, double* gw, hipStream_t st) {
     if (a.Q == 0) return hipSuccess;
-    if (a.K > 8) return hipErrorInvalidValue;
+    if (a.K > 8 || a.s < 1 || a.s > kMaxScale) return hipErrorInvalidValue;
     int g = (a.Q + 3) / 4;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_lam_gw, dim3(g), dim3(256), 0, st, a, gw);
+    if (kPatch * a.s * kPatch * a.s <= 256) hipLaunchKernelGGL(k_lam_gw<4>, dim3(g), dim3(256), 0, st, a, gw);
+    else hipLaunchKernelGGL(k_lam_gw<kPixChunks>, dim3(g), dim3(256), 0, st, a, gw);
     hipLaunchKernelGGL(k_lam_solve, dim3((a.Q + 255) / 256), dim3(256), 0, st, a, gram, gw);
     return hipGetLastError();
 }
 
 hipError_t launch_lle_lambda_adj(const BackwardArgs& a, hipStream_t st) {
-    if (a.K > kMaxK || a.D > 128 || kPatch * a.s * kPatch * a.s > 256) return hipErrorInvalidValue;
+    if (a.K > kMaxK || a.D > 128 || a.s < 1 || a.s > kMaxScale) return hipErrorInvalidValue;
     int g = (a.Q + 3) / 4;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_lle_lambda_adj, dim3(g < 1 ? 1 : g), dim3(256), 0, st, a);
+    if (g < 1) g = 1;
+    if (kPatch * a.s * kPatch * a.s <= 256) hipLaunchKernelGGL(k_lle_lambda_adj<4>, dim3(g), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_lle_lambda_adj<kPixChunks>, dim3(g), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -473,6 +481,7 @@ struct DictGradChunk {
     uint8_t last_start;  // the last run starts in this chunk
 };
 
+template <int U>
 __global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ key, const uint32_t* __restrict__ val,
                                                    int64_t n_ent, uint32_t none, const float* __restrict__ wts,
                                                    const float* __restrict__ gp, int w, int s, int K,
@@ -482,9 +491,9 @@ __global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ 
     const int wpb = blockDim.x >> 6;
     const int ps = kPatch * s, ps2 = ps * ps;
     const int npj = w - kPatch + 1, W = s * w;
-    int off[4];
+    int off[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
         const int P = lane + 64 * u;
         off[u] = P < ps2 ? (P / ps) * W + P % ps : 0;
     }
@@ -507,7 +516,9 @@ __global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ 
             todo &= todo - 1;
             const int stop = __builtin_ctzll(ends & (~0ull << src));   // last entry of the segment
             const uint32_t kk = __shfl(k, src);
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
+            float acc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[u] = 0.0f;
             for (int j = src; j <= stop; ++j) {
                 const uint32_t vv = __shfl(v, j);
                 const float ww = __shfl(wv, j);
@@ -515,7 +526,7 @@ __global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ 
                 const int pi = q / npj, pj = q - pi * npj;
                 const float* g = gp + (int64_t)s * pi * W + (int64_t)s * pj;
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < U; ++u)
                     if (lane + 64 * u < ps2) acc[u] = fmaf(ww, g[off[u]], acc[u]);
             }
             const bool from_prev = src == 0 && __shfl(kprev, 0) == kk;
@@ -524,7 +535,7 @@ __global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ 
             if (from_prev) dst = part + (c * 2) * ps2;
             else if (into_next) dst = part + (c * 2 + 1) * ps2;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int P = lane + 64 * u;
                 if (P < ps2) dst[P] = acc[u];
             }
@@ -546,6 +557,7 @@ __global__ __launch_bounds__(256) void k_dict_grad(const uint32_t* __restrict__ 
 }
 
 // Pass 2: runs that cross chunk borders, from the chunk where they start.
+template <int U>
 __global__ __launch_bounds__(256) void k_dict_grad_join(int64_t n_ent, int s, const float* __restrict__ part,
                                                         const DictGradChunk* __restrict__ info, float* __restrict__ g_r) {
     const int lane = threadIdx.x & 63;
@@ -558,19 +570,19 @@ __global__ __launch_bounds__(256) void k_dict_grad_join(int64_t n_ent, int s, co
         // the run starts in chunk c and continues: its partial is in slot 1,
         // and in slot 0 of every later chunk it reaches
         const float* p0 = part + (c * 2 + 1) * ps2;
-        float acc[4];
+        float acc[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = lane + 64 * u < ps2 ? p0[lane + 64 * u] : 0.0f;
+        for (int u = 0; u < U; ++u) acc[u] = lane + 64 * u < ps2 ? p0[lane + 64 * u] : 0.0f;
         for (int64_t cc = c + 1; cc < nchunk; ++cc) {
             const DictGradChunk cn = info[cc];
             const float* pp = part + (cc * 2) * ps2;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < U; ++u)
                 if (lane + 64 * u < ps2) acc[u] += pp[lane + 64 * u];
             if (!(cn.nseg == 1 && cn.last_cont)) break;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int P = lane + 64 * u;
             if (P < ps2) g_r[(int64_t)ci.key_last * ps2 + P] = acc[u];
         }
@@ -580,15 +592,21 @@ __global__ __launch_bounds__(256) void k_dict_grad_join(int64_t n_ent, int s, co
 hipError_t launch_dict_grad(const uint32_t* key, const uint32_t* val, int64_t n_ent, uint32_t none, const float* wts,
                             const float* gp, int w, int s, int K, float* g_r, float* part, void* info,
                             hipStream_t st) {
-    if (kPatch * s * kPatch * s > 256) return hipErrorInvalidValue;
+    if (s < 1 || s > kMaxScale) return hipErrorInvalidValue;
     if (n_ent == 0) return hipSuccess;
     const int64_t nchunk = (n_ent + 63) / 64;
     int64_t g = (nchunk + 3) / 4;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_dict_grad, dim3((unsigned)g), dim3(256), 0, st, key, val, n_ent, none, wts, gp, w, s, K, g_r,
-                       part, static_cast<DictGradChunk*>(info));
-    hipLaunchKernelGGL(k_dict_grad_join, dim3((unsigned)g), dim3(256), 0, st, n_ent, s, part,
-                       static_cast<const DictGradChunk*>(info), g_r);
+    DictGradChunk* ci = static_cast<DictGradChunk*>(info);
+    if (kPatch * s * kPatch * s <= 256) {
+        hipLaunchKernelGGL(k_dict_grad<4>, dim3((unsigned)g), dim3(256), 0, st, key, val, n_ent, none, wts, gp, w, s, K,
+                           g_r, part, ci);
+        hipLaunchKernelGGL(k_dict_grad_join<4>, dim3((unsigned)g), dim3(256), 0, st, n_ent, s, part, ci, g_r);
+    } else {
+        hipLaunchKernelGGL(k_dict_grad<kPixChunks>, dim3((unsigned)g), dim3(256), 0, st, key, val, n_ent, none, wts, gp,
+                           w, s, K, g_r, part, ci);
+        hipLaunchKernelGGL(k_dict_grad_join<kPixChunks>, dim3((unsigned)g), dim3(256), 0, st, n_ent, s, part, ci, g_r);
+    }
     return hipGetLastError();
 }
 

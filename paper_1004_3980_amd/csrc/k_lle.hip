@@ -398,7 +398,9 @@ hipError_t launch_lle_solve(const LleArgs& a, const void* gram, int gram_fp64, h
     return hipGetLastError();
 }
 
-// x_q = mu_q + sum_m w_m r_{n_m}: one wave per patch.
+// x_q = mu_q + sum_m w_m r_{n_m}: one wave per patch, lane l holds the
+// values l + 64 u, u < U.
+template <int U>
 __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int32_t* __restrict__ ids,
                                                const int32_t* __restrict__ m, const float* __restrict__ w,
                                                const double* __restrict__ mu, const float* __restrict__ resid,
@@ -408,9 +410,11 @@ __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int3
     for (int q = xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6); q < Q; q += nw) {
         const int mq = m[q];
         if (mq <= 0) continue;
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        float acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = 0.0f;
         for (int r0 = 0; r0 < mq; r0 += 8) {
-            float v[8][4];
+            float v[8][U];
             float wr[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int3
                 const int64_t b = ok ? (int64_t)ids[(int64_t)q * K + r0 + r] * ps2 : 0;
                 wr[r] = ok ? w[(int64_t)q * K + r0 + r] : 0.0f;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < U; ++u) {
                     const int p = lane + 64 * u;
                     v[r][u] = (ok && p < ps2) ? resid[b + p] : 0.0f;
                 }
@@ -426,53 +430,69 @@ __global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int3
 #pragma unroll
             for (int r = 0; r < 8; ++r)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc[u] = fmaf(wr[r], v[r][u], acc[u]);
+                for (int u = 0; u < U; ++u) acc[u] = fmaf(wr[r], v[r][u], acc[u]);
         }
         const float mf = (float)mu[q];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int p = lane + 64 * u;
             if (p < ps2) xhat[(int64_t)q * ps2 + p] = mf + acc[u];
         }
     }
 }
 
-// Patches of (5s)^2 = 4c values: half a wave per patch, lane l < c of the half
-// holds values 4l .. 4l+3 and reads them from each neighbour's residual row
-// with one 16-byte load (rows start on 16-byte boundaries); the same fused
+// Patches of (5s)^2 = 4c values: G lanes per patch (half a wave for c <= 32,
+// a wave for c <= 64 U); lane l of the group holds the 16-byte chunks l + G u
+// (values 4(l + G u) .. +3) and reads each from every neighbour's residual
+// row with one 16-byte load (rows start on 16-byte boundaries); the same fused
 // multiply-adds in the same neighbour order as k_synth.
+template <int G, int U>
 __global__ __launch_bounds__(256) void k_synth4(int Q, int K, int ps2, const int32_t* __restrict__ ids,
                                                 const int32_t* __restrict__ m, const float* __restrict__ w,
                                                 const double* __restrict__ mu, const float* __restrict__ resid,
                                                 float* __restrict__ xhat) {
-    const int hl = threadIdx.x & 31;
+    const int hl = threadIdx.x & (G - 1);
     const int nc = ps2 >> 2;
-    const int nh = gridDim.x * (blockDim.x >> 5);
-    for (int q = xcd_block() * (blockDim.x >> 5) + (threadIdx.x >> 5); q < Q; q += nh) {
+    const int nh = gridDim.x * (blockDim.x / G);
+    for (int q = xcd_block() * (blockDim.x / G) + (int)(threadIdx.x / G); q < Q; q += nh) {
         const int mq = m[q];
         if (mq <= 0 || hl >= nc) continue;
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         for (int r0 = 0; r0 < mq; r0 += 8) {
-            float4 v[8];
+            float4 v[8][U];
             float wr[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 const bool ok = r0 + r < mq;
                 const int64_t b = ok ? (int64_t)ids[(int64_t)q * K + r0 + r] * ps2 : 0;
                 wr[r] = ok ? w[(int64_t)q * K + r0 + r] : 0.0f;
-                v[r] = ok ? *reinterpret_cast<const float4*>(resid + b + 4 * hl) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = hl + G * u;
+                    v[r][u] = ok && c < nc ? *reinterpret_cast<const float4*>(resid + b + 4 * c)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
             }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                acc.x = fmaf(wr[r], v[r].x, acc.x);
-                acc.y = fmaf(wr[r], v[r].y, acc.y);
-                acc.z = fmaf(wr[r], v[r].z, acc.z);
-                acc.w = fmaf(wr[r], v[r].w, acc.w);
-            }
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    acc[u].x = fmaf(wr[r], v[r][u].x, acc[u].x);
+                    acc[u].y = fmaf(wr[r], v[r][u].y, acc[u].y);
+                    acc[u].z = fmaf(wr[r], v[r][u].z, acc[u].z);
+                    acc[u].w = fmaf(wr[r], v[r][u].w, acc[u].w);
+                }
         }
         const float mf = (float)mu[q];
-        *reinterpret_cast<float4*>(xhat + (int64_t)q * ps2 + 4 * hl) =
-            make_float4(mf + acc.x, mf + acc.y, mf + acc.z, mf + acc.w);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = hl + G * u;
+            if (c < nc)
+                *reinterpret_cast<float4*>(xhat + (int64_t)q * ps2 + 4 * c) =
+                    make_float4(mf + acc[u].x, mf + acc[u].y, mf + acc[u].z, mf + acc[u].w);
+        }
     }
 }
 
@@ -488,9 +508,12 @@ template <int s>
 __device__ __forceinline__ void blend_seg(const float* __restrict__ xhat, const int32_t* __restrict__ m,
                                           const float* __restrict__ lr, int h, int w, int Y, int X0,
                                           float* __restrict__ hr) {
-    __shared__ float sv[1408];   // staged patch rows: at most 1350 floats (s = 3)
+    __shared__ float sv[1408];   // staged patch rows: at most 1365 floats (s = 3)
     __shared__ int sm[kBlendSeg + 8];
     constexpr int ps = kPatch * s, ps2 = ps * ps;
+    // a segment touches at most (kBlendSeg + ps - 2) / s + 2 patch columns
+    static_assert(((kBlendSeg + ps - 2) / s + 2) * ps <= 1408 && (kBlendSeg + ps - 2) / s + 2 <= kBlendSeg + 8,
+                  "staging buffers too small for this zoom factor");
     const int W = s * w;
     const int npi = h - kPatch + 1, npj = w - kPatch + 1;
     const int X = X0 + threadIdx.x;
@@ -613,18 +636,31 @@ hipError_t launch_lle(const LleArgs& a, hipStream_t st) {
 hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m, const float* w,
                         const double* mu, const float* resid, float* xhat, hipStream_t st) {
     if (Q == 0) return hipSuccess;
-    if (ps2 > 256) return hipErrorInvalidValue;
-    if ((ps2 & 3) == 0 && ps2 <= 128 && (reinterpret_cast<uintptr_t>(resid) & 15) == 0) {
-        int grid = (Q + 7) / 8;
-        if (grid > 65536) grid = 65536;
-        grid = round_grid8(grid);
-        hipLaunchKernelGGL(k_synth4, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+    if (ps2 < 1 || ps2 > kMaxPs2) return hipErrorInvalidValue;
+    const bool vec = (ps2 & 3) == 0 && (reinterpret_cast<uintptr_t>(resid) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(xhat) & 15) == 0;
+    if (vec && ps2 <= 128) {
+        // half a wave per patch
+        const int grid = round_grid8((int)std::min<int64_t>(((int64_t)Q + 7) / 8, 65536));
+        hipLaunchKernelGGL((k_synth4<32, 1>), dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
         return hipGetLastError();
     }
-    int grid = (Q + 3) / 4;
-    if (grid > 65536) grid = 65536;
-    grid = round_grid8(grid);
-    hipLaunchKernelGGL(k_synth, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+    const int grid = round_grid8((int)std::min<int64_t>(((int64_t)Q + 3) / 4, 65536));
+    if (vec) {
+        // a wave per patch, 16-byte chunks
+        if (ps2 <= 256)
+            hipLaunchKernelGGL((k_synth4<64, 1>), dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+        else
+            hipLaunchKernelGGL((k_synth4<64, 2>), dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+        return hipGetLastError();
+    }
+    if (ps2 <= 64)
+        hipLaunchKernelGGL(k_synth<1>, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+    else if (ps2 <= 256)
+        hipLaunchKernelGGL(k_synth<4>, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
+    else
+        hipLaunchKernelGGL(k_synth<(kMaxPs2 + 63) / 64>, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid,
+                           xhat);
     return hipGetLastError();
 }
 
@@ -633,21 +669,28 @@ hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, in
     const int64_t H = (int64_t)scale * h, W = (int64_t)scale * w;
     if (H == 0 || W == 0) return hipSuccess;
     const int64_t g = H * ((W + kBlendSeg - 1) / kBlendSeg);
-    if (g > 0x7FFFFFFF || scale < 1 || scale > 3) return hipErrorInvalidValue;
-    if (scale == 1) hipLaunchKernelGGL(k_blend_rows<1>, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, hr);
-    else if (scale == 2) hipLaunchKernelGGL(k_blend_rows<2>, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, hr);
-    else hipLaunchKernelGGL(k_blend_rows<3>, dim3((unsigned)g), dim3(kBlendSeg), 0, st, xhat, m, lr, h, w, hr);
+    if (g > 0x7FFFFFFF || scale < 1 || scale > kMaxScale) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)g), blk(kBlendSeg);
+    switch (scale) {
+        case 1: hipLaunchKernelGGL(k_blend_rows<1>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
+        case 2: hipLaunchKernelGGL(k_blend_rows<2>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
+        case 3: hipLaunchKernelGGL(k_blend_rows<3>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
+        default: hipLaunchKernelGGL(k_blend_rows<4>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_b_blend(const BatchImage* im, int n, int64_t seg_total, int scale, const float* xhat,
                           const int32_t* m, hipStream_t st) {
     if (seg_total == 0) return hipSuccess;
-    if (seg_total > 0x7FFFFFFF || scale < 1 || scale > 3) return hipErrorInvalidValue;
-    const dim3 g((unsigned)seg_total);
-    if (scale == 1) hipLaunchKernelGGL(k_b_blend<1>, g, dim3(kBlendSeg), 0, st, im, n, xhat, m);
-    else if (scale == 2) hipLaunchKernelGGL(k_b_blend<2>, g, dim3(kBlendSeg), 0, st, im, n, xhat, m);
-    else hipLaunchKernelGGL(k_b_blend<3>, g, dim3(kBlendSeg), 0, st, im, n, xhat, m);
+    if (seg_total > 0x7FFFFFFF || scale < 1 || scale > kMaxScale) return hipErrorInvalidValue;
+    const dim3 g((unsigned)seg_total), blk(kBlendSeg);
+    switch (scale) {
+        case 1: hipLaunchKernelGGL(k_b_blend<1>, g, blk, 0, st, im, n, xhat, m); break;
+        case 2: hipLaunchKernelGGL(k_b_blend<2>, g, blk, 0, st, im, n, xhat, m); break;
+        case 3: hipLaunchKernelGGL(k_b_blend<3>, g, blk, 0, st, im, n, xhat, m); break;
+        default: hipLaunchKernelGGL(k_b_blend<4>, g, blk, 0, st, im, n, xhat, m); break;
+    }
     return hipGetLastError();
 }
 

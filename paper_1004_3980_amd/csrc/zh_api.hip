@@ -59,7 +59,7 @@ struct zh_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     size_t mem_limit = 0, mem_used = 0;
-    Dict dicts[4];                // scale 1..3 (index = scale)
+    Dict dicts[kMaxScale + 1];    // scale 1 .. kMaxScale (index = scale)
     zh_query_opts opts{0, 0, 1, 1};
     // last query
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
@@ -76,7 +76,7 @@ struct zh_ctx {
     };
     struct Batch {
         std::vector<uint64_t> sig;
-        BatchGroup g[4];          // by zoom factor
+        BatchGroup g[kMaxScale + 1];   // by zoom factor
         hipGraphExec_t exec = nullptr;
         hipStream_t stream = nullptr;
         hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -482,7 +482,7 @@ zh_status zh_degrade(zh_ctx* c, const float* hr, int n_img, int H, int W, int sc
 zh_status zh_make_dictionary(zh_ctx* c, const float* hr, int n_img, int H, int W, const int32_t* pos, int64_t n,
                              int scale, float sigma, int mode, float* feat, float* resid) {
     if (!c) return ZH_EINVAL;
-    if (!hr || !pos || !feat || !resid || n_img < 1 || n < 1 || n >= (1ll << 31) || scale < 1 || scale > 3 ||
+    if (!hr || !pos || !feat || !resid || n_img < 1 || n < 1 || n >= (1ll << 31) || scale < 1 || scale > kMaxScale ||
         (mode != ZH_FEAT_MEANREM && mode != ZH_FEAT_GRAD4) || !(sigma > 0.f) || sigma > 5.f)
         return fail(c, ZH_EINVAL, "zh_make_dictionary: bad arguments");
     const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
@@ -517,7 +517,7 @@ zh_status zh_features(zh_ctx* c, const float* lr, int h, int w, int mode, float*
 zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, float w, uint64_t seed) {
     if (!c) return ZH_EINVAL;
     if (!dict || !dict->feat || !dict->resid || dict->n < 1 || dict->n >= (1ll << 31) ||
-        (dict->scale < 1 || dict->scale > 3) ||
+        (dict->scale < 1 || dict->scale > kMaxScale) ||
         (dict->feat_mode != ZH_FEAT_MEANREM && dict->feat_mode != ZH_FEAT_GRAD4) ||
         dict->dim != dim_of(dict->feat_mode))
         return fail(c, ZH_EINVAL, "zh_build_tables: bad dictionary");
@@ -648,7 +648,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
 
 zh_status zh_get_hash_params(zh_ctx* c, int scale, float* alpha, float* beta) {
     if (!c) return ZH_EINVAL;
-    if (scale < 1 || scale > 3 || !c->dicts[scale].valid) return fail(c, ZH_ESTATE, "no tables for scale %d", scale);
+    if (scale < 1 || scale > kMaxScale || !c->dicts[scale].valid) return fail(c, ZH_ESTATE, "no tables for scale %d", scale);
     const Dict& d = c->dicts[scale];
     if (alpha) std::memcpy(alpha, d.h_alpha.data(), sizeof(float) * d.h_alpha.size());
     if (beta) std::memcpy(beta, d.h_beta.data(), sizeof(float) * d.h_beta.size());
@@ -657,7 +657,7 @@ zh_status zh_get_hash_params(zh_ctx* c, int scale, float* alpha, float* beta) {
 
 zh_status zh_hash(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* codes, uint64_t* keys) {
     if (!c) return ZH_EINVAL;
-    if (scale < 1 || scale > 3 || !c->dicts[scale].valid) return fail(c, ZH_ESTATE, "no tables for scale %d", scale);
+    if (scale < 1 || scale > kMaxScale || !c->dicts[scale].valid) return fail(c, ZH_ESTATE, "no tables for scale %d", scale);
     if (!feat || n < 0) return fail(c, ZH_EINVAL, "zh_hash: bad arguments");
     TRY(set_device(c));
     Dict& d = c->dicts[scale];
@@ -702,7 +702,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     if (!c) return ZH_EINVAL;
     if (!lr || h < kPatch || w < kPatch || K < 1 || K > kMaxK)
         return fail(c, ZH_EINVAL, "zh_query: need lr, h, w >= 5 and 1 <= K <= %d", kMaxK);
-    if (scale < 1 || scale > 3 || !c->dicts[scale].valid)
+    if (scale < 1 || scale > kMaxScale || !c->dicts[scale].valid)
         return fail(c, ZH_ESTATE, "zh_query: no tables built for scale %d", scale);
     if (c->opts.rerank > 0 && c->opts.rerank < K)
         return fail(c, ZH_EINVAL, "zh_query: rerank %d below K %d", c->opts.rerank, K);
@@ -879,7 +879,7 @@ zh_status zh_backward(zh_ctx* c, const float* g_hr, float* g_resid, float* g_lam
     if (!d.resid) return fail(c, ZH_ESTATE, "zh_backward: the dictionary has no HR residuals");
     const int s = c->qscale, h = c->qh, w = c->qw, H = s * h, W = s * w, K = c->qK;
     const int ps2 = (kPatch * s) * (kPatch * s);
-    if (K > kMaxK || d.D > 128 || ps2 > 256) return fail(c, ZH_EUNSUPPORTED, "zh_backward: K <= 16, D <= 128, s <= 3");
+    if (K > kMaxK || d.D > 128) return fail(c, ZH_EUNSUPPORTED, "zh_backward: K <= 16, D <= 128");
     TRY(set_device(c));
     const int64_t HW = (int64_t)H * W, Q = c->Q;
     // workspace: gamma, F|S|a, four HR temporaries, H x w, h x w, h x W
@@ -1034,7 +1034,7 @@ zh_status batch_check(zh_ctx* c, const zh_batch* b) {
         const int s = b->scale[i];
         if (!b->lr[i] || !b->hr_out[i] || b->h[i] < kPatch || b->w[i] < kPatch)
             return fail(c, ZH_EINVAL, "zh_run_batch: image %d: null pointer or side < 5", i);
-        if (s < 1 || s > 3 || !c->dicts[s].valid) return fail(c, ZH_ESTATE, "zh_run_batch: no tables for scale %d", s);
+        if (s < 1 || s > kMaxScale || !c->dicts[s].valid) return fail(c, ZH_ESTATE, "zh_run_batch: no tables for scale %d", s);
     }
     return ZH_OK;
 }
@@ -1050,7 +1050,7 @@ std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
                        (uint64_t)c->opts.cap, (uint64_t)c->opts.rerank, (uint64_t)c->opts.proj,
                        (uint64_t)c->opts.lle_fp64, (uint64_t)c->batch.tile, (uint64_t)c->batch.grid_per_cu,
                        (uint64_t)(uintptr_t)c->stream});
-    for (int s = 1; s <= 3; ++s) {
+    for (int s = 1; s <= kMaxScale; ++s) {
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dir.p);
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dfilt.p);
     }
@@ -1064,8 +1064,8 @@ std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
 zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     auto& B = c->batch;
     int64_t q_max = 0, lr_max = 0, hr_max = 0, ps2_max = 0, L_max = 0, k_max = 0, D_max = 0;
-    std::vector<BatchImage> tabs[4];
-    for (int s = 1; s <= 3; ++s) {
+    std::vector<BatchImage> tabs[kMaxScale + 1];
+    for (int s = 1; s <= kMaxScale; ++s) {
         auto& g = B.g[s];
         int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, bsegs = 0;
         for (int i = 0; i < b->n_images; ++i) {
@@ -1109,7 +1109,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     }
     // the groups run one after another and share the scratch
     TRY(ensure(c, B.scr, sizeof(float) * (size_t)std::max<int64_t>(hr_max, 1)));
-    for (int s = 1; s <= 3; ++s) {
+    for (int s = 1; s <= kMaxScale; ++s) {
         auto& g = B.g[s];
         if (!g.n) continue;
         for (auto& im : tabs[s]) im.scr = P<float>(B.scr) + im.hr_off;
@@ -1153,7 +1153,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
     zh_status rc = ZH_OK;
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1) ncu = 256;
-    for (int s = 1; s <= 3 && rc == ZH_OK; ++s) {
+    for (int s = 1; s <= kMaxScale && rc == ZH_OK; ++s) {
         auto& g = B.g[s];
         if (!g.n) continue;
         Dict& d = c->dicts[s];
@@ -1303,7 +1303,7 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
             float bestrun = 1e30f;
             for (int rep = 0; rep < 2 && rc == ZH_OK; ++rep) {
                 if (hipEventRecord(e0, B.stream) != hipSuccess) { rc = fail(c, ZH_EDEVICE, "event"); break; }
-                for (int s = 1; s <= 3; ++s) {
+                for (int s = 1; s <= kMaxScale; ++s) {
                     auto& g = B.g[s];
                     if (!g.n) continue;
                     const BatchImage* tab = P<BatchImage>(g.table);

@@ -9,12 +9,14 @@
 namespace zh {
 
 constexpr int kPatch = 5;       // LR patch side
+constexpr int kMaxScale = 4;    // zoom factors 1 .. 4 (HR patch side 5 s)
+constexpr int kMaxPs2 = kPatch * kMaxScale * kPatch * kMaxScale;
 constexpr int kMaxTaps = 33;    // longest 1-D Gaussian the kernels accept
 constexpr int kMaxK = 16;       // neighbours per patch
 constexpr int kMaxL = 64;       // hash tables
-constexpr int kMaxKHash = 32;
+constexpr int kMaxKHash = 32;   // hashes per table
 constexpr int32_t kCodeUnset = (int32_t)0x80000000;   // MFMA codes lie within +-2^23
-constexpr int kFixSlots = 16;                        // fix-list entries per wave of 16 rows   // hashes per table
+constexpr int kFixSlots = 16;                        // fix-list entries per wave of 16 rows
 
 struct Taps {                   // normalised 1-D Gaussian, offsets -R..R
     double g[kMaxTaps];

@@ -178,6 +178,15 @@ def scaled(wl: Workload, **kw) -> Workload:
     return dataclasses.replace(wl, **kw)
 
 
+def at_scale(wl: Workload, s: int) -> Workload:
+    """The workload at zoom factor s: the same LR test size, dictionary size
+    and seeds; training images are added while their LR grids hold fewer
+    than n_dict patch positions (at x4 a 512^2 HR image gives 124^2)."""
+    per = (wl.dict_hr // s - wl.p + 1) ** 2
+    need = -(-wl.n_dict // per)
+    return dataclasses.replace(wl, name=f"{wl.name}_x{s}", scale=s, dict_images=max(wl.dict_images, need))
+
+
 # dictionaries of the batched workload: 1M pairs per zoom factor from 64
 # seeded 512^2 HR images each; method parameters as the precision workload
 BATCHED = {

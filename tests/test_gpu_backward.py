@@ -22,6 +22,9 @@ REL = 1e-4
 PIX_TOL = 1e-5
 SMALL = dict(test_h=20, test_w=22, dict_images=4, dict_hr=64, n_dict=3000, L=8, k=4, w=32.0, K=5)
 MID = dict(test_h=44, test_w=40, dict_images=8, dict_hr=128, n_dict=20000, L=8, k=8, w=32.0, K=5)
+# zoom x1 (5 x 5 HR patches) and x4 (20 x 20, more values than a wave's four chunks)
+SMALL1 = dict(SMALL, scale=1)
+SMALL4 = dict(SMALL, scale=4, dict_hr=128)
 _cache = {}
 
 
@@ -60,7 +63,8 @@ def _compare(g_gpu, glam_gpu, g_ref, glam_ref, used):
 
 
 @pytest.mark.parametrize("cfg,bp_iters,sigma_r,cap", [(SMALL, 0, 0.1, 0), (SMALL, 3, 0.1, 0), (SMALL, 2, math.inf, 0),
-                                                      (MID, 3, 0.1, 0), (SMALL, 3, 0.1, 20), (MID, 3, 0.1, 40)])
+                                                      (MID, 3, 0.1, 0), (SMALL, 3, 0.1, 20), (MID, 3, 0.1, 40),
+                                                      (SMALL1, 2, 0.1, 0), (SMALL4, 2, 0.1, 0), (SMALL4, 2, 0.1, 20)])
 def test_backward_matches_oracle_gradient(gpu_ok, cfg, bp_iters, sigma_r, cap):
     """cap > 0: the early-stop search, whose FP64 Gram matrices the lambda
     adjoint takes over; cap = 0: the union search, Gram matrices formed in the

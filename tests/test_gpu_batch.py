@@ -1,8 +1,9 @@
-"""Batched form (zh_run_batch): many LR images of uneven size at x2 and x3 in
-one captured launch chain. Bar: bit-exact against the same images run one
+"""Batched form (zh_run_batch): many LR images of uneven size at x2, x3 and x4
+in one captured launch chain. Bar: bit-exact against the same images run one
 by one through zh_query, zh_lle_weights, zh_reconstruct and
 zh_backproject (odd and even iteration counts, a one-patch image, graph
-replays, after autotuning), and an x3 image within 1e-5 of the FP64 oracle.
+replays, after autotuning), and an x3 and an x4 image within 1e-5 of the FP64
+oracle.
 """
 import numpy as np
 import pytest
@@ -12,9 +13,11 @@ from oracle import pipeline
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [(20, 24, 2), (31, 17, 2), (9, 40, 2), (5, 5, 2), (25, 25, 3), (14, 30, 3), (12, 12, 3), (5, 9, 3)]
+SIZES = [(20, 24, 2), (31, 17, 2), (9, 40, 2), (5, 5, 2), (25, 25, 3), (14, 30, 3), (12, 12, 3), (5, 9, 3),
+         (18, 21, 4), (5, 7, 4)]
 WL2 = dict(dict_images=6, dict_hr=96, n_dict=8000, L=8, k=8, w=32.0, K=5, cap=40)
 WL3 = dict(dict_images=10, dict_hr=96, n_dict=6000, L=8, k=8, w=32.0, K=5, cap=40, scale=3)
+WL4 = dict(dict_images=10, dict_hr=128, n_dict=6000, L=8, k=8, w=32.0, K=5, cap=40, scale=4)
 _state = {}
 
 
@@ -33,12 +36,14 @@ def _setup():
     ctx = zb.Context(0)
     wl2 = synthdata.scaled(synthdata.WORKLOADS["mid"], **WL2)
     wl3 = synthdata.scaled(synthdata.WORKLOADS["mid"], **WL3)
+    wl4 = synthdata.scaled(synthdata.WORKLOADS["mid"], **WL4)
     g2 = GpuWorkload(wl2, ctx=ctx)
     g3 = GpuWorkload(wl3, ctx=ctx)
+    g4 = GpuWorkload(wl4, ctx=ctx)
     ctx.set_query_opts(cap=40, rerank=0, proj=1, lle_fp64=1)
     lrs = [torch.from_numpy(synthdata.fractal_voronoi_image(synthdata.SEED_BASE + 7000 + i, h, w)).cuda()
            for i, (h, w, s) in enumerate(SIZES)]
-    _state.update(ctx=ctx, g2=g2, g3=g3, wl2=wl2, wl3=wl3, lrs=lrs, torch=torch)
+    _state.update(ctx=ctx, g2=g2, g3=g3, g4=g4, wl2=wl2, wl3=wl3, wl4=wl4, lrs=lrs, torch=torch)
     return _state
 
 
@@ -93,15 +98,17 @@ def test_batch_after_autotuning():
         assert torch.equal(r, g)
 
 
-def test_batch_x3_image_against_oracle():
+@pytest.mark.parametrize("size", [(14, 30, 3), (18, 21, 4)])
+def test_batch_image_against_oracle(size):
     st = _setup()
-    wl3 = st["wl3"]
+    s = size[2]
+    wl = st[f"wl{s}"]
     got, _ = _batch(st, 2, 5, 1e-3, 1.5, 0.1)
-    pre = pipeline.prepare(wl3.dictionary_images(), wl3.positions(), 3, wl3.feat_mode, wl3.L, wl3.k, wl3.w,
-                           wl3.hash_seed)
-    i = SIZES.index((14, 30, 3))
+    pre = pipeline.prepare(wl.dictionary_images(), wl.positions(), s, wl.feat_mode, wl.L, wl.k, wl.w,
+                           wl.hash_seed)
+    i = SIZES.index(size)
     lr = st["lrs"][i].cpu().numpy()
-    _, _, hr_bp = pipeline.run(pre, lr, 3, 5, 1e-3, 2, 1.5, 0.1, cap=40)
+    _, _, hr_bp = pipeline.run(pre, lr, s, 5, 1e-3, 2, 1.5, 0.1, cap=40)
     assert np.abs(got[i].cpu().numpy() - hr_bp).max() <= 1e-5
 
 

@@ -80,12 +80,18 @@ TINY = "tiny"
 # ragged, non-square test image and a small early-stop limit
 TINY_RAGGED = ("tiny", (("test_h", 50), ("test_w", 77)))
 MID = "mid"
+# zoom x3 (15 x 15 HR patches; the blend, synthesis and search at s = 3)
+TINY3 = ("tiny", (("scale", 3), ("n_dict", 10000)))
+# zoom x1 (de-blurring: 5 x 5 HR patches, the degradation is the blur alone)
+# and x4 (20 x 20 HR patches, 400 values a row); bins of width 8 so that
+# about two thirds of the patches find candidates (with the early stop: at x1
+# some unions exceed the 8192 IDs the uncapped search takes)
+TINY1 = ("tiny", (("scale", 1), ("w", 8.0)))
+TINY4 = ("tiny", (("scale", 4), ("n_dict", 6000), ("w", 8.0)))
 # piecewise-constant images (no noise): most gradient features are exactly
 # zero, so the early-stop search meets bins of thousands of IDs and ties of
 # distance 0 everywhere (the screen's bounds are all 0, every candidate is
 # kept and ranked by ID)
-# zoom x3 (15 x 15 HR patches; the blend, synthesis and search at s = 3)
-TINY3 = ("tiny", (("scale", 3), ("n_dict", 10000)))
 FLAT = ("mid", (("amp", 0.0), ("test_h", 96), ("test_w", 96), ("n_dict", 60000), ("dict_images", 16)))
 
 
@@ -98,7 +104,7 @@ def test_dictionary_bit_exact(gpu):
     assert np.array_equal(_np(m.g.resid), m.pre.dictionary.resid)
 
 
-@pytest.mark.parametrize("scale", [2, 3])
+@pytest.mark.parametrize("scale", [1, 2, 3, 4])
 def test_degrade_bit_exact(gpu, scale):
     torch = _torch()
     hr = synthdata.fractal_voronoi_image(77, 101, 66)
@@ -219,7 +225,8 @@ def _gpu_candidates(c, cap_per_query):
     return _np(counts), _np(ids)
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (TINY3, 12), (MID, 0), (MID, 40), (FLAT, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (TINY3, 12), (TINY1, 12), (TINY4, 12), (MID, 0), (MID, 40),
+                                      (FLAT, 40)])
 def test_candidate_sets_bit_exact(gpu, name, cap):
     c = case(name, cap=cap)
     maxc = max(len(x) for x in c.qr.cand)
@@ -232,7 +239,8 @@ def test_candidate_sets_bit_exact(gpu, name, cap):
         assert np.array_equal(ids[q, :len(ref)], ref), q
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (TINY3, 12), (MID, 0), (MID, 40), (FLAT, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 0), (TINY, 12), (TINY_RAGGED, 0), (TINY3, 12), (TINY1, 12), (TINY4, 12), (MID, 0), (MID, 40),
+                                      (FLAT, 40)])
 def test_neighbours_weights_pixels(gpu, name, cap):
     torch = _torch()
     c = case(name, cap=cap)
@@ -253,7 +261,7 @@ def test_neighbours_weights_pixels(gpu, name, cap):
     assert np.abs(_np(hb).astype(np.float64) - c.hr_bp).max() < PIX_TOL
 
 
-@pytest.mark.parametrize("name,cap", [(TINY, 12), (TINY3, 12), (MID, 40), (FLAT, 40)])
+@pytest.mark.parametrize("name,cap", [(TINY, 12), (TINY3, 12), (TINY1, 12), (TINY4, 12), (MID, 40), (FLAT, 40)])
 def test_screened_form_neighbour_sets_and_pixels(gpu, name, cap):
     """Screened form (int8 screen, at most R = 32 exact fp32 rows, fp32 LLE
     with the FP64 redo): at most R survivors, the neighbour count of the

@@ -22,7 +22,7 @@ from oracle import backproject, backward, imaging, lle, pipeline
 RNG = np.random.default_rng(20240611)
 
 
-@pytest.mark.parametrize("scale", [2, 3])
+@pytest.mark.parametrize("scale", [1, 2, 3, 4])
 @pytest.mark.parametrize("n_hr", [23, 36])
 def test_axis_matrices_reproduce_forward_operators(scale, n_hr):
     H, W = n_hr, n_hr + 5
@@ -77,10 +77,10 @@ def test_lle_dw_dlambda():
     assert np.allclose(w0, 1.0 / M) and not dw0.any()
 
 
-def _small_case(bp_iters, sigma_r):
-    wl = synthdata.scaled(synthdata.WORKLOADS["diff"], test_h=20, test_w=22, dict_images=4, dict_hr=64,
-                          n_dict=3000, L=8, k=4, w=32.0, K=5, bp_iters=bp_iters,
-                          sigma_r=sigma_r)
+def _small_case(bp_iters, sigma_r, scale=2):
+    wl = synthdata.scaled(synthdata.WORKLOADS["diff"], test_h=20, test_w=22, dict_images=4,
+                          dict_hr=64 if scale < 4 else 128, n_dict=3000, L=8, k=4, w=32.0, K=5,
+                          bp_iters=bp_iters, sigma_r=sigma_r, scale=scale)
     pre = pipeline.prepare(wl.dictionary_images(), wl.positions(), wl.scale, wl.feat_mode, wl.L, wl.k,
                            wl.w, wl.hash_seed)
     gt = wl.test_image().astype(np.float64)
@@ -89,9 +89,10 @@ def _small_case(bp_iters, sigma_r):
     return wl, pre, gt, rec
 
 
-@pytest.mark.parametrize("bp_iters,sigma_r", [(0, 0.1), (3, 0.1), (2, math.inf)])
-def test_gradient_matches_central_differences(bp_iters, sigma_r):
-    wl, pre, gt, rec = _small_case(bp_iters, sigma_r)
+@pytest.mark.parametrize("bp_iters,sigma_r,scale", [(0, 0.1, 2), (3, 0.1, 2), (2, math.inf, 2), (2, 0.1, 1),
+                                                   (2, 0.1, 4)])
+def test_gradient_matches_central_differences(bp_iters, sigma_r, scale):
+    wl, pre, gt, rec = _small_case(bp_iters, sigma_r, scale)
     n_pix = gt.size
     assert (rec.qr.m > 0).mean() > 0.5
 

@@ -18,7 +18,7 @@ def test_gauss_weights_match_scipy_kernel():
     assert abs(g.sum() - 1.0) < 1e-15 and np.array_equal(g, g[::-1])
 
 
-@pytest.mark.parametrize("scale", [2, 3])
+@pytest.mark.parametrize("scale", [1, 2, 3, 4])
 def test_degrade_matches_scipy_blur_then_decimate(scale):
     hr = synthdata.fractal_voronoi_image(5, 60, 48).astype(np.float64)
     ref = ndimage.gaussian_filter(hr, 1.0, truncate=3.0, mode="nearest")[::scale, ::scale]
@@ -80,7 +80,7 @@ def test_keys_kernel_closed_form():
     assert abs(imaging.keys_cubic(1.5) + 0.0625) < 1e-15
 
 
-@pytest.mark.parametrize("scale", [2, 3])
+@pytest.mark.parametrize("scale", [1, 2, 3, 4])
 def test_bicubic_samples_and_reproduces_quadratics(scale):
     h, w = 12, 15
     lr = synthdata.fractal_voronoi_image(8, h, w).astype(np.float64)
@@ -95,16 +95,18 @@ def test_bicubic_samples_and_reproduces_quadratics(scale):
     assert np.abs(upq[inner] - ref[inner]).max() < 1e-12
 
 
-def test_dictionary_pairs_recover_hr_patches():
+@pytest.mark.parametrize("scale", [1, 2, 4])
+def test_dictionary_pairs_recover_hr_patches(scale):
     hr = synthdata.image_stack(30, 3, 40, 40)
-    pos = synthdata.sample_positions(31, 3, 20, 20, 5, 200)
-    d = imaging.build_dictionary(hr, pos, 2, 1)
-    assert d.feat.shape == (200, 100) and d.resid.shape == (200, 100)
-    for n in (0, 57, 199):
+    pos = synthdata.sample_positions(31, 3, 40 // scale, 40 // scale, 5, 100)
+    d = imaging.build_dictionary(hr, pos, scale, 1)
+    ps = 5 * scale
+    assert d.feat.shape == (100, 100) and d.resid.shape == (100, ps * ps)
+    for n in (0, 57, 99):
         im, i, j = pos[n]
-        patch = hr[im][2 * i:2 * i + 10, 2 * j:2 * j + 10].astype(np.float64).ravel()
+        patch = hr[im][scale * i:scale * i + ps, scale * j:scale * j + ps].astype(np.float64).ravel()
         assert np.abs(d.resid[n] + d.lr_mean[n] - patch).max() < 1e-7
-        lr = imaging.degrade(hr[im], 2)
+        lr = imaging.degrade(hr[im], scale)
         assert np.array_equal(d.feat[n], imaging.features(lr, np.array([[i, j]]), 1)[0])
     # IDs run over images in row-major order
     key = pos[:, 0] * 1_000_000 + pos[:, 1] * 1000 + pos[:, 2]
