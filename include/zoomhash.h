@@ -83,7 +83,8 @@ enum { ZH_FEAT_MEANREM = 0,   /* D = 25: the patch's pixels minus their mean */
  * of the HR image by `sigma` and `scale`; feat[n, D] is the LR patch's
  * feature vector and resid[n, (5s)^2] the HR patch at (s i, s j) minus the
  * mean of the LR patch. Row n is pair ID n (Section 2.1: unique integer IDs).
- * Positions must satisfy 0 <= i, j <= ceil(H/s) - 5. Uses a temporary device
+ * Positions must satisfy 0 <= i <= floor(H/s) - 5 and 0 <= j <= floor(W/s) - 5
+ * (the HR patch inside the image; not checked). Uses a temporary device
  * buffer of n_img * ceil(H/s) * ceil(W/s) * 5 floats. */
 zh_status zh_make_dictionary(zh_ctx* ctx, const float* hr, int n_img, int H, int W,
                              const int32_t* pos, int64_t n, int scale, float sigma,
