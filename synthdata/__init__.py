@@ -217,3 +217,10 @@ def batched_sizes(seed: int = B + 4, count: int = 64):
         b = int(min(1024, max(96, round(a * rho))))
         out.append((a, b, 2 if i < count // 2 else 3))
     return out
+
+
+def crop_draws(seed: int, n_images: int, per_image: int) -> np.ndarray:
+    """64-bit integer draws [n_images, per_image] for the training-crop sampler."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, np.iinfo(np.uint64).max, size=(n_images, per_image), dtype=np.uint64,
+                        endpoint=True)
