@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="precision")
-    ap.add_argument("--form", choices=["screened", "exact", "batched", "diff"], default="screened",
+    ap.add_argument("--form", choices=["screened", "exact", "batched", "diff", "tools"], default="screened",
                     help="screened/exact: the 1024^2 workload (the headline line); batched: 64 images "
                          "at x2/x3 in one captured graph against per-image launches; diff: forward and "
                          "backward of the differentiation workload")
@@ -134,6 +134,8 @@ def main():
         return bench_batched(args)
     if args.form == "diff":
         return bench_diff(args)
+    if args.form == "tools":
+        return bench_tools(args)
     wl = synthdata.WORKLOADS[args.workload]
     own_scale = args.scale in (0, wl.scale)
     if not own_scale:
@@ -289,6 +291,66 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["extra"]["copy_probe_bytes"] = n * 4
+    print(json.dumps(out), flush=True)
+
+
+def bench_tools(args):
+    """Dictionary-construction tools (off the per-image path): gradient-CDF
+    sampling of 25 crops of 100 x 100 from each of 500 training images of
+    512^2 (the paper's training-set recipe, synthetic images), and the bucket
+    entropy of the 1024^2 workload's 24 tables over 2M pairs."""
+    import torch
+    import synthdata
+    from paper_1004_3980_amd import zoomhash as zb
+    from paper_1004_3980_amd.pipeline import GpuWorkload
+    n_img, side, per, H = 500, 100, 25, 512
+    log(f"[bench] tools: {n_img} images of {H}^2, {per} crops of {side}^2 each")
+    stack = torch.from_numpy(synthdata.image_stack(synthdata.SEED_BASE + 9000, n_img, H, H)).cuda()
+    draws = torch.from_numpy(synthdata.crop_draws(synthdata.SEED_BASE + 9001, n_img, per).view(np.int64)).cuda()
+    corners = torch.empty((n_img, per, 2), dtype=torch.int32, device="cuda")
+    crops = torch.empty((n_img, per, side, side), dtype=torch.float32, device="cuda")
+    ctx = zb.Context(0)
+
+    def crop_call():
+        ctx.sample_crops(stack, n_img, H, H, draws, per, side, corners, crops)
+
+    for _ in range(args.warmup):
+        crop_call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        crop_call()
+    torch.cuda.synchronize()
+    crop_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    # algorithmic bytes: the images read once, the crops written
+    crop_bytes = n_img * H * H * 4 + n_img * per * side * side * 4
+    wl = synthdata.WORKLOADS[args.workload]
+    log(f"[bench] building {wl.name} tables for the entropy diagnostic")
+    g = GpuWorkload(wl, device=0)
+    for _ in range(args.warmup):
+        g.ctx.table_entropy(wl.scale, wl.L)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ent = g.ctx.table_entropy(wl.scale, wl.L)
+    ent_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    cap = 1 << (2 * wl.n_dict - 1).bit_length()
+    ent_bytes = wl.L * cap * 16
+    out = {"metric": "training crops/s (gradient-CDF sampling, 100x100 crops from 512^2 images)",
+           "value": n_img * per / (crop_ms * 1e-3), "unit": "crops/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": crop_ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64/u64", "data": "synthetic",
+           "config": {"workload": f"{n_img} training images of {H}x{H}, {per} crops of {side}x{side} each; "
+                                  f"bucket entropy of {wl.name} ({wl.L} tables, {wl.n_dict} pairs)",
+                      "parallelism": "single GPU"},
+           "roofline": {"bound": "hbm", "kernel": "crop sampling (whole call)",
+                        "achieved": round(crop_bytes / (crop_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(crop_bytes / (crop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": None, "algorithmic_bytes": crop_bytes},
+           "cpu_baseline": None,
+           "extra": {"entropy_ms_per_call": round(ent_ms, 4),
+                     "entropy_directory_gbs": round(ent_bytes / (ent_ms * 1e-3) / 1e9, 1),
+                     "entropy_bits": [round(float(v), 4) for v in ent],
+                     "entropy_bound_bits": float(np.log2(wl.n_dict))}}
     print(json.dumps(out), flush=True)
 
 

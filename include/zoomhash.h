@@ -90,6 +90,24 @@ zh_status zh_make_dictionary(zh_ctx* ctx, const float* hr, int n_img, int H, int
                              const int32_t* pos, int64_t n, int scale, float sigma,
                              int feat_mode, float* feat, float* resid);
 
+/* Training crops (Section 5, training data generation): draw crop centres
+ * from the first-order-gradient distribution of each training image and cut
+ * side x side crops around them.
+ * imgs[n_img, H, W] fp32 (device); draws[n_img, m] 64-bit integers (device),
+ * row i for image i. A pixel weighs q = floor((|dx| + |dy|) 2^20), dx and dy
+ * the differences of its right and left (lower and upper) neighbours in FP64,
+ * replicate border, q saturated at 2^32 - 1 (also for non-finite values).
+ * Draw x picks the first pixel (row-major) whose inclusive cumulative weight
+ * exceeds x mod T, T the image's total weight (pixel x mod (H W) if T = 0).
+ * corners[n_img, m, 2] (device, int32): top-left (row, col) of each crop, the
+ * centre minus side / 2 clamped so the crop lies inside the image.
+ * crops[n_img, m, side, side] (device, fp32) or NULL: the crops themselves.
+ * 1 <= side <= min(H, W), H W < 2^31, n_img <= 65535, n_img m < 2^31.
+ * Scratch: n_img (144 ceil(H W / 1024) + 8) bytes held by the context. */
+zh_status zh_sample_crops(zh_ctx* ctx, const float* imgs, int n_img, int H, int W,
+                          const uint64_t* draws, int m, int side, int32_t* corners,
+                          float* crops);
+
 /* Feature rows of every stride-1 patch of one LR image: feat[Q, D] and the
  * patch means mu[Q] (FP64, may be NULL). */
 zh_status zh_features(zh_ctx* ctx, const float* lr, int h, int w, int feat_mode, float* feat,
@@ -121,6 +139,12 @@ typedef struct {
  * Limits: 1 <= L <= 64, 1 <= k <= 32, w > 0. */
 zh_status zh_build_tables(zh_ctx* ctx, const zh_dictionary* dict, int L, int k, float w,
                           uint64_t seed);
+
+/* Hashing quality (Section 4.1, determining r): the entropy in bits of each
+ * table's bucket occupancy, -sum_b p_b log2 p_b with p_b the fraction of the
+ * dictionary's rows in bucket b, written to the HOST array entropy[L] (FP64;
+ * capacity = its length, at least L). Synchronises the context's stream. */
+zh_status zh_table_entropy(zh_ctx* ctx, int scale, double* entropy, int capacity);
 
 /* Copy the hash parameters of `scale` to HOST arrays alpha[L*k*D], beta[L*k]. */
 zh_status zh_get_hash_params(zh_ctx* ctx, int scale, float* alpha_host, float* beta_host);

@@ -20,7 +20,7 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("ZH_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["zh_api.hip", "k_image.hip", "k_hash.hip", "k_table.hip", "k_search.hip", "k_screen.hip",
-           "k_lle.hip", "k_bp.hip", "k_backward.hip"]
+           "k_lle.hip", "k_bp.hip", "k_backward.hip", "k_tools.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

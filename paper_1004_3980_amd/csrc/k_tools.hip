@@ -1,0 +1,239 @@
+// Dictionary-construction tools, off the per-image path.
+//
+// Training crops (Section 5, training data generation): every pixel of a
+// training image weighs its first-order gradient (taps [-1, 0, 1] along each
+// axis, replicate border), |dx| + |dy| in FP64 from the fp32 pixels,
+// quantised to q = floor(g 2^20) (saturated at 2^32 - 1, also for non-finite
+// g), so the cumulative distribution is an exact integer sum in any order.
+// A 64-bit draw x picks the first pixel (row-major) whose inclusive
+// cumulative weight exceeds x mod T (T the image's total; x mod (H W) when
+// T = 0); the crop of side S around it has its top-left corner at the centre
+// minus S / 2, clamped inside the image.
+//
+// Hashing quality (Section 4.1, determining r): the entropy in bits of each
+// table's bucket occupancy, -sum_b p_b log2 p_b, p_b = (rows in bucket b) / N,
+// read from the bin directory.
+#include <cmath>
+
+#include "zh_internal.h"
+
+namespace zh {
+
+constexpr int kCdfBlock = 1024;   // pixels per block of cumulative weights
+constexpr int kCdfSub = kCdfBlock / 64;   // sub-blocks of 64 pixels per block
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline unsigned long long wave_incl_scan_u64(unsigned long long v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ inline uint32_t grad_weight(const float* __restrict__ img, int H, int W, int r, int c) {
+    const double dx = (double)img[(int64_t)r * W + min(c + 1, W - 1)] - (double)img[(int64_t)r * W + max(c - 1, 0)];
+    const double dy = (double)img[(int64_t)min(r + 1, H - 1) * W + c] - (double)img[(int64_t)max(r - 1, 0) * W + c];
+    const double s = (fabs(dx) + fabs(dy)) * 1048576.0;
+    return s < 4294967295.0 ? (uint32_t)floor(s) : 0xFFFFFFFFu;
+}
+
+// Sum of the weights of block blockIdx.x of image blockIdx.y (bsum) and of
+// each of its 16 sub-blocks of 64 pixels (ssum). The weights themselves are
+// not stored: the sampler recomputes the 64 of the sub-block it lands in.
+__global__ __launch_bounds__(256) void k_cdf_weights(const float* __restrict__ imgs, int H, int W, int nb,
+                                                     unsigned long long* __restrict__ bsum,
+                                                     unsigned long long* __restrict__ ssum) {
+    __shared__ unsigned long long ws[4];
+    const int HW = H * W;
+    const float* img = imgs + (int64_t)blockIdx.y * HW;
+    const int p0 = blockIdx.x * kCdfBlock;
+    unsigned long long acc = 0;
+    unsigned long long* sub = ssum + ((int64_t)blockIdx.y * nb + blockIdx.x) * kCdfSub;
+#pragma unroll
+    for (int u = 0; u < kCdfBlock / 256; ++u) {
+        const int p = p0 + (int)threadIdx.x + 256 * u;
+        unsigned long long v = 0;
+        if (p < HW) {
+            const int r = p / W;
+            v = grad_weight(img, H, W, r, p - r * W);
+        }
+        // the wave's 64 lanes hold one sub-block (pixels 256 u + 64 w ..)
+        v = wave_sum_u64(v);
+        if (__lane_id() == 0) sub[4 * u + (threadIdx.x >> 6)] = v;
+        acc += v;
+    }
+    if (__lane_id() == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[(int64_t)blockIdx.y * nb + blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// Exclusive prefix of the block sums of image blockIdx.x: bpre[0 .. nb], the
+// last entry the image's total. One workgroup per image, 256 sums a pass.
+__global__ __launch_bounds__(256) void k_cdf_scan(const unsigned long long* __restrict__ bsum, int nb,
+                                                  unsigned long long* __restrict__ bpre) {
+    __shared__ unsigned long long wt[4];
+    const unsigned long long* in = bsum + (int64_t)blockIdx.x * nb;
+    unsigned long long* out = bpre + (int64_t)blockIdx.x * (nb + 1);
+    unsigned long long carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const unsigned long long v = b < nb ? in[b] : 0ull;
+        const unsigned long long incl = wave_incl_scan_u64(v);
+        if (__lane_id() == 63) wt[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        unsigned long long before = carry;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) before += wt[w];
+        if (b < nb) out[b] = before + incl - v;
+        carry += wt[0] + wt[1] + wt[2] + wt[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[nb] = carry;
+}
+
+// One wave per draw: the centre pixel, then the clamped crop corner.
+__global__ __launch_bounds__(256) void k_cdf_sample(const float* __restrict__ imgs,
+                                                    const unsigned long long* __restrict__ bpre,
+                                                    const unsigned long long* __restrict__ ssum, int H, int W, int nb,
+                                                    const unsigned long long* __restrict__ draws, int64_t n_draws,
+                                                    int m, int side, int32_t* __restrict__ corners) {
+    const int lane = __lane_id();
+    const int64_t d = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (d >= n_draws) return;
+    const int64_t img = d / m;
+    const int HW = H * W;
+    const unsigned long long* pre = bpre + img * (nb + 1);
+    const unsigned long long T = pre[nb], x = draws[d];
+    int64_t centre = -1;
+    if (T == 0) {
+        centre = (int64_t)(x % (unsigned long long)HW);
+    } else {
+        const unsigned long long t = x % T;
+        // last block whose exclusive prefix is <= t (pre[0] = 0)
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        unsigned long long tl = t - pre[lo];
+        // the sub-block of 64 pixels holding tl, then the pixel inside it
+        const unsigned long long sv = lane < kCdfSub ? ssum[(img * nb + lo) * kCdfSub + lane] : 0ull;
+        const unsigned long long sincl = wave_incl_scan_u64(sv);
+        const uint64_t shit = __ballot(sincl > tl);
+        const int sb = shit ? __builtin_ctzll(shit) : kCdfSub - 1;
+        tl -= __shfl(sincl - sv, sb);
+        const int p = lo * kCdfBlock + sb * 64 + lane;
+        const float* im = imgs + img * HW;
+        unsigned long long q = 0;
+        if (p < HW) {
+            const int r = p / W;
+            q = grad_weight(im, H, W, r, p - r * W);
+        }
+        const unsigned long long incl = wave_incl_scan_u64(q);
+        const uint64_t hit = __ballot(incl > tl);
+        const int src = hit ? __builtin_ctzll(hit) : 63;
+        centre = (int64_t)lo * kCdfBlock + sb * 64 + src;
+    }
+    if (lane == 0) {
+        const int r = (int)(centre / W), c = (int)(centre - (int64_t)(centre / W) * W);
+        corners[2 * d] = min(max(r - side / 2, 0), H - side);
+        corners[2 * d + 1] = min(max(c - side / 2, 0), W - side);
+    }
+}
+
+// One workgroup per crop.
+__global__ __launch_bounds__(256) void k_crop_cut(const float* __restrict__ imgs, int H, int W, int m, int side,
+                                                  const int32_t* __restrict__ corners, float* __restrict__ crops) {
+    const int64_t d = blockIdx.x;
+    const int ss = side * side;
+    const float* src = imgs + (d / m) * ((int64_t)H * W) + (int64_t)corners[2 * d] * W + corners[2 * d + 1];
+    float* dst = crops + d * ss;
+    for (int e = threadIdx.x; e < ss; e += 256) {
+        const int r = e / side;
+        dst[e] = src[(int64_t)r * W + (e - r * side)];
+    }
+}
+
+int64_t crop_scratch_bytes(int n_img, int H, int W) {
+    const int64_t HW = (int64_t)H * W, nb = (HW + kCdfBlock - 1) / kCdfBlock;
+    return (int64_t)n_img * (8 * nb + 8 * (nb + 1) + 8 * kCdfSub * nb);
+}
+
+hipError_t launch_sample_crops(const float* imgs, int n_img, int H, int W, const uint64_t* draws, int m, int side,
+                               int32_t* corners, float* crops, void* scratch, hipStream_t st) {
+    const int64_t HW = (int64_t)H * W;
+    const int nb = (int)((HW + kCdfBlock - 1) / kCdfBlock);
+    if (n_img < 1 || n_img > 65535 || side < 1 || side > H || side > W || m < 0) return hipErrorInvalidValue;
+    unsigned long long* bsum = static_cast<unsigned long long*>(scratch);
+    unsigned long long* bpre = bsum + (int64_t)n_img * nb;
+    unsigned long long* ssum = bpre + (int64_t)n_img * (nb + 1);
+    hipLaunchKernelGGL(k_cdf_weights, dim3(nb, n_img), dim3(256), 0, st, imgs, H, W, nb, bsum, ssum);
+    hipLaunchKernelGGL(k_cdf_scan, dim3(n_img), dim3(256), 0, st, bsum, nb, bpre);
+    const int64_t nd = (int64_t)n_img * m;
+    if (nd == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_cdf_sample, dim3((unsigned)((nd + 3) / 4)), dim3(256), 0, st, imgs, bpre, ssum, H, W, nb,
+                       reinterpret_cast<const unsigned long long*>(draws), nd, m, side, corners);
+    if (crops)
+        hipLaunchKernelGGL(k_crop_cut, dim3((unsigned)nd), dim3(256), 0, st, imgs, H, W, m, side, corners, crops);
+    return hipGetLastError();
+}
+
+// Entropy partial sums: block blockIdx.x of table blockIdx.y, 256 x 16 slots.
+constexpr int kEntSlots = 4096;
+
+__global__ __launch_bounds__(256) void k_dir_entropy(const Slot* __restrict__ dir, uint64_t cap, double n,
+                                                     int nblk, double* __restrict__ part) {
+    __shared__ double ws[4];
+    const Slot* tab = dir + (uint64_t)blockIdx.y * cap;
+    const uint64_t s0 = (uint64_t)blockIdx.x * kEntSlots;
+    double acc = 0.0;
+    for (int u = 0; u < kEntSlots / 256; ++u) {
+        const uint64_t s = s0 + threadIdx.x + 256 * u;
+        if (s < cap) {
+            const Slot e = tab[s];
+            if (e.key != kEmptyKey && e.count > 0) {
+                const double p = (double)e.count / n;
+                acc -= p * log2(p);
+            }
+        }
+    }
+    acc = wave_sum_f64(acc);
+    if (__lane_id() == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * nblk + blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+// Table blockIdx.x's partials: lane i adds blocks i, i + 64, ... in order,
+// then a fixed-order wave sum.
+__global__ __launch_bounds__(64) void k_entropy_sum(const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ out) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)blockIdx.x * nblk + b];
+    s = wave_sum_f64(s);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+int64_t entropy_scratch_bytes(int L, uint64_t cap) {
+    const int64_t nblk = (int64_t)((cap + kEntSlots - 1) / kEntSlots);
+    return 8 * ((int64_t)L * nblk + L);
+}
+
+hipError_t launch_table_entropy(const Slot* dir, int L, uint64_t cap, int64_t n, void* scratch, double* out,
+                                hipStream_t st) {
+    const int nblk = (int)((cap + kEntSlots - 1) / kEntSlots);
+    if (L < 1 || n < 1 || nblk < 1) return hipErrorInvalidValue;
+    double* part = static_cast<double*>(scratch);
+    hipLaunchKernelGGL(k_dir_entropy, dim3(nblk, L), dim3(256), 0, st, dir, cap, (double)n, nblk, part);
+    hipLaunchKernelGGL(k_entropy_sum, dim3(L), dim3(64), 0, st, part, nblk, out);
+    return hipGetLastError();
+}
+
+}  // namespace zh

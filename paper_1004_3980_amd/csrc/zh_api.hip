@@ -91,6 +91,7 @@ struct zh_ctx {
     Buf qrot;                     // [Q, 64] rotated queries of the screen
     Buf bwd_gw;                   // [Q, 8] FP64 scratch of the lambda adjoint
     Buf bwd_part;                 // partial row gradients of the dictionary-gradient passes
+    Buf tools;                    // scratch of the training-crop sampler and the entropy diagnostic
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -450,7 +451,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -494,6 +495,35 @@ zh_status zh_make_dictionary(zh_ctx* c, const float* hr, int n_img, int H, int W
     HIPCHK(c, launch_degrade(hr, n_img, H, W, scale, gauss_taps(sigma), lrs, c->stream));
     HIPCHK(c, launch_gradient_maps(lrs, n_img, h, w, maps, c->stream));
     HIPCHK(c, launch_dict_cut(hr, lrs, maps, H, W, scale, pos, n, mode, feat, resid, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_sample_crops(zh_ctx* c, const float* imgs, int n_img, int H, int W, const uint64_t* draws, int m,
+                          int side, int32_t* corners, float* crops) {
+    if (!c) return ZH_EINVAL;
+    if (!imgs || n_img < 1 || n_img > 65535 || H < 1 || W < 1 || (int64_t)H * W >= (1ll << 31) || m < 0 ||
+        (m > 0 && (!draws || !corners)) || side < 1 || side > H || side > W ||
+        (int64_t)n_img * m >= (1ll << 31))
+        return fail(c, ZH_EINVAL, "zh_sample_crops: bad arguments");
+    if (m == 0) return ZH_OK;
+    TRY(set_device(c));
+    TRY(ensure(c, c->tools, (size_t)crop_scratch_bytes(n_img, H, W)));
+    HIPCHK(c, launch_sample_crops(imgs, n_img, H, W, draws, m, side, corners, crops, c->tools.p, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_table_entropy(zh_ctx* c, int scale, double* entropy, int capacity) {
+    if (!c) return ZH_EINVAL;
+    if (scale < 1 || scale > kMaxScale || !c->dicts[scale].valid)
+        return fail(c, ZH_ESTATE, "zh_table_entropy: no tables for scale %d", scale);
+    Dict& d = c->dicts[scale];
+    if (!entropy || capacity < d.L) return fail(c, ZH_EINVAL, "zh_table_entropy: room for %d tables needed", d.L);
+    TRY(set_device(c));
+    TRY(ensure(c, c->tools, (size_t)entropy_scratch_bytes(d.L, d.cap)));
+    double* out = reinterpret_cast<double*>(static_cast<char*>(c->tools.p) + entropy_scratch_bytes(d.L, d.cap)) - d.L;
+    HIPCHK(c, launch_table_entropy(P<Slot>(d.dir), d.L, d.cap, d.n, c->tools.p, out, c->stream));
+    HIPCHK(c, hipMemcpyAsync(entropy, out, sizeof(double) * d.L, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return ZH_OK;
 }
 

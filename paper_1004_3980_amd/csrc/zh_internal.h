@@ -184,6 +184,13 @@ hipError_t lle_init();  // once per device, before any launch_lle
 hipError_t launch_gram(const LleArgs& a, void* gram, int gram_fp64, hipStream_t st);
 hipError_t launch_lle_solve(const LleArgs& a, const void* gram, int gram_fp64, hipStream_t st);
 hipError_t launch_lle(const LleArgs& a, hipStream_t st);
+// dictionary-construction tools (k_tools.hip)
+int64_t crop_scratch_bytes(int n_img, int H, int W);
+hipError_t launch_sample_crops(const float* imgs, int n_img, int H, int W, const uint64_t* draws, int m, int side,
+                               int32_t* corners, float* crops, void* scratch, hipStream_t st);
+int64_t entropy_scratch_bytes(int L, uint64_t cap);
+hipError_t launch_table_entropy(const Slot* dir, int L, uint64_t cap, int64_t n, void* scratch, double* out,
+                                hipStream_t st);
 hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m,
                         const float* w, const double* mu, const float* resid, float* xhat,
                         hipStream_t st);

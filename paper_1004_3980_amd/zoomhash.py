@@ -71,6 +71,8 @@ SIGNATURES = {
     "zh_degrade": [_V, _V, _I, _I, _I, _I, _F, _V],
     "zh_make_dictionary": [_V, _V, _I, _I, _I, _V, _I64, _I, _F, _I, _V, _V],
     "zh_features": [_V, _V, _I, _I, _I, _V, _V],
+    "zh_sample_crops": [_V, _V, _I, _I, _I, _V, _I, _I, _V, _V],
+    "zh_table_entropy": [_V, _I, _V, _I],
     "zh_build_tables": [_V, ctypes.POINTER(zh_dictionary), _I, _I, _F, _U64],
     "zh_get_hash_params": [_V, _I, _V, _V],
     "zh_hash": [_V, _I, _V, _I64, _V, _V],
@@ -167,6 +169,15 @@ class Context:
     def make_dictionary(self, hr, n_img, H, W, pos, n, scale, sigma, feat_mode, feat, resid):
         self._chk(self.lib.zh_make_dictionary(self.h, _ptr(hr), n_img, H, W, _ptr(pos), n, scale,
                                               sigma, feat_mode, _ptr(feat), _ptr(resid)))
+
+    def sample_crops(self, imgs, n_img, H, W, draws, m, side, corners, crops=None):
+        self._chk(self.lib.zh_sample_crops(self.h, _ptr(imgs), n_img, H, W, _ptr(draws), m, side,
+                                           _ptr(corners), _ptr(crops) if crops is not None else None))
+
+    def table_entropy(self, scale, L):
+        out = np.zeros(L, dtype=np.float64)
+        self._chk(self.lib.zh_table_entropy(self.h, scale, out.ctypes.data_as(ctypes.c_void_p), L))
+        return out
 
     def features(self, lr, h, w, feat_mode, feat, mu=None):
         self._chk(self.lib.zh_features(self.h, _ptr(lr), h, w, feat_mode, _ptr(feat), _ptr(mu)))
