@@ -20,6 +20,29 @@ def knn(qfeat: np.ndarray, dict_feat: np.ndarray, cand: np.ndarray, K: int):
     return cand[order], d[order]
 
 
+def l1dist(qfeat: np.ndarray, dict_feat: np.ndarray, cand: np.ndarray) -> np.ndarray:
+    """l1 distance of the query to each candidate row: sum over the
+    coordinates, in index order, of |q_i - x_i|, in FP64 from the fp32
+    values."""
+    q = np.asarray(qfeat, dtype=np.float32).astype(np.float64)
+    X = np.asarray(dict_feat[cand], dtype=np.float32).astype(np.float64)
+    acc = np.zeros(len(cand), dtype=np.float64)
+    for i in range(q.shape[0]):
+        acc = acc + np.abs(q[i] - X[:, i])
+    return acc
+
+
+def knn_l1(qfeat: np.ndarray, dict_feat: np.ndarray, cand: np.ndarray, K: int):
+    """K nearest candidates under l1, the metric the Cauchy hash is sensitive
+    to (Section 4.1: the 1-stable distribution preserves l1 distances):
+    the first min(K, |C|) in (l1 distance, ID) order."""
+    if len(cand) == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.float64)
+    d = l1dist(qfeat, dict_feat, cand)
+    order = np.lexsort((cand, d))[:K]
+    return cand[order], d[order]
+
+
 def lle_weights(qfeat: np.ndarray, nbr_feat: np.ndarray, lam: float) -> np.ndarray:
     """Weights minimising ||y - sum_m w_m y_m||^2 subject to sum_m w_m = 1
     (Eq. LinSys), regularised: with Z = y - Y (rows), G = Z Z^T,

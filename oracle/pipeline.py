@@ -53,7 +53,10 @@ class QueryResult:
 
 
 def query(pre: Prepared, lr: np.ndarray, K: int, lam: float, pos=None,
-          synthesize: bool = True, cap: int = 0) -> QueryResult:
+          synthesize: bool = True, cap: int = 0, metric: str = "l2") -> QueryResult:
+    """metric "l2": neighbours by squared l2 distance (the LLE objective);
+    "l1": by l1 distance (the hash's metric); the LLE weights are the same
+    l2 solve for both."""
     mode = pre.dictionary.mode
     lr = np.asarray(lr, dtype=np.float32)
     if pos is None:
@@ -72,7 +75,7 @@ def query(pre: Prepared, lr: np.ndarray, K: int, lam: float, pos=None,
     patches = [None] * Q
     D = pre.dictionary
     for q in range(Q):
-        nid, nd = lle.knn(feat[q], D.feat, cand[q], K)
+        nid, nd = (lle.knn_l1 if metric == "l1" else lle.knn)(feat[q], D.feat, cand[q], K)
         mq = len(nid)
         m[q] = mq
         ids[q, :mq] = nid

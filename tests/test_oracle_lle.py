@@ -120,3 +120,39 @@ def test_full_image_self_reproduction(mode):
     out, cnt = pipeline.reconstruct(qr, lr, 2)
     assert cnt.min() > 0
     assert np.abs(out - hr.astype(np.float64)).max() < 1e-6
+
+
+def test_l1_distance_pins():
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(41)
+    X = rng.standard_normal((300, 100)).astype(np.float32)
+    q = rng.standard_normal(100).astype(np.float32)
+    cand = np.arange(0, 300, 3)
+    d = lle.l1dist(q, X, cand)
+    ref = cdist(q[None].astype(np.float64), X[cand].astype(np.float64), "cityblock")[0]
+    assert np.allclose(d, ref, rtol=1e-13, atol=0)
+    # integer-valued features: every partial sum exact, so any order agrees exactly
+    Xi = rng.integers(-50, 50, (40, 25)).astype(np.float32)
+    qi = rng.integers(-50, 50, 25).astype(np.float32)
+    assert np.array_equal(lle.l1dist(qi, Xi, np.arange(40)), np.abs(Xi - qi).sum(axis=1).astype(np.float64))
+    # l1 >= l2, and the l1 distance ignores the order of the coordinates
+    l2 = np.sqrt(((X[cand].astype(np.float64) - q) ** 2).sum(axis=1))
+    assert np.all(d >= l2 * (1 - 1e-12))
+    perm = rng.permutation(100)
+    assert np.allclose(lle.l1dist(q[perm], X[:, perm], cand), d, rtol=1e-13)
+
+
+def test_knn_l1_brute_force_and_ties():
+    rng = np.random.default_rng(42)
+    X = rng.integers(0, 4, (60, 6)).astype(np.float32)       # many ties
+    q = rng.integers(0, 4, 6).astype(np.float32)
+    cand = np.sort(rng.choice(60, 35, replace=False))
+    ids, d = lle.knn_l1(q, X, cand, 7)
+    ref = sorted((float(np.abs(X[i] - q).sum()), int(i)) for i in cand)[:7]
+    assert [int(i) for i in ids] == [i for _, i in ref]
+    assert np.array_equal(d, np.array([v for v, _ in ref]))
+    # a dictionary row queried against itself comes first at distance 0
+    ids0, d0 = lle.knn_l1(X[cand[5]], X, cand, 3)
+    assert d0[0] == 0.0 and (ids0[0] == cand[5] or np.array_equal(X[ids0[0]], X[cand[5]]))
+    # fewer candidates than K: all of them
+    assert len(lle.knn_l1(q, X, cand[:4], 7)[0]) == 4
