@@ -109,6 +109,8 @@ def main():
                     help="screened/exact: the 1024^2 workload (the headline line); batched: 64 images "
                          "at x2/x3 in one captured graph against per-image launches; diff: forward and "
                          "backward of the differentiation workload")
+    ap.add_argument("--metric", choices=["l2", "l1"], default="l2",
+                    help="screened/exact: neighbours by squared l2 (the path) or re-ranked under l1")
     ap.add_argument("--scale", type=int, default=0,
                     help="screened/exact: run the workload at this zoom factor (1..4) instead of its own")
     ap.add_argument("--crop", type=int, default=256, help="LR crop side for quality and the CPU leg")
@@ -155,14 +157,14 @@ def main():
     def timed(form, steps, warmup, stages=None):
         set_form(form)
         for _ in range(warmup):
-            g.zoom()
+            g.zoom(metric=args.metric)
         torch.cuda.synchronize()
         g.ctx.get_timing()
         g.ctx.set_timing(True, stages)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            g.zoom()
+            g.zoom(metric=args.metric)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         g.ctx.set_timing(False)
@@ -187,7 +189,7 @@ def main():
     dom = max(("hash", "search", "lle", "synth", "blend"), key=lambda k: ms_stage[k])
     sb = search_bytes(res["ncand"], res["nsurv"], wl, 4 if args.form == "screened" else 8)
     ach = sb / (ms_stage["search"] * 1e-3) / 1e9
-    traffic = traffic_from_profile(args.form) if own_scale else None
+    traffic = traffic_from_profile(args.form) if own_scale and args.metric == "l2" else None
     roof = {"bound": "hbm", "kernel": "k_search", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes": sb, "launch_ms": round(ms_stage["search"], 4),
@@ -277,7 +279,8 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.test_h}x{wl.test_w} LR x{wl.scale}, "
                                f"{wl.n_dict}-pair dictionary (4-gradient features, D={wl.D}), "
                                f"L={wl.L} k={wl.k} w={wl.w:g} K={wl.K}, early stop {wl.cap}, "
-                               f"form {args.form}" + (f" (bf16 screen to {wl.rerank})" if args.form == "screened" else ""),
+                               f"form {args.form}" + (f" (bf16 screen to {wl.rerank})" if args.form == "screened" else "")
+                               + (", neighbours re-ranked under l1 (zh_knn_l1)" if args.metric == "l1" else ""),
                    "patches_per_step": Q, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

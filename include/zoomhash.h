@@ -184,6 +184,16 @@ zh_status zh_set_query_opts(zh_ctx* ctx, const zh_query_opts* opts);
  * a patch with fewer than K candidates keeps all of them. */
 zh_status zh_query(zh_ctx* ctx, const float* lr, int h, int w, int scale, int K);
 
+/* Re-rank under l1 (Section 4.1: the Cauchy hash is sensitive to l1
+ * distances): replace the neighbours of the last zh_query by the first
+ * min(K, M) of its early-stop candidates in (l1 distance, ID) order, the
+ * distance summed over the coordinates in index order in FP64 from the fp32
+ * features. zh_get_results then reports l1 distances (rounded to fp32) in
+ * place of squared l2; zh_lle_weights and zh_reconstruct use the new
+ * neighbours. Needs the early stop (query option cap > 0, else
+ * ZH_EUNSUPPORTED); runs the candidate search again. */
+zh_status zh_knn_l1(zh_ctx* ctx);
+
 /* LLE weights of every patch (Section 4.2, Eq. LinSys): minimise
  * ||y - sum_m w_m y_m||^2 subject to sum_m w_m = 1, regularised by adding
  * lambda * trace(G) to the diagonal of the Gram matrix G (lambda > 0). */

@@ -237,3 +237,154 @@ hipError_t launch_table_entropy(const Slot* dir, int L, uint64_t cap, int64_t n,
 }
 
 }  // namespace zh
+
+namespace zh {
+
+// K nearest candidates under l1 (Section 4.1: the Cauchy hash is sensitive to
+// l1 distances). One wave (one workgroup) per patch. Candidates go in chunks
+// of 16: the wave stages their feature rows in LDS (the chunk's rows
+// flattened over the lanes, 16-byte loads when D is a multiple of 4; odd row
+// stride in LDS: no bank conflicts), then lane j sums |q_i - x_i| of candidate j
+// over the coordinates in index order in FP64, so every distance is the
+// oracle's to the bit. Then K rounds of a wave minimum over (distance, ID)
+// pick the neighbours in order.
+constexpr int kL1Chunk = 16;    // candidates staged at a time (6.5 KB of LDS at D = 100)
+constexpr int kL1PerLane = 16;  // chunks: at most 256 candidates a patch
+constexpr int kL1MaxD = 128;
+
+// DT: the feature dimension at compile time (0: D at run time, up to 128).
+template <int DT>
+__global__ __launch_bounds__(64) void k_knn_l1(int Q, int Drt, int K, int cap, const float* __restrict__ qfeat,
+                                               const float* __restrict__ xf, const int32_t* __restrict__ cand,
+                                               const int32_t* __restrict__ ncand, int32_t* __restrict__ out_ids,
+                                               float* __restrict__ out_d, int32_t* __restrict__ out_m) {
+    constexpr int kSt = (DT ? DT : kL1MaxD) | 1;
+    __shared__ double sq[DT ? DT : kL1MaxD];
+    __shared__ float sx[kL1Chunk * kSt];
+    __shared__ int sid[kL1Chunk];
+    const int D = DT ? DT : Drt;
+    const int lane = threadIdx.x;
+    const int q = blockIdx.x;
+    const int M = min(ncand[q], cap);
+    const int st = DT ? kSt : (D | 1);
+    for (int i = lane; i < D; i += 64) sq[i] = (double)qfeat[(int64_t)q * D + i];
+    double d[kL1PerLane];
+    int id[kL1PerLane];
+#pragma unroll
+    for (int u = 0; u < kL1PerLane; ++u) {
+        d[u] = INFINITY;
+        id[u] = 0x7FFFFFFF;
+        const int c0 = kL1Chunk * u;
+        if (c0 < M) {
+            const int nc = min(kL1Chunk, M - c0);
+            const int myid = lane < nc ? cand[(int64_t)q * cap + c0 + lane] : 0;
+            __syncthreads();
+            if (lane < kL1Chunk) sid[lane] = myid;
+            __syncthreads();
+            // the chunk's rows, flattened over the wave, eight loads in flight a lane
+            if ((D & 3) == 0) {
+                const int D4 = D >> 2, n4 = nc * D4;
+                const float4* x4 = reinterpret_cast<const float4*>(xf);
+                for (int e0 = 0; e0 < n4; e0 += 64 * 8) {
+                    float4 v[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int e = e0 + lane + 64 * t;
+                        if (e < n4) {
+                            const int c = e / D4;
+                            v[t] = x4[(int64_t)sid[c] * D4 + (e - c * D4)];
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int e = e0 + lane + 64 * t;
+                        if (e < n4) {
+                            const int c = e / D4;
+                            float* dst = sx + c * st + 4 * (e - c * D4);
+                            dst[0] = v[t].x;
+                            dst[1] = v[t].y;
+                            dst[2] = v[t].z;
+                            dst[3] = v[t].w;
+                        }
+                    }
+                }
+            } else {
+                const int n1 = nc * D;
+                for (int e0 = 0; e0 < n1; e0 += 64 * 8) {
+                    float v[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int e = e0 + lane + 64 * t;
+                        if (e < n1) {
+                            const int c = e / D;
+                            v[t] = xf[(int64_t)sid[c] * D + (e - c * D)];
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int e = e0 + lane + 64 * t;
+                        if (e < n1) {
+                            const int c = e / D;
+                            sx[c * st + (e - c * D)] = v[t];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (lane < nc) {
+                double acc = 0.0;
+#pragma unroll 20
+                for (int i = 0; i < D; ++i) acc = acc + fabs(sq[i] - (double)sx[lane * st + i]);
+                d[u] = acc;
+                id[u] = myid;
+            }
+        }
+    }
+    const int m = min(K, M);
+    for (int k = 0; k < m; ++k) {
+        // this lane's smallest (distance, ID), then the wave's
+        double bd = d[0];
+        int bi = id[0];
+#pragma unroll
+        for (int u = 1; u < kL1PerLane; ++u)
+            if (d[u] < bd || (d[u] == bd && id[u] < bi)) {
+                bd = d[u];
+                bi = id[u];
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double od = __shfl_xor(bd, o);
+            const int oi = __shfl_xor(bi, o);
+            if (od < bd || (od == bd && oi < bi)) {
+                bd = od;
+                bi = oi;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kL1PerLane; ++u)
+            if (id[u] == bi) {
+                d[u] = INFINITY;
+                id[u] = 0x7FFFFFFF;
+            }
+        if (lane == 0) {
+            out_ids[(int64_t)q * K + k] = bi;
+            out_d[(int64_t)q * K + k] = (float)bd;
+        }
+    }
+    if (lane == 0) out_m[q] = m;
+}
+
+hipError_t launch_knn_l1(int Q, int D, int K, int cap, const float* qfeat, const float* xf, const int32_t* cand,
+                         const int32_t* ncand, int32_t* ids, float* d, int32_t* m, hipStream_t st) {
+    if (Q == 0) return hipSuccess;
+    if (cap < 1 || cap > kL1Chunk * kL1PerLane || K < 1 || K > kMaxK || D < 1 || D > kL1MaxD) return hipErrorInvalidValue;
+    if (D == 100)
+        hipLaunchKernelGGL(k_knn_l1<100>, dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m);
+    else if (D == 25)
+        hipLaunchKernelGGL(k_knn_l1<25>, dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m);
+    else
+        hipLaunchKernelGGL(k_knn_l1<0>, dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m);
+    return hipGetLastError();
+}
+
+}  // namespace zh

@@ -92,6 +92,7 @@ struct zh_ctx {
     Buf bwd_gw;                   // [Q, 8] FP64 scratch of the lambda adjoint
     Buf bwd_part;                 // partial row gradients of the dictionary-gradient passes
     Buf tools;                    // scratch of the training-crop sampler and the entropy diagnostic
+    Buf l1cand;                   // [Q, cap] candidate lists of the l1 re-rank
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -451,7 +452,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools, &c->l1cand};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -1414,6 +1415,28 @@ zh_status zh_candidates(zh_ctx* c, int32_t cap_per_query, int32_t* counts, int32
     TRY(run_search(c, c->dicts[c->qscale], ids, cap_per_query));
     HIPCHK(c, hipMemcpyAsync(counts, c->ncand.p, (size_t)c->Q * 4, hipMemcpyDeviceToDevice, c->stream));
     if (c->stage > 1) c->stage = 1;
+    return ZH_OK;
+}
+
+zh_status zh_knn_l1(zh_ctx* c) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_knn_l1 before zh_query");
+    const int cap = c->opts.cap;
+    if (cap < 1) return fail(c, ZH_EUNSUPPORTED, "zh_knn_l1 needs the early stop (query option cap > 0)");
+    TRY(set_device(c));
+    Dict& d = c->dicts[c->qscale];
+    TRY(ensure(c, c->l1cand, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1) * cap));
+    TRY(clear_counters(c));
+    // the candidate lists of the last query (the search runs again and dumps them)
+    TRY(run_search(c, d, P<int32_t>(c->l1cand), cap));
+    {
+        StageTimer t(c, ZH_T_SEARCH);
+        HIPCHK(c, launch_knn_l1((int)c->Q, d.D, c->qK, cap, P<float>(c->qfeat), P<float>(d.xf), P<int32_t>(c->l1cand),
+                                P<int32_t>(c->ncand), P<int32_t>(c->ids), P<float>(c->d2), P<int32_t>(c->m),
+                                c->stream));
+    }
+    c->gram_ready = false;   // the Gram matrices of the new neighbours are formed by zh_lle_weights
+    c->stage = 1;
     return ZH_OK;
 }
 

@@ -63,12 +63,15 @@ class GpuWorkload:
         self._cap = self.wl.cap if cap is None else cap
         self.ctx.set_query_opts(cap=self._cap, rerank=rerank, proj=proj, lle_fp64=lle_fp64)
 
-    def zoom(self, lr=None, K=None, lam=None, out=None):
-        """hash + K-NN + LLE + blend for the test image; returns the HR image."""
+    def zoom(self, lr=None, K=None, lam=None, out=None, metric="l2"):
+        """hash + K-NN + LLE + blend for the test image; returns the HR image.
+        metric "l1": neighbours re-ranked under l1 (needs the early stop)."""
         wl = self.wl
         lr = self.lr if lr is None else lr
         out = self.hr_out if out is None else out
         self.ctx.query(lr, lr.shape[0], lr.shape[1], wl.scale, wl.K if K is None else K)
+        if metric == "l1":
+            self.ctx.knn_l1()
         self.ctx.lle_weights(wl.lam if lam is None else lam)
         self.ctx.reconstruct(out)
         return out
