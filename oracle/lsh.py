@@ -180,6 +180,20 @@ class Tables:
         return out, (hi - lo)
 
 
+def candidates_t(tables: Tables, qkeys: np.ndarray, t: int):
+    """The IDs present in at least t of the L tables' bins of each query
+    (Section 4.1: a training patch is a match when it shares the query's
+    bucket in at least t out of L tables), ascending. t = 1 is the union."""
+    lo, hi = tables.bucket_ranges(qkeys)
+    out = []
+    for q in range(qkeys.shape[0]):
+        parts = [tables.sorted_ids[l][lo[q, l]:hi[q, l]] for l in range(tables.L)]
+        ids = np.concatenate(parts) if parts else np.zeros(0, np.int64)
+        u, c = np.unique(ids, return_counts=True)
+        out.append(u[c >= t])
+    return out
+
+
 def build_tables(feat: np.ndarray, alpha: np.ndarray, beta: np.ndarray, w: float, L: int,
                  k: int) -> Tables:
     return Tables(bucket_keys(codes(feat, alpha, beta, w), L, k))

@@ -234,3 +234,30 @@ def test_recall_is_monotone_in_L_and_nested():
         assert rec >= prev_r
         prev_c, prev_r = cand, rec
     assert prev_r > 0.9
+
+
+def test_t_of_l_candidates_pins():
+    rng = np.random.default_rng(51)
+    N, L, Q = 400, 6, 30
+    keys = rng.integers(0, 5, (N, L)).astype(np.uint64)       # few, large buckets
+    tables = lsh.Tables(keys)
+    qkeys = rng.integers(0, 5, (Q, L)).astype(np.uint64)
+    union, _ = tables.candidates(qkeys, 0)
+    c1 = lsh.candidates_t(tables, qkeys, 1)
+    assert all(np.array_equal(a, b) for a, b in zip(c1, union))
+    prev = c1
+    for t in range(2, L + 1):
+        ct = lsh.candidates_t(tables, qkeys, t)
+        assert all(np.all(np.isin(a, b)) for a, b in zip(ct, prev))      # nested
+        prev = ct
+    # t = L: the intersection of the L bins
+    for q in range(Q):
+        inter = np.arange(N)
+        for l in range(L):
+            inter = np.intersect1d(inter, np.nonzero(keys[:, l] == qkeys[q, l])[0])
+        assert np.array_equal(prev[q], inter)
+    # brute force at t = 3
+    c3 = lsh.candidates_t(tables, qkeys, 3)
+    for q in range(Q):
+        hits = (keys == qkeys[q]).sum(axis=1)
+        assert np.array_equal(c3[q], np.nonzero(hits >= 3)[0])
