@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="precision")
-    ap.add_argument("--form", choices=["screened", "exact", "batched", "diff", "tools"], default="screened",
+    ap.add_argument("--form", choices=["screened", "exact", "batched", "diff", "tools", "tofl"], default="screened",
                     help="screened/exact: the 1024^2 workload (the headline line); batched: 64 images "
                          "at x2/x3 in one captured graph against per-image launches; diff: forward and "
                          "backward of the differentiation workload")
@@ -138,6 +138,8 @@ def main():
         return bench_diff(args)
     if args.form == "tools":
         return bench_tools(args)
+    if args.form == "tofl":
+        return bench_tofl(args)
     wl = synthdata.WORKLOADS[args.workload]
     own_scale = args.scale in (0, wl.scale)
     if not own_scale:
@@ -294,6 +296,73 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["extra"]["copy_probe_bytes"] = n * 4
+    print(json.dumps(out), flush=True)
+
+
+def bench_tofl(args):
+    """The paper's run-time axis on the 256^2 workload of the differentiation
+    form (256^2 LR, L = 16, k = 16, w = 32): the similarity checks per LR
+    patch (distinct candidates) against the dictionary size N, with and
+    without the early stop at 3L, and the t-of-L criterion (t = 1..4) at
+    N = 200k."""
+    import torch
+    import synthdata
+    from paper_1004_3980_amd import zoomhash as zb
+    from paper_1004_3980_amd.pipeline import GpuWorkload
+    base = synthdata.WORKLOADS["diff"]
+    ctx = zb.Context(0)
+    curve, tofl = [], []
+    for N in (25_000, 50_000, 100_000, 200_000):
+        wl = synthdata.scaled(base, n_dict=N)
+        log(f"[bench] tofl: tables over {N} pairs")
+        g = GpuWorkload(wl, ctx=ctx)
+        for cap in (0, 3 * wl.L):
+            g.set_mode(cap=cap, rerank=0, proj=1, lle_fp64=1)
+            for _ in range(args.warmup):
+                g.zoom()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                g.zoom()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            if cap > 0:
+                nc = g.results()["ncand"].astype(np.float64)
+            else:
+                # distinct IDs of the union, counted without a size limit
+                cnt = torch.empty(g.Q, dtype=torch.int32, device="cuda")
+                one = torch.empty((g.Q, 1), dtype=torch.int32, device="cuda")
+                g.ctx.candidates_t(1, 1, cnt, one)
+                nc = cnt.cpu().numpy().astype(np.float64)
+            curve.append({"N": N, "early_stop": cap, "similarity_checks_per_patch": round(float(nc.mean()), 2),
+                          "fewer_than_exhaustive": round(N / max(1e-9, float(nc.mean())), 1),
+                          "ms_per_step": round(ms, 3), "patches": g.Q})
+        if N == 200_000:
+            g.set_mode(cap=0, rerank=0, proj=1, lle_fp64=1)
+            g.zoom()
+            Q = g.Q
+            for t in (1, 2, 3, 4):
+                cap_q = 4096
+                counts = torch.empty(Q, dtype=torch.int32, device="cuda")
+                ids = torch.empty((Q, cap_q), dtype=torch.int32, device="cuda")
+                g.ctx.candidates_t(t, cap_q, counts, ids)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    g.ctx.candidates_t(t, cap_q, counts, ids)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / args.steps
+                c = counts.cpu().numpy().astype(np.float64)
+                tofl.append({"t": t, "mean_candidates": round(float(c.mean()), 2),
+                             "patches_without_candidates": int((c == 0).sum()), "ms_per_call": round(ms, 3)})
+    last = [r for r in curve if r["N"] == 200_000 and r["early_stop"] > 0][0]
+    out = {"metric": "similarity checks per LR patch vs dictionary size (256^2 LR, L=16, w=32)",
+           "value": last["fewer_than_exhaustive"], "unit": "x fewer checks than exhaustive at N=200k",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": last["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "diff: 256x256 LR x2, N in {25k, 50k, 100k, 200k} pairs, L=16 k=16 w=32 K=5; "
+                                  "t-of-L at N=200k", "parallelism": "single GPU"},
+           "roofline": None, "cpu_baseline": None, "extra": {"curve": curve, "t_of_L": tofl}}
     print(json.dumps(out), flush=True)
 
 

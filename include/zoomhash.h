@@ -184,6 +184,17 @@ zh_status zh_set_query_opts(zh_ctx* ctx, const zh_query_opts* opts);
  * a patch with fewer than K candidates keeps all of them. */
 zh_status zh_query(zh_ctx* ctx, const float* lr, int h, int w, int scale, int K);
 
+/* The t-of-L candidate criterion (Section 4.1: a training patch matches
+ * when it shares the query's bucket in at least t of the L tables) over the
+ * bins of the last zh_query: counts[Q] (device) the number of such IDs of
+ * each patch and ids[Q, cap_per_query] (device) the first cap_per_query of
+ * them in table-walk order (bins in table order, IDs ascending in a bin,
+ * each ID at the first table that holds it); entries past that are
+ * untouched. 1 <= t <= L; t = 1 is the union of zh_candidates without a cap.
+ * Leaves the neighbours of the query unchanged. */
+zh_status zh_candidates_t(zh_ctx* ctx, int t, int32_t cap_per_query, int32_t* counts,
+                          int32_t* ids);
+
 /* Re-rank under l1 (Section 4.1: the Cauchy hash is sensitive to l1
  * distances): replace the neighbours of the last zh_query by the first
  * min(K, M) of its early-stop candidates in (l1 distance, ID) order, the

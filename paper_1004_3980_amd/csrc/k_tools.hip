@@ -388,3 +388,78 @@ hipError_t launch_knn_l1(int Q, int D, int K, int cap, const float* qfeat, const
 }
 
 }  // namespace zh
+
+namespace zh {
+
+// t-of-L candidates (Section 4.1: a training patch matches when it shares the
+// query's bucket in at least t of the L tables). One wave per patch; the
+// patch's L bins (sorted by ID) are walked in table order, 64 entries at a
+// time. An entry x of bin l is kept at its first table only (no earlier bin
+// holds it) and counted in the later ones, both by binary search; IDs with
+// at least t hits are written in walk order (the set is what is defined).
+__global__ __launch_bounds__(256) void k_cand_t(int Q, int L, int64_t N, int t, const uint2* __restrict__ bins,
+                                                const uint32_t* __restrict__ tids, int cap,
+                                                int32_t* __restrict__ counts, int32_t* __restrict__ ids) {
+    __shared__ uint32_t s_off[4][64], s_cnt[4][64];
+    __shared__ int64_t s_st[4][64];
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    const int q = blockIdx.x * 4 + wv;
+    if (q >= Q) return;
+    const uint2 b = lane < L ? bins[(int64_t)lane * Q + q] : make_uint2(0u, 0u);
+    int64_t incl = b.y;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    s_off[wv][lane] = b.x;
+    s_cnt[wv][lane] = b.y;
+    s_st[wv][lane] = incl - b.y;
+    const int64_t S = __shfl(incl, 63);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    auto in_bin = [&](int l, uint32_t x) {
+        const uint32_t* p = tids + (int64_t)l * N + s_off[wv][l];
+        uint32_t lo = 0, hi = s_cnt[wv][l];
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (p[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo < s_cnt[wv][l] && p[lo] == x;
+    };
+    int64_t kept = 0;
+    for (int64_t e0 = 0; e0 < S; e0 += 64) {
+        const int64_t e = e0 + lane;
+        bool keep = false;
+        uint32_t x = 0;
+        if (e < S) {
+            int l = 0;
+            while (l + 1 < L && s_st[wv][l + 1] <= e) ++l;
+            x = tids[(int64_t)l * N + s_off[wv][l] + (e - s_st[wv][l])];
+            bool first = true;
+            for (int j = 0; j < l && first; ++j) first = !in_bin(j, x);
+            if (first) {
+                int hits = 1;
+                for (int j = l + 1; j < L && hits < t; ++j) hits += in_bin(j, x) ? 1 : 0;
+                keep = hits >= t;
+            }
+        }
+        const uint64_t mask = __ballot(keep);
+        const int64_t pos = kept + __popcll(mask & lanemask_lt());
+        if (keep && pos < cap) ids[(int64_t)q * cap + pos] = (int32_t)x;
+        kept += __popcll(mask);
+    }
+    if (lane == 0) counts[q] = (int32_t)kept;
+}
+
+hipError_t launch_cand_t(int Q, int L, int64_t N, int t, const uint2* bins, const uint32_t* tids, int cap,
+                         int32_t* counts, int32_t* ids, hipStream_t st) {
+    if (Q == 0) return hipSuccess;
+    if (L < 1 || L > 64 || t < 1 || t > L || cap < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cand_t, dim3((Q + 3) / 4), dim3(256), 0, st, Q, L, N, t, bins, tids, cap, counts, ids);
+    return hipGetLastError();
+}
+
+}  // namespace zh

@@ -1418,6 +1418,18 @@ zh_status zh_candidates(zh_ctx* c, int32_t cap_per_query, int32_t* counts, int32
     return ZH_OK;
 }
 
+zh_status zh_candidates_t(zh_ctx* c, int t, int32_t cap_per_query, int32_t* counts, int32_t* ids) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_candidates_t before zh_query");
+    Dict& d = c->dicts[c->qscale];
+    if (t < 1 || t > d.L || cap_per_query < 1 || !counts || !ids)
+        return fail(c, ZH_EINVAL, "zh_candidates_t: need 1 <= t <= L = %d, cap_per_query >= 1", d.L);
+    TRY(set_device(c));
+    HIPCHK(c, launch_cand_t((int)c->Q, d.L, d.n, t, P<uint2>(c->qbins), P<uint32_t>(d.tids), cap_per_query, counts,
+                            ids, c->stream));
+    return ZH_OK;
+}
+
 zh_status zh_knn_l1(zh_ctx* c) {
     if (!c) return ZH_EINVAL;
     if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_knn_l1 before zh_query");

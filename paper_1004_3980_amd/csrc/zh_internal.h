@@ -190,6 +190,8 @@ hipError_t launch_sample_crops(const float* imgs, int n_img, int H, int W, const
                                int32_t* corners, float* crops, void* scratch, hipStream_t st);
 hipError_t launch_knn_l1(int Q, int D, int K, int cap, const float* qfeat, const float* xf, const int32_t* cand,
                          const int32_t* ncand, int32_t* ids, float* d, int32_t* m, hipStream_t st);
+hipError_t launch_cand_t(int Q, int L, int64_t N, int t, const uint2* bins, const uint32_t* tids, int cap,
+                         int32_t* counts, int32_t* ids, hipStream_t st);
 int64_t entropy_scratch_bytes(int L, uint64_t cap);
 hipError_t launch_table_entropy(const Slot* dir, int L, uint64_t cap, int64_t n, void* scratch, double* out,
                                 hipStream_t st);
