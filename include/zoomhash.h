@@ -285,9 +285,12 @@ zh_status zh_tune_batch(zh_ctx* ctx, const zh_batch* batch, zh_batch_tuning* out
 /* ---- results and diagnostics ------------------------------------------ */
 
 /* Copies of the last query's results (device pointers, each may be NULL):
- * ids[Q, K] int32 (-1 past m), d2[Q, K] squared distances, m[Q] neighbours
- * used, w[Q, K] weights (after zh_lle_weights), ncand[Q] distinct candidates
- * (in early-stop mode at most cap). */
+ * ids[Q, K] int32 (-1 past m), d2[Q, K] squared distances (l1 distances
+ * after zh_knn_l1), m[Q] neighbours used, w[Q, K] weights (after
+ * zh_lle_weights), ncand[Q] distinct candidates (in early-stop mode at most
+ * cap; for a patch whose bins hold more than 8192 IDs without a cap, m = -1
+ * and ncand the sum of its bin sizes: zh_candidates_t with t = 1 counts its
+ * distinct IDs). */
 zh_status zh_get_results(zh_ctx* ctx, int32_t* ids, float* d2, int32_t* m, float* w,
                          int32_t* ncand);
 /* Candidates of each patch of the last zh_query that reached the exact
