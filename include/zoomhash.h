@@ -195,6 +195,15 @@ zh_status zh_query(zh_ctx* ctx, const float* lr, int h, int w, int scale, int K)
 zh_status zh_candidates_t(zh_ctx* ctx, int t, int32_t cap_per_query, int32_t* counts,
                           int32_t* ids);
 
+/* Neighbours from the t-of-L candidates (Section 4.1): replace the
+ * neighbours of the last zh_query by the first min(K, M_t) of its t-of-L
+ * candidates (zh_candidates_t) in (squared l2 distance, ID) order, the
+ * distance summed over the coordinates in index order in FP64 from the fp32
+ * features. ncand then reports the t-of-L counts; a patch with more than 256
+ * such IDs ranks the first 256 in table-walk order. zh_lle_weights and
+ * zh_reconstruct use the new neighbours. 1 <= t <= L. */
+zh_status zh_knn_t(zh_ctx* ctx, int t);
+
 /* Re-rank under l1 (Section 4.1: the Cauchy hash is sensitive to l1
  * distances): replace the neighbours of the last zh_query by the first
  * min(K, M) of its early-stop candidates in (l1 distance, ID) order, the

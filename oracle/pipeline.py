@@ -53,10 +53,11 @@ class QueryResult:
 
 
 def query(pre: Prepared, lr: np.ndarray, K: int, lam: float, pos=None,
-          synthesize: bool = True, cap: int = 0, metric: str = "l2") -> QueryResult:
+          synthesize: bool = True, cap: int = 0, metric: str = "l2", t: int = 0) -> QueryResult:
     """metric "l2": neighbours by squared l2 distance (the LLE objective);
     "l1": by l1 distance (the hash's metric); the LLE weights are the same
-    l2 solve for both."""
+    l2 solve for both. t > 0: the candidates are the IDs in at least t of the
+    L bins (Section 4.1) instead of the union / early stop."""
     mode = pre.dictionary.mode
     lr = np.asarray(lr, dtype=np.float32)
     if pos is None:
@@ -67,6 +68,8 @@ def query(pre: Prepared, lr: np.ndarray, K: int, lam: float, pos=None,
     c = lsh.codes(feat, pre.alpha, pre.beta, pre.w)
     keys = lsh.bucket_keys(c, pre.L, pre.k)
     cand, bsz = pre.tables.candidates(keys, cap)
+    if t > 0:
+        cand = lsh.candidates_t(pre.tables, keys, t)
     Q = len(pos)
     ids = np.full((Q, K), -1, dtype=np.int64)
     d2 = np.full((Q, K), np.nan)

@@ -241,10 +241,11 @@ hipError_t launch_table_entropy(const Slot* dir, int L, uint64_t cap, int64_t n,
 namespace zh {
 
 // K nearest candidates under l1 (Section 4.1: the Cauchy hash is sensitive to
-// l1 distances). One wave (one workgroup) per patch. Candidates go in chunks
+// l1 distances) or squared l2 (for candidate sets other than the search's,
+// such as the t-of-L sets). One wave (one workgroup) per patch. Candidates go in chunks
 // of 16: the wave stages their feature rows in LDS (the chunk's rows
 // flattened over the lanes, 16-byte loads when D is a multiple of 4; odd row
-// stride in LDS: no bank conflicts), then lane j sums |q_i - x_i| of candidate j
+// stride in LDS: no bank conflicts), then lane j sums the terms of candidate j
 // over the coordinates in index order in FP64, so every distance is the
 // oracle's to the bit. Then K rounds of a wave minimum over (distance, ID)
 // pick the neighbours in order.
@@ -253,8 +254,10 @@ constexpr int kL1PerLane = 16;  // chunks: at most 256 candidates a patch
 constexpr int kL1MaxD = 128;
 
 // DT: the feature dimension at compile time (0: D at run time, up to 128).
-template <int DT>
-__global__ __launch_bounds__(64) void k_knn_l1(int Q, int Drt, int K, int cap, const float* __restrict__ qfeat,
+// L1: l1 distances; otherwise squared l2, each term (q_i - x_i)^2 rounded
+// before it is added, in index order, as the oracle's FP64 loop does.
+template <int DT, bool L1>
+__global__ __launch_bounds__(64) void k_knn_rank(int Q, int Drt, int K, int cap, const float* __restrict__ qfeat,
                                                const float* __restrict__ xf, const int32_t* __restrict__ cand,
                                                const int32_t* __restrict__ ncand, int32_t* __restrict__ out_ids,
                                                float* __restrict__ out_d, int32_t* __restrict__ out_m) {
@@ -334,7 +337,10 @@ __global__ __launch_bounds__(64) void k_knn_l1(int Q, int Drt, int K, int cap, c
             if (lane < nc) {
                 double acc = 0.0;
 #pragma unroll 20
-                for (int i = 0; i < D; ++i) acc = acc + fabs(sq[i] - (double)sx[lane * st + i]);
+                for (int i = 0; i < D; ++i) {
+                    const double t = sq[i] - (double)sx[lane * st + i];
+                    acc = acc + (L1 ? fabs(t) : t * t);
+                }
                 d[u] = acc;
                 id[u] = myid;
             }
@@ -371,19 +377,30 @@ __global__ __launch_bounds__(64) void k_knn_l1(int Q, int Drt, int K, int cap, c
             out_d[(int64_t)q * K + k] = (float)bd;
         }
     }
+    if (lane >= m && lane < K) {
+        out_ids[(int64_t)q * K + lane] = -1;   // past m, as the search leaves them
+        out_d[(int64_t)q * K + lane] = 0.0f;
+    }
     if (lane == 0) out_m[q] = m;
 }
 
-hipError_t launch_knn_l1(int Q, int D, int K, int cap, const float* qfeat, const float* xf, const int32_t* cand,
-                         const int32_t* ncand, int32_t* ids, float* d, int32_t* m, hipStream_t st) {
+hipError_t launch_knn_rank(int Q, int D, int K, int cap, bool l1, const float* qfeat, const float* xf,
+                           const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
+                           hipStream_t st) {
     if (Q == 0) return hipSuccess;
     if (cap < 1 || cap > kL1Chunk * kL1PerLane || K < 1 || K > kMaxK || D < 1 || D > kL1MaxD) return hipErrorInvalidValue;
-    if (D == 100)
-        hipLaunchKernelGGL(k_knn_l1<100>, dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m);
-    else if (D == 25)
-        hipLaunchKernelGGL(k_knn_l1<25>, dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m);
-    else
-        hipLaunchKernelGGL(k_knn_l1<0>, dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m);
+#define ZH_RANK(DT, M1) \
+    hipLaunchKernelGGL((k_knn_rank<DT, M1>), dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m)
+    if (l1) {
+        if (D == 100) ZH_RANK(100, true);
+        else if (D == 25) ZH_RANK(25, true);
+        else ZH_RANK(0, true);
+    } else {
+        if (D == 100) ZH_RANK(100, false);
+        else if (D == 25) ZH_RANK(25, false);
+        else ZH_RANK(0, false);
+    }
+#undef ZH_RANK
     return hipGetLastError();
 }
 

@@ -1430,6 +1430,26 @@ zh_status zh_candidates_t(zh_ctx* c, int t, int32_t cap_per_query, int32_t* coun
     return ZH_OK;
 }
 
+zh_status zh_knn_t(zh_ctx* c, int t) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_knn_t before zh_query");
+    Dict& d = c->dicts[c->qscale];
+    if (t < 1 || t > d.L) return fail(c, ZH_EINVAL, "zh_knn_t: need 1 <= t <= L = %d", d.L);
+    TRY(set_device(c));
+    TRY(ensure(c, c->l1cand, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1) * kRankMaxCand));
+    {
+        StageTimer tm(c, ZH_T_SEARCH);
+        HIPCHK(c, launch_cand_t((int)c->Q, d.L, d.n, t, P<uint2>(c->qbins), P<uint32_t>(d.tids), kRankMaxCand,
+                                P<int32_t>(c->ncand), P<int32_t>(c->l1cand), c->stream));
+        HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, kRankMaxCand, false, P<float>(c->qfeat), P<float>(d.xf),
+                                  P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids), P<float>(c->d2),
+                                  P<int32_t>(c->m), c->stream));
+    }
+    c->gram_ready = false;   // the Gram matrices of the new neighbours are formed by zh_lle_weights
+    c->stage = 1;
+    return ZH_OK;
+}
+
 zh_status zh_knn_l1(zh_ctx* c) {
     if (!c) return ZH_EINVAL;
     if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_knn_l1 before zh_query");
@@ -1443,9 +1463,9 @@ zh_status zh_knn_l1(zh_ctx* c) {
     TRY(run_search(c, d, P<int32_t>(c->l1cand), cap));
     {
         StageTimer t(c, ZH_T_SEARCH);
-        HIPCHK(c, launch_knn_l1((int)c->Q, d.D, c->qK, cap, P<float>(c->qfeat), P<float>(d.xf), P<int32_t>(c->l1cand),
-                                P<int32_t>(c->ncand), P<int32_t>(c->ids), P<float>(c->d2), P<int32_t>(c->m),
-                                c->stream));
+        HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, cap, true, P<float>(c->qfeat), P<float>(d.xf),
+                                  P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids), P<float>(c->d2),
+                                  P<int32_t>(c->m), c->stream));
     }
     c->gram_ready = false;   // the Gram matrices of the new neighbours are formed by zh_lle_weights
     c->stage = 1;

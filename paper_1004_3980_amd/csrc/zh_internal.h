@@ -188,8 +188,10 @@ hipError_t launch_lle(const LleArgs& a, hipStream_t st);
 int64_t crop_scratch_bytes(int n_img, int H, int W);
 hipError_t launch_sample_crops(const float* imgs, int n_img, int H, int W, const uint64_t* draws, int m, int side,
                                int32_t* corners, float* crops, void* scratch, hipStream_t st);
-hipError_t launch_knn_l1(int Q, int D, int K, int cap, const float* qfeat, const float* xf, const int32_t* cand,
-                         const int32_t* ncand, int32_t* ids, float* d, int32_t* m, hipStream_t st);
+hipError_t launch_knn_rank(int Q, int D, int K, int cap, bool l1, const float* qfeat, const float* xf,
+                           const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
+                           hipStream_t st);
+constexpr int kRankMaxCand = 256;   // candidates a patch the re-rank kernels take
 hipError_t launch_cand_t(int Q, int L, int64_t N, int t, const uint2* bins, const uint32_t* tids, int cap,
                          int32_t* counts, int32_t* ids, hipStream_t st);
 int64_t entropy_scratch_bytes(int L, uint64_t cap);

@@ -65,13 +65,16 @@ class GpuWorkload:
 
     def zoom(self, lr=None, K=None, lam=None, out=None, metric="l2"):
         """hash + K-NN + LLE + blend for the test image; returns the HR image.
-        metric "l1": neighbours re-ranked under l1 (needs the early stop)."""
+        metric "l1": neighbours re-ranked under l1 (needs the early stop);
+        "t=<t>": neighbours among the t-of-L candidates."""
         wl = self.wl
         lr = self.lr if lr is None else lr
         out = self.hr_out if out is None else out
         self.ctx.query(lr, lr.shape[0], lr.shape[1], wl.scale, wl.K if K is None else K)
         if metric == "l1":
             self.ctx.knn_l1()
+        elif metric.startswith("t="):
+            self.ctx.knn_t(int(metric[2:]))
         self.ctx.lle_weights(wl.lam if lam is None else lam)
         self.ctx.reconstruct(out)
         return out

@@ -74,6 +74,7 @@ SIGNATURES = {
     "zh_sample_crops": [_V, _V, _I, _I, _I, _V, _I, _I, _V, _V],
     "zh_table_entropy": [_V, _I, _V, _I],
     "zh_knn_l1": [_V],
+    "zh_knn_t": [_V, _I],
     "zh_candidates_t": [_V, _I, _I, _V, _V],
     "zh_build_tables": [_V, ctypes.POINTER(zh_dictionary), _I, _I, _F, _U64],
     "zh_get_hash_params": [_V, _I, _V, _V],
@@ -178,6 +179,9 @@ class Context:
 
     def candidates_t(self, t, cap_per_query, counts, ids):
         self._chk(self.lib.zh_candidates_t(self.h, t, cap_per_query, _ptr(counts), _ptr(ids)))
+
+    def knn_t(self, t):
+        self._chk(self.lib.zh_knn_t(self.h, t))
 
     def knn_l1(self):
         self._chk(self.lib.zh_knn_l1(self.h))

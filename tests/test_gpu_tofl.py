@@ -66,3 +66,29 @@ def test_t_of_l_argument_errors():
         g.ctx.candidates_t(0, 4, counts, counts)
     with pytest.raises(zb.ZHError):
         g.ctx.candidates_t(wl.L + 1, 4, counts, counts)
+
+
+MIDC = ("mid", (("test_h", 64), ("test_w", 72), ("n_dict", 60000), ("dict_images", 16)))
+
+
+# (t-of-L sets of at most 256 IDs: the tiny union reaches 381)
+@pytest.mark.parametrize("name,kw,t", [("tiny", (), 2), ("tiny", (), 3), (*MIDC, 1)])
+def test_neighbours_from_t_of_l(name, kw, t):
+    """K-NN (squared l2, sequential FP64 sums on both sides), LLE and the
+    blend over the t-of-L candidates: IDs, counts, distances bitwise."""
+    wl, g, pre, _ = _case(name, kw)
+    lr = g.lr.cpu().numpy()
+    qr = pipeline.query(pre, lr, wl.K, wl.lam, t=t)
+    assert max(len(c) for c in qr.cand) <= 256
+    hr_ref, _ = pipeline.reconstruct(qr, lr, wl.scale)
+    g.set_mode(cap=0, rerank=0, proj=1, lle_fp64=1)
+    hr = g.zoom(metric=f"t={t}").cpu().numpy().astype(np.float64)
+    r = g.results()
+    assert np.array_equal(r["m"], qr.m)
+    assert np.array_equal(r["ids"], np.where(qr.ids >= 0, qr.ids, -1).astype(np.int32))
+    assert np.array_equal(r["ncand"], np.array([len(c) for c in qr.cand], dtype=np.int32))
+    for q in np.nonzero(qr.m > 0)[0]:
+        assert np.array_equal(r["d2"][q, :qr.m[q]], qr.d2[q, :qr.m[q]].astype(np.float32)), q
+    dw = np.abs(r["w"].astype(np.float64) - qr.weights)
+    assert (dw <= 2.0 ** -23 * np.abs(qr.weights) + 1e-10).all(), dw.max()
+    assert np.abs(hr - hr_ref).max() < 1e-5
