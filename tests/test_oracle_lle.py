@@ -156,3 +156,29 @@ def test_knn_l1_brute_force_and_ties():
     assert d0[0] == 0.0 and (ids0[0] == cand[5] or np.array_equal(X[ids0[0]], X[cand[5]]))
     # fewer candidates than K: all of them
     assert len(lle.knn_l1(q, X, cand[:4], 7)[0]) == 4
+
+
+@pytest.mark.parametrize("K", [2, 5, 8])
+def test_synthesis_of_an_affine_combination(K):
+    """Eq. LinSys then Eq. HR_Rec with K > 1: a query feature that is an
+    affine combination sum_m c_m y_m (sum c = 1) of its neighbours, whose HR
+    residuals follow the same combination, is synthesised as
+    mu_q + sum_m c_m r_m as lambda -> 0 (the weights recover c and the HR
+    patch is built with them). A dropped mean, a transposed weight/residual
+    product or weights that are not renormalised fail it."""
+    rng = np.random.default_rng(50 + K)
+    Y = rng.standard_normal((K, 100))
+    R = rng.standard_normal((K, 100))
+    c = rng.uniform(-0.5, 1.0, K)
+    c /= c.sum()
+    q = c @ Y
+    w = lle.lle_weights(q, Y, 1e-13)
+    assert np.abs(w - c).max() < 1e-7
+    mu = 0.37
+    x = lle.synthesize(mu, w, R)
+    assert x.shape == (100,)
+    assert np.abs(x - (mu + c @ R)).max() < 1e-6
+    # a larger lambda pulls the weights towards uniform; the patch follows them
+    w2 = lle.lle_weights(q, Y, 0.5)
+    assert np.abs(w2 - c).max() > 1e-3
+    assert np.abs(lle.synthesize(mu, w2, R) - (mu + w2 @ R)).max() < 1e-12
