@@ -8,8 +8,9 @@ k = 20 hashes, K = 8, with the dictionary, tables and LR image resident in
 HBM. The default form ("screened") bounds every candidate's distance from
 below with int8 coordinates in the dictionary's leading principal directions
 and gives exact fp32 distances to at most 32 of them (those the bounds cannot
-rule out); --form exact does the same with no limit and certifies the
-selection against FP64.
+rule out; the number of patches where more were left is reported and is 0);
+--form exact does the same with no limit and certifies the selection against
+FP64.
 
 One JSON line on stdout. Progress goes to stderr.
 """
@@ -74,29 +75,125 @@ def traffic_from_profile(form):
     return float(rec["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(wl, lr, hr_gt, crop):
-    """The FP64 oracle on the top-left crop x crop LR patch grid of the same
-    workload (same dictionary and tables); table build excluded, like the
-    GPU's. Returns (record, oracle query result, oracle HR crop)."""
+# ---- CPU baseline: the FP64 oracle on the host cores -----------------------------
+#
+# The oracle runs in a child process started before this process touches the
+# GPU; it waits on its stdin until the GPU timings are done, so that it does
+# not compete with them. For each sample it builds the tables (timed apart,
+# the code projection on every core), then times the query, LLE, synthesis
+# and blend on one thread, and across all cores with one worker process per
+# core over chunks of the patches (forked after the build).
+
+def _oracle_chunk(arg):
+    q0, q1 = arg
+    st = _ORC
+    qr = st["opipe"].query(st["pre"], st["lr"], st["K"], st["lam"], pos=st["pos"][q0:q1], cap=st["cap"])
+    return qr.ids, qr.m, qr.patches
+
+
+_ORC = {}
+
+
+def _oracle_sample(name, wl, lr, cores, log_fn):
+    import multiprocessing as mp
+    from oracle import _clib
+    from oracle import imaging as oim
+    from oracle import lle as olle
     from oracle import pipeline as opipe
+    _clib.set_threads(cores)
     t0 = time.perf_counter()
-    pre = opipe.prepare(wl.dictionary_images(), wl.positions(), wl.scale, wl.feat_mode, wl.L, wl.k,
-                        wl.w, wl.hash_seed)
+    pre = opipe.prepare(wl.dictionary_images(), wl.positions(), wl.scale, wl.feat_mode, wl.L, wl.k, wl.w,
+                        wl.hash_seed)
     t_build = time.perf_counter() - t0
-    lr_c = np.ascontiguousarray(lr[:crop, :crop])
+    pos = oim.all_positions(*lr.shape)
+    Q = len(pos)
+    _clib.set_threads(1)
     t0 = time.perf_counter()
-    qr = opipe.query(pre, lr_c, wl.K, wl.lam, cap=wl.cap)
-    hr_c, _ = opipe.reconstruct(qr, lr_c, wl.scale)
-    t_q = time.perf_counter() - t0
-    n = len(qr.pos)
+    qr = opipe.query(pre, lr, wl.K, wl.lam, cap=wl.cap)
+    hr1, _ = opipe.reconstruct(qr, lr, wl.scale)
+    t_one = time.perf_counter() - t0
+    _ORC.update(opipe=opipe, pre=pre, lr=lr, pos=pos, K=wl.K, lam=wl.lam, cap=wl.cap)
+    nchunk = 4 * cores
+    bounds = [(Q * i // nchunk, Q * (i + 1) // nchunk) for i in range(nchunk)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        parts = pool.map(_oracle_chunk, bounds)
+    patches = [p for _, _, ps in parts for p in ps]
+    m = np.concatenate([pm for _, pm, _ in parts])
+    hrn, _ = olle.blend(patches, pos, m > 0, wl.scale, np.asarray(lr, np.float32))
+    t_all = time.perf_counter() - t0
+    ids = np.concatenate([pi for pi, _, _ in parts])
+    assert np.array_equal(ids, qr.ids) and np.array_equal(hrn, hr1)
+    rec = {"patches": int(Q), "table_build_s": round(t_build, 2), "one_thread_s": round(t_one, 2),
+           "one_thread_patches_per_s": Q / t_one, "all_cores_s": round(t_all, 2),
+           "all_cores_patches_per_s": Q / t_all, "dictionary_pairs": wl.n_dict,
+           "mean_candidates": float(np.mean([len(c) for c in qr.cand]))}
+    log_fn(f"[oracle] {name}: {Q} patches, build {t_build:.1f} s, one thread {Q / t_one:.4g}/s, "
+           f"{cores} workers {Q / t_all:.4g}/s")
+    return rec, qr, hr1
+
+
+def oracle_child(args):
+    """Child process: wait for "go" on stdin, then time the oracle and print
+    one JSON record; the precision crop's oracle result goes to args.oracle_out."""
+    import synthdata
+    from oracle import imaging as oim
+    if not sys.stdin.readline().strip():
+        return
     cores = len(os.sched_getaffinity(0))
-    rec = {"value": n / t_q, "unit": "LR patches/s", "cores": cores, "kind": "oracle",
-           "sample": f"{crop}x{crop} LR crop ({n} patches) of the same image against the full "
-                     f"{wl.n_dict}-pair dictionary: features, codes, candidates (early stop "
-                     f"{wl.cap}), exact K-NN, FP64 LLE, synthesis, blend; {t_q:.1f} s; the "
-                     f"projection loop runs on {cores} OpenMP threads, the rest on one; table "
-                     f"build ({t_build:.0f} s) excluded"}
-    return rec, qr, hr_c
+    out = {"cores": cores, "os_cpu_count": os.cpu_count(), "affinity": cores, "samples": {}}
+    for name in ("tiny", "mid"):
+        wl = synthdata.WORKLOADS[name]
+        lr = wl.test_image() if wl.test_lr_direct else oim.degrade(wl.test_image(), wl.scale)
+        out["samples"][name], _, _ = _oracle_sample(name, wl, np.ascontiguousarray(lr), cores, log)
+    wl = synthdata.WORKLOADS[args.workload]
+    if args.scale not in (0, wl.scale):
+        wl = synthdata.at_scale(wl, args.scale)
+    img = wl.test_image()
+    lr = img if wl.test_lr_direct else oim.degrade(img, wl.scale)
+    crop = args.crop
+    lr_c = np.ascontiguousarray(lr[:crop, :crop])
+    rec, qr, hr_c = _oracle_sample(f"{wl.name} crop", wl, lr_c, cores, log)
+    out["samples"][f"{wl.name}_crop{crop}"] = rec
+    np.savez(args.oracle_out, ids=qr.ids, m=qr.m, hr=hr_c)
+    print(json.dumps(out), flush=True)
+
+
+def start_oracle_child(args):
+    """Start the oracle's timing process (before any GPU work); returns
+    (process, path of its result file)."""
+    import subprocess
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".npz")
+    os.close(fd)
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-child", "--oracle-out", path,
+           "--workload", args.workload, "--scale", str(args.scale), "--crop", str(args.crop)]
+    env = dict(os.environ, OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    p = subprocess.Popen(cmd, stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+    return p, path
+
+
+def finish_oracle_child(proc, path, wl, crop):
+    """Release the child, read its record; the cpu_baseline object, the
+    oracle's neighbour IDs and counts and HR crop."""
+    out, _ = proc.communicate("go\n", timeout=900)
+    if proc.returncode != 0:
+        raise RuntimeError(f"oracle timing process failed ({proc.returncode})")
+    rec = json.loads(out.strip().splitlines()[-1])
+    z = np.load(path)
+    os.unlink(path)
+    key = f"{wl.name}_crop{crop}"
+    s = rec["samples"][key]
+    cpu = {"value": s["all_cores_patches_per_s"], "unit": "LR patches/s", "cores": rec["cores"], "kind": "oracle",
+           "sample": f"{crop}x{crop} LR crop ({s['patches']} patches) of the same image against the full "
+                     f"{wl.n_dict}-pair dictionary: features, codes, candidates (early stop {wl.cap}), exact "
+                     f"K-NN, FP64 LLE, synthesis, blend, on {rec['cores']} worker processes over chunks of the "
+                     f"patches ({s['all_cores_s']} s); table build ({s['table_build_s']} s, the projection on "
+                     f"{rec['cores']} threads) excluded",
+           "one_thread_value": s["one_thread_patches_per_s"],
+           "os_cpu_count": rec["os_cpu_count"], "affinity": rec["affinity"],
+           "samples": rec["samples"]}
+    return cpu, z["ids"], z["m"], z["hr"]
 
 
 def main():
@@ -119,13 +216,22 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times "
                          "(reference dispatch for scaling HBM counters)")
+    ap.add_argument("--oracle-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-out", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_child:
+        return oracle_child(args)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
               "this path is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's process starts before this one touches the GPU
+    child = None
+    if args.form in ("screened", "exact") and not (args.no_quality and args.no_cpu_baseline):
+        child = start_oracle_child(args)
 
     import torch
     import synthdata
@@ -223,18 +329,18 @@ def main():
              "mean_candidates": float(res["ncand"].mean()),
              "mean_survivors": float(res["nsurv"].mean()),
              "patches_without_neighbours": int((res["m"] == 0).sum()),
+             "truncated_patches": stats["truncated"],
              "similarity_checks_saved": float(wl.n_dict / max(1e-9, res["ncand"].mean())),
              "stats": stats}
 
-    # quality on a crop against the FP64 oracle, and the oracle's CPU rate
+    # quality on a crop against the FP64 oracle, and the oracle's CPU rates
     cpu = None
-    if not (args.no_quality and args.no_cpu_baseline):
+    if child is not None:
         crop = args.crop
-        lr_np = g.lr.cpu().numpy()
         gt = g.hr_gt.cpu().numpy()[: wl.scale * crop, : wl.scale * crop] if g.hr_gt is not None else None
-        log(f"[bench] oracle on the {crop}x{crop} crop (table build first)")
-        cpu, qr, hr_o = cpu_baseline(wl, lr_np, gt, crop)
-        log(f"[bench] oracle: {cpu['value']:.4g} patches/s")
+        log(f"[bench] oracle timings on the host (tiny, mid, the {crop}x{crop} crop)")
+        cpu, ids_o, m_o, hr_o = finish_oracle_child(*child, wl, crop)
+        child = None
         lr_c = g.lr[:crop, :crop].contiguous()
         out = torch.empty((wl.scale * crop, wl.scale * crop), dtype=torch.float32, device="cuda")
         quality = {}
@@ -242,16 +348,15 @@ def main():
             set_form(form)
             g.zoom(lr=lr_c, out=out)
             r = g.results()
-            Kq = wl.K
-            ok = qr.m > 0
-            inter = [len(np.intersect1d(r["ids"][q, :r["m"][q]], qr.ids[q, :qr.m[q]]))
-                     for q in np.nonzero(ok)[0]]
-            rec_k = float(np.sum(inter) / max(1, qr.m[ok].sum()))
+            st_q = g.ctx.stats()
+            ok = m_o > 0
+            inter = [len(np.intersect1d(r["ids"][q, :r["m"][q]], ids_o[q, :m_o[q]])) for q in np.nonzero(ok)[0]]
+            rec_k = float(np.sum(inter) / max(1, m_o[ok].sum()))
             o = out.cpu().numpy()
             qrec = {"recall_at_k": rec_k, "ids_equal": bool(np.array_equal(
-                r["ids"], np.where(qr.ids >= 0, qr.ids, -1).astype(np.int32))),
+                r["ids"], np.where(ids_o >= 0, ids_o, -1).astype(np.int32))),
                 "max_abs_vs_oracle": float(np.abs(o - hr_o).max()),
-                "psnr_vs_oracle_db": psnr(o, hr_o)}
+                "psnr_vs_oracle_db": psnr(o, hr_o), "truncated": st_q["truncated"]}
             if gt is not None:
                 qrec["psnr_gt_db"] = psnr(o, gt)
             quality[form] = qrec
@@ -262,6 +367,8 @@ def main():
                 quality[form]["psnr_loss_db"] = p_or - quality[form]["psnr_gt_db"]
         extra["quality_crop"] = quality
         set_form(args.form)
+        if quality["screened"]["truncated"] or quality["exact"]["truncated"]:
+            raise SystemExit("screened form cut the exact rows of some patch of the crop (truncated > 0)")
         if args.no_cpu_baseline:
             cpu = None
 
@@ -281,7 +388,8 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.test_h}x{wl.test_w} LR x{wl.scale}, "
                                f"{wl.n_dict}-pair dictionary (4-gradient features, D={wl.D}), "
                                f"L={wl.L} k={wl.k} w={wl.w:g} K={wl.K}, early stop {wl.cap}, "
-                               f"form {args.form}" + (f" (bf16 screen to {wl.rerank})" if args.form == "screened" else "")
+                               f"form {args.form}" + (f" (int8 principal-coordinate screen, at most {wl.rerank} "
+                                                      "exact fp32 rows)" if args.form == "screened" else "")
                                + (", neighbours re-ranked under l1 (zh_knn_l1)" if args.metric == "l1" else ""),
                    "patches_per_step": Q, "parallelism": "single GPU"},
         "roofline": roof,

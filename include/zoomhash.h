@@ -46,7 +46,8 @@ enum {
     ZH_ESTATE = 2,        /* call out of order (e.g. zh_reconstruct before zh_lle_weights) */
     ZH_ENOMEM = 3,        /* device allocation failed or exceeded ZH_MEM_LIMIT */
     ZH_EDEVICE = 4,       /* HIP runtime or kernel launch error */
-    ZH_EUNSUPPORTED = 5   /* valid request outside what this build implements */
+    ZH_EUNSUPPORTED = 5,  /* valid request outside what this build implements */
+    ZH_EIO = 6            /* a file could not be read or written, or is damaged */
 };
 
 typedef struct zh_ctx zh_ctx;
@@ -83,9 +84,12 @@ enum { ZH_FEAT_MEANREM = 0,   /* D = 25: the patch's pixels minus their mean */
  * of the HR image by `sigma` and `scale`; feat[n, D] is the LR patch's
  * feature vector and resid[n, (5s)^2] the HR patch at (s i, s j) minus the
  * mean of the LR patch. Row n is pair ID n (Section 2.1: unique integer IDs).
- * Positions must satisfy 0 <= i <= floor(H/s) - 5 and 0 <= j <= floor(W/s) - 5
- * (the HR patch inside the image; not checked). Uses a temporary device
- * buffer of n_img * ceil(H/s) * ceil(W/s) * 5 floats. */
+ * Positions must satisfy 0 <= image < n_img, 0 <= i <= floor(H/s) - 5 and
+ * 0 <= j <= floor(W/s) - 5 (the HR patch inside the image): a device kernel
+ * checks them before anything is cut, and any position outside returns
+ * ZH_EINVAL with feat and resid untouched (the call then synchronises the
+ * context's stream). Uses a temporary device buffer of
+ * n_img * ceil(H/s) * ceil(W/s) * 5 floats. */
 zh_status zh_make_dictionary(zh_ctx* ctx, const float* hr, int n_img, int H, int W,
                              const int32_t* pos, int64_t n, int scale, float sigma,
                              int feat_mode, float* feat, float* resid);
@@ -133,12 +137,39 @@ typedef struct {
  * polar method (first variate of each accepted pair); alpha = a/b with b
  * redrawn while |b| < 1e-3, k*D values in (hash, dim) order; then k values
  * beta = u w, u in [0,1). FP64, rounded to fp32. A bin is the 64-bit key of
- * the k codes floor((alpha.v + beta)/w) of a table, folded in order by
- * h = fmix64(h ^ uint32(code)) from h = fmix64(0x9E3779B97F4A7C15 (l+1)).
+ * the k codes c_j = floor((alpha.v + beta)/w) of a table l (Section 4.1:
+ * "based on the k integers we form the bins"):
+ *   key = fmix64(M[l][63] + sum_j uint32(c_j) M[l][j]  mod 2^64),
+ * M[l][j] the SplitMix64 output number 64 l + j + 1 from state 0 (output n is
+ * fmix64(n 0x9E3779B97F4A7C15)), fmix64 the SplitMix64 output function; a key
+ * equal to 2^64 - 1 becomes 2^64 - 2 (that value marks empty directory slots).
  * Codes equal the FP64 sequential dot-product definition exactly.
  * Limits: 1 <= L <= 64, 1 <= k <= 32, w > 0. */
 zh_status zh_build_tables(zh_ctx* ctx, const zh_dictionary* dict, int L, int k, float w,
                           uint64_t seed);
+
+/* Tables on disk (Section 2.1: the training patch pairs are stored on disk
+ * and found again through their unique integer IDs). zh_save_tables writes
+ * what zh_build_tables built for `scale` to the file `path` (host string):
+ * a header (magic, version, n, D, scale, feature mode, L, k, w, seed, the
+ * directory size, the error-bound constants, a 64-bit content hash of the
+ * dictionary features, the size and content hash of every section, and a
+ * hash of the header itself), then the hash parameters, the bucket-key
+ * multipliers, the L bin directories with their presence filters, the IDs of
+ * the L tables laid out bin by bin, the screen rows and the screen
+ * directions: L (16 cap + cap / 2 + 4 n) + 64 n bytes and a few more, cap the
+ * power of two with 2 n <= cap < 4 n (2.0 GB for 2M pairs and 24 tables).
+ * Synchronises the context's stream.
+ * zh_load_tables replaces the tables of dict->scale by those of the file for
+ * the dictionary `dict` (as for zh_build_tables: its features are copied, its
+ * HR residuals BORROWED); the features must be those the tables were built
+ * on (same n, D, scale, mode and content hash, else ZH_EINVAL). A file that
+ * is not a table file of this version, is truncated, or whose header or any
+ * section does not match its hash gives ZH_EIO and leaves no tables for that
+ * scale. The loaded tables are bitwise those that were saved: queries give
+ * the results they gave before. */
+zh_status zh_save_tables(zh_ctx* ctx, int scale, const char* path);
+zh_status zh_load_tables(zh_ctx* ctx, const zh_dictionary* dict, const char* path);
 
 /* Hashing quality (Section 4.1, determining r): the entropy in bits of each
  * table's bucket occupancy, -sum_b p_b log2 p_b with p_b the fraction of the
@@ -178,10 +209,16 @@ zh_status zh_set_query_opts(zh_ctx* ctx, const zh_query_opts* opts);
 
 /* ---- the path --------------------------------------------------------- */
 
-/* Features, codes, bins and the K nearest candidates of every patch of the
- * LR image lr[h, w] (copied into the context) against the dictionary of
- * `scale`. 1 <= K <= 16, h, w >= 5. Neighbours are ordered by (distance, ID);
- * a patch with fewer than K candidates keeps all of them. */
+/* Section 3.2 and Section 4.2 (query every table, collect the matches, stop
+ * early when there are more than a preset number of them), Section 3.1
+ * step 1(a) (the K nearest neighbours): features (Section 4.1), codes and
+ * bins of every stride-1 patch of the LR image lr[h, w] (copied into the
+ * context), then the candidates of each patch (the union of its L bins, or
+ * the early stop of the query options) and the K nearest of them by squared
+ * l2 distance against the dictionary of `scale`. 1 <= K <= 16, h, w >= 5.
+ * Neighbours are ordered by (distance, ID); a patch with fewer than K
+ * candidates keeps all of them, one with none contributes no HR patch.
+ * Results stay in the context (zh_get_results). */
 zh_status zh_query(zh_ctx* ctx, const float* lr, int h, int w, int scale, int K);
 
 /* The t-of-L candidate criterion (Section 4.1: a training patch matches
@@ -199,9 +236,9 @@ zh_status zh_candidates_t(zh_ctx* ctx, int t, int32_t cap_per_query, int32_t* co
  * neighbours of the last zh_query by the first min(K, M_t) of its t-of-L
  * candidates (zh_candidates_t) in (squared l2 distance, ID) order, the
  * distance summed over the coordinates in index order in FP64 from the fp32
- * features. ncand then reports the t-of-L counts; a patch with more than 256
- * such IDs ranks the first 256 in table-walk order. zh_lle_weights and
- * zh_reconstruct use the new neighbours. 1 <= t <= L. */
+ * features; every t-of-L candidate is ranked, however many there are.
+ * ncand then reports the t-of-L counts. zh_lle_weights and zh_reconstruct use
+ * the new neighbours. 1 <= t <= L. */
 zh_status zh_knn_t(zh_ctx* ctx, int t);
 
 /* Re-rank under l1 (Section 4.1: the Cauchy hash is sensitive to l1
@@ -323,6 +360,13 @@ typedef struct {
     uint64_t unsupported;       /* patches whose bins exceed 8192 IDs without a cap */
     uint64_t lle_fp64;          /* fp32 solves redone in FP64 */
     uint64_t dict_bytes;        /* device bytes held for dictionaries and tables */
+    uint64_t truncated;         /* screened early-stop search (rerank = R): patches
+                                   whose candidates that the screen's lower bounds
+                                   could not rule out numbered more than R; only
+                                   the R with the smallest bounds were ranked, so
+                                   their neighbours may differ from the exact ones
+                                   (0: the screened neighbours are the exact K
+                                   nearest up to fp32 ties) */
 } zh_stats_t;
 /* Counters of the last zh_query / zh_lle_weights (synchronises the stream). */
 zh_status zh_stats(zh_ctx* ctx, zh_stats_t* out);

@@ -34,6 +34,8 @@ def lib():
         L.orc_sqdist.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
         L.orc_sqdist.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -49,6 +51,11 @@ def codes(V: np.ndarray, A: np.ndarray, beta: np.ndarray, w: float) -> np.ndarra
     lib().orc_codes(V.ctypes.data, n, D, A.ctypes.data, beta.ctypes.data, m, float(w),
                     out.ctypes.data)
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the helper's OpenMP loops (the code projection)."""
+    lib().orc_set_threads(int(n))
 
 
 def sqdist(q: np.ndarray, Y: np.ndarray, rows: np.ndarray) -> np.ndarray:

@@ -10,7 +10,15 @@
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC orc_seq.c -o liborc_seq.so
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
+
+/* Threads of the OpenMP loops below (timing of the oracle at one thread and
+ * at many). */
+void orc_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
 
 void orc_codes(const float* V, int64_t n, int D, const float* A, const float* beta,
                int m, double w, int32_t* out)

@@ -322,6 +322,23 @@ hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_tot
     return hipGetLastError();
 }
 
+// flag[0] = 1 when any training position (image, i, j) lies outside
+// [0, n_img) x [0, imax] x [0, jmax]; flag is cleared by the caller
+__global__ __launch_bounds__(256) void k_check_positions(const int32_t* __restrict__ pos, int64_t n, int n_img,
+                                                         int imax, int jmax, uint32_t* __restrict__ flag) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int im = pos[3 * r], i = pos[3 * r + 1], j = pos[3 * r + 2];
+    if (im < 0 || im >= n_img || i < 0 || i > imax || j < 0 || j > jmax) flag[0] = 1u;
+}
+
+hipError_t launch_check_positions(const int32_t* pos, int64_t n, int n_img, int imax, int jmax, uint32_t* flag,
+                                  hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_positions, dim3(grid_for(n, 256)), dim3(256), 0, st, pos, n, n_img, imax, jmax, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_dict_cut(const float* hr, const float* lr, const float* maps, int H, int W,
                            int scale, const int32_t* pos, int64_t n, int mode, float* feat,
                            float* resid, hipStream_t st) {

@@ -10,8 +10,11 @@
 // each fp32 distance certifies the selected set and its order against the
 // FP64 sequential distance, and when it cannot, the ambiguous candidates are
 // re-ranked by that FP64 distance, so the result equals the FP64 definition.
-// Screened mode (rerank = R): the high plane alone (a bf16 feature) ranks the
-// candidates, the best R are re-ranked exactly in fp32.
+// Screened mode (rerank = R): with the early stop, lower bounds from int8
+// coordinates in the dictionary's principal directions rule candidates out and
+// at most R of the others get exact fp32 distances (patches where more than R
+// survive are counted); without it, a distance on the high plane alone (a
+// bf16 feature) ranks the candidates and the best R are re-ranked in fp32.
 #include <type_traits>
 
 #include "zh_internal.h"
@@ -276,7 +279,7 @@ __device__ void certify_or_fix(const SearchArgs& a, int q, const uint32_t* cids,
         out_d = key_dist(mykey);
         return;
     }
-    if (lane == 0) atomicAdd(&a.counters[1], 1u);
+    if (lane == 0) atomicAdd(&a.counters[C_RANKFB], 1u);
     const float* qrow = a.qfeat + (int64_t)q * a.D;
     const bool bounded = Kp < M && !last_ex;
     double lastd = 0.0;
@@ -820,7 +823,9 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
                 S += __popcll(__ballot(sel[s]));
             }
             if (!EXACT && K + S > a.rerank) {
-                // screened form: at most R survivors in all, by lower bound, equal bounds by lower ID
+                // screened form: at most R survivors in all, by lower bound, equal bounds by lower ID;
+                // the cut is counted (the neighbours may then differ from the exact ones)
+                if (lane == 0) atomicAdd(&a.counters[C_TRUNC], 1u);
                 bool keep[NSL];
                 mark_smallest<NSL>(lv, iv, sel, M, a.rerank - K, keep);
 #pragma unroll
@@ -876,7 +881,7 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
     __shared__ uint32_t soff[kMaxL];
     const int lane = threadIdx.x;
     const int L = a.L;
-    const int nq = BIG ? (int)a.counters[0] : a.Q;
+    const int nq = BIG ? (int)a.counters[C_OVERFLOW] : a.Q;
 
     for (int t = xcd_block(); t < nq; t += gridDim.x) {
         const int q = BIG ? a.overflow[t] : t;
@@ -890,14 +895,14 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
         if (T > CMAX) {
             if (!BIG) {
                 if (lane == 0) {
-                    const unsigned int pos = atomicAdd(&a.counters[0], 1u);
+                    const unsigned int pos = atomicAdd(&a.counters[C_OVERFLOW], 1u);
                     a.overflow[pos] = q;
                 }
             } else {
                 if (lane == 0) {
                     a.out_m[q] = -1;
                     a.out_ncand[q] = T;
-                    atomicAdd(&a.counters[2], 1u);
+                    atomicAdd(&a.counters[C_UNSUP], 1u);
                 }
                 if (lane < a.K) a.out_ids[(int64_t)q * a.K + lane] = -1;
             }

@@ -223,4 +223,26 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     return hipSuccess;
 }
 
+// Content hash of n 32-bit words for the table files: the sum over i of
+// fmix64((i G + salt) ^ w_i) mod 2^64, G the SplitMix64 increment. Integer sums do not depend on their
+// order, so the value is the same for every launch shape; it changes with any
+// word and with its position.
+__global__ __launch_bounds__(256) void k_hash_words(const uint32_t* __restrict__ p, int64_t n, uint64_t salt,
+                                                    unsigned long long* __restrict__ out) {
+    uint64_t acc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += fmix64(((uint64_t)i * kGolden + salt) ^ (uint64_t)p[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, (unsigned long long)acc);
+}
+
+hipError_t launch_hash_words(const void* p, int64_t n_words, uint64_t salt, unsigned long long* out,
+                             hipStream_t st) {
+    if (n_words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hash_words, dim3(grid_for(n_words, 256)), dim3(256), 0, st,
+                       static_cast<const uint32_t*>(p), n_words, salt, out);
+    return hipGetLastError();
+}
+
 }  // namespace zh

@@ -471,6 +471,159 @@ __global__ __launch_bounds__(256) void k_cand_t(int Q, int L, int64_t N, int t, 
     if (lane == 0) counts[q] = (int32_t)kept;
 }
 
+// K nearest of the t-of-L candidates, however many there are. One wave per
+// patch walks its bins as k_cand_t does (an ID kept at its first table when
+// it has at least t hits); each lane with a kept ID sums its squared l2
+// distance over the coordinates in index order in FP64 (each term rounded
+// before it is added, as the oracle's loop), and the wave merges the chunk's
+// (distance, ID) pairs into a running top K held by lanes 0..K-1: K rounds
+// of a wave minimum over both sets. IDs are distinct across chunks (first
+// occurrences only), so no pair is seen twice.
+template <int DT>
+__global__ __launch_bounds__(256) void k_knn_tofl(int Q, int L, int64_t N, int t, int Drt, int K,
+                                                  const uint2* __restrict__ bins, const uint32_t* __restrict__ tids,
+                                                  const float* __restrict__ qfeat, const float* __restrict__ xf,
+                                                  int32_t* __restrict__ counts, int32_t* __restrict__ out_ids,
+                                                  float* __restrict__ out_d, int32_t* __restrict__ out_m) {
+    __shared__ uint32_t s_off[4][64], s_cnt[4][64];
+    __shared__ int64_t s_st[4][64];
+    __shared__ double s_q[4][kL1MaxD];
+    const int D = DT ? DT : Drt;
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    const int q = blockIdx.x * 4 + wv;
+    if (q >= Q) return;
+    const uint2 b = lane < L ? bins[(int64_t)lane * Q + q] : make_uint2(0u, 0u);
+    int64_t incl = b.y;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    s_off[wv][lane] = b.x;
+    s_cnt[wv][lane] = b.y;
+    s_st[wv][lane] = incl - b.y;
+    for (int i = lane; i < D; i += 64) s_q[wv][i] = (double)qfeat[(int64_t)q * D + i];
+    const int64_t S = __shfl(incl, 63);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    auto in_bin = [&](int l, uint32_t x) {
+        const uint32_t* p = tids + (int64_t)l * N + s_off[wv][l];
+        uint32_t lo = 0, hi = s_cnt[wv][l];
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (p[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo < s_cnt[wv][l] && p[lo] == x;
+    };
+    // running top K: lane k < K holds the k-th smallest (distance, ID) so far
+    double bd = INFINITY;
+    int bi = 0x7FFFFFFF;
+    int64_t kept = 0;
+    for (int64_t e0 = 0; e0 < S; e0 += 64) {
+        const int64_t e = e0 + lane;
+        bool keep = false;
+        uint32_t x = 0;
+        if (e < S) {
+            int l = 0;
+            while (l + 1 < L && s_st[wv][l + 1] <= e) ++l;
+            x = tids[(int64_t)l * N + s_off[wv][l] + (e - s_st[wv][l])];
+            bool first = true;
+            for (int j = 0; j < l && first; ++j) first = !in_bin(j, x);
+            if (first) {
+                int hits = 1;
+                for (int j = l + 1; j < L && hits < t; ++j) hits += in_bin(j, x) ? 1 : 0;
+                keep = hits >= t;
+            }
+        }
+        const uint64_t mask = __ballot(keep);
+        kept += __popcll(mask);
+        if (!mask) continue;
+        double nd = INFINITY;
+        int ni = 0x7FFFFFFF;
+        if (keep) {
+            const float* row = xf + (int64_t)x * D;
+            double acc = 0.0;
+            if ((D & 3) == 0) {
+                const float4* r4 = reinterpret_cast<const float4*>(row);
+                for (int i = 0; i < D; i += 4) {
+                    const float4 v = r4[i >> 2];
+                    const double t0 = s_q[wv][i] - (double)v.x;
+                    acc = acc + t0 * t0;
+                    const double t1 = s_q[wv][i + 1] - (double)v.y;
+                    acc = acc + t1 * t1;
+                    const double t2 = s_q[wv][i + 2] - (double)v.z;
+                    acc = acc + t2 * t2;
+                    const double t3 = s_q[wv][i + 3] - (double)v.w;
+                    acc = acc + t3 * t3;
+                }
+            } else {
+                for (int i = 0; i < D; ++i) {
+                    const double t0 = s_q[wv][i] - (double)row[i];
+                    acc = acc + t0 * t0;
+                }
+            }
+            nd = acc;
+            ni = (int)x;
+        }
+        // K rounds: the smallest of the running top K and the chunk's pairs
+        double rd = INFINITY;
+        int ri = 0x7FFFFFFF;
+        for (int k = 0; k < K; ++k) {
+            const bool bfirst = bd < nd || (bd == nd && bi < ni);
+            double md = bfirst ? bd : nd;
+            int mi = bfirst ? bi : ni;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double od = __shfl_xor(md, o);
+                const int oi = __shfl_xor(mi, o);
+                if (od < md || (od == md && oi < mi)) {
+                    md = od;
+                    mi = oi;
+                }
+            }
+            if (bi == mi && bd == md) {
+                bd = INFINITY;
+                bi = 0x7FFFFFFF;
+            } else if (ni == mi && nd == md) {
+                nd = INFINITY;
+                ni = 0x7FFFFFFF;
+            }
+            if (lane == k) {
+                rd = md;
+                ri = mi;
+            }
+        }
+        bd = rd;
+        bi = ri;
+    }
+    const int m = (int)(kept < K ? kept : K);
+    if (lane < m) {
+        out_ids[(int64_t)q * K + lane] = bi;
+        out_d[(int64_t)q * K + lane] = (float)bd;
+    } else if (lane < K) {
+        out_ids[(int64_t)q * K + lane] = -1;
+        out_d[(int64_t)q * K + lane] = 0.0f;
+    }
+    if (lane == 0) {
+        counts[q] = (int32_t)kept;
+        out_m[q] = m;
+    }
+}
+
+hipError_t launch_knn_tofl(int Q, int L, int64_t N, int t, int D, int K, const uint2* bins, const uint32_t* tids,
+                           const float* qfeat, const float* xf, int32_t* counts, int32_t* ids, float* d, int32_t* m,
+                           hipStream_t st) {
+    if (Q == 0) return hipSuccess;
+    if (L < 1 || L > 64 || t < 1 || t > L || K < 1 || K > kMaxK || D < 1 || D > kL1MaxD) return hipErrorInvalidValue;
+    const dim3 grid((Q + 3) / 4);
+    if (D == 100) hipLaunchKernelGGL(k_knn_tofl<100>, grid, dim3(256), 0, st, Q, L, N, t, D, K, bins, tids, qfeat, xf, counts, ids, d, m);
+    else if (D == 25) hipLaunchKernelGGL(k_knn_tofl<25>, grid, dim3(256), 0, st, Q, L, N, t, D, K, bins, tids, qfeat, xf, counts, ids, d, m);
+    else hipLaunchKernelGGL(k_knn_tofl<0>, grid, dim3(256), 0, st, Q, L, N, t, D, K, bins, tids, qfeat, xf, counts, ids, d, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_cand_t(int Q, int L, int64_t N, int t, const uint2* bins, const uint32_t* tids, int cap,
                          int32_t* counts, int32_t* ids, hipStream_t st) {
     if (Q == 0) return hipSuccess;

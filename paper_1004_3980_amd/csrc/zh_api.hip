@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,10 +48,9 @@ struct Dict {
     float inv_s2 = 0.f;           // lower bound of 1 / sigma_max(Phi)^2
     float rot_c1 = 0.f;           // error-bound coefficient of the query rotation
     std::vector<float> h_alpha, h_beta;
+    uint64_t feat_hash = 0;       // content hash of the features the tables were built on
 };
 
-constexpr int kNumCounters = 8;
-enum { C_OVERFLOW = 0, C_RANKFB = 1, C_UNSUP = 2, C_CODEFIX = 3, C_LLE64 = 4 };
 
 }  // namespace
 
@@ -59,6 +59,10 @@ struct zh_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     size_t mem_limit = 0, mem_used = 0;
+    // bumped whenever a device buffer of the context is allocated, freed or a
+    // dictionary is rebuilt: a captured batch graph holds the addresses and
+    // the dictionary parameters of the time it was captured
+    uint64_t gen = 0;
     Dict dicts[kMaxScale + 1];    // scale 1 .. kMaxScale (index = scale)
     zh_query_opts opts{0, 0, 1, 1};
     // last query
@@ -89,6 +93,7 @@ struct zh_ctx {
     int64_t Q = 0;
     Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv, guides, bwd, bwd_k, clam;
     Buf qrot;                     // [Q, 64] rotated queries of the screen
+    Buf chk;                      // flag of the training-position check
     Buf bwd_gw;                   // [Q, 8] FP64 scratch of the lambda adjoint
     Buf bwd_part;                 // partial row gradients of the dictionary-gradient passes
     Buf tools;                    // scratch of the training-crop sampler and the entropy diagnostic
@@ -123,6 +128,7 @@ zh_status fail(zh_ctx* c, zh_status s, const char* fmt, ...) {
 zh_status ensure(zh_ctx* c, Buf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (b.bytes >= bytes) return ZH_OK;
+    ++c->gen;
     if (b.p) {
         hipFree(b.p);
         c->mem_used -= b.bytes;
@@ -145,6 +151,7 @@ void release(zh_ctx* c, Buf& b) {
     if (b.p) {
         hipFree(b.p);
         c->mem_used -= b.bytes;
+        ++c->gen;
     }
     b.p = nullptr;
     b.bytes = 0;
@@ -347,6 +354,32 @@ out:
     return st;
 }
 
+// Content hash of `bytes` bytes of device memory (a multiple of 4), salted by the section.
+zh_status device_hash(zh_ctx* c, const void* p, uint64_t bytes, uint64_t salt, uint64_t* out) {
+    TRY(ensure(c, c->chk, 16));
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, P<uint32_t>(c->chk), 4, 0u);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, launch_hash_words(p, (int64_t)(bytes / 4), salt, P<unsigned long long>(c->chk), c->stream));
+    HIPCHK(c, hipMemcpyAsync(out, c->chk.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ZH_OK;
+}
+
+// The library's own copies of the dictionary features: the split bf16/low
+// planes and the fp32 rows of the exact passes.
+zh_status store_features(zh_ctx* c, Dict& d, const float* feat) {
+    const int64_t n = d.n;
+    const int D = d.D;
+    TRY(ensure(c, d.hi, sizeof(uint16_t) * (size_t)n * hi_stride(D) + 64));
+    TRY(ensure(c, d.lo, sizeof(uint16_t) * (size_t)n * D + 64));
+    HIPCHK(c, hipMemsetAsync(d.hi.p, 0, d.hi.bytes, c->stream));
+    HIPCHK(c, hipMemsetAsync(d.lo.p, 0, d.lo.bytes, c->stream));
+    HIPCHK(c, launch_split_planes(feat, n, D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
+    TRY(ensure(c, d.xf, sizeof(float) * (size_t)n * D + 64));
+    HIPCHK(c, hipMemcpyAsync(d.xf.p, feat, sizeof(float) * (size_t)n * D, hipMemcpyDeviceToDevice, c->stream));
+    return ZH_OK;
+}
+
 zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     SearchArgs a{};
     a.Q = (int)c->Q;
@@ -452,7 +485,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools, &c->l1cand};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools, &c->l1cand, &c->chk};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -488,8 +521,20 @@ zh_status zh_make_dictionary(zh_ctx* c, const float* hr, int n_img, int H, int W
         (mode != ZH_FEAT_MEANREM && mode != ZH_FEAT_GRAD4) || !(sigma > 0.f) || sigma > 5.f)
         return fail(c, ZH_EINVAL, "zh_make_dictionary: bad arguments");
     const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
-    if (h < kPatch || w < kPatch) return fail(c, ZH_EINVAL, "zh_make_dictionary: images too small");
+    if (H / scale < kPatch || W / scale < kPatch) return fail(c, ZH_EINVAL, "zh_make_dictionary: images too small");
     TRY(set_device(c));
+    // every position inside its image, checked on the device before any cut
+    TRY(ensure(c, c->chk, 16));
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, P<uint32_t>(c->chk), 4, 0u);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, launch_check_positions(pos, n, n_img, H / scale - kPatch, W / scale - kPatch, P<uint32_t>(c->chk),
+                                     c->stream));
+    {
+        uint32_t bad = 0;
+        HIPCHK(c, hipMemcpyAsync(&bad, c->chk.p, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (bad) return fail(c, ZH_EINVAL, "zh_make_dictionary: a position lies outside its image");
+    }
     TRY(ensure(c, c->tmp, sizeof(float) * (size_t)n_img * h * w * 5));
     float* lrs = P<float>(c->tmp);
     float* maps = lrs + (size_t)n_img * h * w;
@@ -558,6 +603,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     Dict& d = c->dicts[dict->scale];
     d.valid = false;
     c->stage = 0;
+    ++c->gen;   // the tables and parameters a captured batch graph baked in change
     const int64_t n = dict->n;
     const int D = dict->dim;
     d.scale = dict->scale;
@@ -572,14 +618,8 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     uint64_t cap = 1;
     while (cap < 2 * (uint64_t)n) cap <<= 1;
     d.cap = cap;
-    // split storage of the features
-    TRY(ensure(c, d.hi, sizeof(uint16_t) * (size_t)n * hi_stride(D) + 64));
-    TRY(ensure(c, d.lo, sizeof(uint16_t) * (size_t)n * D + 64));
-    HIPCHK(c, hipMemsetAsync(d.hi.p, 0, d.hi.bytes, c->stream));
-    HIPCHK(c, hipMemsetAsync(d.lo.p, 0, d.lo.bytes, c->stream));
-    HIPCHK(c, launch_split_planes(dict->feat, n, D, P<uint16_t>(d.hi), P<uint16_t>(d.lo), c->stream));
-    TRY(ensure(c, d.xf, sizeof(float) * (size_t)n * D + 64));
-    HIPCHK(c, hipMemcpyAsync(d.xf.p, dict->feat, sizeof(float) * (size_t)n * D, hipMemcpyDeviceToDevice, c->stream));
+    TRY(store_features(c, d, dict->feat));
+    TRY(device_hash(c, dict->feat, sizeof(float) * (uint64_t)n * D, 0, &d.feat_hash));
     TRY(build_screen(c, d, dict->feat));
     // hash parameters
     hash_params(seed, L, k, D, (double)w, d.h_alpha, d.h_beta);
@@ -673,6 +713,217 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     release(c, c->keys_dict);
+    d.valid = true;
+    return ZH_OK;
+}
+
+}  // extern "C"
+
+// ---- tables on disk ------------------------------------------------------------
+namespace {
+
+constexpr int kTabSections = 13;
+constexpr uint32_t kTabVersion = 1;
+constexpr size_t kTabStage = (size_t)32 << 20;   // pinned staging buffer of the file I/O
+
+// File header: everything zh_build_tables decided, the size and content hash
+// of each section, and a hash of the header itself (every byte before
+// header_hash, padding zeroed).
+struct TabHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    int64_t n;
+    int32_t D, scale, mode, L, k, nsec;
+    float w, inv_s2, rot_c1, bc1[2], bc2[2];
+    uint64_t seed, cap, feat_hash;
+    uint64_t sec_bytes[kTabSections], sec_hash[kTabSections];
+    uint64_t header_hash;
+};
+
+uint64_t fnv64(const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+// The device buffers of a dictionary's tables in file order, with the bytes
+// each holds for the parameters in d.
+void tab_sections(Dict& d, Buf* (&buf)[kTabSections], uint64_t (&bytes)[kTabSections]) {
+    const uint64_t m = (uint64_t)d.L * d.k, DP = (uint64_t)((d.D + 31) & ~31);
+    Buf* b[kTabSections] = {&d.alpha, &d.beta, &d.bc0[0], &d.bc0[1], &d.ahi, &d.alo, &d.kmul, &d.dir, &d.dfilt,
+                            &d.tids, &d.sc, &d.phi_hi, &d.phi_lo};
+    const uint64_t z[kTabSections] = {4 * m * d.D, 4 * m, 4 * m, 4 * m, 2 * m * DP, 2 * m * DP,
+                                      8 * (uint64_t)d.L * (d.k + 1), sizeof(Slot) * (uint64_t)d.L * d.cap,
+                                      4 * (uint64_t)d.L * dir_filter_words(d.cap), 4 * (uint64_t)d.L * d.n,
+                                      (uint64_t)kScreenBytes * d.n, 2 * (uint64_t)kRotStride * DP,
+                                      2 * (uint64_t)kRotStride * DP};
+    for (int i = 0; i < kTabSections; ++i) {
+        buf[i] = b[i];
+        bytes[i] = z[i];
+    }
+}
+
+struct PinnedStage {
+    void* p = nullptr;
+    ~PinnedStage() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+struct File {
+    FILE* f = nullptr;
+    ~File() {
+        if (f) fclose(f);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+zh_status zh_save_tables(zh_ctx* c, int scale, const char* path) {
+    if (!c) return ZH_EINVAL;
+    if (!path) return fail(c, ZH_EINVAL, "zh_save_tables: null path");
+    if (scale < 1 || scale > kMaxScale || !c->dicts[scale].valid)
+        return fail(c, ZH_ESTATE, "zh_save_tables: no tables for scale %d", scale);
+    TRY(set_device(c));
+    Dict& d = c->dicts[scale];
+    TabHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, "ZHTABLE", 8);
+    h.version = kTabVersion;
+    h.header_bytes = sizeof(TabHeader);
+    h.n = d.n;
+    h.D = d.D;
+    h.scale = d.scale;
+    h.mode = d.mode;
+    h.L = d.L;
+    h.k = d.k;
+    h.nsec = kTabSections;
+    h.w = d.w;
+    h.inv_s2 = d.inv_s2;
+    h.rot_c1 = d.rot_c1;
+    for (int i = 0; i < 2; ++i) {
+        h.bc1[i] = d.bc1[i];
+        h.bc2[i] = d.bc2[i];
+    }
+    h.seed = d.seed;
+    h.cap = d.cap;
+    h.feat_hash = d.feat_hash;
+    Buf* buf[kTabSections];
+    uint64_t bytes[kTabSections];
+    tab_sections(d, buf, bytes);
+    for (int i = 0; i < kTabSections; ++i) {
+        h.sec_bytes[i] = bytes[i];
+        TRY(device_hash(c, buf[i]->p, bytes[i], (uint64_t)i + 1, &h.sec_hash[i]));
+    }
+    h.header_hash = fnv64(&h, offsetof(TabHeader, header_hash));
+    File f;
+    f.f = std::fopen(path, "wb");
+    if (!f.f) return fail(c, ZH_EIO, "zh_save_tables: cannot open %s for writing", path);
+    if (std::fwrite(&h, sizeof(h), 1, f.f) != 1) return fail(c, ZH_EIO, "zh_save_tables: write failed");
+    PinnedStage stage;
+    HIPCHK(c, hipHostMalloc(&stage.p, kTabStage, hipHostMallocDefault));
+    for (int i = 0; i < kTabSections; ++i) {
+        for (uint64_t off = 0; off < bytes[i]; off += kTabStage) {
+            const size_t len = (size_t)std::min<uint64_t>(kTabStage, bytes[i] - off);
+            HIPCHK(c, hipMemcpyAsync(stage.p, static_cast<char*>(buf[i]->p) + off, len, hipMemcpyDeviceToHost,
+                                     c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (std::fwrite(stage.p, 1, len, f.f) != len) return fail(c, ZH_EIO, "zh_save_tables: write failed");
+        }
+    }
+    if (std::fclose(f.f) != 0) {
+        f.f = nullptr;
+        return fail(c, ZH_EIO, "zh_save_tables: close failed");
+    }
+    f.f = nullptr;
+    return ZH_OK;
+}
+
+zh_status zh_load_tables(zh_ctx* c, const zh_dictionary* dict, const char* path) {
+    if (!c) return ZH_EINVAL;
+    if (!path) return fail(c, ZH_EINVAL, "zh_load_tables: null path");
+    if (!dict || !dict->feat || !dict->resid || dict->n < 1 || dict->n >= (1ll << 31) ||
+        (dict->scale < 1 || dict->scale > kMaxScale) ||
+        (dict->feat_mode != ZH_FEAT_MEANREM && dict->feat_mode != ZH_FEAT_GRAD4) ||
+        dict->dim != dim_of(dict->feat_mode))
+        return fail(c, ZH_EINVAL, "zh_load_tables: bad dictionary");
+    TRY(set_device(c));
+    File f;
+    f.f = std::fopen(path, "rb");
+    if (!f.f) return fail(c, ZH_EIO, "zh_load_tables: cannot open %s", path);
+    TabHeader h;
+    if (std::fread(&h, sizeof(h), 1, f.f) != 1 || std::memcmp(h.magic, "ZHTABLE", 8) != 0 ||
+        h.version != kTabVersion || h.header_bytes != sizeof(TabHeader) || h.nsec != kTabSections ||
+        h.header_hash != fnv64(&h, offsetof(TabHeader, header_hash)))
+        return fail(c, ZH_EIO, "zh_load_tables: %s is not a table file of this version (or its header is damaged)", path);
+    if (h.n != dict->n || h.D != dict->dim || h.scale != dict->scale || h.mode != dict->feat_mode)
+        return fail(c, ZH_EINVAL, "zh_load_tables: the file holds tables of another dictionary shape");
+    if (h.L < 1 || h.L > kMaxL || h.k < 1 || h.k > kMaxKHash || !(h.w > 0.f))
+        return fail(c, ZH_EIO, "zh_load_tables: bad parameters in %s", path);
+    uint64_t fh = 0;
+    TRY(device_hash(c, dict->feat, sizeof(float) * (uint64_t)dict->n * dict->dim, 0, &fh));
+    if (fh != h.feat_hash)
+        return fail(c, ZH_EINVAL, "zh_load_tables: the dictionary features differ from those the tables were built on");
+    Dict& d = c->dicts[dict->scale];
+    d.valid = false;
+    c->stage = 0;
+    ++c->gen;
+    d.scale = h.scale;
+    d.D = h.D;
+    d.mode = h.mode;
+    d.n = h.n;
+    d.L = h.L;
+    d.k = h.k;
+    d.w = h.w;
+    d.seed = h.seed;
+    d.cap = h.cap;
+    d.inv_s2 = h.inv_s2;
+    d.rot_c1 = h.rot_c1;
+    for (int i = 0; i < 2; ++i) {
+        d.bc1[i] = h.bc1[i];
+        d.bc2[i] = h.bc2[i];
+    }
+    d.feat_hash = fh;
+    d.resid = dict->resid;
+    {
+        uint64_t cap = 1;
+        while (cap < 2 * (uint64_t)d.n) cap <<= 1;
+        if (cap != d.cap) return fail(c, ZH_EIO, "zh_load_tables: directory size in %s does not match", path);
+    }
+    Buf* buf[kTabSections];
+    uint64_t bytes[kTabSections];
+    tab_sections(d, buf, bytes);
+    for (int i = 0; i < kTabSections; ++i)
+        if (bytes[i] != h.sec_bytes[i]) return fail(c, ZH_EIO, "zh_load_tables: section %d of %s has the wrong size", i, path);
+    TRY(store_features(c, d, dict->feat));
+    PinnedStage stage;
+    HIPCHK(c, hipHostMalloc(&stage.p, kTabStage, hipHostMallocDefault));
+    for (int i = 0; i < kTabSections; ++i) {
+        TRY(ensure(c, *buf[i], bytes[i]));
+        for (uint64_t off = 0; off < bytes[i]; off += kTabStage) {
+            const size_t len = (size_t)std::min<uint64_t>(kTabStage, bytes[i] - off);
+            HIPCHK(c, hipStreamSynchronize(c->stream));   // the stage is free again
+            if (std::fread(stage.p, 1, len, f.f) != len) return fail(c, ZH_EIO, "zh_load_tables: %s is truncated", path);
+            HIPCHK(c, hipMemcpyAsync(static_cast<char*>(buf[i]->p) + off, stage.p, len, hipMemcpyHostToDevice,
+                                     c->stream));
+        }
+        uint64_t sh = 0;
+        TRY(device_hash(c, buf[i]->p, bytes[i], (uint64_t)i + 1, &sh));
+        if (sh != h.sec_hash[i]) return fail(c, ZH_EIO, "zh_load_tables: section %d of %s is damaged", i, path);
+    }
+    // host copies of the hash parameters (zh_get_hash_params)
+    const size_t m = (size_t)d.L * d.k;
+    d.h_alpha.resize(m * d.D);
+    d.h_beta.resize(m);
+    HIPCHK(c, hipMemcpyAsync(d.h_alpha.data(), d.alpha.p, sizeof(float) * m * d.D, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.h_beta.data(), d.beta.p, sizeof(float) * m, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     d.valid = true;
     return ZH_OK;
 }
@@ -1080,7 +1331,7 @@ std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
     v.insert(v.end(), {(uint64_t)b->n_images, (uint64_t)b->K, lb, (uint64_t)b->bp_iters, ss, sr,
                        (uint64_t)c->opts.cap, (uint64_t)c->opts.rerank, (uint64_t)c->opts.proj,
                        (uint64_t)c->opts.lle_fp64, (uint64_t)c->batch.tile, (uint64_t)c->batch.grid_per_cu,
-                       (uint64_t)(uintptr_t)c->stream});
+                       (uint64_t)(uintptr_t)c->stream, c->gen});
     for (int s = 1; s <= kMaxScale; ++s) {
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dir.p);
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dfilt.p);
@@ -1301,7 +1552,9 @@ zh_status zh_run_batch(zh_ctx* c, const zh_batch* b) {
         const hipError_t ei = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(c, ei);
-        B.sig = std::move(sig);
+        // planning sizes (and may reallocate) buffers: the signature is that
+        // of the state the graph was captured against
+        B.sig = batch_signature(c, b);
     }
     HIPCHK(c, hipEventRecord(B.ev_in, c->stream));
     HIPCHK(c, hipStreamWaitEvent(B.stream, B.ev_in, 0));
@@ -1436,14 +1689,11 @@ zh_status zh_knn_t(zh_ctx* c, int t) {
     Dict& d = c->dicts[c->qscale];
     if (t < 1 || t > d.L) return fail(c, ZH_EINVAL, "zh_knn_t: need 1 <= t <= L = %d", d.L);
     TRY(set_device(c));
-    TRY(ensure(c, c->l1cand, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1) * kRankMaxCand));
     {
         StageTimer tm(c, ZH_T_SEARCH);
-        HIPCHK(c, launch_cand_t((int)c->Q, d.L, d.n, t, P<uint2>(c->qbins), P<uint32_t>(d.tids), kRankMaxCand,
-                                P<int32_t>(c->ncand), P<int32_t>(c->l1cand), c->stream));
-        HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, kRankMaxCand, false, P<float>(c->qfeat), P<float>(d.xf),
-                                  P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids), P<float>(c->d2),
-                                  P<int32_t>(c->m), c->stream));
+        HIPCHK(c, launch_knn_tofl((int)c->Q, d.L, d.n, t, d.D, c->qK, P<uint2>(c->qbins), P<uint32_t>(d.tids),
+                                  P<float>(c->qfeat), P<float>(d.xf), P<int32_t>(c->ncand), P<int32_t>(c->ids),
+                                  P<float>(c->d2), P<int32_t>(c->m), c->stream));
     }
     c->gram_ready = false;   // the Gram matrices of the new neighbours are formed by zh_lle_weights
     c->stage = 1;
@@ -1488,6 +1738,7 @@ zh_status zh_stats(zh_ctx* c, zh_stats_t* out) {
     out->deferred = h[C_OVERFLOW];
     out->unsupported = h[C_UNSUP];
     out->lle_fp64 = h[C_LLE64];
+    out->truncated = h[C_TRUNC];
     uint64_t db = 0;
     for (const Dict& d : c->dicts)
         db += d.hi.bytes + d.lo.bytes + d.dir.bytes + d.dfilt.bytes + d.tids.bytes + d.alpha.bytes + d.ahi.bytes + d.alo.bytes;

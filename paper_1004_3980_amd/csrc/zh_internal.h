@@ -18,6 +18,12 @@ constexpr int kMaxKHash = 32;   // hashes per table
 constexpr int32_t kCodeUnset = (int32_t)0x80000000;   // MFMA codes lie within +-2^23
 constexpr int kFixSlots = 16;                        // fix-list entries per wave of 16 rows
 
+// Device counters of the last query (uint32 each): patches deferred to the
+// large-union search, FP64 re-ranks, patches beyond the large-union limit,
+// codes fixed in FP64, fp32 LLE solves redone in FP64, screened patches whose
+// survivors exceeded the exact-row limit.
+enum { C_OVERFLOW = 0, C_RANKFB = 1, C_UNSUP = 2, C_CODEFIX = 3, C_LLE64 = 4, C_TRUNC = 5, kNumCounters = 8 };
+
 struct Taps {                   // normalised 1-D Gaussian, offsets -R..R
     double g[kMaxTaps];
     int R;
@@ -34,6 +40,10 @@ hipError_t launch_gradient_maps(const float* lr, int n_img, int h, int w, float*
 // features of every stride-1 patch of one LR image (row-major patch order)
 hipError_t launch_query_features(const float* lr, const float* maps, int h, int w, int mode,
                                  float* feat, double* mu, hipStream_t st);
+// flag[0] set to 1 when a position (image, i, j) of pos[n, 3] is outside
+// [0, n_img) x [0, imax] x [0, jmax]
+hipError_t launch_check_positions(const int32_t* pos, int64_t n, int n_img, int imax, int jmax, uint32_t* flag,
+                                  hipStream_t st);
 hipError_t launch_dict_cut(const float* hr, const float* lr, const float* maps, int H, int W,
                            int scale, const int32_t* pos, int64_t n, int mode, float* feat,
                            float* resid, hipStream_t st);
@@ -104,6 +114,10 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
                             int bits, uint32_t* hist, int64_t hist_cap, hipStream_t st,
                             bool* result_in_first);
 int64_t radix_hist_size(int64_t n);
+// adds the content hash of n_words 32-bit words at p into *out (cleared by
+// the caller): sum_i fmix64((i G + salt) ^ word_i) mod 2^64, G = kGolden
+hipError_t launch_hash_words(const void* p, int64_t n_words, uint64_t salt, unsigned long long* out,
+                             hipStream_t st);
 
 // ---- search (k_search.hip) ---------------------------------------------------
 struct SearchArgs {
@@ -192,6 +206,11 @@ hipError_t launch_knn_rank(int Q, int D, int K, int cap, bool l1, const float* q
                            const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
                            hipStream_t st);
 constexpr int kRankMaxCand = 256;   // candidates a patch the re-rank kernels take
+// K nearest (squared l2, sequential FP64) of each patch's t-of-L candidates,
+// any number of them; counts[Q] the t-of-L counts
+hipError_t launch_knn_tofl(int Q, int L, int64_t N, int t, int D, int K, const uint2* bins, const uint32_t* tids,
+                           const float* qfeat, const float* xf, int32_t* counts, int32_t* ids, float* d, int32_t* m,
+                           hipStream_t st);
 hipError_t launch_cand_t(int Q, int L, int64_t N, int t, const uint2* bins, const uint32_t* tids, int cap,
                          int32_t* counts, int32_t* ids, hipStream_t st);
 int64_t entropy_scratch_bytes(int L, uint64_t cap);

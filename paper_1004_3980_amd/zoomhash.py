@@ -16,10 +16,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzoomhash.so")
 
-ZH_OK, ZH_EINVAL, ZH_ESTATE, ZH_ENOMEM, ZH_EDEVICE, ZH_EUNSUPPORTED = range(6)
+ZH_OK, ZH_EINVAL, ZH_ESTATE, ZH_ENOMEM, ZH_EDEVICE, ZH_EUNSUPPORTED, ZH_EIO = range(7)
 ZH_FEAT_MEANREM, ZH_FEAT_GRAD4 = 0, 1
 STATUS_NAMES = {0: "ZH_OK", 1: "ZH_EINVAL", 2: "ZH_ESTATE", 3: "ZH_ENOMEM", 4: "ZH_EDEVICE",
-                5: "ZH_EUNSUPPORTED"}
+                5: "ZH_EUNSUPPORTED", 6: "ZH_EIO"}
 
 
 class ZHError(RuntimeError):
@@ -43,7 +43,7 @@ class zh_stats_t(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_uint64), ("codes_fixed", ctypes.c_uint64),
                 ("rank_fallbacks", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
                 ("unsupported", ctypes.c_uint64), ("lle_fp64", ctypes.c_uint64),
-                ("dict_bytes", ctypes.c_uint64)]
+                ("dict_bytes", ctypes.c_uint64), ("truncated", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -77,6 +77,8 @@ SIGNATURES = {
     "zh_knn_t": [_V, _I],
     "zh_candidates_t": [_V, _I, _I, _V, _V],
     "zh_build_tables": [_V, ctypes.POINTER(zh_dictionary), _I, _I, _F, _U64],
+    "zh_save_tables": [_V, _I, ctypes.c_char_p],
+    "zh_load_tables": [_V, ctypes.POINTER(zh_dictionary), ctypes.c_char_p],
     "zh_get_hash_params": [_V, _I, _V, _V],
     "zh_hash": [_V, _I, _V, _I64, _V, _V],
     "zh_set_query_opts": [_V, ctypes.POINTER(zh_query_opts)],
@@ -197,6 +199,20 @@ class Context:
     def build_tables(self, feat, resid, n, dim, scale, feat_mode, L, k, w, seed):
         d = zh_dictionary(n, dim, scale, feat_mode, _ptr(feat), _ptr(resid))
         self._chk(self.lib.zh_build_tables(self.h, ctypes.byref(d), L, k, w, seed))
+        self._keep = [t for t in self._keep if getattr(t, "_zh_scale", None) != scale]
+        for t in (feat, resid):
+            try:
+                t._zh_scale = scale
+            except AttributeError:
+                pass
+            self._keep.append(t)
+
+    def save_tables(self, scale, path):
+        self._chk(self.lib.zh_save_tables(self.h, scale, os.fsencode(path)))
+
+    def load_tables(self, feat, resid, n, dim, scale, feat_mode, path):
+        d = zh_dictionary(n, dim, scale, feat_mode, _ptr(feat), _ptr(resid))
+        self._chk(self.lib.zh_load_tables(self.h, ctypes.byref(d), os.fsencode(path)))
         self._keep = [t for t in self._keep if getattr(t, "_zh_scale", None) != scale]
         for t in (feat, resid):
             try:

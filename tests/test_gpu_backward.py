@@ -25,6 +25,8 @@ MID = dict(test_h=44, test_w=40, dict_images=8, dict_hr=128, n_dict=20000, L=8, 
 # zoom x1 (5 x 5 HR patches) and x4 (20 x 20, more values than a wave's four chunks)
 SMALL1 = dict(SMALL, scale=1)
 SMALL4 = dict(SMALL, scale=4, dict_hr=128)
+# the parameters of the 1024^2 workload (L = 24, k = 20, K = 8, early stop 72)
+HEADP = dict(test_h=40, test_w=36, dict_images=8, dict_hr=128, n_dict=20000, L=24, k=20, w=32.0, K=8)
 _cache = {}
 
 
@@ -64,7 +66,8 @@ def _compare(g_gpu, glam_gpu, g_ref, glam_ref, used):
 
 @pytest.mark.parametrize("cfg,bp_iters,sigma_r,cap", [(SMALL, 0, 0.1, 0), (SMALL, 3, 0.1, 0), (SMALL, 2, math.inf, 0),
                                                       (MID, 3, 0.1, 0), (SMALL, 3, 0.1, 20), (MID, 3, 0.1, 40),
-                                                      (SMALL1, 2, 0.1, 0), (SMALL4, 2, 0.1, 0), (SMALL4, 2, 0.1, 20)])
+                                                      (SMALL1, 2, 0.1, 0), (SMALL4, 2, 0.1, 0), (SMALL4, 2, 0.1, 20),
+                                                      (HEADP, 3, 0.1, 72)])
 def test_backward_matches_oracle_gradient(gpu_ok, cfg, bp_iters, sigma_r, cap):
     """cap > 0: the early-stop search, whose FP64 Gram matrices the lambda
     adjoint takes over; cap = 0: the union search, Gram matrices formed in the

@@ -124,3 +124,35 @@ def test_batch_argument_errors():
         st["ctx"].run_batch([lr], [out], [2], 0, 1e-3, 1, 1.5, 0.1)     # K = 0
     with pytest.raises(ValueError):
         st["ctx"].run_batch([lr], [], [2], 5, 1e-3, 1, 1.5, 0.1)
+
+
+def test_batch_graph_recaptured_after_buffers_or_tables_change():
+    """A captured batch graph holds the addresses of the context's buffers and
+    the parameters of its tables. A zh_query on a larger image with a larger
+    K (the query buffers are reallocated) and a rebuild of the x2 tables with
+    other parameters both happen between two zh_run_batch calls of the same
+    batch: each later call must capture again and still equal the images run
+    one by one."""
+    st = _setup()
+    torch, ctx = st["torch"], st["ctx"]
+    ref = _one_by_one(st, 1, 5, 1e-3, 1.5, 0.1)
+    got, _ = _batch(st, 1, 5, 1e-3, 1.5, 0.1)
+    for r, g in zip(ref, got):
+        assert torch.equal(r, g)
+    big = torch.from_numpy(synthdata.fractal_voronoi_image(synthdata.SEED_BASE + 7100, 120, 100)).cuda()
+    ctx.query(big, 120, 100, 2, 16)
+    ctx.lle_weights(1e-3)
+    got2, _ = _batch(st, 1, 5, 1e-3, 1.5, 0.1)
+    for r, g, sz in zip(ref, got2, SIZES):
+        assert torch.equal(r, g), sz
+    # other x2 tables (L = 6, k = 6), then the original ones again
+    g2, wl2 = st["g2"], st["wl2"]
+    try:
+        ctx.build_tables(g2.feat, g2.resid, g2.n, g2.D, 2, wl2.feat_mode, 6, 6, wl2.w, wl2.hash_seed)
+        ref3 = _one_by_one(st, 1, 5, 1e-3, 1.5, 0.1)
+        got3, _ = _batch(st, 1, 5, 1e-3, 1.5, 0.1)
+        for r, g, sz in zip(ref3, got3, SIZES):
+            assert torch.equal(r, g), sz
+        assert any(not torch.equal(a, b) for a, b, sz in zip(ref, ref3, SIZES) if sz[2] == 2)
+    finally:
+        ctx.build_tables(g2.feat, g2.resid, g2.n, g2.D, 2, wl2.feat_mode, wl2.L, wl2.k, wl2.w, wl2.hash_seed)
