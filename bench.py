@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(*a):
@@ -294,7 +295,7 @@ def main():
         f"stages ms {json.dumps({k: round(v, 4) for k, v in ms_stage.items()})}")
 
     # dominant kernel: the candidate search
-    dom = max(("hash", "search", "lle", "synth", "blend"), key=lambda k: ms_stage[k])
+    dom = max(("hash", "probe", "search", "lle", "synth", "blend"), key=lambda k: ms_stage[k])
     sb = search_bytes(res["ncand"], res["nsurv"], wl, 4 if args.form == "screened" else 8)
     ach = sb / (ms_stage["search"] * 1e-3) / 1e9
     traffic = traffic_from_profile(args.form) if own_scale and args.metric == "l2" else None
@@ -302,6 +303,13 @@ def main():
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes": sb, "launch_ms": round(ms_stage["search"], 4),
             "dominant_stage": dom}
+    # the projection of the hash (Eq. hash_fn) against the bf16 matrix-core peak:
+    # useful flops 2 Q D L k over the hash stage (projection, codes, keys, FP64 fixes)
+    hflop = 2.0 * Q * wl.D * wl.L * wl.k
+    hach = hflop / (ms_stage["hash"] * 1e-3) / 1e12 if ms_stage["hash"] > 0 else 0.0
+    hash_roof = {"bound": "mfma", "kernel": "k_hash", "achieved": round(hach, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
+                 "unit": "TFLOP/s", "frac": round(hach / MFMA_BF16_PEAK_TFLOPS, 4), "flops": hflop,
+                 "launch_ms": round(ms_stage["hash"], 4)}
 
     # other form on the same image, back-projection, whole path with back-projection
     other = "exact" if args.form == "screened" else "screened"
@@ -323,6 +331,7 @@ def main():
     stats = g.ctx.stats()
 
     extra = {"ms_per_stage": {k: round(v, 4) for k, v in ms_stage.items()},
+             "hash_roofline": hash_roof,
              "backprojection_ms": round(bp_ms, 3), "bp_iters": wl.bp_iters,
              "value_with_backprojection": Q / (dt / args.steps + bp_ms * 1e-3),
              "other_form": other_rec,

@@ -94,6 +94,29 @@ zh_status zh_make_dictionary(zh_ctx* ctx, const float* hr, int n_img, int H, int
                              const int32_t* pos, int64_t n, int scale, float sigma,
                              int feat_mode, float* feat, float* resid);
 
+/* Interpolated pairing (Section 2.1: the LR training images are interpolated
+ * back to the size of the HR images and both are cut into overlapping
+ * patches at the same places). zh_upsample writes that interpolation of an
+ * LR image lr[h, w] into out[scale h, scale w]: bicubic, Keys' cubic with
+ * a = -0.5, HR pixel X sampling LR coordinate X / scale (phase 0), taps
+ * floor - 1 .. floor + 2 with replicate border, in FP64 (along x for each of
+ * the four rows, then along y; the weights from the host's libm) and rounded
+ * once to fp32. 1 <= scale <= 4.
+ * zh_make_dictionary_interp cuts n pairs at HR-grid positions pos[n, 3] =
+ * (image, r, c), 0 <= r <= H - 5, 0 <= c <= W - 5 (checked as for
+ * zh_make_dictionary): the LR patch is the 5 x 5 patch at (r, c) of the
+ * degraded image (sigma, scale) interpolated back by zh_upsample, its
+ * features feat[n, D] as for zh_make_dictionary, and resid[n, 25] the 5 x 5
+ * HR patch at (r, c) minus the mean of the LR patch. H and W must be
+ * multiples of scale. These pairs have 5 x 5 HR patches: build their tables
+ * with dictionary scale 1 and query the zh_upsample of the LR image at
+ * scale 1; zh_backproject_lr then refines the result against the LR image.
+ * Temporary device buffer: n_img (H W (5 + 1 / scale^2)) floats. */
+zh_status zh_upsample(zh_ctx* ctx, const float* lr, int h, int w, int scale, float* out);
+zh_status zh_make_dictionary_interp(zh_ctx* ctx, const float* hr, int n_img, int H, int W,
+                                    const int32_t* pos, int64_t n, int scale, float sigma,
+                                    int feat_mode, float* feat, float* resid);
+
 /* Training crops (Section 5, training data generation): draw crop centres
  * from the first-order-gradient distribution of each training image and cut
  * side x side crops around them.
@@ -256,6 +279,20 @@ zh_status zh_knn_l1(zh_ctx* ctx);
  * lambda * trace(G) to the diagonal of the Gram matrix G (lambda > 0). */
 zh_status zh_lle_weights(zh_ctx* ctx, double lambda);
 
+/* LLE over all M matches (Section 4.2: Eq. LinSys and Eq. HR_Rec with m
+ * running over every match the search found, not only the K nearest). Needs
+ * the early stop of the last zh_query (query option cap, 1 <= cap <= 80;
+ * else ZH_EUNSUPPORTED): the search runs again and lists each patch's M <=
+ * cap candidates ascending; the weights minimise ||y - sum_m w_m y_m||^2
+ * subject to sum_m w_m = 1 with lambda trace(G) added to the diagonal of the
+ * M x M Gram matrix G (FP64: exact differences, Cholesky, two triangular
+ * solves; uniform weights when trace(G) = 0). ids[Q, cap] and w[Q, cap]
+ * (device, each nullable) receive the lists (-1 past M) and the weights
+ * (0 past M). zh_reconstruct then synthesises every HR patch from all of
+ * its M matches; zh_backward returns ZH_EUNSUPPORTED until the next
+ * zh_lle_weights. */
+zh_status zh_lle_all(zh_ctx* ctx, double lambda, int32_t* ids, float* w);
+
 /* HR image hr_out[s h, s w]: each patch x_q = mean(LR patch) + sum_m w_m r_m
  * (Eq. HR_Rec on the residuals), overlaps averaged per pixel (Section 4
  * prior); pixels covered by no patch with a neighbour take the bicubic
@@ -271,6 +308,15 @@ zh_status zh_reconstruct(zh_ctx* ctx, float* hr_out);
  * +inf (plain Gaussian back-projection). Uses the LR image of the last
  * zh_query and the blur sigma of the degradation (1.0). */
 zh_status zh_backproject(zh_ctx* ctx, float* hr_inout, int iters, float sigma_s, float sigma_r);
+
+/* The back-projection of zh_backproject on hr_inout[scale h, scale w]
+ * against an explicit LR image lr[h, w] (device) and zoom factor (1 .. 4),
+ * independent of the last query (the interpolated pairing of Section 2.1
+ * queries the upsampled image at zoom factor 1 and is refined against the
+ * original LR image). Not recorded for zh_backward: after it, zh_backward on
+ * the last zh_reconstruct returns ZH_ESTATE. */
+zh_status zh_backproject_lr(zh_ctx* ctx, float* hr_inout, const float* lr, int h, int w, int scale,
+                            int iters, float sigma_s, float sigma_r);
 
 /* Gradients of a loss L on the output image of the last zh_reconstruct,
  * or of the zh_backproject call that followed it on that image (one call;
@@ -334,9 +380,7 @@ zh_status zh_tune_batch(zh_ctx* ctx, const zh_batch* batch, zh_batch_tuning* out
  * ids[Q, K] int32 (-1 past m), d2[Q, K] squared distances (l1 distances
  * after zh_knn_l1), m[Q] neighbours used, w[Q, K] weights (after
  * zh_lle_weights), ncand[Q] distinct candidates (in early-stop mode at most
- * cap; for a patch whose bins hold more than 8192 IDs without a cap, m = -1
- * and ncand the sum of its bin sizes: zh_candidates_t with t = 1 counts its
- * distinct IDs). */
+ * cap). */
 zh_status zh_get_results(zh_ctx* ctx, int32_t* ids, float* d2, int32_t* m, float* w,
                          int32_t* ncand);
 /* Candidates of each patch of the last zh_query that reached the exact
@@ -357,7 +401,9 @@ typedef struct {
     uint64_t codes_fixed;       /* codes decided by the FP64 recomputation */
     uint64_t rank_fallbacks;    /* patches re-ranked by FP64 distances */
     uint64_t deferred;          /* patches sent to the large-union path */
-    uint64_t unsupported;       /* patches whose bins exceed 8192 IDs without a cap */
+    uint64_t streamed;          /* patches whose bins hold more than 8192 IDs without
+                                   a cap: their union is merged from the sorted bins
+                                   and ranked by FP64 distances in a streaming pass */
     uint64_t lle_fp64;          /* fp32 solves redone in FP64 */
     uint64_t dict_bytes;        /* device bytes held for dictionaries and tables */
     uint64_t truncated;         /* screened early-stop search (rerank = R): patches
@@ -373,10 +419,12 @@ zh_status zh_stats(zh_ctx* ctx, zh_stats_t* out);
 
 /* ---- stage timing (HIP events on the context's stream) ----------------- */
 enum { ZH_T_FEATURES = 0, ZH_T_HASH = 1, ZH_T_SEARCH = 2, ZH_T_LLE = 3, ZH_T_SYNTH = 4,
-       ZH_T_BLEND = 5, ZH_T_BP_ERROR = 6, ZH_T_BP_UPDATE = 7, ZH_T_ROTATE = 8, ZH_T_COUNT = 9 };
-/* ZH_T_SEARCH times the candidate search kernel alone; ZH_T_ROTATE the
- * projection of the queries onto the dictionary's screen directions that
- * precedes it (early-stop search only). */
+       ZH_T_BLEND = 5, ZH_T_BP_ERROR = 6, ZH_T_BP_UPDATE = 7, ZH_T_ROTATE = 8, ZH_T_PROBE = 9,
+       ZH_T_COUNT = 10 };
+/* ZH_T_HASH times the projection, codes and keys (with their FP64 fixes);
+ * ZH_T_PROBE the lookup of the keys' bins; ZH_T_SEARCH the candidate search
+ * kernel alone; ZH_T_ROTATE the projection of the queries onto the
+ * dictionary's screen directions that precedes it (early-stop search only). */
 /* on != 0: bracket every kernel launch of the stages above with a pair of HIP
  * events (at most 256 launches per stage between two zh_get_timing calls;
  * later launches are not timed). on = 0 stops recording. */

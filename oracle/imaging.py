@@ -228,3 +228,30 @@ def build_dictionary(hr_stack: np.ndarray, positions: np.ndarray, scale: int, mo
                 hp[:, a * ps + b] = hr[scale * ij[:, 0] + a, scale * ij[:, 1] + b]
         resid[sel] = (hp - mu[:, None]).astype(np.float32)
     return Dictionary(feat, resid, scale, mode, lr_mean)
+
+
+# ---------------------------------------------------------------------------
+# Interpolated pairing (Section 2.1): the LR training images are interpolated
+# back to the size of the HR images and both are cut at the same places
+# ---------------------------------------------------------------------------
+def interpolated_lr(lr: np.ndarray, scale: int) -> np.ndarray:
+    """The LR image brought back to the HR grid: bicubic_up (FP64) of the fp32
+    LR image, rounded once to fp32."""
+    return bicubic_up(np.asarray(lr, dtype=np.float32), scale).astype(np.float32)
+
+
+def build_dictionary_interp(hr_stack: np.ndarray, positions: np.ndarray, scale: int, mode: int,
+                            sigma: float = 1.0) -> Dictionary:
+    """Pairs of 5x5 patches at HR-grid positions (image, r, c): the LR patch
+    from the degraded image interpolated back to the HR size, the HR patch
+    from the HR image at the same place (a dictionary of HR patch side 5,
+    queried at zoom factor 1). H and W must be multiples of the scale."""
+    H, W = hr_stack.shape[1:]
+    assert H % scale == 0 and W % scale == 0
+    ups = {}
+    for im in np.unique(positions[:, 0]):
+        ups[im] = interpolated_lr(degrade(hr_stack[im], scale, sigma), scale)
+    lr_stack = np.zeros(hr_stack.shape, dtype=np.float32)
+    for im, u in ups.items():
+        lr_stack[im] = u
+    return build_dictionary(hr_stack, positions, 1, mode, sigma, lr_stack=lr_stack)

@@ -50,14 +50,19 @@ class QueryResult:
     m: np.ndarray            # [Q] number of neighbours used (min(K, |C|))
     weights: np.ndarray      # [Q, K] FP64, 0 past m
     patches: list            # Q synthesised HR patches (FP64) or None
+    all_weights: list = None  # all_matches: Q arrays of weights over cand[q] (in cand order)
 
 
 def query(pre: Prepared, lr: np.ndarray, K: int, lam: float, pos=None,
-          synthesize: bool = True, cap: int = 0, metric: str = "l2", t: int = 0) -> QueryResult:
+          synthesize: bool = True, cap: int = 0, metric: str = "l2", t: int = 0,
+          all_matches: bool = False) -> QueryResult:
     """metric "l2": neighbours by squared l2 distance (the LLE objective);
     "l1": by l1 distance (the hash's metric); the LLE weights are the same
     l2 solve for both. t > 0: the candidates are the IDs in at least t of the
-    L bins (Section 4.1) instead of the union / early stop."""
+    L bins (Section 4.1) instead of the union / early stop.
+    all_matches: the weights are solved over all M matches of the patch
+    (Eq. LinSys with m = 1..M, Section 4.2) and the HR patch is synthesised
+    from all of them (Eq. HR_Rec); the K nearest are still reported."""
     mode = pre.dictionary.mode
     lr = np.asarray(lr, dtype=np.float32)
     if pos is None:
@@ -76,6 +81,7 @@ def query(pre: Prepared, lr: np.ndarray, K: int, lam: float, pos=None,
     m = np.zeros(Q, dtype=np.int64)
     wts = np.zeros((Q, K))
     patches = [None] * Q
+    all_w = [None] * Q if all_matches else None
     D = pre.dictionary
     for q in range(Q):
         nid, nd = (lle.knn_l1 if metric == "l1" else lle.knn)(feat[q], D.feat, cand[q], K)
@@ -85,11 +91,36 @@ def query(pre: Prepared, lr: np.ndarray, K: int, lam: float, pos=None,
         d2[q, :mq] = nd
         if mq == 0:
             continue
+        if all_matches:
+            wa = lle.lle_weights(feat[q], D.feat[cand[q]], lam)
+            all_w[q] = wa
+            if synthesize:
+                patches[q] = lle.synthesize(mu[q], wa, D.resid[cand[q]])
+            continue
         w = lle.lle_weights(feat[q], D.feat[nid], lam)
         wts[q, :mq] = w
         if synthesize:
             patches[q] = lle.synthesize(mu[q], w, D.resid[nid])
-    return QueryResult(pos, feat, mu, c, keys, bsz, cand, ids, d2, m, wts, patches)
+    return QueryResult(pos, feat, mu, c, keys, bsz, cand, ids, d2, m, wts, patches, all_w)
+
+
+def prepare_interp(hr_stack, positions, scale, mode, L, k, w, seed, sigma=1.0) -> Prepared:
+    """Tables over interpolated pairs (Section 2.1): positions on the HR
+    grid, 5x5 HR patches (used at zoom factor 1)."""
+    d = imaging.build_dictionary_interp(hr_stack, positions, scale, mode, sigma)
+    alpha, beta = lsh.hash_params(seed, L, k, d.feat.shape[1], w)
+    keys = lsh.bucket_keys(lsh.codes(d.feat, alpha, beta, w), L, k)
+    return Prepared(d, alpha, beta, lsh.Tables(keys), keys, L, k, w)
+
+
+def run_interp(pre: Prepared, lr, scale, K, lam, bp_iters, sigma_s=1.5, sigma_r=0.1, sigma=1.0, cap=0):
+    """The interpolated pairing end to end: the LR image interpolated to the
+    HR grid, queried at zoom factor 1 (5x5 HR patches, stride 1), blended,
+    then back-projected against the LR image at its own zoom factor."""
+    up = imaging.interpolated_lr(lr, scale)
+    qr = query(pre, up, K, lam, cap=cap)
+    hr, _ = reconstruct(qr, up, 1)
+    return qr, up, hr, backproject(hr, lr, scale, bp_iters, sigma, sigma_s, sigma_r)
 
 
 def reconstruct(qr: QueryResult, lr: np.ndarray, scale: int):

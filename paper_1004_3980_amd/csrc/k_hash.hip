@@ -660,6 +660,23 @@ static void launch_split(const HashArgs& a, dim3 grid, size_t lds, hipStream_t s
 }
 
 hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
+    const hipError_t e = launch_hash_codes(a, st);
+    if (e != hipSuccess || !a.bins) return e;
+    return launch_probe(a, st);
+}
+
+hipError_t launch_probe(const HashArgs& a, hipStream_t st) {
+    if (a.n == 0 || !a.bins) return hipSuccess;
+    if (!a.keys_tmajor || !a.dir || !a.dir_filter) return hipErrorInvalidValue;
+    const int64_t total = a.n * a.L;
+    int64_t g = (total + 256 * kProbeRows - 1) / (256 * kProbeRows);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_probe, dim3((unsigned)g), dim3(256), 0, st, a.keys, a.n, a.L, a.dir, a.dir_cap,
+                       a.dir_filter, a.bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_codes(const HashArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
     if (a.D < 1 || a.D > 128 || a.k < 1 || a.k > 32 || a.L < 1 || a.L > 64 || !a.dirty || !a.fix_count || !a.key_mul ||
         a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list) ||
@@ -692,13 +709,6 @@ hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
     const dim3 gfix((unsigned)((a.n + 63) / 64));
     const size_t lfix = (size_t)fix_groups(a.k) * (a.k + 1) * a.D * sizeof(float);
     hipLaunchKernelGGL(k_hash_fix, gfix, dim3(64), lfix, st, a);
-    e = hipGetLastError();
-    if (e != hipSuccess || !a.bins) return e;
-    const int64_t total = a.n * a.L;
-    int64_t g = (total + 256 * kProbeRows - 1) / (256 * kProbeRows);
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_probe, dim3((unsigned)g), dim3(256), 0, st, a.keys, a.n, a.L, a.dir, a.dir_cap,
-                       a.dir_filter, a.bins);
     return hipGetLastError();
 }
 

@@ -254,6 +254,38 @@ __global__ void k_bicubic(const float* __restrict__ lr, int h, int w, int s, flo
         out[idx] = bicubic_at(lr, h, w, s, (int)(idx / W), (int)(idx % W));
 }
 
+// The LR image interpolated back to the HR grid (Section 2.1, the paired
+// LR images of the training set have the HR images' size): bicubic with
+// Keys' weights (a = -0.5) taken from the host table wt[r][tap] for the
+// phase r = X mod s, taps floor - 1 .. floor + 2, replicate border; FP64,
+// along x first (for each of the four rows), then along y, every sum started
+// at 0 and taken in tap order; rounded once to fp32.
+struct UpWeights {
+    double w[kMaxScale * 2][4];
+};
+__global__ void k_upsample64(const float* __restrict__ lr, int h, int w, int s, UpWeights uw,
+                             float* __restrict__ out) {
+    const int H = s * h, W = s * w;
+    const int64_t total = (int64_t)H * W;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int Y = (int)(idx / W), X = (int)(idx % W);
+        const int i0 = Y / s, j0 = X / s;
+        const double* wy = uw.w[Y - i0 * s];
+        const double* wx = uw.w[X - j0 * s];
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const float* row = lr + (int64_t)clampi(i0 - 1 + a, 0, h - 1) * w;
+            double r = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) r = r + wx[b] * (double)row[clampi(j0 - 1 + b, 0, w - 1)];
+            acc = acc + wy[a] * r;
+        }
+        out[idx] = (float)acc;
+    }
+}
+
 static inline int grid_for(int64_t total, int block) {
     int64_t g = (total + block - 1) / block;
     if (g > 65536) g = 65536;
@@ -355,6 +387,16 @@ hipError_t launch_split_planes(const float* x, int64_t n, int D, uint16_t* hi, u
     return hipGetLastError();
 }
 
+
+hipError_t launch_upsample64(const float* lr, int h, int w, int scale, const double* wt, float* out, hipStream_t st) {
+    if (scale < 1 || scale > 2 * kMaxScale) return hipErrorInvalidValue;
+    UpWeights uw{};
+    for (int r = 0; r < scale; ++r)
+        for (int a = 0; a < 4; ++a) uw.w[r][a] = wt[4 * r + a];
+    hipLaunchKernelGGL(k_upsample64, dim3(grid_for((int64_t)scale * h * scale * w, 256)), dim3(256), 0, st, lr, h, w,
+                       scale, uw, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_bicubic(const float* lr, int h, int w, int scale, float* out, hipStream_t st) {
     hipLaunchKernelGGL(k_bicubic, dim3(grid_for((int64_t)scale * h * scale * w, 256)), dim3(256),

@@ -398,6 +398,114 @@ hipError_t launch_lle_solve(const LleArgs& a, const void* gram, int gram_fp64, h
     return hipGetLastError();
 }
 
+// LLE over all M matches of each patch (Section 4.2: Eq. LinSys with m
+// running over every match found, M <= kAllMax): one wave per patch. The M
+// candidate rows sit in LDS (fp32, odd stride); the packed lower triangle of
+// G = Z Z^T, z_m = q - y_m, is formed in FP64 from exact differences (sums in
+// coordinate order), tau = tr G is added times lambda to the diagonal, the
+// Cholesky factor overwrites it (column by column, lanes over rows), and two
+// triangular solves give w~ = A^-1 1, w = w~ / sum w~. tau = 0 (every
+// candidate equals the query) gives uniform weights. Weights past M are 0 and
+// list entries past M are set to -1.
+__global__ __launch_bounds__(64) void k_lle_all(int Q, int D, int cap, double lam, const float* __restrict__ qfeat,
+                                                const float* __restrict__ xf, int32_t* __restrict__ cand,
+                                                const int32_t* __restrict__ ncand, float* __restrict__ w) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int q = blockIdx.x;
+    const int M = min(ncand[q], cap);
+    const int st = D | 1;
+    double* A = reinterpret_cast<double*>(smem);                        // [cap (cap + 1) / 2]
+    double* y = A + (size_t)cap * (cap + 1) / 2;                         // [cap]
+    double* sq = y + cap;                                               // [D]
+    float* rows = reinterpret_cast<float*>(sq + D);                     // [cap][st]
+    for (int i = lane; i < D; i += 64) sq[i] = (double)qfeat[(int64_t)q * D + i];
+    for (int e = lane; e < M * D; e += 64) {
+        const int r = e / D, c = e - r * D;
+        rows[r * st + c] = xf[(int64_t)cand[(int64_t)q * cap + r] * D + c];
+    }
+    for (int i = M + lane; i < cap; i += 64) cand[(int64_t)q * cap + i] = -1;   // list entries past M
+    __syncthreads();
+    // G, packed: entry (i, j <= i) at i (i + 1) / 2 + j
+    const int np = M * (M + 1) / 2;
+    for (int e = lane; e < np; e += 64) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (i * (i + 1) / 2 > e) --i;
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        const int j = e - i * (i + 1) / 2;
+        const float* ri = rows + i * st;
+        const float* rj = rows + j * st;
+        double g = 0.0;
+        for (int c = 0; c < D; ++c) {
+            const double zi = sq[c] - (double)ri[c];
+            const double zj = sq[c] - (double)rj[c];
+            g = g + zi * zj;
+        }
+        A[e] = g;
+    }
+    __syncthreads();
+    double tau = 0.0;
+    for (int i = lane; i < M; i += 64) tau += A[i * (i + 1) / 2 + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tau += __shfl_xor(tau, o);
+    if (M > 0 && tau == 0.0) {
+        for (int i = lane; i < cap; i += 64) w[(int64_t)q * cap + i] = i < M ? (float)(1.0 / M) : 0.0f;
+        return;
+    }
+    for (int i = lane; i < M; i += 64) A[i * (i + 1) / 2 + i] += lam * tau;
+    __syncthreads();
+    // Cholesky, right-looking: column j, then the trailing rows of later columns
+    for (int j = 0; j < M; ++j) {
+        const int dj = j * (j + 1) / 2 + j;
+        const double d = sqrt(A[dj]);
+        __syncthreads();
+        for (int i = j + 1 + lane; i < M; i += 64) A[i * (i + 1) / 2 + j] /= d;
+        if (lane == 0) A[dj] = d;
+        __syncthreads();
+        for (int i = j + 1 + lane; i < M; i += 64) {
+            const int ri = i * (i + 1) / 2;
+            const double lij = A[ri + j];
+            for (int k = j + 1; k <= i; ++k) A[ri + k] -= lij * A[k * (k + 1) / 2 + j];
+        }
+        __syncthreads();
+    }
+    // L y = 1, then L^T w~ = y (columns in turn, lanes over the other rows)
+    for (int i = lane; i < M; i += 64) y[i] = 1.0;
+    __syncthreads();
+    for (int j = 0; j < M; ++j) {
+        const double yj = y[j] / A[j * (j + 1) / 2 + j];
+        __syncthreads();
+        if (lane == 0) y[j] = yj;
+        for (int i = j + 1 + lane; i < M; i += 64) y[i] -= A[i * (i + 1) / 2 + j] * yj;
+        __syncthreads();
+    }
+    for (int j = M - 1; j >= 0; --j) {
+        const int rj = j * (j + 1) / 2;
+        const double xj = y[j] / A[rj + j];
+        __syncthreads();
+        if (lane == 0) y[j] = xj;
+        for (int i = lane; i < j; i += 64) y[i] -= A[rj + i] * xj;
+        __syncthreads();
+    }
+    double sum = 0.0;
+    for (int i = lane; i < M; i += 64) sum += y[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    for (int i = lane; i < cap; i += 64) w[(int64_t)q * cap + i] = i < M ? (float)(y[i] / sum) : 0.0f;
+}
+
+size_t lle_all_lds(int cap, int D) {
+    return sizeof(double) * ((size_t)cap * (cap + 1) / 2 + cap + D) + sizeof(float) * (size_t)cap * (D | 1);
+}
+
+hipError_t launch_lle_all(int Q, int D, int cap, double lam, const float* qfeat, const float* xf, int32_t* cand,
+                          const int32_t* ncand, float* w, hipStream_t st) {
+    if (Q == 0) return hipSuccess;
+    if (cap < 1 || cap > kAllMax || D < 1 || D > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lle_all, dim3(Q), dim3(64), lle_all_lds(cap, D), st, Q, D, cap, lam, qfeat, xf, cand, ncand, w);
+    return hipGetLastError();
+}
+
 // x_q = mu_q + sum_m w_m r_{n_m}: one wave per patch, lane l holds the
 // values l + 64 u, u < U.
 template <int U>

@@ -898,13 +898,10 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
                     const unsigned int pos = atomicAdd(&a.counters[C_OVERFLOW], 1u);
                     a.overflow[pos] = q;
                 }
-            } else {
-                if (lane == 0) {
-                    a.out_m[q] = -1;
-                    a.out_ncand[q] = T;
-                    atomicAdd(&a.counters[C_UNSUP], 1u);
-                }
-                if (lane < a.K) a.out_ids[(int64_t)q * a.K + lane] = -1;
+            } else if (lane == 0) {
+                // too many for LDS: the streaming pass ranks it (second half of the list)
+                const unsigned int pos = atomicAdd(&a.counters[C_STREAM], 1u);
+                a.overflow[(int64_t)a.Q + pos] = q;
             }
             continue;
         }
@@ -969,6 +966,127 @@ __global__ __launch_bounds__(64) void k_search_union(SearchArgs a) {
     }
 }
 
+// Union search for patches whose bins hold more IDs than LDS takes (any
+// number): one wave per listed patch merges the L bins (each sorted by ID)
+// into the ascending sequence of distinct IDs, lane l streaming bin l from a
+// register buffer of its next eight IDs; every step takes the wave minimum of
+// the heads and advances every bin that holds it. Chunks of 64 distinct IDs
+// get their squared distances as the FP64 sequential sum over the
+// coordinates (the definition, so no certification is needed) and are merged
+// into a running top K held by lanes 0..K-1 (K rounds of a wave minimum over
+// (distance, ID)). Writes the neighbours, their distances rounded to fp32,
+// the distinct-ID count and, when asked, the first dump_cap IDs ascending.
+__global__ __launch_bounds__(64) void k_union_stream(SearchArgs a) {
+    __shared__ uint32_t chunk[64];
+    __shared__ double sq[128];
+    const int lane = threadIdx.x;
+    const int n = (int)a.counters[C_STREAM];
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const int q = a.overflow[(int64_t)a.Q + t];
+        const int D = a.D;
+        for (int i = lane; i < 128; i += 64) sq[i] = i < D ? (double)a.qfeat[(int64_t)q * D + i] : 0.0;
+        uint32_t off = 0, cnt = 0;
+        if (lane < a.L) {
+            const uint2 b = a.bins[(int64_t)lane * a.Q + q];
+            off = b.x;
+            cnt = b.y;
+        }
+        const uint32_t* src = a.tids + (int64_t)lane * a.N + off;
+        uint32_t buf[8];
+        uint32_t pos = 0;   // next position of this lane's bin to load into buf
+        int have = 0, at = 0;
+        auto refill = [&]() {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) buf[e] = (lane < a.L && pos + e < cnt) ? src[pos + e] : 0xFFFFFFFFu;
+            have = (lane < a.L && pos < cnt) ? (int)min(8u, cnt - pos) : 0;
+            pos += 8;
+            at = 0;
+        };
+        refill();
+        double bd = INFINITY;
+        int bi = 0x7FFFFFFF;
+        int nd = 0;
+        __syncthreads();
+        for (;;) {
+            // the next chunk of up to 64 distinct IDs, ascending
+            int nc = 0;
+            for (; nc < 64; ++nc) {
+                uint32_t head = 0xFFFFFFFFu;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (e == at) head = at < have ? buf[e] : 0xFFFFFFFFu;
+                const uint32_t mn = wave_min_u32(head);
+                if (mn == 0xFFFFFFFFu) break;
+                if (head == mn) {
+                    if (++at == have) {
+                        if (pos < cnt) refill();
+                        else have = 0, at = 0;
+                    }
+                }
+                if (lane == 0) chunk[nc] = mn;
+            }
+            __syncthreads();
+            if (nc == 0) break;
+            if (a.dump && lane < nc && nd + lane < a.dump_cap)
+                a.dump[(int64_t)q * a.dump_cap + nd + lane] = (int32_t)chunk[lane];
+            double nd2 = INFINITY;
+            int ni = 0x7FFFFFFF;
+            if (lane < nc) {
+                const float* row = a.xf + (int64_t)chunk[lane] * D;
+                double acc = 0.0;
+                for (int i = 0; i < D; ++i) {
+                    const double z = sq[i] - (double)row[i];
+                    acc = acc + z * z;
+                }
+                nd2 = acc;
+                ni = (int)chunk[lane];
+            }
+            double rd = INFINITY;
+            int rI = 0x7FFFFFFF;
+            for (int k = 0; k < a.K; ++k) {
+                const bool bfirst = bd < nd2 || (bd == nd2 && bi < ni);
+                double md = bfirst ? bd : nd2;
+                int mi = bfirst ? bi : ni;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const double od = __shfl_xor(md, o);
+                    const int oi = __shfl_xor(mi, o);
+                    if (od < md || (od == md && oi < mi)) {
+                        md = od;
+                        mi = oi;
+                    }
+                }
+                if (bi == mi && bd == md) {
+                    bd = INFINITY;
+                    bi = 0x7FFFFFFF;
+                } else if (ni == mi && nd2 == md) {
+                    nd2 = INFINITY;
+                    ni = 0x7FFFFFFF;
+                }
+                if (lane == k) {
+                    rd = md;
+                    rI = mi;
+                }
+            }
+            bd = rd;
+            bi = rI;
+            nd += nc;
+            __syncthreads();
+            if (nc < 64) break;
+        }
+        const int m = min(a.K, nd);
+        if (lane < a.K) {
+            a.out_ids[(int64_t)q * a.K + lane] = lane < m ? bi : -1;
+            a.out_d2[(int64_t)q * a.K + lane] = lane < m ? (float)bd : 0.0f;
+        }
+        if (lane == 0) {
+            a.out_m[q] = m;
+            a.out_ncand[q] = nd;
+        }
+        __syncthreads();
+    }
+}
+
 constexpr int kCapMax = 256;      // early-stop limit a wave can hold
 constexpr int kUnionMax = 2048;   // uncapped: IDs per wave before deferring
 constexpr int kUnionBig = 8192;   // uncapped, deferred patches
@@ -1028,6 +1146,9 @@ hipError_t launch_search_overflow(const SearchArgs& a_in, int grid, hipStream_t 
     const bool v4 = a.D % 4 == 0 && a.D <= 128;
     if (v4) hipLaunchKernelGGL((k_search_union<4, kUnionBig, true>), dim3(grid), dim3(64), 0, st, a);
     else hipLaunchKernelGGL((k_search_union<1, kUnionBig, true>), dim3(grid), dim3(64), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_union_stream, dim3(grid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

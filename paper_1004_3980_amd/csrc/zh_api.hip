@@ -68,6 +68,8 @@ struct zh_ctx {
     // last query
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
+    bool all_m = false;           // the last weights are over all matches (zh_lle_all)
+    int all_cap = 0;              // ... with lists of this many entries a patch
     bool gram_ready = false;      // gram holds the Gram matrices of the last search's neighbours
     int gram_fp64 = 0;            // ... in FP64 (else fp32)
     double lam = 0.0;             // lambda of the last zh_lle_weights
@@ -97,7 +99,8 @@ struct zh_ctx {
     Buf bwd_gw;                   // [Q, 8] FP64 scratch of the lambda adjoint
     Buf bwd_part;                 // partial row gradients of the dictionary-gradient passes
     Buf tools;                    // scratch of the training-crop sampler and the entropy diagnostic
-    Buf l1cand;                   // [Q, cap] candidate lists of the l1 re-rank
+    Buf l1cand;                   // [Q, cap] candidate lists of the l1 re-rank and of zh_lle_all
+    Buf wall;                     // [Q, cap] weights over all matches (zh_lle_all)
     Buf rs_k1, rs_v1, rs_hist, slot_of, idsort, keys_dict;
     // stage timing
     bool timing = false;
@@ -485,7 +488,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
                    &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
-                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools, &c->l1cand, &c->chk};
+                   &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools, &c->l1cand, &c->chk, &c->wall};
     for (Buf* b : bufs) release(c, *b);
     delete c;
 }
@@ -1005,7 +1008,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     TRY(ensure(c, c->w, sizeof(float) * (size_t)Q * K));
     TRY(ensure(c, c->m, sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)Q));
-    TRY(ensure(c, c->over, sizeof(int32_t) * (size_t)Q));
+    TRY(ensure(c, c->over, 2 * sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->xhat, sizeof(float) * (size_t)Q * ps2));
     HIPCHK(c, hipMemcpyAsync(c->lr.p, lr, sizeof(float) * (size_t)h * w, hipMemcpyDeviceToDevice, c->stream));
     c->qh = h;
@@ -1013,6 +1016,7 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     c->qscale = scale;
     c->qK = K;
     c->Q = Q;
+    c->all_m = false;
     TRY(clear_counters(c));
     {
         StageTimer t(c, ZH_T_FEATURES);
@@ -1045,7 +1049,11 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     ha.keys_tmajor = 1;
     {
         StageTimer t(c, ZH_T_HASH);
-        HIPCHK(c, launch_hash(ha, c->stream));
+        HIPCHK(c, launch_hash_codes(ha, c->stream));
+    }
+    {
+        StageTimer t(c, ZH_T_PROBE);
+        HIPCHK(c, launch_probe(ha, c->stream));
     }
     TRY(run_search(c, d, nullptr, 0));
     c->stage = 1;
@@ -1084,6 +1092,36 @@ zh_status zh_lle_weights(zh_ctx* c, double lambda) {
         HIPCHK(c, launch_lle(a, c->stream));
     }
     c->lam = lambda;
+    c->all_m = false;
+    c->stage = 2;
+    return ZH_OK;
+}
+
+zh_status zh_lle_all(zh_ctx* c, double lambda, int32_t* ids, float* w) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_lle_all before zh_query");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, ZH_EINVAL, "zh_lle_all: lambda must be > 0");
+    const int cap = c->opts.cap;
+    if (cap < 1 || cap > kAllMax)
+        return fail(c, ZH_EUNSUPPORTED, "zh_lle_all needs the early stop with cap <= %d (query option cap)", kAllMax);
+    TRY(set_device(c));
+    Dict& d = c->dicts[c->qscale];
+    const size_t Qn = (size_t)(c->Q > 0 ? c->Q : 1);
+    TRY(ensure(c, c->l1cand, sizeof(int32_t) * Qn * cap));
+    TRY(ensure(c, c->wall, sizeof(float) * Qn * cap));
+    TRY(clear_counters(c));
+    // the candidate lists of the last query, ascending (the search runs again and dumps them)
+    TRY(run_search(c, d, P<int32_t>(c->l1cand), cap));
+    {
+        StageTimer t(c, ZH_T_LLE);
+        HIPCHK(c, launch_lle_all((int)c->Q, d.D, cap, lambda, P<float>(c->qfeat), P<float>(d.xf), P<int32_t>(c->l1cand),
+                                 P<int32_t>(c->ncand), P<float>(c->wall), c->stream));
+    }
+    if (ids) HIPCHK(c, hipMemcpyAsync(ids, c->l1cand.p, sizeof(int32_t) * (size_t)c->Q * cap, hipMemcpyDeviceToDevice, c->stream));
+    if (w) HIPCHK(c, hipMemcpyAsync(w, c->wall.p, sizeof(float) * (size_t)c->Q * cap, hipMemcpyDeviceToDevice, c->stream));
+    c->lam = lambda;
+    c->all_m = true;
+    c->all_cap = cap;
     c->stage = 2;
     return ZH_OK;
 }
@@ -1097,8 +1135,13 @@ zh_status zh_reconstruct(zh_ctx* c, float* hr_out) {
     const int s = c->qscale, ps2 = (kPatch * s) * (kPatch * s);
     {
         StageTimer t(c, ZH_T_SYNTH);
-        HIPCHK(c, launch_synth((int)c->Q, c->qK, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
-                               P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
+        if (c->all_m)
+            // every match: M = ncand (at most cap) rows of the dumped lists
+            HIPCHK(c, launch_synth((int)c->Q, c->all_cap, ps2, P<int32_t>(c->l1cand), P<int32_t>(c->ncand),
+                                   P<float>(c->wall), P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
+        else
+            HIPCHK(c, launch_synth((int)c->Q, c->qK, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
+                                   P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
     }
     {
         StageTimer t(c, ZH_T_BLEND);
@@ -1110,21 +1153,20 @@ zh_status zh_reconstruct(zh_ctx* c, float* hr_out) {
     return ZH_OK;
 }
 
-zh_status zh_backproject(zh_ctx* c, float* hr, int iters, float sigma_s, float sigma_r) {
-    if (!c) return ZH_EINVAL;
-    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_backproject needs the LR image of a zh_query");
-    if (!hr || iters < 0 || !(sigma_s > 0.f) || std::ceil(3.0 * sigma_s) > 8.0 || !(sigma_r > 0.f))
-        return fail(c, ZH_EINVAL, "zh_backproject: need iters >= 0, 0 < sigma_s <= 8/3, sigma_r > 0");
-    TRY(set_device(c));
-    const int s = c->qscale, H = s * c->qh, W = s * c->qw;
-    TRY(ensure(c, c->e, sizeof(float) * (size_t)c->qh * c->qw));
+}  // extern "C"
+
+namespace {
+
+// `iters` back-projection steps of hr [s h, s w] against the LR image lr [h, w];
+// record: keep the guides of the steps for zh_backward.
+zh_status backproject_steps(zh_ctx* c, float* hr, const float* lr, int h, int w, int s, int iters, float sigma_s,
+                            float sigma_r, bool record) {
+    const int H = s * h, W = s * w;
+    TRY(ensure(c, c->e, sizeof(float) * (size_t)h * w));
     TRY(ensure(c, c->tmp, sizeof(float) * (size_t)H * W));
     const Taps g = gauss_taps(1.0);
     float* a = hr;
     float* b = P<float>(c->tmp);
-    // keep the guides I^0 .. I^{iters-1} of the first call after zh_reconstruct
-    const bool record = c->stage == 3 && c->bp_rec == 0;
-    if (c->stage == 3 && c->bp_rec != 0) c->bp_rec = -1;
     if (record) {
         TRY(ensure(c, c->guides, sizeof(float) * (size_t)H * W * (size_t)(iters > 0 ? iters : 1)));
         c->bp_rec = 1;
@@ -1138,16 +1180,108 @@ zh_status zh_backproject(zh_ctx* c, float* hr, int iters, float sigma_s, float s
                                      hipMemcpyDeviceToDevice, c->stream));
         {
             StageTimer t1(c, ZH_T_BP_ERROR);
-            HIPCHK(c, launch_degrade_residual(a, H, W, s, g, P<float>(c->lr), P<float>(c->e), c->stream));
+            HIPCHK(c, launch_degrade_residual(a, H, W, s, g, lr, P<float>(c->e), c->stream));
         }
         {
             StageTimer t2(c, ZH_T_BP_UPDATE);
-            HIPCHK(c, launch_bp_update(a, P<float>(c->e), H, W, c->qh, c->qw, s, sigma_s, sigma_r, b, c->stream));
+            HIPCHK(c, launch_bp_update(a, P<float>(c->e), H, W, h, w, s, sigma_s, sigma_r, b, c->stream));
         }
         float* t2 = a; a = b; b = t2;
     }
     if (a != hr)
         HIPCHK(c, hipMemcpyAsync(hr, a, sizeof(float) * (size_t)H * W, hipMemcpyDeviceToDevice, c->stream));
+    return ZH_OK;
+}
+
+// Keys' cubic (a = -0.5) at distance x, written as the oracle's expression
+// (host libm pow), so that the weight tables agree bit for bit.
+double keys_cubic_host(double x) {
+    const double a = -0.5;
+    x = std::fabs(x);
+    if (x <= 1.0) return (a + 2.0) * std::pow(x, 3.0) - (a + 3.0) * std::pow(x, 2.0) + 1.0;
+    if (x < 2.0) return a * std::pow(x, 3.0) - 5.0 * a * std::pow(x, 2.0) + 8.0 * a * x - 4.0 * a;
+    return 0.0;
+}
+
+// wt[4 r + a] = weight of tap a (offset a - 1) at phase t = r / s
+void upsample_weights(int s, double* wt) {
+    for (int r = 0; r < s; ++r) {
+        const double t = (double)r / (double)s;
+        for (int a = 0; a < 4; ++a) wt[4 * r + a] = keys_cubic_host(t - (double)(a - 1));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+zh_status zh_backproject(zh_ctx* c, float* hr, int iters, float sigma_s, float sigma_r) {
+    if (!c) return ZH_EINVAL;
+    if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_backproject needs the LR image of a zh_query");
+    if (!hr || iters < 0 || !(sigma_s > 0.f) || std::ceil(3.0 * sigma_s) > 8.0 || !(sigma_r > 0.f))
+        return fail(c, ZH_EINVAL, "zh_backproject: need iters >= 0, 0 < sigma_s <= 8/3, sigma_r > 0");
+    TRY(set_device(c));
+    // keep the guides I^0 .. I^{iters-1} of the first call after zh_reconstruct
+    const bool record = c->stage == 3 && c->bp_rec == 0;
+    if (c->stage == 3 && c->bp_rec != 0) c->bp_rec = -1;
+    return backproject_steps(c, hr, P<float>(c->lr), c->qh, c->qw, c->qscale, iters, sigma_s, sigma_r, record);
+}
+
+zh_status zh_backproject_lr(zh_ctx* c, float* hr, const float* lr, int h, int w, int scale, int iters, float sigma_s,
+                            float sigma_r) {
+    if (!c) return ZH_EINVAL;
+    if (!hr || !lr || h < 1 || w < 1 || scale < 1 || scale > kMaxScale || iters < 0 || !(sigma_s > 0.f) ||
+        std::ceil(3.0 * sigma_s) > 8.0 || !(sigma_r > 0.f))
+        return fail(c, ZH_EINVAL, "zh_backproject_lr: need h, w >= 1, 1 <= scale <= %d, iters >= 0, "
+                                  "0 < sigma_s <= 8/3, sigma_r > 0", kMaxScale);
+    TRY(set_device(c));
+    if (c->stage == 3) c->bp_rec = -1;   // the output of zh_reconstruct is no longer the recorded chain
+    return backproject_steps(c, hr, lr, h, w, scale, iters, sigma_s, sigma_r, false);
+}
+
+zh_status zh_upsample(zh_ctx* c, const float* lr, int h, int w, int scale, float* out) {
+    if (!c) return ZH_EINVAL;
+    if (!lr || !out || h < 1 || w < 1 || scale < 1 || scale > kMaxScale || (int64_t)scale * h * scale * w >= (1ll << 31))
+        return fail(c, ZH_EINVAL, "zh_upsample: bad arguments");
+    TRY(set_device(c));
+    double wt[4 * kMaxScale];
+    upsample_weights(scale, wt);
+    HIPCHK(c, launch_upsample64(lr, h, w, scale, wt, out, c->stream));
+    return ZH_OK;
+}
+
+zh_status zh_make_dictionary_interp(zh_ctx* c, const float* hr, int n_img, int H, int W, const int32_t* pos, int64_t n,
+                                    int scale, float sigma, int mode, float* feat, float* resid) {
+    if (!c) return ZH_EINVAL;
+    if (!hr || !pos || !feat || !resid || n_img < 1 || n < 1 || n >= (1ll << 31) || scale < 1 || scale > kMaxScale ||
+        (mode != ZH_FEAT_MEANREM && mode != ZH_FEAT_GRAD4) || !(sigma > 0.f) || sigma > 5.f)
+        return fail(c, ZH_EINVAL, "zh_make_dictionary_interp: bad arguments");
+    if (H % scale || W % scale || H < kPatch || W < kPatch || (int64_t)n_img * H * W >= (1ll << 31))
+        return fail(c, ZH_EINVAL, "zh_make_dictionary_interp: H and W must be multiples of scale and >= 5");
+    TRY(set_device(c));
+    TRY(ensure(c, c->chk, 16));
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, P<uint32_t>(c->chk), 4, 0u);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, launch_check_positions(pos, n, n_img, H - kPatch, W - kPatch, P<uint32_t>(c->chk), c->stream));
+    {
+        uint32_t bad = 0;
+        HIPCHK(c, hipMemcpyAsync(&bad, c->chk.p, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (bad) return fail(c, ZH_EINVAL, "zh_make_dictionary_interp: a position lies outside its image");
+    }
+    const int h = H / scale, w = W / scale;
+    const size_t hw = (size_t)h * w, HW = (size_t)H * W;
+    TRY(ensure(c, c->tmp, sizeof(float) * ((size_t)n_img * hw + 5 * (size_t)n_img * HW)));
+    float* lrs = P<float>(c->tmp);
+    float* up = lrs + (size_t)n_img * hw;
+    float* maps = up + (size_t)n_img * HW;
+    double wt[4 * kMaxScale];
+    upsample_weights(scale, wt);
+    HIPCHK(c, launch_degrade(hr, n_img, H, W, scale, gauss_taps(sigma), lrs, c->stream));
+    for (int i = 0; i < n_img; ++i)
+        HIPCHK(c, launch_upsample64(lrs + (size_t)i * hw, h, w, scale, wt, up + (size_t)i * HW, c->stream));
+    HIPCHK(c, launch_gradient_maps(up, n_img, H, W, maps, c->stream));
+    HIPCHK(c, launch_dict_cut(hr, up, maps, H, W, 1, pos, n, mode, feat, resid, c->stream));
     return ZH_OK;
 }
 
@@ -1157,6 +1291,7 @@ zh_status zh_backward(zh_ctx* c, const float* g_hr, float* g_resid, float* g_lam
     if (c->bp_rec < 0)
         return fail(c, ZH_ESTATE, "zh_backward: more than one zh_backproject after zh_reconstruct");
     if (!g_hr || !g_resid || !g_lambda) return fail(c, ZH_EINVAL, "zh_backward: null pointer");
+    if (c->all_m) return fail(c, ZH_EUNSUPPORTED, "zh_backward: weights over all matches (zh_lle_all) have no adjoint here");
     Dict& d = c->dicts[c->qscale];
     if (!d.resid) return fail(c, ZH_ESTATE, "zh_backward: the dictionary has no HR residuals");
     const int s = c->qscale, h = c->qh, w = c->qw, H = s * h, W = s * w, K = c->qK;
@@ -1413,7 +1548,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)q_max));
     TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)std::max<int64_t>(q_max, 1)));
     TRY(ensure(c, c->qrot, sizeof(float) * kRotStride * (size_t)std::max<int64_t>(q_max, 1)));
-    TRY(ensure(c, c->over, sizeof(int32_t) * (size_t)q_max));
+    TRY(ensure(c, c->over, 2 * sizeof(int32_t) * (size_t)q_max));
     TRY(ensure(c, c->xhat, sizeof(float) * (size_t)q_max * ps2_max));
     TRY(ensure(c, c->counters, kNumCounters * sizeof(uint32_t)));
     if (K <= 8) TRY(ensure(c, c->gram, (c->opts.lle_fp64 ? 8 : 4) * (size_t)q_max * 36));
@@ -1631,7 +1766,8 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
 zh_status zh_get_results(zh_ctx* c, int32_t* ids, float* d2, int32_t* m, float* w, int32_t* ncand) {
     if (!c) return ZH_EINVAL;
     if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_get_results before zh_query");
-    if (w && c->stage < 2) return fail(c, ZH_ESTATE, "weights requested before zh_lle_weights");
+    if (w && (c->stage < 2 || c->all_m))
+        return fail(c, ZH_ESTATE, "weights of the K nearest requested before zh_lle_weights (or after zh_lle_all)");
     TRY(set_device(c));
     const size_t QK = (size_t)c->Q * c->qK, Q = (size_t)c->Q;
     if (ids) HIPCHK(c, hipMemcpyAsync(ids, c->ids.p, QK * 4, hipMemcpyDeviceToDevice, c->stream));
@@ -1736,7 +1872,7 @@ zh_status zh_stats(zh_ctx* c, zh_stats_t* out) {
     out->codes_fixed = h[C_CODEFIX];
     out->rank_fallbacks = h[C_RANKFB];
     out->deferred = h[C_OVERFLOW];
-    out->unsupported = h[C_UNSUP];
+    out->streamed = h[C_STREAM];
     out->lle_fp64 = h[C_LLE64];
     out->truncated = h[C_TRUNC];
     uint64_t db = 0;

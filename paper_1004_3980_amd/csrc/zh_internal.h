@@ -19,10 +19,10 @@ constexpr int32_t kCodeUnset = (int32_t)0x80000000;   // MFMA codes lie within +
 constexpr int kFixSlots = 16;                        // fix-list entries per wave of 16 rows
 
 // Device counters of the last query (uint32 each): patches deferred to the
-// large-union search, FP64 re-ranks, patches beyond the large-union limit,
-// codes fixed in FP64, fp32 LLE solves redone in FP64, screened patches whose
-// survivors exceeded the exact-row limit.
-enum { C_OVERFLOW = 0, C_RANKFB = 1, C_UNSUP = 2, C_CODEFIX = 3, C_LLE64 = 4, C_TRUNC = 5, kNumCounters = 8 };
+// large-union search, FP64 re-ranks, patches beyond the large-union limit
+// (ranked by the streaming merge), codes fixed in FP64, fp32 LLE solves redone
+// in FP64, screened patches whose survivors exceeded the exact-row limit.
+enum { C_OVERFLOW = 0, C_RANKFB = 1, C_STREAM = 2, C_CODEFIX = 3, C_LLE64 = 4, C_TRUNC = 5, kNumCounters = 8 };
 
 struct Taps {                   // normalised 1-D Gaussian, offsets -R..R
     double g[kMaxTaps];
@@ -50,6 +50,9 @@ hipError_t launch_dict_cut(const float* hr, const float* lr, const float* maps, 
 hipError_t launch_split_planes(const float* x, int64_t n, int D, uint16_t* hi, uint16_t* lo,
                                hipStream_t st);
 hipError_t launch_bicubic(const float* lr, int h, int w, int scale, float* out, hipStream_t st);
+// FP64 bicubic upsampling rounded to fp32 (the interpolated LR images of the
+// training pairs); wt[4 r + a]: Keys' weight of tap a at phase r (host table)
+hipError_t launch_upsample64(const float* lr, int h, int w, int scale, const double* wt, float* out, hipStream_t st);
 
 // ---- hashing (k_hash.hip) ----------------------------------------------------
 struct HashArgs {
@@ -98,7 +101,9 @@ __host__ __device__ inline uint32_t dir_filter_bit(uint64_t key, uint64_t cap) {
 __device__ __forceinline__ int64_t key_pos(const HashArgs& a, int64_t row, int l) {
     return a.keys_tmajor ? (int64_t)l * a.n + row : row * a.L + l;
 }
-hipError_t launch_hash(const HashArgs& a, hipStream_t st);
+hipError_t launch_hash(const HashArgs& a, hipStream_t st);   // codes and keys, then the bin lookup
+hipError_t launch_hash_codes(const HashArgs& a, hipStream_t st);   // codes and keys (with their FP64 fixes)
+hipError_t launch_probe(const HashArgs& a, hipStream_t st);        // the bins of the keys (a.bins set)
 // bound coefficients for the MFMA projection of precision `prec` (host)
 void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, float* c0, float* c1,
                        float* c2);
@@ -145,7 +150,8 @@ struct SearchArgs {
     int32_t* out_nsurv;      // [Q] candidates given an exact distance (early-stop search), nullable
     int32_t* dump;           // [Q, dump_cap] or null
     int dump_cap;
-    int32_t* overflow;       // [Q] deferred queries (uncapped, too many IDs for a wave)
+    int32_t* overflow;       // [2 Q] deferred queries (uncapped, too many IDs for a wave), then those
+                             // beyond the large-union limit
     unsigned int* counters;  // [0] overflow count, [1] FP64 rank fallbacks
 };
 hipError_t launch_search(const SearchArgs& a, hipStream_t st);
@@ -198,6 +204,12 @@ hipError_t lle_init();  // once per device, before any launch_lle
 hipError_t launch_gram(const LleArgs& a, void* gram, int gram_fp64, hipStream_t st);
 hipError_t launch_lle_solve(const LleArgs& a, const void* gram, int gram_fp64, hipStream_t st);
 hipError_t launch_lle(const LleArgs& a, hipStream_t st);
+// LLE over all M <= cap matches of each patch: cand[Q, cap] (IDs, M = ncand
+// capped; entries past M set to -1), weights w[Q, cap] (0 past M); Gram and solves in FP64; the LDS of
+// a workgroup (packed Gram, rows) stays within 64 KB up to cap 80 at D = 100
+constexpr int kAllMax = 80;
+hipError_t launch_lle_all(int Q, int D, int cap, double lam, const float* qfeat, const float* xf, int32_t* cand,
+                          const int32_t* ncand, float* w, hipStream_t st);
 // dictionary-construction tools (k_tools.hip)
 int64_t crop_scratch_bytes(int n_img, int H, int W);
 hipError_t launch_sample_crops(const float* imgs, int n_img, int H, int W, const uint64_t* draws, int m, int side,

@@ -42,7 +42,7 @@ class zh_query_opts(ctypes.Structure):
 class zh_stats_t(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_uint64), ("codes_fixed", ctypes.c_uint64),
                 ("rank_fallbacks", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
-                ("unsupported", ctypes.c_uint64), ("lle_fp64", ctypes.c_uint64),
+                ("streamed", ctypes.c_uint64), ("lle_fp64", ctypes.c_uint64),
                 ("dict_bytes", ctypes.c_uint64), ("truncated", ctypes.c_uint64)]
 
     def as_dict(self):
@@ -71,6 +71,9 @@ SIGNATURES = {
     "zh_degrade": [_V, _V, _I, _I, _I, _I, _F, _V],
     "zh_make_dictionary": [_V, _V, _I, _I, _I, _V, _I64, _I, _F, _I, _V, _V],
     "zh_features": [_V, _V, _I, _I, _I, _V, _V],
+    "zh_upsample": [_V, _V, _I, _I, _I, _V],
+    "zh_make_dictionary_interp": [_V, _V, _I, _I, _I, _V, _I64, _I, _F, _I, _V, _V],
+    "zh_backproject_lr": [_V, _V, _V, _I, _I, _I, _I, _F, _F],
     "zh_sample_crops": [_V, _V, _I, _I, _I, _V, _I, _I, _V, _V],
     "zh_table_entropy": [_V, _I, _V, _I],
     "zh_knn_l1": [_V],
@@ -84,6 +87,7 @@ SIGNATURES = {
     "zh_set_query_opts": [_V, ctypes.POINTER(zh_query_opts)],
     "zh_query": [_V, _V, _I, _I, _I, _I],
     "zh_lle_weights": [_V, ctypes.c_double],
+    "zh_lle_all": [_V, ctypes.c_double, _V, _V],
     "zh_reconstruct": [_V, _V],
     "zh_backproject": [_V, _V, _I, _F, _F],
     "zh_backward": [_V, _V, _V, _V],
@@ -98,7 +102,7 @@ SIGNATURES = {
     "zh_set_timing_stages": [_V, ctypes.c_uint32],
     "zh_get_timing": [_V, _V, _V],
 }
-STAGES = ["features", "hash", "search", "lle", "synth", "blend", "bp_error", "bp_update", "rotate"]
+STAGES = ["features", "hash", "search", "lle", "synth", "blend", "bp_error", "bp_update", "rotate", "probe"]
 
 _lib = None
 
@@ -175,6 +179,16 @@ class Context:
         self._chk(self.lib.zh_make_dictionary(self.h, _ptr(hr), n_img, H, W, _ptr(pos), n, scale,
                                               sigma, feat_mode, _ptr(feat), _ptr(resid)))
 
+    def upsample(self, lr, h, w, scale, out):
+        self._chk(self.lib.zh_upsample(self.h, _ptr(lr), h, w, scale, _ptr(out)))
+
+    def make_dictionary_interp(self, hr, n_img, H, W, pos, n, scale, sigma, feat_mode, feat, resid):
+        self._chk(self.lib.zh_make_dictionary_interp(self.h, _ptr(hr), n_img, H, W, _ptr(pos), n, scale, sigma,
+                                                     feat_mode, _ptr(feat), _ptr(resid)))
+
+    def backproject_lr(self, hr, lr, h, w, scale, iters, sigma_s, sigma_r):
+        self._chk(self.lib.zh_backproject_lr(self.h, _ptr(hr), _ptr(lr), h, w, scale, iters, sigma_s, sigma_r))
+
     def sample_crops(self, imgs, n_img, H, W, draws, m, side, corners, crops=None):
         self._chk(self.lib.zh_sample_crops(self.h, _ptr(imgs), n_img, H, W, _ptr(draws), m, side,
                                            _ptr(corners), _ptr(crops) if crops is not None else None))
@@ -239,6 +253,9 @@ class Context:
 
     def lle_weights(self, lam):
         self._chk(self.lib.zh_lle_weights(self.h, lam))
+
+    def lle_all(self, lam, ids=None, w=None):
+        self._chk(self.lib.zh_lle_all(self.h, lam, _ptr(ids), _ptr(w)))
 
     def reconstruct(self, hr_out):
         self._chk(self.lib.zh_reconstruct(self.h, _ptr(hr_out)))

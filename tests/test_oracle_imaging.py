@@ -111,3 +111,48 @@ def test_dictionary_pairs_recover_hr_patches(scale):
     # IDs run over images in row-major order
     key = pos[:, 0] * 1_000_000 + pos[:, 1] * 1000 + pos[:, 2]
     assert np.all(np.diff(key) > 0)
+
+
+def test_interpolated_pairs_at_zoom_one_are_the_plain_pairs():
+    """At zoom factor 1 the interpolation is the identity (Keys' weights are
+    0, 1, 0, 0 at phase 0), so interpolated pairs equal the plain pairs of a
+    zoom-1 dictionary at the same positions."""
+    hr = synthdata.image_stack(synthdata.SEED_BASE + 60, 2, 40, 36)
+    pos = synthdata.sample_positions(synthdata.SEED_BASE + 61, 2, 40, 36, 5, 300)
+    for mode in (0, 1):
+        a = imaging.build_dictionary(hr, pos, 1, mode)
+        b = imaging.build_dictionary_interp(hr, pos, 1, mode)
+        assert np.array_equal(a.feat, b.feat) and np.array_equal(a.resid, b.resid)
+
+
+def test_interpolated_lr_is_the_bicubic_and_reproduces_quadratics():
+    """The interpolated LR image is the fp32 rounding of the bicubic
+    interpolation; Keys' kernel reproduces quadratics exactly away from the
+    border, so a quadratic LR image comes back as the same quadratic sampled
+    at X / s (to the fp32 rounding)."""
+    for s in (2, 3, 4):
+        yy, xx = np.meshgrid(np.arange(12.0), np.arange(14.0), indexing="ij")
+        lr = (0.01 * yy * yy - 0.02 * xx * yy + 0.3 * xx + 0.1).astype(np.float32)
+        up = imaging.interpolated_lr(lr, s)
+        assert up.dtype == np.float32 and up.shape == (12 * s, 14 * s)
+        assert np.array_equal(up, imaging.bicubic_up(lr, s).astype(np.float32))
+        Y, X = np.meshgrid(np.arange(12 * s) / s, np.arange(14 * s) / s, indexing="ij")
+        q = 0.01 * Y * Y - 0.02 * X * Y + 0.3 * X + 0.1
+        inner = (slice(2 * s, 9 * s), slice(2 * s, 11 * s))
+        assert np.abs(up[inner] - q[inner]).max() < 2e-6
+
+
+def test_interpolated_pairs_self_reproduction():
+    """A dictionary of every interpolated pair of one image (all 5x5 patches
+    of the interpolated LR image and of the HR image): each query patch of
+    the interpolated image finds itself and K = 1 gives back the HR image
+    (the blend of its own HR patches at zoom factor 1)."""
+    from oracle import pipeline
+    hr = synthdata.fractal_voronoi_image(41, 40, 44)
+    lr = imaging.degrade(hr, 2)
+    H, W = hr.shape
+    pos = np.concatenate([np.zeros(((H - 4) * (W - 4), 1), np.int64), imaging.all_positions(H, W)], axis=1)
+    pre = pipeline.prepare_interp(hr[None], pos, 2, 1, L=4, k=6, w=4.0, seed=9)
+    qr, up, out, _ = pipeline.run_interp(pre, lr, 2, 1, 1e-3, 0)
+    assert np.all(qr.d2[:, 0] == 0.0)
+    assert np.abs(out - hr.astype(np.float64)).max() < 1e-6

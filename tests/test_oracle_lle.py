@@ -182,3 +182,48 @@ def test_synthesis_of_an_affine_combination(K):
     w2 = lle.lle_weights(q, Y, 0.5)
     assert np.abs(w2 - c).max() > 1e-3
     assert np.abs(lle.synthesize(mu, w2, R) - (mu + w2 @ R)).max() < 1e-12
+
+
+def test_all_matches_equals_k_nearest_when_every_set_is_small():
+    """LLE over all M matches (Eq. LinSys with m = 1..M): when no patch has
+    more than K candidates the K nearest are all of them, and the weights
+    (a permutation of the K-NN ones: the solve is equivariant under a
+    reordering of the neighbours) and the image agree with the K-NN path."""
+    wl = synthdata.WORKLOADS["tiny"]
+    pre = pipeline.prepare(wl.dictionary_images(), wl.positions(), wl.scale, wl.feat_mode, 4, 12, 4.0,
+                           wl.hash_seed)
+    lr = wl.test_image()
+    K = 400      # above the largest candidate set
+    a = pipeline.query(pre, lr, K, wl.lam, cap=0)
+    b = pipeline.query(pre, lr, K, wl.lam, cap=0, all_matches=True)
+    assert max(len(c) for c in a.cand) < K and (a.m > 1).sum() > 100
+    for q in np.nonzero(a.m > 0)[0]:
+        order = np.argsort(a.ids[q, :a.m[q]])
+        assert np.allclose(b.all_weights[q], a.weights[q, :a.m[q]][order], rtol=0, atol=1e-9)
+    ha, _ = pipeline.reconstruct(a, lr, wl.scale)
+    hb, _ = pipeline.reconstruct(b, lr, wl.scale)
+    assert np.abs(ha - hb).max() < 1e-9
+
+
+def test_all_matches_uses_every_candidate():
+    """With the early stop at 24 and K = 5, the all-M weights of a patch are
+    the LLE solve over its whole candidate list (checked against the KKT
+    system of Eq. LinSys with the trace regulariser) and its HR patch the
+    weighted sum of all M residuals."""
+    wl = synthdata.WORKLOADS["tiny"]
+    pre = pipeline.prepare(wl.dictionary_images(), wl.positions(), wl.scale, wl.feat_mode, wl.L, wl.k, 16.0,
+                           wl.hash_seed)
+    lr = wl.test_image()
+    b = pipeline.query(pre, lr, 5, wl.lam, cap=24, all_matches=True)
+    big = [q for q in range(len(b.cand)) if len(b.cand[q]) == 24][:5]
+    assert len(big) == 5
+    for q in big:
+        Y = pre.dictionary.feat[b.cand[q]].astype(np.float64)
+        Z = b.feat[q].astype(np.float64)[None] - Y
+        G = Z @ Z.T
+        A = G + wl.lam * np.trace(G) * np.eye(24)
+        kkt = np.block([[2 * A, np.ones((24, 1))], [np.ones((1, 24)), np.zeros((1, 1))]])
+        sol = np.linalg.solve(kkt, np.r_[np.zeros(24), 1.0])
+        assert np.allclose(b.all_weights[q], sol[:24], rtol=0, atol=1e-8)
+        R = pre.dictionary.resid[b.cand[q]].astype(np.float64)
+        assert np.allclose(b.patches[q], b.mu[q] + sol[:24] @ R, rtol=0, atol=1e-7)
