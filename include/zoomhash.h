@@ -208,6 +208,24 @@ zh_status zh_get_hash_params(zh_ctx* ctx, int scale, float* alpha_host, float* b
 zh_status zh_hash(zh_ctx* ctx, int scale, const float* feat, int64_t n, int32_t* codes,
                   uint64_t* keys);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): zh_hash
+ * with `keys` required, whose kernels take their scratch (the per-row dirty
+ * mask and the fix list of the FP64 recomputation) from a fixed device array
+ * of the library instead of the context's buffers, so that the call
+ * allocates nothing. The array is 8 MiB per GPU, held from the first
+ * zh_create on that GPU until the process ends; it bounds n to
+ * floor((8 MiB - 512) / (9 + 4 f)) rounded down to a multiple of 16,
+ * f = k + 2 rounded up to a multiple of 4 (79,872 rows at k = 20, 94,240 at
+ * k = 16, 54,816 at k = 32); a larger n returns ZH_EINVAL and enqueues
+ * nothing. Results equal those of zh_hash. Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other streams, other contexts, other
+ * host threads) race, so order them. Nothing in the array has to start at
+ * any value: each call writes what it reads. The count of codes fixed in
+ * FP64 (zh_stats) is not updated by this call. */
+zh_status zh_hash_noalloc(zh_ctx* ctx, int scale, const float* feat, int64_t n, int32_t* codes,
+                          uint64_t* keys);
+
 /* ---- query options ----------------------------------------------------- */
 typedef struct {
     int32_t cap;           /* 0: candidates are the union of the L bins; > 0: the

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,10 @@
 #include "zh_internal.h"
 
 using namespace zh;
+
+// Scratch of zh_hash_noalloc: a fixed device array of the library, one copy
+// per GPU, held until the process ends (its size is kNoAllocBytes).
+static __device__ __align__(256) unsigned char scratch[(size_t)8 << 20];
 
 namespace {
 
@@ -51,6 +56,15 @@ struct Dict {
     uint64_t feat_hash = 0;       // content hash of the features the tables were built on
 };
 
+
+// ---- fixed scratch of the allocation-free entry point (zh_hash_noalloc) ------
+// Host code never uses the array's name `scratch` as an address: each
+// device's address is taken once, with that device current, by
+// hipGetSymbolAddress (at zh_create) and kept in g_noalloc_ptr.
+constexpr size_t kNoAllocBytes = sizeof(scratch);
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocDevices] = {};
 
 }  // namespace
 
@@ -459,6 +473,19 @@ zh_status zh_create(zh_ctx** out, int device, void* hip_stream) {
         (void)hipGetLastError();
         delete c;
         return ZH_EDEVICE;
+    }
+    if (device < kNoAllocDevices) {
+        // the device address of this GPU's copy of the fixed scratch, once per device
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (!g_noalloc_ptr[device]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+                (void)hipGetLastError();
+                delete c;
+                return ZH_EDEVICE;
+            }
+            g_noalloc_ptr[device] = ptr;
+        }
     }
     *out = c;
     return ZH_OK;
@@ -970,6 +997,60 @@ zh_status zh_hash(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* c
     ha.codes = codes;
     ha.n_fixed = P<unsigned int>(c->counters) + C_CODEFIX;
     TRY(hash_scratch(c, ha));
+    HIPCHK(c, launch_hash(ha, c->stream));
+    return ZH_OK;
+}
+
+// Per feature row of zh_hash_noalloc: the dirty mask (8 bytes) and its share of
+// the fix list (kFixSlots entries per 16 rows) and of the list's counts.
+static size_t noalloc_row_bytes(int k) {
+    return 8 + (size_t)kFixSlots * sizeof(int32_t) * (size_t)(((k + 2) + 3) & ~3) / 16 + 1;
+}
+static int64_t noalloc_max_rows(int k) {
+    return (int64_t)((kNoAllocBytes - 512) / noalloc_row_bytes(k)) & ~(int64_t)15;
+}
+
+zh_status zh_hash_noalloc(zh_ctx* c, int scale, const float* feat, int64_t n, int32_t* codes, uint64_t* keys) {
+    if (!c) return ZH_EINVAL;
+    if (scale < 1 || scale > kMaxScale || !c->dicts[scale].valid) return fail(c, ZH_ESTATE, "no tables for scale %d", scale);
+    Dict& d = c->dicts[scale];
+    if (!feat || !keys || n < 0) return fail(c, ZH_EINVAL, "zh_hash_noalloc: need feat and keys, n >= 0");
+    const int64_t nmax = noalloc_max_rows(d.k);
+    if (n > nmax)
+        return fail(c, ZH_EINVAL, "zh_hash_noalloc: %lld rows exceed the fixed scratch (%zu bytes: at most %lld rows at k = %d)",
+                    (long long)n, kNoAllocBytes, (long long)nmax, d.k);
+    if (c->device >= kNoAllocDevices || !g_noalloc_ptr[c->device])
+        return fail(c, ZH_EDEVICE, "zh_hash_noalloc: no fixed scratch on device %d", c->device);
+    if (n == 0) return ZH_OK;
+    TRY(set_device(c));
+    // carve the scratch: dirty mask [n] u64, fix list, fix counts [ceil(n/16)]
+    // (every entry the kernels read is written by them first in the same
+    // call, so nothing needs clearing)
+    unsigned char* base = static_cast<unsigned char*>(g_noalloc_ptr[c->device]);
+    const size_t nw = (size_t)((n + 15) / 16);
+    const size_t fe = (size_t)(((d.k + 2) + 3) & ~3);
+    HashArgs ha{};
+    ha.feat = feat;
+    ha.n = n;
+    ha.D = d.D;
+    ha.L = d.L;
+    ha.k = d.k;
+    ha.alpha = P<float>(d.alpha);
+    ha.a_hi = P<uint16_t>(d.ahi);
+    ha.a_lo = P<uint16_t>(d.alo);
+    ha.beta = P<float>(d.beta);
+    ha.key_mul = P<uint64_t>(d.kmul);
+    set_bounds(ha, d, c->opts.proj);
+    ha.w = d.w;
+    ha.prec = c->opts.proj;
+    ha.keys = keys;
+    ha.codes = codes;
+    ha.n_fixed = nullptr;
+    ha.dirty = reinterpret_cast<uint64_t*>(base);
+    ha.fix_cap = kFixSlots;
+    ha.fix_list = reinterpret_cast<int32_t*>(base + ((8 * (size_t)n + 255) & ~(size_t)255));
+    ha.fix_count = reinterpret_cast<unsigned int*>(reinterpret_cast<unsigned char*>(ha.fix_list) +
+                                                  ((nw * kFixSlots * fe * sizeof(int32_t) + 255) & ~(size_t)255));
     HIPCHK(c, launch_hash(ha, c->stream));
     return ZH_OK;
 }

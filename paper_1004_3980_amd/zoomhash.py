@@ -84,6 +84,7 @@ SIGNATURES = {
     "zh_load_tables": [_V, ctypes.POINTER(zh_dictionary), ctypes.c_char_p],
     "zh_get_hash_params": [_V, _I, _V, _V],
     "zh_hash": [_V, _I, _V, _I64, _V, _V],
+    "zh_hash_noalloc": [_V, _I, _V, _I64, _V, _V],
     "zh_set_query_opts": [_V, ctypes.POINTER(zh_query_opts)],
     "zh_query": [_V, _V, _I, _I, _I, _I],
     "zh_lle_weights": [_V, ctypes.c_double],
@@ -243,6 +244,9 @@ class Context:
 
     def hash(self, scale, feat, n, codes=None, keys=None):
         self._chk(self.lib.zh_hash(self.h, scale, _ptr(feat), n, _ptr(codes), _ptr(keys)))
+
+    def hash_noalloc(self, scale, feat, n, codes, keys):
+        self._chk(self.lib.zh_hash_noalloc(self.h, scale, _ptr(feat), n, _ptr(codes), _ptr(keys)))
 
     def set_query_opts(self, cap=0, rerank=0, proj=1, lle_fp64=1):
         o = zh_query_opts(cap, rerank, proj, lle_fp64)
