@@ -24,41 +24,118 @@ constexpr int kBpMaxR = 8;
 // One T x T output tile with origin (Y0, X0). TERMS: instead of the update,
 // write F, S and a = I - mu (the pieces the adjoint of the iteration needs)
 // to out, out + H W and out + 2 H W.
+//
+// E on the staged region comes from the LR error patch under it: the patch
+// (clamped indices, so the border replicates) is staged in LDS, upsampled
+// along x for each of its rows, then along y, with the same fused
+// multiply-adds in the same order as bicubic_at (bitwise its values). Tiles
+// whose halo lies inside the image take the Gaussian and box sums without
+// per-tap border tests (the same operations in the same order).
 template <int T, bool TERMS>
 __device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float* __restrict__ e, int H, int W, int h,
                                         int w, int s, int R, float sigma_s, float inv2sr2, float* __restrict__ out,
                                         int Y0, int X0) {
     constexpr int REG = T + 2 * kBpMaxR;
+    // LR rows / columns under REG HR pixels at zoom >= 2: REG / 2 + 4
+    constexpr int LREG = REG / 2 + 5;
     __shared__ float sI[REG][REG];
-    __shared__ float sE[REG][REG];
-    __shared__ float sHE[REG][T];
-    __shared__ float sHB[REG][T];
+    __shared__ float sE[REG][REG];          // first the staged LR error patch [LREG][LREG]
+    __shared__ float sH[2][REG][T];         // the passes' sums; first the x pass of the upsampling [LREG][REG]
     __shared__ float sg[2 * kBpMaxR + 1];
+    __shared__ float sw[kMaxScale][4];      // Keys' weights of each phase
+    static_assert(LREG * LREG <= REG * REG && LREG * REG <= 2 * REG * T, "LDS aliases");
+    float (*sHE)[T] = sH[0];
+    float (*sHB)[T] = sH[1];
+    float* eL = &sE[0][0];
+    float* xU = &sH[0][0][0];
     const int reg = T + 2 * R;
     if ((int)threadIdx.x < 2 * R + 1) {
         const float d = (float)((int)threadIdx.x - R);
         sg[threadIdx.x] = expf(-(d * d) / (2.0f * sigma_s * sigma_s));
+    }
+    if ((int)threadIdx.x < 4 * s && s <= kMaxScale) {
+        const int ph = threadIdx.x >> 2, a = threadIdx.x & 3;
+        sw[ph][a] = keys_w((float)ph / (float)s - (float)(a - 1));
     }
     for (int t = threadIdx.x; t < reg * reg; t += blockDim.x) {
         const int r = t / reg, c = t % reg;
         const int Y = Y0 - R + r, X = X0 - R + c;
         const bool in = Y >= 0 && Y < H && X >= 0 && X < W;
         sI[r][c] = in ? I[(int64_t)Y * W + X] : 0.0f;
-        sE[r][c] = in ? bicubic_at(e, h, w, s, Y, X) : 0.0f;
+    }
+    // the staged region's in-image HR rows [ya, yb] and columns [xa, xb]
+    const int ya = max(0, Y0 - R), yb = min(H - 1, Y0 - R + reg - 1);
+    const int xa = max(0, X0 - R), xb = min(W - 1, X0 - R + reg - 1);
+    const bool sep = s >= 2 && s <= kMaxScale;
+    const int la = ya / s - 1, lc = xa / s - 1;          // first staged LR row / column
+    const int nlr = yb / s + 2 - la + 1, nlc = xb / s + 2 - lc + 1;
+    if (sep) {
+        for (int t = threadIdx.x; t < nlr * nlc; t += blockDim.x) {
+            const int r = t / nlc, c = t % nlc;
+            eL[r * LREG + c] = e[(int64_t)clampi(la + r, 0, h - 1) * w + clampi(lc + c, 0, w - 1)];
+        }
     }
     __syncthreads();
+    if (sep) {
+        // along x: every staged LR row at the region's columns
+        for (int t = threadIdx.x; t < nlr * reg; t += blockDim.x) {
+            const int r = t / reg, c = t % reg;
+            const int X = X0 - R + c;
+            if (X < xa || X > xb) continue;
+            const int j0 = X / s;
+            const float* wx = sw[X - j0 * s];
+            const float* row = eL + r * LREG + (j0 - 1 - lc);
+            float v = 0.0f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v = fmaf(wx[b], row[b], v);
+            xU[r * REG + c] = v;
+        }
+        __syncthreads();
+        // along y
+        for (int t = threadIdx.x; t < reg * reg; t += blockDim.x) {
+            const int r = t / reg, c = t % reg;
+            const int Y = Y0 - R + r, X = X0 - R + c;
+            float v = 0.0f;
+            if (Y >= 0 && Y < H && X >= 0 && X < W) {
+                const int i0 = Y / s;
+                const float* wy = sw[Y - i0 * s];
+                const int r0 = i0 - 1 - la;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) v = fmaf(wy[a], xU[(r0 + a) * REG + c], v);
+            }
+            sE[r][c] = v;
+        }
+    } else {
+        for (int t = threadIdx.x; t < reg * reg; t += blockDim.x) {
+            const int r = t / reg, c = t % reg;
+            const int Y = Y0 - R + r, X = X0 - R + c;
+            const bool in = Y >= 0 && Y < H && X >= 0 && X < W;
+            sE[r][c] = in ? bicubic_at(e, h, w, s, Y, X) : 0.0f;
+        }
+    }
+    __syncthreads();
+    const bool inner = Y0 - R >= 0 && X0 - R >= 0 && Y0 + T + R <= H && X0 + T + R <= W;
     // horizontal passes over every staged row, the tile's columns
     for (int t = threadIdx.x; t < reg * T; t += blockDim.x) {
         const int r = t / T, c = t % T;
         const int X = X0 + c;
         float ge = 0.0f, gn = 0.0f, bs = 0.0f;
-        for (int d = -R; d <= R; ++d) {
-            const int x = X + d;
-            if (x < 0 || x >= W) continue;
-            const float g = sg[d + R];
-            ge = fmaf(g, sE[r][c + R + d], ge);
-            gn += g;
-            bs += sI[r][c + R + d];
+        if (inner) {
+            for (int d = -R; d <= R; ++d) {
+                const float g = sg[d + R];
+                ge = fmaf(g, sE[r][c + R + d], ge);
+                gn += g;
+                bs += sI[r][c + R + d];
+            }
+        } else {
+            for (int d = -R; d <= R; ++d) {
+                const int x = X + d;
+                if (x < 0 || x >= W) continue;
+                const float g = sg[d + R];
+                ge = fmaf(g, sE[r][c + R + d], ge);
+                gn += g;
+                bs += sI[r][c + R + d];
+            }
         }
         sHE[r][c] = gn > 0.0f ? ge / gn : 0.0f;
         sHB[r][c] = bs;
@@ -69,13 +146,22 @@ __device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float
         const int Y = Y0 + r, X = X0 + c;
         if (Y >= H || X >= W) continue;
         float ge = 0.0f, gn = 0.0f, bs = 0.0f;
-        for (int d = -R; d <= R; ++d) {
-            const int y = Y + d;
-            if (y < 0 || y >= H) continue;
-            const float g = sg[d + R];
-            ge = fmaf(g, sHE[r + R + d][c], ge);
-            gn += g;
-            bs += sHB[r + R + d][c];
+        if (inner) {
+            for (int d = -R; d <= R; ++d) {
+                const float g = sg[d + R];
+                ge = fmaf(g, sHE[r + R + d][c], ge);
+                gn += g;
+                bs += sHB[r + R + d][c];
+            }
+        } else {
+            for (int d = -R; d <= R; ++d) {
+                const int y = Y + d;
+                if (y < 0 || y >= H) continue;
+                const float g = sg[d + R];
+                ge = fmaf(g, sHE[r + R + d][c], ge);
+                gn += g;
+                bs += sHB[r + R + d][c];
+            }
         }
         const int ny = min(H - 1, Y + R) - max(0, Y - R) + 1;
         const int nx = min(W - 1, X + R) - max(0, X - R) + 1;

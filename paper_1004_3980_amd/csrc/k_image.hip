@@ -48,6 +48,46 @@ __global__ void k_degrade_residual(const float* __restrict__ hr, int H, int W, i
     }
 }
 
+// The same LR error by LR tiles of kDrI x kDrJ: the HR rows and columns under
+// a tile (clamped indices: replicate border) are staged in LDS, the
+// horizontal FP64 sums are formed once per (HR row, LR column) and shared by
+// the LR rows that use them, then the vertical sums; each value is the
+// blur_at sum to the bit (same products, same order).
+constexpr int kDrI = 8, kDrJ = 32;
+__global__ __launch_bounds__(256) void k_degrade_residual_t(const float* __restrict__ hr, int H, int W, int scale,
+                                                            Taps t, const float* __restrict__ lr_ref,
+                                                            float* __restrict__ e) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
+    const int R = t.R;
+    const int i0 = blockIdx.y * kDrI, j0 = blockIdx.x * kDrJ;
+    const int ny = scale * (kDrI - 1) + 2 * R + 1, nx = scale * (kDrJ - 1) + 2 * R + 1;
+    double* hrow = reinterpret_cast<double*>(smem);                       // [ny][kDrJ]
+    float* sh = reinterpret_cast<float*>(smem + sizeof(double) * ny * kDrJ);   // [ny][nx]
+    const int y0 = scale * i0 - R, x0 = scale * j0 - R;
+    for (int q = threadIdx.x; q < ny * nx; q += blockDim.x) {
+        const int r = q / nx, c = q % nx;
+        sh[q] = hr[(int64_t)clampi(y0 + r, 0, H - 1) * W + clampi(x0 + c, 0, W - 1)];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ny * kDrJ; q += blockDim.x) {
+        const int r = q / kDrJ, jj = q % kDrJ;
+        const float* row = sh + r * nx + scale * jj;
+        double v = 0.0;
+        for (int b = 0; b <= 2 * R; ++b) v = v + t.g[b] * (double)row[b];
+        hrow[q] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kDrI * kDrJ; q += blockDim.x) {
+        const int ii = q / kDrJ, jj = q % kDrJ;
+        const int i = i0 + ii, j = j0 + jj;
+        if (i >= h || j >= w) continue;
+        double acc = 0.0;
+        for (int a = 0; a <= 2 * R; ++a) acc = acc + t.g[a] * hrow[(scale * ii + a) * kDrJ + jj];
+        e[(int64_t)i * w + j] = (float)((double)lr_ref[(int64_t)i * w + j] - acc);
+    }
+}
+
 // Batched: LR error of every image, the current estimate in out (parity 0)
 // or scr (parity 1); image b's error at e + lr_off.
 __global__ void k_b_degrade_residual(const BatchImage* __restrict__ im, int n, int64_t total, int scale, Taps t,
@@ -302,7 +342,15 @@ hipError_t launch_degrade(const float* hr, int n_img, int H, int W, int scale, c
 
 hipError_t launch_degrade_residual(const float* hr, int H, int W, int scale, const Taps& t,
                                    const float* lr_ref, float* e, hipStream_t st) {
-    const int64_t total = (int64_t)((H + scale - 1) / scale) * ((W + scale - 1) / scale);
+    const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
+    const size_t lds = sizeof(double) * (size_t)(scale * (kDrI - 1) + 2 * t.R + 1) * kDrJ +
+                       sizeof(float) * (size_t)(scale * (kDrI - 1) + 2 * t.R + 1) * (scale * (kDrJ - 1) + 2 * t.R + 1);
+    if (lds <= 48 * 1024 && h > 0 && w > 0) {
+        const dim3 grid((unsigned)((w + kDrJ - 1) / kDrJ), (unsigned)((h + kDrI - 1) / kDrI));
+        hipLaunchKernelGGL(k_degrade_residual_t, grid, dim3(256), lds, st, hr, H, W, scale, t, lr_ref, e);
+        return hipGetLastError();
+    }
+    const int64_t total = (int64_t)h * w;
     hipLaunchKernelGGL(k_degrade_residual, dim3(grid_for(total, 256)), dim3(256), 0, st, hr, H, W,
                        scale, t, lr_ref, e);
     return hipGetLastError();
