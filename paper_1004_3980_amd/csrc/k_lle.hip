@@ -742,12 +742,12 @@ hipError_t launch_lle(const LleArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m, const float* w,
-                        const double* mu, const float* resid, float* xhat, hipStream_t st) {
+                        const double* mu, const float* resid, float* xhat, hipStream_t st, int group) {
     if (Q == 0) return hipSuccess;
     if (ps2 < 1 || ps2 > kMaxPs2) return hipErrorInvalidValue;
     const bool vec = (ps2 & 3) == 0 && (reinterpret_cast<uintptr_t>(resid) & 15) == 0 &&
                      (reinterpret_cast<uintptr_t>(xhat) & 15) == 0;
-    if (vec && ps2 <= 128) {
+    if (vec && ps2 <= 128 && group != 64) {
         // half a wave per patch
         const int grid = round_grid8((int)std::min<int64_t>(((int64_t)Q + 7) / 8, 65536));
         hipLaunchKernelGGL((k_synth4<32, 1>), dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);

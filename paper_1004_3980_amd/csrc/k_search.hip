@@ -181,10 +181,27 @@ __device__ uint64_t select_topk(const uint32_t* cids, const uint32_t* cdist, int
 }
 
 // Sorted selection for M <= 64 NSL candidates: lane r < min(M, 64) receives
-// the r-th smallest key.
+// the r-th smallest key. Up to 16 candidates: each lane counts the keys below
+// its own (the keys are distinct: they carry the ID) and places its key at
+// that rank in `rk` (16 slots of LDS).
 template <int NSL = 4>
-__device__ __forceinline__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int M) {
+__device__ __forceinline__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int M,
+                                                uint64_t* rk = nullptr) {
     const int lane = threadIdx.x;
+    if (rk && M <= 16) {
+        const uint64_t mine = lane < M ? cand_key(cdist[lane], cids[lane]) : ~0ull;
+        const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
+        int rank = 0;
+        for (int c = 0; c < M; ++c) {
+            const uint32_t lo = __builtin_amdgcn_readlane(mlo, c), hi = __builtin_amdgcn_readlane(mhi, c);
+            rank += ((((uint64_t)hi << 32) | lo) < mine) ? 1 : 0;
+        }
+        if (lane < M) rk[rank] = mine;
+        __syncthreads();
+        const uint64_t out = lane < M ? rk[lane] : ~0ull;
+        __syncthreads();
+        return out;
+    }
     if (M <= 64) {
         uint64_t k[1] = {lane < M ? cand_key(cdist[lane], cids[lane]) : ~0ull};
         if (M <= 16)
@@ -550,8 +567,10 @@ __device__ void write_gram(const SearchArgs& a, int q, const float* sq, uint32_t
     __syncthreads();
     GT* out = reinterpret_cast<GT*>(a.gram) + (int64_t)q * 36;
     if (lane < 36) {
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= lane) ++i;
+        // row i of packed entry `lane` (i (i + 1) / 2 <= lane < (i + 1) (i + 2) / 2)
+        int i = (int)((sqrtf((float)(8 * lane + 1)) - 1.0f) * 0.5f);
+        if ((i + 1) * (i + 2) / 2 <= lane) ++i;
+        if (i * (i + 1) / 2 > lane) --i;
         const int j = lane - i * (i + 1) / 2;
         const int pa = __shfl(pi, i), pb = __shfl(pi, j);
         out[lane] = i < Kp ? sG[pa * 8 + pb] : (GT)0;
@@ -631,6 +650,7 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
     __shared__ __align__(16) float sq[128];
     __shared__ uint32_t sstart[kMaxL + 1];
     __shared__ uint32_t soff[kMaxL];
+    __shared__ uint64_t srank[16];
     const int lane = threadIdx.x;
     const int L = a.L, D = a.D;
     const int hsz = a.hsz;
@@ -856,7 +876,7 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
 
         // ---- 4. K best, certification, output
         const int Kp = min(a.K, Mr);
-        const uint64_t mykey = sort_select<NSL>(cids, cdist, Mr);
+        const uint64_t mykey = sort_select<NSL>(cids, cdist, Mr, srank);
         uint32_t oid = 0xFFFFFFFFu;
         float od = 0.0f;
         if (EXACT && Kp > 0) {

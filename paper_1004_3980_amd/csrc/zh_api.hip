@@ -101,6 +101,7 @@ struct zh_ctx {
         hipStream_t stream = nullptr;
         hipEvent_t ev_in = nullptr, ev_out = nullptr;
         int tile = 32, grid_per_cu = 4;
+        int synth_group = 0;          // lanes per patch of the synthesis (0: the launcher's choice)
         Buf scr, e, counter;
     } batch;
     // back-projection record for zh_backward: 0 none, 1 one call kept, -1 more than one
@@ -1547,7 +1548,7 @@ std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
     v.insert(v.end(), {(uint64_t)b->n_images, (uint64_t)b->K, lb, (uint64_t)b->bp_iters, ss, sr,
                        (uint64_t)c->opts.cap, (uint64_t)c->opts.rerank, (uint64_t)c->opts.proj,
                        (uint64_t)c->opts.lle_fp64, (uint64_t)c->batch.tile, (uint64_t)c->batch.grid_per_cu,
-                       (uint64_t)(uintptr_t)c->stream, c->gen});
+                       (uint64_t)c->batch.synth_group, (uint64_t)(uintptr_t)c->stream, c->gen});
     for (int s = 1; s <= kMaxScale; ++s) {
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dir.p);
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dfilt.p);
@@ -1710,7 +1711,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
                 HIPCHK(c, launch_lle(la, st));
             }
             HIPCHK(c, launch_synth((int)g.q_total, K, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
-                                   P<double>(c->qmu), d.resid, P<float>(c->xhat), st));
+                                   P<double>(c->qmu), d.resid, P<float>(c->xhat), st, B.synth_group));
             HIPCHK(c, launch_b_blend(tab, g.n, g.bsegs, s, P<float>(c->xhat), P<int32_t>(c->m), st));
             const Taps tg = gauss_taps(1.0);
             for (int t = 0; t < b->bp_iters; ++t) {
@@ -1780,10 +1781,113 @@ zh_status zh_run_batch(zh_ctx* c, const zh_batch* b) {
     return ZH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Key of a batch for the tuning cache: device, HIP runtime, and everything
+// that shapes the launches (sizes, zoom factors, K, iterations, query options).
+uint64_t tune_key(zh_ctx* c, const zh_batch* b, std::string& dev, std::string& arch, int& rt) {
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) (void)hipGetLastError();
+    dev = prop.name;
+    arch = prop.gcnArchName;
+    rt = 0;
+    if (hipRuntimeGetVersion(&rt) != hipSuccess) (void)hipGetLastError();
+    uint64_t h = fmix64(0x5A17ull + (uint64_t)rt);
+    auto mix = [&](uint64_t v) { h = fmix64(h ^ (v + kGolden)); };
+    for (char ch : dev) mix((uint64_t)(unsigned char)ch);
+    for (char ch : arch) mix((uint64_t)(unsigned char)ch);
+    mix((uint64_t)b->n_images);
+    for (int i = 0; i < b->n_images; ++i) {
+        mix((uint64_t)b->h[i]);
+        mix((uint64_t)b->w[i]);
+        mix((uint64_t)b->scale[i]);
+    }
+    mix((uint64_t)b->K);
+    mix((uint64_t)b->bp_iters);
+    mix((uint64_t)c->opts.cap);
+    mix((uint64_t)c->opts.rerank);
+    mix((uint64_t)c->opts.proj);
+    mix((uint64_t)c->opts.lle_fp64);
+    return h;
+}
+
+// An earlier choice for `key` in the cache file (one JSON object per line).
+bool tune_lookup(const char* path, uint64_t key, int& tile, int& mult, int& group) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[2048];
+    char want[64];
+    std::snprintf(want, sizeof(want), "\"key\": \"%016llx\"", (unsigned long long)key);
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (!std::strstr(line, want)) continue;
+        const char* a = std::strstr(line, "\"bp_tile\": ");
+        const char* g = std::strstr(line, "\"bp_grid_per_cu\": ");
+        const char* y = std::strstr(line, "\"synth_group\": ");
+        int t = 0, m = 0, sg = 0;
+        if (a && g && y && std::sscanf(a + 11, "%d", &t) == 1 && std::sscanf(g + 18, "%d", &m) == 1 &&
+            std::sscanf(y + 15, "%d", &sg) == 1 && (t == 16 || t == 32) && (m == 2 || m == 4 || m == 8) &&
+            (sg == 32 || sg == 64)) {
+            tile = t;
+            mult = m;
+            group = sg;
+            found = true;   // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store(const char* path, uint64_t key, const std::string& dev, const std::string& arch, int rt,
+                const zh_batch_tuning& t) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::string d;
+    for (char ch : dev) d += (ch == '"' || ch == '\\') ? '_' : ch;
+    std::string a;
+    for (char ch : arch) a += (ch == '"' || ch == '\\') ? '_' : ch;
+    std::fprintf(f, "{\"key\": \"%016llx\", \"device\": \"%s\", \"arch\": \"%s\", \"hip_runtime\": %d, "
+                    "\"bp_tile\": %d, \"bp_grid_per_cu\": %d, \"synth_group\": %d, \"bp_ms\": [%.4f, %.4f, %.4f, "
+                    "%.4f, %.4f, %.4f], \"synth_ms\": [%.4f, %.4f]}\n",
+                 (unsigned long long)key, d.c_str(), a.c_str(), rt, t.bp_tile, t.bp_grid_per_cu, t.synth_group,
+                 t.bp_ms[0], t.bp_ms[1], t.bp_ms[2], t.bp_ms[3], t.bp_ms[4], t.bp_ms[5], t.synth_ms[0],
+                 t.synth_ms[1]);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
 zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
     if (!c) return ZH_EINVAL;
-    TRY(zh_run_batch(c, b));
+    TRY(batch_check(c, b));
+    TRY(set_device(c));
     auto& B = c->batch;
+    const char* cache = std::getenv("ZH_TUNE_CACHE");
+    std::string dev, arch;
+    int rt = 0;
+    const uint64_t key = tune_key(c, b, dev, arch, rt);
+    if (cache && cache[0]) {
+        int t = 0, m = 0, g = 0;
+        if (tune_lookup(cache, key, t, m, g)) {
+            B.tile = t;
+            B.grid_per_cu = m;
+            B.synth_group = g;
+            B.sig.clear();
+            if (out) {
+                std::memset(out, 0, sizeof(*out));
+                out->bp_tile = t;
+                out->bp_grid_per_cu = m;
+                out->synth_group = g;
+                out->from_cache = 1;
+            }
+            return zh_run_batch(c, b);
+        }
+    }
+    TRY(zh_run_batch(c, b));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int tiles[2] = {16, 32}, mults[3] = {2, 4, 8};
     float ms[6];
@@ -1793,16 +1897,26 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
     HIPCHK(c, hipEventCreate(&e1));
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1) ncu = 256;
-    const int keep_tile = B.tile, keep_mult = B.grid_per_cu;
+    const int keep_tile = B.tile, keep_mult = B.grid_per_cu, keep_group = B.synth_group;
     zh_status rc = ZH_OK;
+    auto time_once = [&](auto&& launch, float& best_ms) {
+        best_ms = 1e30f;
+        for (int rep = 0; rep < 2 && rc == ZH_OK; ++rep) {
+            if (hipEventRecord(e0, B.stream) != hipSuccess) { rc = fail(c, ZH_EDEVICE, "event"); return; }
+            if (!launch()) { rc = fail(c, ZH_EDEVICE, "zh_tune_batch: launch failed"); return; }
+            (void)hipEventRecord(e1, B.stream);
+            (void)hipEventSynchronize(e1);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            best_ms = std::min(best_ms, t);
+        }
+    };
     for (int ti = 0; ti < 2 && rc == ZH_OK; ++ti) {
         B.tile = tiles[ti];
         B.sig.clear();
         rc = batch_plan(c, b);   // tile offsets of this tile size
         for (int mi = 0; mi < 3 && rc == ZH_OK; ++mi) {
-            float bestrun = 1e30f;
-            for (int rep = 0; rep < 2 && rc == ZH_OK; ++rep) {
-                if (hipEventRecord(e0, B.stream) != hipSuccess) { rc = fail(c, ZH_EDEVICE, "event"); break; }
+            time_once([&]() {
                 for (int s = 1; s <= kMaxScale; ++s) {
                     auto& g = B.g[s];
                     if (!g.n) continue;
@@ -1810,37 +1924,55 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
                     if (launch_b_degrade_residual(tab, g.n, g.lr_total, s, gauss_taps(1.0), 0, P<float>(B.e), B.stream) !=
                             hipSuccess ||
                         launch_b_bp_update(tab, g.n, g.tiles, tiles[ti], mults[mi] * ncu, s, b->sigma_s, b->sigma_r,
-                                           P<float>(B.e), 0, P<unsigned int>(B.counter), B.stream) != hipSuccess) {
-                        rc = fail(c, ZH_EDEVICE, "zh_tune_batch: launch failed");
-                        break;
-                    }
+                                           P<float>(B.e), 0, P<unsigned int>(B.counter), B.stream) != hipSuccess)
+                        return false;
                 }
-                (void)hipEventRecord(e1, B.stream);
-                (void)hipEventSynchronize(e1);
-                float t = 0.f;
-                (void)hipEventElapsedTime(&t, e0, e1);
-                bestrun = std::min(bestrun, t);
-            }
-            ms[ti * 3 + mi] = bestrun;
-            if (best < 0 || bestrun < ms[best]) best = ti * 3 + mi;
+                return true;
+            }, ms[ti * 3 + mi]);
+            if (best < 0 || ms[ti * 3 + mi] < ms[best]) best = ti * 3 + mi;
         }
+    }
+    // synthesis of the last zoom factor of the batch (its neighbours and
+    // weights are the context's) with 32 and 64 lanes per patch
+    float sms[2] = {0.f, 0.f};
+    int sbest = 32;
+    int last = 0;
+    for (int s = 1; s <= kMaxScale; ++s)
+        if (B.g[s].n) last = s;
+    if (rc == ZH_OK && last > 0) {
+        const auto& g = B.g[last];
+        const int ps2 = (kPatch * last) * (kPatch * last);
+        const Dict& d = c->dicts[last];
+        for (int gi = 0; gi < 2 && rc == ZH_OK; ++gi)
+            time_once([&]() {
+                return launch_synth((int)g.q_total, b->K, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
+                                    P<double>(c->qmu), d.resid, P<float>(c->xhat), B.stream, gi ? 64 : 32) == hipSuccess;
+            }, sms[gi]);
+        sbest = sms[1] < sms[0] ? 64 : 32;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != ZH_OK || best < 0) {
         B.tile = keep_tile;
         B.grid_per_cu = keep_mult;
+        B.synth_group = keep_group;
         B.sig.clear();
         return rc != ZH_OK ? rc : fail(c, ZH_EDEVICE, "zh_tune_batch: nothing timed");
     }
     B.tile = tiles[best / 3];
     B.grid_per_cu = mults[best % 3];
+    B.synth_group = sbest;
     B.sig.clear();   // re-plan and capture again with the chosen tuning
-    if (out) {
-        out->bp_tile = B.tile;
-        out->bp_grid_per_cu = B.grid_per_cu;
-        for (int i = 0; i < 6; ++i) out->bp_ms[i] = ms[i];
-    }
+    zh_batch_tuning t{};
+    t.bp_tile = B.tile;
+    t.bp_grid_per_cu = B.grid_per_cu;
+    for (int i = 0; i < 6; ++i) t.bp_ms[i] = ms[i];
+    t.synth_group = sbest;
+    t.synth_ms[0] = sms[0];
+    t.synth_ms[1] = sms[1];
+    t.from_cache = 0;
+    if (cache && cache[0]) tune_store(cache, key, dev, arch, rt, t);
+    if (out) *out = t;
     return ZH_OK;
 }
 

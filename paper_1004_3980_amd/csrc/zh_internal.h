@@ -228,9 +228,10 @@ hipError_t launch_cand_t(int Q, int L, int64_t N, int t, const uint2* bins, cons
 int64_t entropy_scratch_bytes(int L, uint64_t cap);
 hipError_t launch_table_entropy(const Slot* dir, int L, uint64_t cap, int64_t n, void* scratch, double* out,
                                 hipStream_t st);
+// group: lanes per patch of the 16-byte path (0: 32 when (5s)^2 <= 128, else 64; 64: a wave)
 hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m,
                         const float* w, const double* mu, const float* resid, float* xhat,
-                        hipStream_t st);
+                        hipStream_t st, int group = 0);
 hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, int h, int w,
                         int scale, float* hr, hipStream_t st);
 

@@ -94,8 +94,39 @@ def test_batch_after_autotuning():
     got, info = _batch(st, 3, 5, 1e-3, 1.5, 0.1, tune=True)
     assert info["bp_tile"] in (16, 32) and info["bp_grid_per_cu"] in (2, 4, 8)
     assert all(t > 0 for t in info["bp_ms"])
+    assert info["synth_group"] in (32, 64) and all(t > 0 for t in info["synth_ms"]) and info["from_cache"] == 0
     for r, g in zip(ref, got):
         assert torch.equal(r, g)
+
+
+def test_tuning_cache(tmp_path, monkeypatch):
+    """With ZH_TUNE_CACHE set, the first tuning of a batch times and appends
+    its choice (one JSON object per line, keyed by device, HIP runtime and
+    batch); the next tuning of the same batch takes it from the file without
+    timing; another batch (other K) is timed again. Outputs stay equal to the
+    images run one by one."""
+    import json
+    st = _setup()
+    torch = st["torch"]
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("ZH_TUNE_CACHE", str(path))
+    ref = _one_by_one(st, 2, 5, 1e-3, 1.5, 0.1)
+    got, info = _batch(st, 2, 5, 1e-3, 1.5, 0.1, tune=True)
+    assert info["from_cache"] == 0
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert rec["bp_tile"] == info["bp_tile"] and rec["synth_group"] == info["synth_group"]
+    assert rec["arch"].startswith("gfx9") and rec["hip_runtime"] > 0
+    got2, info2 = _batch(st, 2, 5, 1e-3, 1.5, 0.1, tune=True)
+    assert info2["from_cache"] == 1 and info2["bp_ms"] == [0.0] * 6
+    assert (info2["bp_tile"], info2["bp_grid_per_cu"], info2["synth_group"]) == \
+        (info["bp_tile"], info["bp_grid_per_cu"], info["synth_group"])
+    assert len(path.read_text().splitlines()) == 1
+    for r, a, b in zip(ref, got, got2):
+        assert torch.equal(r, a) and torch.equal(r, b)
+    _, info3 = _batch(st, 2, 6, 1e-3, 1.5, 0.1, tune=True)
+    assert info3["from_cache"] == 0 and len(path.read_text().splitlines()) == 2
 
 
 @pytest.mark.parametrize("size", [(14, 30, 3), (18, 21, 4)])
