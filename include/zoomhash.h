@@ -384,10 +384,14 @@ zh_status zh_run_batch(zh_ctx* ctx, const zh_batch* batch);
  * sub-problems; the launch shapes are chosen per batch): runs the batch once,
  * then times (HIP events, best of 2) the back-projection update over the
  * batch's tiles for tile sides {16, 32} and persistent grids of {2, 4, 8}
- * workgroups per compute unit, and the HR synthesis of the last zoom factor
- * with 32 and 64 lanes per patch; keeps the fastest of each for later
- * zh_run_batch calls and reports them in *out (host, nullable). The images'
- * outputs are overwritten. When the environment names a cache file
+ * workgroups per compute unit, and the fused synthesis and blend of the last
+ * zoom factor with tiles of 4 and 8 patch rows; keeps the fastest of each
+ * for later zh_run_batch calls and reports them in *out (host, nullable).
+ * The tile height is the context's for zh_reconstruct too: it sets how the
+ * blend's sum of a pixel is grouped (patch rows of one tile, then tile by
+ * tile), so outputs may change in the last bits after tuning, and the
+ * batched and single-image results stay bitwise equal. The images' outputs
+ * are overwritten. When the environment names a cache file
  * (ZH_TUNE_CACHE), a previous choice for the same device (name and
  * architecture), HIP runtime version and batch (sizes, zoom factors, K,
  * iterations, query options) is taken from it without timing (from_cache =
@@ -397,8 +401,8 @@ typedef struct {
     int32_t bp_tile;             /* chosen tile side */
     int32_t bp_grid_per_cu;      /* chosen workgroups per compute unit */
     float bp_ms[6];              /* per configuration (tile 16: 2, 4, 8; tile 32: 2, 4, 8), ms per iteration */
-    int32_t synth_group;         /* chosen lanes per patch of the synthesis (32 or 64) */
-    float synth_ms[2];           /* synthesis of the last zoom factor with 32 and 64 lanes per patch, ms */
+    int32_t synth_rows;          /* chosen patch rows per tile of the fused synthesis and blend (4 or 8) */
+    float synth_ms[2];           /* synthesis and blend of the last zoom factor with tiles of 4 and 8 rows, ms */
     int32_t from_cache;          /* 1: the choice came from the cache file */
 } zh_batch_tuning;
 zh_status zh_tune_batch(zh_ctx* ctx, const zh_batch* batch, zh_batch_tuning* out);

@@ -108,15 +108,19 @@ __host__ __device__ inline int stage_bytes(int prec, int k, int D) {
 // its beta and bound constants and shared by the four waves; on the split
 // path the next pair is fetched into registers while the current one is in
 // use. The 2k hash rows of a pair are packed into ceil(2k/16) MFMA tiles.
+// A wave owns RT tiles of 16 feature rows: every A fragment read from LDS
+// feeds the products of all RT tiles (RT = 2 halves the LDS reads and the
+// staging per row).
 // A code whose interval [P - B, P + B] holds an integer is left to the FP64
 // definition: the table's k codes go to a compact list (the uncertain ones
 // marked kCodeUnset) for k_hash_fixlist, or, when the list is full, the
 // table's bit is set in the row's dirty mask for k_hash_fix; the key written
-// here is replaced there.
-// Three waves per SIMD (at most 168 registers, a few bytes of spill) run the
-// kernel faster than two without spill.
-template <int PREC, int NS, int NPRE>
-__global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
+// here is replaced there. The list has a region of fix_cap entries per 16
+// feature rows.
+// Three waves per SIMD (at most 168 registers) for one tile a wave, two for two.
+template <int PREC, int NS, int NPRE, int RT>
+__global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
+    constexpr int RPW = kRowsPerWave * RT;   // feature rows of a wave
     const int D = a.D, k = a.k, L = a.L, m = L * k;
     const int GK = kStage * k;
     const int R = stage_rows(k);
@@ -124,72 +128,77 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
     const int nsteps = PREC == 0 ? (D + 3) / 4 : NS;
     const int DP = (D + 31) & ~31;
     const int DS = stage_stride(PREC, D);
-    const int fold = fold_tables(k);
+    const int fold = fold_tables(k) / RT;   // tables folded together: fold * RPW = 64 lanes
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ri = lane & 15, kb = lane >> 4;
-    const int64_t r0 = ((int64_t)blockIdx.x * kWaves + wave) * kRowsPerWave;
-    const int64_t myrow = r0 + ri;
-    const bool rowok = myrow < a.n;
+    const int64_t r0 = ((int64_t)blockIdx.x * kWaves + wave) * RPW;
 
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* sA16 = reinterpret_cast<uint16_t*>(smem);
     float* sAf = reinterpret_cast<float*>(smem);
     float* sBeta = reinterpret_cast<float*>(smem + ((stage_alpha_bytes(PREC, k, D) + 15) & ~15));
     float* sBc0 = sBeta + R;
-    // per wave codes of `fold` tables: [fold*k][16 rows], then per wave a flag
-    // per (table of the fold group, row) with an uncertain code
-    int32_t* sC = reinterpret_cast<int32_t*>(smem + stage_bytes(PREC, k, D)) + wave * (fold * k * kRowsPerWave);
+    // per wave codes of `fold` tables: [fold*k][RPW rows], then per wave a
+    // flag per (table of the fold group, row) with an uncertain code
+    int32_t* sC = reinterpret_cast<int32_t*>(smem + stage_bytes(PREC, k, D)) + wave * (fold * k * RPW);
     uint8_t* sU = reinterpret_cast<uint8_t*>(reinterpret_cast<int32_t*>(smem + stage_bytes(PREC, k, D)) +
-                                             kWaves * fold * k * kRowsPerWave) + wave * (4 * kRowsPerWave);
-    if (lane < 4 * kRowsPerWave) sU[lane] = 0;
+                                             kWaves * fold * k * RPW) + wave * 64;
+    sU[lane] = 0;
     // key multipliers of every table, [L][k + 1]
-    uint64_t* smul = reinterpret_cast<uint64_t*>(reinterpret_cast<unsigned char*>(sU - wave * (4 * kRowsPerWave)) +
-                                                 kWaves * 4 * kRowsPerWave);
+    uint64_t* smul = reinterpret_cast<uint64_t*>(reinterpret_cast<unsigned char*>(sU - wave * 64) + kWaves * 64);
     for (int e = threadIdx.x; e < L * (k + 1); e += 256) smul[e] = a.key_mul[e];
 
-    // B operand of this lane for every k-step: feature row ri, coordinates
-    // 32 s + 8 kb + e (e < 8) as bf16 high/low parts (PREC 1), or 4 s + kb
-    // as fp32 (PREC 0)
-    u16x8 bh[PREC == 1 ? NS : 1], bl[PREC == 1 ? NS : 1];
+    // B operand of this lane for every k-step and row tile rt: feature row
+    // r0 + 16 rt + ri, coordinates 32 s + 8 kb + e (e < 8) as bf16 high/low
+    // parts (PREC 1), or 4 s + kb as fp32 (PREC 0)
+    u16x8 bh[RT][PREC == 1 ? NS : 1], bl[RT][PREC == 1 ? NS : 1];
     float bf[PREC == 0 ? 32 : 1];
+    bool rowok[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) rowok[rt] = r0 + 16 * rt + ri < a.n;
     if (PREC == 1) {
         // rows on 16-byte boundaries: two 16-byte loads per step
         const bool vec = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(a.feat) & 15) == 0;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int d0 = 32 * s + 8 * kb;
-            float x[8];
-            if (vec) {
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t row = r0 + 16 * rt + ri;
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const float4 v = (rowok && d0 + 4 * j < D)
-                                         ? *reinterpret_cast<const float4*>(a.feat + myrow * D + d0 + 4 * j)
-                                         : make_float4(0.f, 0.f, 0.f, 0.f);
-                    x[4 * j] = v.x;
-                    x[4 * j + 1] = v.y;
-                    x[4 * j + 2] = v.z;
-                    x[4 * j + 3] = v.w;
+            for (int s = 0; s < NS; ++s) {
+                const int d0 = 32 * s + 8 * kb;
+                float x[8];
+                if (vec) {
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const float4 v = (rowok[rt] && d0 + 4 * j < D)
+                                             ? *reinterpret_cast<const float4*>(a.feat + row * D + d0 + 4 * j)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+                        x[4 * j] = v.x;
+                        x[4 * j + 1] = v.y;
+                        x[4 * j + 2] = v.z;
+                        x[4 * j + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) x[e] = (rowok[rt] && d0 + e < D) ? a.feat[row * D + d0 + e] : 0.0f;
                 }
-            } else {
+                // high part: x rounded to bf16 (nearest even); low part: the
+                // exact remainder rounded likewise
+                bf16x8 hv, lv;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) x[e] = (rowok && d0 + e < D) ? a.feat[myrow * D + d0 + e] : 0.0f;
+                for (int e = 0; e < 8; ++e) {
+                    hv[e] = (__bf16)x[e];
+                    lv[e] = (__bf16)(x[e] - (float)hv[e]);
+                }
+                bh[rt][s] = __builtin_bit_cast(u16x8, hv);
+                bl[rt][s] = __builtin_bit_cast(u16x8, lv);
             }
-            // high part: x rounded to bf16 (nearest even); low part: the
-            // exact remainder rounded likewise
-            bf16x8 hv, lv;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                hv[e] = (__bf16)x[e];
-                lv[e] = (__bf16)(x[e] - (float)hv[e]);
-            }
-            bh[s] = __builtin_bit_cast(u16x8, hv);
-            bl[s] = __builtin_bit_cast(u16x8, lv);
         }
     } else {
+        const int64_t row = r0 + ri;
 #pragma unroll
         for (int s = 0; s < 32; ++s) {
             const int d = 4 * s + kb;
-            bf[s] = (rowok && d < D) ? a.feat[myrow * D + d] : 0.0f;
+            bf[s] = (rowok[0] && d < D) ? a.feat[row * D + d] : 0.0f;
         }
     }
     const float c1 = a.bound_c1, c2 = a.bound_c2;
@@ -280,16 +289,23 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
     }
     __syncthreads();
 
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + wave;
+    // fix-list regions of the wave: one per 16 rows (region of lane (t, rr)
+    // in the fold stage: rr / 16)
+    const int64_t w16 = r0 / kRowsPerWave;
     uint64_t dirty = 0;
-    unsigned nflag = 0, wcnt = 0;
+    unsigned nflag = 0;
+    unsigned wcnt[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) wcnt[rt] = 0;
     for (int g = 0; g < ngroups; ++g) {
         const int l0 = g * kStage;
         const int GKa = (L - l0 < kStage ? L - l0 : kStage) * k;
         if (PREC == 1 && g + 1 < ngroups) fetch(g + 1);
         for (int tt = 0; tt < ntile; ++tt) {
             const int ar = tt * 16 + ri;
-            f32x4 cs = f32x4{0.f, 0.f, 0.f, 0.f}, cab = cs;
+            f32x4 cs[RT], cab[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) cs[rt] = cab[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
             if (PREC == 1) {
                 // the three split products share one fp32 accumulator: the
                 // bound covers any order of the 3 DP additions
@@ -303,24 +319,28 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
                 }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const bf16x8 vhb = __builtin_bit_cast(bf16x8, bh[s]);
-                    const bf16x8 vlb = __builtin_bit_cast(bf16x8, bl[s]);
-                    const bf16x8 vab = __builtin_bit_cast(bf16x8, abs8(bh[s]));
                     const bf16x8 ahb = __builtin_bit_cast(bf16x8, ah[s]);
                     const bf16x8 alb = __builtin_bit_cast(bf16x8, al[s]);
                     const bf16x8 aab8 = __builtin_bit_cast(bf16x8, abs8(ah[s]));
-                    cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vhb, cs, 0, 0, 0);
-                    cab = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aab8, vab, cab, 0, 0, 0);
-                    cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, cs, 0, 0, 0);
-                    cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, cs, 0, 0, 0);
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) {
+                        const bf16x8 vhb = __builtin_bit_cast(bf16x8, bh[rt][s]);
+                        const bf16x8 vlb = __builtin_bit_cast(bf16x8, bl[rt][s]);
+                        const bf16x8 vab = __builtin_bit_cast(bf16x8, abs8(bh[rt][s]));
+                        cs[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vhb, cs[rt], 0, 0, 0);
+                        cab[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aab8, vab, cab[rt], 0, 0, 0);
+                        cs[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahb, vlb, cs[rt], 0, 0, 0);
+                        cs[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alb, vhb, cs[rt], 0, 0, 0);
+                    }
                 }
             } else {
                 const float* Af = sAf + ar * DS;
                 for (int s = 0; s < nsteps; ++s) {
                     const int d = 4 * s + kb;
                     const float av = d < D ? Af[d] : 0.0f;
-                    cs = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[s < 32 ? s : 0], cs, 0, 0, 0);
-                    cab = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(av), fabsf(bf[s < 32 ? s : 0]), cab, 0, 0, 0);
+                    cs[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[s < 32 ? s : 0], cs[0], 0, 0, 0);
+                    cab[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(av), fabsf(bf[s < 32 ? s : 0]), cab[0], 0, 0,
+                                                                  0);
                 }
             }
             // 16x16 tile: lane holds hash rows 4*kb+i of the tile, feature row ri
@@ -332,37 +352,40 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
             // slots belong to other tables); codes of feature rows past n are
             // written but never read
             const bool full = tt * 16 + 16 <= GKa;
-            int32_t* cdst = sC + ((l0 % fold) * k + tt * 16 + 4 * kb) * kRowsPerWave + ri;
-            unsigned fl = 0;
-            int32_t cv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float S = cs[i];
-                const float P = (S + bev[i]) * a.inv_w;
-                const float B = fmaf(c1, cab[i], fmaf(c2, fabsf(S), b0v[i]));
-                // uncertain when an integer lies within B of P; every P of
-                // magnitude >= 2^23 is an integer, so each certain code has
-                // |floor(P)| <= 2^23 (a NaN P or B is uncertain as well)
-                const bool flag = !(fabsf(P - rintf(P)) > B);
-                fl |= (flag ? 1u : 0u) << i;
-                const int32_t c = cvt_floor(P);
-                cv[i] = flag ? kCodeUnset : c;
-            }
-            if (full) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) cdst[i * kRowsPerWave] = cv[i];
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (tt * 16 + 4 * kb + i < GKa) cdst[i * kRowsPerWave] = cv[i];
-            }
-            if (fl != 0 && rowok) {
+            for (int rt = 0; rt < RT; ++rt) {
+                int32_t* cdst = sC + ((l0 % fold) * k + tt * 16 + 4 * kb) * RPW + 16 * rt + ri;
+                unsigned fl = 0;
+                int32_t cv[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int hr = tt * 16 + 4 * kb + i;
-                    if (((fl >> i) & 1u) && hr < GKa) {
-                        ++nflag;
-                        sU[((l0 % fold) + (hr >= k ? 1 : 0)) * kRowsPerWave + ri] = 1;
+                    const float S = cs[rt][i];
+                    const float P = (S + bev[i]) * a.inv_w;
+                    const float B = fmaf(c1, cab[rt][i], fmaf(c2, fabsf(S), b0v[i]));
+                    // uncertain when an integer lies within B of P; every P of
+                    // magnitude >= 2^23 is an integer, so each certain code has
+                    // |floor(P)| <= 2^23 (a NaN P or B is uncertain as well)
+                    const bool flag = !(fabsf(P - rintf(P)) > B);
+                    fl |= (flag ? 1u : 0u) << i;
+                    const int32_t c = cvt_floor(P);
+                    cv[i] = flag ? kCodeUnset : c;
+                }
+                if (full) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cdst[i * RPW] = cv[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (tt * 16 + 4 * kb + i < GKa) cdst[i * RPW] = cv[i];
+                }
+                if (fl != 0 && rowok[rt]) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int hr = tt * 16 + 4 * kb + i;
+                        if (((fl >> i) & 1u) && hr < GKa) {
+                            ++nflag;
+                            sU[((l0 % fold) + (hr >= k ? 1 : 0)) * RPW + 16 * rt + ri] = 1;
+                        }
                     }
                 }
             }
@@ -377,48 +400,58 @@ __global__ __launch_bounds__(256, 3) void k_hash(HashArgs a) {
         if ((l0 + kStage) % fold == 0 || g + 1 == ngroups) {
             // fold codes into keys: lane = (table of the fold group, feature row)
             const int fl0 = (l0 / fold) * fold;
-            const int t = lane >> 4, rr = lane & 15;
+            const int t = lane / RPW, rr = lane - t * RPW;
             const int lt = fl0 + t;
             const int64_t row = r0 + rr;
             const bool act = t < fold && lt < L && row < a.n;
-            const bool unset = act && sU[t * kRowsPerWave + rr] != 0;
-            // a table with an uncertain code goes to this wave's region of the
-            // fix list with its codes (or, when the region is full, to the
+            const bool unset = act && sU[t * RPW + rr] != 0;
+            // a table with an uncertain code goes to the fix-list region of
+            // its row's 16 with its codes (or, when the region is full, to the
             // row's dirty mask)
             const uint64_t bal = __ballot(unset);
-            const int idx = (int)wcnt + __popcll(bal & lanemask_lt());
+            const int reg = rr >> 4;
+            // lanes of region reg: rr in [16 reg, 16 reg + 16) of every table slot
+            const uint64_t regmask = RT == 1 ? ~0ull : (reg ? 0xFFFF0000FFFF0000ull : 0x0000FFFF0000FFFFull);
+            const int idx = (int)wcnt[RT == 1 ? 0 : reg] + __popcll(bal & regmask & lanemask_lt());
             int32_t* ent = nullptr;
             if (unset) {
                 if (idx < a.fix_cap) {
-                    ent = a.fix_list + ((int64_t)wid * a.fix_cap + idx) * fix_entry_ints(k);
+                    ent = a.fix_list + ((w16 + reg) * a.fix_cap + idx) * fix_entry_ints(k);
                     ent[0] = (int32_t)row;
                     ent[1] = lt;
                 } else {
                     dirty |= 1ull << lt;
                 }
             }
-            wcnt += (unsigned)__popcll(bal);
+            if (RT == 1) {
+                wcnt[0] += (unsigned)__popcll(bal);
+            } else {
+                wcnt[0] += (unsigned)__popcll(bal & 0x0000FFFF0000FFFFull);
+                wcnt[RT - 1] += (unsigned)__popcll(bal & 0xFFFF0000FFFF0000ull);
+            }
             if (act) {
                 const uint64_t* mul = smul + lt * (k + 1);
-                const int32_t* cp = sC + t * k * kRowsPerWave + rr;
+                const int32_t* cp = sC + t * k * RPW + rr;
                 uint64_t h = mul[k];
 #pragma unroll 10
-                for (int j = 0; j < k; ++j) h += key_term(cp[j * kRowsPerWave], mul[j]);
+                for (int j = 0; j < k; ++j) h += key_term(cp[j * RPW], mul[j]);
                 a.keys[key_pos(a, row, lt)] = key_final(h);
                 if (a.codes)
-                    for (int j = 0; j < k; ++j) a.codes[row * m + lt * k + j] = cp[j * kRowsPerWave];
+                    for (int j = 0; j < k; ++j) a.codes[row * m + lt * k + j] = cp[j * RPW];
                 if (ent)
-                    for (int j = 0; j < k; ++j) ent[2 + j] = cp[j * kRowsPerWave];
+                    for (int j = 0; j < k; ++j) ent[2 + j] = cp[j * RPW];
             }
-            if (lane < 4 * kRowsPerWave) sU[lane] = 0;
+            sU[lane] = 0;
         }
         __syncthreads();
     }
     // tables of the fold lanes (t, row) that did not fit in the list
-    dirty |= __shfl_xor(dirty, 16);
-    dirty |= __shfl_xor(dirty, 32);
-    if (kb == 0 && rowok) a.dirty[myrow] = dirty;
-    if (lane == 0 && r0 < a.n) a.fix_count[wid] = wcnt < (unsigned)a.fix_cap ? wcnt : (unsigned)a.fix_cap;
+    for (int o = RPW; o < 64; o <<= 1) dirty |= __shfl_xor(dirty, o);
+    if (lane < RPW && r0 + lane < a.n) a.dirty[r0 + lane] = dirty;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+        if (lane == 0 && r0 + 16 * rt < a.n)
+            a.fix_count[w16 + rt] = wcnt[rt] < (unsigned)a.fix_cap ? wcnt[rt] : (unsigned)a.fix_cap;
     if (nflag && a.n_fixed) atomicAdd(a.n_fixed, nflag);
 }
 
@@ -650,13 +683,25 @@ void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, floa
     for (int j = 0; j < m; ++j) c0[j] = (float)((2.0 * 3.1 * u * std::fabs((double)beta[j]) / w + 1e-30) * up);
 }
 
+// Split path: two 16-row tiles per wave when the fold group of four tables
+// splits into two (k <= 24), else one.
 template <int NS>
-static void launch_split(const HashArgs& a, dim3 grid, size_t lds, hipStream_t st) {
+static void launch_split(const HashArgs& a, size_t lds, hipStream_t st) {
     const int nc = 2 * kStage * a.k * 4 * NS;
-    if (nc <= 5 * 256)
-        hipLaunchKernelGGL((k_hash<1, NS, 5>), grid, dim3(256), lds, st, a);
-    else
-        hipLaunchKernelGGL((k_hash<1, NS, 8>), grid, dim3(256), lds, st, a);
+    const int rt = fold_tables(a.k) == 4 ? 2 : 1;
+    const int rows = kWaves * kRowsPerWave * rt;
+    const dim3 grid((unsigned)((a.n + rows - 1) / rows));
+    if (rt == 2) {
+        if (nc <= 5 * 256)
+            hipLaunchKernelGGL((k_hash<1, NS, 5, 2>), grid, dim3(256), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_hash<1, NS, 8, 2>), grid, dim3(256), lds, st, a);
+    } else {
+        if (nc <= 5 * 256)
+            hipLaunchKernelGGL((k_hash<1, NS, 5, 1>), grid, dim3(256), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_hash<1, NS, 8, 1>), grid, dim3(256), lds, st, a);
+    }
 }
 
 hipError_t launch_hash(const HashArgs& a, hipStream_t st) {
@@ -682,19 +727,19 @@ hipError_t launch_hash_codes(const HashArgs& a, hipStream_t st) {
         a.fix_cap < 0 || a.fix_cap > kFixSlots || (a.fix_cap > 0 && !a.fix_list) ||
         (a.bins && (!a.keys_tmajor || !a.dir || !a.dir_filter)))
         return hipErrorInvalidValue;
-    const int rows = kWaves * kRowsPerWave;
-    const dim3 grid((unsigned)((a.n + rows - 1) / rows));
     const size_t lds = (size_t)stage_bytes(a.prec, a.k, a.D) +
                        (size_t)kWaves * fold_tables(a.k) * a.k * kRowsPerWave * 4 + kWaves * 4 * kRowsPerWave +
                        sizeof(uint64_t) * (size_t)a.L * (a.k + 1);
     if (a.prec == 0) {
-        hipLaunchKernelGGL((k_hash<0, 1, 1>), grid, dim3(256), lds, st, a);
+        const int rows = kWaves * kRowsPerWave;
+        const dim3 grid((unsigned)((a.n + rows - 1) / rows));
+        hipLaunchKernelGGL((k_hash<0, 1, 1, 1>), grid, dim3(256), lds, st, a);
     } else {
         switch ((a.D + 31) / 32) {
-            case 1: launch_split<1>(a, grid, lds, st); break;
-            case 2: launch_split<2>(a, grid, lds, st); break;
-            case 3: launch_split<3>(a, grid, lds, st); break;
-            default: launch_split<4>(a, grid, lds, st); break;
+            case 1: launch_split<1>(a, lds, st); break;
+            case 2: launch_split<2>(a, lds, st); break;
+            case 3: launch_split<3>(a, lds, st); break;
+            default: launch_split<4>(a, lds, st); break;
         }
     }
     hipError_t e = hipGetLastError();

@@ -7,6 +7,7 @@
 // A workgroup (one wave) forms the Gram matrices of QPW patches one after
 // the other, every lane owning one (a, b) entry; then each lane solves one
 // patch's system.
+#include <algorithm>
 #include <type_traits>
 
 #include "zh_internal.h"
@@ -705,6 +706,284 @@ __global__ __launch_bounds__(kBlendSeg) void k_b_blend(const BatchImage* __restr
     const int Y = (int)(lb / nseg);
     blend_seg<s>(xhat + b.q_off * ps2, m + b.q_off, b.lr, b.h, b.w, Y, (int)(lb - (int64_t)Y * nseg) * kBlendSeg,
                  b.out);
+}
+
+// ---- synthesis fused with the blend -------------------------------------------
+// The synthesised patches are never written out. The patch origins are cut
+// into tiles of TI patch rows x sb_cols(s) patch columns; a workgroup takes a
+// tile, forms x_q = mu_q + sum_m w_m r_{n_m} of one patch row at a time in
+// LDS (the K residual rows read once, in chunks of eight neighbours, with the
+// same fused multiply-adds in the same order as k_synth4) and adds each
+// pixel's values of the row's patches, in ascending column order, to the
+// tile's region: the (TI + 4) s x (TJ + 4) s HR pixels its patches cover,
+// together with the count of covering patches of every LR cell. Regions go
+// to a partial buffer; k_sb_combine then gives each HR pixel the sum of the
+// (at most four) regions that hold it, in tile order, divided by the summed
+// count, or the bicubic of the LR image where no patch covers it. The sum
+// of a pixel is therefore taken patch row by patch row in row-major order
+// inside a tile and tile by tile across tiles.
+template <int s, int TI>
+struct SbGeom {
+    static constexpr int ps = kPatch * s, ps2 = ps * ps;
+    static constexpr int VEC = (ps2 & 3) == 0 ? 4 : 1;    // floats per load
+    static constexpr int NCH = ps2 / VEC;                  // loads per residual row
+    static constexpr int TJ = sb_cols(s);
+    static constexpr int CY = TI + kPatch - 1, CX = TJ + kPatch - 1;   // LR cells of a region
+    static constexpr int RY = CY * s, RX = CX * s;                       // HR pixels of a region
+    static constexpr int64_t PART = (int64_t)RY * RX + CY * CX;         // floats + counts per tile
+};
+
+template <int s, int TI>
+__device__ __forceinline__ void sb_tile(const int32_t* __restrict__ ids, const int32_t* __restrict__ m,
+                                        const float* __restrict__ wt, const double* __restrict__ mu,
+                                        const float* __restrict__ resid, int K, int h, int w, int64_t tile,
+                                        float* __restrict__ part) {
+    using G = SbGeom<s, TI>;
+    constexpr int ps = G::ps, ps2 = G::ps2, VEC = G::VEC, NCH = G::NCH, TJ = G::TJ;
+    constexpr int CX = G::CX, RY = G::RY, RX = G::RX, CY = G::CY;
+    __shared__ __align__(16) float sx[TJ * ps2];   // the synthesised patches of one patch row
+    __shared__ float sacc[RY * RX];
+    __shared__ int scnt[CY * CX];
+    __shared__ int64_t sbase[TJ * 8];              // residual row offsets of a chunk (-1: none)
+    __shared__ float swt[TJ * 8];
+    __shared__ int sflag[TJ];
+    __shared__ float smu[TJ];
+    const int tid = threadIdx.x;
+    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
+    const int ntj = (npj + TJ - 1) / TJ;
+    const int ti = (int)(tile / ntj), tj = (int)(tile - (int64_t)ti * ntj);
+    const int i0 = ti * TI, j0 = tj * TJ;
+    for (int e = tid; e < RY * RX; e += 256) sacc[e] = 0.0f;
+    for (int e = tid; e < CY * CX; e += 256) scnt[e] = 0;
+    for (int ii = 0; ii < TI && i0 + ii < npi; ++ii) {
+        const int64_t qrow = (int64_t)(i0 + ii) * npj;
+        // ---- the patches of this row
+        for (int r0 = 0; r0 < K; r0 += 8) {
+            __syncthreads();   // the previous chunk, row or the zeroing is done
+            for (int e = tid; e < TJ * 8; e += 256) {
+                const int jj = e >> 3, r = e & 7, j = j0 + jj;
+                const int64_t q = qrow + j;
+                const int mq = j < npj ? m[q] : 0;
+                const bool ok = r0 + r < mq;
+                sbase[e] = ok ? (int64_t)ids[q * K + r0 + r] * ps2 : -1;
+                swt[e] = ok ? wt[q * K + r0 + r] : 0.0f;
+                if (r0 == 0 && r == 0) {
+                    sflag[jj] = mq > 0;
+                    smu[jj] = mq > 0 ? (float)mu[q] : 0.0f;
+                }
+            }
+            __syncthreads();
+            const bool last = r0 + 8 >= K;
+            for (int it = tid; it < TJ * NCH; it += 256) {
+                const int jj = it / NCH, c = it - jj * NCH;
+                float* dst = sx + jj * ps2 + c * VEC;
+                float acc[VEC];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] = r0 == 0 ? 0.0f : dst[e];
+                float v[8][VEC];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int64_t b = sbase[jj * 8 + r];
+                    if constexpr (VEC == 4) {
+                        const float4 x = b >= 0 ? *reinterpret_cast<const float4*>(resid + b + 4 * c)
+                                                : make_float4(0.f, 0.f, 0.f, 0.f);
+                        v[r][0] = x.x;
+                        v[r][1] = x.y;
+                        v[r][2] = x.z;
+                        v[r][3] = x.w;
+                    } else {
+                        v[r][0] = b >= 0 ? resid[b + c] : 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const float wr = swt[jj * 8 + r];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = fmaf(wr, v[r][e], acc[e]);
+                }
+                const float mf = last ? smu[jj] : 0.0f;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) dst[e] = last ? mf + acc[e] : acc[e];
+            }
+        }
+        __syncthreads();
+        // ---- their values added to the region rows s ii .. s ii + 5 s
+        for (int it = tid; it < ps * RX; it += 256) {
+            const int u = it / RX, X = it - u * RX;
+            const int cl = X / s;
+            const int jlo = cl - (kPatch - 1) > 0 ? cl - (kPatch - 1) : 0, jhi = cl < TJ - 1 ? cl : TJ - 1;
+            float* a = sacc + (s * ii + u) * RX + X;
+            float acc = *a;
+            for (int jj = jlo; jj <= jhi; ++jj)
+                if (sflag[jj]) acc += sx[jj * ps2 + u * ps + X - s * jj];
+            *a = acc;
+        }
+        for (int it = tid; it < kPatch * CX; it += 256) {
+            const int cu = it / CX, cl = it - cu * CX;
+            const int jlo = cl - (kPatch - 1) > 0 ? cl - (kPatch - 1) : 0, jhi = cl < TJ - 1 ? cl : TJ - 1;
+            int n = 0;
+            for (int jj = jlo; jj <= jhi; ++jj) n += sflag[jj];
+            scnt[(ii + cu) * CX + cl] += n;
+        }
+    }
+    __syncthreads();
+    float* pa = part + tile * G::PART;
+    int* pc = reinterpret_cast<int*>(pa + RY * RX);
+    for (int e = tid; e < RY * RX; e += 256) pa[e] = sacc[e];
+    for (int e = tid; e < CY * CX; e += 256) pc[e] = scnt[e];
+}
+
+template <int s, int TI>
+__device__ __forceinline__ float sb_pixel(const float* __restrict__ part, const float* __restrict__ lr, int h, int w,
+                                          int Y, int X) {
+    using G = SbGeom<s, TI>;
+    constexpr int TJ = G::TJ, CX = G::CX, RX = G::RX, RY = G::RY;
+    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
+    float acc = 0.0f;
+    int cnt = 0;
+    if (npi > 0 && npj > 0) {
+        const int ntj = (npj + TJ - 1) / TJ, nti = (npi + TI - 1) / TI;
+        const int cy = Y / s, cx = X / s;
+        // tiles holding a patch origin in [cy - 4, cy] x [cx - 4, cx]
+        const int tilo = cy >= kPatch - 1 ? (cy - (kPatch - 1)) / TI : 0, tihi = min(nti - 1, cy / TI);
+        const int tjlo = cx >= kPatch - 1 ? (cx - (kPatch - 1)) / TJ : 0, tjhi = min(ntj - 1, cx / TJ);
+        for (int ti = tilo; ti <= tihi; ++ti)
+            for (int tj = tjlo; tj <= tjhi; ++tj) {
+                const float* pa = part + ((int64_t)ti * ntj + tj) * G::PART;
+                const int ly = Y - s * TI * ti, lx = X - s * TJ * tj;
+                acc += pa[ly * RX + lx];
+                cnt += reinterpret_cast<const int*>(pa + RY * RX)[(cy - TI * ti) * CX + (cx - TJ * tj)];
+            }
+    }
+    return cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
+}
+
+template <int s, int TI>
+__global__ __launch_bounds__(256) void k_sb_tile(int K, int h, int w, const int32_t* __restrict__ ids,
+                                                 const int32_t* __restrict__ m, const float* __restrict__ wt,
+                                                 const double* __restrict__ mu, const float* __restrict__ resid,
+                                                 float* __restrict__ part) {
+    sb_tile<s, TI>(ids, m, wt, mu, resid, K, h, w, xcd_block(), part);
+}
+
+template <int s, int TI>
+__global__ __launch_bounds__(256) void k_sb_combine(const float* __restrict__ part, const float* __restrict__ lr,
+                                                    int h, int w, float* __restrict__ hr) {
+    const int W = s * w;
+    const int64_t total = (int64_t)s * h * W;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const int Y = (int)(p / W), X = (int)(p - (int64_t)Y * W);
+        hr[p] = sb_pixel<s, TI>(part, lr, h, w, Y, X);
+    }
+}
+
+// Batched: the tiles and HR pixels of every image of the batch, the image
+// found from its first tile (sbt_off) or HR pixel (hr_off); partial regions
+// at the image's first tile.
+template <int s, int TI>
+__global__ __launch_bounds__(256) void k_b_sb_tile(const BatchImage* __restrict__ im, int n, int K,
+                                                   const int32_t* __restrict__ ids, const int32_t* __restrict__ m,
+                                                   const float* __restrict__ wt, const double* __restrict__ mu,
+                                                   const float* __restrict__ resid, float* __restrict__ part) {
+    const int64_t t = xcd_block();
+    const BatchImage& b = im[batch_image_of<&BatchImage::sbt_off>(im, n, t)];
+    sb_tile<s, TI>(ids + b.q_off * K, m + b.q_off, wt + b.q_off * K, mu + b.q_off, resid, K, b.h, b.w,
+                   t - b.sbt_off, part + b.sbt_off * SbGeom<s, TI>::PART);
+}
+
+template <int s, int TI>
+__global__ __launch_bounds__(256) void k_b_sb_combine(const BatchImage* __restrict__ im, int n, int64_t total,
+                                                      const float* __restrict__ part) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const BatchImage& b = im[batch_image_of<&BatchImage::hr_off>(im, n, p)];
+        const int W = s * b.w;
+        const int64_t lp = p - b.hr_off;
+        const int Y = (int)(lp / W), X = (int)(lp - (int64_t)Y * W);
+        b.out[lp] = sb_pixel<s, TI>(part + b.sbt_off * SbGeom<s, TI>::PART, b.lr, b.h, b.w, Y, X);
+    }
+}
+
+int64_t sb_tiles(int s, int rows, int h, int w) {
+    if (h < kPatch || w < kPatch) return 0;
+    const int64_t npi = h - kPatch + 1, npj = w - kPatch + 1;
+    return ((npi + rows - 1) / rows) * ((npj + sb_cols(s) - 1) / sb_cols(s));
+}
+
+int64_t sb_part_floats(int s, int rows) {
+    const int64_t cy = rows + kPatch - 1, cx = sb_cols(s) + kPatch - 1;
+    return cy * s * cx * s + cy * cx;
+}
+
+template <int s, int TI>
+static hipError_t sb_launch(int K, int h, int w, const int32_t* ids, const int32_t* m, const float* wt,
+                            const double* mu, const float* resid, float* part, const float* lr, float* hr,
+                            hipStream_t st, int which) {
+    const int64_t nt = sb_tiles(s, TI, h, w);
+    if (which & 1 && nt > 0) {
+        if (nt > 0x7FFFFFFF) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_sb_tile<s, TI>), dim3((unsigned)round_grid8((int)nt)), dim3(256), 0, st, K, h, w, ids, m,
+                           wt, mu, resid, part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (which & 2) {
+        const int64_t total = (int64_t)s * h * s * w;
+        if (total > 0)
+            hipLaunchKernelGGL((k_sb_combine<s, TI>), dim3((unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20)),
+                               dim3(256), 0, st, part, lr, h, w, hr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_synth_blend(int scale, int rows, int K, int h, int w, const int32_t* ids, const int32_t* m,
+                              const float* wt, const double* mu, const float* resid, float* part, const float* lr,
+                              float* hr, hipStream_t st, int which) {
+    if (K < 1 || (rows != 4 && rows != 8)) return hipErrorInvalidValue;
+    switch (scale * 10 + rows) {
+        case 14: return sb_launch<1, 4>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        case 18: return sb_launch<1, 8>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        case 24: return sb_launch<2, 4>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        case 28: return sb_launch<2, 8>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        case 34: return sb_launch<3, 4>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        case 38: return sb_launch<3, 8>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        case 44: return sb_launch<4, 4>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        case 48: return sb_launch<4, 8>(K, h, w, ids, m, wt, mu, resid, part, lr, hr, st, which);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int s, int TI>
+static hipError_t b_sb_launch(const BatchImage* im, int n, int64_t tiles, int64_t hr_total, int K, const int32_t* ids,
+                              const int32_t* m, const float* wt, const double* mu, const float* resid, float* part,
+                              hipStream_t st) {
+    if (tiles > 0) {
+        if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_b_sb_tile<s, TI>), dim3((unsigned)round_grid8((int)tiles)), dim3(256), 0, st, im, n, K,
+                           ids, m, wt, mu, resid, part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (hr_total > 0)
+        hipLaunchKernelGGL((k_b_sb_combine<s, TI>), dim3((unsigned)std::min<int64_t>((hr_total + 255) / 256, 1 << 20)),
+                           dim3(256), 0, st, im, n, hr_total, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_synth_blend(const BatchImage* im, int n, int64_t tiles, int64_t hr_total, int scale, int rows,
+                                int K, const int32_t* ids, const int32_t* m, const float* wt, const double* mu,
+                                const float* resid, float* part, hipStream_t st) {
+    if (K < 1 || (rows != 4 && rows != 8)) return hipErrorInvalidValue;
+    switch (scale * 10 + rows) {
+        case 14: return b_sb_launch<1, 4>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        case 18: return b_sb_launch<1, 8>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        case 24: return b_sb_launch<2, 4>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        case 28: return b_sb_launch<2, 8>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        case 34: return b_sb_launch<3, 4>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        case 38: return b_sb_launch<3, 8>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        case 44: return b_sb_launch<4, 4>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        case 48: return b_sb_launch<4, 8>(im, n, tiles, hr_total, K, ids, m, wt, mu, resid, part, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t lle_init() {

@@ -87,11 +87,13 @@ struct zh_ctx {
     bool gram_ready = false;      // gram holds the Gram matrices of the last search's neighbours
     int gram_fp64 = 0;            // ... in FP64 (else fp32)
     double lam = 0.0;             // lambda of the last zh_lle_weights
+    int sb_rows = kSbRows;        // patch rows per tile of the fused synthesis and blend (4 or 8)
     // batched form: plan of the last batch, its captured graph, tuning
     struct BatchGroup {
         int n = 0;
         int64_t q_total = 0, lr_total = 0, hr_total = 0, tiles = 0;
         int64_t fsegs = 0, bsegs = 0;   // feature and blend segments of all images
+        int64_t sbtiles = 0;            // tiles of the fused synthesis and blend of all images
         Buf table;                // device BatchImage[n]
     };
     struct Batch {
@@ -101,14 +103,13 @@ struct zh_ctx {
         hipStream_t stream = nullptr;
         hipEvent_t ev_in = nullptr, ev_out = nullptr;
         int tile = 32, grid_per_cu = 4;
-        int synth_group = 0;          // lanes per patch of the synthesis (0: the launcher's choice)
         Buf scr, e, counter;
     } batch;
     // back-projection record for zh_backward: 0 none, 1 one call kept, -1 more than one
     int bp_rec = 0, bp_iters = 0;
     float bp_sigma_s = 0.f, bp_sigma_r = 0.f;
     int64_t Q = 0;
-    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, xhat, e, tmp, counters, gram, hmask, fixl, fixc, nsurv, guides, bwd, bwd_k, clam;
+    Buf lr, maps, qfeat, qmu, qkeys, qbins, ids, d2, m, ncand, w, over, sbpart, e, tmp, counters, gram, hmask, fixl, fixc, nsurv, guides, bwd, bwd_k, clam;
     Buf qrot;                     // [Q, 64] rotated queries of the screen
     Buf chk;                      // flag of the training-position check
     Buf bwd_gw;                   // [Q, 8] FP64 scratch of the lambda adjoint
@@ -515,7 +516,7 @@ void zh_destroy(zh_ctx* c) {
     release(c, c->batch.e);
     release(c, c->batch.counter);
     Buf* bufs[] = {&c->lr, &c->maps, &c->qfeat, &c->qmu, &c->qkeys, &c->qbins, &c->ids, &c->d2, &c->m,
-                   &c->ncand, &c->w, &c->over, &c->xhat, &c->e, &c->tmp, &c->counters, &c->rs_k1,
+                   &c->ncand, &c->w, &c->over, &c->sbpart, &c->e, &c->tmp, &c->counters, &c->rs_k1,
                    &c->rs_v1, &c->rs_hist, &c->slot_of, &c->idsort, &c->keys_dict, &c->gram, &c->hmask, &c->fixl, &c->fixc, &c->nsurv, &c->guides, &c->bwd, &c->bwd_k, &c->clam, &c->qrot, &c->bwd_gw, &c->bwd_part, &c->tools, &c->l1cand, &c->chk, &c->wall};
     for (Buf* b : bufs) release(c, *b);
     delete c;
@@ -1091,7 +1092,6 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     TRY(ensure(c, c->m, sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->ncand, sizeof(int32_t) * (size_t)Q));
     TRY(ensure(c, c->over, 2 * sizeof(int32_t) * (size_t)Q));
-    TRY(ensure(c, c->xhat, sizeof(float) * (size_t)Q * ps2));
     HIPCHK(c, hipMemcpyAsync(c->lr.p, lr, sizeof(float) * (size_t)h * w, hipMemcpyDeviceToDevice, c->stream));
     c->qh = h;
     c->qw = w;
@@ -1215,20 +1215,24 @@ zh_status zh_reconstruct(zh_ctx* c, float* hr_out) {
     TRY(set_device(c));
     Dict& d = c->dicts[c->qscale];
     const int s = c->qscale, ps2 = (kPatch * s) * (kPatch * s);
+    // every match (zh_lle_all): ncand rows of the dumped lists; else the m
+    // nearest
+    const int32_t* ids = P<int32_t>(c->all_m ? c->l1cand : c->ids);
+    const int32_t* cnt = P<int32_t>(c->all_m ? c->ncand : c->m);
+    const float* wt = P<float>(c->all_m ? c->wall : c->w);
+    const int K = c->all_m ? c->all_cap : c->qK;
+    TRY(ensure(c, c->sbpart,
+               sizeof(float) *
+                   (size_t)std::max<int64_t>(sb_tiles(s, c->sb_rows, c->qh, c->qw) * sb_part_floats(s, c->sb_rows), 1)));
     {
         StageTimer t(c, ZH_T_SYNTH);
-        if (c->all_m)
-            // every match: M = ncand (at most cap) rows of the dumped lists
-            HIPCHK(c, launch_synth((int)c->Q, c->all_cap, ps2, P<int32_t>(c->l1cand), P<int32_t>(c->ncand),
-                                   P<float>(c->wall), P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
-        else
-            HIPCHK(c, launch_synth((int)c->Q, c->qK, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
-                                   P<double>(c->qmu), d.resid, P<float>(c->xhat), c->stream));
+        HIPCHK(c, launch_synth_blend(s, c->sb_rows, K, c->qh, c->qw, ids, cnt, wt, P<double>(c->qmu), d.resid,
+                                     P<float>(c->sbpart), P<float>(c->lr), hr_out, c->stream, 1));
     }
     {
         StageTimer t(c, ZH_T_BLEND);
-        HIPCHK(c, launch_blend(P<float>(c->xhat), P<int32_t>(c->m), P<float>(c->lr), c->qh, c->qw, s, hr_out,
-                               c->stream));
+        HIPCHK(c, launch_synth_blend(s, c->sb_rows, K, c->qh, c->qw, ids, cnt, wt, P<double>(c->qmu), d.resid,
+                                     P<float>(c->sbpart), P<float>(c->lr), hr_out, c->stream, 2));
     }
     c->stage = 3;
     c->bp_rec = 0;
@@ -1548,7 +1552,7 @@ std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
     v.insert(v.end(), {(uint64_t)b->n_images, (uint64_t)b->K, lb, (uint64_t)b->bp_iters, ss, sr,
                        (uint64_t)c->opts.cap, (uint64_t)c->opts.rerank, (uint64_t)c->opts.proj,
                        (uint64_t)c->opts.lle_fp64, (uint64_t)c->batch.tile, (uint64_t)c->batch.grid_per_cu,
-                       (uint64_t)c->batch.synth_group, (uint64_t)(uintptr_t)c->stream, c->gen});
+                       (uint64_t)c->sb_rows, (uint64_t)(uintptr_t)c->stream, c->gen});
     for (int s = 1; s <= kMaxScale; ++s) {
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dir.p);
         v.push_back((uint64_t)(uintptr_t)c->dicts[s].dfilt.p);
@@ -1562,11 +1566,11 @@ std::vector<uint64_t> batch_signature(zh_ctx* c, const zh_batch* b) {
 // Image tables and every buffer the chain needs, sized before any capture.
 zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     auto& B = c->batch;
-    int64_t q_max = 0, lr_max = 0, hr_max = 0, ps2_max = 0, L_max = 0, k_max = 0, D_max = 0;
+    int64_t q_max = 0, lr_max = 0, hr_max = 0, part_max = 0, L_max = 0, k_max = 0, D_max = 0;
     std::vector<BatchImage> tabs[kMaxScale + 1];
     for (int s = 1; s <= kMaxScale; ++s) {
         auto& g = B.g[s];
-        int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, bsegs = 0;
+        int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, bsegs = 0, sbt = 0;
         for (int i = 0; i < b->n_images; ++i) {
             if (b->scale[i] != s) continue;
             BatchImage im{};
@@ -1580,6 +1584,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
             im.tile_off = tiles;
             im.fblk_off = fsegs;
             im.bblk_off = bsegs;
+            im.sbt_off = sbt;
             tabs[s].push_back(im);
             lr += (int64_t)im.h * im.w;
             q += (int64_t)(im.h - 4) * (im.w - 4);
@@ -1587,6 +1592,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
             tiles += bp_tiles(s * im.h, s * im.w, B.tile);
             fsegs += feature_segments(im.h, im.w);
             bsegs += blend_segments(s, im.h, im.w);
+            sbt += sb_tiles(s, c->sb_rows, im.h, im.w);
         }
         g.n = (int)tabs[s].size();
         g.q_total = q;
@@ -1595,13 +1601,14 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
         g.tiles = tiles;
         g.fsegs = fsegs;
         g.bsegs = bsegs;
+        g.sbtiles = sbt;
         if (!g.n) continue;
         if (q * kMaxK >= (1ll << 31)) return fail(c, ZH_EINVAL, "zh_run_batch: too many patches at scale %d", s);
         const Dict& d = c->dicts[s];
         q_max = std::max(q_max, q);
         lr_max = std::max(lr_max, lr);
         hr_max = std::max(hr_max, hr);
-        ps2_max = std::max<int64_t>(ps2_max, (kPatch * s) * (kPatch * s));
+        part_max = std::max<int64_t>(part_max, g.sbtiles * sb_part_floats(s, c->sb_rows));
         L_max = std::max<int64_t>(L_max, d.L);
         k_max = std::max<int64_t>(k_max, d.k);
         D_max = std::max<int64_t>(D_max, d.D);
@@ -1631,7 +1638,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)std::max<int64_t>(q_max, 1)));
     TRY(ensure(c, c->qrot, sizeof(float) * kRotStride * (size_t)std::max<int64_t>(q_max, 1)));
     TRY(ensure(c, c->over, 2 * sizeof(int32_t) * (size_t)q_max));
-    TRY(ensure(c, c->xhat, sizeof(float) * (size_t)q_max * ps2_max));
+    TRY(ensure(c, c->sbpart, sizeof(float) * (size_t)std::max<int64_t>(part_max, 1)));
     TRY(ensure(c, c->counters, kNumCounters * sizeof(uint32_t)));
     if (K <= 8) TRY(ensure(c, c->gram, (c->opts.lle_fp64 ? 8 : 4) * (size_t)q_max * 36));
     HashArgs ha{};
@@ -1657,7 +1664,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
         if (!g.n) continue;
         Dict& d = c->dicts[s];
         const BatchImage* tab = P<BatchImage>(g.table);
-        const int K = b->K, ps2 = (kPatch * s) * (kPatch * s);
+        const int K = b->K;
         rc = [&]() -> zh_status {
             c->Q = g.q_total;
             c->qK = K;
@@ -1710,9 +1717,9 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             } else {
                 HIPCHK(c, launch_lle(la, st));
             }
-            HIPCHK(c, launch_synth((int)g.q_total, K, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
-                                   P<double>(c->qmu), d.resid, P<float>(c->xhat), st, B.synth_group));
-            HIPCHK(c, launch_b_blend(tab, g.n, g.bsegs, s, P<float>(c->xhat), P<int32_t>(c->m), st));
+            HIPCHK(c, launch_b_synth_blend(tab, g.n, g.sbtiles, g.hr_total, s, c->sb_rows, K, P<int32_t>(c->ids),
+                                           P<int32_t>(c->m), P<float>(c->w), P<double>(c->qmu), d.resid,
+                                           P<float>(c->sbpart), st));
             const Taps tg = gauss_taps(1.0);
             for (int t = 0; t < b->bp_iters; ++t) {
                 HIPCHK(c, launch_b_degrade_residual(tab, g.n, g.lr_total, s, tg, t & 1, P<float>(B.e), st));
@@ -1814,7 +1821,7 @@ uint64_t tune_key(zh_ctx* c, const zh_batch* b, std::string& dev, std::string& a
 }
 
 // An earlier choice for `key` in the cache file (one JSON object per line).
-bool tune_lookup(const char* path, uint64_t key, int& tile, int& mult, int& group) {
+bool tune_lookup(const char* path, uint64_t key, int& tile, int& mult, int& rows) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char line[2048];
@@ -1825,14 +1832,14 @@ bool tune_lookup(const char* path, uint64_t key, int& tile, int& mult, int& grou
         if (!std::strstr(line, want)) continue;
         const char* a = std::strstr(line, "\"bp_tile\": ");
         const char* g = std::strstr(line, "\"bp_grid_per_cu\": ");
-        const char* y = std::strstr(line, "\"synth_group\": ");
+        const char* y = std::strstr(line, "\"synth_rows\": ");
         int t = 0, m = 0, sg = 0;
         if (a && g && y && std::sscanf(a + 11, "%d", &t) == 1 && std::sscanf(g + 18, "%d", &m) == 1 &&
-            std::sscanf(y + 15, "%d", &sg) == 1 && (t == 16 || t == 32) && (m == 2 || m == 4 || m == 8) &&
-            (sg == 32 || sg == 64)) {
+            std::sscanf(y + 14, "%d", &sg) == 1 && (t == 16 || t == 32) && (m == 2 || m == 4 || m == 8) &&
+            (sg == 4 || sg == 8)) {
             tile = t;
             mult = m;
-            group = sg;
+            rows = sg;
             found = true;   // the last matching line wins
         }
     }
@@ -1849,9 +1856,9 @@ void tune_store(const char* path, uint64_t key, const std::string& dev, const st
     std::string a;
     for (char ch : arch) a += (ch == '"' || ch == '\\') ? '_' : ch;
     std::fprintf(f, "{\"key\": \"%016llx\", \"device\": \"%s\", \"arch\": \"%s\", \"hip_runtime\": %d, "
-                    "\"bp_tile\": %d, \"bp_grid_per_cu\": %d, \"synth_group\": %d, \"bp_ms\": [%.4f, %.4f, %.4f, "
+                    "\"bp_tile\": %d, \"bp_grid_per_cu\": %d, \"synth_rows\": %d, \"bp_ms\": [%.4f, %.4f, %.4f, "
                     "%.4f, %.4f, %.4f], \"synth_ms\": [%.4f, %.4f]}\n",
-                 (unsigned long long)key, d.c_str(), a.c_str(), rt, t.bp_tile, t.bp_grid_per_cu, t.synth_group,
+                 (unsigned long long)key, d.c_str(), a.c_str(), rt, t.bp_tile, t.bp_grid_per_cu, t.synth_rows,
                  t.bp_ms[0], t.bp_ms[1], t.bp_ms[2], t.bp_ms[3], t.bp_ms[4], t.bp_ms[5], t.synth_ms[0],
                  t.synth_ms[1]);
     std::fclose(f);
@@ -1875,13 +1882,13 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
         if (tune_lookup(cache, key, t, m, g)) {
             B.tile = t;
             B.grid_per_cu = m;
-            B.synth_group = g;
+            c->sb_rows = g;
             B.sig.clear();
             if (out) {
                 std::memset(out, 0, sizeof(*out));
                 out->bp_tile = t;
                 out->bp_grid_per_cu = m;
-                out->synth_group = g;
+                out->synth_rows = g;
                 out->from_cache = 1;
             }
             return zh_run_batch(c, b);
@@ -1897,7 +1904,7 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
     HIPCHK(c, hipEventCreate(&e1));
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1) ncu = 256;
-    const int keep_tile = B.tile, keep_mult = B.grid_per_cu, keep_group = B.synth_group;
+    const int keep_tile = B.tile, keep_mult = B.grid_per_cu, keep_rows = c->sb_rows;
     zh_status rc = ZH_OK;
     auto time_once = [&](auto&& launch, float& best_ms) {
         best_ms = 1e30f;
@@ -1932,42 +1939,48 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
             if (best < 0 || ms[ti * 3 + mi] < ms[best]) best = ti * 3 + mi;
         }
     }
-    // synthesis of the last zoom factor of the batch (its neighbours and
-    // weights are the context's) with 32 and 64 lanes per patch
+    // fused synthesis and blend of the last zoom factor of the batch (its
+    // neighbours and weights are the context's) with tiles of 4 and 8 patch
+    // rows
     float sms[2] = {0.f, 0.f};
-    int sbest = 32;
+    int sbest = kSbRows;
     int last = 0;
     for (int s = 1; s <= kMaxScale; ++s)
         if (B.g[s].n) last = s;
     if (rc == ZH_OK && last > 0) {
-        const auto& g = B.g[last];
-        const int ps2 = (kPatch * last) * (kPatch * last);
         const Dict& d = c->dicts[last];
-        for (int gi = 0; gi < 2 && rc == ZH_OK; ++gi)
+        for (int ri = 0; ri < 2 && rc == ZH_OK; ++ri) {
+            c->sb_rows = ri ? 8 : 4;
+            B.sig.clear();
+            rc = batch_plan(c, b);   // tile offsets of this tile height
+            if (rc != ZH_OK) break;
+            auto& g = B.g[last];
             time_once([&]() {
-                return launch_synth((int)g.q_total, b->K, ps2, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
-                                    P<double>(c->qmu), d.resid, P<float>(c->xhat), B.stream, gi ? 64 : 32) == hipSuccess;
-            }, sms[gi]);
-        sbest = sms[1] < sms[0] ? 64 : 32;
+                return launch_b_synth_blend(P<BatchImage>(g.table), g.n, g.sbtiles, g.hr_total, last, c->sb_rows,
+                                            b->K, P<int32_t>(c->ids), P<int32_t>(c->m), P<float>(c->w),
+                                            P<double>(c->qmu), d.resid, P<float>(c->sbpart), B.stream) == hipSuccess;
+            }, sms[ri]);
+        }
+        sbest = sms[0] < sms[1] ? 4 : 8;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != ZH_OK || best < 0) {
         B.tile = keep_tile;
         B.grid_per_cu = keep_mult;
-        B.synth_group = keep_group;
+        c->sb_rows = keep_rows;
         B.sig.clear();
         return rc != ZH_OK ? rc : fail(c, ZH_EDEVICE, "zh_tune_batch: nothing timed");
     }
     B.tile = tiles[best / 3];
     B.grid_per_cu = mults[best % 3];
-    B.synth_group = sbest;
+    c->sb_rows = sbest;
     B.sig.clear();   // re-plan and capture again with the chosen tuning
     zh_batch_tuning t{};
     t.bp_tile = B.tile;
     t.bp_grid_per_cu = B.grid_per_cu;
     for (int i = 0; i < 6; ++i) t.bp_ms[i] = ms[i];
-    t.synth_group = sbest;
+    t.synth_rows = sbest;
     t.synth_ms[0] = sms[0];
     t.synth_ms[1] = sms[1];
     t.from_cache = 0;

@@ -234,6 +234,18 @@ hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t
                         hipStream_t st, int group = 0);
 hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, int h, int w,
                         int scale, float* hr, hipStream_t st);
+// Synthesis fused with the blend (k_lle.hip): tiles of `rows` (4 or 8) patch
+// rows x sb_cols(s) patch columns; `part` holds sb_part_floats(s, rows)
+// floats for each of the sb_tiles(s, rows, h, w) tiles. which: 1 the tiles,
+// 2 the combine into hr, 3 both. m[q] counts the rows of ids/w used for
+// patch q (0: the patch is left out of the blend).
+__host__ __device__ constexpr int sb_cols(int s) { return s <= 2 ? 40 : 16; }
+constexpr int kSbRows = 8;   // tile height of the single-image call
+int64_t sb_tiles(int s, int rows, int h, int w);
+int64_t sb_part_floats(int s, int rows);
+hipError_t launch_synth_blend(int scale, int rows, int K, int h, int w, const int32_t* ids, const int32_t* m,
+                              const float* wt, const double* mu, const float* resid, float* part, const float* lr,
+                              float* hr, hipStream_t st, int which = 3);
 
 // ---- back-projection (k_bp.hip) ---------------------------------------------
 hipError_t launch_bp_update(const float* I, const float* e, int H, int W, int h, int w,
@@ -254,6 +266,7 @@ struct BatchImage {
     int h, w;
     int64_t lr_off, q_off, hr_off, tile_off;
     int64_t fblk_off, bblk_off;   // first workgroup of the image's feature and blend segments
+    int64_t sbt_off;              // first tile of the image's fused synthesis and blend
 };
 // feature segments (64 patches of a patch row) and blend segments
 // (kBlendSeg HR pixels of a row) of an h x w LR image at zoom s
@@ -281,6 +294,11 @@ hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t seg_tota
                                    float* feat, double* mu, hipStream_t st);
 hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int scale, const Taps& t,
                                      int parity, float* e, hipStream_t st);
+// fused synthesis and blend of every image: `tiles` tiles of `rows` patch
+// rows (offsets sbt_off), then the combine over the hr_total HR pixels
+hipError_t launch_b_synth_blend(const BatchImage* im, int n, int64_t tiles, int64_t hr_total, int scale, int rows,
+                                int K, const int32_t* ids, const int32_t* m, const float* wt, const double* mu,
+                                const float* resid, float* part, hipStream_t st);
 // one workgroup per blend segment (256 HR pixels of a row) of every image
 hipError_t launch_b_blend(const BatchImage* im, int n, int64_t seg_total, int scale, const float* xhat,
                           const int32_t* m, hipStream_t st);

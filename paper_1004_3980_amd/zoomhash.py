@@ -59,7 +59,7 @@ class zh_batch(ctypes.Structure):
 
 class zh_batch_tuning(ctypes.Structure):
     _fields_ = [("bp_tile", ctypes.c_int32), ("bp_grid_per_cu", ctypes.c_int32), ("bp_ms", ctypes.c_float * 6),
-                ("synth_group", ctypes.c_int32), ("synth_ms", ctypes.c_float * 2), ("from_cache", ctypes.c_int32)]
+                ("synth_rows", ctypes.c_int32), ("synth_ms", ctypes.c_float * 2), ("from_cache", ctypes.c_int32)]
 
 
 _V, _I, _I64, _U64, _F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
@@ -294,7 +294,7 @@ class Context:
         t = zh_batch_tuning()
         self._chk(self.lib.zh_tune_batch(self.h, ctypes.byref(b), ctypes.byref(t)))
         return {"bp_tile": t.bp_tile, "bp_grid_per_cu": t.bp_grid_per_cu, "bp_ms": list(t.bp_ms),
-                "synth_group": t.synth_group, "synth_ms": list(t.synth_ms), "from_cache": t.from_cache}
+                "synth_rows": t.synth_rows, "synth_ms": list(t.synth_ms), "from_cache": t.from_cache}
 
     def get_results(self, ids=None, d2=None, m=None, w=None, ncand=None):
         self._chk(self.lib.zh_get_results(self.h, _ptr(ids), _ptr(d2), _ptr(m), _ptr(w), _ptr(ncand)))

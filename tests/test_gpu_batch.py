@@ -2,8 +2,8 @@
 in one captured launch chain. Bar: bit-exact against the same images run one
 by one through zh_query, zh_lle_weights, zh_reconstruct and
 zh_backproject (odd and even iteration counts, a one-patch image, graph
-replays, after autotuning), and an x3 and an x4 image within 1e-5 of the FP64
-oracle.
+replays, after autotuning, whose tile height both forms then use), and an
+x3 and an x4 image within 1e-5 of the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -88,13 +88,15 @@ def test_batch_equals_image_by_image(iters):
 
 
 def test_batch_after_autotuning():
+    """The tuned tile height of the fused synthesis and blend is the
+    context's: images run one by one after the tuning equal the batch."""
     st = _setup()
     torch = st["torch"]
-    ref = _one_by_one(st, 3, 5, 1e-3, 1.5, 0.1)
     got, info = _batch(st, 3, 5, 1e-3, 1.5, 0.1, tune=True)
+    ref = _one_by_one(st, 3, 5, 1e-3, 1.5, 0.1)
     assert info["bp_tile"] in (16, 32) and info["bp_grid_per_cu"] in (2, 4, 8)
     assert all(t > 0 for t in info["bp_ms"])
-    assert info["synth_group"] in (32, 64) and all(t > 0 for t in info["synth_ms"]) and info["from_cache"] == 0
+    assert info["synth_rows"] in (4, 8) and all(t > 0 for t in info["synth_ms"]) and info["from_cache"] == 0
     for r, g in zip(ref, got):
         assert torch.equal(r, g)
 
@@ -110,18 +112,18 @@ def test_tuning_cache(tmp_path, monkeypatch):
     torch = st["torch"]
     path = tmp_path / "tune.jsonl"
     monkeypatch.setenv("ZH_TUNE_CACHE", str(path))
-    ref = _one_by_one(st, 2, 5, 1e-3, 1.5, 0.1)
     got, info = _batch(st, 2, 5, 1e-3, 1.5, 0.1, tune=True)
+    ref = _one_by_one(st, 2, 5, 1e-3, 1.5, 0.1)
     assert info["from_cache"] == 0
     lines = path.read_text().splitlines()
     assert len(lines) == 1
     rec = json.loads(lines[0])
-    assert rec["bp_tile"] == info["bp_tile"] and rec["synth_group"] == info["synth_group"]
+    assert rec["bp_tile"] == info["bp_tile"] and rec["synth_rows"] == info["synth_rows"]
     assert rec["arch"].startswith("gfx9") and rec["hip_runtime"] > 0
     got2, info2 = _batch(st, 2, 5, 1e-3, 1.5, 0.1, tune=True)
     assert info2["from_cache"] == 1 and info2["bp_ms"] == [0.0] * 6
-    assert (info2["bp_tile"], info2["bp_grid_per_cu"], info2["synth_group"]) == \
-        (info["bp_tile"], info["bp_grid_per_cu"], info["synth_group"])
+    assert (info2["bp_tile"], info2["bp_grid_per_cu"], info2["synth_rows"]) == \
+        (info["bp_tile"], info["bp_grid_per_cu"], info["synth_rows"])
     assert len(path.read_text().splitlines()) == 1
     for r, a, b in zip(ref, got, got2):
         assert torch.equal(r, a) and torch.equal(r, b)

@@ -181,6 +181,38 @@ def test_codes_and_keys_when_fix_list_overflows(gpu, fix_cap, monkeypatch):
     assert np.array_equal(_np(keys).view(np.uint64), lsh.bucket_keys(ref, wl.L, wl.k))
 
 
+@pytest.mark.parametrize("L,k,proj", [(7, 24, 1), (5, 28, 1), (3, 1, 1), (9, 13, 1), (7, 24, 0)])
+def test_codes_and_keys_other_table_shapes(gpu, L, k, proj):
+    """Tables of other shapes on the mid dictionary (D = 100): an odd table
+    count (the last staged pair holds one table), k above 24 (one 16-row
+    feature tile per wave instead of two), k = 1, and 1077 rows (a ragged
+    last workgroup and a wave with one live tile). Codes and keys bitwise
+    against the oracle's parameters; the original tables are restored."""
+    torch = _torch()
+    c = case(MID)
+    wl, g = c.wl, c.g
+    ctx = g.ctx
+    alpha, beta = lsh.hash_params(wl.hash_seed, L, k, wl.D, wl.w)
+    feat = c.pre.dictionary.feat[:1077]
+    n = feat.shape[0]
+    try:
+        ctx.build_tables(g.feat, g.resid, g.n, g.D, wl.scale, wl.feat_mode, L, k, wl.w, wl.hash_seed)
+        ctx.set_query_opts(cap=c.cap, proj=proj)
+        a, b = ctx.get_hash_params(wl.scale, L, k, wl.D)
+        assert np.array_equal(a, alpha) and np.array_equal(b, beta)
+        ft = torch.from_numpy(feat).cuda()
+        codes = torch.empty((n, L * k), dtype=torch.int32, device="cuda")
+        keys = torch.empty((n, L), dtype=torch.int64, device="cuda")
+        ctx.hash(wl.scale, ft, n, codes, keys)
+        ctx.sync()
+        ref = lsh.codes(feat, alpha, beta, wl.w)
+        assert np.array_equal(_np(codes), ref)
+        assert np.array_equal(_np(keys).view(np.uint64), lsh.bucket_keys(ref, L, k))
+    finally:
+        ctx.set_query_opts(cap=c.cap, proj=1)
+        ctx.build_tables(g.feat, g.resid, g.n, g.D, wl.scale, wl.feat_mode, wl.L, wl.k, wl.w, wl.hash_seed)
+
+
 def test_codes_boundary_cases_are_fixed(gpu):
     """Rows built so that alpha.v + beta sits within a few ulps of a bin
     edge: the fp32 and split-bf16 projections alone would misplace some of
