@@ -3,13 +3,15 @@
 //
 //   code_j(v) = floor((alpha_j . v + beta_j) / w)
 //
-// One wave owns 16 feature rows and runs over all tables. The dot products of
-// its rows with the k hashes of a table run on the matrix cores, either as
-// fp32 MFMA or as three bf16 MFMAs over a high/low split of both operands
-// (alpha = a_hi + a_lo, v = v_hi + v_lo; a_hi v_hi + a_hi v_lo + a_lo v_hi
-// accumulate in fp32); the split of the wave's rows stays in registers for
-// all tables. A fourth product of the absolute values bounds
-// sum_i |alpha_i v_i|, which gives a rigorous bound B on |P_mfma - P_exact|;
+// A wave owns 16 or 32 feature rows and runs over all tables. The dot
+// products of its rows with the k hashes of a table run on the matrix cores,
+// either as fp32 MFMA (P = (alpha.v + beta) / w evaluated as written) or as
+// three bf16 MFMAs over a high/low split of both operands, with alpha / w
+// and beta / w rounded to fp32 beforehand (a' = alpha / w = a_hi + a_lo,
+// v = v_hi + v_lo; a_hi v_hi + a_hi v_lo + a_lo v_hi accumulate in fp32 and
+// P = S + beta / w); the split of the wave's rows stays in registers for all
+// tables. A fourth product of the absolute values bounds
+// sum_i |a'_i v_i|, which gives a rigorous bound B on |P_mfma - P_exact|;
 // when [P - B, P + B] holds no integer the MFMA floor is the exact code,
 // otherwise the code is recomputed by the FP64 sequential dot product that
 // defines it (in a second kernel, for the few tables that need it). The
@@ -95,9 +97,10 @@ __host__ __device__ inline int fold_tables(int k) { return k <= 24 ? 4 : 2; }
 // fix-list entry: row, table, k codes, padded to 16 bytes
 __host__ __device__ inline int fix_entry_ints(int k) { return (k + 2 + 3) & ~3; }
 // bytes of the staged alpha, then beta and the bound constant of each staged row
+// (split path: the high plane, the low plane, and |high| for the bound's product)
 __host__ __device__ inline int stage_alpha_bytes(int prec, int k, int D) {
     const int R = stage_rows(k);
-    return prec == 0 ? R * stage_stride(0, D) * 4 : 2 * R * stage_stride(1, D) * 2;
+    return prec == 0 ? R * stage_stride(0, D) * 4 : 3 * R * stage_stride(1, D) * 2;
 }
 __host__ __device__ inline int stage_bytes(int prec, int k, int D) {
     return ((stage_alpha_bytes(prec, k, D) + 15) & ~15) + 2 * stage_rows(k) * 4;
@@ -105,9 +108,10 @@ __host__ __device__ inline int stage_bytes(int prec, int k, int D) {
 
 // PREC 0: fp32 MFMA (4 coordinates per step); PREC 1: split bf16 (32 per
 // step, NS steps). The alpha of two tables at a time is staged in LDS with
-// its beta and bound constants and shared by the four waves; on the split
-// path the next pair is fetched into registers while the current one is in
-// use. The 2k hash rows of a pair are packed into ceil(2k/16) MFMA tiles.
+// its beta and bound constants and shared by the four waves (the split path
+// stages alpha / w, beta / w and the absolute values of the high parts);
+// on the split path the next pair is fetched into registers while the
+// current one is in use. The 2k hash rows of a pair are packed into ceil(2k/16) MFMA tiles.
 // A wave owns RT tiles of 16 feature rows: every A fragment read from LDS
 // feeds the products of all RT tiles (RT = 2 halves the LDS reads and the
 // staging per row).
@@ -243,12 +247,17 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
         const int t = threadIdx.x;
         const int r = t < GK ? t : t - GK;
         pbc = 0.0f;
-        if (t < 2 * GK && l0 * k + r < m) pbc = (t < GK ? a.beta : a.bound_c0)[l0 * k + r];
+        if (t < 2 * GK && l0 * k + r < m) pbc = (t < GK ? a.beta_w : a.bound_c0)[l0 * k + r];
     };
     auto stash = [&]() {
 #pragma unroll
         for (int c = 0; c < NPRE; ++c)
-            if (cdesc[c] != 0x7FFFFFFFu) *reinterpret_cast<u16x8*>(sA16 + ((cdesc[c] >> 16) & 0x7FFFu)) = pre[c];
+            if (cdesc[c] != 0x7FFFFFFFu) {
+                const uint32_t off = (cdesc[c] >> 16) & 0x7FFFu;
+                *reinterpret_cast<u16x8*>(sA16 + off) = pre[c];
+                // high plane: its absolute values into the third plane
+                if (!(cdesc[c] >> 31)) *reinterpret_cast<u16x8*>(sA16 + 2 * R * DS + off) = abs8(pre[c]);
+            }
         const int t = threadIdx.x;
         if (t < 2 * GK) (t < GK ? sBeta[t] : sBc0[t - GK]) = pbc;
     };
@@ -269,8 +278,8 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
     // rows GK..R-1 of the stage are never written by the staging: zero them
     if (PREC == 1) {
         const int padrows = R - GK;
-        for (int e = threadIdx.x; e < 2 * padrows * (DS / 8); e += 256) {
-            const int plane = e >= padrows * (DS / 8);
+        for (int e = threadIdx.x; e < 3 * padrows * (DS / 8); e += 256) {
+            const int plane = e / (padrows * (DS / 8));
             const int e2 = e - plane * padrows * (DS / 8);
             const int r = GK + e2 / (DS / 8), ch = e2 % (DS / 8);
             *reinterpret_cast<u16x8*>(sA16 + (plane * R + r) * DS + 8 * ch) = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
@@ -311,6 +320,7 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
                 // bound covers any order of the 3 DP additions
                 const uint16_t* Ah = sA16 + ar * DS + 8 * kb;
                 const uint16_t* Al = Ah + R * DS;
+                const uint16_t* Aa = Al + R * DS;
                 u16x8 ah[NS], al[NS];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -321,7 +331,7 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
                 for (int s = 0; s < NS; ++s) {
                     const bf16x8 ahb = __builtin_bit_cast(bf16x8, ah[s]);
                     const bf16x8 alb = __builtin_bit_cast(bf16x8, al[s]);
-                    const bf16x8 aab8 = __builtin_bit_cast(bf16x8, abs8(ah[s]));
+                    const bf16x8 aab8 = *reinterpret_cast<const bf16x8*>(Aa + 32 * s);
 #pragma unroll
                     for (int rt = 0; rt < RT; ++rt) {
                         const bf16x8 vhb = __builtin_bit_cast(bf16x8, bh[rt][s]);
@@ -360,8 +370,10 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float S = cs[rt][i];
-                    const float P = (S + bev[i]) * a.inv_w;
-                    const float B = fmaf(c1, cab[rt][i], fmaf(c2, fabsf(S), b0v[i]));
+                    // split path: alpha and beta came divided by w
+                    const float P = PREC == 1 ? S + bev[i] : (S + bev[i]) * a.inv_w;
+                    const float B = PREC == 1 ? fmaf(c1, cab[rt][i], b0v[i])
+                                              : fmaf(c1, cab[rt][i], fmaf(c2, fabsf(S), b0v[i]));
                     // uncertain when an integer lies within B of P; every P of
                     // magnitude >= 2^23 is an integer, so each certain code has
                     // |floor(P)| <= 2^23 (a NaN P or B is uncertain as well)
@@ -650,16 +662,21 @@ __global__ __launch_bounds__(256) void k_probe(const uint64_t* __restrict__ keys
     }
 }
 
-// Error bound of the fp32 code value P = fl(fl(S~ + beta) * fl(1/w)) against
-// the exact (S + beta)/w, S = sum_i alpha_i v_i, from the MFMA sums S~ and
-// S_abs (the MFMA value of sum |alpha_i||v_i|, from the bf16 high parts on
-// the split path). With u = 2^-24 and n the fp32 additions of one dot
-// product (counted twice for safety):
-//   split bf16: |S~ - S| <= (gamma_n 1.016 + 3.5 2^-16) sum|alpha_i v_i|,
-//     the dropped low x low and rounding-residual products contributing at
-//     most 3.1 2^-16 relative; sum|alpha_i||v_i| <= S_abs / ((1-2^-8)^2 (1-gamma))
-//   fp32: |S~ - S| <= gamma_n sum|alpha_i v_i|, sum <= S_abs / (1 - gamma)
-//   the add, the reciprocal and the multiply add 3.1 u (|S~| + |beta|) / w.
+// Error bound of the fp32 code value P against the exact (S + beta) / w,
+// S = sum_i alpha_i v_i, from the MFMA sums S~ and S_abs (the MFMA value of
+// sum |a_i||v_i| over the operands' high parts). u = 2^-24, n the fp32
+// additions of one dot product (counted twice for safety).
+//   fp32 path, P = fl(fl(S~ + beta) * fl(1/w)): |S~ - S| <= gamma_n
+//     sum|alpha_i v_i|, sum <= S_abs / (1 - gamma); the add, the reciprocal
+//     and the multiply add 3.1 u (|S~| + |beta|) / w.
+//   split path, P = fl(S~ + beta'), alpha' = fl(alpha / w), beta' =
+//     fl(beta / w): |S~ - sum alpha'_i v_i| <= (gamma_n 1.016 + 3.5 2^-16)
+//     sum|alpha'_i v_i| (the dropped low x low and rounding-residual
+//     products contribute at most 3.1 2^-16), the rounding of alpha / w adds
+//     u (1 + u) of the same sum and that of beta / w u / (1 - u) |beta'|;
+//     the final add u / (1 - u) |P| with |P| <= (1 + u) ((1 + E) sum + |beta'|);
+//     sum|alpha'_i v_i| <= S_abs / ((1 - 2^-8)^2 (1 - gamma)). All of it is
+//     c1 S_abs + c0_j (c2 = 0): one fused multiply-add a code.
 // Every term is doubled, and the FP64 sequential sum of the definition is
 // within ~1e-13 of the exact value, far inside the margin.
 void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, float* c0, float* c1,
@@ -668,19 +685,24 @@ void hash_bound_coeffs(int prec, int D, double w, const float* beta, int m, floa
     const int DP = prec == 0 ? ((D + 3) & ~3) : ((D + 31) & ~31);
     const int nadd = prec == 0 ? 2 * DP : 2 * 3 * DP;
     const double g = gamma_n(nadd, u);
-    double e_rel, c_abs;
-    if (prec == 0) {
-        e_rel = g;
-        c_abs = 1.0 / (1.0 - gamma_n(2 * DP, u));
-    } else {
-        e_rel = g * 1.016 + 3.5 / 65536.0;
-        const double t = 1.0 - 1.0 / 256.0;
-        c_abs = 1.0 / (t * t * (1.0 - gamma_n(2 * DP, u)));
-    }
     const double up = 1.0 + 1e-6;
-    *c1 = (float)(2.0 * e_rel * c_abs / w * up);
-    *c2 = (float)(2.0 * 3.1 * u / w * up);
-    for (int j = 0; j < m; ++j) c0[j] = (float)((2.0 * 3.1 * u * std::fabs((double)beta[j]) / w + 1e-30) * up);
+    if (prec == 0) {
+        const double c_abs = 1.0 / (1.0 - gamma_n(2 * DP, u));
+        *c1 = (float)(2.0 * g * c_abs / w * up);
+        *c2 = (float)(2.0 * 3.1 * u / w * up);
+        for (int j = 0; j < m; ++j) c0[j] = (float)((2.0 * 3.1 * u * std::fabs((double)beta[j]) / w + 1e-30) * up);
+        return;
+    }
+    const double t = 1.0 - 1.0 / 256.0;
+    const double c_abs = 1.0 / (t * t * (1.0 - gamma_n(2 * DP, u)));
+    const double E = g * 1.016 + 3.5 / 65536.0 + u * (1.0 + u);
+    const double e2 = u / (1.0 - u);
+    *c1 = (float)(2.0 * c_abs * (E + e2 * (1.0 + u) * (1.0 + E)) * up);
+    *c2 = 0.0f;
+    for (int j = 0; j < m; ++j) {
+        const double bw = std::fabs((double)(beta[j] / (float)w));
+        c0[j] = (float)((2.0 * (e2 + e2 * (1.0 + u)) * bw + 1e-30) * up);
+    }
 }
 
 // Split path: two 16-row tiles per wave when the fold group of four tables

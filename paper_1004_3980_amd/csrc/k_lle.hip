@@ -507,207 +507,6 @@ hipError_t launch_lle_all(int Q, int D, int cap, double lam, const float* qfeat,
     return hipGetLastError();
 }
 
-// x_q = mu_q + sum_m w_m r_{n_m}: one wave per patch, lane l holds the
-// values l + 64 u, u < U.
-template <int U>
-__global__ __launch_bounds__(256) void k_synth(int Q, int K, int ps2, const int32_t* __restrict__ ids,
-                                               const int32_t* __restrict__ m, const float* __restrict__ w,
-                                               const double* __restrict__ mu, const float* __restrict__ resid,
-                                               float* __restrict__ xhat) {
-    const int lane = threadIdx.x & 63;
-    const int nw = gridDim.x * (blockDim.x >> 6);
-    for (int q = xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6); q < Q; q += nw) {
-        const int mq = m[q];
-        if (mq <= 0) continue;
-        float acc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = 0.0f;
-        for (int r0 = 0; r0 < mq; r0 += 8) {
-            float v[8][U];
-            float wr[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const bool ok = r0 + r < mq;
-                const int64_t b = ok ? (int64_t)ids[(int64_t)q * K + r0 + r] * ps2 : 0;
-                wr[r] = ok ? w[(int64_t)q * K + r0 + r] : 0.0f;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int p = lane + 64 * u;
-                    v[r][u] = (ok && p < ps2) ? resid[b + p] : 0.0f;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-#pragma unroll
-                for (int u = 0; u < U; ++u) acc[u] = fmaf(wr[r], v[r][u], acc[u]);
-        }
-        const float mf = (float)mu[q];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = lane + 64 * u;
-            if (p < ps2) xhat[(int64_t)q * ps2 + p] = mf + acc[u];
-        }
-    }
-}
-
-// Patches of (5s)^2 = 4c values: G lanes per patch (half a wave for c <= 32,
-// a wave for c <= 64 U); lane l of the group holds the 16-byte chunks l + G u
-// (values 4(l + G u) .. +3) and reads each from every neighbour's residual
-// row with one 16-byte load (rows start on 16-byte boundaries); the same fused
-// multiply-adds in the same neighbour order as k_synth.
-template <int G, int U>
-__global__ __launch_bounds__(256) void k_synth4(int Q, int K, int ps2, const int32_t* __restrict__ ids,
-                                                const int32_t* __restrict__ m, const float* __restrict__ w,
-                                                const double* __restrict__ mu, const float* __restrict__ resid,
-                                                float* __restrict__ xhat) {
-    const int hl = threadIdx.x & (G - 1);
-    const int nc = ps2 >> 2;
-    const int nh = gridDim.x * (blockDim.x / G);
-    for (int q = xcd_block() * (blockDim.x / G) + (int)(threadIdx.x / G); q < Q; q += nh) {
-        const int mq = m[q];
-        if (mq <= 0 || hl >= nc) continue;
-        float4 acc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int r0 = 0; r0 < mq; r0 += 8) {
-            float4 v[8][U];
-            float wr[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const bool ok = r0 + r < mq;
-                const int64_t b = ok ? (int64_t)ids[(int64_t)q * K + r0 + r] * ps2 : 0;
-                wr[r] = ok ? w[(int64_t)q * K + r0 + r] : 0.0f;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = hl + G * u;
-                    v[r][u] = ok && c < nc ? *reinterpret_cast<const float4*>(resid + b + 4 * c)
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    acc[u].x = fmaf(wr[r], v[r][u].x, acc[u].x);
-                    acc[u].y = fmaf(wr[r], v[r][u].y, acc[u].y);
-                    acc[u].z = fmaf(wr[r], v[r][u].z, acc[u].z);
-                    acc[u].w = fmaf(wr[r], v[r][u].w, acc[u].w);
-                }
-        }
-        const float mf = (float)mu[q];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = hl + G * u;
-            if (c < nc)
-                *reinterpret_cast<float4*>(xhat + (int64_t)q * ps2 + 4 * c) =
-                    make_float4(mf + acc[u].x, mf + acc[u].y, mf + acc[u].z, mf + acc[u].w);
-        }
-    }
-}
-
-// Per HR pixel: the mean of the synthesised patches covering it (patches in
-// row-major order, each added in fp32), or the bicubic of the LR image where
-// no patch covers it. One workgroup per segment of 256 HR pixels of one HR
-// row Y: for each patch row i covering Y (ascending), the row Y - s i of every
-// patch the segment touches is staged in LDS with coalesced loads (ps
-// consecutive floats per patch), then each pixel adds the staged values of
-// its patches in ascending column order. The zoom factor is a template
-// parameter: every division by s or 5 s is by a constant.
-template <int s>
-__device__ __forceinline__ void blend_seg(const float* __restrict__ xhat, const int32_t* __restrict__ m,
-                                          const float* __restrict__ lr, int h, int w, int Y, int X0,
-                                          float* __restrict__ hr) {
-    __shared__ float sv[1408];   // staged patch rows: at most 1365 floats (s = 3)
-    __shared__ int sm[kBlendSeg + 8];
-    constexpr int ps = kPatch * s, ps2 = ps * ps;
-    // a segment touches at most (kBlendSeg + ps - 2) / s + 2 patch columns
-    static_assert(((kBlendSeg + ps - 2) / s + 2) * ps <= 1408 && (kBlendSeg + ps - 2) / s + 2 <= kBlendSeg + 8,
-                  "staging buffers too small for this zoom factor");
-    const int W = s * w;
-    const int npi = h - kPatch + 1, npj = w - kPatch + 1;
-    const int X = X0 + threadIdx.x;
-    const int X1 = min(W, X0 + kBlendSeg) - 1;
-    // patch columns of the segment
-    const int jb0 = X0 - ps + 1 <= 0 ? 0 : (X0 - ps + s) / s;
-    const int jb1 = min(npj - 1, X1 / s);
-    const int njb = jb1 - jb0 + 1;
-    const int ilo = Y - ps + 1 <= 0 ? 0 : (Y - ps + s) / s;
-    const int ihi = min(npi - 1, Y / s);
-    const int jlo = X - ps + 1 <= 0 ? 0 : (X - ps + s) / s;
-    const int jhi = min(npj - 1, X / s);
-    float acc = 0.0f;
-    int cnt = 0;
-    // the next patch row's values are loaded into registers while the
-    // current one is summed (at most kStg staged values per thread)
-    constexpr int kStg = (1408 + kBlendSeg - 1) / kBlendSeg;
-    constexpr int kSm = (kBlendSeg + 8 + kBlendSeg - 1) / kBlendSeg;   // patch flags per thread
-    float pv[kStg];
-    int pm[kSm];
-    auto fetch = [&](int i) {
-        const int u = Y - s * i;
-        const int64_t qrow = (int64_t)i * npj + jb0;
-#pragma unroll
-        for (int r = 0; r < kSm; ++r) {
-            const int e = (int)threadIdx.x + r * kBlendSeg;
-            pm[r] = e < njb ? m[qrow + e] > 0 : 0;
-        }
-#pragma unroll
-        for (int r = 0; r < kStg; ++r) {
-            const int e = (int)threadIdx.x + r * kBlendSeg;
-            const int jj = e / ps, v = e - jj * ps;
-            pv[r] = e < njb * ps ? xhat[(qrow + jj) * ps2 + u * ps + v] : 0.0f;
-        }
-    };
-    if (ilo <= ihi) fetch(ilo);
-    for (int i = ilo; i <= ihi; ++i) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kSm; ++r) {
-            const int e = (int)threadIdx.x + r * kBlendSeg;
-            if (e < njb) sm[e] = pm[r];
-        }
-#pragma unroll
-        for (int r = 0; r < kStg; ++r) {
-            const int e = (int)threadIdx.x + r * kBlendSeg;
-            if (e < njb * ps) sv[e] = pv[r];
-        }
-        __syncthreads();
-        if (i < ihi) fetch(i + 1);
-        if (X < W) {
-            for (int j = jlo; j <= jhi; ++j) {
-                if (sm[j - jb0]) {
-                    acc += sv[(j - jb0) * ps + (X - s * j)];
-                    ++cnt;
-                }
-            }
-        }
-    }
-    if (X < W) hr[(int64_t)Y * W + X] = cnt > 0 ? acc / (float)cnt : bicubic_at(lr, h, w, s, Y, X);
-}
-
-template <int s>
-__global__ __launch_bounds__(kBlendSeg) void k_blend_rows(const float* __restrict__ xhat, const int32_t* __restrict__ m,
-                                                          const float* __restrict__ lr, int h, int w,
-                                                          float* __restrict__ hr) {
-    const int nseg = (s * w + kBlendSeg - 1) / kBlendSeg;
-    const int Y = blockIdx.x / nseg;
-    blend_seg<s>(xhat, m, lr, h, w, Y, (blockIdx.x - Y * nseg) * kBlendSeg, hr);
-}
-
-// Batched: one workgroup per segment of every image (the image from the
-// table's segment offsets), the single-image code on the image's patches.
-template <int s>
-__global__ __launch_bounds__(kBlendSeg) void k_b_blend(const BatchImage* __restrict__ im, int n,
-                                                       const float* __restrict__ xhat, const int32_t* __restrict__ m) {
-    constexpr int ps2 = (kPatch * s) * (kPatch * s);
-    const BatchImage& b = im[batch_image_of<&BatchImage::bblk_off>(im, n, blockIdx.x)];
-    const int64_t lb = blockIdx.x - b.bblk_off;
-    const int nseg = (s * b.w + kBlendSeg - 1) / kBlendSeg;
-    const int Y = (int)(lb / nseg);
-    blend_seg<s>(xhat + b.q_off * ps2, m + b.q_off, b.lr, b.h, b.w, Y, (int)(lb - (int64_t)Y * nseg) * kBlendSeg,
-                 b.out);
-}
-
 // ---- synthesis fused with the blend -------------------------------------------
 // The synthesised patches are never written out. The patch origins are cut
 // into tiles of TI patch rows x sb_cols(s) patch columns; a workgroup takes a
@@ -1016,67 +815,6 @@ hipError_t launch_lle(const LleArgs& a, hipStream_t st) {
         const int grid = (a.Q + 15) / 16;
         if (a.fp64) hipLaunchKernelGGL((k_lle<double, 16, 16>), dim3(grid), dim3(64), 0, st, a);
         else hipLaunchKernelGGL((k_lle<float, 16, 16>), dim3(grid), dim3(64), 0, st, a);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m, const float* w,
-                        const double* mu, const float* resid, float* xhat, hipStream_t st, int group) {
-    if (Q == 0) return hipSuccess;
-    if (ps2 < 1 || ps2 > kMaxPs2) return hipErrorInvalidValue;
-    const bool vec = (ps2 & 3) == 0 && (reinterpret_cast<uintptr_t>(resid) & 15) == 0 &&
-                     (reinterpret_cast<uintptr_t>(xhat) & 15) == 0;
-    if (vec && ps2 <= 128 && group != 64) {
-        // half a wave per patch
-        const int grid = round_grid8((int)std::min<int64_t>(((int64_t)Q + 7) / 8, 65536));
-        hipLaunchKernelGGL((k_synth4<32, 1>), dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
-        return hipGetLastError();
-    }
-    const int grid = round_grid8((int)std::min<int64_t>(((int64_t)Q + 3) / 4, 65536));
-    if (vec) {
-        // a wave per patch, 16-byte chunks
-        if (ps2 <= 256)
-            hipLaunchKernelGGL((k_synth4<64, 1>), dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
-        else
-            hipLaunchKernelGGL((k_synth4<64, 2>), dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
-        return hipGetLastError();
-    }
-    if (ps2 <= 64)
-        hipLaunchKernelGGL(k_synth<1>, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
-    else if (ps2 <= 256)
-        hipLaunchKernelGGL(k_synth<4>, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid, xhat);
-    else
-        hipLaunchKernelGGL(k_synth<(kMaxPs2 + 63) / 64>, dim3(grid), dim3(256), 0, st, Q, K, ps2, ids, m, w, mu, resid,
-                           xhat);
-    return hipGetLastError();
-}
-
-hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, int h, int w, int scale,
-                        float* hr, hipStream_t st) {
-    const int64_t H = (int64_t)scale * h, W = (int64_t)scale * w;
-    if (H == 0 || W == 0) return hipSuccess;
-    const int64_t g = H * ((W + kBlendSeg - 1) / kBlendSeg);
-    if (g > 0x7FFFFFFF || scale < 1 || scale > kMaxScale) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)g), blk(kBlendSeg);
-    switch (scale) {
-        case 1: hipLaunchKernelGGL(k_blend_rows<1>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
-        case 2: hipLaunchKernelGGL(k_blend_rows<2>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
-        case 3: hipLaunchKernelGGL(k_blend_rows<3>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
-        default: hipLaunchKernelGGL(k_blend_rows<4>, grid, blk, 0, st, xhat, m, lr, h, w, hr); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_b_blend(const BatchImage* im, int n, int64_t seg_total, int scale, const float* xhat,
-                          const int32_t* m, hipStream_t st) {
-    if (seg_total == 0) return hipSuccess;
-    if (seg_total > 0x7FFFFFFF || scale < 1 || scale > kMaxScale) return hipErrorInvalidValue;
-    const dim3 g((unsigned)seg_total), blk(kBlendSeg);
-    switch (scale) {
-        case 1: hipLaunchKernelGGL(k_b_blend<1>, g, blk, 0, st, im, n, xhat, m); break;
-        case 2: hipLaunchKernelGGL(k_b_blend<2>, g, blk, 0, st, im, n, xhat, m); break;
-        case 3: hipLaunchKernelGGL(k_b_blend<3>, g, blk, 0, st, im, n, xhat, m); break;
-        default: hipLaunchKernelGGL(k_b_blend<4>, g, blk, 0, st, im, n, xhat, m); break;
     }
     return hipGetLastError();
 }

@@ -648,8 +648,8 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
     uint32_t* cdist = cids + a.cp;
     float2* stl = reinterpret_cast<float2*>(hset);
     __shared__ __align__(16) float sq[128];
-    __shared__ uint32_t sstart[kMaxL + 1];
-    __shared__ uint32_t soff[kMaxL];
+    __shared__ int64_t sbase[kMaxL];       // per table: bin offset in tids minus the bin's first position
+    __shared__ int32_t smark[64];          // table whose bin starts at a position of the current chunk, or -1
     __shared__ uint64_t srank[16];
     const int lane = threadIdx.x;
     const int L = a.L, D = a.D;
@@ -668,12 +668,10 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
             cnt = b.y;
         }
         const int T = wave_sum_i32((int)cnt);
-        const int incl = wave_incl_scan((int)cnt);
-        if (lane < L) {
-            sstart[lane] = (uint32_t)(incl - (int)cnt);
-            soff[lane] = off;
-        }
-        if (lane == 0) sstart[L] = (uint32_t)T;
+        // bins concatenated in table order: position i of bin l is entry
+        // i - start_l of that bin
+        const int start = wave_incl_scan((int)cnt) - (int)cnt;
+        if (lane < L) sbase[lane] = (int64_t)lane * a.N + off - start;
         for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
         for (int i = lane; i < 128; i += 64) sq[i] = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
         // the coded query y^ = s_q (h + l / 128): int8 codes h and l, then
@@ -684,18 +682,24 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
 
         // ---- 1. candidates, first occurrences in order, up to cap
         int M = 0;
+        int carry = 0;   // table of the position before the chunk
         for (int base = 0; base < T && M < a.cap; base += 64) {
             const int i = base + lane;
             const bool valid = i < T;
+            // the table of each position: the last nonempty bin starting at
+            // or before it (the bins starting inside the chunk mark their
+            // first position)
+            smark[lane] = -1;
+            __syncthreads();
+            const int ps = start - base;
+            if (lane < L && cnt > 0 && ps >= 0 && ps < 64) smark[ps] = lane;
+            __syncthreads();
+            const uint64_t starts = __ballot(smark[lane] >= 0);
+            const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+            const int tbl = below ? smark[63 - __builtin_clzll(below)] : carry;
+            carry = __builtin_amdgcn_readlane(tbl, 63);
             uint32_t id = 0xFFFFFFFFu;
-            if (valid) {
-                int lo = 0, hi = L;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sstart[mid] <= (uint32_t)i) lo = mid; else hi = mid;
-                }
-                id = a.tids[(int64_t)lo * a.N + soff[lo] + (i - sstart[lo])];
-            }
+            if (valid) id = a.tids[sbase[tbl] + i];
             uint32_t slot = (id * 0x9E3779B1u) >> hshift;
             bool found = false;
             if (valid) {

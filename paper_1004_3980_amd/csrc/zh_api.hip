@@ -41,7 +41,8 @@ struct Dict {
     uint64_t cap = 0;             // directory slots per table
     const float* resid = nullptr; // borrowed
     Buf hi, lo;                   // [n, hi_stride(D)] and [n, D] split planes (64 bytes of slack at the end)
-    Buf alpha, beta, bc0[2], ahi, alo;
+    Buf alpha, beta, bc0[2], ahi, alo;   // ahi, alo: bf16 split of fl(alpha / w)
+    Buf bw;                       // [L k] fl(beta / w)
     float bc1[2] = {0.f, 0.f}, bc2[2] = {0.f, 0.f};
     Buf dir;                      // [L, cap] Slot
     Buf dfilt;                    // [L, dir_filter_words(cap)] presence bits of the keys
@@ -92,7 +93,7 @@ struct zh_ctx {
     struct BatchGroup {
         int n = 0;
         int64_t q_total = 0, lr_total = 0, hr_total = 0, tiles = 0;
-        int64_t fsegs = 0, bsegs = 0;   // feature and blend segments of all images
+        int64_t fsegs = 0;              // feature segments of all images
         int64_t sbtiles = 0;            // tiles of the fused synthesis and blend of all images
         Buf table;                // device BatchImage[n]
     };
@@ -271,11 +272,22 @@ Taps gauss_taps(double sigma) {
     return t;
 }
 
+// fl(beta / w) of the host copy of beta, to the device (synchronous)
+zh_status upload_beta_w(zh_ctx* c, Dict& d) {
+    std::vector<float> bw(d.h_beta.size());
+    for (size_t j = 0; j < bw.size(); ++j) bw[j] = d.h_beta[j] / d.w;
+    TRY(ensure(c, d.bw, sizeof(float) * std::max<size_t>(bw.size(), 1)));
+    HIPCHK(c, hipMemcpyAsync(d.bw.p, bw.data(), sizeof(float) * bw.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ZH_OK;
+}
+
 void set_bounds(HashArgs& ha, Dict& d, int prec) {
     ha.bound_c0 = P<float>(d.bc0[prec]);
     ha.bound_c1 = d.bc1[prec];
     ha.bound_c2 = d.bc2[prec];
     ha.inv_w = 1.0f / d.w;
+    ha.beta_w = P<float>(d.bw);
 }
 
 zh_status set_device(zh_ctx* c) {
@@ -499,7 +511,7 @@ void zh_destroy(zh_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (Dict& d : c->dicts) {
         release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.bc0[0]); release(c, d.bc0[1]);
-        release(c, d.ahi); release(c, d.alo); release(c, d.dir); release(c, d.dfilt); release(c, d.tids);
+        release(c, d.ahi); release(c, d.alo); release(c, d.bw); release(c, d.dir); release(c, d.dfilt); release(c, d.tids);
         release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo); release(c, d.kmul); release(c, d.xf);
     }
     for (int st = 0; st < ZH_T_COUNT; ++st)
@@ -660,7 +672,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     std::vector<uint16_t> ahi((size_t)m * DP, 0), alo((size_t)m * DP, 0);
     for (int j = 0; j < m; ++j) {
         for (int i = 0; i < D; ++i) {
-            const float a = d.h_alpha[(size_t)j * D + i];
+            const float a = d.h_alpha[(size_t)j * D + i] / w;
             const uint16_t h = bf16_rne_host(a);
             ahi[(size_t)j * DP + i] = h;
             alo[(size_t)j * DP + i] = bf16_rne_host(a - bf16_f_host(h));
@@ -687,6 +699,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     TRY(ensure(c, d.alo, sizeof(uint16_t) * (size_t)m * DP));
     HIPCHK(c, hipMemcpyAsync(d.alpha.p, d.h_alpha.data(), sizeof(float) * (size_t)m * D, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(d.beta.p, d.h_beta.data(), sizeof(float) * (size_t)m, hipMemcpyHostToDevice, c->stream));
+    TRY(upload_beta_w(c, d));
     for (int pr = 0; pr < 2; ++pr)
         HIPCHK(c, hipMemcpyAsync(d.bc0[pr].p, bc0[pr].data(), sizeof(float) * (size_t)m, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -755,7 +768,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
 namespace {
 
 constexpr int kTabSections = 13;
-constexpr uint32_t kTabVersion = 1;
+constexpr uint32_t kTabVersion = 2;
 constexpr size_t kTabStage = (size_t)32 << 20;   // pinned staging buffer of the file I/O
 
 // File header: everything zh_build_tables decided, the size and content hash
@@ -956,6 +969,7 @@ zh_status zh_load_tables(zh_ctx* c, const zh_dictionary* dict, const char* path)
     HIPCHK(c, hipMemcpyAsync(d.h_alpha.data(), d.alpha.p, sizeof(float) * m * d.D, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(d.h_beta.data(), d.beta.p, sizeof(float) * m, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    TRY(upload_beta_w(c, d));
     d.valid = true;
     return ZH_OK;
 }
@@ -1570,7 +1584,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     std::vector<BatchImage> tabs[kMaxScale + 1];
     for (int s = 1; s <= kMaxScale; ++s) {
         auto& g = B.g[s];
-        int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, bsegs = 0, sbt = 0;
+        int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, sbt = 0;
         for (int i = 0; i < b->n_images; ++i) {
             if (b->scale[i] != s) continue;
             BatchImage im{};
@@ -1583,7 +1597,6 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
             im.hr_off = hr;
             im.tile_off = tiles;
             im.fblk_off = fsegs;
-            im.bblk_off = bsegs;
             im.sbt_off = sbt;
             tabs[s].push_back(im);
             lr += (int64_t)im.h * im.w;
@@ -1591,7 +1604,6 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
             hr += (int64_t)s * im.h * s * im.w;
             tiles += bp_tiles(s * im.h, s * im.w, B.tile);
             fsegs += feature_segments(im.h, im.w);
-            bsegs += blend_segments(s, im.h, im.w);
             sbt += sb_tiles(s, c->sb_rows, im.h, im.w);
         }
         g.n = (int)tabs[s].size();
@@ -1600,7 +1612,6 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
         g.hr_total = hr;
         g.tiles = tiles;
         g.fsegs = fsegs;
-        g.bsegs = bsegs;
         g.sbtiles = sbt;
         if (!g.n) continue;
         if (q * kMaxK >= (1ll << 31)) return fail(c, ZH_EINVAL, "zh_run_batch: too many patches at scale %d", s);

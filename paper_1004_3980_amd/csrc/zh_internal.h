@@ -61,12 +61,13 @@ struct HashArgs {
     int D;
     int L, k;
     const float* alpha;      // [L*k, D] fp32
-    const uint16_t* a_hi;    // [L*k, DP] bf16 high parts (split projection), DP = D rounded to 32
+    const uint16_t* a_hi;    // [L*k, DP] bf16 high parts of fl(alpha / w) (split projection), DP = D rounded to 32
     const uint16_t* a_lo;    // [L*k, DP] bf16 low parts
     const float* beta;       // [L*k]
+    const float* beta_w;     // [L*k] fl(beta / w) (split path; its a_hi, a_lo split fl(alpha / w))
     const float* bound_c0;   // [L*k] per-hash constant term of the code error bound
     float bound_c1;          // coefficient of the |alpha|.|v| MFMA value in the bound
-    float bound_c2;          // coefficient of |alpha.v|
+    float bound_c2;          // coefficient of |alpha.v| (fp32 path)
     float inv_w;             // fp32 1/w
     float w;
     int prec;                // 0 = fp32 MFMA, 1 = split bf16 MFMA
@@ -228,12 +229,6 @@ hipError_t launch_cand_t(int Q, int L, int64_t N, int t, const uint2* bins, cons
 int64_t entropy_scratch_bytes(int L, uint64_t cap);
 hipError_t launch_table_entropy(const Slot* dir, int L, uint64_t cap, int64_t n, void* scratch, double* out,
                                 hipStream_t st);
-// group: lanes per patch of the 16-byte path (0: 32 when (5s)^2 <= 128, else 64; 64: a wave)
-hipError_t launch_synth(int Q, int K, int ps2, const int32_t* ids, const int32_t* m,
-                        const float* w, const double* mu, const float* resid, float* xhat,
-                        hipStream_t st, int group = 0);
-hipError_t launch_blend(const float* xhat, const int32_t* m, const float* lr, int h, int w,
-                        int scale, float* hr, hipStream_t st);
 // Synthesis fused with the blend (k_lle.hip): tiles of `rows` (4 or 8) patch
 // rows x sb_cols(s) patch columns; `part` holds sb_part_floats(s, rows)
 // floats for each of the sb_tiles(s, rows, h, w) tiles. which: 1 the tiles,
@@ -265,18 +260,13 @@ struct BatchImage {
     float* scr;              // [s h, s w] back-projection scratch
     int h, w;
     int64_t lr_off, q_off, hr_off, tile_off;
-    int64_t fblk_off, bblk_off;   // first workgroup of the image's feature and blend segments
+    int64_t fblk_off;             // first workgroup of the image's feature segments
     int64_t sbt_off;              // first tile of the image's fused synthesis and blend
 };
-// feature segments (64 patches of a patch row) and blend segments
-// (kBlendSeg HR pixels of a row) of an h x w LR image at zoom s
+// feature segments (64 patches of a patch row) of an h x w LR image
 constexpr int kFeatSeg = 64;
-constexpr int kBlendSeg = 256;
 __host__ __device__ inline int64_t feature_segments(int h, int w) {
     return h >= kPatch && w >= kPatch ? (int64_t)(h - kPatch + 1) * ((w - kPatch + 1 + kFeatSeg - 1) / kFeatSeg) : 0;
-}
-__host__ __device__ inline int64_t blend_segments(int s, int h, int w) {
-    return (int64_t)s * h * ((s * w + kBlendSeg - 1) / kBlendSeg);
 }
 // image of a concatenated index: the last entry whose offset field is <= i
 template <int64_t BatchImage::*F>
@@ -299,9 +289,6 @@ hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_tot
 hipError_t launch_b_synth_blend(const BatchImage* im, int n, int64_t tiles, int64_t hr_total, int scale, int rows,
                                 int K, const int32_t* ids, const int32_t* m, const float* wt, const double* mu,
                                 const float* resid, float* part, hipStream_t st);
-// one workgroup per blend segment (256 HR pixels of a row) of every image
-hipError_t launch_b_blend(const BatchImage* im, int n, int64_t seg_total, int scale, const float* xhat,
-                          const int32_t* m, hipStream_t st);
 // one back-projection update over all tiles of the batch, persistent: `grid`
 // workgroups take tiles from the counter (zeroed here by a fill kernel);
 // parity 0 reads out and writes scr, parity 1 the reverse
