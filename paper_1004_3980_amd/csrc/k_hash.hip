@@ -97,10 +97,10 @@ __host__ __device__ inline int fold_tables(int k) { return k <= 24 ? 4 : 2; }
 // fix-list entry: row, table, k codes, padded to 16 bytes
 __host__ __device__ inline int fix_entry_ints(int k) { return (k + 2 + 3) & ~3; }
 // bytes of the staged alpha, then beta and the bound constant of each staged row
-// (split path: the high plane, the low plane, and |high| for the bound's product)
+// (split path: the high plane, then the low plane)
 __host__ __device__ inline int stage_alpha_bytes(int prec, int k, int D) {
     const int R = stage_rows(k);
-    return prec == 0 ? R * stage_stride(0, D) * 4 : 3 * R * stage_stride(1, D) * 2;
+    return prec == 0 ? R * stage_stride(0, D) * 4 : 2 * R * stage_stride(1, D) * 2;
 }
 __host__ __device__ inline int stage_bytes(int prec, int k, int D) {
     return ((stage_alpha_bytes(prec, k, D) + 15) & ~15) + 2 * stage_rows(k) * 4;
@@ -109,7 +109,7 @@ __host__ __device__ inline int stage_bytes(int prec, int k, int D) {
 // PREC 0: fp32 MFMA (4 coordinates per step); PREC 1: split bf16 (32 per
 // step, NS steps). The alpha of two tables at a time is staged in LDS with
 // its beta and bound constants and shared by the four waves (the split path
-// stages alpha / w, beta / w and the absolute values of the high parts);
+// stages alpha / w and beta / w);
 // on the split path the next pair is fetched into registers while the
 // current one is in use. The 2k hash rows of a pair are packed into ceil(2k/16) MFMA tiles.
 // A wave owns RT tiles of 16 feature rows: every A fragment read from LDS
@@ -252,12 +252,7 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
     auto stash = [&]() {
 #pragma unroll
         for (int c = 0; c < NPRE; ++c)
-            if (cdesc[c] != 0x7FFFFFFFu) {
-                const uint32_t off = (cdesc[c] >> 16) & 0x7FFFu;
-                *reinterpret_cast<u16x8*>(sA16 + off) = pre[c];
-                // high plane: its absolute values into the third plane
-                if (!(cdesc[c] >> 31)) *reinterpret_cast<u16x8*>(sA16 + 2 * R * DS + off) = abs8(pre[c]);
-            }
+            if (cdesc[c] != 0x7FFFFFFFu) *reinterpret_cast<u16x8*>(sA16 + ((cdesc[c] >> 16) & 0x7FFFu)) = pre[c];
         const int t = threadIdx.x;
         if (t < 2 * GK) (t < GK ? sBeta[t] : sBc0[t - GK]) = pbc;
     };
@@ -278,7 +273,7 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
     // rows GK..R-1 of the stage are never written by the staging: zero them
     if (PREC == 1) {
         const int padrows = R - GK;
-        for (int e = threadIdx.x; e < 3 * padrows * (DS / 8); e += 256) {
+        for (int e = threadIdx.x; e < 2 * padrows * (DS / 8); e += 256) {
             const int plane = e / (padrows * (DS / 8));
             const int e2 = e - plane * padrows * (DS / 8);
             const int r = GK + e2 / (DS / 8), ch = e2 % (DS / 8);
@@ -320,7 +315,6 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
                 // bound covers any order of the 3 DP additions
                 const uint16_t* Ah = sA16 + ar * DS + 8 * kb;
                 const uint16_t* Al = Ah + R * DS;
-                const uint16_t* Aa = Al + R * DS;
                 u16x8 ah[NS], al[NS];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -331,7 +325,7 @@ __global__ __launch_bounds__(256, RT == 1 ? 3 : 2) void k_hash(HashArgs a) {
                 for (int s = 0; s < NS; ++s) {
                     const bf16x8 ahb = __builtin_bit_cast(bf16x8, ah[s]);
                     const bf16x8 alb = __builtin_bit_cast(bf16x8, al[s]);
-                    const bf16x8 aab8 = *reinterpret_cast<const bf16x8*>(Aa + 32 * s);
+                    const bf16x8 aab8 = __builtin_bit_cast(bf16x8, abs8(ah[s]));
 #pragma unroll
                     for (int rt = 0; rt < RT; ++rt) {
                         const bf16x8 vhb = __builtin_bit_cast(bf16x8, bh[rt][s]);

@@ -184,10 +184,13 @@ __device__ uint64_t select_topk(const uint32_t* cids, const uint32_t* cdist, int
 // the r-th smallest key. Up to 16 candidates: each lane counts the keys below
 // its own (the keys are distinct: they carry the ID) and places its key at
 // that rank in `rk` (16 slots of LDS).
+// slot (optional): on the ranking path, lane r < M also receives the
+// candidate index (into cids) of its key; elsewhere -1.
 template <int NSL = 4>
 __device__ __forceinline__ uint64_t sort_select(const uint32_t* cids, const uint32_t* cdist, int M,
-                                                uint64_t* rk = nullptr) {
+                                                uint64_t* rk = nullptr, int* slot = nullptr) {
     const int lane = threadIdx.x;
+    if (slot) *slot = -1;
     if (rk && M <= 16) {
         const uint64_t mine = lane < M ? cand_key(cdist[lane], cids[lane]) : ~0ull;
         const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
@@ -196,9 +199,15 @@ __device__ __forceinline__ uint64_t sort_select(const uint32_t* cids, const uint
             const uint32_t lo = __builtin_amdgcn_readlane(mlo, c), hi = __builtin_amdgcn_readlane(mhi, c);
             rank += ((((uint64_t)hi << 32) | lo) < mine) ? 1 : 0;
         }
-        if (lane < M) rk[rank] = mine;
+        // rk[0..16): the keys by rank; the candidate index of each in the
+        // upper half of its slot's neighbour (rk + 16)
+        if (lane < M) {
+            rk[rank] = mine;
+            if (slot) reinterpret_cast<int*>(rk + 16)[rank] = lane;
+        }
         __syncthreads();
         const uint64_t out = lane < M ? rk[lane] : ~0ull;
+        if (slot && lane < M) *slot = reinterpret_cast<const int*>(rk + 16)[lane];
         __syncthreads();
         return out;
     }
@@ -550,11 +559,17 @@ __device__ __forceinline__ void exact_rows(const SearchArgs& a, const float* sq,
 // taken from it; otherwise the rows of the neighbours are read again.
 template <typename GT>
 __device__ void write_gram(const SearchArgs& a, int q, const float* sq, uint32_t* cids, uint32_t* cdist, int nA,
-                           int Kp, uint32_t oid, GT* sG) {
+                           int Kp, uint32_t oid, GT* sG, int slot) {
     const int lane = threadIdx.x;
+    // index of the neighbour among the first pass's rows: the ranking's
+    // candidate index when known, else a search of cids[0..nA)
     int pi = -1;
-    for (int s = 0; s < nA; ++s)
-        if (cids[s] == oid) pi = s;
+    if (__ballot(lane < Kp && slot < 0) == 0) {
+        pi = slot < nA ? slot : -1;
+    } else {
+        for (int s = 0; s < nA; ++s)
+            if (cids[s] == oid) pi = s;
+    }
     const bool all = __ballot(lane < Kp && pi < 0) == 0;
     if (!all) {
         // rare: a neighbour outside the first pass; its rows in final order
@@ -650,7 +665,7 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
     __shared__ __align__(16) float sq[128];
     __shared__ int64_t sbase[kMaxL];       // per table: bin offset in tids minus the bin's first position
     __shared__ int32_t smark[64];          // table whose bin starts at a position of the current chunk, or -1
-    __shared__ uint64_t srank[16];
+    __shared__ uint64_t srank[24];        // ranked keys, then their candidate indices
     const int lane = threadIdx.x;
     const int L = a.L, D = a.D;
     const int hsz = a.hsz;
@@ -880,17 +895,21 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
 
         // ---- 4. K best, certification, output
         const int Kp = min(a.K, Mr);
-        const uint64_t mykey = sort_select<NSL>(cids, cdist, Mr, srank);
+        int slot = -1;
+        const uint64_t mykey = sort_select<NSL>(cids, cdist, Mr, srank, &slot);
         uint32_t oid = 0xFFFFFFFFu;
         float od = 0.0f;
         if (EXACT && Kp > 0) {
+            // the certification may re-rank: the slots no longer apply
             certify_or_fix(a, q, cids, cdist, Mr, Kp, mykey, oid, od);
+            slot = -1;
         } else if (lane < Kp) {
             oid = key_id(mykey);
             od = key_dist(mykey);
         }
         write_result(a, q, Kp, oid, od);
-        if constexpr (!std::is_same<GT, int>::value) write_gram<GT>(a, q, sq, cids, cdist, nA, Kp, oid, reinterpret_cast<GT*>(hset));
+        if constexpr (!std::is_same<GT, int>::value)
+            write_gram<GT>(a, q, sq, cids, cdist, nA, Kp, oid, reinterpret_cast<GT*>(hset), slot);
         __syncthreads();
     }
 }
