@@ -156,6 +156,20 @@ def oracle_child(args):
     lr_c = np.ascontiguousarray(lr[:crop, :crop])
     rec, qr, hr_c = _oracle_sample(f"{wl.name} crop", wl, lr_c, cores, log)
     out["samples"][f"{wl.name}_crop{crop}"] = rec
+    # Section 4.3's approximation of the cross bilateral filter, on the
+    # crop's oracle result: the back-projection with each filter
+    from oracle import backproject as obp
+    t0 = time.perf_counter()
+    hr_a = obp.backproject(hr_c, lr_c, wl.scale, wl.bp_iters, wl.blur_sigma, wl.sigma_s, wl.sigma_r)
+    hr_e = obp.backproject_exact(hr_c, lr_c, wl.scale, wl.bp_iters, wl.blur_sigma, wl.sigma_s, wl.sigma_r)
+    bil = {"crop": crop, "iters": wl.bp_iters, "sigma_s": wl.sigma_s, "sigma_r": wl.sigma_r,
+           "max_abs_approximate_vs_exact": float(np.abs(hr_a - hr_e).max()),
+           "psnr_approximate_vs_exact_db": psnr(hr_a, hr_e), "seconds": round(time.perf_counter() - t0, 2)}
+    if not wl.test_lr_direct:
+        gt = np.asarray(img, np.float64)[: wl.scale * crop, : wl.scale * crop]
+        bil["psnr_gt_db"] = {"before": psnr(hr_c, gt), "approximate": psnr(hr_a, gt), "exact": psnr(hr_e, gt)}
+    out["bilateral_approximation"] = bil
+    log(f"[oracle] cross bilateral approximation on the crop: {json.dumps(bil)}")
     np.savez(args.oracle_out, ids=qr.ids, m=qr.m, hr=hr_c)
     print(json.dumps(out), flush=True)
 
@@ -194,6 +208,7 @@ def finish_oracle_child(proc, path, wl, crop):
            "one_thread_value": s["one_thread_patches_per_s"],
            "os_cpu_count": rec["os_cpu_count"], "affinity": rec["affinity"],
            "samples": rec["samples"]}
+    cpu["bilateral_approximation"] = rec.get("bilateral_approximation")
     return cpu, z["ids"], z["m"], z["hr"]
 
 
@@ -375,6 +390,7 @@ def main():
             for form in ("screened", "exact"):
                 quality[form]["psnr_loss_db"] = p_or - quality[form]["psnr_gt_db"]
         extra["quality_crop"] = quality
+        extra["bilateral_approximation"] = cpu.pop("bilateral_approximation", None)
         set_form(args.form)
         if quality["screened"]["truncated"] or quality["exact"]["truncated"]:
             raise SystemExit("screened form cut the exact rows of some patch of the crop (truncated > 0)")

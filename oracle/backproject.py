@@ -112,3 +112,17 @@ def exact_cross_bilateral(E: np.ndarray, I: np.ndarray, sigma_s: float,
             num[y0:y1, x0:x1] += wgt * E[y0 + dy:y1 + dy, x0 + dx:x1 + dx]
             den[y0:y1, x0:x1] += wgt
     return num / den
+
+
+def backproject_exact(I0: np.ndarray, lr: np.ndarray, scale: int, iters: int, sigma_blur: float = 1.0,
+                      sigma_s: float = 1.5, sigma_r: float = 0.1) -> np.ndarray:
+    """Back-projection with the filter that Section 4.3 approximates: each
+    iteration adds the exact cross bilateral filter of the upsampled error
+    (guide: the current estimate) instead of S * (C * E). Used only to report
+    the effect of the approximation on the result (small images)."""
+    I = np.asarray(I0, dtype=np.float64).copy()
+    for _ in range(iters):
+        sim = degrade(I, scale, sigma_blur, to_f32=False)
+        E = bicubic_up(np.asarray(lr, dtype=np.float64) - sim, scale, I.shape[0], I.shape[1])
+        I = I + exact_cross_bilateral(E, I, sigma_s, sigma_r)
+    return I

@@ -166,3 +166,23 @@ def test_approximate_vs_exact_cross_bilateral_error():
         rel.append(float(np.sqrt(((approx - exact) ** 2).mean() / (exact ** 2).mean())))
     assert all(b < a for a, b in zip(rel, rel[1:])), rel
     assert 0.6 < rel[1] < 0.95 and rel[-1] < 1e-6, rel
+
+
+def test_exact_filter_back_projection_limits():
+    """The back-projection with the exact cross bilateral filter equals the
+    approximate one when the range kernel is flat (sigma_r -> inf: both add
+    the normalised Gaussian of the upsampled error), and both reduce the RMS
+    LR residual of a bicubic start at the workloads' sigma_r (measured: 0.027
+    to 0.022 approximate, 0.015 exact, in 3 iterations)."""
+    hr = synthdata.fractal_voronoi_image(synthdata.SEED_BASE + 52, 64, 72).astype(np.float64)
+    lr = imaging.degrade(hr, 2, to_f32=False)
+    I0 = imaging.bicubic_up(lr, 2)
+    a = bp.backproject(I0, lr, 2, 2, 1.0, 1.5, math.inf)
+    e = bp.backproject_exact(I0, lr, 2, 2, 1.0, 1.5, 1e12)
+    assert np.abs(a - e).max() < 1e-10
+    def rms(I):
+        return float(np.sqrt(((imaging.degrade(I, 2, to_f32=False) - lr) ** 2).mean()))
+
+    for f in (bp.backproject, bp.backproject_exact):
+        out = f(I0, lr, 2, 3, 1.0, 1.5, 0.1)
+        assert rms(out) < 0.9 * rms(I0)
