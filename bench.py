@@ -76,6 +76,33 @@ def traffic_from_profile(form):
     return float(rec["hbm_bytes_per_launch"])
 
 
+# MI355X: 256 compute units of 4 SIMDs at 2.4 GHz; a wave64 VALU instruction
+# takes 4 cycles of its SIMD.
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+
+
+def issue_from_profile(name, src_name, launch_ms):
+    """Issue fractions of a kernel from the committed rocprofv3 counter summary
+    profiles/<name>_counters.json (SQ_WAVES, SQ_INSTS_VALU and
+    SQ_VALU_MFMA_BUSY_CYCLES per launch), if it was taken with the current
+    source: VALU instructions x 4 cycles, and matrix-core busy cycles, over the
+    SIMD cycles of this run's launch time."""
+    path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
+    src = os.path.join(ROOT, "paper_1004_3980_amd", "csrc", src_name)
+    if not os.path.exists(path) or launch_ms <= 0:
+        return {}
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("src_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return {}
+    cyc = launch_ms * 1e-3 * CLOCK_HZ * SIMDS
+    out = {"valu_issue_frac": round(rec["valu_insts"] * 4.0 / cyc, 4)}
+    if rec.get("mfma_busy_cycles"):
+        out["mfma_busy_frac"] = round(rec["mfma_busy_cycles"] / cyc, 4)
+    return out
+
+
 # ---- CPU baseline: the FP64 oracle on the host cores -----------------------------
 #
 # The oracle runs in a child process started before this process touches the
@@ -318,6 +345,8 @@ def main():
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes": sb, "launch_ms": round(ms_stage["search"], 4),
             "dominant_stage": dom}
+    if own_scale and args.metric == "l2" and args.form == "screened":
+        roof.update(issue_from_profile("search_screened", "k_search.hip", ms_stage["search"]))
     # the projection of the hash (Eq. hash_fn) against the bf16 matrix-core peak:
     # useful flops 2 Q D L k over the hash stage (projection, codes, keys, FP64 fixes)
     hflop = 2.0 * Q * wl.D * wl.L * wl.k
@@ -325,6 +354,8 @@ def main():
     hash_roof = {"bound": "mfma", "kernel": "k_hash", "achieved": round(hach, 2), "peak": MFMA_BF16_PEAK_TFLOPS,
                  "unit": "TFLOP/s", "frac": round(hach / MFMA_BF16_PEAK_TFLOPS, 4), "flops": hflop,
                  "launch_ms": round(ms_stage["hash"], 4)}
+    if own_scale:
+        hash_roof.update(issue_from_profile("hash", "k_hash.hip", ms_stage["hash"]))
 
     # other form on the same image, back-projection, whole path with back-projection
     other = "exact" if args.form == "screened" else "screened"

@@ -550,6 +550,9 @@ __device__ __forceinline__ void sb_tile(const int32_t* __restrict__ ids, const i
     const int tid = threadIdx.x;
     const int npi = h - kPatch + 1, npj = w - kPatch + 1;
     const int ntj = (npj + TJ - 1) / TJ;
+    // the grid is rounded up to a multiple of 8: workgroups past the last
+    // tile have no region
+    if (npi <= 0 || npj <= 0 || tile >= (int64_t)((npi + TI - 1) / TI) * ntj) return;
     const int ti = (int)(tile / ntj), tj = (int)(tile - (int64_t)ti * ntj);
     const int i0 = ti * TI, j0 = tj * TJ;
     for (int e = tid; e < RY * RX; e += 256) sacc[e] = 0.0f;
@@ -680,11 +683,12 @@ __global__ __launch_bounds__(256) void k_sb_combine(const float* __restrict__ pa
 // found from its first tile (sbt_off) or HR pixel (hr_off); partial regions
 // at the image's first tile.
 template <int s, int TI>
-__global__ __launch_bounds__(256) void k_b_sb_tile(const BatchImage* __restrict__ im, int n, int K,
+__global__ __launch_bounds__(256) void k_b_sb_tile(const BatchImage* __restrict__ im, int n, int64_t tiles, int K,
                                                    const int32_t* __restrict__ ids, const int32_t* __restrict__ m,
                                                    const float* __restrict__ wt, const double* __restrict__ mu,
                                                    const float* __restrict__ resid, float* __restrict__ part) {
     const int64_t t = xcd_block();
+    if (t >= tiles) return;   // the grid is rounded up to a multiple of 8
     const BatchImage& b = im[batch_image_of<&BatchImage::sbt_off>(im, n, t)];
     sb_tile<s, TI>(ids + b.q_off * K, m + b.q_off, wt + b.q_off * K, mu + b.q_off, resid, K, b.h, b.w,
                    t - b.sbt_off, part + b.sbt_off * SbGeom<s, TI>::PART);
@@ -757,8 +761,8 @@ static hipError_t b_sb_launch(const BatchImage* im, int n, int64_t tiles, int64_
                               hipStream_t st) {
     if (tiles > 0) {
         if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_b_sb_tile<s, TI>), dim3((unsigned)round_grid8((int)tiles)), dim3(256), 0, st, im, n, K,
-                           ids, m, wt, mu, resid, part);
+        hipLaunchKernelGGL((k_b_sb_tile<s, TI>), dim3((unsigned)round_grid8((int)tiles)), dim3(256), 0, st, im, n, tiles,
+                           K, ids, m, wt, mu, resid, part);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -58,7 +58,8 @@ __device__ void wave_sort_u32(uint32_t* s, int n) {
 
 // Bitonic sort of NS*64 keys held NS per lane (element s*64 + lane) in
 // registers, ascending. With NS == 1 and N < 64, each aligned group of N lanes
-// is sorted on its own.
+// is sorted on its own: ascending where (lane & N) == 0, descending in the
+// other groups.
 template <int NS, int N = NS * 64>
 __device__ __forceinline__ void wave_sort_keys(uint64_t (&key)[NS]) {
     const int lane = threadIdx.x & 63;
