@@ -641,8 +641,9 @@ __device__ void mark_smallest(const uint32_t (&kv)[NSL], const uint32_t (&tie)[N
 //     row (its coordinates y~ = s_x c in the dictionary's leading principal
 //     directions as int8 codes c, with |y~|^2, s_x and rho_x) gives
 //     |y^_q - y~|^2 = |y^_q|^2 + |y~|^2 - 2 y^_q.y~ from one int8 product on
-//     the matrix cores (screen rows as A, the rotated query coded as
-//     s_q (h + l / 128), its int8 codes h and l as two columns of B), and
+//     the matrix cores (the rotated query coded as s_q (h + l / 128), its
+//     int8 codes h and l as two rows of A, the screen rows as the columns of
+//     B, so that one lane receives both products of a candidate), and
 //     with the error bounds a lower bound L <= |q - x|^2. The K
 //     candidates of smallest L get exact distances; the largest upper bound
 //     U_K of those bounds the K-th smallest distance, so only candidates with
@@ -761,12 +762,12 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
         int nA = 0;   // rows of the first exact pass (cids[0..nA)), whose Gram matrix is in hset
         if (M > a.K) {
             const int K = a.K;
-            // B operand: column 0 the high codes of y_q, column 1 the low
-            // codes, lane (ri, kb) coordinates 16 kb .. 16 kb + 15
-            const i32x4 qb = ri < 2 ? *reinterpret_cast<const i32x4*>(qr + 16 * ri + 4 * kb) : i32x4{0, 0, 0, 0};
-            // screen rows of 16 candidates: lane (ri, kb) holds bytes
-            // 16 kb .. 16 kb + 15 of candidate t + ri's row; the tail (bytes
-            // 56 .. 63) goes to stl and out of the product
+            // A operand: row 0 the high codes of y_q, row 1 the low codes,
+            // lane (ri, kb) coordinates 16 kb .. 16 kb + 15
+            const i32x4 qa = ri < 2 ? *reinterpret_cast<const i32x4*>(qr + 16 * ri + 4 * kb) : i32x4{0, 0, 0, 0};
+            // B operand, the screen rows of 16 candidates as columns: lane
+            // (ri, kb) holds bytes 16 kb .. 16 kb + 15 of candidate t + ri's
+            // row; the tail (bytes 56 .. 63) goes to stl and out of the product
             auto load_chunk = [&](int t, i32x4& v) {
                 const int c = t + ri;
                 const uint32_t id = c < M ? cids[c] : 0u;
@@ -780,19 +781,10 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
                     v[2] = 0;
                     v[3] = 0;
                 }
-                const i32x4 acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(v, qb, i32x4{0, 0, 0, 0}, 0, 0, 0);
-                // lane (kb, 0) holds h.c and lane (kb, 1) l.c of candidates
-                // t + 4 kb + r, both exact; (128 h.c + l.c) / 128 is rounded once
-                int lo4[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) lo4[r] = __shfl_down(acc[r], 1);
-                if (ri == 0) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int cc = t + 4 * kb + r;
-                        if (cc < M) cdist[cc] = __float_as_uint((float)(128 * acc[r] + lo4[r]) * (1.0f / 128.0f));
-                    }
-                }
+                const i32x4 acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(qa, v, i32x4{0, 0, 0, 0}, 0, 0, 0);
+                // lane j < 16 holds rows 0 and 1 of column j: h.c and l.c of
+                // candidate t + j, both exact; (128 h.c + l.c) / 128 is rounded once
+                if (lane < 16 && c < M) cdist[c] = __float_as_uint((float)(128 * acc[0] + acc[1]) * (1.0f / 128.0f));
             };
             // four chunks (64 rows) in flight per step
             for (int t = 0; t < M; t += 64) {
@@ -821,7 +813,9 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
                     const float nn = qn2 + tl.x;
                     const float a2 = nn - 2.0f * dot;
                     const float E = fmaf(a.ce, nn, 1e-30f);
-                    const float alo = sqrtf(fmaxf((a2 - E) * (1.0f - 1e-6f), 0.0f)) * (1.0f - 1e-6f);
+                    // the hardware square root (within 1 ulp; a flushed tiny
+                    // argument gives 0), then 1e-6 down
+                    const float alo = __builtin_amdgcn_sqrtf(fmaxf((a2 - E) * (1.0f - 1e-6f), 0.0f)) * (1.0f - 1e-6f);
                     const float l = fmaxf(alo * (1.0f - 1e-6f) - (rho_q + rho_x) * (1.0f + 1e-6f), 0.0f);
                     lv[s] = __float_as_uint(l * l * a.inv_s2 * (1.0f - 1e-5f));
                     iv[s] = cids[c];
