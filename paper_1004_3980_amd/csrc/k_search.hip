@@ -584,7 +584,7 @@ __device__ void write_gram(const SearchArgs& a, int q, const float* sq, uint32_t
     GT* out = reinterpret_cast<GT*>(a.gram) + (int64_t)q * 36;
     if (lane < 36) {
         // row i of packed entry `lane` (i (i + 1) / 2 <= lane < (i + 1) (i + 2) / 2)
-        int i = (int)((sqrtf((float)(8 * lane + 1)) - 1.0f) * 0.5f);
+        int i = (int)((__builtin_amdgcn_sqrtf((float)(8 * lane + 1)) - 1.0f) * 0.5f);
         if ((i + 1) * (i + 2) / 2 <= lane) ++i;
         if (i * (i + 1) / 2 > lane) --i;
         const int j = lane - i * (i + 1) / 2;
@@ -767,20 +767,18 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
             const i32x4 qa = ri < 2 ? *reinterpret_cast<const i32x4*>(qr + 16 * ri + 4 * kb) : i32x4{0, 0, 0, 0};
             // B operand, the screen rows of 16 candidates as columns: lane
             // (ri, kb) holds bytes 16 kb .. 16 kb + 15 of candidate t + ri's
-            // row; the tail (bytes 56 .. 63) goes to stl and out of the product
+            // row (columns past M read row 0: column j of the product
+            // depends on column j of B only, and is not used); the tail
+            // (bytes 56 .. 63) goes to stl, and meets the query's zero codes
+            // past the 56 screen coordinates in the product
             auto load_chunk = [&](int t, i32x4& v) {
                 const int c = t + ri;
                 const uint32_t id = c < M ? cids[c] : 0u;
-                v = i32x4{0, 0, 0, 0};
-                if (c < M) v = *reinterpret_cast<const i32x4*>(a.sc + (size_t)id * kScreenBytes + 16 * kb);
+                v = *reinterpret_cast<const i32x4*>(a.sc + (size_t)id * kScreenBytes + 16 * kb);
             };
-            auto screen_chunk = [&](int t, i32x4& v) {
+            auto screen_chunk = [&](int t, const i32x4& v) {
                 const int c = t + ri;
-                if (kb == 3) {
-                    if (c < M) stl[c] = make_float2(__int_as_float(v[2]), __int_as_float(v[3]));
-                    v[2] = 0;
-                    v[3] = 0;
-                }
+                if (kb == 3 && c < M) stl[c] = make_float2(__int_as_float(v[2]), __int_as_float(v[3]));
                 const i32x4 acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(qa, v, i32x4{0, 0, 0, 0}, 0, 0, 0);
                 // lane j < 16 holds rows 0 and 1 of column j: h.c and l.c of
                 // candidate t + j, both exact; (128 h.c + l.c) / 128 is rounded once
