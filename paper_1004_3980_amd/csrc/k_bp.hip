@@ -38,27 +38,35 @@ __device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float
     constexpr int REG = T + 2 * kBpMaxR;
     // LR rows / columns under REG HR pixels at zoom >= 2: REG / 2 + 4
     constexpr int LREG = REG / 2 + 5;
+    constexpr int NT = 2 * kBpMaxR + 1;
     __shared__ float sI[REG][REG];
     __shared__ float sE[REG][REG];          // first the staged LR error patch [LREG][LREG]
     __shared__ float sH[2][REG][T];         // the passes' sums; first the x pass of the upsampling [LREG][REG]
-    __shared__ float sg[2 * kBpMaxR + 1];
+    __shared__ float sg[NT];
     __shared__ float sw[kMaxScale][4];      // Keys' weights of each phase
+    // per staged row / column in the image: the first of its four LR taps
+    // relative to the staged LR patch (<< 8) and its phase; -1 outside the image
+    __shared__ int srow[REG], scol[REG];
     static_assert(LREG * LREG <= REG * REG && LREG * REG <= 2 * REG * T, "LDS aliases");
     float (*sHE)[T] = sH[0];
     float (*sHB)[T] = sH[1];
     float* eL = &sE[0][0];
     float* xU = &sH[0][0][0];
     const int reg = T + 2 * R;
-    if ((int)threadIdx.x < 2 * R + 1) {
-        const float d = (float)((int)threadIdx.x - R);
-        sg[threadIdx.x] = expf(-(d * d) / (2.0f * sigma_s * sigma_s));
+    const int tid = threadIdx.x;
+    if (tid < 2 * R + 1) {
+        const float d = (float)(tid - R);
+        sg[tid] = expf(-(d * d) / (2.0f * sigma_s * sigma_s));
     }
-    if ((int)threadIdx.x < 4 * s && s <= kMaxScale) {
-        const int ph = threadIdx.x >> 2, a = threadIdx.x & 3;
+    if (tid < 4 * s && s <= kMaxScale) {
+        const int ph = tid >> 2, a = tid & 3;
         sw[ph][a] = keys_w((float)ph / (float)s - (float)(a - 1));
     }
-    for (int t = threadIdx.x; t < reg * reg; t += blockDim.x) {
-        const int r = t / reg, c = t % reg;
+    // loops over the staged region run over REG x REG (a constant divisor)
+    // and skip what lies past reg
+    for (int t = tid; t < REG * REG; t += blockDim.x) {
+        const int r = t / REG, c = t - r * REG;
+        if (r >= reg || c >= reg) continue;
         const int Y = Y0 - R + r, X = X0 - R + c;
         const bool in = Y >= 0 && Y < H && X >= 0 && X < W;
         sI[r][c] = in ? I[(int64_t)Y * W + X] : 0.0f;
@@ -70,21 +78,32 @@ __device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float
     const int la = ya / s - 1, lc = xa / s - 1;          // first staged LR row / column
     const int nlr = yb / s + 2 - la + 1, nlc = xb / s + 2 - lc + 1;
     if (sep) {
-        for (int t = threadIdx.x; t < nlr * nlc; t += blockDim.x) {
-            const int r = t / nlc, c = t % nlc;
+        for (int t = tid; t < LREG * LREG; t += blockDim.x) {
+            const int r = t / LREG, c = t - r * LREG;
+            if (r >= nlr || c >= nlc) continue;
             eL[r * LREG + c] = e[(int64_t)clampi(la + r, 0, h - 1) * w + clampi(lc + c, 0, w - 1)];
+        }
+        if (tid < reg) {
+            const int Y = Y0 - R + tid;
+            const int i0 = Y / s;
+            srow[tid] = Y < ya || Y > yb ? -1 : ((i0 - 1 - la) << 8) | (Y - i0 * s);
+        } else if (tid >= 64 && tid < 64 + reg) {
+            const int c = tid - 64;
+            const int X = X0 - R + c;
+            const int j0 = X / s;
+            scol[c] = X < xa || X > xb ? -1 : ((j0 - 1 - lc) << 8) | (X - j0 * s);
         }
     }
     __syncthreads();
     if (sep) {
         // along x: every staged LR row at the region's columns
-        for (int t = threadIdx.x; t < nlr * reg; t += blockDim.x) {
-            const int r = t / reg, c = t % reg;
-            const int X = X0 - R + c;
-            if (X < xa || X > xb) continue;
-            const int j0 = X / s;
-            const float* wx = sw[X - j0 * s];
-            const float* row = eL + r * LREG + (j0 - 1 - lc);
+        for (int t = tid; t < LREG * REG; t += blockDim.x) {
+            const int r = t / REG, c = t - r * REG;
+            if (r >= nlr || c >= reg) continue;
+            const int sc = scol[c];
+            if (sc < 0) continue;
+            const float* wx = sw[sc & 0xFF];
+            const float* row = eL + r * LREG + (sc >> 8);
             float v = 0.0f;
 #pragma unroll
             for (int b = 0; b < 4; ++b) v = fmaf(wx[b], row[b], v);
@@ -92,22 +111,23 @@ __device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float
         }
         __syncthreads();
         // along y
-        for (int t = threadIdx.x; t < reg * reg; t += blockDim.x) {
-            const int r = t / reg, c = t % reg;
-            const int Y = Y0 - R + r, X = X0 - R + c;
+        for (int t = tid; t < REG * REG; t += blockDim.x) {
+            const int r = t / REG, c = t - r * REG;
+            if (r >= reg || c >= reg) continue;
+            const int sr = srow[r];
             float v = 0.0f;
-            if (Y >= 0 && Y < H && X >= 0 && X < W) {
-                const int i0 = Y / s;
-                const float* wy = sw[Y - i0 * s];
-                const int r0 = i0 - 1 - la;
+            if (sr >= 0 && scol[c] >= 0) {
+                const float* wy = sw[sr & 0xFF];
+                const int r0 = sr >> 8;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) v = fmaf(wy[a], xU[(r0 + a) * REG + c], v);
             }
             sE[r][c] = v;
         }
     } else {
-        for (int t = threadIdx.x; t < reg * reg; t += blockDim.x) {
-            const int r = t / reg, c = t % reg;
+        for (int t = tid; t < REG * REG; t += blockDim.x) {
+            const int r = t / REG, c = t - r * REG;
+            if (r >= reg || c >= reg) continue;
             const int Y = Y0 - R + r, X = X0 - R + c;
             const bool in = Y >= 0 && Y < H && X >= 0 && X < W;
             sE[r][c] = in ? bicubic_at(e, h, w, s, Y, X) : 0.0f;
@@ -115,54 +135,10 @@ __device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float
     }
     __syncthreads();
     const bool inner = Y0 - R >= 0 && X0 - R >= 0 && Y0 + T + R <= H && X0 + T + R <= W;
-    // horizontal passes over every staged row, the tile's columns
-    for (int t = threadIdx.x; t < reg * T; t += blockDim.x) {
-        const int r = t / T, c = t % T;
-        const int X = X0 + c;
-        float ge = 0.0f, gn = 0.0f, bs = 0.0f;
-        if (inner) {
-            for (int d = -R; d <= R; ++d) {
-                const float g = sg[d + R];
-                ge = fmaf(g, sE[r][c + R + d], ge);
-                gn += g;
-                bs += sI[r][c + R + d];
-            }
-        } else {
-            for (int d = -R; d <= R; ++d) {
-                const int x = X + d;
-                if (x < 0 || x >= W) continue;
-                const float g = sg[d + R];
-                ge = fmaf(g, sE[r][c + R + d], ge);
-                gn += g;
-                bs += sI[r][c + R + d];
-            }
-        }
-        sHE[r][c] = gn > 0.0f ? ge / gn : 0.0f;
-        sHB[r][c] = bs;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < T * T; t += blockDim.x) {
-        const int r = t / T, c = t % T;
+    const int nt = 2 * R + 1;
+    // the output of pixel (r, c) of the tile from its vertical sums
+    auto emit = [&](int r, int c, float ge, float gn, float bs) {
         const int Y = Y0 + r, X = X0 + c;
-        if (Y >= H || X >= W) continue;
-        float ge = 0.0f, gn = 0.0f, bs = 0.0f;
-        if (inner) {
-            for (int d = -R; d <= R; ++d) {
-                const float g = sg[d + R];
-                ge = fmaf(g, sHE[r + R + d][c], ge);
-                gn += g;
-                bs += sHB[r + R + d][c];
-            }
-        } else {
-            for (int d = -R; d <= R; ++d) {
-                const int y = Y + d;
-                if (y < 0 || y >= H) continue;
-                const float g = sg[d + R];
-                ge = fmaf(g, sHE[r + R + d][c], ge);
-                gn += g;
-                bs += sHB[r + R + d][c];
-            }
-        }
         const int ny = min(H - 1, Y + R) - max(0, Y - R) + 1;
         const int nx = min(W - 1, X + R) - max(0, X - R) + 1;
         const float Ixy = sI[r + R][c + R];
@@ -177,6 +153,103 @@ __device__ __forceinline__ void bp_tile(const float* __restrict__ I, const float
         } else {
             out[(int64_t)Y * W + X] = fmaf(S, ge / gn, Ixy);
         }
+    };
+    if (inner) {
+        // no tap leaves the image: four adjacent outputs a thread, their
+        // taps d = -R .. R in order from registers (the same operations as
+        // the one-output loops below)
+        for (int t = tid; t < reg * (T / 4); t += blockDim.x) {
+            const int r = t / (T / 4), c = 4 * (t % (T / 4));
+            // columns past the last tap (c + q >= reg) are read and not used
+            float ev[NT + 3], iv[NT + 3];
+#pragma unroll
+            for (int q = 0; q < (NT + 3) / 4; ++q) {
+                const float4 x = *reinterpret_cast<const float4*>(&sE[r][c + 4 * q]);
+                const float4 y = *reinterpret_cast<const float4*>(&sI[r][c + 4 * q]);
+                ev[4 * q] = x.x, ev[4 * q + 1] = x.y, ev[4 * q + 2] = x.z, ev[4 * q + 3] = x.w;
+                iv[4 * q] = y.x, iv[4 * q + 1] = y.y, iv[4 * q + 2] = y.z, iv[4 * q + 3] = y.w;
+            }
+            float ge[4] = {0.0f, 0.0f, 0.0f, 0.0f}, bs[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gn = 0.0f;
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                if (u >= nt) break;
+                const float g = sg[u];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    ge[j] = fmaf(g, ev[j + u], ge[j]);
+                    bs[j] += iv[j + u];
+                }
+                gn += g;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sHE[r][c + j] = gn > 0.0f ? ge[j] / gn : 0.0f;
+                sHB[r][c + j] = bs[j];
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < (T / 4) * T; t += blockDim.x) {
+            const int r = 4 * (t / T), c = t % T;
+            float hv[NT + 3], bv[NT + 3];
+            // rows past the last tap (r + q >= reg) are read and not used
+#pragma unroll
+            for (int q = 0; q < NT + 3; ++q) {
+                hv[q] = sHE[r + q][c];
+                bv[q] = sHB[r + q][c];
+            }
+            float ge[4] = {0.0f, 0.0f, 0.0f, 0.0f}, bs[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gn = 0.0f;
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                if (u >= nt) break;
+                const float g = sg[u];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    ge[j] = fmaf(g, hv[j + u], ge[j]);
+                    bs[j] += bv[j + u];
+                }
+                gn += g;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) emit(r + j, c, ge[j], gn, bs[j]);
+        }
+        return;
+    }
+    // horizontal passes over every staged row, the tile's columns; the taps
+    // d = -R .. R in order, those outside the image left out
+    for (int t = tid; t < reg * T; t += blockDim.x) {
+        const int r = t / T, c = t % T;
+        const int X = X0 + c;
+        float ge = 0.0f, gn = 0.0f, bs = 0.0f;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            if (u >= nt) break;
+            const int x = X + u - R;
+            if (x < 0 || x >= W) continue;
+            const float g = sg[u];
+            ge = fmaf(g, sE[r][c + u], ge);
+            gn += g;
+            bs += sI[r][c + u];
+        }
+        sHE[r][c] = gn > 0.0f ? ge / gn : 0.0f;
+        sHB[r][c] = bs;
+    }
+    __syncthreads();
+    for (int t = tid; t < T * T; t += blockDim.x) {
+        const int r = t / T, c = t % T;
+        const int Y = Y0 + r, X = X0 + c;
+        if (Y >= H || X >= W) continue;
+        float ge = 0.0f, gn = 0.0f, bs = 0.0f;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            if (u >= nt) break;
+            const int y = Y + u - R;
+            if (y < 0 || y >= H) continue;
+            const float g = sg[u];
+            ge = fmaf(g, sHE[r + u][c], ge);
+            gn += g;
+            bs += sHB[r + u][c];
+        }
+        emit(r, c, ge, gn, bs);
     }
 }
 
