@@ -692,9 +692,14 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
         for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
         for (int i = lane; i < 128; i += 64) sq[i] = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
         // the coded query y^ = s_q (h + l / 128): int8 codes h and l, then
-        // s_q, |y^|^2 and rho_q >= |y^ - Phi q|
-        const float* qr = a.qrot + (int64_t)q * kRotStride;
-        const float s_q = qr[32], qn2 = qr[33], rho_q = qr[34];
+        // s_q, |y^|^2 and rho_q >= |y^ - Phi q| (none in the candidates-only form)
+        const float* qr = a.qrot ? a.qrot + (int64_t)q * kRotStride : nullptr;
+        float s_q = 0.0f, qn2 = 0.0f, rho_q = 0.0f;
+        if (qr) {
+            s_q = qr[32];
+            qn2 = qr[33];
+            rho_q = qr[34];
+        }
         __syncthreads();
 
         // ---- 1. candidates, first occurrences in order, up to cap
@@ -756,6 +761,7 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
             for (int i = lane; i < M && i < a.dump_cap; i += 64) a.dump[(int64_t)q * a.dump_cap + i] = (int32_t)cids[i];
         }
         if (lane == 0) a.out_ncand[q] = M;
+        if (a.cand_only) return;
 
         // ---- 2. screen lower bounds, exact distances of the K lowest, U_K
         int Mr = M;

@@ -384,6 +384,88 @@ __global__ __launch_bounds__(64) void k_knn_rank(int Q, int Drt, int K, int cap,
     if (lane == 0) out_m[q] = m;
 }
 
+// The same ranking when D is a multiple of 4 (D = 100): lane j takes
+// candidate j of each chunk of 64, reads its whole row into registers with
+// 16-byte loads (all in flight at once) and sums its terms in index order in
+// FP64, the same operations as above; the K rounds of wave minimum follow.
+template <int DT, bool L1>
+__global__ __launch_bounds__(64) void k_knn_rank_rows(int Q, int K, int cap, const float* __restrict__ qfeat,
+                                                    const float* __restrict__ xf, const int32_t* __restrict__ cand,
+                                                    const int32_t* __restrict__ ncand, int32_t* __restrict__ out_ids,
+                                                    float* __restrict__ out_d, int32_t* __restrict__ out_m) {
+    static_assert(DT % 4 == 0 && DT <= kL1MaxD, "rows of whole 16-byte chunks");
+    constexpr int D4 = DT / 4;
+    constexpr int NCH = kL1Chunk * kL1PerLane / 64;
+    __shared__ double sq[DT];
+    const int lane = threadIdx.x;
+    const int q = blockIdx.x;
+    const int M = min(ncand[q], cap);
+    for (int i = lane; i < DT; i += 64) sq[i] = (double)qfeat[(int64_t)q * DT + i];
+    __syncthreads();
+    double d[NCH];
+    int id[NCH];
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+        d[u] = INFINITY;
+        id[u] = 0x7FFFFFFF;
+        const int c = 64 * u + lane;
+        if (c < M) {
+            const int myid = cand[(int64_t)q * cap + c];
+            const float4* row = reinterpret_cast<const float4*>(xf) + (int64_t)myid * D4;
+            float4 x[D4];
+#pragma unroll
+            for (int t = 0; t < D4; ++t) x[t] = row[t];
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < D4; ++t) {
+                const float xv[4] = {x[t].x, x[t].y, x[t].z, x[t].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double dv = sq[4 * t + e] - (double)xv[e];
+                    acc = acc + (L1 ? fabs(dv) : dv * dv);
+                }
+            }
+            d[u] = acc;
+            id[u] = myid;
+        }
+    }
+    const int m = min(K, M);
+    for (int k = 0; k < m; ++k) {
+        double bd = d[0];
+        int bi = id[0];
+#pragma unroll
+        for (int u = 1; u < NCH; ++u)
+            if (d[u] < bd || (d[u] == bd && id[u] < bi)) {
+                bd = d[u];
+                bi = id[u];
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double od = __shfl_xor(bd, o);
+            const int oi = __shfl_xor(bi, o);
+            if (od < bd || (od == bd && oi < bi)) {
+                bd = od;
+                bi = oi;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NCH; ++u)
+            if (id[u] == bi) {
+                d[u] = INFINITY;
+                id[u] = 0x7FFFFFFF;
+            }
+        if (lane == 0) {
+            out_ids[(int64_t)q * K + k] = bi;
+            out_d[(int64_t)q * K + k] = (float)bd;
+        }
+    }
+    if (lane >= m && lane < K) {
+        out_ids[(int64_t)q * K + lane] = -1;
+        out_d[(int64_t)q * K + lane] = 0.0f;
+    }
+    if (lane == 0) out_m[q] = m;
+}
+
 hipError_t launch_knn_rank(int Q, int D, int K, int cap, bool l1, const float* qfeat, const float* xf,
                            const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
                            hipStream_t st) {
@@ -391,6 +473,16 @@ hipError_t launch_knn_rank(int Q, int D, int K, int cap, bool l1, const float* q
     if (cap < 1 || cap > kL1Chunk * kL1PerLane || K < 1 || K > kMaxK || D < 1 || D > kL1MaxD) return hipErrorInvalidValue;
 #define ZH_RANK(DT, M1) \
     hipLaunchKernelGGL((k_knn_rank<DT, M1>), dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m)
+    if (D == 100) {
+        const bool al = (reinterpret_cast<uintptr_t>(xf) & 15) == 0;
+        if (al && l1)
+            hipLaunchKernelGGL((k_knn_rank_rows<100, true>), dim3(Q), dim3(64), 0, st, Q, K, cap, qfeat, xf, cand, ncand,
+                               ids, d, m);
+        else if (al)
+            hipLaunchKernelGGL((k_knn_rank_rows<100, false>), dim3(Q), dim3(64), 0, st, Q, K, cap, qfeat, xf, cand,
+                               ncand, ids, d, m);
+        if (al) return hipGetLastError();
+    }
     if (l1) {
         if (D == 100) ZH_RANK(100, true);
         else if (D == 25) ZH_RANK(25, true);

@@ -411,7 +411,9 @@ zh_status store_features(zh_ctx* c, Dict& d, const float* feat) {
     return ZH_OK;
 }
 
-zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
+// cand_only (early stop): the candidate counts and the dump only; the
+// neighbour outputs and the Gram matrices of the last search stay as they are
+zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap, bool cand_only = false) {
     SearchArgs a{};
     a.Q = (int)c->Q;
     a.D = d.D;
@@ -435,7 +437,8 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.out_d2 = P<float>(c->d2);
     a.out_m = P<int32_t>(c->m);
     a.out_ncand = P<int32_t>(c->ncand);
-    if (a.cap > 0) {
+    a.cand_only = cand_only && a.cap > 0 ? 1 : 0;
+    if (a.cap > 0 && !a.cand_only) {
         TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)(a.Q > 0 ? a.Q : 1)));
         a.out_nsurv = P<int32_t>(c->nsurv);
         TRY(ensure(c, c->qrot, sizeof(float) * kRotStride * (size_t)(a.Q > 0 ? a.Q : 1)));
@@ -454,6 +457,11 @@ zh_status run_search(zh_ctx* c, Dict& d, int32_t* dump, int dump_cap) {
     a.dump_cap = dump_cap;
     a.overflow = P<int32_t>(c->over);
     a.counters = P<unsigned int>(c->counters);
+    if (a.cand_only) {
+        StageTimer t(c, ZH_T_SEARCH);
+        HIPCHK(c, launch_search(a, c->stream));
+        return ZH_OK;
+    }
     c->gram_ready = false;
     {
         StageTimer t(c, ZH_T_SEARCH);
@@ -2082,8 +2090,8 @@ zh_status zh_knn_l1(zh_ctx* c) {
     Dict& d = c->dicts[c->qscale];
     TRY(ensure(c, c->l1cand, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1) * cap));
     TRY(clear_counters(c));
-    // the candidate lists of the last query (the search runs again and dumps them)
-    TRY(run_search(c, d, P<int32_t>(c->l1cand), cap));
+    // the candidate lists of the last query (the union runs again and dumps them)
+    TRY(run_search(c, d, P<int32_t>(c->l1cand), cap, true));
     {
         StageTimer t(c, ZH_T_SEARCH);
         HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, cap, true, P<float>(c->qfeat), P<float>(d.xf),
