@@ -54,13 +54,12 @@ __global__ void k_degrade_residual(const float* __restrict__ hr, int H, int W, i
 // the LR rows that use them, then the vertical sums; each value is the
 // blur_at sum to the bit (same products, same order).
 constexpr int kDrI = 8, kDrJ = 32;
-__global__ __launch_bounds__(256) void k_degrade_residual_t(const float* __restrict__ hr, int H, int W, int scale,
-                                                            Taps t, const float* __restrict__ lr_ref,
-                                                            float* __restrict__ e) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// The LR tile with origin (i0, j0) of an h x w LR error (h, w from H, W).
+__device__ __forceinline__ void degrade_tile(const float* __restrict__ hr, int H, int W, int scale, const Taps& t,
+                                             const float* __restrict__ lr_ref, float* __restrict__ e, int i0, int j0,
+                                             unsigned char* smem) {
     const int h = (H + scale - 1) / scale, w = (W + scale - 1) / scale;
     const int R = t.R;
-    const int i0 = blockIdx.y * kDrI, j0 = blockIdx.x * kDrJ;
     const int ny = scale * (kDrI - 1) + 2 * R + 1, nx = scale * (kDrJ - 1) + 2 * R + 1;
     double* hrow = reinterpret_cast<double*>(smem);                       // [ny][kDrJ]
     float* sh = reinterpret_cast<float*>(smem + sizeof(double) * ny * kDrJ);   // [ny][nx]
@@ -87,6 +86,31 @@ __global__ __launch_bounds__(256) void k_degrade_residual_t(const float* __restr
         e[(int64_t)i * w + j] = (float)((double)lr_ref[(int64_t)i * w + j] - acc);
     }
 }
+
+__global__ __launch_bounds__(256) void k_degrade_residual_t(const float* __restrict__ hr, int H, int W, int scale,
+                                                            Taps t, const float* __restrict__ lr_ref,
+                                                            float* __restrict__ e) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    degrade_tile(hr, H, W, scale, t, lr_ref, e, blockIdx.y * kDrI, blockIdx.x * kDrJ, smem);
+}
+
+// Batched, by tiles: workgroup b takes tile b of the concatenated tile lists
+// of the images (the current estimate in out for parity 0, scr for parity 1;
+// image b's error at e + lr_off); the grid may be rounded up past the last tile.
+__global__ __launch_bounds__(256) void k_b_degrade_residual_t(const BatchImage* __restrict__ im, int n, int64_t tiles,
+                                                              int scale, Taps t, int parity, float* __restrict__ e) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t tile = blockIdx.x;
+    if (tile >= tiles) return;
+    const BatchImage& b = im[batch_image_of<&BatchImage::dtile_off>(im, n, tile)];
+    const int local = (int)(tile - b.dtile_off);
+    const int tx = (b.w + kDrJ - 1) / kDrJ;
+    const float* hr = parity ? b.scr : b.out;
+    degrade_tile(hr, scale * b.h, scale * b.w, scale, t, b.lr, e + b.lr_off, (local / tx) * kDrI, (local % tx) * kDrJ,
+                 smem);
+}
+
+int64_t degrade_tiles(int h, int w) { return (int64_t)((h + kDrI - 1) / kDrI) * ((w + kDrJ - 1) / kDrJ); }
 
 // Batched: LR error of every image, the current estimate in out (parity 0)
 // or scr (parity 1); image b's error at e + lr_off.
@@ -394,9 +418,16 @@ hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t seg_tota
     return hipGetLastError();
 }
 
-hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int scale, const Taps& t,
-                                     int parity, float* e, hipStream_t st) {
+hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int64_t tiles, int scale,
+                                     const Taps& t, int parity, float* e, hipStream_t st) {
     if (lr_total == 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (size_t)(scale * (kDrI - 1) + 2 * t.R + 1) * kDrJ +
+                       sizeof(float) * (size_t)(scale * (kDrI - 1) + 2 * t.R + 1) * (scale * (kDrJ - 1) + 2 * t.R + 1);
+    if (lds <= 48 * 1024 && tiles > 0 && tiles <= 0x7FFFFFFF) {
+        hipLaunchKernelGGL(k_b_degrade_residual_t, dim3((unsigned)tiles), dim3(256), lds, st, im, n, tiles, scale, t,
+                           parity, e);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_b_degrade_residual, dim3(grid_for(lr_total, 256)), dim3(256), 0, st, im, n, lr_total, scale,
                        t, parity, e);
     return hipGetLastError();

@@ -95,6 +95,7 @@ struct zh_ctx {
         int64_t q_total = 0, lr_total = 0, hr_total = 0, tiles = 0;
         int64_t fsegs = 0;              // feature segments of all images
         int64_t sbtiles = 0;            // tiles of the fused synthesis and blend of all images
+        int64_t dtiles = 0;             // LR-error tiles of all images
         Buf table;                // device BatchImage[n]
     };
     struct Batch {
@@ -1592,7 +1593,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
     std::vector<BatchImage> tabs[kMaxScale + 1];
     for (int s = 1; s <= kMaxScale; ++s) {
         auto& g = B.g[s];
-        int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, sbt = 0;
+        int64_t q = 0, lr = 0, hr = 0, tiles = 0, fsegs = 0, sbt = 0, dt = 0;
         for (int i = 0; i < b->n_images; ++i) {
             if (b->scale[i] != s) continue;
             BatchImage im{};
@@ -1606,6 +1607,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
             im.tile_off = tiles;
             im.fblk_off = fsegs;
             im.sbt_off = sbt;
+            im.dtile_off = dt;
             tabs[s].push_back(im);
             lr += (int64_t)im.h * im.w;
             q += (int64_t)(im.h - 4) * (im.w - 4);
@@ -1613,6 +1615,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
             tiles += bp_tiles(s * im.h, s * im.w, B.tile);
             fsegs += feature_segments(im.h, im.w);
             sbt += sb_tiles(s, c->sb_rows, im.h, im.w);
+            dt += degrade_tiles(im.h, im.w);
         }
         g.n = (int)tabs[s].size();
         g.q_total = q;
@@ -1621,6 +1624,7 @@ zh_status batch_plan(zh_ctx* c, const zh_batch* b) {
         g.tiles = tiles;
         g.fsegs = fsegs;
         g.sbtiles = sbt;
+        g.dtiles = dt;
         if (!g.n) continue;
         if (q * kMaxK >= (1ll << 31)) return fail(c, ZH_EINVAL, "zh_run_batch: too many patches at scale %d", s);
         const Dict& d = c->dicts[s];
@@ -1741,7 +1745,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
                                            P<float>(c->sbpart), st));
             const Taps tg = gauss_taps(1.0);
             for (int t = 0; t < b->bp_iters; ++t) {
-                HIPCHK(c, launch_b_degrade_residual(tab, g.n, g.lr_total, s, tg, t & 1, P<float>(B.e), st));
+                HIPCHK(c, launch_b_degrade_residual(tab, g.n, g.lr_total, g.dtiles, s, tg, t & 1, P<float>(B.e), st));
                 HIPCHK(c, launch_b_bp_update(tab, g.n, g.tiles, B.tile, B.grid_per_cu * ncu, s, b->sigma_s, b->sigma_r,
                                              P<float>(B.e), t & 1, P<unsigned int>(B.counter), st));
             }
@@ -1947,7 +1951,8 @@ zh_status zh_tune_batch(zh_ctx* c, const zh_batch* b, zh_batch_tuning* out) {
                     auto& g = B.g[s];
                     if (!g.n) continue;
                     const BatchImage* tab = P<BatchImage>(g.table);
-                    if (launch_b_degrade_residual(tab, g.n, g.lr_total, s, gauss_taps(1.0), 0, P<float>(B.e), B.stream) !=
+                    if (launch_b_degrade_residual(tab, g.n, g.lr_total, g.dtiles, s, gauss_taps(1.0), 0, P<float>(B.e),
+                                                  B.stream) !=
                             hipSuccess ||
                         launch_b_bp_update(tab, g.n, g.tiles, tiles[ti], mults[mi] * ncu, s, b->sigma_s, b->sigma_r,
                                            P<float>(B.e), 0, P<unsigned int>(B.counter), B.stream) != hipSuccess)

@@ -263,6 +263,7 @@ struct BatchImage {
     int64_t lr_off, q_off, hr_off, tile_off;
     int64_t fblk_off;             // first workgroup of the image's feature segments
     int64_t sbt_off;              // first tile of the image's fused synthesis and blend
+    int64_t dtile_off;            // first tile of the image's LR error (back-projection)
 };
 // feature segments (64 patches of a patch row) of an h x w LR image
 constexpr int kFeatSeg = 64;
@@ -283,8 +284,10 @@ hipError_t launch_b_gradient_maps(const BatchImage* im, int n, int64_t lr_total,
 // one workgroup per feature segment (64 patches of a patch row) of every image
 hipError_t launch_b_query_features(const BatchImage* im, int n, int64_t seg_total, int mode, const float* maps,
                                    float* feat, double* mu, hipStream_t st);
-hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int scale, const Taps& t,
-                                     int parity, float* e, hipStream_t st);
+// LR error of every image: `tiles` LR tiles in all (degrade_tiles per image)
+hipError_t launch_b_degrade_residual(const BatchImage* im, int n, int64_t lr_total, int64_t tiles, int scale,
+                                     const Taps& t, int parity, float* e, hipStream_t st);
+int64_t degrade_tiles(int h, int w);
 // fused synthesis and blend of every image: `tiles` tiles of `rows` patch
 // rows (offsets sbt_off), then the combine over the hr_total HR pixels
 hipError_t launch_b_synth_blend(const BatchImage* im, int n, int64_t tiles, int64_t hr_total, int scale, int rows,
