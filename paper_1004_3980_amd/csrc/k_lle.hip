@@ -511,8 +511,9 @@ hipError_t launch_lle_all(int Q, int D, int cap, double lam, const float* qfeat,
 // The synthesised patches are never written out. The patch origins are cut
 // into tiles of TI patch rows x sb_cols(s) patch columns; a workgroup takes a
 // tile, forms x_q = mu_q + sum_m w_m r_{n_m} of one patch row at a time in
-// LDS (the K residual rows read once, in chunks of eight neighbours, with the
-// same fused multiply-adds in the same order as k_synth4) and adds each
+// LDS (the K residual rows read once, in chunks of eight neighbours; each
+// value is a fused multiply-add over the neighbours in order from zero, then
+// mu_q is added) and adds each
 // pixel's values of the row's patches, in ascending column order, to the
 // tile's region: the (TI + 4) s x (TJ + 4) s HR pixels its patches cover,
 // together with the count of covering patches of every LR cell. Regions go
