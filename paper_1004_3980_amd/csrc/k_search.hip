@@ -632,6 +632,88 @@ __device__ void mark_smallest(const uint32_t (&kv)[NSL], const uint32_t (&tie)[N
     (void)lane;
 }
 
+// The early stop's candidates of patch q (step 1 of the search below):
+// the concatenation of its L bins read 64 positions at a time; an LDS hash
+// set of the IDs seen so far (open addressing, atomic compare-and-swap
+// inserts, an atomic minimum keeping the earliest lane of a chunk) keeps
+// first occurrences in order, up to cap. Leaves them in cids[0..M) and
+// returns M; hset holds hsz slots. Ends with the workgroup synchronised.
+__device__ __forceinline__ int cap_union(const SearchArgs& a, int q, uint64_t* hset, uint32_t* cids, int64_t* sbase,
+                                         int32_t* smark) {
+    const int lane = threadIdx.x;
+    const int L = a.L;
+    const int hsz = a.hsz;
+    const uint32_t hmask = (uint32_t)hsz - 1u;
+    const int hshift = 32 - __builtin_ctz((unsigned)hsz);
+    uint32_t off = 0, cnt = 0;
+    if (lane < L) {
+        const uint2 b = a.bins[(int64_t)lane * a.Q + q];
+        off = b.x;
+        cnt = b.y;
+    }
+    const int T = wave_sum_i32((int)cnt);
+    // bins concatenated in table order: position i of bin l is entry
+    // i - start_l of that bin
+    const int start = wave_incl_scan((int)cnt) - (int)cnt;
+    if (lane < L) sbase[lane] = (int64_t)lane * a.N + off - start;
+    for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
+    __syncthreads();
+    int M = 0;
+    int carry = 0;   // table of the position before the chunk
+    for (int base = 0; base < T && M < a.cap; base += 64) {
+        const int i = base + lane;
+        const bool valid = i < T;
+        // the table of each position: the last nonempty bin starting at
+        // or before it (the bins starting inside the chunk mark their
+        // first position)
+        smark[lane] = -1;
+        __syncthreads();
+        const int ps = start - base;
+        if (lane < L && cnt > 0 && ps >= 0 && ps < 64) smark[ps] = lane;
+        __syncthreads();
+        const uint64_t starts = __ballot(smark[lane] >= 0);
+        const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+        const int tbl = below ? smark[63 - __builtin_clzll(below)] : carry;
+        carry = __builtin_amdgcn_readlane(tbl, 63);
+        uint32_t id = 0xFFFFFFFFu;
+        if (valid) id = a.tids[sbase[tbl] + i];
+        uint32_t slot = (id * 0x9E3779B1u) >> hshift;
+        bool found = false;
+        if (valid) {
+            for (;;) {
+                const uint64_t v = hset[slot];
+                if ((uint32_t)(v >> 32) == id) {
+                    found = true;
+                    break;
+                }
+                if (v == ~0ull) break;
+                slot = (slot + 1u) & hmask;
+            }
+        }
+        const bool ins = valid && !found;
+        const uint64_t mine = ((uint64_t)id << 32) | (uint32_t)lane;
+        if (ins) {
+            for (;;) {
+                const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&hset[slot]), ~0ull, mine);
+                if (old == ~0ull) break;
+                if ((uint32_t)(old >> 32) == id) {
+                    atomicMin(reinterpret_cast<unsigned long long*>(&hset[slot]), mine);
+                    break;
+                }
+                slot = (slot + 1u) & hmask;
+            }
+        }
+        __syncthreads();
+        const bool nw = ins && hset[slot] == mine;
+        const uint64_t bal = __ballot(nw);
+        const int rank = __popcll(bal & lanemask_lt());
+        if (nw && M + rank < a.cap) cids[M + rank] = id;
+        M = min(a.cap, M + (int)__popcll(bal));
+    }
+    __syncthreads();
+    return M;
+}
+
 // Early-stop search (cap <= 256), one wave per patch.
 //  1. Candidates: the concatenation of the L bins is read 64 positions at a
 //     time; an LDS hash set of the IDs seen so far (open addressing, atomic
@@ -669,99 +751,25 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
     __shared__ int32_t smark[64];          // table whose bin starts at a position of the current chunk, or -1
     __shared__ uint64_t srank[24];        // ranked keys, then their candidate indices
     const int lane = threadIdx.x;
-    const int L = a.L, D = a.D;
-    const int hsz = a.hsz;
-    const uint32_t hmask = (uint32_t)hsz - 1u;
-    const int hshift = 32 - __builtin_ctz((unsigned)hsz);
+    const int D = a.D;
     const int ri = lane & 15, kb = lane >> 4;   // MFMA layout
 
     {
         const int q = xcd_block();
         if (q >= a.Q) return;
-        uint32_t off = 0, cnt = 0;
-        if (lane < L) {
-            const uint2 b = a.bins[(int64_t)lane * a.Q + q];
-            off = b.x;
-            cnt = b.y;
-        }
-        const int T = wave_sum_i32((int)cnt);
-        // bins concatenated in table order: position i of bin l is entry
-        // i - start_l of that bin
-        const int start = wave_incl_scan((int)cnt) - (int)cnt;
-        if (lane < L) sbase[lane] = (int64_t)lane * a.N + off - start;
-        for (int i = lane; i < hsz; i += 64) hset[i] = ~0ull;
         for (int i = lane; i < 128; i += 64) sq[i] = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
         // the coded query y^ = s_q (h + l / 128): int8 codes h and l, then
-        // s_q, |y^|^2 and rho_q >= |y^ - Phi q| (none in the candidates-only form)
-        const float* qr = a.qrot ? a.qrot + (int64_t)q * kRotStride : nullptr;
-        float s_q = 0.0f, qn2 = 0.0f, rho_q = 0.0f;
-        if (qr) {
-            s_q = qr[32];
-            qn2 = qr[33];
-            rho_q = qr[34];
-        }
-        __syncthreads();
+        // s_q, |y^|^2 and rho_q >= |y^ - Phi q|
+        const float* qr = a.qrot + (int64_t)q * kRotStride;
+        const float s_q = qr[32], qn2 = qr[33], rho_q = qr[34];
 
         // ---- 1. candidates, first occurrences in order, up to cap
-        int M = 0;
-        int carry = 0;   // table of the position before the chunk
-        for (int base = 0; base < T && M < a.cap; base += 64) {
-            const int i = base + lane;
-            const bool valid = i < T;
-            // the table of each position: the last nonempty bin starting at
-            // or before it (the bins starting inside the chunk mark their
-            // first position)
-            smark[lane] = -1;
-            __syncthreads();
-            const int ps = start - base;
-            if (lane < L && cnt > 0 && ps >= 0 && ps < 64) smark[ps] = lane;
-            __syncthreads();
-            const uint64_t starts = __ballot(smark[lane] >= 0);
-            const uint64_t below = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-            const int tbl = below ? smark[63 - __builtin_clzll(below)] : carry;
-            carry = __builtin_amdgcn_readlane(tbl, 63);
-            uint32_t id = 0xFFFFFFFFu;
-            if (valid) id = a.tids[sbase[tbl] + i];
-            uint32_t slot = (id * 0x9E3779B1u) >> hshift;
-            bool found = false;
-            if (valid) {
-                for (;;) {
-                    const uint64_t v = hset[slot];
-                    if ((uint32_t)(v >> 32) == id) {
-                        found = true;
-                        break;
-                    }
-                    if (v == ~0ull) break;
-                    slot = (slot + 1u) & hmask;
-                }
-            }
-            const bool ins = valid && !found;
-            const uint64_t mine = ((uint64_t)id << 32) | (uint32_t)lane;
-            if (ins) {
-                for (;;) {
-                    const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&hset[slot]), ~0ull, mine);
-                    if (old == ~0ull) break;
-                    if ((uint32_t)(old >> 32) == id) {
-                        atomicMin(reinterpret_cast<unsigned long long*>(&hset[slot]), mine);
-                        break;
-                    }
-                    slot = (slot + 1u) & hmask;
-                }
-            }
-            __syncthreads();
-            const bool nw = ins && hset[slot] == mine;
-            const uint64_t bal = __ballot(nw);
-            const int rank = __popcll(bal & lanemask_lt());
-            if (nw && M + rank < a.cap) cids[M + rank] = id;
-            M = min(a.cap, M + (int)__popcll(bal));
-        }
-        __syncthreads();
+        const int M = cap_union(a, q, hset, cids, sbase, smark);
         if (a.dump) {
             wave_sort_u32(cids, M);
             for (int i = lane; i < M && i < a.dump_cap; i += 64) a.dump[(int64_t)q * a.dump_cap + i] = (int32_t)cids[i];
         }
         if (lane == 0) a.out_ncand[q] = M;
-        if (a.cand_only) return;
 
         // ---- 2. screen lower bounds, exact distances of the K lowest, U_K
         int Mr = M;
@@ -911,6 +919,25 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
             write_gram<GT>(a, q, sq, cids, cdist, nA, Kp, oid, reinterpret_cast<GT*>(hset), slot);
         __syncthreads();
     }
+}
+
+// Step 1 of the early-stop search alone (the candidates-only form): M into
+// out_ncand and the dump, ascending, when asked. Few registers, so more
+// waves per SIMD hide the dependent reads of the bins.
+__global__ __launch_bounds__(64, 12) void k_union_cap(SearchArgs a) {
+    extern __shared__ uint64_t hset[];
+    uint32_t* cids = reinterpret_cast<uint32_t*>(hset + a.hsz);
+    __shared__ int64_t sbase[kMaxL];
+    __shared__ int32_t smark[64];
+    const int lane = threadIdx.x;
+    const int q = xcd_block();
+    if (q >= a.Q) return;
+    const int M = cap_union(a, q, hset, cids, sbase, smark);
+    if (a.dump) {
+        wave_sort_u32(cids, M);
+        for (int i = lane; i < M && i < a.dump_cap; i += 64) a.dump[(int64_t)q * a.dump_cap + i] = (int32_t)cids[i];
+    }
+    if (lane == 0) a.out_ncand[q] = M;
 }
 
 // Union search without early stop: all IDs of the L bins are gathered,
@@ -1150,6 +1177,11 @@ static void launch_cap_n(const SearchArgs& a, int grid, size_t lds, hipStream_t 
 // held in registers from one patch to the next
 static void launch_cap(const SearchArgs& a, hipStream_t st) {
     const int grid = round_grid8(a.Q);
+    if (a.cand_only) {
+        const size_t lu = (size_t)a.hsz * sizeof(uint64_t) + (size_t)a.cp * sizeof(uint32_t);
+        hipLaunchKernelGGL(k_union_cap, dim3(grid), dim3(64), lu, st, a);
+        return;
+    }
     const size_t lds = (size_t)a.hsz * sizeof(uint64_t) + 2 * (size_t)a.cp * sizeof(uint32_t);
     if (a.cap <= 128) launch_cap_n<2>(a, grid, lds, st);
     else launch_cap_n<4>(a, grid, lds, st);
