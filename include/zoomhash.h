@@ -289,7 +289,9 @@ zh_status zh_knn_t(zh_ctx* ctx, int t);
  * features. zh_get_results then reports l1 distances (rounded to fp32) in
  * place of squared l2; zh_lle_weights and zh_reconstruct use the new
  * neighbours. Needs the early stop (query option cap > 0, else
- * ZH_EUNSUPPORTED); runs the candidate search again. */
+ * ZH_EUNSUPPORTED); forms the candidate lists again (the union step of the
+ * search alone). The counters of zh_stats then cover this call only (the
+ * search's truncation count stays 0). */
 zh_status zh_knn_l1(zh_ctx* ctx);
 
 /* LLE weights of every patch (Section 4.2, Eq. LinSys): minimise

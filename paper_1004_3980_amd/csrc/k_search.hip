@@ -758,13 +758,13 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
         const int q = xcd_block();
         if (q >= a.Q) return;
         for (int i = lane; i < 128; i += 64) sq[i] = i < D ? a.qfeat[(int64_t)q * D + i] : 0.0f;
+
+        // ---- 1. candidates, first occurrences in order, up to cap
+        const int M = cap_union(a, q, hset, cids, sbase, smark);
         // the coded query y^ = s_q (h + l / 128): int8 codes h and l, then
         // s_q, |y^|^2 and rho_q >= |y^ - Phi q|
         const float* qr = a.qrot + (int64_t)q * kRotStride;
         const float s_q = qr[32], qn2 = qr[33], rho_q = qr[34];
-
-        // ---- 1. candidates, first occurrences in order, up to cap
-        const int M = cap_union(a, q, hset, cids, sbase, smark);
         if (a.dump) {
             wave_sort_u32(cids, M);
             for (int i = lane; i < M && i < a.dump_cap; i += 64) a.dump[(int64_t)q * a.dump_cap + i] = (int32_t)cids[i];
