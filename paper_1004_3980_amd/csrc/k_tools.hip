@@ -267,7 +267,8 @@ __global__ __launch_bounds__(64) void k_knn_rank(int Q, int Drt, int K, int cap,
     __shared__ int sid[kL1Chunk];
     const int D = DT ? DT : Drt;
     const int lane = threadIdx.x;
-    const int q = blockIdx.x;
+    const int q = xcd_block();
+    if (q >= Q) return;
     const int M = min(ncand[q], cap);
     const int st = DT ? kSt : (D | 1);
     for (int i = lane; i < D; i += 64) sq[i] = (double)qfeat[(int64_t)q * D + i];
@@ -398,7 +399,8 @@ __global__ __launch_bounds__(64) void k_knn_rank_rows(int Q, int K, int cap, con
     constexpr int NCH = kL1Chunk * kL1PerLane / 64;
     __shared__ double sq[DT];
     const int lane = threadIdx.x;
-    const int q = blockIdx.x;
+    const int q = xcd_block();
+    if (q >= Q) return;
     const int M = min(ncand[q], cap);
     for (int i = lane; i < DT; i += 64) sq[i] = (double)qfeat[(int64_t)q * DT + i];
     __syncthreads();
@@ -466,20 +468,325 @@ __global__ __launch_bounds__(64) void k_knn_rank_rows(int Q, int K, int cap, con
     if (lane == 0) out_m[q] = m;
 }
 
+// The l1 screen rows, one thread an entry. Any lo and step give valid
+// bounds, since eps is measured against the very values fmaf(step, u, lo)
+// the ranking forms; the row's minimum and range / 255 keep eps small. eps is
+// summed in FP64 and rounded up with a margin of 2^-20 relative, which covers
+// that sum's own rounding and the fp32 rounding of the bounds formed from it.
+__global__ __launch_bounds__(256) void k_l1_screen_rows(const float* __restrict__ xf, int64_t n,
+                                                      uint8_t* __restrict__ l1s) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const float4* x4 = reinterpret_cast<const float4*>(xf + r * kL1sDim);
+    float x[kL1sDim];
+#pragma unroll
+    for (int t = 0; t < kL1sDim / 4; ++t) {
+        const float4 v = x4[t];
+        x[4 * t] = v.x;
+        x[4 * t + 1] = v.y;
+        x[4 * t + 2] = v.z;
+        x[4 * t + 3] = v.w;
+    }
+    float lo = x[0], hi = x[0];
+#pragma unroll
+    for (int i = 1; i < kL1sDim; ++i) {
+        lo = fminf(lo, x[i]);
+        hi = fmaxf(hi, x[i]);
+    }
+    float step = (hi - lo) * (1.0f / 255.0f);
+    if (!(step > 0.0f) || !(step < INFINITY)) step = 0.0f;
+    uint32_t w[kL1sBytes / 4];
+#pragma unroll
+    for (int i = 0; i < kL1sBytes / 4; ++i) w[i] = 0u;
+    double eps = 0.0;
+#pragma unroll
+    for (int i = 0; i < kL1sDim; ++i) {
+        float u = step > 0.0f ? rintf((x[i] - lo) / step) : 0.0f;
+        u = fminf(fmaxf(u, 0.0f), 255.0f);
+        eps += fabs((double)x[i] - (double)fmaf(step, u, lo));
+        w[i >> 2] |= (uint32_t)u << (8 * (i & 3));
+    }
+    const double eu = eps * (1.0 + 0x1p-20);
+    float ef = (float)eu;
+    if ((double)ef < eu) ef = nextafterf(ef, INFINITY);
+    if (!(ef >= 0.0f)) ef = INFINITY;   // a non-finite feature: bounds that prune nothing
+    constexpr int t0 = kL1sTail / 4;
+    w[t0] = __float_as_uint(lo);
+    w[t0 + 1] = __float_as_uint(step);
+    w[t0 + 2] = __float_as_uint(ef);
+    uint4* out = reinterpret_cast<uint4*>(l1s + r * kL1sBytes);
+#pragma unroll
+    for (int t = 0; t < kL1sBytes / 16; ++t) out[t] = make_uint4(w[4 * t], w[4 * t + 1], w[4 * t + 2], w[4 * t + 3]);
+}
+
+hipError_t launch_l1_screen_rows(const float* xf, int64_t n, uint8_t* l1s, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if ((reinterpret_cast<uintptr_t>(xf) & 15) || (reinterpret_cast<uintptr_t>(l1s) & 15)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_l1_screen_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xf, n, l1s);
+    return hipGetLastError();
+}
+
+// K nearest under l1 with the screen (D = 100). One wave a patch:
+//  1. A = sum_i |q_i - fmaf(step, u_i, lo)| in fp32 from the candidate's
+//     128-byte screen row; with eps = ||x - x~||_1 the triangle inequality
+//     puts its l1 distance in [A - eps, A + eps]. An fp32 sum of 100
+//     non-negative terms, in any order, is within 101 u A of its exact value,
+//     so the bounds widen A by 2^-15 relative: lb = fmaf(A, 1 - 2^-15, -eps),
+//     ub = fmaf(A, 1 + 2^-15, eps), each rounded once. Lane j takes candidate
+//     j of a chunk of 64; a last chunk of at most 8 candidates is spread over
+//     8 lanes each, one 16-byte segment of the row a lane.
+//  2. tau = the K-th smallest ub, by binary search over the bit patterns of
+//     the (non-negative) bounds with ballot counts: K candidates lie within
+//     tau.
+//  3. A candidate with lb > tau (1 + 2^-20) is farther than those K even
+//     after the FP64 rounding of every distance, so it cannot be among the K
+//     nearest in (distance, ID) order; the others survive, compacted in LDS.
+//  4. The survivors' exact distances, summed in index order in FP64 as the
+//     unscreened kernels do; with at most 64 survivors each one's rank in
+//     (distance, ID) order is counted against all the others (IDs are
+//     distinct), else K rounds of wave minimum pick them.
+// With M <= K candidates nothing is screened.
+__global__ __launch_bounds__(64) void k_knn_l1_screened(int Q, int K, int cap, const float* __restrict__ qfeat,
+                                                      const float* __restrict__ xf, const uint8_t* __restrict__ l1s,
+                                                      const int32_t* __restrict__ cand,
+                                                      const int32_t* __restrict__ ncand, int32_t* __restrict__ out_ids,
+                                                      float* __restrict__ out_d, int32_t* __restrict__ out_m) {
+    constexpr int DT = kL1sDim, D4 = DT / 4, NCH = kRankMaxCand / 64;
+    constexpr int kSeg = (kL1sTail + 12 + 15) / 16;   // 16-byte loads that hold the codes and the tail
+    static_assert(kSeg <= 8 && kL1sTail % 16 == 4, "codes, then lo, step, eps in the last 16-byte load");
+    __shared__ double sq[DT];
+    __shared__ float4 sqf[D4];
+    __shared__ int sid[kRankMaxCand];
+    const int lane = threadIdx.x;
+    const int q = xcd_block();
+    if (q >= Q) return;
+    const int M = min(ncand[q], cap);
+    const int32_t* cq = cand + (int64_t)q * cap;
+    for (int i = lane; i < DT; i += 64) {
+        const float v = qfeat[(int64_t)q * DT + i];
+        sq[i] = (double)v;
+        reinterpret_cast<float*>(sqf)[i] = v;
+    }
+    int ns = 0;
+    if (M > K) {
+        __syncthreads();
+        uint32_t ubb[NCH];   // bit patterns of the upper bounds; 0xFFFFFFFF: no candidate
+        float lb[NCH];
+        int idc[NCH];
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+            ubb[u] = 0xFFFFFFFFu;
+            lb[u] = INFINITY;
+            idc[u] = 0;
+            const int base = 64 * u;
+            if (base >= M) continue;
+            const int r = M - base;
+            float A = 0.0f, lo = 0.0f, st = 0.0f, e = 0.0f;
+            bool own = false;   // this lane reports the chunk's candidate
+            int id = 0;
+            if (r > 8) {
+                if (lane < r) {
+                    id = cq[base + lane];
+                    own = true;
+                    const uint4* row = reinterpret_cast<const uint4*>(l1s + (size_t)id * kL1sBytes);
+                    uint4 v[kSeg];
+#pragma unroll
+                    for (int t = 0; t < kSeg; ++t) v[t] = row[t];
+                    const uint32_t* wv = reinterpret_cast<const uint32_t*>(v);
+                    lo = __uint_as_float(wv[kL1sTail / 4]);
+                    st = __uint_as_float(wv[kL1sTail / 4 + 1]);
+                    e = __uint_as_float(wv[kL1sTail / 4 + 2]);
+#pragma unroll
+                    for (int t = 0; t < D4; ++t) {
+                        const float4 qv = sqf[t];
+                        const uint32_t cw = wv[t];
+                        A += fabsf(qv.x - fmaf(st, (float)(cw & 255u), lo));
+                        A += fabsf(qv.y - fmaf(st, (float)((cw >> 8) & 255u), lo));
+                        A += fabsf(qv.z - fmaf(st, (float)((cw >> 16) & 255u), lo));
+                        A += fabsf(qv.w - fmaf(st, (float)(cw >> 24), lo));
+                    }
+                }
+            } else {
+                // 8 lanes a candidate, lane seg of the group on codes 16 seg .. 16 seg + 15
+                const int g = lane >> 3, seg = lane & 7;
+                if (g < r) {
+                    id = cq[base + g];
+                    own = seg == 0;
+                    const uint4* row = reinterpret_cast<const uint4*>(l1s + (size_t)id * kL1sBytes);
+                    const uint4 tl = row[kSeg - 1];
+                    lo = __uint_as_float(tl.y);
+                    st = __uint_as_float(tl.z);
+                    e = __uint_as_float(tl.w);
+                    if (seg < kSeg) {
+                        const uint4 v = row[seg];
+                        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            if (4 * seg + t >= D4) break;
+                            const float4 qv = sqf[4 * seg + t];
+                            const uint32_t cw = wv[t];
+                            A += fabsf(qv.x - fmaf(st, (float)(cw & 255u), lo));
+                            A += fabsf(qv.y - fmaf(st, (float)((cw >> 8) & 255u), lo));
+                            A += fabsf(qv.z - fmaf(st, (float)((cw >> 16) & 255u), lo));
+                            A += fabsf(qv.w - fmaf(st, (float)(cw >> 24), lo));
+                        }
+                    }
+                }
+                A += __shfl_xor(A, 1);
+                A += __shfl_xor(A, 2);
+                A += __shfl_xor(A, 4);
+            }
+            if (own) {
+                float l = fmaf(A, 1.0f - 0x1p-15f, -e);
+                float h = fmaf(A, 1.0f + 0x1p-15f, e);
+                if (!(h >= 0.0f)) {   // non-finite: keep the candidate, set no threshold by it
+                    l = 0.0f;
+                    h = INFINITY;
+                }
+                lb[u] = l;
+                ubb[u] = __float_as_uint(h);
+                idc[u] = id;
+            }
+        }
+        // 2. tau: the smallest bit pattern with at least K upper bounds at or below it
+        uint32_t blo = 0u, bhi = 0x7F800000u;
+        while (blo < bhi) {
+            const uint32_t mid = blo + ((bhi - blo) >> 1);
+            int cnt = 0;
+#pragma unroll
+            for (int u = 0; u < NCH; ++u) {
+                if (64 * u >= M) break;
+                cnt += __popcll(__ballot(ubb[u] <= mid));
+            }
+            if (cnt >= K) bhi = mid;
+            else blo = mid + 1u;
+        }
+        const float thr = __uint_as_float(blo) * (1.0f + 0x1p-20f);
+        // 3. survivors, compacted in candidate order
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+            if (64 * u >= M) break;
+            const bool keep = ubb[u] != 0xFFFFFFFFu && !(lb[u] > thr);
+            const uint64_t bm = __ballot(keep);
+            if (keep) sid[ns + __popcll(bm & ((1ull << lane) - 1ull))] = idc[u];
+            ns += __popcll(bm);
+        }
+    } else {
+        for (int j = lane; j < M; j += 64) sid[j] = cq[j];
+        ns = M;
+    }
+    __syncthreads();
+    // 4. exact distances of the survivors
+    double d[NCH];
+    int id[NCH];
+#pragma unroll
+    for (int u = 0; u < NCH; ++u) {
+        d[u] = INFINITY;
+        id[u] = 0x7FFFFFFF;
+        const int j = 64 * u + lane;
+        if (64 * u < ns && j < ns) {
+            const int myid = sid[j];
+            const float4* row = reinterpret_cast<const float4*>(xf) + (int64_t)myid * D4;
+            double acc = 0.0;
+            constexpr int H = (D4 + 1) / 2;   // the row in two halves of loads in flight
+#pragma unroll
+            for (int h0 = 0; h0 < D4; h0 += H) {
+                float4 x[H];
+#pragma unroll
+                for (int t = 0; t < H; ++t)
+                    if (h0 + t < D4) x[t] = row[h0 + t];
+#pragma unroll
+                for (int t = 0; t < H; ++t) {
+                    if (h0 + t >= D4) break;
+                    const float xv[4] = {x[t].x, x[t].y, x[t].z, x[t].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc = acc + fabs(sq[4 * (h0 + t) + e] - (double)xv[e]);
+                }
+            }
+            d[u] = acc;
+            id[u] = myid;
+        }
+    }
+    const int m = min(K, M);
+    if (ns <= 64) {
+        // rank of survivor lane among all survivors in (distance, ID) order
+        const int64_t dbits = __double_as_longlong(d[0]);
+        const int dlo = (int)(dbits & 0xFFFFFFFF), dhi = (int)(dbits >> 32);
+        int rank = 0;
+        for (int t = 0; t < ns; ++t) {
+            const int tlo = __builtin_amdgcn_readlane(dlo, t), thi = __builtin_amdgcn_readlane(dhi, t);
+            const int tid = __builtin_amdgcn_readlane(id[0], t);
+            const double dt = __longlong_as_double(((int64_t)thi << 32) | (int64_t)(uint32_t)tlo);
+            rank += (dt < d[0] || (dt == d[0] && tid < id[0])) ? 1 : 0;
+        }
+        if (lane < ns && rank < m) {
+            out_ids[(int64_t)q * K + rank] = id[0];
+            out_d[(int64_t)q * K + rank] = (float)d[0];
+        }
+    } else {
+        for (int k = 0; k < m; ++k) {
+            double bd = d[0];
+            int bi = id[0];
+#pragma unroll
+            for (int u = 1; u < NCH; ++u)
+                if (d[u] < bd || (d[u] == bd && id[u] < bi)) {
+                    bd = d[u];
+                    bi = id[u];
+                }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double od = __shfl_xor(bd, o);
+                const int oi = __shfl_xor(bi, o);
+                if (od < bd || (od == bd && oi < bi)) {
+                    bd = od;
+                    bi = oi;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NCH; ++u)
+                if (id[u] == bi) {
+                    d[u] = INFINITY;
+                    id[u] = 0x7FFFFFFF;
+                }
+            if (lane == 0) {
+                out_ids[(int64_t)q * K + k] = bi;
+                out_d[(int64_t)q * K + k] = (float)bd;
+            }
+        }
+    }
+    if (lane >= m && lane < K) {
+        out_ids[(int64_t)q * K + lane] = -1;
+        out_d[(int64_t)q * K + lane] = 0.0f;
+    }
+    if (lane == 0) out_m[q] = m;
+}
+
+hipError_t launch_knn_l1_screened(int Q, int K, int cap, const float* qfeat, const float* xf, const uint8_t* l1s,
+                                  const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
+                                  hipStream_t st) {
+    if (Q == 0) return hipSuccess;
+    if (cap < 1 || cap > kRankMaxCand || K < 1 || K > kMaxK) return hipErrorInvalidValue;
+    if ((reinterpret_cast<uintptr_t>(xf) & 15) || (reinterpret_cast<uintptr_t>(l1s) & 15)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_knn_l1_screened, dim3(round_grid8(Q)), dim3(64), 0, st, Q, K, cap, qfeat, xf, l1s, cand,
+                       ncand, ids, d, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_knn_rank(int Q, int D, int K, int cap, bool l1, const float* qfeat, const float* xf,
                            const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
                            hipStream_t st) {
     if (Q == 0) return hipSuccess;
     if (cap < 1 || cap > kL1Chunk * kL1PerLane || K < 1 || K > kMaxK || D < 1 || D > kL1MaxD) return hipErrorInvalidValue;
+    const int grid = round_grid8(Q);   // patches in contiguous runs per XCD: neighbours share candidates in L2
 #define ZH_RANK(DT, M1) \
-    hipLaunchKernelGGL((k_knn_rank<DT, M1>), dim3(Q), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m)
+    hipLaunchKernelGGL((k_knn_rank<DT, M1>), dim3(grid), dim3(64), 0, st, Q, D, K, cap, qfeat, xf, cand, ncand, ids, d, m)
     if (D == 100) {
         const bool al = (reinterpret_cast<uintptr_t>(xf) & 15) == 0;
         if (al && l1)
-            hipLaunchKernelGGL((k_knn_rank_rows<100, true>), dim3(Q), dim3(64), 0, st, Q, K, cap, qfeat, xf, cand, ncand,
+            hipLaunchKernelGGL((k_knn_rank_rows<100, true>), dim3(grid), dim3(64), 0, st, Q, K, cap, qfeat, xf, cand, ncand,
                                ids, d, m);
         else if (al)
-            hipLaunchKernelGGL((k_knn_rank_rows<100, false>), dim3(Q), dim3(64), 0, st, Q, K, cap, qfeat, xf, cand,
+            hipLaunchKernelGGL((k_knn_rank_rows<100, false>), dim3(grid), dim3(64), 0, st, Q, K, cap, qfeat, xf, cand,
                                ncand, ids, d, m);
         if (al) return hipGetLastError();
     }

@@ -55,6 +55,8 @@ struct Dict {
     float rot_c1 = 0.f;           // error-bound coefficient of the query rotation
     std::vector<float> h_alpha, h_beta;
     uint64_t feat_hash = 0;       // content hash of the features the tables were built on
+    Buf l1s;                      // [n, kL1sBytes] l1 screen rows (D = 100), formed at the first zh_knn_l1
+    bool l1s_ok = false;          // l1s holds the rows of the current features
 };
 
 
@@ -522,6 +524,7 @@ void zh_destroy(zh_ctx* c) {
         release(c, d.hi); release(c, d.lo); release(c, d.alpha); release(c, d.beta); release(c, d.bc0[0]); release(c, d.bc0[1]);
         release(c, d.ahi); release(c, d.alo); release(c, d.bw); release(c, d.dir); release(c, d.dfilt); release(c, d.tids);
         release(c, d.sc); release(c, d.phi_hi); release(c, d.phi_lo); release(c, d.kmul); release(c, d.xf);
+        release(c, d.l1s);
     }
     for (int st = 0; st < ZH_T_COUNT; ++st)
         for (int i = 0; i < zh_ctx::kEv; ++i)
@@ -655,6 +658,7 @@ zh_status zh_build_tables(zh_ctx* c, const zh_dictionary* dict, int L, int k, fl
     TRY(set_device(c));
     Dict& d = c->dicts[dict->scale];
     d.valid = false;
+    d.l1s_ok = false;
     c->stage = 0;
     ++c->gen;   // the tables and parameters a captured batch graph baked in change
     const int64_t n = dict->n;
@@ -926,6 +930,7 @@ zh_status zh_load_tables(zh_ctx* c, const zh_dictionary* dict, const char* path)
         return fail(c, ZH_EINVAL, "zh_load_tables: the dictionary features differ from those the tables were built on");
     Dict& d = c->dicts[dict->scale];
     d.valid = false;
+    d.l1s_ok = false;
     c->stage = 0;
     ++c->gen;
     d.scale = h.scale;
@@ -2095,13 +2100,25 @@ zh_status zh_knn_l1(zh_ctx* c) {
     Dict& d = c->dicts[c->qscale];
     TRY(ensure(c, c->l1cand, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1) * cap));
     TRY(clear_counters(c));
+    // the l1 screen of the dictionary (D = 100), once per set of features
+    const bool screened = d.D == kL1sDim && cap <= kRankMaxCand;
+    if (screened && !d.l1s_ok) {
+        TRY(ensure(c, d.l1s, (size_t)kL1sBytes * (size_t)d.n));
+        HIPCHK(c, launch_l1_screen_rows(P<float>(d.xf), d.n, P<uint8_t>(d.l1s), c->stream));
+        d.l1s_ok = true;
+    }
     // the candidate lists of the last query (the union runs again and dumps them)
     TRY(run_search(c, d, P<int32_t>(c->l1cand), cap, true));
     {
         StageTimer t(c, ZH_T_SEARCH);
-        HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, cap, true, P<float>(c->qfeat), P<float>(d.xf),
-                                  P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids), P<float>(c->d2),
-                                  P<int32_t>(c->m), c->stream));
+        if (screened)
+            HIPCHK(c, launch_knn_l1_screened((int)c->Q, c->qK, cap, P<float>(c->qfeat), P<float>(d.xf),
+                                             P<uint8_t>(d.l1s), P<int32_t>(c->l1cand), P<int32_t>(c->ncand),
+                                             P<int32_t>(c->ids), P<float>(c->d2), P<int32_t>(c->m), c->stream));
+        else
+            HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, cap, true, P<float>(c->qfeat), P<float>(d.xf),
+                                      P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids),
+                                      P<float>(c->d2), P<int32_t>(c->m), c->stream));
     }
     c->gram_ready = false;   // the Gram matrices of the new neighbours are formed by zh_lle_weights
     c->stage = 1;
@@ -2127,7 +2144,8 @@ zh_status zh_stats(zh_ctx* c, zh_stats_t* out) {
     out->truncated = h[C_TRUNC];
     uint64_t db = 0;
     for (const Dict& d : c->dicts)
-        db += d.hi.bytes + d.lo.bytes + d.dir.bytes + d.dfilt.bytes + d.tids.bytes + d.alpha.bytes + d.ahi.bytes + d.alo.bytes;
+        db += d.hi.bytes + d.lo.bytes + d.dir.bytes + d.dfilt.bytes + d.tids.bytes + d.alpha.bytes + d.ahi.bytes + d.alo.bytes +
+              d.l1s.bytes;
     out->dict_bytes = db;
     return ZH_OK;
 }
