@@ -30,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# --metric: the form of GpuWorkload.zoom that measures it
+ZOOM_METRIC = {"l2": "l2", "l1": "l1q", "l1-rerank": "l1"}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -59,6 +61,19 @@ def search_bytes(ncand, nsurv, wl, gram_bytes):
     D, L, K = wl.D, wl.L, wl.K
     per_q = 8 * L + 4 * D + 140 + 8 * K + 12 + 36 * gram_bytes
     return int(len(M) * per_q + (M * (4 + 64)).sum() + (S * 4 * D).sum())
+
+
+def l1_rank_bytes(ncand, nsurv, wl, cap):
+    """Algorithmic HBM bytes of one launch of the l1 ranking with the screen
+    (D = 100). Per patch: its feature row (4D B), the output (K ids, K
+    distances, count, survivor count). Per candidate: its ID (4 B), and,
+    where there are more than K candidates, its screen row (D codes, three
+    floats). Per survivor: its fp32 feature row (4D B)."""
+    M = np.minimum(ncand.astype(np.int64), cap)
+    S = nsurv.astype(np.int64)
+    D, K = wl.D, wl.K
+    per_q = 4 * D + 8 * K + 8
+    return int(len(M) * per_q + (4 * M).sum() + ((D + 12) * M * (M > K)).sum() + (S * 4 * D).sum())
 
 
 def traffic_from_profile(form):
@@ -249,8 +264,9 @@ def main():
                     help="screened/exact: the 1024^2 workload (the headline line); batched: 64 images "
                          "at x2/x3 in one captured graph against per-image launches; diff: forward and "
                          "backward of the differentiation workload")
-    ap.add_argument("--metric", choices=["l2", "l1"], default="l2",
-                    help="screened/exact: neighbours by squared l2 (the path) or re-ranked under l1")
+    ap.add_argument("--metric", choices=["l2", "l1", "l1-rerank"], default="l2",
+                    help="screened/exact: neighbours by squared l2 (the path), by l1 (the query ranks under "
+                         "l1) or re-ranked under l1 after the l2 query (zh_knn_l1)")
     ap.add_argument("--scale", type=int, default=0,
                     help="screened/exact: run the workload at this zoom factor (1..4) instead of its own")
     ap.add_argument("--crop", type=int, default=256, help="LR crop side for quality and the CPU leg")
@@ -309,14 +325,14 @@ def main():
     def timed(form, steps, warmup, stages=None):
         set_form(form)
         for _ in range(warmup):
-            g.zoom(metric=args.metric)
+            g.zoom(metric=ZOOM_METRIC[args.metric])
         torch.cuda.synchronize()
         g.ctx.get_timing()
         g.ctx.set_timing(True, stages)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            g.zoom(metric=args.metric)
+            g.zoom(metric=ZOOM_METRIC[args.metric])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         g.ctx.set_timing(False)
@@ -339,6 +355,12 @@ def main():
 
     # dominant kernel: the candidate search
     dom = max(("hash", "probe", "search", "lle", "synth", "blend"), key=lambda k: ms_stage[k])
+    if args.metric != "l2":
+        # the l1 ranking: its algorithmic bytes, and the survivors of its screen
+        M = np.minimum(res["ncand"], wl.cap)
+        extra_l1 = {"mean_candidates": float(M.mean()), "mean_survivors": float(res["nsurv"].mean()),
+                    "rank_bytes": l1_rank_bytes(res["ncand"], res["nsurv"], wl, wl.cap)}
+        log(f"[bench] l1 ranking: {json.dumps(extra_l1)}")
     sb = search_bytes(res["ncand"], res["nsurv"], wl, 4 if args.form == "screened" else 8)
     ach = sb / (ms_stage["search"] * 1e-3) / 1e9
     traffic = traffic_from_profile(args.form) if own_scale and args.metric == "l2" else None
@@ -348,6 +370,10 @@ def main():
             "dominant_stage": dom}
     if own_scale and args.metric == "l2" and args.form == "screened":
         roof.update(issue_from_profile("search_screened", "k_search.hip", ms_stage["search"]))
+    if args.metric != "l2":
+        # the search stage holds the union and the l1 ranking together: no one
+        # kernel's duration to divide by (the l2 line carries the roofline)
+        roof = None
     # the projection of the hash (Eq. hash_fn) against the bf16 matrix-core peak:
     # useful flops 2 Q D L k over the hash stage (projection, codes, keys, FP64 fixes)
     hflop = 2.0 * Q * wl.D * wl.L * wl.k
@@ -392,6 +418,7 @@ def main():
             raise SystemExit("batched outputs differ from the images run one by one")
 
     extra = {"ms_per_stage": {k: round(v, 4) for k, v in ms_stage.items()},
+             **({"l1_ranking": extra_l1} if args.metric != "l2" else {}),
              "hash_roofline": hash_roof,
              "backprojection_ms": round(bp_ms, 3), "bp_iters": wl.bp_iters,
              "value_with_backprojection": Q / (dt / args.steps + bp_ms * 1e-3),
@@ -462,7 +489,8 @@ def main():
                                f"L={wl.L} k={wl.k} w={wl.w:g} K={wl.K}, early stop {wl.cap}, "
                                f"form {args.form}" + (f" (int8 principal-coordinate screen, at most {wl.rerank} "
                                                       "exact fp32 rows)" if args.form == "screened" else "")
-                               + (", neighbours re-ranked under l1 (zh_knn_l1)" if args.metric == "l1" else ""),
+                               + {"l2": "", "l1": ", neighbours under l1 (query metric l1)",
+                                  "l1-rerank": ", neighbours re-ranked under l1 (zh_knn_l1)"}[args.metric],
                    "patches_per_step": Q, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -248,6 +248,20 @@ typedef struct {
 /* Defaults: cap 0, rerank 0, proj 1, lle_fp64 1. */
 zh_status zh_set_query_opts(zh_ctx* ctx, const zh_query_opts* opts);
 
+/* Distance by which zh_query ranks the candidates (Section 4.1: the Cauchy
+ * hash is sensitive to l1 distances; the LLE objective is squared l2).
+ * ZH_METRIC_L2 (the default): squared l2, as documented at zh_query.
+ * ZH_METRIC_L1: the neighbours are the first min(K, M) early-stop candidates
+ * in (l1 distance, ID) order, exactly those of zh_query under ZH_METRIC_L2
+ * followed by zh_knn_l1, without the l2 ranking; needs the early stop
+ * (query option cap > 0, else zh_query returns ZH_EUNSUPPORTED), the rerank
+ * option does not apply, zh_get_results reports l1 distances, and
+ * zh_run_batch and zh_tune_batch return
+ * ZH_EUNSUPPORTED while it is set. Other values: ZH_EINVAL. Applies to later
+ * calls of zh_query. */
+enum { ZH_METRIC_L2 = 0, ZH_METRIC_L1 = 1 };
+zh_status zh_set_query_metric(zh_ctx* ctx, int metric);
+
 /* ---- the path --------------------------------------------------------- */
 
 /* Section 3.2 and Section 4.2 (query every table, collect the matches, stop
@@ -420,8 +434,10 @@ zh_status zh_get_results(zh_ctx* ctx, int32_t* ids, float* d2, int32_t* m, float
                          int32_t* ncand);
 /* Candidates of each patch of the last zh_query that reached the exact
  * distance pass (after the screen's lower bounds; equal to the candidate
- * count when the screen did not run) into survivors[Q] (device). Early-stop
- * search only (cap > 0); ZH_ESTATE otherwise. */
+ * count when the screen did not run) into survivors[Q] (device); after
+ * zh_knn_l1, or for a query under ZH_METRIC_L1, those that reached the exact
+ * l1 pass (after the l1 screen at D = 100). Early-stop search only
+ * (cap > 0); ZH_ESTATE otherwise. */
 zh_status zh_survivors(zh_ctx* ctx, int32_t* survivors);
 /* Query size of the last zh_query: *Q patches, *D feature dimension. */
 zh_status zh_query_shape(zh_ctx* ctx, int64_t* Q, int32_t* D);

@@ -519,6 +519,17 @@ __global__ __launch_bounds__(256) void k_l1_screen_rows(const float* __restrict_
     for (int t = 0; t < kL1sBytes / 16; ++t) out[t] = make_uint4(w[4 * t], w[4 * t + 1], w[4 * t + 2], w[4 * t + 3]);
 }
 
+__global__ void k_min_i32(int n, const int32_t* __restrict__ in, int cap, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = min(in[i], cap);
+}
+
+hipError_t launch_min_i32(int n, const int32_t* in, int cap, int32_t* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_min_i32, dim3((n + 255) / 256), dim3(256), 0, st, n, in, cap, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_l1_screen_rows(const float* xf, int64_t n, uint8_t* l1s, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if ((reinterpret_cast<uintptr_t>(xf) & 15) || (reinterpret_cast<uintptr_t>(l1s) & 15)) return hipErrorInvalidValue;
@@ -550,7 +561,8 @@ __global__ __launch_bounds__(64) void k_knn_l1_screened(int Q, int K, int cap, c
                                                       const float* __restrict__ xf, const uint8_t* __restrict__ l1s,
                                                       const int32_t* __restrict__ cand,
                                                       const int32_t* __restrict__ ncand, int32_t* __restrict__ out_ids,
-                                                      float* __restrict__ out_d, int32_t* __restrict__ out_m) {
+                                                      float* __restrict__ out_d, int32_t* __restrict__ out_m,
+                                                      int32_t* __restrict__ out_ns) {
     constexpr int DT = kL1sDim, D4 = DT / 4, NCH = kRankMaxCand / 64;
     constexpr int kSeg = (kL1sTail + 12 + 15) / 16;   // 16-byte loads that hold the codes and the tail
     static_assert(kSeg <= 8 && kL1sTail % 16 == 4, "codes, then lo, step, eps in the last 16-byte load");
@@ -676,6 +688,7 @@ __global__ __launch_bounds__(64) void k_knn_l1_screened(int Q, int K, int cap, c
         ns = M;
     }
     __syncthreads();
+    if (out_ns && lane == 0) out_ns[q] = ns;
     // 4. exact distances of the survivors
     double d[NCH];
     int id[NCH];
@@ -763,12 +776,12 @@ __global__ __launch_bounds__(64) void k_knn_l1_screened(int Q, int K, int cap, c
 
 hipError_t launch_knn_l1_screened(int Q, int K, int cap, const float* qfeat, const float* xf, const uint8_t* l1s,
                                   const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
-                                  hipStream_t st) {
+                                  int32_t* ns, hipStream_t st) {
     if (Q == 0) return hipSuccess;
     if (cap < 1 || cap > kRankMaxCand || K < 1 || K > kMaxK) return hipErrorInvalidValue;
     if ((reinterpret_cast<uintptr_t>(xf) & 15) || (reinterpret_cast<uintptr_t>(l1s) & 15)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_knn_l1_screened, dim3(round_grid8(Q)), dim3(64), 0, st, Q, K, cap, qfeat, xf, l1s, cand,
-                       ncand, ids, d, m);
+                       ncand, ids, d, m, ns);
     return hipGetLastError();
 }
 

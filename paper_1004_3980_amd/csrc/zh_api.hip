@@ -82,6 +82,7 @@ struct zh_ctx {
     uint64_t gen = 0;
     Dict dicts[kMaxScale + 1];    // scale 1 .. kMaxScale (index = scale)
     zh_query_opts opts{0, 0, 1, 1};
+    int metric = ZH_METRIC_L2;    // distance of zh_query's neighbour ranking
     // last query
     int stage = 0;                // 0 none, 1 queried, 2 weighted, 3 reconstructed
     int qh = 0, qw = 0, qscale = 0, qK = 0;
@@ -1094,6 +1095,44 @@ zh_status zh_set_query_opts(zh_ctx* c, const zh_query_opts* o) {
     return ZH_OK;
 }
 
+zh_status zh_set_query_metric(zh_ctx* c, int metric) {
+    if (!c) return ZH_EINVAL;
+    if (metric != ZH_METRIC_L2 && metric != ZH_METRIC_L1)
+        return fail(c, ZH_EINVAL, "zh_set_query_metric: ZH_METRIC_L2 or ZH_METRIC_L1");
+    c->metric = metric;
+    return ZH_OK;
+}
+
+// The K nearest of every patch of the current query under l1 (Section 4.1):
+// the early-stop candidate lists (the union step of the search alone), then
+// the ranking, through the l1 screen when D = 100. Needs opts.cap > 0.
+zh_status rank_l1(zh_ctx* c, Dict& d) {
+    const int cap = c->opts.cap;
+    TRY(ensure(c, c->l1cand, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1) * cap));
+    // the l1 screen of the dictionary (D = 100), once per set of features
+    const bool screened = d.D == kL1sDim && cap <= kRankMaxCand;
+    if (screened && !d.l1s_ok) {
+        TRY(ensure(c, d.l1s, (size_t)kL1sBytes * (size_t)d.n));
+        HIPCHK(c, launch_l1_screen_rows(P<float>(d.xf), d.n, P<uint8_t>(d.l1s), c->stream));
+        d.l1s_ok = true;
+    }
+    TRY(ensure(c, c->nsurv, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1)));
+    TRY(run_search(c, d, P<int32_t>(c->l1cand), cap, true));
+    StageTimer t(c, ZH_T_SEARCH);
+    if (screened) {
+        HIPCHK(c, launch_knn_l1_screened((int)c->Q, c->qK, cap, P<float>(c->qfeat), P<float>(d.xf), P<uint8_t>(d.l1s),
+                                         P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids),
+                                         P<float>(c->d2), P<int32_t>(c->m), P<int32_t>(c->nsurv), c->stream));
+    } else {
+        HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, cap, true, P<float>(c->qfeat), P<float>(d.xf),
+                                  P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids), P<float>(c->d2),
+                                  P<int32_t>(c->m), c->stream));
+        // every candidate reaches the exact pass: survivors = min(ncand, cap)
+        HIPCHK(c, launch_min_i32((int)c->Q, P<int32_t>(c->ncand), cap, P<int32_t>(c->nsurv), c->stream));
+    }
+    return ZH_OK;
+}
+
 zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
     if (!c) return ZH_EINVAL;
     if (!lr || h < kPatch || w < kPatch || K < 1 || K > kMaxK)
@@ -1102,6 +1141,8 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
         return fail(c, ZH_ESTATE, "zh_query: no tables built for scale %d", scale);
     if (c->opts.rerank > 0 && c->opts.rerank < K)
         return fail(c, ZH_EINVAL, "zh_query: rerank %d below K %d", c->opts.rerank, K);
+    if (c->metric == ZH_METRIC_L1 && c->opts.cap < 1)
+        return fail(c, ZH_EUNSUPPORTED, "zh_query: the l1 metric needs the early stop (query option cap > 0)");
     const int64_t Q = (int64_t)(h - 4) * (w - 4);
     if (Q >= (1ll << 31) / kMaxK) return fail(c, ZH_EINVAL, "zh_query: image too large");
     TRY(set_device(c));
@@ -1165,7 +1206,12 @@ zh_status zh_query(zh_ctx* c, const float* lr, int h, int w, int scale, int K) {
         StageTimer t(c, ZH_T_PROBE);
         HIPCHK(c, launch_probe(ha, c->stream));
     }
-    TRY(run_search(c, d, nullptr, 0));
+    if (c->metric == ZH_METRIC_L1) {
+        TRY(rank_l1(c, d));
+        c->gram_ready = false;   // no search formed Gram matrices; zh_lle_weights forms them
+    } else {
+        TRY(run_search(c, d, nullptr, 0));
+    }
     c->stage = 1;
     return ZH_OK;
 }
@@ -1561,6 +1607,8 @@ zh_status batch_check(zh_ctx* c, const zh_batch* b) {
         !(b->sigma_s > 0.f) || std::ceil(3.0 * b->sigma_s) > 8.0 || !(b->sigma_r > 0.f))
         return fail(c, ZH_EINVAL, "zh_run_batch: bad K, lambda or back-projection parameters");
     if (c->opts.rerank > 0 && c->opts.rerank < b->K) return fail(c, ZH_EINVAL, "zh_run_batch: rerank below K");
+    if (c->metric != ZH_METRIC_L2)
+        return fail(c, ZH_EUNSUPPORTED, "zh_run_batch: the batched form ranks by squared l2 (query metric l1 set)");
     for (int i = 0; i < b->n_images; ++i) {
         const int s = b->scale[i];
         if (!b->lr[i] || !b->hr_out[i] || b->h[i] < kPatch || b->w[i] < kPatch)
@@ -2094,32 +2142,10 @@ zh_status zh_knn_t(zh_ctx* c, int t) {
 zh_status zh_knn_l1(zh_ctx* c) {
     if (!c) return ZH_EINVAL;
     if (c->stage < 1) return fail(c, ZH_ESTATE, "zh_knn_l1 before zh_query");
-    const int cap = c->opts.cap;
-    if (cap < 1) return fail(c, ZH_EUNSUPPORTED, "zh_knn_l1 needs the early stop (query option cap > 0)");
+    if (c->opts.cap < 1) return fail(c, ZH_EUNSUPPORTED, "zh_knn_l1 needs the early stop (query option cap > 0)");
     TRY(set_device(c));
-    Dict& d = c->dicts[c->qscale];
-    TRY(ensure(c, c->l1cand, sizeof(int32_t) * (size_t)(c->Q > 0 ? c->Q : 1) * cap));
     TRY(clear_counters(c));
-    // the l1 screen of the dictionary (D = 100), once per set of features
-    const bool screened = d.D == kL1sDim && cap <= kRankMaxCand;
-    if (screened && !d.l1s_ok) {
-        TRY(ensure(c, d.l1s, (size_t)kL1sBytes * (size_t)d.n));
-        HIPCHK(c, launch_l1_screen_rows(P<float>(d.xf), d.n, P<uint8_t>(d.l1s), c->stream));
-        d.l1s_ok = true;
-    }
-    // the candidate lists of the last query (the union runs again and dumps them)
-    TRY(run_search(c, d, P<int32_t>(c->l1cand), cap, true));
-    {
-        StageTimer t(c, ZH_T_SEARCH);
-        if (screened)
-            HIPCHK(c, launch_knn_l1_screened((int)c->Q, c->qK, cap, P<float>(c->qfeat), P<float>(d.xf),
-                                             P<uint8_t>(d.l1s), P<int32_t>(c->l1cand), P<int32_t>(c->ncand),
-                                             P<int32_t>(c->ids), P<float>(c->d2), P<int32_t>(c->m), c->stream));
-        else
-            HIPCHK(c, launch_knn_rank((int)c->Q, d.D, c->qK, cap, true, P<float>(c->qfeat), P<float>(d.xf),
-                                      P<int32_t>(c->l1cand), P<int32_t>(c->ncand), P<int32_t>(c->ids),
-                                      P<float>(c->d2), P<int32_t>(c->m), c->stream));
-    }
+    TRY(rank_l1(c, c->dicts[c->qscale]));
     c->gram_ready = false;   // the Gram matrices of the new neighbours are formed by zh_lle_weights
     c->stage = 1;
     return ZH_OK;

@@ -227,12 +227,15 @@ constexpr int kL1sBytes = 128;
 constexpr int kL1sDim = 100;
 constexpr int kL1sTail = kL1sDim;
 hipError_t launch_l1_screen_rows(const float* xf, int64_t n, uint8_t* l1s, hipStream_t st);
+// out[i] = min(in[i], cap), i < n
+hipError_t launch_min_i32(int n, const int32_t* in, int cap, int32_t* out, hipStream_t st);
 // K nearest under l1 of each patch's candidates (D = 100, cap <= 256), the
 // screen pruning those whose lower bound exceeds the K-th smallest upper
-// bound; outputs as launch_knn_rank's
+// bound; outputs as launch_knn_rank's, and (ns non-null) ns[Q] the
+// candidates that reached the exact pass
 hipError_t launch_knn_l1_screened(int Q, int K, int cap, const float* qfeat, const float* xf, const uint8_t* l1s,
                                   const int32_t* cand, const int32_t* ncand, int32_t* ids, float* d, int32_t* m,
-                                  hipStream_t st);
+                                  int32_t* ns, hipStream_t st);
 // K nearest (squared l2, sequential FP64) of each patch's t-of-L candidates,
 // any number of them; counts[Q] the t-of-L counts
 hipError_t launch_knn_tofl(int Q, int L, int64_t N, int t, int D, int K, const uint2* bins, const uint32_t* tids,

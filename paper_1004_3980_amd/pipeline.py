@@ -65,12 +65,21 @@ class GpuWorkload:
 
     def zoom(self, lr=None, K=None, lam=None, out=None, metric="l2"):
         """hash + K-NN + LLE + blend for the test image; returns the HR image.
-        metric "l1": neighbours re-ranked under l1 (needs the early stop);
-        "t=<t>": neighbours among the t-of-L candidates."""
+        metric "l1": neighbours re-ranked under l1 after the l2 query
+        (zh_knn_l1); "l1q": the query itself ranks under l1
+        (zh_set_query_metric), the same neighbours without the l2 ranking
+        (both need the early stop); "t=<t>": neighbours among the t-of-L
+        candidates."""
         wl = self.wl
         lr = self.lr if lr is None else lr
         out = self.hr_out if out is None else out
-        self.ctx.query(lr, lr.shape[0], lr.shape[1], wl.scale, wl.K if K is None else K)
+        if metric == "l1q":
+            self.ctx.set_query_metric("l1")
+        try:
+            self.ctx.query(lr, lr.shape[0], lr.shape[1], wl.scale, wl.K if K is None else K)
+        finally:
+            if metric == "l1q":
+                self.ctx.set_query_metric("l2")
         if metric == "l1":
             self.ctx.knn_l1()
         elif metric.startswith("t="):

@@ -87,6 +87,7 @@ SIGNATURES = {
     "zh_hash": [_V, _I, _V, _I64, _V, _V],
     "zh_hash_noalloc": [_V, _I, _V, _I64, _V, _V],
     "zh_set_query_opts": [_V, ctypes.POINTER(zh_query_opts)],
+    "zh_set_query_metric": [_V, _I],
     "zh_query": [_V, _V, _I, _I, _I, _I],
     "zh_lle_weights": [_V, ctypes.c_double],
     "zh_lle_all": [_V, ctypes.c_double, _V, _V],
@@ -252,6 +253,10 @@ class Context:
     def set_query_opts(self, cap=0, rerank=0, proj=1, lle_fp64=1):
         o = zh_query_opts(cap, rerank, proj, lle_fp64)
         self._chk(self.lib.zh_set_query_opts(self.h, ctypes.byref(o)))
+
+    def set_query_metric(self, metric):
+        """metric: "l2" or "l1" (the ranking of zh_query)."""
+        self._chk(self.lib.zh_set_query_metric(self.h, {"l2": 0, "l1": 1}[metric]))
 
     def query(self, lr, h, w, scale, K):
         self._chk(self.lib.zh_query(self.h, _ptr(lr), h, w, scale, K))

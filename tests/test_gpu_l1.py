@@ -107,3 +107,55 @@ def test_l1_screen_ties_and_near_ties():
         assert np.array_equal(r["d2"][q, :ref.m[q]], ref.d2[q, :ref.m[q]].astype(np.float32)), q
     # the copies do tie: some patch has two neighbours at the same l1 distance
     assert any(len(set(ref.d2[q, :ref.m[q]])) < ref.m[q] for q in range(len(ref.m)))
+
+
+@pytest.mark.parametrize("case", [0, 3])
+def test_query_metric_l1_equals_rerank(case):
+    """zh_query under ZH_METRIC_L1 gives the neighbours, l1 distances, counts,
+    weights and pixels of zh_query under l2 followed by zh_knn_l1, bitwise
+    (the tiny case through the unscreened ranking, the wide-bin 256^2 case
+    through the l1 screen), and the oracle's."""
+    import torch
+    wl, g, qr, hr_ref, _ = _case(*CASES[case])
+    cap = CASES[case][2]
+    g.set_mode(cap=cap, rerank=0, proj=1, lle_fp64=1)
+    a = g.zoom(metric="l1").clone()
+    ra = g.results()
+    b = g.zoom(metric="l1q").clone()
+    rb = g.results()
+    for k in ("ids", "d2", "m", "w", "ncand", "nsurv"):
+        assert np.array_equal(ra[k], rb[k]), k
+    assert torch.equal(a, b)
+    # survivors of the l1 pass: at least the neighbours, at most the candidates;
+    # all of them without the screen (D = 25), far fewer with it (D = 100)
+    M = np.minimum(rb["ncand"], cap)
+    assert (rb["m"] <= rb["nsurv"]).all() and (rb["nsurv"] <= M).all()
+    if wl.D == 25:
+        assert np.array_equal(rb["nsurv"], M)
+    else:
+        assert rb["nsurv"][M > wl.K].mean() < 0.5 * M[M > wl.K].mean()
+    assert np.array_equal(rb["ids"], np.where(qr.ids >= 0, qr.ids, -1).astype(np.int32))
+    assert np.abs(b.cpu().numpy().astype(np.float64) - hr_ref).max() < 1e-5
+
+
+def test_query_metric_errors():
+    import torch
+    from paper_1004_3980_amd import zoomhash as zb
+    wl, g, _, _, _ = _case(*CASES[0])
+    ctx = g.ctx
+    with pytest.raises(KeyError):
+        ctx.set_query_metric("l3")
+    assert ctx.lib.zh_set_query_metric(ctx.h, 2) == zb.ZH_EINVAL
+    g.set_mode(cap=0, rerank=0, proj=1, lle_fp64=1)
+    ctx.set_query_metric("l1")
+    try:
+        with pytest.raises(zb.ZHError):   # the l1 metric needs the early stop
+            ctx.query(g.lr, g.lr.shape[0], g.lr.shape[1], wl.scale, wl.K)
+        g.set_mode(cap=12, rerank=0, proj=1, lle_fp64=1)
+        ctx.query(g.lr, g.lr.shape[0], g.lr.shape[1], wl.scale, wl.K)
+        out = torch.empty((wl.scale * g.h, wl.scale * g.w), device=g.dev)
+        with pytest.raises(zb.ZHError):   # the batched form ranks by squared l2
+            ctx.run_batch([g.lr], [out], [wl.scale], wl.K, wl.lam, 1, 1.5, 0.1)
+    finally:
+        ctx.set_query_metric("l2")
+    ctx.query(g.lr, g.lr.shape[0], g.lr.shape[1], wl.scale, wl.K)
