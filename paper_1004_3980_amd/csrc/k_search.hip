@@ -922,8 +922,10 @@ __global__ __launch_bounds__(64, 7) void k_search_cap(SearchArgs a) {
 }
 
 // Step 1 of the early-stop search alone (the candidates-only form): M into
-// out_ncand and the dump, ascending, when asked. Few registers, so more
-// waves per SIMD hide the dependent reads of the bins.
+// out_ncand and, when asked, the dump of the M IDs in the order the union
+// met them (its only reader, the l1 ranking, does not depend on the order,
+// so no sort). Few registers, so more waves per SIMD hide the dependent
+// reads of the bins.
 __global__ __launch_bounds__(64, 12) void k_union_cap(SearchArgs a) {
     extern __shared__ uint64_t hset[];
     uint32_t* cids = reinterpret_cast<uint32_t*>(hset + a.hsz);
@@ -933,10 +935,8 @@ __global__ __launch_bounds__(64, 12) void k_union_cap(SearchArgs a) {
     const int q = xcd_block();
     if (q >= a.Q) return;
     const int M = cap_union(a, q, hset, cids, sbase, smark);
-    if (a.dump) {
-        wave_sort_u32(cids, M);
+    if (a.dump)
         for (int i = lane; i < M && i < a.dump_cap; i += 64) a.dump[(int64_t)q * a.dump_cap + i] = (int32_t)cids[i];
-    }
     if (lane == 0) a.out_ncand[q] = M;
 }
 

@@ -151,7 +151,7 @@ struct SearchArgs {
     int32_t* out_nsurv;      // [Q] candidates given an exact distance (early-stop search), nullable
     int32_t* dump;           // [Q, dump_cap] or null
     int dump_cap;
-    int cand_only;           // early-stop search: candidate counts (and the dump) only, neighbours untouched
+    int cand_only;           // early-stop search: candidate counts (and the dump, in the union's order) only, neighbours untouched
     int32_t* overflow;       // [2 Q] deferred queries (uncapped, too many IDs for a wave), then those
                              // beyond the large-union limit
     unsigned int* counters;  // [0] overflow count, [1] FP64 rank fallbacks
