@@ -200,38 +200,57 @@ __global__ __launch_bounds__(256) void k_gram(LleArgs a, T* __restrict__ gram) {
         float qf[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) qf[e] = (qv && dl) ? a.qfeat[(int64_t)q * D + hl * VEC + e] : 0.0f;
-        raw_t hr[8], lr[8];
+        T z[8][VEC];
+        if (VEC == 4 && a.xf) {
+            // the fp32 copy: one 16-byte load of a contiguous 400-byte row
+            float4 xr[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            hr[r] = raw_t{};
-            lr[r] = raw_t{};
-            if (r < m && dl) {
-                const uint32_t id = (uint32_t)a.ids[(int64_t)q * a.K + r];
-                const uint32_t bo = (id * (uint32_t)D + (uint32_t)(hl * VEC)) * 2u;
-                const uint32_t bh = (id * (uint32_t)a.hs + (uint32_t)(hl * VEC)) * 2u;
-                if constexpr (VEC == 4) {
-                    hr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.hi) + bh);
-                    lr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.lo) + bo);
-                } else {
-                    hr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.hi) + bh);
-                    lr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.lo) + bo);
+            for (int r = 0; r < 8; ++r) {
+                xr[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r < m && dl) {
+                    const int64_t id = a.ids[(int64_t)q * a.K + r];
+                    xr[r] = *reinterpret_cast<const float4*>(a.xf + id * D + hl * VEC);
                 }
             }
-        }
-        T z[8][VEC];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            uint32_t hv[VEC], lv[VEC];
-            if constexpr (VEC == 4) {
-                hv[0] = hr[r].x & 0xFFFFu; hv[1] = hr[r].x >> 16; hv[2] = hr[r].y & 0xFFFFu; hv[3] = hr[r].y >> 16;
-                lv[0] = lr[r].x & 0xFFFFu; lv[1] = lr[r].x >> 16; lv[2] = lr[r].y & 0xFFFFu; lv[3] = lr[r].y >> 16;
-            } else {
-                hv[0] = hr[r];
-                lv[0] = lr[r];
+            for (int r = 0; r < 8; ++r) {
+                const float xv[4] = {xr[r].x, xr[r].y, xr[r].z, xr[r].w};
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) z[r][e] = (r < m && dl) ? (T)qf[e] - (T)xv[e % 4] : (T)0;
             }
-#pragma unroll
-            for (int e = 0; e < VEC; ++e)
-                z[r][e] = (r < m && dl) ? (T)qf[e] - (T)__uint_as_float((hv[e] << 16) | lv[e]) : (T)0;
+        } else {
+            raw_t hr[8], lr[8];
+    #pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                hr[r] = raw_t{};
+                lr[r] = raw_t{};
+                if (r < m && dl) {
+                    const uint32_t id = (uint32_t)a.ids[(int64_t)q * a.K + r];
+                    const uint32_t bo = (id * (uint32_t)D + (uint32_t)(hl * VEC)) * 2u;
+                    const uint32_t bh = (id * (uint32_t)a.hs + (uint32_t)(hl * VEC)) * 2u;
+                    if constexpr (VEC == 4) {
+                        hr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.hi) + bh);
+                        lr[r] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(a.lo) + bo);
+                    } else {
+                        hr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.hi) + bh);
+                        lr[r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(a.lo) + bo);
+                    }
+                }
+            }
+    #pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                uint32_t hv[VEC], lv[VEC];
+                if constexpr (VEC == 4) {
+                    hv[0] = hr[r].x & 0xFFFFu; hv[1] = hr[r].x >> 16; hv[2] = hr[r].y & 0xFFFFu; hv[3] = hr[r].y >> 16;
+                    lv[0] = lr[r].x & 0xFFFFu; lv[1] = lr[r].x >> 16; lv[2] = lr[r].y & 0xFFFFu; lv[3] = lr[r].y >> 16;
+                } else {
+                    hv[0] = hr[r];
+                    lv[0] = lr[r];
+                }
+    #pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    z[r][e] = (r < m && dl) ? (T)qf[e] - (T)__uint_as_float((hv[e] << 16) | lv[e]) : (T)0;
+            }
         }
 #pragma unroll
         for (int g = 0; g < 2; ++g) {

@@ -1232,6 +1232,7 @@ zh_status zh_lle_weights(zh_ctx* c, double lambda) {
     a.hi = P<uint16_t>(d.hi);
     a.lo = P<uint16_t>(d.lo);
     a.hs = hi_stride(d.D);
+    a.xf = P<float>(d.xf);
     a.lam = lambda;
     a.fp64 = c->opts.lle_fp64;
     a.w = P<float>(c->w);
@@ -1559,6 +1560,7 @@ zh_status zh_backward(zh_ctx* c, const float* g_hr, float* g_resid, float* g_lam
             la.hi = P<uint16_t>(d.hi);
             la.lo = P<uint16_t>(d.lo);
             la.hs = hi_stride(d.D);
+            la.xf = P<float>(d.xf);
             TRY(ensure(c, c->gram, sizeof(double) * (size_t)(Q > 0 ? Q : 1) * 36));
             HIPCHK(c, launch_gram(la, c->gram.p, 1, c->stream));
             c->gram_ready = true;
@@ -1783,6 +1785,7 @@ zh_status batch_chain(zh_ctx* c, const zh_batch* b, hipStream_t st) {
             la.hi = P<uint16_t>(d.hi);
             la.lo = P<uint16_t>(d.lo);
             la.hs = hi_stride(d.D);
+            la.xf = P<float>(d.xf);
             la.lam = b->lambda;
             la.fp64 = c->opts.lle_fp64;
             la.w = P<float>(c->w);

@@ -195,6 +195,7 @@ struct LleArgs {
     const int32_t* m;
     const uint16_t* hi;
     const uint16_t* lo;
+    const float* xf;         // [n, D] fp32 copy of the same features (16-byte aligned rows when D % 4 == 0), or null
     double lam;
     int fp64;                // 1: FP64 Gram and solve; 0: FP32, FP64 redo when cond > 1e6
     float* w;                // [Q, K]
